@@ -1,0 +1,344 @@
+"""FP64 reference oracle for the AQMP encoder (test infrastructure only).
+
+This module is a plain, slow, literal CPU implementation of what the GPU path
+computes.  It exists to check that path: only the test suite, the smoke check
+and the CPU-baseline leg of the benchmark may import it.  It shares no code,
+tables or constants with the GPU library, which never imports it.
+
+Everything is float64 NumPy, one quadtree node at a time.
+
+Sources in the paper (AQMP, arXiv 2605.09190):
+
+* Section 2.1: the 1D DCT-II matrix ``C[k, n] = alpha_k cos(pi/N (n + 1/2) k)``
+  with ``alpha_0 = sqrt(1/N)``, ``alpha_k = sqrt(2/N)``; the 2D atoms are outer
+  products of two 1D rows.
+* Section 2.3 and Appendix A: the dictionary for block size N concatenates a
+  DCT basis with a Haar basis; a block is flattened by concatenating its
+  columns.
+* Section 2.2, eq. (1)-(2) and the MP steps (a)-(d): residual initialised to
+  the signal, arg-max of the absolute correlation, rank-1 residual update,
+  stop when the residual norm falls below the tolerance or after k steps.
+* Algorithms 1-2 (encoder) and 3 (decoder) of Section 2.3.
+
+Readings taken where the paper is silent or inconsistent (each one is listed
+with its reason in the design notes of the repository):
+
+* plain MP (the rank-1 update of step (c)), not OMP;
+* split when MP ends without meeting the accuracy target and N > N_min
+  (rule "r1", the prose of Section 2.3); the pseudocode's literal
+  ``||x||_0 >= k`` test is available as rule "r2";
+* k counts MP iterations; re-selecting an atom gives a new record;
+* the stop test is checked before every iteration, including the first,
+  on squared norms with a strict ``<``;
+* tolerance mode "rms": eps_N = tol * N (residual RMS over the block);
+  mode "abs": the same eps at every level, as Algorithm 2 passes it down;
+* M_N = 2 N^2: one orthonormal DCT basis and one orthonormal separable
+  (Kronecker) Haar basis; atom index ``a = f N^2 + q N + p`` for the atom
+  ``A[i, j] = T_f[p, i] T_f[q, j]``;
+* both constant (DC) atoms are set to exactly 1/N, so the duplicate pair
+  ties exactly; arg-max ties go to the lowest atom index;
+* stop when the largest absolute correlation is exactly zero;
+* children encode the original pixels of their quadrant (Algorithm 2
+  recurses on the block ``b``) in the order TL, TR, BL, BR.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Sequence
+
+import numpy as np
+
+DCT = 1
+HAAR = 2
+
+
+# ---------------------------------------------------------------------------
+# Dictionaries (Section 2.1; Section 2.3 "DCT basis with wavelets (e.g. Haar)";
+# Appendix A)
+# ---------------------------------------------------------------------------
+
+def dct_matrix(n: int) -> np.ndarray:
+    """1D DCT-II matrix of Section 2.1: ``C[k, m] = alpha_k cos(pi/n (m + 1/2) k)``."""
+    k = np.arange(n, dtype=np.float64)[:, None]
+    m = np.arange(n, dtype=np.float64)[None, :]
+    alpha = np.where(k == 0, np.sqrt(1.0 / n), np.sqrt(2.0 / n))
+    return alpha * np.cos(np.pi / n * (m + 0.5) * k)
+
+
+def haar_matrix(n: int) -> np.ndarray:
+    """Orthonormal 1D Haar matrix, built by the two-scale recursion.
+
+    ``H_1 = [1]`` and ``H_2m = (1/sqrt 2) [H_m (x) (1, 1); I_m (x) (1, -1)]``.
+    Row 0 is the constant; the remaining rows are the wavelets from coarse
+    to fine.  The paper names Haar wavelets without a construction; this is
+    the standard orthonormal one.
+    """
+    if n < 1 or n & (n - 1):
+        raise ValueError("n must be a power of two")
+    h = np.ones((1, 1))
+    while h.shape[0] < n:
+        m = h.shape[0]
+        top = np.kron(h, np.array([[1.0, 1.0]]))
+        bot = np.kron(np.eye(m), np.array([[1.0, -1.0]]))
+        h = np.vstack([top, bot]) / np.sqrt(2.0)
+    return h
+
+
+def unravel(block: np.ndarray) -> np.ndarray:
+    """Flatten an N x N block by concatenating its columns (Appendix A)."""
+    return np.asarray(block, dtype=np.float64).reshape(-1, order="F")
+
+
+def unravel_inv(vec: np.ndarray, n: int) -> np.ndarray:
+    """Inverse of :func:`unravel`."""
+    return np.asarray(vec, dtype=np.float64).reshape((n, n), order="F")
+
+
+def dictionary(n: int, families: int = DCT | HAAR) -> np.ndarray:
+    """Dictionary D_N as an ``N^2 x M`` matrix whose columns are unit atoms.
+
+    For each family T (DCT first, then Haar) and each pair (p, q) the 2D atom
+    is the outer product ``A[i, j] = T[p, i] T[q, j]`` (Section 2.1), flattened
+    column-major; its index is ``f N^2 + q N + p``.  The constant atom of every
+    family is set to exactly 1/N.
+    """
+    mats = []
+    if families & DCT:
+        mats.append(dct_matrix(n))
+    if families & HAAR:
+        mats.append(haar_matrix(n))
+    if not mats:
+        raise ValueError("empty dictionary")
+    cols = []
+    for t in mats:
+        d = np.empty((n * n, n * n))
+        for q in range(n):
+            for p in range(n):
+                a = np.outer(t[p], t[q])          # A[i, j] = T[p, i] T[q, j]
+                d[:, q * n + p] = unravel(a)
+        d[:, 0] = 1.0 / n                          # constant atom, exact
+        cols.append(d)
+    return np.hstack(cols)
+
+
+def duplicate_groups(d: np.ndarray) -> np.ndarray:
+    """``rep[a]`` = lowest index of an atom whose column equals atom ``a`` bit for bit."""
+    m = d.shape[1]
+    rep = np.arange(m)
+    seen: dict[bytes, int] = {}
+    for a in range(m):
+        key = d[:, a].tobytes()
+        if key in seen:
+            rep[a] = seen[key]
+        else:
+            seen[key] = a
+    return rep
+
+
+class Dict:
+    """One block size's dictionary with the transposed copy used for correlations."""
+
+    def __init__(self, n: int, families: int = DCT | HAAR):
+        self.n = n
+        self.families = families
+        self.D = dictionary(n, families)                  # [N^2, M]
+        self.Dt = np.ascontiguousarray(self.D.T)          # [M, N^2]
+        self.m = self.D.shape[1]
+        self.rep = duplicate_groups(self.D)
+
+
+_DICT_CACHE: dict[tuple[int, int], Dict] = {}
+
+
+def get_dict(n: int, families: int = DCT | HAAR) -> Dict:
+    key = (n, families)
+    if key not in _DICT_CACHE:
+        _DICT_CACHE[key] = Dict(n, families)
+    return _DICT_CACHE[key]
+
+
+# ---------------------------------------------------------------------------
+# Matching Pursuit (Section 2.2, eq. (1)-(2), steps (a)-(d))
+# ---------------------------------------------------------------------------
+
+@dataclass
+class MPResult:
+    idx: list = field(default_factory=list)      # selected atom per iteration
+    coef: list = field(default_factory=list)     # <r, phi_i> per iteration
+    gap: list = field(default_factory=list)      # relative top-2 gap over distinct atoms
+    e: list = field(default_factory=list)        # ||r||^2 before each iteration, then final
+    stop: str = ""                               # "accuracy" | "sparsity" | "zero"
+
+    @property
+    def t(self) -> int:
+        return len(self.idx)
+
+    @property
+    def e_final(self) -> float:
+        return self.e[-1]
+
+
+def top2_gap(c_abs: np.ndarray, rep: np.ndarray, i: int) -> float:
+    """Relative gap between the best atom ``i`` and the best atom that is not a
+    bit-identical copy of it: ``(|c|_(1) - |c|_(2)) / |c|_(1)``."""
+    other = c_abs.copy()
+    other[rep == rep[i]] = -1.0
+    second = other.max() if other.size else -1.0
+    if c_abs[i] == 0.0:
+        return 0.0
+    return float((c_abs[i] - max(second, 0.0)) / c_abs[i])
+
+
+def mp(dic: Dict, y: np.ndarray, eps2: float, k: int) -> MPResult:
+    """Plain Matching Pursuit on one signal.
+
+    ``r = y``; before every iteration stop if ``||r||^2 < eps2`` (eq. (2),
+    accuracy) or if ``k`` iterations have been made (eq. (2), sparsity);
+    otherwise ``c = D^T r``, ``i = argmax |c|`` (lowest index among equal
+    values), ``r <- r - c_i phi_i``.  A zero maximum correlation stops too.
+    """
+    r = np.array(y, dtype=np.float64, copy=True)
+    out = MPResult()
+    e = float(r @ r)
+    out.e.append(e)
+    while True:
+        if e < eps2:
+            out.stop = "accuracy"
+            break
+        if out.t >= k:
+            out.stop = "sparsity"
+            break
+        c = dic.Dt @ r
+        c_abs = np.abs(c)
+        i = int(np.argmax(c_abs))          # first maximal index
+        if c_abs[i] == 0.0:
+            out.stop = "zero"
+            break
+        ci = float(c[i])
+        out.gap.append(top2_gap(c_abs, dic.rep, i))
+        r = r - ci * dic.D[:, i]
+        e = float(r @ r)
+        out.idx.append(i)
+        out.coef.append(ci)
+        out.e.append(e)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Encoder (Algorithms 1-2) and decoder (Algorithm 3)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Params:
+    tol: float
+    tol_mode: str = "rms"          # "rms": eps_N = tol*N ; "abs": eps_N = tol
+    max_atoms: int = 32
+    n_min: int = 8
+    n_max: int = 64
+    split_rule: str = "r1"         # "r1" accuracy not met ; "r2" ||x||_0 >= k literal
+    k_per_level: dict | None = None
+    families: int = DCT | HAAR
+
+    def eps2(self, n: int) -> float:
+        eps = self.tol * n if self.tol_mode == "rms" else self.tol
+        return float(eps) * float(eps)
+
+    def k(self, n: int) -> int:
+        if self.k_per_level is not None and n in self.k_per_level:
+            return int(self.k_per_level[n])
+        return int(self.max_atoms)
+
+    @staticmethod
+    def from_dict(d: dict) -> "Params":
+        keys = {"tol", "tol_mode", "max_atoms", "n_min", "n_max", "split_rule",
+                "k_per_level", "families"}
+        return Params(**{k: v for k, v in d.items() if k in keys})
+
+
+@dataclass
+class Node:
+    x0: int
+    y0: int
+    n: int
+    mp: MPResult
+    split: bool
+    eps2: float
+    norm2: float            # ||y||^2 of the node's original pixels
+
+
+def split_decision(p: Params, n: int, res: MPResult) -> bool:
+    """Whether a node of size ``n`` is refined into its four quadrants."""
+    if n <= p.n_min:
+        return False
+    if p.split_rule == "r1":
+        return res.e_final >= p.eps2(n)
+    return res.t >= p.k(n)
+
+
+def encode_block(img: np.ndarray, p: Params, x0: int, y0: int, n: int,
+                 nodes: list[Node] | None = None) -> list[Node]:
+    """Algorithm 2 on one block: MP, then either emit it or recurse into its
+    quadrants (TL, TR, BL, BR) of the original pixels.  Returns the visited
+    nodes in depth-first order; the leaves are those with ``split=False``."""
+    if nodes is None:
+        nodes = []
+    block = img[y0:y0 + n, x0:x0 + n]
+    y = unravel(block)
+    dic = get_dict(n, p.families)
+    res = mp(dic, y, p.eps2(n), p.k(n))
+    sp = split_decision(p, n, res)
+    nodes.append(Node(x0, y0, n, res, sp, p.eps2(n), float(y @ y)))
+    if sp:
+        h = n // 2
+        for dy, dx in ((0, 0), (0, h), (h, 0), (h, h)):
+            encode_block(img, p, x0 + dx, y0 + dy, h, nodes)
+    return nodes
+
+
+def top_blocks(h: int, w: int, n_max: int) -> list[tuple[int, int]]:
+    """Top-level blocks of size n_max in raster order, as (x0, y0)."""
+    if h % n_max or w % n_max:
+        raise ValueError("image size must be a multiple of n_max")
+    return [(x, y) for y in range(0, h, n_max) for x in range(0, w, n_max)]
+
+
+def encode_channel(img: np.ndarray, p: Params, blocks=None) -> list[Node]:
+    """Algorithm 2 started at N_max on every top-level block (or on the given
+    subset of top-level blocks)."""
+    img = np.asarray(img, dtype=np.float64)
+    if blocks is None:
+        blocks = top_blocks(img.shape[0], img.shape[1], p.n_max)
+    nodes: list[Node] = []
+    for (x0, y0) in blocks:
+        encode_block(img, p, x0, y0, p.n_max, nodes)
+    return nodes
+
+
+def encode(channels: Sequence[np.ndarray], p: Params) -> list[list[Node]]:
+    """Algorithm 1: each channel is encoded independently."""
+    return [encode_channel(c, p) for c in channels]
+
+
+def leaves(nodes: list[Node]) -> list[Node]:
+    return [nd for nd in nodes if not nd.split]
+
+
+def decode(nodes: list[Node], h: int, w: int, families: int = DCT | HAAR) -> np.ndarray:
+    """Algorithm 3: every leaf's block is ``unravel^-1(D_N x)`` placed at its
+    position.  Pixels not covered by a leaf stay zero."""
+    out = np.zeros((h, w))
+    for nd in leaves(nodes):
+        dic = get_dict(nd.n, families)
+        x = np.zeros(dic.m)
+        for i, c in zip(nd.mp.idx, nd.mp.coef):
+            x[i] += c
+        out[nd.y0:nd.y0 + nd.n, nd.x0:nd.x0 + nd.n] = unravel_inv(dic.D @ x, nd.n)
+    return out
+
+
+def psnr(ref: np.ndarray, rec: np.ndarray, peak: float = 1.0) -> float:
+    """PSNR in dB with the given peak; the MSE is taken in float64 over all
+    samples, without clipping the reconstruction."""
+    d = np.asarray(ref, dtype=np.float64) - np.asarray(rec, dtype=np.float64)
+    mse = float(np.mean(d * d))
+    return float("inf") if mse == 0.0 else 10.0 * np.log10(peak * peak / mse)
