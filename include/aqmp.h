@@ -1,0 +1,222 @@
+/*
+ * aqmp.h - C ABI of the MI355X (gfx950) AQMP encoder.
+ *
+ * AQMP (Adaptive Quadtree Matching Pursuit, arXiv 2605.09190) codes every
+ * channel of an image as a quadtree of square blocks.  Each block is
+ * approximated by greedy Matching Pursuit over a dictionary of unit-norm 2D
+ * atoms; a block whose residual misses the accuracy target after k
+ * iterations is split into its four quadrants, down to a minimum size.
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: AQMP_OK (0) or a negative AQMP_E_* code.  Nothing throws
+ *     or aborts across this boundary.  aqmp_last_error() gives a message for
+ *     the calling thread's last failure.  On failure no output handle is
+ *     created and caller buffers are left untouched.
+ *   - "device" pointers are HIP device memory of the current device;
+ *     "host" pointers are ordinary host memory.  The caller owns every
+ *     buffer it passes in; the library owns the handles it returns.
+ *   - hip_stream is a hipStream_t passed as void* (NULL = the null stream).
+ *     Encode and decode are stream-ordered and asynchronous.
+ *   - Same inputs give bit-identical outputs (all reductions have a fixed
+ *     order; compaction is a stable prefix sum).
+ *   - Block sizes N are powers of two with 4 <= N <= 64.
+ *
+ * Pixel and atom layout.  A block b of size N is the N x N sub-matrix of a
+ * channel, b[i][j] with i the row and j the column.  The paper flattens a
+ * block by concatenating its columns (Appendix A): element (i, j) sits at
+ * position j*N + i of the flattened vector.  For family f (0 = DCT, 1 = Haar
+ * when both are built) and frequencies (p, q), atom a = f*N*N + q*N + p is
+ * the 2D block A[i][j] = T_f[p][i] * T_f[q][j] (outer product of two 1D
+ * basis rows, Section 2.1), where T_0 is the orthonormal DCT-II matrix of
+ * Section 2.1 and T_1 the orthonormal Haar matrix.  The constant atom of each
+ * family is exactly 1/N.  M_N = (number of families) * N * N.
+ */
+#ifndef AQMP_H
+#define AQMP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+enum {
+  AQMP_OK = 0,
+  AQMP_E_INVALID = -1,   /* null pointer, bad enum, n not a power of two,
+                            n_min > n_max, tol < 0, k out of range ...     */
+  AQMP_E_SHAPE = -2,     /* width or height not a multiple of n_max        */
+  AQMP_E_NODICT = -3,    /* the dictionary lacks a block size the jobs use */
+  AQMP_E_NOMEM = -4,     /* device or host allocation failed, or the
+                            AQMP_MAX_DEVICE_BYTES environment cap is hit   */
+  AQMP_E_HIP = -5,       /* a HIP runtime call failed                      */
+  AQMP_E_CAPACITY = -6   /* caller's output buffer too small               */
+};
+
+/* ---- enumerations ------------------------------------------------------ */
+enum { AQMP_DCT = 1, AQMP_HAAR = 2 };             /* dictionary families   */
+enum { AQMP_F32 = 0, AQMP_F64 = 1 };              /* sample types          */
+enum { AQMP_TOL_RMS = 0, AQMP_TOL_ABS = 1 };      /* tolerance modes       */
+enum { AQMP_SPLIT_R1 = 0, AQMP_SPLIT_R2 = 1 };    /* split rules           */
+enum { AQMP_PREC_FP32 = 0, AQMP_PREC_BF16 = 1 };  /* correlation precision */
+enum { AQMP_SCHED_PLAIN = 0, AQMP_SCHED_BATCHED = 1 };
+
+#define AQMP_MIN_N 4
+#define AQMP_MAX_N 64
+#define AQMP_MAX_ATOMS 256     /* largest k (iterations per node)          */
+#define AQMP_CANDIDATES 8      /* candidates re-scored per MP iteration    */
+
+typedef struct aqmp_dict aqmp_dict;
+typedef struct aqmp_code aqmp_code;
+
+/* One channel plane: h rows of w samples, sample (row y, column x) at
+ * dev_ptr[y * row_stride + x].  Device memory, read-only, owned by the
+ * caller and valid until the encode's stream work has completed. */
+typedef struct {
+  const void* dev_ptr;
+  int32_t dtype;          /* AQMP_F32 or AQMP_F64 */
+  int32_t w, h;
+  int64_t row_stride;     /* in samples, >= w */
+} aqmp_image;
+
+/* Parameters of the problem statement (Section 2.3): accuracy tolerance,
+ * sparsity, admissible block sizes.
+ *   tol_mode AQMP_TOL_RMS: eps_N = tol * N (residual RMS <= tol per block);
+ *   tol_mode AQMP_TOL_ABS: eps_N = tol at every level (Algorithm 2 passes
+ *                          the same eps to the children).
+ * A node stops when ||r||^2 < eps_N^2 or after k_N iterations (eq. (2)),
+ * checked before every iteration.  k_N = k_per_level[log2 N] when that entry
+ * is >= 0, else max_atoms.  0 <= k_N <= AQMP_MAX_ATOMS.
+ *   split_rule AQMP_SPLIT_R1: split when N > n_min and ||r||^2 >= eps_N^2
+ *                             after MP (accuracy not met);
+ *   split_rule AQMP_SPLIT_R2: split when N > n_min and k_N iterations ran
+ *                             (the pseudocode's ||x||_0 >= k test). */
+typedef struct {
+  double tol;
+  int32_t tol_mode;
+  int32_t max_atoms;
+  int32_t n_min, n_max;
+  int32_t split_rule;
+  int32_t k_per_level[7];   /* index log2(N); -1 = use max_atoms */
+} aqmp_params;
+
+/* One job = one channel plane coded under one parameter set (Algorithm 1's
+ * loop over channels; a hyperparameter trial is another job on the same
+ * plane). */
+typedef struct {
+  int32_t image;
+  int32_t params;
+} aqmp_job;
+
+typedef struct {
+  int32_t precision;   /* AQMP_PREC_FP32: FP32 MFMA correlation;
+                          AQMP_PREC_BF16: BF16 MFMA, FP32 accumulate.
+                          Both re-score the AQMP_CANDIDATES best atoms in
+                          FP64 and take the coefficient and the stop/split
+                          test in FP64. */
+  int32_t schedule;    /* AQMP_SCHED_PLAIN: jobs one after another,
+                          stream-ordered launches;
+                          AQMP_SCHED_BATCHED: every job in one pass,
+                          captured once as a HIP graph and replayed. */
+  int32_t reserved[6];
+} aqmp_options;
+
+/* A leaf of the quadtree (or, from aqmp_code_export_nodes, any visited
+ * node).  Its atoms are atom_idx[atom_off .. atom_off + n_atoms) with
+ * coefficients coef[...] in MP order.  flags bit 0: the node was split. */
+typedef struct {
+  int32_t job;
+  int32_t x0, y0, n;
+  int32_t n_atoms;
+  int32_t flags;
+  int64_t atom_off;
+  double resid_sq;          /* ||r||^2 when MP stopped (FP64) */
+} aqmp_leaf;
+
+typedef struct {
+  int64_t nodes[7];         /* visited nodes per log2(N)                    */
+  int64_t leaves[7];        /* leaves per log2(N)                           */
+  int64_t iters_executed;   /* MP iterations, nodes later split included    */
+  int64_t iters_emitted;    /* MP iterations kept in leaves                 */
+  int64_t steps_launched;   /* MP steps issued (levels x k)                 */
+} aqmp_stats;
+
+/* ---- dictionaries (Section 2.1; Section 2.3 "D_N assumed available") --- */
+
+/* Builds D_N for every N = n_min, 2 n_min, ..., n_max (4 <= N <= 64) with the
+ * given families (AQMP_DCT | AQMP_HAAR, DCT first).  The 1D tables are
+ * computed in FP64 on the host; the device keeps the FP64 tables and the
+ * atoms rounded to FP32 and to BF16.  *out is owned by the library; free it
+ * with aqmp_dictionary_free.  Synchronous (returns when uploaded). */
+int aqmp_dictionary_build(int n_min, int n_max, uint32_t families,
+                          void* hip_stream, aqmp_dict** out);
+
+/* Null-safe. */
+void aqmp_dictionary_free(aqmp_dict* d);
+
+/* Number of atoms M_N of block size n; AQMP_E_NODICT if n was not built. */
+int aqmp_dictionary_atoms(const aqmp_dict* d, int n, int* m_out);
+
+/* Copies D_N in FP64 to host memory as an N^2 x M column-major matrix:
+ * element (flattened pixel j*N + i, atom a) at host_out[a * N*N + j*N + i].
+ * host_out must hold N*N*M doubles. */
+int aqmp_dictionary_copy(const aqmp_dict* d, int n, double* host_out);
+
+/* ---- encoder (Algorithms 1-2, MP of Section 2.2) ----------------------- */
+
+/* Encodes n_jobs jobs.  Every image, parameter set and job is validated on
+ * the host first (AQMP_E_INVALID, AQMP_E_SHAPE, AQMP_E_NODICT).  The call
+ * allocates the code's device buffers (worst case for these shapes), then
+ * enqueues the encode on hip_stream and returns; *out is valid once that
+ * stream's work has completed (the aqmp_code_* readers synchronise it).
+ * The images must stay valid until then.  The returned handle keeps its
+ * buffers (and, for the batched schedule, its graph) for aqmp_reencode. */
+int aqmp_encode(const aqmp_dict* d,
+                const aqmp_image* imgs, int n_imgs,
+                const aqmp_params* prm, int n_prm,
+                const aqmp_job* jobs, int n_jobs,
+                const aqmp_options* opt, void* hip_stream, aqmp_code** out);
+
+/* Runs the same encode again on new planes of the same count, types and
+ * shapes (device pointers and strides may change), on hip_stream, reusing
+ * the handle's buffers and graph.  Previous results are overwritten. */
+int aqmp_reencode(aqmp_code* c, const aqmp_image* imgs, int n_imgs, void* hip_stream);
+
+/* Synchronises the encode stream, then reports the number of leaves and of
+ * atoms kept in leaves. */
+int aqmp_code_sizes(const aqmp_code* c, int64_t* n_leaves, int64_t* n_atoms);
+
+/* Copies the leaves in canonical order (job, then top-level blocks in raster
+ * order, then depth-first TL, TR, BL, BR) with their atoms to host buffers.
+ * AQMP_E_CAPACITY (nothing written) if cap_leaves or cap_atoms is too small. */
+int aqmp_code_export(const aqmp_code* c, aqmp_leaf* leaves, int32_t* atom_idx,
+                     double* coef, int64_t cap_leaves, int64_t cap_atoms);
+
+/* Like aqmp_code_export, but for every visited node (split nodes included,
+ * flags bit 0 set, with the atoms MP chose before the split was decided).
+ * Sizes: aqmp_code_stats (sum of nodes[] and iters_executed). */
+int aqmp_code_export_nodes(const aqmp_code* c, aqmp_leaf* nodes, int32_t* atom_idx,
+                           double* coef, int64_t cap_nodes, int64_t cap_atoms);
+
+int aqmp_code_stats(const aqmp_code* c, aqmp_stats* s);
+
+/* Null-safe; waits for the handle's stream work first. */
+void aqmp_code_free(aqmp_code* c);
+
+/* ---- decoder (Algorithm 3) --------------------------------------------- */
+
+/* Writes job's reconstruction sum_t c_t phi_{i_t} of every leaf, placed at
+ * its (x0, y0), into dev_out (device, dtype AQMP_F32 or AQMP_F64, h rows of
+ * w samples of the job's plane, row stride row_stride samples); no clipping.
+ * Samples outside every leaf are not written (leaves tile the plane).
+ * Stream-ordered on hip_stream, after the encode's stream work. */
+int aqmp_decode(const aqmp_dict* d, const aqmp_code* c, int job,
+                void* dev_out, int dtype, int64_t row_stride, void* hip_stream);
+
+/* Message for the calling thread's last failure ("" if none). */
+const char* aqmp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AQMP_H */

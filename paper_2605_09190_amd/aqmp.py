@@ -1,0 +1,264 @@
+"""Thin ctypes binding of libaqmp.so (the C ABI in include/aqmp.h).
+
+Argument marshalling only: every step of the encoder and decoder runs in the
+library's HIP kernels.  PyTorch tensors supply device memory and the HIP
+stream.  Importing this module loads the library and fails loudly when it
+has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+# torch ships its own HIP runtime (SONAME libamdhip64.so.7).  Loading it first
+# makes libaqmp.so bind to that same runtime instead of a second copy from
+# /opt/rocm, which would not see the device once torch has initialised it.
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaqmp.so")
+
+# enums of aqmp.h
+OK, E_INVALID, E_SHAPE, E_NODICT, E_NOMEM, E_HIP, E_CAPACITY = 0, -1, -2, -3, -4, -5, -6
+DCT, HAAR = 1, 2
+F32, F64 = 0, 1
+TOL_RMS, TOL_ABS = 0, 1
+SPLIT_R1, SPLIT_R2 = 0, 1
+PREC_FP32, PREC_BF16 = 0, 1
+SCHED_PLAIN, SCHED_BATCHED = 0, 1
+MAX_ATOMS = 256
+CANDIDATES = 8
+
+# Every entry point declared in include/aqmp.h.
+EXPORTS = [
+    "aqmp_dictionary_build", "aqmp_dictionary_free", "aqmp_dictionary_atoms", "aqmp_dictionary_copy",
+    "aqmp_encode", "aqmp_reencode", "aqmp_code_sizes", "aqmp_code_export", "aqmp_code_export_nodes",
+    "aqmp_code_stats", "aqmp_code_free", "aqmp_decode", "aqmp_last_error",
+]
+
+
+class Image(C.Structure):
+    _fields_ = [("dev_ptr", C.c_void_p), ("dtype", C.c_int32), ("w", C.c_int32), ("h", C.c_int32),
+                ("row_stride", C.c_int64)]
+
+
+class Params(C.Structure):
+    _fields_ = [("tol", C.c_double), ("tol_mode", C.c_int32), ("max_atoms", C.c_int32),
+                ("n_min", C.c_int32), ("n_max", C.c_int32), ("split_rule", C.c_int32),
+                ("k_per_level", C.c_int32 * 7)]
+
+
+class Job(C.Structure):
+    _fields_ = [("image", C.c_int32), ("params", C.c_int32)]
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("schedule", C.c_int32), ("reserved", C.c_int32 * 6)]
+
+
+class Leaf(C.Structure):
+    _fields_ = [("job", C.c_int32), ("x0", C.c_int32), ("y0", C.c_int32), ("n", C.c_int32),
+                ("n_atoms", C.c_int32), ("flags", C.c_int32), ("atom_off", C.c_int64),
+                ("resid_sq", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("nodes", C.c_int64 * 7), ("leaves", C.c_int64 * 7), ("iters_executed", C.c_int64),
+                ("iters_emitted", C.c_int64), ("steps_launched", C.c_int64)]
+
+
+LEAF_DTYPE = np.dtype([("job", "<i4"), ("x0", "<i4"), ("y0", "<i4"), ("n", "<i4"), ("n_atoms", "<i4"),
+                       ("flags", "<i4"), ("atom_off", "<i8"), ("resid_sq", "<f8")])
+
+
+class AqmpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"aqmp error {code}: {msg}")
+        self.code = code
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2605_09190_amd.build.build() first")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int, C.c_int64
+    lib.aqmp_dictionary_build.argtypes = [i32, i32, C.c_uint32, vp, C.POINTER(vp)]
+    lib.aqmp_dictionary_free.argtypes = [vp]
+    lib.aqmp_dictionary_free.restype = None
+    lib.aqmp_dictionary_atoms.argtypes = [vp, i32, C.POINTER(C.c_int)]
+    lib.aqmp_dictionary_copy.argtypes = [vp, i32, C.POINTER(C.c_double)]
+    lib.aqmp_encode.argtypes = [vp, C.POINTER(Image), i32, C.POINTER(Params), i32, C.POINTER(Job), i32,
+                                C.POINTER(Options), vp, C.POINTER(vp)]
+    lib.aqmp_reencode.argtypes = [vp, C.POINTER(Image), i32, vp]
+    lib.aqmp_code_sizes.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
+    lib.aqmp_code_export.argtypes = [vp, vp, vp, vp, i64, i64]
+    lib.aqmp_code_export_nodes.argtypes = [vp, vp, vp, vp, i64, i64]
+    lib.aqmp_code_stats.argtypes = [vp, C.POINTER(Stats)]
+    lib.aqmp_code_free.argtypes = [vp]
+    lib.aqmp_code_free.restype = None
+    lib.aqmp_decode.argtypes = [vp, vp, i32, vp, i32, i64, vp]
+    lib.aqmp_last_error.argtypes = []
+    lib.aqmp_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if not hasattr(lib, name):
+            raise ImportError(f"{LIB_PATH} lacks {name}")
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc: int) -> None:
+    if rc != OK:
+        raise AqmpError(rc, lib.aqmp_last_error().decode())
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def make_params(tol: float, tol_mode: str = "rms", max_atoms: int = 32, n_min: int = 8, n_max: int = 64,
+                split_rule: str = "r1", k_per_level: dict | None = None, **_ignored) -> Params:
+    p = Params()
+    p.tol = float(tol)
+    p.tol_mode = {"rms": TOL_RMS, "abs": TOL_ABS}[tol_mode] if isinstance(tol_mode, str) else int(tol_mode)
+    p.max_atoms = int(max_atoms)
+    p.n_min, p.n_max = int(n_min), int(n_max)
+    p.split_rule = {"r1": SPLIT_R1, "r2": SPLIT_R2}[split_rule] if isinstance(split_rule, str) else int(split_rule)
+    for i in range(7):
+        p.k_per_level[i] = -1
+    if k_per_level:
+        for n, k in k_per_level.items():
+            p.k_per_level[int(n).bit_length() - 1] = int(k)
+    return p
+
+
+def make_image(t) -> Image:
+    """Describes a 2D CUDA tensor (float32 or float64, unit column stride)."""
+    import torch
+    if t.dim() != 2 or not t.is_cuda or t.stride(1) != 1:
+        raise ValueError("images must be 2D CUDA tensors with unit column stride")
+    if t.dtype not in (torch.float32, torch.float64):
+        raise ValueError("images must be float32 or float64")
+    im = Image()
+    im.dev_ptr = t.data_ptr()
+    im.dtype = F32 if t.dtype == torch.float32 else F64
+    im.h, im.w = int(t.shape[0]), int(t.shape[1])
+    im.row_stride = int(t.stride(0))
+    return im
+
+
+class Dictionary:
+    """D_N for N = n_min .. n_max (powers of two), DCT and/or Haar families."""
+
+    def __init__(self, n_min: int = 4, n_max: int = 64, families: int = DCT | HAAR, stream=None):
+        h = C.c_void_p()
+        _check(lib.aqmp_dictionary_build(n_min, n_max, families, _stream_handle(stream), C.byref(h)))
+        self.h = h
+        self.n_min, self.n_max, self.families = n_min, n_max, families
+
+    def atoms(self, n: int) -> int:
+        m = C.c_int()
+        _check(lib.aqmp_dictionary_atoms(self.h, n, C.byref(m)))
+        return m.value
+
+    def copy(self, n: int) -> np.ndarray:
+        """D_N in FP64 as an (N*N, M) array; columns are column-major flattened atoms."""
+        m = self.atoms(n)
+        buf = np.empty(n * n * m, dtype=np.float64)
+        _check(lib.aqmp_dictionary_copy(self.h, n, buf.ctypes.data_as(C.POINTER(C.c_double))))
+        return buf.reshape(m, n * n).T
+
+    def free(self) -> None:
+        if self.h:
+            lib.aqmp_dictionary_free(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+@dataclass
+class Export:
+    leaves: np.ndarray      # structured LEAF_DTYPE
+    atom_idx: np.ndarray    # int32
+    coef: np.ndarray        # float64
+
+
+class Code:
+    """An encode: the quadtree leaves and their atoms, kept on the device."""
+
+    def __init__(self, dic: Dictionary, images, params, jobs, precision: int = PREC_FP32,
+                 schedule: int = SCHED_PLAIN, stream=None):
+        self.dic = dic
+        self._keep = list(images)
+        imgs = (Image * len(images))(*[make_image(t) for t in images])
+        prms = (Params * len(params))(*[p if isinstance(p, Params) else make_params(**p) for p in params])
+        jbs = (Job * len(jobs))(*[Job(int(a), int(b)) for a, b in jobs])
+        opt = Options()
+        opt.precision, opt.schedule = int(precision), int(schedule)
+        h = C.c_void_p()
+        _check(lib.aqmp_encode(dic.h, imgs, len(images), prms, len(params), jbs, len(jobs), C.byref(opt),
+                               _stream_handle(stream), C.byref(h)))
+        self.h = h
+        self.n_jobs = len(jobs)
+
+    def reencode(self, images, stream=None) -> None:
+        self._keep = list(images)
+        imgs = (Image * len(images))(*[make_image(t) for t in images])
+        _check(lib.aqmp_reencode(self.h, imgs, len(images), _stream_handle(stream)))
+
+    def sizes(self) -> tuple[int, int]:
+        a, b = C.c_int64(), C.c_int64()
+        _check(lib.aqmp_code_sizes(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib.aqmp_code_stats(self.h, C.byref(s)))
+        return dict(nodes=list(s.nodes), leaves=list(s.leaves), iters_executed=s.iters_executed,
+                    iters_emitted=s.iters_emitted, steps_launched=s.steps_launched)
+
+    def _export(self, fn, n_rec: int, n_atoms: int) -> Export:
+        leaves = np.zeros(max(n_rec, 1), dtype=LEAF_DTYPE)
+        idx = np.zeros(max(n_atoms, 1), dtype=np.int32)
+        coef = np.zeros(max(n_atoms, 1), dtype=np.float64)
+        _check(fn(self.h, leaves.ctypes.data, idx.ctypes.data, coef.ctypes.data, n_rec, n_atoms))
+        return Export(leaves[:n_rec], idx[:n_atoms], coef[:n_atoms])
+
+    def export(self) -> Export:
+        n_leaves, n_atoms = self.sizes()
+        return self._export(lib.aqmp_code_export, n_leaves, n_atoms)
+
+    def export_nodes(self) -> Export:
+        s = self.stats()
+        return self._export(lib.aqmp_code_export_nodes, int(sum(s["nodes"])), int(s["iters_executed"]))
+
+    def decode(self, job: int, out, stream=None) -> None:
+        import torch
+        if out.dim() != 2 or not out.is_cuda or out.stride(1) != 1:
+            raise ValueError("out must be a 2D CUDA tensor with unit column stride")
+        dt = F32 if out.dtype == torch.float32 else F64
+        _check(lib.aqmp_decode(self.dic.h, self.h, job, out.data_ptr(), dt, int(out.stride(0)),
+                               _stream_handle(stream)))
+
+    def free(self) -> None:
+        if self.h:
+            lib.aqmp_code_free(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

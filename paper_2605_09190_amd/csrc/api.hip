@@ -1,0 +1,142 @@
+// api.hip - the extern "C" entry points declared in aqmp.h: argument
+// marshalling, error state and the device allocation cap.  Every computation
+// runs in the kernels behind encode.hip / dict.hip.
+#include <atomic>
+#include <cstdlib>
+#include <string>
+
+#include "host_util.h"
+#include "internal.h"
+
+namespace aqmp {
+
+int dictionary_build(int n_min, int n_max, uint32_t families, hipStream_t s, aqmp_dict** out);
+void dictionary_free(aqmp_dict* d);
+int dictionary_atoms(const aqmp_dict* d, int n, int* m_out);
+int dictionary_copy(const aqmp_dict* d, int n, double* host_out);
+int encode(const aqmp_dict* d, const aqmp_image* imgs, int n_imgs, const aqmp_params* prm, int n_prm,
+           const aqmp_job* jobs, int n_jobs, const aqmp_options* opt, hipStream_t s, aqmp_code** out);
+int reencode(aqmp_code* c, const aqmp_image* imgs, int n_imgs, hipStream_t s);
+void code_free(aqmp_code* c);
+int code_stats(const aqmp_code* c, aqmp_stats* s);
+int code_sizes(const aqmp_code* c, int64_t* n_leaves, int64_t* n_atoms);
+int code_export(const aqmp_code* c, bool leaves_only, aqmp_leaf* leaves, int32_t* atom_idx, double* coef,
+                int64_t cap_leaves, int64_t cap_atoms);
+int decode(const aqmp_dict* d, const aqmp_code* c, int job, void* out, int dtype, int64_t row_stride,
+           hipStream_t s);
+
+namespace {
+thread_local std::string g_error;
+std::atomic<long long> g_bytes{0};
+
+long long byte_cap() {
+  static const long long cap = [] {
+    const char* v = std::getenv("AQMP_MAX_DEVICE_BYTES");
+    return v ? std::atoll(v) : 0LL;
+  }();
+  return cap;
+}
+}  // namespace
+
+void set_error(const std::string& msg) { g_error = msg; }
+void clear_error() { g_error.clear(); }
+const char* last_error() { return g_error.c_str(); }
+
+int dev_alloc(void** p, size_t bytes) {
+  *p = nullptr;
+  const long long cap = byte_cap();
+  if (cap > 0 && g_bytes.load() + (long long)bytes > cap) {
+    set_error("device allocation of " + std::to_string(bytes) + " bytes exceeds AQMP_MAX_DEVICE_BYTES");
+    return AQMP_E_NOMEM;
+  }
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    set_error("hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    return AQMP_E_NOMEM;
+  }
+  g_bytes += (long long)bytes;
+  return AQMP_OK;
+}
+
+void dev_free(void* p, size_t bytes) {
+  if (!p) return;
+  (void)hipFree(p);
+  g_bytes -= (long long)bytes;
+}
+
+}  // namespace aqmp
+
+using namespace aqmp;
+
+#define AQMP_ENTRY(expr)       \
+  do {                         \
+    clear_error();             \
+    try {                      \
+      return (expr);           \
+    } catch (...) {            \
+      set_error("internal error"); \
+      return AQMP_E_NOMEM;     \
+    }                          \
+  } while (0)
+
+extern "C" {
+
+int aqmp_dictionary_build(int n_min, int n_max, uint32_t families, void* hip_stream, aqmp_dict** out) {
+  AQMP_ENTRY(dictionary_build(n_min, n_max, families, (hipStream_t)hip_stream, out));
+}
+
+void aqmp_dictionary_free(aqmp_dict* d) {
+  try {
+    dictionary_free(d);
+  } catch (...) {
+  }
+}
+
+int aqmp_dictionary_atoms(const aqmp_dict* d, int n, int* m_out) { AQMP_ENTRY(dictionary_atoms(d, n, m_out)); }
+
+int aqmp_dictionary_copy(const aqmp_dict* d, int n, double* host_out) {
+  AQMP_ENTRY(dictionary_copy(d, n, host_out));
+}
+
+int aqmp_encode(const aqmp_dict* d, const aqmp_image* imgs, int n_imgs, const aqmp_params* prm, int n_prm,
+                const aqmp_job* jobs, int n_jobs, const aqmp_options* opt, void* hip_stream, aqmp_code** out) {
+  AQMP_ENTRY(encode(d, imgs, n_imgs, prm, n_prm, jobs, n_jobs, opt, (hipStream_t)hip_stream, out));
+}
+
+int aqmp_reencode(aqmp_code* c, const aqmp_image* imgs, int n_imgs, void* hip_stream) {
+  AQMP_ENTRY(reencode(c, imgs, n_imgs, (hipStream_t)hip_stream));
+}
+
+int aqmp_code_sizes(const aqmp_code* c, int64_t* n_leaves, int64_t* n_atoms) {
+  AQMP_ENTRY(code_sizes(c, n_leaves, n_atoms));
+}
+
+int aqmp_code_export(const aqmp_code* c, aqmp_leaf* leaves, int32_t* atom_idx, double* coef, int64_t cap_leaves,
+                     int64_t cap_atoms) {
+  AQMP_ENTRY(code_export(c, true, leaves, atom_idx, coef, cap_leaves, cap_atoms));
+}
+
+int aqmp_code_export_nodes(const aqmp_code* c, aqmp_leaf* nodes, int32_t* atom_idx, double* coef, int64_t cap_nodes,
+                           int64_t cap_atoms) {
+  AQMP_ENTRY(code_export(c, false, nodes, atom_idx, coef, cap_nodes, cap_atoms));
+}
+
+int aqmp_code_stats(const aqmp_code* c, aqmp_stats* s) { AQMP_ENTRY(code_stats(c, s)); }
+
+void aqmp_code_free(aqmp_code* c) {
+  try {
+    code_free(c);
+  } catch (...) {
+  }
+}
+
+int aqmp_decode(const aqmp_dict* d, const aqmp_code* c, int job, void* dev_out, int dtype, int64_t row_stride,
+                void* hip_stream) {
+  AQMP_ENTRY(decode(d, c, job, dev_out, dtype, row_stride, (hipStream_t)hip_stream));
+}
+
+const char* aqmp_last_error(void) { return last_error(); }
+
+}  // extern "C"

@@ -1,0 +1,590 @@
+// encode.hip - host orchestration of the AQMP encoder (Algorithms 1-2):
+// planning, device buffers, the level-synchronous launch sequence, the HIP
+// graph of the batched schedule, result export and the decoder launch.
+//
+// Launch sequence of one pass (a set of jobs coded together):
+//   init counts; for each block size N from the largest to the smallest:
+//     gather the level's nodes -> residuals, norms, first stop test;
+//     compact the running nodes into the active list;
+//     k_N times: correlation + top-R keys (MFMA), select/update (FP64),
+//                compact the still-running nodes;
+//     split test, stable scan, emit the children into the next level.
+// All data-dependent counts live in device memory: kernels read them and
+// idle when there is no work, so the sequence is fixed and can be captured
+// once as a graph.  The batched schedule runs every job in one pass (one
+// launch per MP step for every image, channel and parameter set); the plain
+// schedule runs one pass per job, stream-ordered without a graph.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "host_util.h"
+#include "internal.h"
+
+namespace aqmp {
+
+struct PassPlan {
+  int j0 = 0, j1 = 0;                 // jobs [j0, j1)
+  int64_t base[kLevels] = {};          // first node slot of the pass per level
+  int64_t cap[kLevels] = {};           // node capacity per level
+  int32_t ntop[kLevels] = {};          // top-level nodes per level
+  int32_t kmax[kLevels] = {};          // MP steps launched per level
+  int lg_hi = 0, lg_lo = 0;
+};
+
+}  // namespace aqmp
+
+struct aqmp_code {
+  const aqmp_dict* dict = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  aqmp_options opt{};
+  std::vector<aqmp_image> imgs;
+  std::vector<aqmp_params> prm;
+  std::vector<aqmp_job> jobs;
+  std::vector<aqmp::JobDev> hjobs;
+  aqmp::JobDev* djobs = nullptr;
+  std::vector<aqmp::PassPlan> passes;
+  aqmp::Counters* dcnt = nullptr;      // one per pass
+  int32_t* dntop = nullptr;            // [pass][kLevels]
+  int64_t cap_total[aqmp::kLevels] = {};
+  int32_t kmax_total[aqmp::kLevels] = {};
+  aqmp::LevelDev lv[aqmp::kLevels] = {};
+  float* r32 = nullptr;
+  uint16_t* r16 = nullptr;
+  unsigned long long* keys = nullptr;
+  int32_t* act[2] = {nullptr, nullptr};
+  aqmp::ScanState ss{};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  struct Alloc {
+    void* p;
+    size_t bytes;
+  };
+  std::vector<Alloc> allocs;
+  int64_t steps_launched = 0;
+};
+
+namespace aqmp {
+
+namespace {
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int k_of(const aqmp_params& p, int lg) {
+  const int k = p.k_per_level[lg];
+  return k >= 0 ? k : p.max_atoms;
+}
+
+int validate(const aqmp_dict* d, const aqmp_image* imgs, int n_imgs, const aqmp_params* prm, int n_prm,
+             const aqmp_job* jobs, int n_jobs, const aqmp_options* opt) {
+  if (!d) AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: dictionary is null");
+  if (n_imgs < 1 || !imgs) AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: no images");
+  if (n_prm < 1 || !prm) AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: no parameter sets");
+  if (n_jobs < 1 || !jobs) AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: no jobs");
+  if (opt) {
+    if (opt->precision != AQMP_PREC_FP32 && opt->precision != AQMP_PREC_BF16)
+      AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad precision");
+    if (opt->schedule != AQMP_SCHED_PLAIN && opt->schedule != AQMP_SCHED_BATCHED)
+      AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad schedule");
+  }
+  for (int i = 0; i < n_imgs; ++i) {
+    const aqmp_image& im = imgs[i];
+    if (!im.dev_ptr) AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: image " + std::to_string(i) + " has no data");
+    if (im.dtype != AQMP_F32 && im.dtype != AQMP_F64)
+      AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: image " + std::to_string(i) + " has a bad dtype");
+    if (im.w < 1 || im.h < 1 || im.row_stride < im.w)
+      AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: image " + std::to_string(i) + " has a bad shape or stride");
+  }
+  for (int i = 0; i < n_prm; ++i) {
+    const aqmp_params& p = prm[i];
+    const std::string tag = "aqmp_encode: params " + std::to_string(i) + ": ";
+    if (!pow2(p.n_min) || !pow2(p.n_max) || p.n_min < AQMP_MIN_N || p.n_max > AQMP_MAX_N || p.n_min > p.n_max)
+      AQMP_FAIL(AQMP_E_INVALID, tag + "need powers of two 4 <= n_min <= n_max <= 64");
+    if (!(p.tol >= 0.0) || !std::isfinite(p.tol)) AQMP_FAIL(AQMP_E_INVALID, tag + "tol must be finite and >= 0");
+    if (p.tol_mode != AQMP_TOL_RMS && p.tol_mode != AQMP_TOL_ABS) AQMP_FAIL(AQMP_E_INVALID, tag + "bad tol_mode");
+    if (p.split_rule != AQMP_SPLIT_R1 && p.split_rule != AQMP_SPLIT_R2)
+      AQMP_FAIL(AQMP_E_INVALID, tag + "bad split_rule");
+    if (p.max_atoms < 0 || p.max_atoms > AQMP_MAX_ATOMS) AQMP_FAIL(AQMP_E_INVALID, tag + "max_atoms out of range");
+    for (int l = 0; l < kLevels; ++l)
+      if (p.k_per_level[l] < -1 || p.k_per_level[l] > AQMP_MAX_ATOMS)
+        AQMP_FAIL(AQMP_E_INVALID, tag + "k_per_level out of range");
+    for (int n = p.n_min; n <= p.n_max; n *= 2)
+      if (!d->lv[ilog2(n)].have)
+        AQMP_FAIL(AQMP_E_NODICT, tag + "the dictionary has no block size " + std::to_string(n));
+  }
+  for (int i = 0; i < n_jobs; ++i) {
+    const aqmp_job& j = jobs[i];
+    if (j.image < 0 || j.image >= n_imgs || j.params < 0 || j.params >= n_prm)
+      AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: job " + std::to_string(i) + " refers to a missing image or params");
+    const aqmp_image& im = imgs[j.image];
+    const aqmp_params& p = prm[j.params];
+    if (im.w % p.n_max || im.h % p.n_max)
+      AQMP_FAIL(AQMP_E_SHAPE, "aqmp_encode: job " + std::to_string(i) + ": image " + std::to_string(im.w) + "x" +
+                                  std::to_string(im.h) + " is not a multiple of n_max " + std::to_string(p.n_max));
+  }
+  return AQMP_OK;
+}
+
+int alloc(aqmp_code* c, void** p, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  const int rc = dev_alloc(p, bytes);
+  if (rc == AQMP_OK) c->allocs.push_back({*p, bytes});
+  return rc;
+}
+
+JobDev make_jobdev(const aqmp_image& im, const aqmp_params& p) {
+  JobDev j{};
+  j.img = im.dev_ptr;
+  j.dtype = im.dtype;
+  j.w = im.w;
+  j.h = im.h;
+  j.row_stride = im.row_stride;
+  j.n_min = p.n_min;
+  j.n_max = p.n_max;
+  j.split_rule = p.split_rule;
+  for (int l = 0; l < kLevels; ++l) {
+    const double n = (double)(1 << l);
+    const double eps = p.tol_mode == AQMP_TOL_RMS ? p.tol * n : p.tol;
+    j.eps2[l] = eps * eps;
+    j.k[l] = k_of(p, l);
+  }
+  return j;
+}
+
+void plan_pass(const aqmp_code* c, int j0, int j1, PassPlan& pp) {
+  pp.j0 = j0;
+  pp.j1 = j1;
+  pp.lg_hi = 0;
+  pp.lg_lo = kLevels;
+  for (int j = j0; j < j1; ++j) {
+    const aqmp_image& im = c->imgs[c->jobs[j].image];
+    const aqmp_params& p = c->prm[c->jobs[j].params];
+    const int hi = ilog2(p.n_max), lo = ilog2(p.n_min);
+    pp.lg_hi = std::max(pp.lg_hi, hi);
+    pp.lg_lo = std::min(pp.lg_lo, lo);
+    for (int l = lo; l <= hi; ++l) {
+      const int64_t n = 1 << l;
+      pp.cap[l] += (int64_t)(im.w / n) * (im.h / n);
+      pp.kmax[l] = std::max(pp.kmax[l], k_of(p, l));
+    }
+    pp.ntop[hi] += (im.w >> hi) * (im.h >> hi);
+  }
+}
+
+// Top-level nodes of a pass at one level: jobs in order, blocks in raster order.
+void top_nodes(const aqmp_code* c, const PassPlan& pp, int lg, std::vector<int32_t>& job,
+               std::vector<int32_t>& x0, std::vector<int32_t>& y0) {
+  const int n = 1 << lg;
+  for (int j = pp.j0; j < pp.j1; ++j) {
+    const aqmp_image& im = c->imgs[c->jobs[j].image];
+    const aqmp_params& p = c->prm[c->jobs[j].params];
+    if (p.n_max != n) continue;
+    for (int y = 0; y < im.h; y += n)
+      for (int x = 0; x < im.w; x += n) {
+        job.push_back(j);
+        x0.push_back(x);
+        y0.push_back(y);
+      }
+  }
+}
+
+LevelDev level_at(const aqmp_code* c, int lg, int64_t base) {
+  LevelDev L = c->lv[lg];
+  L.job += base;
+  L.x0 += base;
+  L.y0 += base;
+  L.e += base;
+  L.t += base;
+  L.st += base;
+  L.rec_idx += base * L.kmax;
+  L.rec_coef += base * L.kmax;
+  return L;
+}
+
+void free_code(aqmp_code* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->done) (void)hipEventDestroy(c->done);
+  for (auto& a : c->allocs) dev_free(a.p, a.bytes);
+  delete c;
+}
+
+int build_plan(aqmp_code* c) {
+  const int nj = (int)c->jobs.size();
+  c->hjobs.resize(nj);
+  for (int j = 0; j < nj; ++j) c->hjobs[j] = make_jobdev(c->imgs[c->jobs[j].image], c->prm[c->jobs[j].params]);
+  if (c->opt.schedule == AQMP_SCHED_BATCHED) {
+    c->passes.resize(1);
+    plan_pass(c, 0, nj, c->passes[0]);
+  } else {
+    c->passes.resize(nj);
+    for (int j = 0; j < nj; ++j) plan_pass(c, j, j + 1, c->passes[j]);
+  }
+  // Level arrays: the passes are laid out one after the other.
+  int64_t max_r = 0, max_keys = 0, max_cap = 0;
+  for (auto& pp : c->passes) {
+    for (int l = 0; l < kLevels; ++l) {
+      pp.base[l] = c->cap_total[l];
+      c->cap_total[l] += pp.cap[l];
+      c->kmax_total[l] = std::max(c->kmax_total[l], pp.kmax[l]);
+      const int64_t n = 1 << l;
+      if (pp.cap[l] == 0) continue;
+      const aqmp_dict::Level& D = c->dict->lv[l];
+      max_r = std::max(max_r, pp.cap[l] * n * n);
+      max_keys = std::max(max_keys, pp.cap[l] * (D.m_pad / corr_atom_tile((int)n)) * kTopR);
+      max_cap = std::max(max_cap, pp.cap[l]);
+      c->steps_launched += pp.kmax[l];
+    }
+  }
+#define ALLOC(ptr, bytes)                                      \
+  do {                                                         \
+    const int rc_ = alloc(c, (void**)&(ptr), (size_t)(bytes)); \
+    if (rc_ != AQMP_OK) return rc_;                            \
+  } while (0)
+  for (int l = 0; l < kLevels; ++l) {
+    const int64_t cap = c->cap_total[l];
+    if (cap == 0) continue;
+    LevelDev& L = c->lv[l];
+    L.kmax = std::max(1, c->kmax_total[l]);
+    ALLOC(L.job, cap * 4);
+    ALLOC(L.x0, cap * 4);
+    ALLOC(L.y0, cap * 4);
+    ALLOC(L.e, cap * 8);
+    ALLOC(L.t, cap * 4);
+    ALLOC(L.st, cap);
+    ALLOC(L.rec_idx, cap * L.kmax * 4);
+    ALLOC(L.rec_coef, cap * L.kmax * 8);
+  }
+  ALLOC(c->r32, max_r * 4);
+  if (c->opt.precision == AQMP_PREC_BF16) ALLOC(c->r16, max_r * 2);
+  ALLOC(c->keys, max_keys * 8);
+  ALLOC(c->act[0], max_cap * 4);
+  ALLOC(c->act[1], max_cap * 4);
+  ALLOC(c->djobs, sizeof(JobDev) * nj);
+  ALLOC(c->dcnt, sizeof(Counters) * c->passes.size());
+  ALLOC(c->dntop, sizeof(int32_t) * kLevels * c->passes.size());
+  c->ss.ntiles_max = (int32_t)((max_cap + kScanTile - 1) / kScanTile + 1);
+  ALLOC(c->ss.tiles, sizeof(unsigned long long) * c->ss.ntiles_max);
+  ALLOC(c->ss.ticket, sizeof(int32_t) * 2);
+#undef ALLOC
+  hipStream_t s = c->stream;
+  AQMP_HIP(hipMemsetAsync(c->ss.tiles, 0, sizeof(unsigned long long) * c->ss.ntiles_max, s));
+  AQMP_HIP(hipMemsetAsync(c->ss.ticket, 0, sizeof(int32_t) * 2, s));
+  AQMP_HIP(hipMemsetAsync(c->dcnt, 0, sizeof(Counters) * c->passes.size(), s));
+  // Static top-level node lists.
+  std::vector<int32_t> ntop_all(kLevels * c->passes.size(), 0);
+  for (size_t pi = 0; pi < c->passes.size(); ++pi) {
+    const PassPlan& pp = c->passes[pi];
+    for (int l = 0; l < kLevels; ++l) {
+      ntop_all[pi * kLevels + l] = pp.ntop[l];
+      if (!pp.ntop[l]) continue;
+      std::vector<int32_t> job, x0, y0;
+      top_nodes(c, pp, l, job, x0, y0);
+      const int64_t b = pp.base[l];
+      AQMP_HIP(hipMemcpyAsync(c->lv[l].job + b, job.data(), 4 * job.size(), hipMemcpyHostToDevice, s));
+      AQMP_HIP(hipMemcpyAsync(c->lv[l].x0 + b, x0.data(), 4 * x0.size(), hipMemcpyHostToDevice, s));
+      AQMP_HIP(hipMemcpyAsync(c->lv[l].y0 + b, y0.data(), 4 * y0.size(), hipMemcpyHostToDevice, s));
+      AQMP_HIP(hipStreamSynchronize(s));
+    }
+  }
+  AQMP_HIP(hipMemcpyAsync(c->dntop, ntop_all.data(), 4 * ntop_all.size(), hipMemcpyHostToDevice, s));
+  AQMP_HIP(hipStreamSynchronize(s));
+  AQMP_HIP(hipEventCreateWithFlags(&c->done, hipEventDisableTiming));
+  return AQMP_OK;
+}
+
+#define AQMP_LAUNCH(call)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) AQMP_FAIL(AQMP_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
+  const PassPlan& pp = c->passes[pi];
+  Counters* cnt = c->dcnt + pi;
+  const aqmp_dict* d = c->dict;
+  AQMP_LAUNCH(launch_init_counts(cnt, c->dntop + pi * kLevels, s));
+  for (int l = pp.lg_hi; l >= pp.lg_lo; --l) {
+    if (pp.cap[l] == 0) continue;
+    const int n = 1 << l;
+    const aqmp_dict::Level& D = d->lv[l];
+    StepArgs a{};
+    a.jobs = c->djobs;
+    a.lv = level_at(c, l, pp.base[l]);
+    a.lg = l;
+    a.n_atoms = D.m;
+    a.nfam = d->nfam;
+    a.tab = D.d_tab;
+    a.r32 = c->r32;
+    a.r16 = c->opt.precision == AQMP_PREC_BF16 ? c->r16 : nullptr;
+    a.keys = c->keys;
+    a.n_atom_tiles = D.m_pad / corr_atom_tile(n);
+    int32_t* count = &cnt->count[l];
+    AQMP_LAUNCH(launch_gather(n, a, count, s));
+    AQMP_LAUNCH(launch_compact(nullptr, count, a.lv.st, c->act[0], &cnt->act[0], pp.cap[l], c->ss,
+                               &cnt->scan_error, s));
+    int cur = 0;
+    const void* atoms = c->opt.precision == AQMP_PREC_BF16 ? (const void*)D.d_bf16 : (const void*)D.d_f32;
+    for (int t = 0; t < pp.kmax[l]; ++t) {
+      a.act = c->act[cur];
+      a.act_count = &cnt->act[cur];
+      AQMP_LAUNCH(launch_corr(n, c->opt.precision, atoms, a, D.m_pad, s));
+      AQMP_LAUNCH(launch_select(n, a, s));
+      if (t + 1 < pp.kmax[l])
+        AQMP_LAUNCH(launch_compact(c->act[cur], &cnt->act[cur], a.lv.st, c->act[cur ^ 1], &cnt->act[cur ^ 1],
+                                   pp.cap[l], c->ss, &cnt->scan_error, s));
+      cur ^= 1;
+    }
+    if (l > pp.lg_lo && pp.cap[l - 1] > 0)
+      AQMP_LAUNCH(launch_split_emit(c->djobs, a.lv, count, level_at(c, l - 1, pp.base[l - 1]), pp.ntop[l - 1],
+                                    &cnt->count[l - 1], l, pp.cap[l], c->ss, &cnt->scan_error, s));
+  }
+  return AQMP_OK;
+}
+
+int run(aqmp_code* c, hipStream_t s) {
+  AQMP_HIP(hipMemcpyAsync(c->djobs, c->hjobs.data(), sizeof(JobDev) * c->hjobs.size(), hipMemcpyHostToDevice, s));
+  if (c->opt.schedule == AQMP_SCHED_BATCHED) {
+    if (!c->gexec) {
+      // Capture on a private stream (the caller's may be the null stream,
+      // which cannot be captured); the graph is launched on the caller's.
+      hipStream_t cs = nullptr;
+      AQMP_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        AQMP_FAIL(AQMP_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+      }
+      int rc = enqueue_pass(c, 0, cs);
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(cs, &g);
+      (void)hipStreamDestroy(cs);
+      if (rc != AQMP_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) AQMP_FAIL(AQMP_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+      c->graph = g;
+      AQMP_HIP(hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0));
+    }
+    AQMP_HIP(hipGraphLaunch(c->gexec, s));
+  } else {
+    for (size_t pi = 0; pi < c->passes.size(); ++pi) {
+      const int rc = enqueue_pass(c, pi, s);
+      if (rc != AQMP_OK) return rc;
+    }
+  }
+  c->stream = s;
+  AQMP_HIP(hipEventRecord(c->done, s));
+  return AQMP_OK;
+}
+
+struct HostNode {
+  aqmp_leaf leaf;
+  int64_t key_hi, key_lo;      // canonical order
+  const int32_t* idx;
+  const double* coef;
+};
+
+uint64_t morton(uint32_t x, uint32_t y) {
+  uint64_t m = 0;
+  for (int b = 0; b < 16; ++b) {
+    m |= (uint64_t)((x >> b) & 1u) << (2 * b);
+    m |= (uint64_t)((y >> b) & 1u) << (2 * b + 1);
+  }
+  return m;
+}
+
+// Copies every visited node back and orders them canonically: job, top-level
+// block in raster order, then depth-first (Morton order of the corner, the
+// larger node first).
+int collect(const aqmp_code* c, bool leaves_only, std::vector<HostNode>& out,
+            std::vector<std::vector<int32_t>>& idx_store, std::vector<std::vector<double>>& coef_store) {
+  AQMP_HIP(hipStreamSynchronize(c->stream));
+  std::vector<Counters> cnt(c->passes.size());
+  AQMP_HIP(hipMemcpy(cnt.data(), c->dcnt, sizeof(Counters) * cnt.size(), hipMemcpyDeviceToHost));
+  for (auto& k : cnt)
+    if (k.scan_error) AQMP_FAIL(AQMP_E_HIP, "aqmp_encode: a device scan exceeded its bounded wait");
+  idx_store.clear();
+  coef_store.clear();
+  for (size_t pi = 0; pi < c->passes.size(); ++pi) {
+    const PassPlan& pp = c->passes[pi];
+    for (int l = pp.lg_hi; l >= pp.lg_lo; --l) {
+      const int64_t n = cnt[pi].count[l];
+      if (pp.cap[l] == 0 || n <= 0) continue;
+      if (n > pp.cap[l]) AQMP_FAIL(AQMP_E_HIP, "aqmp_encode: level count exceeds its capacity");
+      const LevelDev L = level_at(c, l, pp.base[l]);
+      std::vector<int32_t> job(n), x0(n), y0(n), t(n);
+      std::vector<double> e(n);
+      std::vector<uint8_t> st(n);
+      AQMP_HIP(hipMemcpy(job.data(), L.job, 4 * n, hipMemcpyDeviceToHost));
+      AQMP_HIP(hipMemcpy(x0.data(), L.x0, 4 * n, hipMemcpyDeviceToHost));
+      AQMP_HIP(hipMemcpy(y0.data(), L.y0, 4 * n, hipMemcpyDeviceToHost));
+      AQMP_HIP(hipMemcpy(t.data(), L.t, 4 * n, hipMemcpyDeviceToHost));
+      AQMP_HIP(hipMemcpy(e.data(), L.e, 8 * n, hipMemcpyDeviceToHost));
+      AQMP_HIP(hipMemcpy(st.data(), L.st, n, hipMemcpyDeviceToHost));
+      idx_store.emplace_back((size_t)n * L.kmax);
+      coef_store.emplace_back((size_t)n * L.kmax);
+      AQMP_HIP(hipMemcpy(idx_store.back().data(), L.rec_idx, 4 * n * L.kmax, hipMemcpyDeviceToHost));
+      AQMP_HIP(hipMemcpy(coef_store.back().data(), L.rec_coef, 8 * n * L.kmax, hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < n; ++i) {
+        const bool split = (st[i] & ST_SPLIT) != 0;
+        if (leaves_only && split) continue;
+        const int nm = c->prm[c->jobs[job[i]].params].n_max;
+        HostNode h{};
+        h.leaf.job = job[i];
+        h.leaf.x0 = x0[i];
+        h.leaf.y0 = y0[i];
+        h.leaf.n = 1 << l;
+        h.leaf.n_atoms = t[i];
+        h.leaf.flags = split ? 1 : 0;
+        h.leaf.resid_sq = e[i];
+        const int64_t img_w = c->imgs[c->jobs[job[i]].image].w;
+        h.key_hi = ((int64_t)job[i] << 40) | ((int64_t)(y0[i] / nm) * (img_w / nm) + x0[i] / nm);
+        h.key_lo = (int64_t)(morton((uint32_t)(x0[i] % nm), (uint32_t)(y0[i] % nm)) << 8) | (255 - l);
+        h.idx = idx_store.back().data() + (size_t)i * L.kmax;
+        h.coef = coef_store.back().data() + (size_t)i * L.kmax;
+        out.push_back(h);
+      }
+    }
+  }
+  std::sort(out.begin(), out.end(), [](const HostNode& a, const HostNode& b) {
+    return a.key_hi != b.key_hi ? a.key_hi < b.key_hi : a.key_lo < b.key_lo;
+  });
+  return AQMP_OK;
+}
+
+}  // namespace
+
+int encode(const aqmp_dict* d, const aqmp_image* imgs, int n_imgs, const aqmp_params* prm, int n_prm,
+           const aqmp_job* jobs, int n_jobs, const aqmp_options* opt, hipStream_t s, aqmp_code** out) {
+  if (!out) AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: out is null");
+  *out = nullptr;
+  int rc = validate(d, imgs, n_imgs, prm, n_prm, jobs, n_jobs, opt);
+  if (rc != AQMP_OK) return rc;
+  aqmp_code* c = new (std::nothrow) aqmp_code();
+  if (!c) AQMP_FAIL(AQMP_E_NOMEM, "aqmp_encode: host allocation failed");
+  c->dict = d;
+  c->stream = s;
+  if (opt) c->opt = *opt;
+  else c->opt.precision = AQMP_PREC_FP32, c->opt.schedule = AQMP_SCHED_PLAIN;
+  c->imgs.assign(imgs, imgs + n_imgs);
+  c->prm.assign(prm, prm + n_prm);
+  c->jobs.assign(jobs, jobs + n_jobs);
+  rc = build_plan(c);
+  if (rc == AQMP_OK) rc = run(c, s);
+  if (rc != AQMP_OK) {
+    const std::string msg = last_error();
+    free_code(c);
+    set_error(msg);
+    return rc;
+  }
+  *out = c;
+  return AQMP_OK;
+}
+
+int reencode(aqmp_code* c, const aqmp_image* imgs, int n_imgs, hipStream_t s) {
+  if (!c || !imgs) AQMP_FAIL(AQMP_E_INVALID, "aqmp_reencode: null argument");
+  if (n_imgs != (int)c->imgs.size()) AQMP_FAIL(AQMP_E_INVALID, "aqmp_reencode: image count differs");
+  for (int i = 0; i < n_imgs; ++i) {
+    const aqmp_image& a = imgs[i];
+    const aqmp_image& b = c->imgs[i];
+    if (!a.dev_ptr || a.dtype != b.dtype || a.w != b.w || a.h != b.h || a.row_stride < a.w)
+      AQMP_FAIL(AQMP_E_INVALID, "aqmp_reencode: image " + std::to_string(i) + " differs in type or shape");
+  }
+  // Wait for any earlier use of the buffers on another stream.
+  if (c->stream != s) AQMP_HIP(hipStreamWaitEvent(s, c->done, 0));
+  c->imgs.assign(imgs, imgs + n_imgs);
+  for (size_t j = 0; j < c->jobs.size(); ++j) {
+    c->hjobs[j].img = c->imgs[c->jobs[j].image].dev_ptr;
+    c->hjobs[j].row_stride = c->imgs[c->jobs[j].image].row_stride;
+  }
+  return run(c, s);
+}
+
+void code_free(aqmp_code* c) { free_code(c); }
+
+int code_stats(const aqmp_code* c, aqmp_stats* s) {
+  if (!c || !s) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_stats: null argument");
+  std::vector<HostNode> nodes;
+  std::vector<std::vector<int32_t>> is;
+  std::vector<std::vector<double>> cs;
+  const int rc = collect(c, false, nodes, is, cs);
+  if (rc != AQMP_OK) return rc;
+  std::memset(s, 0, sizeof(*s));
+  for (const auto& h : nodes) {
+    const int l = ilog2(h.leaf.n);
+    s->nodes[l]++;
+    s->iters_executed += h.leaf.n_atoms;
+    if (!(h.leaf.flags & 1)) {
+      s->leaves[l]++;
+      s->iters_emitted += h.leaf.n_atoms;
+    }
+  }
+  s->steps_launched = c->steps_launched;
+  return AQMP_OK;
+}
+
+int code_sizes(const aqmp_code* c, int64_t* n_leaves, int64_t* n_atoms) {
+  if (!c || !n_leaves || !n_atoms) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_sizes: null argument");
+  aqmp_stats s;
+  const int rc = code_stats(c, &s);
+  if (rc != AQMP_OK) return rc;
+  *n_leaves = 0;
+  for (int l = 0; l < kLevels; ++l) *n_leaves += s.leaves[l];
+  *n_atoms = s.iters_emitted;
+  return AQMP_OK;
+}
+
+int code_export(const aqmp_code* c, bool leaves_only, aqmp_leaf* leaves, int32_t* atom_idx, double* coef,
+                int64_t cap_leaves, int64_t cap_atoms) {
+  if (!c || !leaves || !atom_idx || !coef) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_export: null argument");
+  std::vector<HostNode> nodes;
+  std::vector<std::vector<int32_t>> is;
+  std::vector<std::vector<double>> cs;
+  const int rc = collect(c, leaves_only, nodes, is, cs);
+  if (rc != AQMP_OK) return rc;
+  int64_t na = 0;
+  for (const auto& h : nodes) na += h.leaf.n_atoms;
+  if ((int64_t)nodes.size() > cap_leaves || na > cap_atoms)
+    AQMP_FAIL(AQMP_E_CAPACITY, "aqmp_code_export: need " + std::to_string(nodes.size()) + " records and " +
+                                   std::to_string(na) + " atoms");
+  int64_t off = 0;
+  for (size_t i = 0; i < nodes.size(); ++i) {
+    aqmp_leaf L = nodes[i].leaf;
+    L.atom_off = off;
+    for (int t = 0; t < L.n_atoms; ++t) {
+      atom_idx[off + t] = nodes[i].idx[t];
+      coef[off + t] = nodes[i].coef[t];
+    }
+    off += L.n_atoms;
+    leaves[i] = L;
+  }
+  return AQMP_OK;
+}
+
+int decode(const aqmp_dict* d, const aqmp_code* c, int job, void* out, int dtype, int64_t row_stride,
+           hipStream_t s) {
+  if (!d || !c || !out) AQMP_FAIL(AQMP_E_INVALID, "aqmp_decode: null argument");
+  if (d != c->dict) AQMP_FAIL(AQMP_E_INVALID, "aqmp_decode: code was made with another dictionary");
+  if (job < 0 || job >= (int)c->jobs.size()) AQMP_FAIL(AQMP_E_INVALID, "aqmp_decode: job out of range");
+  if (dtype != AQMP_F32 && dtype != AQMP_F64) AQMP_FAIL(AQMP_E_INVALID, "aqmp_decode: bad dtype");
+  if (row_stride < c->imgs[c->jobs[job].image].w) AQMP_FAIL(AQMP_E_INVALID, "aqmp_decode: row stride too small");
+  AQMP_HIP(hipStreamWaitEvent(s, c->done, 0));
+  size_t pi = 0;
+  while (pi < c->passes.size() && !(job >= c->passes[pi].j0 && job < c->passes[pi].j1)) ++pi;
+  const PassPlan& pp = c->passes[pi];
+  for (int l = pp.lg_hi; l >= pp.lg_lo; --l) {
+    if (pp.cap[l] == 0) continue;
+    AQMP_LAUNCH(launch_decode(1 << l, c->djobs, level_at(c, l, pp.base[l]), &c->dcnt[pi].count[l], job, d->nfam,
+                              d->lv[l].d_tab, out, dtype, row_stride, s));
+  }
+  return AQMP_OK;
+}
+
+}  // namespace aqmp

@@ -1,0 +1,132 @@
+// internal.h - structures shared by the host orchestration and the kernels
+// of the AQMP encoder library.  Not part of the public ABI (see aqmp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "aqmp.h"
+
+namespace aqmp {
+
+// Node status byte.  The low two bits say why MP stopped (or that it is still
+// running); ST_SPLIT is set by the split pass.
+enum : uint8_t {
+  ST_RUN = 0,       // MP continues at the next step
+  ST_ACC = 1,       // stopped: ||r||^2 < eps_N^2 (eq. (2), accuracy)
+  ST_SPARSE = 2,    // stopped: k_N iterations made (eq. (2), sparsity)
+  ST_ZERO = 3,      // stopped: the largest |correlation| is exactly zero
+  ST_SPLIT = 0x10,  // node refined into its four quadrants
+};
+
+constexpr int kLevels = 7;        // log2(N) for N = 1 .. 64
+constexpr int kCand = AQMP_CANDIDATES;
+constexpr int kTopR = 8;          // keys kept per node per atom tile
+constexpr int kScanTile = 1024;   // items per block of the stable scans
+
+inline int ilog2(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+// Per-job table read by the kernels.  eps2 and k are indexed by log2(N).
+struct JobDev {
+  const void* img;
+  int32_t dtype;
+  int32_t w, h;
+  int32_t n_min, n_max;
+  int32_t split_rule;
+  int64_t row_stride;
+  double eps2[kLevels];
+  int32_t k[kLevels];
+  int32_t pad;
+};
+
+// Device-side arrays of one quadtree level (block size N = 1 << lg).  The
+// node arrays are shared by all passes; a pass owns [base, base + cap).
+struct LevelDev {
+  int32_t* job;
+  int32_t* x0;
+  int32_t* y0;
+  double* e;        // ||r||^2 after the last iteration (FP64)
+  int32_t* t;       // iterations made
+  uint8_t* st;      // ST_* status
+  int32_t* rec_idx;   // [node * kmax + t] selected atom
+  double* rec_coef;   // [node * kmax + t] FP64 coefficient
+  int32_t kmax;
+};
+
+// Per-pass counters in device memory.
+struct Counters {
+  int32_t count[kLevels];   // nodes present at each level
+  int32_t act[2];           // active-list lengths (ping-pong)
+  int32_t scan_error;       // set if a bounded scan wait ran out
+  int32_t pad[7];
+};
+
+// Look-back scan bookkeeping: one 64-bit word per tile plus two counters.
+// The last block of every scan launch restores it to zero.
+struct ScanState {
+  unsigned long long* tiles;
+  int32_t* ticket;   // [0] tile ticket, [1] blocks done
+  int32_t ntiles_max;
+};
+
+// Arguments of the per-step kernels of one level.
+struct StepArgs {
+  const JobDev* jobs;
+  LevelDev lv;            // already offset by the pass base
+  int32_t lg;             // log2(N)
+  int32_t n_atoms;        // M (real atoms; the correlation pads to its tile)
+  int32_t nfam;
+  const double* tab;      // FP64 1D tables [nfam][N][N]
+  float* r32;             // residual [node][N*N] FP32, row-major pixels
+  uint16_t* r16;          // BF16 shadow of r32 (null in the FP32 form)
+  const int32_t* act;     // active list (node slots within the pass)
+  const int32_t* act_count;
+  unsigned long long* keys;   // [pos][atom tile][kTopR]
+  int32_t n_atom_tiles;
+};
+
+// ---------------------------------------------------------------------------
+// Launch wrappers (defined in the kernel translation units).
+// ---------------------------------------------------------------------------
+hipError_t launch_init_counts(Counters* c, const int32_t* ntop_dev, hipStream_t s);
+hipError_t launch_gather(int n, const StepArgs& a, const int32_t* count, hipStream_t s);
+hipError_t launch_compact(const int32_t* in_list, const int32_t* in_count, const uint8_t* st,
+                          int32_t* out_list, int32_t* out_count, int64_t cap, ScanState ss,
+                          int32_t* err, hipStream_t s);
+hipError_t launch_split_emit(const JobDev* jobs, LevelDev parent, const int32_t* parent_count,
+                             LevelDev child, int32_t child_ntop, int32_t* child_count,
+                             int32_t lg, int64_t cap, ScanState ss, int32_t* err, hipStream_t s);
+hipError_t launch_corr(int n, int precision, const void* dict_atoms, const StepArgs& a,
+                       int32_t m_pad, hipStream_t s);
+hipError_t launch_select(int n, const StepArgs& a, hipStream_t s);
+hipError_t launch_decode(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t job,
+                         int32_t nfam, const double* tab, void* out, int32_t dtype,
+                         int64_t row_stride, hipStream_t s);
+
+// Tile geometry of the correlation kernel per block size (atoms per tile).
+int corr_atom_tile(int n);
+int corr_grid(int n, int precision);
+
+}  // namespace aqmp
+
+// Opaque public handles.
+struct aqmp_dict {
+  int n_min, n_max;
+  uint32_t families;
+  int nfam;
+  struct Level {
+    bool have = false;
+    int n = 0, k = 0, m = 0, m_pad = 0;
+    std::vector<double> h_tab;     // [nfam][n][n]
+    double* d_tab = nullptr;
+    float* d_f32 = nullptr;        // [m_pad][k]
+    uint16_t* d_bf16 = nullptr;    // [m_pad][k]
+  } lv[aqmp::kLevels];
+};

@@ -1,0 +1,371 @@
+// kernels_corr.hip - the batched correlation of every active node's residual
+// with every atom of D_N (MP step (b): c_a = <r, phi_a> for all a), as an
+// MFMA contraction, fused with a per-node top-R selection so that the
+// correlations never reach HBM.
+//
+// Contraction: C^T[atom][node] = sum_k D[atom][k] * X[node][k], K = N*N,
+// with D stored atom-major ([M_pad][K], K contiguous) and the residuals X
+// node-major ([slot][K]).  Rows of X are gathered through the active list.
+// A workgroup owns a BA (atoms) x BB (nodes) tile and streams K through a
+// double-buffered LDS stage of BK.  Four waves split the tile WA x WB; each
+// wave holds MA x MB accumulators of the 32x32 MFMA shape, so every lane owns
+// one node column and 16 atom rows per accumulator.
+//
+// Epilogue: each lane keeps the R best |c| of its node among its atoms as
+// 32-bit keys (|c| bits with the low byte replaced by 255 - local atom, so a
+// plain unsigned max prefers larger |c| and then the lower atom); the two
+// half-waves and the WA waves are merged, and the R keys of every (node,
+// atom tile) go out as 64-bit keys ((|c| bits) << 32 | ~atom).  The key keeps
+// 15 mantissa bits of |c|: it only ranks candidates for the FP64 re-score.
+#include "internal.h"
+#include "dev_common.h"
+
+namespace aqmp {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+template <int BA_, int BB_, int BK_, int WA_, int WB_>
+struct Cfg {
+  static constexpr int BA = BA_, BB = BB_, BK = BK_, WA = WA_, WB = WB_;
+  static constexpr int WTA = BA / WA, WTB = BB / WB;     // wave tile
+  static constexpr int MA = WTA / 32, MB = WTB / 32;     // 32x32 blocks per wave
+  static_assert(WA * WB == 4, "four waves");
+  static_assert(MA >= 1 && MB >= 1 && BA <= 256, "tile shape");
+};
+
+// Persistent tile walk with an XCD-aware order: workgroup b runs on XCD
+// b % 8; each XCD takes a contiguous chunk of the atom-major tile order, so
+// the workgroups of one XCD share the same few dictionary tiles in its L2.
+struct TileWalk {
+  int ntiles, chunk, xcd, slot, per;
+  __device__ TileWalk(int nt) : ntiles(nt) {
+    xcd = blockIdx.x & 7;
+    slot = blockIdx.x >> 3;
+    per = gridDim.x >> 3;
+    chunk = (nt + 7) >> 3;
+  }
+  __device__ int tile(int j) const { return xcd * chunk + j; }
+};
+
+__device__ inline void insert_key(uint32_t* top, uint32_t v, int R) {
+  for (int j = 0; j < R; ++j) {
+    const uint32_t hi = top[j] > v ? top[j] : v;
+    v = top[j] > v ? v : top[j];
+    top[j] = hi;
+  }
+}
+
+// Shared epilogue: accumulators -> per (node, atom tile) top-R keys.
+template <class C>
+__device__ inline void epilogue(f32x16 (&acc)[C::MA][C::MB], uint32_t* sK, int a0, int a_tile,
+                                int n_atom_tiles, int b0, int count, unsigned long long* keys) {
+  constexpr int R = kTopR;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wa = w % C::WA, wb = w / C::WA;
+#pragma unroll
+  for (int mb = 0; mb < C::MB; ++mb) {
+    uint32_t top[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) top[j] = 0u;
+#pragma unroll
+    for (int ma = 0; ma < C::MA; ++ma) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int loc = wa * C::WTA + ma * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const uint32_t bits = __float_as_uint(fabsf(acc[ma][mb][r]));
+        const uint32_t key = (bits & 0xFFFFFF00u) | (uint32_t)(255 - loc);
+        if (key > top[R - 1]) insert_key(top, key, R);
+      }
+    }
+    // merge with the other half-wave (same node, other atom rows)
+    uint32_t other[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) other[j] = __shfl_xor(top[j], 32, 64);
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      if (other[j] > top[R - 1]) insert_key(top, other[j], R);
+    if (lane < 32) {
+      const int nl = wb * C::WTB + mb * 32 + lane;
+#pragma unroll
+      for (int j = 0; j < R; ++j) sK[(wa * C::BB + nl) * R + j] = top[j];
+    }
+  }
+  __syncthreads();
+  for (int nl = tid; nl < C::BB; nl += 256) {
+    const int pos = b0 + nl;
+    if (pos >= count) continue;
+    uint32_t top[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) top[j] = sK[nl * R + j];
+    for (int q = 1; q < C::WA; ++q)
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const uint32_t v = sK[(q * C::BB + nl) * R + j];
+        if (v > top[R - 1]) insert_key(top, v, R);
+      }
+    unsigned long long* out = keys + ((size_t)pos * n_atom_tiles + a_tile) * R;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const uint32_t atom = (uint32_t)a0 + (255u - (top[j] & 0xFFu));
+      out[j] = ((unsigned long long)(top[j] & 0xFFFFFF00u) << 32) | (unsigned long long)(0xFFFFFFFFu - atom);
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// BF16 x BF16 -> FP32 (v_mfma_f32_32x32x16_bf16).
+// ---------------------------------------------------------------------------
+template <class C>
+__global__ __launch_bounds__(256, 1) void k_corr_bf16(const uint16_t* __restrict__ D,
+                                                      const uint16_t* __restrict__ X,
+                                                      const int32_t* __restrict__ act,
+                                                      const int32_t* __restrict__ act_count,
+                                                      unsigned long long* __restrict__ keys, int K,
+                                                      int n_atom_tiles) {
+  constexpr int BK = C::BK, LDA = BK + 8;         // +16 B per row against bank conflicts
+  constexpr int CPR = BK / 8;                     // 16-byte chunks per row
+  constexpr int NCA = C::BA * CPR, NCB = C::BB * CPR;    // chunks per stage
+  constexpr int CA = (NCA + 255) / 256, CB = (NCB + 255) / 256;
+  __shared__ __attribute__((aligned(16))) uint16_t sA[2][C::BA * LDA];
+  __shared__ __attribute__((aligned(16))) uint16_t sB[2][C::BB * LDA];
+  __shared__ uint32_t sK[C::WA * C::BB * kTopR];
+
+  const int count = *act_count;
+  const int ntB = (count + C::BB - 1) / C::BB;
+  const int ntiles = n_atom_tiles * ntB;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wa = w % C::WA, wb = w / C::WA;
+  const int nst = K / BK;
+  TileWalk walk(ntiles);
+  for (int j = walk.slot; j < walk.chunk; j += walk.per) {
+    const int tile = walk.tile(j);
+    if (tile >= ntiles) break;
+    const int a_tile = tile / ntB, b_tile = tile % ntB;
+    const int a0 = a_tile * C::BA, b0 = b_tile * C::BB;
+
+    const uint16_t* ga[CA];
+    const uint16_t* gb[CB];
+    int la[CA], lb[CB];
+#pragma unroll
+    for (int i = 0; i < CA; ++i) {
+      const int c = tid + 256 * i, row = c / CPR, kc = c % CPR;
+      ga[i] = c < NCA ? D + (size_t)(a0 + row) * K + kc * 8 : nullptr;
+      la[i] = row * LDA + kc * 8;
+    }
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+      const int c = tid + 256 * i, row = c / CPR, kc = c % CPR;
+      const int pos = b0 + row;
+      gb[i] = (c < NCB && pos < count) ? X + (size_t)act[pos] * K + kc * 8 : nullptr;
+      lb[i] = row * LDA + kc * 8;
+    }
+    uint4 ra[CA], rb[CB];
+    auto gload = [&](int s) {
+#pragma unroll
+      for (int i = 0; i < CA; ++i) ra[i] = ga[i] ? *(const uint4*)(ga[i] + s * BK) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < CB; ++i) rb[i] = gb[i] ? *(const uint4*)(gb[i] + s * BK) : make_uint4(0, 0, 0, 0);
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+      for (int i = 0; i < CA; ++i)
+        if (tid + 256 * i < NCA) *(uint4*)&sA[buf][la[i]] = ra[i];
+#pragma unroll
+      for (int i = 0; i < CB; ++i)
+        if (tid + 256 * i < NCB) *(uint4*)&sB[buf][lb[i]] = rb[i];
+    };
+
+    f32x16 acc[C::MA][C::MB];
+#pragma unroll
+    for (int ma = 0; ma < C::MA; ++ma)
+#pragma unroll
+      for (int mb = 0; mb < C::MB; ++mb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[ma][mb][r] = 0.f;
+
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int s = 0; s < nst; ++s) {
+      const int buf = s & 1;
+      if (s + 1 < nst) gload(s + 1);
+#pragma unroll
+      for (int kk = 0; kk < BK / 16; ++kk) {
+        bf16x8 af[C::MA], bfr[C::MB];
+        const int ko = kk * 16 + (lane >> 5) * 8;
+#pragma unroll
+        for (int ma = 0; ma < C::MA; ++ma)
+          af[ma] = *(const bf16x8*)&sA[buf][(wa * C::WTA + ma * 32 + (lane & 31)) * LDA + ko];
+#pragma unroll
+        for (int mb = 0; mb < C::MB; ++mb)
+          bfr[mb] = *(const bf16x8*)&sB[buf][(wb * C::WTB + mb * 32 + (lane & 31)) * LDA + ko];
+#pragma unroll
+        for (int ma = 0; ma < C::MA; ++ma)
+#pragma unroll
+          for (int mb = 0; mb < C::MB; ++mb)
+            acc[ma][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[ma], bfr[mb], acc[ma][mb], 0, 0, 0);
+      }
+      if (s + 1 < nst) lstore(buf ^ 1);
+      __syncthreads();
+    }
+    epilogue<C>(acc, sK, a0, a_tile, n_atom_tiles, b0, count, keys);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 x FP32 -> FP32 (v_mfma_f32_32x32x2f32).  Inside a BK stage the lane
+// half h consumes k in [h*BK/2, (h+1)*BK/2) one MFMA at a time, so a lane
+// reads its operands as contiguous 16-byte chunks (A and B use the same k
+// order, which is all the contraction needs).
+// ---------------------------------------------------------------------------
+template <class C>
+__global__ __launch_bounds__(256, 1) void k_corr_f32(const float* __restrict__ D, const float* __restrict__ X,
+                                                     const int32_t* __restrict__ act,
+                                                     const int32_t* __restrict__ act_count,
+                                                     unsigned long long* __restrict__ keys, int K,
+                                                     int n_atom_tiles) {
+  constexpr int BK = C::BK, LDA = BK + 4;
+  constexpr int CPR = BK / 4;
+  constexpr int NCA = C::BA * CPR, NCB = C::BB * CPR;    // chunks per stage
+  constexpr int CA = (NCA + 255) / 256, CB = (NCB + 255) / 256;
+  __shared__ __attribute__((aligned(16))) float sA[2][C::BA * LDA];
+  __shared__ __attribute__((aligned(16))) float sB[2][C::BB * LDA];
+  __shared__ uint32_t sK[C::WA * C::BB * kTopR];
+
+  const int count = *act_count;
+  const int ntB = (count + C::BB - 1) / C::BB;
+  const int ntiles = n_atom_tiles * ntB;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wa = w % C::WA, wb = w / C::WA;
+  const int nst = K / BK;
+  TileWalk walk(ntiles);
+  for (int j = walk.slot; j < walk.chunk; j += walk.per) {
+    const int tile = walk.tile(j);
+    if (tile >= ntiles) break;
+    const int a_tile = tile / ntB, b_tile = tile % ntB;
+    const int a0 = a_tile * C::BA, b0 = b_tile * C::BB;
+
+    const float* ga[CA];
+    const float* gb[CB];
+    int la[CA], lb[CB];
+#pragma unroll
+    for (int i = 0; i < CA; ++i) {
+      const int c = tid + 256 * i, row = c / CPR, kc = c % CPR;
+      ga[i] = c < NCA ? D + (size_t)(a0 + row) * K + kc * 4 : nullptr;
+      la[i] = row * LDA + kc * 4;
+    }
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+      const int c = tid + 256 * i, row = c / CPR, kc = c % CPR;
+      const int pos = b0 + row;
+      gb[i] = (c < NCB && pos < count) ? X + (size_t)act[pos] * K + kc * 4 : nullptr;
+      lb[i] = row * LDA + kc * 4;
+    }
+    float4 ra[CA], rb[CB];
+    auto gload = [&](int s) {
+#pragma unroll
+      for (int i = 0; i < CA; ++i) ra[i] = ga[i] ? *(const float4*)(ga[i] + s * BK) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int i = 0; i < CB; ++i) rb[i] = gb[i] ? *(const float4*)(gb[i] + s * BK) : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+      for (int i = 0; i < CA; ++i)
+        if (tid + 256 * i < NCA) *(float4*)&sA[buf][la[i]] = ra[i];
+#pragma unroll
+      for (int i = 0; i < CB; ++i)
+        if (tid + 256 * i < NCB) *(float4*)&sB[buf][lb[i]] = rb[i];
+    };
+
+    f32x16 acc[C::MA][C::MB];
+#pragma unroll
+    for (int ma = 0; ma < C::MA; ++ma)
+#pragma unroll
+      for (int mb = 0; mb < C::MB; ++mb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[ma][mb][r] = 0.f;
+
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    const int hk = (lane >> 5) * (BK / 2);
+    for (int s = 0; s < nst; ++s) {
+      const int buf = s & 1;
+      if (s + 1 < nst) gload(s + 1);
+#pragma unroll
+      for (int kc = 0; kc < BK / 8; ++kc) {
+        float4 af[C::MA], bfr[C::MB];
+#pragma unroll
+        for (int ma = 0; ma < C::MA; ++ma)
+          af[ma] = *(const float4*)&sA[buf][(wa * C::WTA + ma * 32 + (lane & 31)) * LDA + hk + kc * 4];
+#pragma unroll
+        for (int mb = 0; mb < C::MB; ++mb)
+          bfr[mb] = *(const float4*)&sB[buf][(wb * C::WTB + mb * 32 + (lane & 31)) * LDA + hk + kc * 4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int ma = 0; ma < C::MA; ++ma)
+#pragma unroll
+            for (int mb = 0; mb < C::MB; ++mb) {
+              const float x = e == 0 ? af[ma].x : e == 1 ? af[ma].y : e == 2 ? af[ma].z : af[ma].w;
+              const float y = e == 0 ? bfr[mb].x : e == 1 ? bfr[mb].y : e == 2 ? bfr[mb].z : bfr[mb].w;
+              acc[ma][mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(x, y, acc[ma][mb], 0, 0, 0);
+            }
+      }
+      if (s + 1 < nst) lstore(buf ^ 1);
+      __syncthreads();
+    }
+    epilogue<C>(acc, sK, a0, a_tile, n_atom_tiles, b0, count, keys);
+  }
+}
+
+using CfgBig = Cfg<256, 128, 64, 2, 2>;     // N >= 16, BF16
+using CfgMid = Cfg<128, 128, 64, 2, 2>;     // N = 8, BF16
+using CfgSmall = Cfg<32, 256, 16, 1, 4>;    // N = 4, BF16
+using CfgBigF = Cfg<256, 128, 32, 2, 2>;    // N >= 16, FP32
+using CfgMidF = Cfg<128, 128, 32, 2, 2>;    // N = 8, FP32
+using CfgSmallF = Cfg<32, 256, 16, 1, 4>;   // N = 4, FP32
+
+constexpr int kCorrGrid = 256;   // one persistent workgroup per CU
+
+}  // namespace
+
+int corr_atom_tile(int n) { return n >= 16 ? 256 : (n == 8 ? 128 : 32); }
+
+int corr_grid(int, int) { return kCorrGrid; }
+
+hipError_t launch_corr(int n, int precision, const void* dict_atoms, const StepArgs& a, int32_t m_pad,
+                       hipStream_t s) {
+  const int K = n * n;
+  const int nat = m_pad / corr_atom_tile(n);
+  if (precision == AQMP_PREC_BF16) {
+    const uint16_t* D = (const uint16_t*)dict_atoms;
+    if (n >= 16)
+      hipLaunchKernelGGL(k_corr_bf16<CfgBig>, dim3(kCorrGrid), dim3(256), 0, s, D, a.r16, a.act, a.act_count,
+                         a.keys, K, nat);
+    else if (n == 8)
+      hipLaunchKernelGGL(k_corr_bf16<CfgMid>, dim3(kCorrGrid), dim3(256), 0, s, D, a.r16, a.act, a.act_count,
+                         a.keys, K, nat);
+    else
+      hipLaunchKernelGGL(k_corr_bf16<CfgSmall>, dim3(kCorrGrid), dim3(256), 0, s, D, a.r16, a.act,
+                         a.act_count, a.keys, K, nat);
+  } else {
+    const float* D = (const float*)dict_atoms;
+    if (n >= 16)
+      hipLaunchKernelGGL(k_corr_f32<CfgBigF>, dim3(kCorrGrid), dim3(256), 0, s, D, a.r32, a.act, a.act_count,
+                         a.keys, K, nat);
+    else if (n == 8)
+      hipLaunchKernelGGL(k_corr_f32<CfgMidF>, dim3(kCorrGrid), dim3(256), 0, s, D, a.r32, a.act, a.act_count,
+                         a.keys, K, nat);
+    else
+      hipLaunchKernelGGL(k_corr_f32<CfgSmallF>, dim3(kCorrGrid), dim3(256), 0, s, D, a.r32, a.act,
+                         a.act_count, a.keys, K, nat);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace aqmp

@@ -1,0 +1,342 @@
+// kernels_mp.hip - per-node Matching Pursuit kernels: gathering a block into
+// its residual, the candidate re-score / coefficient / rank-1 update / norm
+// step of MP (Section 2.2, steps (b)-(c) and eq. (2)), and the decoder of
+// Algorithm 3.
+//
+// Layout: the residual of node slot i is r32[i * N*N + y*N + x] (row-major
+// pixels of the block; the correlation sums over pixels, so the dictionary
+// uses the same order).  Atom a = f*N*N + q*N + p has the 2D shape
+// T_f[p][y] * T_f[q][x]; the constant atom (p = q = 0) is exactly 1/N.
+#include "internal.h"
+#include "dev_common.h"
+
+namespace aqmp {
+
+namespace {
+
+// Pixels of thread `lt` in its node: rows y0..y0+PH-1, columns x0..x0+PW-1.
+template <int N>
+__device__ inline void patch_origin(int lt, int& y0, int& x0) {
+  using G = Geo<N>;
+  y0 = (lt / G::PX) * G::PH;
+  x0 = (lt % G::PX) * G::PW;
+}
+
+// ---------------------------------------------------------------------------
+// Gather: residual r = unravel(block) (Algorithm 2, y := unravel(b)), its
+// squared norm in FP64 and the stop test before the first iteration.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(256) void k_gather(StepArgs a, const int32_t* count_ptr) {
+  using G = Geo<N>;
+  constexpr int K = G::K;
+  __shared__ double s_red[G::NPW][4];
+  const int count = *count_ptr;
+  const int g = threadIdx.x / G::TPN, lt = threadIdx.x % G::TPN;
+  const int lg = a.lg;
+  for (int base = blockIdx.x * G::NPW; base < count; base += gridDim.x * G::NPW) {
+    const int i = base + g;
+    const bool valid = i < count;
+    const int node = valid ? i : 0;
+    const JobDev& jb = a.jobs[a.lv.job[node]];
+    const int bx = a.lv.x0[node], by = a.lv.y0[node];
+    int py, px;
+    patch_origin<N>(lt, py, px);
+    float* r = a.r32 + (size_t)node * K;
+    double e = 0.0;
+#pragma unroll
+    for (int dy = 0; dy < G::PH; ++dy) {
+      const int64_t row = (int64_t)(by + py + dy) * jb.row_stride + bx + px;
+#pragma unroll
+      for (int dx = 0; dx < G::PW; ++dx) {
+        double v;
+        if (jb.dtype == AQMP_F64)
+          v = ((const double*)jb.img)[row + dx];
+        else
+          v = (double)((const float*)jb.img)[row + dx];
+        const float f = (float)v;
+        const int o = (py + dy) * N + px + dx;
+        if (valid) {
+          r[o] = f;
+          if (a.r16) a.r16[(size_t)node * K + o] = f32_to_bf16(f);
+        }
+        e += v * v;
+      }
+    }
+    e = group_sum<G::TPN>(e, s_red[g]);
+    if (valid && lt == 0) {
+      a.lv.e[node] = e;
+      a.lv.t[node] = 0;
+      uint8_t st = ST_RUN;
+      if (e < jb.eps2[lg])
+        st = ST_ACC;
+      else if (jb.k[lg] <= 0)
+        st = ST_SPARSE;
+      a.lv.st[node] = st;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Select/update: one MP iteration for every active node after the
+// correlation pass has left each node's best keys per atom tile.
+//   1. merge the keys into the kCand best candidates;
+//   2. re-score them in FP64 against the FP32 residual (this is also the
+//      coefficient <r, phi_i> of the chosen atom);
+//   3. i = argmax |c| (lowest atom index on ties); stop if max |c| = 0;
+//   4. r <- r - c_i phi_i (FP64 arithmetic, stored in FP32), ||r||^2 in FP64;
+//   5. record (i, c_i), t <- t + 1, stop test of eq. (2).
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(256) void k_select(StepArgs a) {
+  using G = Geo<N>;
+  constexpr int K = G::K;
+  constexpr int TPN = G::TPN;
+  constexpr int L = TPN < 64 ? TPN : 64;   // lanes merging the keys
+  constexpr int KPL = 4;                   // keys per lane (<= 256 keys)
+  __shared__ double s_red[G::NPW][kCand * 4];
+  __shared__ int s_cand[G::NPW][kCand];
+  const int count = *a.act_count;
+  const int g = threadIdx.x / TPN, lt = threadIdx.x % TPN;
+  const int lg = a.lg;
+  const int nkeys = a.n_atom_tiles * kTopR;
+  const double inv_n = 1.0 / N;
+  for (int base = blockIdx.x * G::NPW; base < count; base += gridDim.x * G::NPW) {
+    const int pos = base + g;
+    const bool valid = pos < count;
+    const int node = valid ? a.act[pos] : a.act[base];
+
+    // 1. top kCand keys over the node's per-tile lists.
+    if (lt < L) {
+      unsigned long long k[KPL];
+      const unsigned long long* kp = a.keys + (size_t)(valid ? pos : base) * nkeys;
+#pragma unroll
+      for (int j = 0; j < KPL; ++j) {
+        const int idx = lt + j * L;
+        k[j] = idx < nkeys ? kp[idx] : 0ull;
+      }
+      // sort descending (4-element network)
+#pragma unroll
+      for (int p0 = 0; p0 < KPL; ++p0)
+#pragma unroll
+        for (int p1 = 0; p1 < KPL - 1 - p0; ++p1)
+          if (k[p1] < k[p1 + 1]) {
+            unsigned long long t = k[p1];
+            k[p1] = k[p1 + 1];
+            k[p1 + 1] = t;
+          }
+      for (int r = 0; r < kCand; ++r) {
+        unsigned long long mx = k[0];
+#pragma unroll
+        for (int off = 1; off < L; off <<= 1) {
+          const unsigned long long o = __shfl_xor(mx, off, 64);
+          mx = o > mx ? o : mx;
+        }
+        if (mx != 0ull && k[0] == mx) {
+#pragma unroll
+          for (int j = 0; j < KPL - 1; ++j) k[j] = k[j + 1];
+          k[KPL - 1] = 0ull;
+        }
+        if (lt == 0) {
+          const unsigned atom = 0xFFFFFFFFu - (unsigned)(mx & 0xFFFFFFFFull);
+          s_cand[g][r] = (mx != 0ull && atom < (unsigned)a.n_atoms) ? (int)atom : -1;
+        }
+      }
+    }
+    __syncthreads();
+
+    // 2. FP64 re-score of the candidates.
+    int py, px;
+    patch_origin<N>(lt, py, px);
+    float* r = a.r32 + (size_t)node * K;
+    float rv[G::PH][G::PW];
+#pragma unroll
+    for (int dy = 0; dy < G::PH; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < G::PW; ++dx) rv[dy][dx] = r[(py + dy) * N + px + dx];
+    double c[kCand];
+#pragma unroll
+    for (int ci = 0; ci < kCand; ++ci) {
+      const int atom = s_cand[g][ci];
+      double part = 0.0;
+      if (atom >= 0) {
+        const int f = atom / K, q = (atom % K) / N, p = atom % N;
+        const double* tf = a.tab + (size_t)f * K;
+        if (p == 0 && q == 0) {
+          double s = 0.0;
+#pragma unroll
+          for (int dy = 0; dy < G::PH; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < G::PW; ++dx) s += (double)rv[dy][dx];
+          part = s * inv_n;
+        } else {
+#pragma unroll
+          for (int dy = 0; dy < G::PH; ++dy) {
+            double s = 0.0;
+#pragma unroll
+            for (int dx = 0; dx < G::PW; ++dx) s = fma((double)rv[dy][dx], tf[q * N + px + dx], s);
+            part = fma(tf[p * N + py + dy], s, part);
+          }
+        }
+      }
+      c[ci] = part;
+    }
+    group_sum_n<TPN, kCand>(c, s_red[g]);
+
+    // 3. arg-max over the re-scored candidates, lowest atom index on ties.
+    int best = -1;
+    double bmag = -1.0;
+#pragma unroll
+    for (int ci = 0; ci < kCand; ++ci) {
+      const int atom = s_cand[g][ci];
+      if (atom < 0) continue;
+      const double m = fabs(c[ci]);
+      if (best < 0 || m > bmag || (m == bmag && atom < s_cand[g][best])) {
+        best = ci;
+        bmag = m;
+      }
+    }
+    const JobDev& jb = a.jobs[a.lv.job[node]];
+    const int t = a.lv.t[node];
+    const bool zero = (best < 0 || bmag == 0.0);   // uniform within the group
+    const int atom = zero ? 0 : s_cand[g][best];
+    const double coef = zero ? 0.0 : c[best];
+
+    // 4. rank-1 update and the new squared norm.
+    const int f = atom / K, q = (atom % K) / N, p = atom % N;
+    const double* tf = a.tab + (size_t)f * K;
+    const bool dc = (p == 0 && q == 0);
+    double e = 0.0;
+#pragma unroll
+    for (int dy = 0; dy < G::PH; ++dy) {
+      const double ty = tf[p * N + py + dy];
+#pragma unroll
+      for (int dx = 0; dx < G::PW; ++dx) {
+        const double phi = dc ? inv_n : ty * tf[q * N + px + dx];
+        const float rn = (float)fma(-coef, phi, (double)rv[dy][dx]);
+        const int o = (py + dy) * N + px + dx;
+        if (valid && !zero) {
+          r[o] = rn;
+          if (a.r16) a.r16[(size_t)node * K + o] = f32_to_bf16(rn);
+        }
+        e = fma((double)rn, (double)rn, e);
+      }
+    }
+    e = group_sum<TPN>(e, s_red[g]);
+
+    // 5. record and stop test (a zero correlation stops without a record).
+    if (valid && lt == 0) {
+      if (zero) {
+        a.lv.st[node] = ST_ZERO;
+      } else {
+        const size_t slot = (size_t)node * a.lv.kmax + t;
+        a.lv.rec_idx[slot] = atom;
+        a.lv.rec_coef[slot] = coef;
+        a.lv.t[node] = t + 1;
+        a.lv.e[node] = e;
+        uint8_t st = ST_RUN;
+        if (e < jb.eps2[lg])
+          st = ST_ACC;
+        else if (t + 1 >= jb.k[lg])
+          st = ST_SPARSE;
+        a.lv.st[node] = st;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Decoder (Algorithm 3): every leaf of `job` at this level writes
+// sum_t c_t phi_{i_t} at its position.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(256) void k_decode(const JobDev* jobs, LevelDev lv, const int32_t* count_ptr,
+                                                int32_t job, const double* tab, void* out, int32_t dtype,
+                                                int64_t row_stride) {
+  using G = Geo<N>;
+  constexpr int K = G::K;
+  const int count = *count_ptr;
+  const int g = threadIdx.x / G::TPN, lt = threadIdx.x % G::TPN;
+  const double inv_n = 1.0 / N;
+  for (int base = blockIdx.x * G::NPW; base < count; base += gridDim.x * G::NPW) {
+    const int i = base + g;
+    if (i >= count) continue;
+    if (lv.job[i] != job || (lv.st[i] & ST_SPLIT)) continue;
+    int py, px;
+    patch_origin<N>(lt, py, px);
+    double acc[G::PH][G::PW];
+#pragma unroll
+    for (int dy = 0; dy < G::PH; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < G::PW; ++dx) acc[dy][dx] = 0.0;
+    const int na = lv.t[i];
+    for (int s = 0; s < na; ++s) {
+      const size_t slot = (size_t)i * lv.kmax + s;
+      const int atom = lv.rec_idx[slot];
+      const double coef = lv.rec_coef[slot];
+      const int f = atom / K, q = (atom % K) / N, p = atom % N;
+      const double* tf = tab + (size_t)f * K;
+      const bool dc = (p == 0 && q == 0);
+#pragma unroll
+      for (int dy = 0; dy < G::PH; ++dy) {
+        const double ty = tf[p * N + py + dy];
+#pragma unroll
+        for (int dx = 0; dx < G::PW; ++dx) {
+          const double phi = dc ? inv_n : ty * tf[q * N + px + dx];
+          acc[dy][dx] = fma(coef, phi, acc[dy][dx]);
+        }
+      }
+    }
+    const int bx = lv.x0[i], by = lv.y0[i];
+#pragma unroll
+    for (int dy = 0; dy < G::PH; ++dy) {
+      const int64_t row = (int64_t)(by + py + dy) * row_stride + bx + px;
+#pragma unroll
+      for (int dx = 0; dx < G::PW; ++dx) {
+        if (dtype == AQMP_F64)
+          ((double*)out)[row + dx] = acc[dy][dx];
+        else
+          ((float*)out)[row + dx] = (float)acc[dy][dx];
+      }
+    }
+  }
+}
+
+template <int N>
+int grid_for(int per_cu) {
+  return 256 * per_cu;
+}
+
+}  // namespace
+
+#define AQMP_DISPATCH_N(n, CALL)         \
+  switch (n) {                           \
+    case 4: { constexpr int NN = 4; CALL; } break;   \
+    case 8: { constexpr int NN = 8; CALL; } break;   \
+    case 16: { constexpr int NN = 16; CALL; } break; \
+    case 32: { constexpr int NN = 32; CALL; } break; \
+    case 64: { constexpr int NN = 64; CALL; } break; \
+    default: return hipErrorInvalidValue;            \
+  }
+
+hipError_t launch_gather(int n, const StepArgs& a, const int32_t* count, hipStream_t s) {
+  AQMP_DISPATCH_N(n, hipLaunchKernelGGL(k_gather<NN>, dim3(grid_for<NN>(8)), dim3(256), 0, s, a, count));
+  return hipGetLastError();
+}
+
+hipError_t launch_select(int n, const StepArgs& a, hipStream_t s) {
+  AQMP_DISPATCH_N(n, hipLaunchKernelGGL(k_select<NN>, dim3(grid_for<NN>(8)), dim3(256), 0, s, a));
+  return hipGetLastError();
+}
+
+hipError_t launch_decode(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t job,
+                         int32_t nfam, const double* tab, void* out, int32_t dtype, int64_t row_stride,
+                         hipStream_t s) {
+  (void)nfam;
+  AQMP_DISPATCH_N(n, hipLaunchKernelGGL(k_decode<NN>, dim3(grid_for<NN>(4)), dim3(256), 0, s, jobs, lv,
+                                        count, job, tab, out, dtype, row_stride));
+  return hipGetLastError();
+}
+
+}  // namespace aqmp

@@ -1,0 +1,156 @@
+"""Node-by-node comparison of the GPU encoder's quadtree with the oracle's.
+
+Rules (per node, in the oracle's iteration order):
+* atom tie: the oracle's relative gap between its two best distinct atoms is
+  below 1e-6 and the GPU chose another atom whose oracle correlation is within
+  that window; the rest of the node and its subtree are then excluded;
+* stop tie: the oracle's squared residual norm is within 1e-6 ||y||^2 of
+  eps_N^2 where the two sides took a different stop or split decision;
+  the node's subtree is excluded;
+* everything else must be identical: visited node set, per-node atom index
+  sequence, number of iterations and split decision;
+* coefficients: |c_gpu - c_orc| / max(|c_orc|, 1e-3 ||y||) <= coef_tol.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from oracle import aqmp_oracle as O
+
+GAP_TIE = 1e-6
+STOP_TIE = 1e-6
+
+
+@dataclass
+class Report:
+    nodes: int = 0
+    iters: int = 0
+    atom_ties: int = 0
+    stop_ties: int = 0
+    excluded_nodes: int = 0
+    max_coef_err: float = 0.0
+    max_coef_err_unfloored: float = 0.0
+    failures: list = field(default_factory=list)
+
+    def ok(self) -> bool:
+        return not self.failures
+
+    def summary(self) -> str:
+        return (f"nodes={self.nodes} iters={self.iters} atom_ties={self.atom_ties} stop_ties={self.stop_ties} "
+                f"excluded={self.excluded_nodes} max_coef_err={self.max_coef_err:.3e} "
+                f"failures={len(self.failures)} {self.failures[:5]}")
+
+
+def gpu_nodes_by_key(exp, job: int) -> dict:
+    """{(x0, y0, n): (idx list, coef list, split flag, resid_sq)} of one job."""
+    out = {}
+    lv = exp.leaves
+    sel = np.nonzero(lv["job"] == job)[0]
+    for r in sel:
+        rec = lv[r]
+        o, na = int(rec["atom_off"]), int(rec["n_atoms"])
+        out[(int(rec["x0"]), int(rec["y0"]), int(rec["n"]))] = (
+            exp.atom_idx[o:o + na].tolist(), exp.coef[o:o + na].tolist(), bool(rec["flags"] & 1),
+            float(rec["resid_sq"]))
+    return out
+
+
+def _is_near_tie_member(img, nd: O.Node, t: int, gpu_atom: int, families: int) -> bool:
+    """Replays the oracle's MP on the node up to step t and checks that the GPU's
+    atom is within the 1e-6 relative window of the best |correlation|."""
+    dic = O.get_dict(nd.n, families)
+    r = O.unravel(img[nd.y0:nd.y0 + nd.n, nd.x0:nd.x0 + nd.n]).copy()
+    for i, c in zip(nd.mp.idx[:t], nd.mp.coef[:t]):
+        r = r - c * dic.D[:, i]
+    c = np.abs(dic.Dt @ r)
+    return c[gpu_atom] >= c.max() * (1.0 - GAP_TIE)
+
+
+def compare_job(img, onodes: list, gpu: dict, coef_tol: float, n_max: int, families: int = O.DCT | O.HAAR,
+                rep: Report | None = None) -> Report:
+    """Compares the oracle's visited nodes (one job; possibly a subset of top
+    blocks) with the GPU's nodes of that job."""
+    rep = rep or Report()
+    okeys = {(nd.x0, nd.y0, nd.n): nd for nd in onodes}
+    excluded: list[tuple[int, int, int]] = []
+
+    def inside(key) -> bool:
+        x, y, n = key
+        for (ex, ey, en) in excluded:
+            if ex <= x and x + n <= ex + en and ey <= y and y + n <= ey + en:
+                return True
+        return False
+
+    for nd in onodes:            # depth-first order: parents before children
+        key = (nd.x0, nd.y0, nd.n)
+        if inside(key):
+            rep.excluded_nodes += 1
+            continue
+        if key not in gpu:
+            rep.failures.append(("missing node on GPU", key))
+            continue
+        g_idx, g_coef, g_split, g_e = gpu[key]
+        rep.nodes += 1
+        ynorm = float(np.sqrt(nd.norm2))
+        o_idx, o_coef = nd.mp.idx, nd.mp.coef
+        diverged = False
+        for t in range(min(len(o_idx), len(g_idx))):
+            if o_idx[t] != g_idx[t]:
+                if nd.mp.gap[t] < GAP_TIE and _is_near_tie_member(img, nd, t, g_idx[t], families):
+                    rep.atom_ties += 1
+                    excluded.append(key)
+                else:
+                    rep.failures.append(("atom mismatch", key, t, o_idx[t], g_idx[t], nd.mp.gap[t]))
+                diverged = True
+                break
+            rep.iters += 1
+            den = max(abs(o_coef[t]), 1e-3 * ynorm)
+            err = abs(g_coef[t] - o_coef[t]) / den
+            rep.max_coef_err = max(rep.max_coef_err, err)
+            if o_coef[t] != 0:
+                rep.max_coef_err_unfloored = max(rep.max_coef_err_unfloored,
+                                                 abs(g_coef[t] - o_coef[t]) / abs(o_coef[t]))
+            if err > coef_tol:
+                rep.failures.append(("coef", key, t, o_coef[t], g_coef[t], err))
+        if diverged:
+            continue
+        stop_tie_window = STOP_TIE * nd.norm2
+        if len(o_idx) != len(g_idx):
+            t = min(len(o_idx), len(g_idx))
+            if abs(nd.mp.e[t] - nd.eps2) <= stop_tie_window:
+                rep.stop_ties += 1
+                excluded.append(key)
+            else:
+                rep.failures.append(("iteration count", key, len(o_idx), len(g_idx)))
+            continue
+        if g_split != nd.split:
+            if abs(nd.mp.e_final - nd.eps2) <= stop_tie_window:
+                rep.stop_ties += 1
+                excluded.append(key)
+            else:
+                rep.failures.append(("split", key, nd.split, g_split, nd.mp.e_final, nd.eps2))
+            continue
+    # GPU nodes inside the compared region that the oracle never visited
+    tops = {(nd.x0, nd.y0) for nd in onodes if nd.n == n_max}
+    for key in gpu:
+        x, y, n = key
+        if (x - x % n_max, y - y % n_max) in tops and key not in okeys and not inside(key):
+            rep.failures.append(("extra node on GPU", key))
+    return rep
+
+
+def decode_region(img_shape, onodes, families=O.DCT | O.HAAR):
+    return O.decode(onodes, img_shape[0], img_shape[1], families)
+
+
+def psnr_region(ref, rec, blocks, n):
+    """PSNR over the union of the given top-level blocks (peak 1)."""
+    se, cnt = 0.0, 0
+    for (x0, y0) in blocks:
+        d = ref[y0:y0 + n, x0:x0 + n] - rec[y0:y0 + n, x0:x0 + n]
+        se += float(np.sum(d * d))
+        cnt += d.size
+    mse = se / cnt
+    return float("inf") if mse == 0 else 10 * np.log10(1.0 / mse)

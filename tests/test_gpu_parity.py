@@ -1,0 +1,133 @@
+"""GPU path vs the FP64 oracle, node by node (all calls go through the C ABI).
+
+Tolerances: identical quadtree and atom sequences except counted atom/stop
+ties; coefficients within 1e-5 (FP32 correlation) or 2e-3 (BF16
+correlation) relative, floored at 1e-3 ||y||; PSNR within 0.01 dB.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import aqmp_oracle as O
+from tests import parity_util as PU
+from workloads import workload, gradient_edges_image, piecewise_image
+
+pytestmark = pytest.mark.gpu
+
+COEF_TOL = {0: 1e-5, 1: 2e-3}
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_09190_amd import aqmp
+    return aqmp
+
+
+@pytest.fixture(scope="module")
+def dic(A):
+    d = A.Dictionary(4, 64)
+    yield d
+    d.free()
+
+
+def _dev(img, dtype="f32"):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(img))
+    t = t.to(torch.float32 if dtype == "f32" else torch.float64)
+    return t.cuda()
+
+
+def _encode(A, dic, chans, params, jobs, prec, sched, dtype="f32"):
+    imgs = [_dev(c, dtype) for c in chans]
+    code = A.Code(dic, imgs, params, jobs, precision=prec, schedule=sched)
+    return code, imgs
+
+
+def _check(A, code, chans, params, jobs, prec, blocks_per_job=None):
+    exp = code.export_nodes()
+    rep = PU.Report()
+    for j, (ci, pi) in enumerate(jobs):
+        img = chans[ci]
+        p = O.Params.from_dict(params[pi])
+        blocks = None if blocks_per_job is None else blocks_per_job[j]
+        onodes = O.encode_channel(img, p, blocks=blocks)
+        gpu = PU.gpu_nodes_by_key(exp, j)
+        PU.compare_job(img, onodes, gpu, COEF_TOL[prec], p.n_max, rep=rep)
+    return rep
+
+
+@pytest.mark.parametrize("prec,sched", [(0, 0), (1, 1), (0, 1), (1, 0)])
+def test_c0_full_parity(A, dic, prec, sched):
+    w = workload("c0")
+    _say("c0", prec, sched)
+    code, imgs = _encode(A, dic, w["channels"], w["params"], w["jobs"], prec, sched)
+    rep = _check(A, code, w["channels"], w["params"], w["jobs"], prec)
+    _say(rep.summary())
+    assert rep.ok(), rep.summary()
+    assert rep.nodes > 10
+
+
+def test_c0_dictionary_matches_oracle(A, dic):
+    for n in (4, 8, 16, 32, 64):
+        g = dic.copy(n)
+        o = O.get_dict(n).D
+        assert g.shape == o.shape
+        assert np.all(g[:, 0] == 1.0 / n) and np.all(g[:, n * n] == 1.0 / n)
+        assert np.abs(g - o).max() < 4e-16
+
+
+def test_decode_psnr_matches_oracle(A, dic):
+    import torch
+    w = workload("c0")
+    img = w["channels"][0]
+    p = O.Params.from_dict(w["params"][0])
+    onodes = O.encode_channel(img, p)
+    ps_o = O.psnr(img, O.decode(onodes, 64, 64))
+    for prec in (0, 1):
+        code, imgs = _encode(A, dic, w["channels"], w["params"], w["jobs"], prec, 1)
+        out = torch.zeros(64, 64, dtype=torch.float64, device="cuda")
+        code.decode(0, out)
+        torch.cuda.synchronize()
+        ps_g = O.psnr(img, out.cpu().numpy())
+        _say("psnr", prec, ps_o, ps_g)
+        assert abs(ps_g - ps_o) < 0.01
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_c1_sampled_parity(A, dic, prec):
+    w = workload("c1")
+    img = w["channels"][0]
+    p = w["params"][0]
+    rng = np.random.default_rng(11)
+    tops = O.top_blocks(512, 512, 64)
+    sample = [tops[i] for i in sorted(rng.choice(len(tops), size=6, replace=False))]
+    _say("c1 sample", prec, sample)
+    code, imgs = _encode(A, dic, [img], [p], [(0, 0)], prec, 1)
+    rep = _check(A, code, [img], [p], [(0, 0)], prec, blocks_per_job=[sample])
+    _say(rep.summary())
+    assert rep.ok(), rep.summary()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mixed_jobs_small_sizes(A, dic, prec):
+    """Several jobs with different block ranges (4..32), k, tolerances and both
+    split rules in one batched pass, plus an FP64 input plane."""
+    chans = [gradient_edges_image(64, 64, seed=3), piecewise_image(64, 128, seed=4)]
+    params = [dict(tol=0.03, max_atoms=8, n_min=4, n_max=16),
+              dict(tol=0.01, max_atoms=20, n_min=8, n_max=32, split_rule="r2"),
+              dict(tol=0.5, tol_mode="abs", max_atoms=40, n_min=4, n_max=32)]
+    jobs = [(0, 0), (1, 1), (0, 2), (1, 0)]
+    _say("mixed", prec)
+    code, imgs = _encode(A, dic, chans, params, jobs, prec, 1, dtype="f64")
+    rep = _check(A, code, chans, params, jobs, prec)
+    _say(rep.summary())
+    assert rep.ok(), rep.summary()
