@@ -1,0 +1,250 @@
+"""Benchmark of the AQMP encoder on one MI355X.
+
+A step is one complete encode of the workload (every job, every quadtree
+level, every MP step: gather, correlation + top-R, re-score / update / norm,
+compaction, split / emit) with the input planes already in HBM.  The headline
+form is the batched BF16 encode (one graph for all jobs); the plain FP32 form
+(jobs one after another, FP32 correlation) runs on the same input for the
+comparison at equal PSNR.  One JSON line is printed on stdout.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c1|c4]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "AQMP encode Mpixel/s (batched BF16 vs plain FP32) at equal PSNR; MP iters/s"
+PEAK_BF16_TFLOPS = 2500.0     # MI355X dense BF16 MFMA
+PEAK_FP32_TFLOPS = 157.3      # MI355X dense FP32 MFMA
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def to_device(chans):
+    import torch
+    return [torch.from_numpy(np.ascontiguousarray(c)).to(torch.float32).cuda() for c in chans]
+
+
+def time_steps(code, imgs, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        code.reencode(imgs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        code.reencode(imgs)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def psnr_jobs(code, imgs, jobs):
+    import torch
+    out = []
+    for j, (ci, _) in enumerate(jobs):
+        rec = torch.zeros_like(imgs[ci], dtype=torch.float64)
+        code.decode(j, rec)
+        d = rec - imgs[ci].to(torch.float64)
+        mse = float((d * d).mean())
+        out.append(float("inf") if mse == 0 else 10.0 * np.log10(1.0 / mse))
+    return out
+
+
+def roofline(stats, timing, precision):
+    """Dominant kernel: the correlation of the largest block size.  Algorithmic
+    work per node-iteration is 2*K*M = 4 N^4 flops (every atom correlated with
+    the residual); one launch processes the nodes active in that MP step."""
+    lg = max(l for l in range(7) if stats["iters_level"][l] > 0)
+    n = 1 << lg
+    flops = 4.0 * n ** 4 * stats["iters_level"][lg]
+    ms = timing["corr_ms"][lg]
+    steps = timing["steps"][lg]
+    peak = PEAK_BF16_TFLOPS if precision == 1 else PEAK_FP32_TFLOPS
+    achieved = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    per_level = {}
+    for l in range(7):
+        if stats["iters_level"][l] and timing["corr_ms"][l] > 0:
+            nn = 1 << l
+            a = 4.0 * nn ** 4 * stats["iters_level"][l] / (timing["corr_ms"][l] * 1e-3) / 1e12
+            per_level[str(nn)] = dict(tflops=round(a, 2), frac=round(a / peak, 4),
+                                      corr_ms=round(timing["corr_ms"][l], 3),
+                                      select_ms=round(timing["select_ms"][l], 3),
+                                      level_ms=round(timing["level_ms"][l], 3),
+                                      launches=int(timing["steps"][l]),
+                                      avg_corr_us=round(1e3 * timing["corr_ms"][l] / max(1, timing["steps"][l]), 2))
+    return dict(bound="mfma", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
+                frac=round(achieved / peak, 4), traffic=None,
+                kernel=f"k_corr_{'bf16' if precision == 1 else 'f32'}<N={n}>",
+                avg_launch_us=round(1e3 * ms / max(1, steps), 2), launches=int(steps),
+                flops_per_unit=4 * n ** 4, units=int(stats["iters_level"][lg]), per_level=per_level)
+
+
+def _oracle_block(args):
+    ci, x0, y0, prm = args
+    from oracle import aqmp_oracle as O
+    img = _ORACLE_CHANS[ci]
+    nodes = O.encode_block(img, O.Params.from_dict(prm), x0, y0, prm["n_max"])
+    return sum(nd.mp.t for nd in nodes)
+
+
+_ORACLE_CHANS = None
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """The FP64 oracle on a seeded sample of top-level blocks of the same
+    workload, process-parallel over blocks on the host cores."""
+    global _ORACLE_CHANS
+    import multiprocessing as mp
+    from threadpoolctl import threadpool_limits
+    from oracle import aqmp_oracle as O
+    _ORACLE_CHANS = w["channels"]
+    prm = dict(w["params"][0])
+    nmax = prm["n_max"]
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    for n in (8, 16, 32, 64):
+        if prm["n_min"] <= n <= nmax:
+            O.get_dict(n)        # built once, shared with the workers by fork
+    rng = np.random.default_rng(1234)
+    blocks = []
+    for j, (ci, _) in enumerate(w["jobs"]):
+        h, wd = w["channels"][ci].shape
+        for (x0, y0) in O.top_blocks(h, wd, nmax):
+            blocks.append((ci, x0, y0, prm))
+    order = rng.permutation(len(blocks))
+    # calibrate on a few blocks, then size the sample to the time budget
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        with mp.get_context("fork").Pool(cores) as pool:
+            calib = [blocks[i] for i in order[:cores]]
+            it = pool.map(_oracle_block, calib)
+            t1 = time.perf_counter() - t0
+            per_round = max(t1, 1e-3)
+            rounds = max(1, int(round(budget_s / per_round)))
+            rest = [blocks[i] for i in order[cores:cores * (1 + rounds)]]
+            t2 = time.perf_counter()
+            it2 = pool.map(_oracle_block, rest)
+            t3 = time.perf_counter() - t2
+    nb = len(rest)
+    px = nb * nmax * nmax
+    return dict(value=round(px / t3 / 1e6, 6), unit="Mpixel/s", cores=cores, kind="oracle",
+                sample=f"{nb} of {len(blocks)} top-level {nmax}x{nmax} blocks (seed 1234), all levels below them, "
+                       f"FP64 NumPy, one process per core, {t3:.1f} s",
+                mp_iters_per_s=round(sum(it2) / t3, 1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--fp32-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the encoder is a single-GPU path (--gpus {args.gpus} "
+              f"requested); see the sharding notes in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2605_09190_amd import aqmp as A
+    from workloads import workload
+
+    log("generating workload", args.workload)
+    w = workload(args.workload)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before any device call: the oracle's worker processes are forked
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(w)
+    imgs = to_device(w["channels"])
+    npx = sum(int(w["channels"][ci].size) for ci, _ in w["jobs"])
+    nmin = min(p["n_min"] for p in w["params"])
+    nmax = max(p["n_max"] for p in w["params"])
+    dic = A.Dictionary(nmin, nmax)
+
+    # Headline: batched BF16, all jobs in one captured graph, replayed.
+    log("batched bf16: build + capture")
+    code = A.Code(dic, imgs, w["params"], w["jobs"], precision=A.PREC_BF16, schedule=A.SCHED_BATCHED)
+    torch.cuda.synchronize()
+    sec = time_steps(code, imgs, args.steps, args.warmup)
+    stats = code.stats()
+    psnr_b = psnr_jobs(code, imgs, w["jobs"])
+    log(f"bf16 batched (graph): {sec * 1e3:.3f} ms/step")
+
+    # Kernel durations: the same batched launch sequence with HIP events
+    # around every MP-step launch (events cannot be timed inside a graph, so
+    # this encode is issued on the stream), K steps, then the roofline of the
+    # dominant kernel from the summed event times.
+    code_t = A.Code(dic, imgs, w["params"], w["jobs"], precision=A.PREC_BF16, schedule=A.SCHED_BATCHED,
+                    timing=True)
+    sec_t = time_steps(code_t, imgs, args.steps, args.warmup)
+    roof = roofline(code_t.stats(), code_t.timing(), A.PREC_BF16)
+    code_t.free()
+    log(f"bf16 batched (stream, timed): {sec_t * 1e3:.3f} ms/step, corr {roof['achieved']} TFLOP/s")
+
+    fp32 = None
+    if not args.no_fp32:
+        log("plain fp32")
+        code3 = A.Code(dic, imgs, w["params"], w["jobs"], precision=A.PREC_FP32, schedule=A.SCHED_PLAIN,
+                       timing=True)
+        torch.cuda.synchronize()
+        sec3 = time_steps(code3, imgs, args.fp32_steps, 1)
+        st3 = code3.stats()
+        psnr_f = psnr_jobs(code3, imgs, w["jobs"])
+        roof3 = roofline(st3, code3.timing(), A.PREC_FP32)
+        fp32 = dict(value=round(npx / sec3 / 1e6, 3), ms_per_step=round(sec3 * 1e3, 3), steps=args.fp32_steps,
+                    mp_iters_per_s=round(st3["iters_executed"] / sec3, 1), psnr_db=[round(p, 4) for p in psnr_f],
+                    corr_tflops=roof3["achieved"], corr_frac_fp32_peak=roof3["frac"],
+                    leaves=int(sum(st3["leaves"])))
+        code3.free()
+        log(f"fp32 plain: {sec3 * 1e3:.3f} ms/step")
+
+    value = npx / sec / 1e6
+    res = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "jobs": len(w["jobs"]), "pixels_per_step": npx,
+                   "form": "batched: all jobs in one HIP graph, BF16 MFMA correlation, top-8 FP64 re-score"},
+        "mp_iters_per_s": round(stats["iters_executed"] / sec, 1),
+        "mp_iters_executed": int(stats["iters_executed"]),
+        "mp_iters_emitted": int(stats["iters_emitted"]),
+        "leaves": int(sum(stats["leaves"])),
+        "ms_per_step_stream_timed": round(sec_t * 1e3, 4),
+        "psnr_db": [round(p, 4) for p in psnr_b],
+        "fp32_plain": fp32,
+        "roofline": roof,
+    }
+    if fp32:
+        res["speedup_vs_fp32_plain"] = round(value / fp32["value"], 2)
+        res["max_abs_psnr_delta_db"] = round(max(abs(a - b) for a, b in zip(psnr_b, fp32["psnr_db"])), 5)
+    code.free()
+    dic.free()
+    if cpu is not None:
+        res["cpu_baseline"] = cpu
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -108,6 +108,8 @@ typedef struct {
   int32_t params;
 } aqmp_job;
 
+enum { AQMP_OPT_TIMING = 1 };   /* aqmp_options.flags */
+
 typedef struct {
   int32_t precision;   /* AQMP_PREC_FP32: FP32 MFMA correlation;
                           AQMP_PREC_BF16: BF16 MFMA, FP32 accumulate.
@@ -118,7 +120,12 @@ typedef struct {
                           stream-ordered launches;
                           AQMP_SCHED_BATCHED: every job in one pass,
                           captured once as a HIP graph and replayed. */
-  int32_t reserved[6];
+  int32_t flags;       /* AQMP_OPT_TIMING: record HIP events around every
+                          launch of an MP step (see aqmp_code_timing).
+                          Events cannot be timed inside a graph, so a timed
+                          batched encode issues the same launches directly
+                          on the stream. */
+  int32_t reserved[5];
 } aqmp_options;
 
 /* A leaf of the quadtree (or, from aqmp_code_export_nodes, any visited
@@ -136,10 +143,20 @@ typedef struct {
 typedef struct {
   int64_t nodes[7];         /* visited nodes per log2(N)                    */
   int64_t leaves[7];        /* leaves per log2(N)                           */
+  int64_t iters_level[7];   /* MP iterations executed per log2(N)           */
   int64_t iters_executed;   /* MP iterations, nodes later split included    */
   int64_t iters_emitted;    /* MP iterations kept in leaves                 */
   int64_t steps_launched;   /* MP steps issued (levels x k)                 */
 } aqmp_stats;
+
+/* Device time of the last encode, per log2(N), from HIP events recorded
+ * around the launches (only with AQMP_OPT_TIMING). */
+typedef struct {
+  double corr_ms[7];        /* correlation + top-R key launches             */
+  double select_ms[7];      /* re-score / update / norm launches            */
+  double level_ms[7];       /* whole level: gather .. split/emit            */
+  int64_t steps[7];         /* MP steps timed                               */
+} aqmp_timing;
 
 /* ---- dictionaries (Section 2.1; Section 2.3 "D_N assumed available") --- */
 
@@ -199,6 +216,11 @@ int aqmp_code_export_nodes(const aqmp_code* c, aqmp_leaf* nodes, int32_t* atom_i
                            double* coef, int64_t cap_nodes, int64_t cap_atoms);
 
 int aqmp_code_stats(const aqmp_code* c, aqmp_stats* s);
+
+/* Synchronises the encode stream and sums the per-launch event times of the
+ * last encode or re-encode.  AQMP_E_INVALID if the code was not made with
+ * AQMP_OPT_TIMING. */
+int aqmp_code_timing(const aqmp_code* c, aqmp_timing* t);
 
 /* Null-safe; waits for the handle's stream work first. */
 void aqmp_code_free(aqmp_code* c);

@@ -28,6 +28,7 @@ TOL_RMS, TOL_ABS = 0, 1
 SPLIT_R1, SPLIT_R2 = 0, 1
 PREC_FP32, PREC_BF16 = 0, 1
 SCHED_PLAIN, SCHED_BATCHED = 0, 1
+OPT_TIMING = 1
 MAX_ATOMS = 256
 CANDIDATES = 8
 
@@ -35,7 +36,7 @@ CANDIDATES = 8
 EXPORTS = [
     "aqmp_dictionary_build", "aqmp_dictionary_free", "aqmp_dictionary_atoms", "aqmp_dictionary_copy",
     "aqmp_encode", "aqmp_reencode", "aqmp_code_sizes", "aqmp_code_export", "aqmp_code_export_nodes",
-    "aqmp_code_stats", "aqmp_code_free", "aqmp_decode", "aqmp_last_error",
+    "aqmp_code_stats", "aqmp_code_timing", "aqmp_code_free", "aqmp_decode", "aqmp_last_error",
 ]
 
 
@@ -55,7 +56,8 @@ class Job(C.Structure):
 
 
 class Options(C.Structure):
-    _fields_ = [("precision", C.c_int32), ("schedule", C.c_int32), ("reserved", C.c_int32 * 6)]
+    _fields_ = [("precision", C.c_int32), ("schedule", C.c_int32), ("flags", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class Leaf(C.Structure):
@@ -65,8 +67,13 @@ class Leaf(C.Structure):
 
 
 class Stats(C.Structure):
-    _fields_ = [("nodes", C.c_int64 * 7), ("leaves", C.c_int64 * 7), ("iters_executed", C.c_int64),
-                ("iters_emitted", C.c_int64), ("steps_launched", C.c_int64)]
+    _fields_ = [("nodes", C.c_int64 * 7), ("leaves", C.c_int64 * 7), ("iters_level", C.c_int64 * 7),
+                ("iters_executed", C.c_int64), ("iters_emitted", C.c_int64), ("steps_launched", C.c_int64)]
+
+
+class Timing(C.Structure):
+    _fields_ = [("corr_ms", C.c_double * 7), ("select_ms", C.c_double * 7), ("level_ms", C.c_double * 7),
+                ("steps", C.c_int64 * 7)]
 
 
 LEAF_DTYPE = np.dtype([("job", "<i4"), ("x0", "<i4"), ("y0", "<i4"), ("n", "<i4"), ("n_atoms", "<i4"),
@@ -96,6 +103,7 @@ def _load() -> C.CDLL:
     lib.aqmp_code_export.argtypes = [vp, vp, vp, vp, i64, i64]
     lib.aqmp_code_export_nodes.argtypes = [vp, vp, vp, vp, i64, i64]
     lib.aqmp_code_stats.argtypes = [vp, C.POINTER(Stats)]
+    lib.aqmp_code_timing.argtypes = [vp, C.POINTER(Timing)]
     lib.aqmp_code_free.argtypes = [vp]
     lib.aqmp_code_free.restype = None
     lib.aqmp_decode.argtypes = [vp, vp, i32, vp, i32, i64, vp]
@@ -199,7 +207,7 @@ class Code:
     """An encode: the quadtree leaves and their atoms, kept on the device."""
 
     def __init__(self, dic: Dictionary, images, params, jobs, precision: int = PREC_FP32,
-                 schedule: int = SCHED_PLAIN, stream=None):
+                 schedule: int = SCHED_PLAIN, stream=None, timing: bool = False):
         self.dic = dic
         self._keep = list(images)
         imgs = (Image * len(images))(*[make_image(t) for t in images])
@@ -207,6 +215,7 @@ class Code:
         jbs = (Job * len(jobs))(*[Job(int(a), int(b)) for a, b in jobs])
         opt = Options()
         opt.precision, opt.schedule = int(precision), int(schedule)
+        opt.flags = OPT_TIMING if timing else 0
         h = C.c_void_p()
         _check(lib.aqmp_encode(dic.h, imgs, len(images), prms, len(params), jbs, len(jobs), C.byref(opt),
                                _stream_handle(stream), C.byref(h)))
@@ -226,8 +235,15 @@ class Code:
     def stats(self) -> dict:
         s = Stats()
         _check(lib.aqmp_code_stats(self.h, C.byref(s)))
-        return dict(nodes=list(s.nodes), leaves=list(s.leaves), iters_executed=s.iters_executed,
-                    iters_emitted=s.iters_emitted, steps_launched=s.steps_launched)
+        return dict(nodes=list(s.nodes), leaves=list(s.leaves), iters_level=list(s.iters_level),
+                    iters_executed=s.iters_executed, iters_emitted=s.iters_emitted,
+                    steps_launched=s.steps_launched)
+
+    def timing(self) -> dict:
+        t = Timing()
+        _check(lib.aqmp_code_timing(self.h, C.byref(t)))
+        return dict(corr_ms=list(t.corr_ms), select_ms=list(t.select_ms), level_ms=list(t.level_ms),
+                    steps=list(t.steps))
 
     def _export(self, fn, n_rec: int, n_atoms: int) -> Export:
         leaves = np.zeros(max(n_rec, 1), dtype=LEAF_DTYPE)

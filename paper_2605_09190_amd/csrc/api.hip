@@ -19,6 +19,7 @@ int encode(const aqmp_dict* d, const aqmp_image* imgs, int n_imgs, const aqmp_pa
 int reencode(aqmp_code* c, const aqmp_image* imgs, int n_imgs, hipStream_t s);
 void code_free(aqmp_code* c);
 int code_stats(const aqmp_code* c, aqmp_stats* s);
+int code_timing(const aqmp_code* c, aqmp_timing* t);
 int code_sizes(const aqmp_code* c, int64_t* n_leaves, int64_t* n_atoms);
 int code_export(const aqmp_code* c, bool leaves_only, aqmp_leaf* leaves, int32_t* atom_idx, double* coef,
                 int64_t cap_leaves, int64_t cap_atoms);
@@ -124,6 +125,8 @@ int aqmp_code_export_nodes(const aqmp_code* c, aqmp_leaf* nodes, int32_t* atom_i
 }
 
 int aqmp_code_stats(const aqmp_code* c, aqmp_stats* s) { AQMP_ENTRY(code_stats(c, s)); }
+
+int aqmp_code_timing(const aqmp_code* c, aqmp_timing* t) { AQMP_ENTRY(code_timing(c, t)); }
 
 void aqmp_code_free(aqmp_code* c) {
   try {

@@ -65,6 +65,20 @@ struct aqmp_code {
   };
   std::vector<Alloc> allocs;
   int64_t steps_launched = 0;
+  // Timing events (AQMP_OPT_TIMING): per level of every pass a start/end
+  // pair, per MP step three events (before the correlation, after it, after
+  // the select/update launch).
+  struct LevelEv {
+    int lg;
+    hipEvent_t start, end;
+  };
+  struct StepEv {
+    int lg;
+    hipEvent_t a, b, c;
+  };
+  std::vector<LevelEv> lev;
+  std::vector<StepEv> sev;
+  size_t lev_pos = 0, sev_pos = 0;
 };
 
 namespace aqmp {
@@ -210,6 +224,8 @@ void free_code(aqmp_code* c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->done) (void)hipEventDestroy(c->done);
+  for (auto& e : c->lev) (void)hipEventDestroy(e.start), (void)hipEventDestroy(e.end);
+  for (auto& e : c->sev) (void)hipEventDestroy(e.a), (void)hipEventDestroy(e.b), (void)hipEventDestroy(e.c);
   for (auto& a : c->allocs) dev_free(a.p, a.bytes);
   delete c;
 }
@@ -295,6 +311,23 @@ int build_plan(aqmp_code* c) {
   AQMP_HIP(hipMemcpyAsync(c->dntop, ntop_all.data(), 4 * ntop_all.size(), hipMemcpyHostToDevice, s));
   AQMP_HIP(hipStreamSynchronize(s));
   AQMP_HIP(hipEventCreateWithFlags(&c->done, hipEventDisableTiming));
+  if (c->opt.flags & AQMP_OPT_TIMING) {
+    for (const auto& pp : c->passes)
+      for (int l = pp.lg_hi; l >= pp.lg_lo; --l) {
+        if (pp.cap[l] == 0) continue;
+        aqmp_code::LevelEv le{l, nullptr, nullptr};
+        AQMP_HIP(hipEventCreate(&le.start));
+        AQMP_HIP(hipEventCreate(&le.end));
+        c->lev.push_back(le);
+        for (int t = 0; t < pp.kmax[l]; ++t) {
+          aqmp_code::StepEv se{l, nullptr, nullptr, nullptr};
+          AQMP_HIP(hipEventCreate(&se.a));
+          AQMP_HIP(hipEventCreate(&se.b));
+          AQMP_HIP(hipEventCreate(&se.c));
+          c->sev.push_back(se);
+        }
+      }
+  }
   return AQMP_OK;
 }
 
@@ -325,6 +358,9 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
     a.keys = c->keys;
     a.n_atom_tiles = D.m_pad / corr_atom_tile(n);
     int32_t* count = &cnt->count[l];
+    const bool timing = (c->opt.flags & AQMP_OPT_TIMING) != 0;
+    const aqmp_code::LevelEv* le = timing ? &c->lev[c->lev_pos++] : nullptr;
+    if (le) AQMP_HIP(hipEventRecord(le->start, s));
     AQMP_LAUNCH(launch_gather(n, a, count, s));
     AQMP_LAUNCH(launch_compact(nullptr, count, a.lv.st, c->act[0], &cnt->act[0], pp.cap[l], c->ss,
                                &cnt->scan_error, s));
@@ -333,8 +369,12 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
     for (int t = 0; t < pp.kmax[l]; ++t) {
       a.act = c->act[cur];
       a.act_count = &cnt->act[cur];
+      const aqmp_code::StepEv* se = timing ? &c->sev[c->sev_pos++] : nullptr;
+      if (se) AQMP_HIP(hipEventRecord(se->a, s));
       AQMP_LAUNCH(launch_corr(n, c->opt.precision, atoms, a, D.m_pad, s));
+      if (se) AQMP_HIP(hipEventRecord(se->b, s));
       AQMP_LAUNCH(launch_select(n, a, s));
+      if (se) AQMP_HIP(hipEventRecord(se->c, s));
       if (t + 1 < pp.kmax[l])
         AQMP_LAUNCH(launch_compact(c->act[cur], &cnt->act[cur], a.lv.st, c->act[cur ^ 1], &cnt->act[cur ^ 1],
                                    pp.cap[l], c->ss, &cnt->scan_error, s));
@@ -343,13 +383,17 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
     if (l > pp.lg_lo && pp.cap[l - 1] > 0)
       AQMP_LAUNCH(launch_split_emit(c->djobs, a.lv, count, level_at(c, l - 1, pp.base[l - 1]), pp.ntop[l - 1],
                                     &cnt->count[l - 1], l, pp.cap[l], c->ss, &cnt->scan_error, s));
+    if (le) AQMP_HIP(hipEventRecord(le->end, s));
   }
   return AQMP_OK;
 }
 
 int run(aqmp_code* c, hipStream_t s) {
+  c->lev_pos = c->sev_pos = 0;
   AQMP_HIP(hipMemcpyAsync(c->djobs, c->hjobs.data(), sizeof(JobDev) * c->hjobs.size(), hipMemcpyHostToDevice, s));
-  if (c->opt.schedule == AQMP_SCHED_BATCHED) {
+  // HIP events recorded inside a graph cannot be timed, so a timed encode
+  // issues the same launch sequence directly on the stream.
+  if (c->opt.schedule == AQMP_SCHED_BATCHED && !(c->opt.flags & AQMP_OPT_TIMING)) {
     if (!c->gexec) {
       // Capture on a private stream (the caller's may be the null stream,
       // which cannot be captured); the graph is launched on the caller's.
@@ -520,6 +564,7 @@ int code_stats(const aqmp_code* c, aqmp_stats* s) {
   for (const auto& h : nodes) {
     const int l = ilog2(h.leaf.n);
     s->nodes[l]++;
+    s->iters_level[l] += h.leaf.n_atoms;
     s->iters_executed += h.leaf.n_atoms;
     if (!(h.leaf.flags & 1)) {
       s->leaves[l]++;
@@ -527,6 +572,26 @@ int code_stats(const aqmp_code* c, aqmp_stats* s) {
     }
   }
   s->steps_launched = c->steps_launched;
+  return AQMP_OK;
+}
+
+int code_timing(const aqmp_code* c, aqmp_timing* t) {
+  if (!c || !t) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_timing: null argument");
+  if (!(c->opt.flags & AQMP_OPT_TIMING)) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_timing: encode made without timing");
+  AQMP_HIP(hipStreamSynchronize(c->stream));
+  std::memset(t, 0, sizeof(*t));
+  float ms = 0.f;
+  for (const auto& e : c->lev) {
+    AQMP_HIP(hipEventElapsedTime(&ms, e.start, e.end));
+    t->level_ms[e.lg] += ms;
+  }
+  for (const auto& e : c->sev) {
+    AQMP_HIP(hipEventElapsedTime(&ms, e.a, e.b));
+    t->corr_ms[e.lg] += ms;
+    AQMP_HIP(hipEventElapsedTime(&ms, e.b, e.c));
+    t->select_ms[e.lg] += ms;
+    t->steps[e.lg] += 1;
+  }
   return AQMP_OK;
 }
 

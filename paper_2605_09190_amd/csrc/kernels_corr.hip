@@ -17,6 +17,8 @@
 // half-waves and the WA waves are merged, and the R keys of every (node,
 // atom tile) go out as 64-bit keys ((|c| bits) << 32 | ~atom).  The key keeps
 // 15 mantissa bits of |c|: it only ranks candidates for the FP64 re-score.
+#include <type_traits>
+
 #include "internal.h"
 #include "dev_common.h"
 
@@ -119,13 +121,14 @@ __device__ inline void epilogue(f32x16 (&acc)[C::MA][C::MB], uint32_t* sK, int a
 // ---------------------------------------------------------------------------
 // BF16 x BF16 -> FP32 (v_mfma_f32_32x32x16_bf16).
 // ---------------------------------------------------------------------------
-template <class C>
+template <int N, class C>
 __global__ __launch_bounds__(256, 1) void k_corr_bf16(const uint16_t* __restrict__ D,
                                                       const uint16_t* __restrict__ X,
                                                       const int32_t* __restrict__ act,
                                                       const int32_t* __restrict__ act_count,
-                                                      unsigned long long* __restrict__ keys, int K,
+                                                      unsigned long long* __restrict__ keys,
                                                       int n_atom_tiles) {
+  constexpr int K = N * N;
   constexpr int BK = C::BK, LDA = BK + 8;         // +16 B per row against bank conflicts
   constexpr int CPR = BK / 8;                     // 16-byte chunks per row
   constexpr int NCA = C::BA * CPR, NCB = C::BB * CPR;    // chunks per stage
@@ -139,7 +142,8 @@ __global__ __launch_bounds__(256, 1) void k_corr_bf16(const uint16_t* __restrict
   const int ntiles = n_atom_tiles * ntB;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wa = w % C::WA, wb = w / C::WA;
-  const int nst = K / BK;
+  constexpr int nst = K / BK;
+  static_assert(K % BK == 0, "K must be a whole number of stages");
   TileWalk walk(ntiles);
   for (int j = walk.slot; j < walk.chunk; j += walk.per) {
     const int tile = walk.tile(j);
@@ -222,12 +226,13 @@ __global__ __launch_bounds__(256, 1) void k_corr_bf16(const uint16_t* __restrict
 // reads its operands as contiguous 16-byte chunks (A and B use the same k
 // order, which is all the contraction needs).
 // ---------------------------------------------------------------------------
-template <class C>
+template <int N, class C>
 __global__ __launch_bounds__(256, 1) void k_corr_f32(const float* __restrict__ D, const float* __restrict__ X,
                                                      const int32_t* __restrict__ act,
                                                      const int32_t* __restrict__ act_count,
-                                                     unsigned long long* __restrict__ keys, int K,
+                                                     unsigned long long* __restrict__ keys,
                                                      int n_atom_tiles) {
+  constexpr int K = N * N;
   constexpr int BK = C::BK, LDA = BK + 4;
   constexpr int CPR = BK / 4;
   constexpr int NCA = C::BA * CPR, NCB = C::BB * CPR;    // chunks per stage
@@ -241,7 +246,8 @@ __global__ __launch_bounds__(256, 1) void k_corr_f32(const float* __restrict__ D
   const int ntiles = n_atom_tiles * ntB;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wa = w % C::WA, wb = w / C::WA;
-  const int nst = K / BK;
+  constexpr int nst = K / BK;
+  static_assert(K % BK == 0, "K must be a whole number of stages");
   TileWalk walk(ntiles);
   for (int j = walk.slot; j < walk.chunk; j += walk.per) {
     const int tile = walk.tile(j);
@@ -338,32 +344,28 @@ int corr_atom_tile(int n) { return n >= 16 ? 256 : (n == 8 ? 128 : 32); }
 
 int corr_grid(int, int) { return kCorrGrid; }
 
+template <int N>
+static void launch_corr_n(int precision, const void* atoms, const StepArgs& a, int nat, hipStream_t s) {
+  using CB = typename std::conditional<(N >= 16), CfgBig, typename std::conditional<(N == 8), CfgMid, CfgSmall>::type>::type;
+  using CF = typename std::conditional<(N >= 16), CfgBigF, typename std::conditional<(N == 8), CfgMidF, CfgSmallF>::type>::type;
+  if (precision == AQMP_PREC_BF16)
+    hipLaunchKernelGGL((k_corr_bf16<N, CB>), dim3(kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms, a.r16, a.act,
+                       a.act_count, a.keys, nat);
+  else
+    hipLaunchKernelGGL((k_corr_f32<N, CF>), dim3(kCorrGrid), dim3(256), 0, s, (const float*)atoms, a.r32, a.act,
+                       a.act_count, a.keys, nat);
+}
+
 hipError_t launch_corr(int n, int precision, const void* dict_atoms, const StepArgs& a, int32_t m_pad,
                        hipStream_t s) {
-  const int K = n * n;
   const int nat = m_pad / corr_atom_tile(n);
-  if (precision == AQMP_PREC_BF16) {
-    const uint16_t* D = (const uint16_t*)dict_atoms;
-    if (n >= 16)
-      hipLaunchKernelGGL(k_corr_bf16<CfgBig>, dim3(kCorrGrid), dim3(256), 0, s, D, a.r16, a.act, a.act_count,
-                         a.keys, K, nat);
-    else if (n == 8)
-      hipLaunchKernelGGL(k_corr_bf16<CfgMid>, dim3(kCorrGrid), dim3(256), 0, s, D, a.r16, a.act, a.act_count,
-                         a.keys, K, nat);
-    else
-      hipLaunchKernelGGL(k_corr_bf16<CfgSmall>, dim3(kCorrGrid), dim3(256), 0, s, D, a.r16, a.act,
-                         a.act_count, a.keys, K, nat);
-  } else {
-    const float* D = (const float*)dict_atoms;
-    if (n >= 16)
-      hipLaunchKernelGGL(k_corr_f32<CfgBigF>, dim3(kCorrGrid), dim3(256), 0, s, D, a.r32, a.act, a.act_count,
-                         a.keys, K, nat);
-    else if (n == 8)
-      hipLaunchKernelGGL(k_corr_f32<CfgMidF>, dim3(kCorrGrid), dim3(256), 0, s, D, a.r32, a.act, a.act_count,
-                         a.keys, K, nat);
-    else
-      hipLaunchKernelGGL(k_corr_f32<CfgSmallF>, dim3(kCorrGrid), dim3(256), 0, s, D, a.r32, a.act,
-                         a.act_count, a.keys, K, nat);
+  switch (n) {
+    case 4: launch_corr_n<4>(precision, dict_atoms, a, nat, s); break;
+    case 8: launch_corr_n<8>(precision, dict_atoms, a, nat, s); break;
+    case 16: launch_corr_n<16>(precision, dict_atoms, a, nat, s); break;
+    case 32: launch_corr_n<32>(precision, dict_atoms, a, nat, s); break;
+    case 64: launch_corr_n<64>(precision, dict_atoms, a, nat, s); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
