@@ -70,4 +70,64 @@ __device__ inline void group_sum_n(double (&v)[CNT], double* scratch) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Decoupled look-back for stable single-pass prefix sums.  A tile word holds a
+// flag in its top two bits (1: tile aggregate published, 2: inclusive prefix
+// published) and a 32-bit count.  Tiles are taken in ticket order, so a tile
+// only waits on tiles held by workgroups that started before it.  Each wait
+// is bounded; when the bound runs out *err is set and the (then wrong) sum is
+// used, so every wave still finishes.
+// ---------------------------------------------------------------------------
+constexpr unsigned long long kFlagAgg = 1ull << 62;
+constexpr unsigned long long kFlagInc = 2ull << 62;
+constexpr int kSpinLimit = 1 << 24;
+
+__device__ inline unsigned long long load_acq(unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void store_rel(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wave-parallel look-back, called by all 64 lanes of one wave: publishes
+// tile `tile`'s aggregate, then reads up to 64 predecessors per probe (lane i
+// reads tile - 1 - i), stops at the nearest inclusive prefix, and publishes its
+// own inclusive prefix.  Returns the exclusive prefix in every lane.
+__device__ inline int lookback_wave(unsigned long long* tiles, int tile, int agg, int32_t* err) {
+  const int lane = threadIdx.x & 63;
+  if (tile == 0) {
+    if (lane == 0) store_rel(&tiles[0], kFlagInc | (unsigned)agg);
+    return 0;
+  }
+  if (lane == 0) store_rel(&tiles[tile], kFlagAgg | (unsigned)agg);
+  int prefix = 0, end = tile, spins = 0;
+  for (;;) {
+    const int idx = end - 1 - lane;
+    const unsigned long long v = idx >= 0 ? load_acq(&tiles[idx]) : (kFlagInc | 0ull);
+    const unsigned fl = (unsigned)(v >> 62);
+    const int val = (int)(unsigned)(v & 0xFFFFFFFFull);
+    const unsigned long long inc = __ballot(fl == 2);
+    const unsigned long long miss = __ballot(fl == 0);
+    const unsigned long long upto = inc ? (inc & (~inc + 1ull)) : 0ull;   // lowest inclusive lane
+    const unsigned long long need = inc ? (upto | (upto - 1ull)) : ~0ull;   // lanes that must be ready
+    if (miss & need) {
+      if (++spins > kSpinLimit) {
+        if (lane == 0) atomicExch(err, 1);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    int x = ((need >> lane) & 1ull) ? val : 0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) x += __shfl_xor(x, off, 64);
+    prefix += x;
+    if (inc) break;
+    end -= 64;
+    spins = 0;
+  }
+  if (lane == 0) store_rel(&tiles[tile], kFlagInc | (unsigned)(prefix + agg));
+  return prefix;
+}
+
 }  // namespace aqmp

@@ -284,7 +284,9 @@ int build_plan(aqmp_code* c) {
   ALLOC(c->djobs, sizeof(JobDev) * nj);
   ALLOC(c->dcnt, sizeof(Counters) * c->passes.size());
   ALLOC(c->dntop, sizeof(int32_t) * kLevels * c->passes.size());
-  c->ss.ntiles_max = (int32_t)((max_cap + kScanTile - 1) / kScanTile + 1);
+  // Tile words: one per scan tile of kScanTile items, or one per select chunk
+  // of at least 4 positions, whichever is more.
+  c->ss.ntiles_max = (int32_t)(max_cap / 4 + 2);
   ALLOC(c->ss.tiles, sizeof(unsigned long long) * c->ss.ntiles_max);
   ALLOC(c->ss.ticket, sizeof(int32_t) * 2);
 #undef ALLOC

@@ -120,7 +120,81 @@ __device__ inline void epilogue(f32x16 (&acc)[C::MA][C::MB], uint32_t* sK, int a
 
 // ---------------------------------------------------------------------------
 // BF16 x BF16 -> FP32 (v_mfma_f32_32x32x16_bf16).
+//
+// Pipeline per K stage s (LDS buffer s & 1):
+//   issue the global loads of stage s + 2 into register set s & 1;
+//   compute stage s, reading the operand fragments of sub-step kk + 1 from
+//   LDS while the MFMAs of sub-step kk run;
+//   store register set (s + 1) & 1 (stage s + 1, loaded one stage earlier)
+//   into LDS buffer (s + 1) & 1; one barrier.
+// Rows of X past the active count are read from the last active row (their
+// results are never written), so no load is predicated.
 // ---------------------------------------------------------------------------
+template <class C, int K>
+struct Bf16Tile {
+  static constexpr int BK = C::BK, LDA = BK + 8;   // +16 B per row against bank conflicts
+  static constexpr int CPR = BK / 8;               // 16-byte chunks per row
+  static constexpr int NCA = C::BA * CPR, NCB = C::BB * CPR;
+  static constexpr int CA = (NCA + 255) / 256, CB = (NCB + 255) / 256;
+  static constexpr bool FULLA = NCA % 256 == 0, FULLB = NCB % 256 == 0;
+  static constexpr int NST = K / BK;
+  static_assert(K % BK == 0, "K must be a whole number of stages");
+};
+
+template <class C, class T>
+struct Bf16Regs {
+  uint4 a[T::CA], b[T::CB];
+};
+
+template <class C, class T>
+__device__ inline void bf16_gload(Bf16Regs<C, T>& r, const uint16_t* const* ga, const uint16_t* const* gb, int s) {
+#pragma unroll
+  for (int i = 0; i < T::CA; ++i)
+    if (T::FULLA || ga[i]) r.a[i] = *(const uint4*)(ga[i] + s * T::BK);
+#pragma unroll
+  for (int i = 0; i < T::CB; ++i)
+    if (T::FULLB || gb[i]) r.b[i] = *(const uint4*)(gb[i] + s * T::BK);
+}
+
+template <class C, class T>
+__device__ inline void bf16_lstore(const Bf16Regs<C, T>& r, uint16_t* sa, uint16_t* sb, const int* la, const int* lb) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < T::CA; ++i)
+    if (T::FULLA || tid + 256 * i < T::NCA) *(uint4*)&sa[la[i]] = r.a[i];
+#pragma unroll
+  for (int i = 0; i < T::CB; ++i)
+    if (T::FULLB || tid + 256 * i < T::NCB) *(uint4*)&sb[lb[i]] = r.b[i];
+}
+
+template <class C, class T>
+__device__ inline void bf16_compute(f32x16 (&acc)[C::MA][C::MB], const uint16_t* sa, const uint16_t* sb) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wa = w % C::WA, wb = w / C::WA;
+  const uint16_t* pa = sa + (wa * C::WTA + (lane & 31)) * T::LDA + (lane >> 5) * 8;
+  const uint16_t* pb = sb + (wb * C::WTB + (lane & 31)) * T::LDA + (lane >> 5) * 8;
+  bf16x8 fa[2][C::MA], fb[2][C::MB];
+#pragma unroll
+  for (int ma = 0; ma < C::MA; ++ma) fa[0][ma] = *(const bf16x8*)(pa + ma * 32 * T::LDA);
+#pragma unroll
+  for (int mb = 0; mb < C::MB; ++mb) fb[0][mb] = *(const bf16x8*)(pb + mb * 32 * T::LDA);
+#pragma unroll
+  for (int kk = 0; kk < T::BK / 16; ++kk) {
+    const int cur = kk & 1, nxt = cur ^ 1;
+    if (kk + 1 < T::BK / 16) {
+#pragma unroll
+      for (int ma = 0; ma < C::MA; ++ma) fa[nxt][ma] = *(const bf16x8*)(pa + ma * 32 * T::LDA + (kk + 1) * 16);
+#pragma unroll
+      for (int mb = 0; mb < C::MB; ++mb) fb[nxt][mb] = *(const bf16x8*)(pb + mb * 32 * T::LDA + (kk + 1) * 16);
+    }
+#pragma unroll
+    for (int ma = 0; ma < C::MA; ++ma)
+#pragma unroll
+      for (int mb = 0; mb < C::MB; ++mb)
+        acc[ma][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[cur][ma], fb[cur][mb], acc[ma][mb], 0, 0, 0);
+  }
+}
+
 template <int N, class C>
 __global__ __launch_bounds__(256, 1) void k_corr_bf16(const uint16_t* __restrict__ D,
                                                       const uint16_t* __restrict__ X,
@@ -129,21 +203,16 @@ __global__ __launch_bounds__(256, 1) void k_corr_bf16(const uint16_t* __restrict
                                                       unsigned long long* __restrict__ keys,
                                                       int n_atom_tiles) {
   constexpr int K = N * N;
-  constexpr int BK = C::BK, LDA = BK + 8;         // +16 B per row against bank conflicts
-  constexpr int CPR = BK / 8;                     // 16-byte chunks per row
-  constexpr int NCA = C::BA * CPR, NCB = C::BB * CPR;    // chunks per stage
-  constexpr int CA = (NCA + 255) / 256, CB = (NCB + 255) / 256;
-  __shared__ __attribute__((aligned(16))) uint16_t sA[2][C::BA * LDA];
-  __shared__ __attribute__((aligned(16))) uint16_t sB[2][C::BB * LDA];
+  using T = Bf16Tile<C, K>;
+  constexpr int NST = T::NST;
+  __shared__ __attribute__((aligned(16))) uint16_t sA[2][C::BA * T::LDA];
+  __shared__ __attribute__((aligned(16))) uint16_t sB[2][C::BB * T::LDA];
   __shared__ uint32_t sK[C::WA * C::BB * kTopR];
 
   const int count = *act_count;
   const int ntB = (count + C::BB - 1) / C::BB;
   const int ntiles = n_atom_tiles * ntB;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wa = w % C::WA, wb = w / C::WA;
-  constexpr int nst = K / BK;
-  static_assert(K % BK == 0, "K must be a whole number of stages");
+  const int tid = threadIdx.x;
   TileWalk walk(ntiles);
   for (int j = walk.slot; j < walk.chunk; j += walk.per) {
     const int tile = walk.tile(j);
@@ -151,37 +220,22 @@ __global__ __launch_bounds__(256, 1) void k_corr_bf16(const uint16_t* __restrict
     const int a_tile = tile / ntB, b_tile = tile % ntB;
     const int a0 = a_tile * C::BA, b0 = b_tile * C::BB;
 
-    const uint16_t* ga[CA];
-    const uint16_t* gb[CB];
-    int la[CA], lb[CB];
+    const uint16_t* ga[T::CA];
+    const uint16_t* gb[T::CB];
+    int la[T::CA], lb[T::CB];
 #pragma unroll
-    for (int i = 0; i < CA; ++i) {
-      const int c = tid + 256 * i, row = c / CPR, kc = c % CPR;
-      ga[i] = c < NCA ? D + (size_t)(a0 + row) * K + kc * 8 : nullptr;
-      la[i] = row * LDA + kc * 8;
+    for (int i = 0; i < T::CA; ++i) {
+      const int c = tid + 256 * i, row = c / T::CPR, kc = c % T::CPR;
+      ga[i] = (T::FULLA || c < T::NCA) ? D + (size_t)(a0 + row) * K + kc * 8 : nullptr;
+      la[i] = row * T::LDA + kc * 8;
     }
 #pragma unroll
-    for (int i = 0; i < CB; ++i) {
-      const int c = tid + 256 * i, row = c / CPR, kc = c % CPR;
-      const int pos = b0 + row;
-      gb[i] = (c < NCB && pos < count) ? X + (size_t)act[pos] * K + kc * 8 : nullptr;
-      lb[i] = row * LDA + kc * 8;
+    for (int i = 0; i < T::CB; ++i) {
+      const int c = tid + 256 * i, row = c / T::CPR, kc = c % T::CPR;
+      const int pos = min(b0 + row, count - 1);
+      gb[i] = (T::FULLB || c < T::NCB) ? X + (size_t)act[pos] * K + kc * 8 : nullptr;
+      lb[i] = row * T::LDA + kc * 8;
     }
-    uint4 ra[CA], rb[CB];
-    auto gload = [&](int s) {
-#pragma unroll
-      for (int i = 0; i < CA; ++i) ra[i] = ga[i] ? *(const uint4*)(ga[i] + s * BK) : make_uint4(0, 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < CB; ++i) rb[i] = gb[i] ? *(const uint4*)(gb[i] + s * BK) : make_uint4(0, 0, 0, 0);
-    };
-    auto lstore = [&](int buf) {
-#pragma unroll
-      for (int i = 0; i < CA; ++i)
-        if (tid + 256 * i < NCA) *(uint4*)&sA[buf][la[i]] = ra[i];
-#pragma unroll
-      for (int i = 0; i < CB; ++i)
-        if (tid + 256 * i < NCB) *(uint4*)&sB[buf][lb[i]] = rb[i];
-    };
 
     f32x16 acc[C::MA][C::MB];
 #pragma unroll
@@ -191,31 +245,206 @@ __global__ __launch_bounds__(256, 1) void k_corr_bf16(const uint16_t* __restrict
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[ma][mb][r] = 0.f;
 
-    gload(0);
-    lstore(0);
+    Bf16Regs<C, T> r0, r1;
+    bf16_gload<C, T>(r0, ga, gb, 0);
+    if (NST > 1) bf16_gload<C, T>(r1, ga, gb, 1);
+    bf16_lstore<C, T>(r0, sA[0], sB[0], la, lb);
     __syncthreads();
-    for (int s = 0; s < nst; ++s) {
-      const int buf = s & 1;
-      if (s + 1 < nst) gload(s + 1);
-#pragma unroll
-      for (int kk = 0; kk < BK / 16; ++kk) {
-        bf16x8 af[C::MA], bfr[C::MB];
-        const int ko = kk * 16 + (lane >> 5) * 8;
-#pragma unroll
-        for (int ma = 0; ma < C::MA; ++ma)
-          af[ma] = *(const bf16x8*)&sA[buf][(wa * C::WTA + ma * 32 + (lane & 31)) * LDA + ko];
-#pragma unroll
-        for (int mb = 0; mb < C::MB; ++mb)
-          bfr[mb] = *(const bf16x8*)&sB[buf][(wb * C::WTB + mb * 32 + (lane & 31)) * LDA + ko];
-#pragma unroll
-        for (int ma = 0; ma < C::MA; ++ma)
-#pragma unroll
-          for (int mb = 0; mb < C::MB; ++mb)
-            acc[ma][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[ma], bfr[mb], acc[ma][mb], 0, 0, 0);
-      }
-      if (s + 1 < nst) lstore(buf ^ 1);
+    // Two stages per trip so that the register sets are compile-time.
+    for (int s = 0; s < NST; s += 2) {
+      if (s + 2 < NST) bf16_gload<C, T>(r0, ga, gb, s + 2);
+      bf16_compute<C, T>(acc, sA[0], sB[0]);
+      if (s + 1 < NST) bf16_lstore<C, T>(r1, sA[1], sB[1], la, lb);
+      __syncthreads();
+      if (s + 1 >= NST) break;
+      if (s + 3 < NST) bf16_gload<C, T>(r1, ga, gb, s + 3);
+      bf16_compute<C, T>(acc, sA[1], sB[1]);
+      if (s + 2 < NST) bf16_lstore<C, T>(r0, sA[0], sB[0], la, lb);
       __syncthreads();
     }
+    epilogue<C>(acc, sK, a0, a_tile, n_atom_tiles, b0, count, keys);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BF16, large blocks (N >= 16): direct-to-LDS loads and a three-stage ring.
+//
+// Tile 256 atoms x 128 nodes, BK = 64 (128-byte rows).  Each global load
+// (global_load_lds_dwordx4) moves 16 bytes per lane straight into LDS, 1 KB
+// per wave instruction (8 rows); no staging registers, so three stages stay
+// in flight: at stage s the loads of stage s + 2 are issued while stage s is
+// computed.  Row r keeps its 16-byte chunk c at slot c ^ f(r) with
+// f(r) = (r & 7) ^ ((r >> 3) & 1): the 8 or 16 rows read together by one
+// LDS phase hit distinct banks.  Waits are explicit (vmcnt per wave, then a
+// raw barrier), because a full workgroup fence would drain the ring.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) const void gbl_void_t;
+
+namespace dma {
+constexpr int BA = 256, BB = 128, BK = 64, WA = 2, WB = 2;
+constexpr int WTA = BA / WA, WTB = BB / WB, MA = WTA / 32, MB = WTB / 32;
+constexpr int ROWB = BK * 2;                  // bytes per LDS row
+constexpr int A_BYTES = BA * ROWB, B_BYTES = BB * ROWB;
+constexpr int A_INS = BA / 8 / 4, B_INS = BB / 8 / 4;   // 1 KB blocks per wave
+constexpr int INS = A_INS + B_INS;                       // DMA instructions per wave per stage
+}  // namespace dma
+
+// vmcnt(n) with the other counters left alone (gfx9 encoding).
+#define AQMP_WAIT_VM(n) __builtin_amdgcn_s_waitcnt(((n) & 0xF) | (0x7 << 4) | (0xF << 8) | ((((n) >> 4) & 0x3) << 14))
+
+struct DmaPtrs {
+  const char* a_lane[2];     // A: lane part for even / odd blocks (bytes, stage 0)
+  const char* b_lane[dma::B_INS];
+};
+
+template <int K>
+__device__ inline void dma_issue(const DmaPtrs& p, char* sa, char* sb, int s) {
+  using namespace dma;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const size_t kofs = (size_t)s * BK * 2;
+#pragma unroll
+  for (int i = 0; i < A_INS; ++i) {
+    const int blk = w * A_INS + i;
+    const char* g = p.a_lane[i & 1] + (size_t)i * 8 * K * 2 + kofs;
+    __builtin_amdgcn_global_load_lds((gbl_void_t*)g, (lds_void_t*)(sa + blk * 1024), 16, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < B_INS; ++i) {
+    const int blk = w * B_INS + i;
+    __builtin_amdgcn_global_load_lds((gbl_void_t*)(p.b_lane[i] + kofs), (lds_void_t*)(sb + blk * 1024), 16, 0, 0);
+  }
+}
+
+__device__ inline void dma_compute(f32x16 (&acc)[dma::MA][dma::MB], const char* sa, const char* sb,
+                                   const int (&off)[dma::BK / 16]) {
+  using namespace dma;
+  const int w = threadIdx.x >> 6;
+  const int wa = w % WA, wb = w / WA;
+  const char* pa = sa + wa * WTA * ROWB;
+  const char* pb = sb + wb * WTB * ROWB;
+  bf16x8 fa[2][MA], fb[2][MB];
+#pragma unroll
+  for (int ma = 0; ma < MA; ++ma) fa[0][ma] = *(const bf16x8*)(pa + ma * 32 * ROWB + off[0]);
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) fb[0][mb] = *(const bf16x8*)(pb + mb * 32 * ROWB + off[0]);
+#pragma unroll
+  for (int kk = 0; kk < BK / 16; ++kk) {
+    const int cur = kk & 1, nxt = cur ^ 1;
+    if (kk + 1 < BK / 16) {
+#pragma unroll
+      for (int ma = 0; ma < MA; ++ma) fa[nxt][ma] = *(const bf16x8*)(pa + ma * 32 * ROWB + off[kk + 1]);
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) fb[nxt][mb] = *(const bf16x8*)(pb + mb * 32 * ROWB + off[kk + 1]);
+    }
+#pragma unroll
+    for (int ma = 0; ma < MA; ++ma)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+        acc[ma][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[cur][ma], fb[cur][mb], acc[ma][mb], 0, 0, 0);
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(256, 1) void k_corr_bf16_dma(const uint16_t* __restrict__ D,
+                                                          const uint16_t* __restrict__ X,
+                                                          const int32_t* __restrict__ act,
+                                                          const int32_t* __restrict__ act_count,
+                                                          unsigned long long* __restrict__ keys,
+                                                          int n_atom_tiles) {
+  using namespace dma;
+  constexpr int K = N * N;
+  constexpr int NST = K / BK;
+  static_assert(K % BK == 0 && NST >= 1, "stages");
+  using C = Cfg<BA, BB, BK, WA, WB>;
+  __shared__ __attribute__((aligned(1024))) char sA0[A_BYTES];
+  __shared__ __attribute__((aligned(1024))) char sA1[A_BYTES];
+  __shared__ __attribute__((aligned(1024))) char sA2[A_BYTES];
+  __shared__ __attribute__((aligned(1024))) char sB0[B_BYTES];
+  __shared__ __attribute__((aligned(1024))) char sB1[B_BYTES];
+  __shared__ __attribute__((aligned(1024))) char sB2[B_BYTES];
+  uint32_t* sK = (uint32_t*)sA0;   // epilogue scratch, after the ring drains
+
+  const int count = *act_count;
+  const int ntB = (count + BB - 1) / BB;
+  const int ntiles = n_atom_tiles * ntB;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // swizzle of this lane's MFMA rows (row & 31 == lane & 31)
+  const int fr = (lane & 7) ^ ((lane >> 3) & 1);
+  int off[BK / 16];
+#pragma unroll
+  for (int kk = 0; kk < BK / 16; ++kk) off[kk] = (lane & 31) * ROWB + (((2 * kk + (lane >> 5)) ^ fr) << 4);
+  // DMA lane geometry: lane l of a 1 KB block fills row (l >> 3), slot (l & 7)
+  const int drow = lane >> 3, dslot = lane & 7;
+  TileWalk walk(ntiles);
+  for (int j = walk.slot; j < walk.chunk; j += walk.per) {
+    const int tile = walk.tile(j);
+    if (tile >= ntiles) break;
+    const int a_tile = tile / ntB, b_tile = tile % ntB;
+    const int a0 = a_tile * BA, b0 = b_tile * BB;
+    DmaPtrs p;
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+      // block parity flips f(r) by (r >> 3) & 1 == block & 1
+      const int gc = dslot ^ drow ^ par;
+      p.a_lane[par] = (const char*)(D + (size_t)(a0 + w * A_INS * 8 + drow) * K + gc * 8);
+    }
+#pragma unroll
+    for (int i = 0; i < B_INS; ++i) {
+      const int blk = w * B_INS + i;
+      const int row = blk * 8 + drow;
+      const int gc = dslot ^ drow ^ (blk & 1);
+      const int pos = min(b0 + row, count - 1);
+      p.b_lane[i] = (const char*)(X + (size_t)act[pos] * K + gc * 8);
+    }
+    f32x16 acc[MA][MB];
+#pragma unroll
+    for (int ma = 0; ma < MA; ++ma)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[ma][mb][r] = 0.f;
+
+    __syncthreads();   // previous tile's epilogue is done with sK (= sA0)
+    dma_issue<K>(p, sA0, sB0, 0);
+    if constexpr (NST > 1) dma_issue<K>(p, sA1, sB1, 1);
+    // Steady state: every stage waits for its own loads (the next stage's
+    // stay in flight), passes the barrier, issues stage s + 2 and computes.
+    // Three stages per trip so that the buffers are compile-time.
+    constexpr int FULL = NST > 2 ? NST - 2 : 0;    // stages that issue a load
+    constexpr int TRIPS = FULL / 3;
+    for (int t = 0; t < TRIPS; ++t) {
+      const int s = 3 * t;
+      AQMP_WAIT_VM(dma::INS);
+      __builtin_amdgcn_s_barrier();
+      dma_issue<K>(p, sA2, sB2, s + 2);
+      dma_compute(acc, sA0, sB0, off);
+      AQMP_WAIT_VM(dma::INS);
+      __builtin_amdgcn_s_barrier();
+      dma_issue<K>(p, sA0, sB0, s + 3);
+      dma_compute(acc, sA1, sB1, off);
+      AQMP_WAIT_VM(dma::INS);
+      __builtin_amdgcn_s_barrier();
+      dma_issue<K>(p, sA1, sB1, s + 4);
+      dma_compute(acc, sA2, sB2, off);
+    }
+    // Tail: the last (at most four) stages, all decisions compile-time.
+    constexpr int S0 = 3 * TRIPS;
+#define AQMP_DMA_TAIL(I, SA, SB, NA, NB)                                  \
+    if constexpr (S0 + (I) < NST) {                                       \
+      if constexpr (S0 + (I) + 1 < NST) AQMP_WAIT_VM(dma::INS);           \
+      else AQMP_WAIT_VM(0);                                               \
+      __builtin_amdgcn_s_barrier();                                       \
+      if constexpr (S0 + (I) + 2 < NST) dma_issue<K>(p, NA, NB, S0 + (I) + 2); \
+      dma_compute(acc, SA, SB, off);                                      \
+    }
+    AQMP_DMA_TAIL(0, sA0, sB0, sA2, sB2)
+    AQMP_DMA_TAIL(1, sA1, sB1, sA0, sB0)
+    AQMP_DMA_TAIL(2, sA2, sB2, sA1, sB1)
+    AQMP_DMA_TAIL(3, sA0, sB0, sA2, sB2)
+    static_assert(NST - S0 <= 4, "tail covers the remaining stages");
+#undef AQMP_DMA_TAIL
+    __syncthreads();   // all waves done reading the ring before sK reuses sA0
     epilogue<C>(acc, sK, a0, a_tile, n_atom_tiles, b0, count, keys);
   }
 }
@@ -348,9 +577,14 @@ template <int N>
 static void launch_corr_n(int precision, const void* atoms, const StepArgs& a, int nat, hipStream_t s) {
   using CB = typename std::conditional<(N >= 16), CfgBig, typename std::conditional<(N == 8), CfgMid, CfgSmall>::type>::type;
   using CF = typename std::conditional<(N >= 16), CfgBigF, typename std::conditional<(N == 8), CfgMidF, CfgSmallF>::type>::type;
-  if (precision == AQMP_PREC_BF16)
-    hipLaunchKernelGGL((k_corr_bf16<N, CB>), dim3(kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms, a.r16, a.act,
-                       a.act_count, a.keys, nat);
+  if (precision == AQMP_PREC_BF16) {
+    if constexpr (N >= 16)
+      hipLaunchKernelGGL((k_corr_bf16_dma<N>), dim3(kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms, a.r16,
+                         a.act, a.act_count, a.keys, nat);
+    else
+      hipLaunchKernelGGL((k_corr_bf16<N, CB>), dim3(kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms, a.r16,
+                         a.act, a.act_count, a.keys, nat);
+  }
   else
     hipLaunchKernelGGL((k_corr_f32<N, CF>), dim3(kCorrGrid), dim3(256), 0, s, (const float*)atoms, a.r32, a.act,
                        a.act_count, a.keys, nat);

@@ -77,6 +77,27 @@ __global__ __launch_bounds__(256) void k_gather(StepArgs a, const int32_t* count
   }
 }
 
+// Lane groups of the select kernel: TPN lanes (at most one wave) per node,
+// each lane owning a PH x PW patch of the block.
+template <int N>
+struct WGeo {
+  static constexpr int K = N * N;
+  static constexpr int TPN = K < 64 ? K : 64;
+  static constexpr int NPI = 64 / TPN;               // nodes per wave per iteration
+  static constexpr int PPT = K / TPN;
+  static constexpr int PH = PPT == 64 ? 8 : (PPT == 16 ? 4 : (PPT == 4 ? 2 : 1));
+  static constexpr int PW = PPT / PH;
+  static constexpr int PX = N / PW;
+};
+
+// Sum over the TPN lanes of a group (fixed butterfly: bit-reproducible).
+template <int TPN>
+__device__ inline double lanes_sum(double v) {
+#pragma unroll
+  for (int off = 1; off < TPN; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 // ---------------------------------------------------------------------------
 // Select/update: one MP iteration for every active node after the
 // correlation pass has left each node's best keys per atom tile.
@@ -86,49 +107,54 @@ __global__ __launch_bounds__(256) void k_gather(StepArgs a, const int32_t* count
 //   3. i = argmax |c| (lowest atom index on ties); stop if max |c| = 0;
 //   4. r <- r - c_i phi_i (FP64 arithmetic, stored in FP32), ||r||^2 in FP64;
 //   5. record (i, c_i), t <- t + 1, stop test of eq. (2).
+// A node is handled by one group of TPN lanes: no workgroup barriers and no
+// atomics, positions are walked grid-stride.  The stable compaction of the
+// nodes still running is a separate launch.
 // ---------------------------------------------------------------------------
 template <int N>
 __global__ __launch_bounds__(256) void k_select(StepArgs a) {
-  using G = Geo<N>;
-  constexpr int K = G::K;
-  constexpr int TPN = G::TPN;
-  constexpr int L = TPN < 64 ? TPN : 64;   // lanes merging the keys
+  using G = WGeo<N>;
+  constexpr int K = G::K, TPN = G::TPN;
   constexpr int KPL = 4;                   // keys per lane (<= 256 keys)
-  __shared__ double s_red[G::NPW][kCand * 4];
-  __shared__ int s_cand[G::NPW][kCand];
   const int count = *a.act_count;
-  const int g = threadIdx.x / TPN, lt = threadIdx.x % TPN;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int g = lane / TPN, lt = lane % TPN;
   const int lg = a.lg;
   const int nkeys = a.n_atom_tiles * kTopR;
   const double inv_n = 1.0 / N;
-  for (int base = blockIdx.x * G::NPW; base < count; base += gridDim.x * G::NPW) {
-    const int pos = base + g;
-    const bool valid = pos < count;
-    const int node = valid ? a.act[pos] : a.act[base];
+  const int py = (lt / G::PX) * G::PH;
+  const int px = (lt % G::PX) * G::PW;
+  const int stride = gridDim.x * 4 * G::NPI;
+  for (int pos0 = (blockIdx.x * 4 + w) * G::NPI; pos0 < count; pos0 += stride) {
+    {
+      const int pos = pos0 + g;
+      const bool valid = pos < count;
+      const int node = a.act[valid ? pos : pos0];
+      const int base = pos0;
 
-    // 1. top kCand keys over the node's per-tile lists.
-    if (lt < L) {
+      // 1. top kCand keys over the node's per-tile lists.
       unsigned long long k[KPL];
       const unsigned long long* kp = a.keys + (size_t)(valid ? pos : base) * nkeys;
 #pragma unroll
       for (int j = 0; j < KPL; ++j) {
-        const int idx = lt + j * L;
+        const int idx = lt + j * TPN;
         k[j] = idx < nkeys ? kp[idx] : 0ull;
       }
-      // sort descending (4-element network)
 #pragma unroll
       for (int p0 = 0; p0 < KPL; ++p0)
 #pragma unroll
         for (int p1 = 0; p1 < KPL - 1 - p0; ++p1)
           if (k[p1] < k[p1 + 1]) {
-            unsigned long long t = k[p1];
+            const unsigned long long t = k[p1];
             k[p1] = k[p1 + 1];
             k[p1 + 1] = t;
           }
+      int cand[kCand];
+#pragma unroll
       for (int r = 0; r < kCand; ++r) {
         unsigned long long mx = k[0];
 #pragma unroll
-        for (int off = 1; off < L; off <<= 1) {
+        for (int off = 1; off < TPN; off <<= 1) {
           const unsigned long long o = __shfl_xor(mx, off, 64);
           mx = o > mx ? o : mx;
         }
@@ -137,112 +163,132 @@ __global__ __launch_bounds__(256) void k_select(StepArgs a) {
           for (int j = 0; j < KPL - 1; ++j) k[j] = k[j + 1];
           k[KPL - 1] = 0ull;
         }
-        if (lt == 0) {
-          const unsigned atom = 0xFFFFFFFFu - (unsigned)(mx & 0xFFFFFFFFull);
-          s_cand[g][r] = (mx != 0ull && atom < (unsigned)a.n_atoms) ? (int)atom : -1;
-        }
+        const unsigned atom = 0xFFFFFFFFu - (unsigned)(mx & 0xFFFFFFFFull);
+        cand[r] = (mx != 0ull && atom < (unsigned)a.n_atoms) ? (int)atom : -1;
       }
-    }
-    __syncthreads();
 
-    // 2. FP64 re-score of the candidates.
-    int py, px;
-    patch_origin<N>(lt, py, px);
-    float* r = a.r32 + (size_t)node * K;
-    float rv[G::PH][G::PW];
+      // 2. FP64 re-score of the candidates on this lane's patch.
+      float* r = a.r32 + (size_t)node * K;
+      float rv[G::PH][G::PW];
 #pragma unroll
-    for (int dy = 0; dy < G::PH; ++dy)
+      for (int dy = 0; dy < G::PH; ++dy)
 #pragma unroll
-      for (int dx = 0; dx < G::PW; ++dx) rv[dy][dx] = r[(py + dy) * N + px + dx];
-    double c[kCand];
+        for (int dx = 0; dx < G::PW; ++dx) rv[dy][dx] = r[(py + dy) * N + px + dx];
+      double c[kCand];
 #pragma unroll
-    for (int ci = 0; ci < kCand; ++ci) {
-      const int atom = s_cand[g][ci];
-      double part = 0.0;
-      if (atom >= 0) {
-        const int f = atom / K, q = (atom % K) / N, p = atom % N;
-        const double* tf = a.tab + (size_t)f * K;
-        if (p == 0 && q == 0) {
-          double s = 0.0;
-#pragma unroll
-          for (int dy = 0; dy < G::PH; ++dy)
-#pragma unroll
-            for (int dx = 0; dx < G::PW; ++dx) s += (double)rv[dy][dx];
-          part = s * inv_n;
-        } else {
-#pragma unroll
-          for (int dy = 0; dy < G::PH; ++dy) {
+      for (int ci = 0; ci < kCand; ++ci) {
+        const int atom = cand[ci];
+        double part = 0.0;
+        if (atom >= 0) {
+          const int f = atom / K, q = (atom % K) / N, p = atom % N;
+          const double* tf = a.tab + (size_t)f * K;
+          if (p == 0 && q == 0) {
             double s = 0.0;
 #pragma unroll
-            for (int dx = 0; dx < G::PW; ++dx) s = fma((double)rv[dy][dx], tf[q * N + px + dx], s);
-            part = fma(tf[p * N + py + dy], s, part);
+            for (int dy = 0; dy < G::PH; ++dy)
+#pragma unroll
+              for (int dx = 0; dx < G::PW; ++dx) s += (double)rv[dy][dx];
+            part = s * inv_n;
+          } else {
+            double tq[G::PW];
+#pragma unroll
+            for (int dx = 0; dx < G::PW; ++dx) tq[dx] = tf[q * N + px + dx];
+#pragma unroll
+            for (int dy = 0; dy < G::PH; ++dy) {
+              double s = 0.0;
+#pragma unroll
+              for (int dx = 0; dx < G::PW; ++dx) s = fma((double)rv[dy][dx], tq[dx], s);
+              part = fma(tf[p * N + py + dy], s, part);
+            }
+          }
+        }
+        c[ci] = lanes_sum<TPN>(part);
+      }
+
+      // 3. arg-max over the re-scored candidates, lowest atom index on ties.
+      int best = -1;
+      double bmag = -1.0;
+#pragma unroll
+      for (int ci = 0; ci < kCand; ++ci) {
+        const int atom = cand[ci];
+        if (atom < 0) continue;
+        const double m = fabs(c[ci]);
+        if (best < 0 || m > bmag || (m == bmag && atom < cand[best])) {
+          best = ci;
+          bmag = m;
+        }
+      }
+      const bool zero = (best < 0 || bmag == 0.0);
+      int atom = 0;
+      double coef = 0.0;
+#pragma unroll
+      for (int ci = 0; ci < kCand; ++ci)
+        if (ci == best) {
+          atom = cand[ci];
+          coef = c[ci];
+        }
+      if (zero) {
+        atom = 0;
+        coef = 0.0;
+      }
+
+      // 4. rank-1 update and the new squared norm.
+      const int f = atom / K, q = (atom % K) / N, p = atom % N;
+      const double* tf = a.tab + (size_t)f * K;
+      const bool dc = (p == 0 && q == 0);
+      double tq[G::PW];
+#pragma unroll
+      for (int dx = 0; dx < G::PW; ++dx) tq[dx] = tf[q * N + px + dx];
+      double e = 0.0;
+      const bool store = valid && !zero;
+#pragma unroll
+      for (int dy = 0; dy < G::PH; ++dy) {
+        const double ty = tf[p * N + py + dy];
+        float rn[G::PW];
+#pragma unroll
+        for (int dx = 0; dx < G::PW; ++dx) {
+          const double phi = dc ? inv_n : ty * tq[dx];
+          rn[dx] = (float)fma(-coef, phi, (double)rv[dy][dx]);
+          e = fma((double)rn[dx], (double)rn[dx], e);
+        }
+        if (store) {
+          const int o = (py + dy) * N + px;
+#pragma unroll
+          for (int dx = 0; dx < G::PW; ++dx) r[o + dx] = rn[dx];
+          if (a.r16) {
+#pragma unroll
+            for (int dx = 0; dx < G::PW; ++dx) a.r16[(size_t)node * K + o + dx] = f32_to_bf16(rn[dx]);
           }
         }
       }
-      c[ci] = part;
-    }
-    group_sum_n<TPN, kCand>(c, s_red[g]);
+      e = lanes_sum<TPN>(e);
 
-    // 3. arg-max over the re-scored candidates, lowest atom index on ties.
-    int best = -1;
-    double bmag = -1.0;
-#pragma unroll
-    for (int ci = 0; ci < kCand; ++ci) {
-      const int atom = s_cand[g][ci];
-      if (atom < 0) continue;
-      const double m = fabs(c[ci]);
-      if (best < 0 || m > bmag || (m == bmag && atom < s_cand[g][best])) {
-        best = ci;
-        bmag = m;
-      }
-    }
-    const JobDev& jb = a.jobs[a.lv.job[node]];
-    const int t = a.lv.t[node];
-    const bool zero = (best < 0 || bmag == 0.0);   // uniform within the group
-    const int atom = zero ? 0 : s_cand[g][best];
-    const double coef = zero ? 0.0 : c[best];
-
-    // 4. rank-1 update and the new squared norm.
-    const int f = atom / K, q = (atom % K) / N, p = atom % N;
-    const double* tf = a.tab + (size_t)f * K;
-    const bool dc = (p == 0 && q == 0);
-    double e = 0.0;
-#pragma unroll
-    for (int dy = 0; dy < G::PH; ++dy) {
-      const double ty = tf[p * N + py + dy];
-#pragma unroll
-      for (int dx = 0; dx < G::PW; ++dx) {
-        const double phi = dc ? inv_n : ty * tf[q * N + px + dx];
-        const float rn = (float)fma(-coef, phi, (double)rv[dy][dx]);
-        const int o = (py + dy) * N + px + dx;
-        if (valid && !zero) {
-          r[o] = rn;
-          if (a.r16) a.r16[(size_t)node * K + o] = f32_to_bf16(rn);
+      // 5. record and stop test (a zero correlation stops without a record).
+      bool run = false;
+      if (valid) {
+        const JobDev& jb = a.jobs[a.lv.job[node]];
+        const int t = a.lv.t[node];
+        if (zero) {
+          if (lt == 0) a.lv.st[node] = ST_ZERO;
+        } else {
+          uint8_t st = ST_RUN;
+          if (e < jb.eps2[lg])
+            st = ST_ACC;
+          else if (t + 1 >= jb.k[lg])
+            st = ST_SPARSE;
+          run = (st == ST_RUN);
+          if (lt == 0) {
+            const size_t rs = (size_t)node * a.lv.kmax + t;
+            a.lv.rec_idx[rs] = atom;
+            a.lv.rec_coef[rs] = coef;
+            a.lv.t[node] = t + 1;
+            a.lv.e[node] = e;
+            a.lv.st[node] = st;
+          }
         }
-        e = fma((double)rn, (double)rn, e);
       }
+      (void)run;
     }
-    e = group_sum<TPN>(e, s_red[g]);
-
-    // 5. record and stop test (a zero correlation stops without a record).
-    if (valid && lt == 0) {
-      if (zero) {
-        a.lv.st[node] = ST_ZERO;
-      } else {
-        const size_t slot = (size_t)node * a.lv.kmax + t;
-        a.lv.rec_idx[slot] = atom;
-        a.lv.rec_coef[slot] = coef;
-        a.lv.t[node] = t + 1;
-        a.lv.e[node] = e;
-        uint8_t st = ST_RUN;
-        if (e < jb.eps2[lg])
-          st = ST_ACC;
-        else if (t + 1 >= jb.k[lg])
-          st = ST_SPARSE;
-        a.lv.st[node] = st;
-      }
-    }
-    __syncthreads();
   }
 }
 
@@ -326,7 +372,7 @@ hipError_t launch_gather(int n, const StepArgs& a, const int32_t* count, hipStre
 }
 
 hipError_t launch_select(int n, const StepArgs& a, hipStream_t s) {
-  AQMP_DISPATCH_N(n, hipLaunchKernelGGL(k_select<NN>, dim3(grid_for<NN>(8)), dim3(256), 0, s, a));
+  AQMP_DISPATCH_N(n, hipLaunchKernelGGL(k_select<NN>, dim3(grid_for<NN>(4)), dim3(256), 0, s, a));
   return hipGetLastError();
 }
 

@@ -9,17 +9,6 @@ namespace aqmp {
 
 namespace {
 
-constexpr unsigned long long kFlagAgg = 1ull << 62;   // tile aggregate published
-constexpr unsigned long long kFlagInc = 2ull << 62;   // inclusive prefix published
-constexpr int kSpinLimit = 1 << 24;                   // bounded wait per look-back step
-
-__device__ inline unsigned long long load_acq(unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void store_rel(unsigned long long* p, unsigned long long v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // One launch = one stable scan over op.count() items with 0/1 keep flags.
 // Blocks take tiles in ticket order, so a block only ever waits on tiles
 // owned by blocks that started before it.  Every wait is bounded; when a
@@ -59,33 +48,9 @@ __device__ void stable_scan(Op& op, ScanState ss, int32_t* err) {
     for (int j = 0; j < w; ++j) wpre += s_wsum[j];
     const int agg = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
     const int excl = wpre + x - loc;
-    if (tid == 0) {
-      int prefix = 0;
-      if (tile == 0) {
-        store_rel(&ss.tiles[0], kFlagInc | (unsigned)agg);
-      } else {
-        store_rel(&ss.tiles[tile], kFlagAgg | (unsigned)agg);
-        int p = tile - 1;
-        int spins = 0;
-        while (p >= 0) {
-          const unsigned long long v = load_acq(&ss.tiles[p]);
-          const unsigned long long fl = v >> 62;
-          if (fl == 0) {
-            if (++spins > kSpinLimit) {
-              atomicExch(err, 1);
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-          }
-          prefix += (int)(unsigned)(v & 0xFFFFFFFFull);
-          if (fl == 2) break;
-          --p;
-          spins = 0;
-        }
-        store_rel(&ss.tiles[tile], kFlagInc | (unsigned)(prefix + agg));
-      }
-      s_prefix = prefix;
+    if (w == 0) {
+      const int pre = lookback_wave(ss.tiles, tile, agg, err);
+      if (lane == 0) s_prefix = pre;
     }
     __syncthreads();
     int pos = s_prefix + excl;
