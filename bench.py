@@ -151,6 +151,7 @@ def main():
     ap.add_argument("--fp32-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--corr-variant", type=int, default=0, help="BF16 correlation kernel variant (0 = default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the encoder is a single-GPU path (--gpus {args.gpus} "
@@ -176,7 +177,8 @@ def main():
 
     # Headline: batched BF16, all jobs in one captured graph, replayed.
     log("batched bf16: build + capture")
-    code = A.Code(dic, imgs, w["params"], w["jobs"], precision=A.PREC_BF16, schedule=A.SCHED_BATCHED)
+    code = A.Code(dic, imgs, w["params"], w["jobs"], precision=A.PREC_BF16, schedule=A.SCHED_BATCHED,
+                  corr_variant=args.corr_variant)
     torch.cuda.synchronize()
     sec = time_steps(code, imgs, args.steps, args.warmup)
     stats = code.stats()
@@ -188,7 +190,7 @@ def main():
     # this encode is issued on the stream), K steps, then the roofline of the
     # dominant kernel from the summed event times.
     code_t = A.Code(dic, imgs, w["params"], w["jobs"], precision=A.PREC_BF16, schedule=A.SCHED_BATCHED,
-                    timing=True)
+                    timing=True, corr_variant=args.corr_variant)
     sec_t = time_steps(code_t, imgs, args.steps, args.warmup)
     roof = roofline(code_t.stats(), code_t.timing(), A.PREC_BF16)
     code_t.free()

@@ -125,7 +125,10 @@ typedef struct {
                           Events cannot be timed inside a graph, so a timed
                           batched encode issues the same launches directly
                           on the stream. */
-  int32_t reserved[5];
+  int32_t corr_variant;  /* tuning: 0 = library default; 1..3 force one
+                            BF16 correlation kernel variant for N >= 16
+                            (results are identical, only speed differs) */
+  int32_t reserved[4];
 } aqmp_options;
 
 /* A leaf of the quadtree (or, from aqmp_code_export_nodes, any visited

@@ -57,7 +57,7 @@ class Job(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("schedule", C.c_int32), ("flags", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("corr_variant", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class Leaf(C.Structure):
@@ -207,7 +207,7 @@ class Code:
     """An encode: the quadtree leaves and their atoms, kept on the device."""
 
     def __init__(self, dic: Dictionary, images, params, jobs, precision: int = PREC_FP32,
-                 schedule: int = SCHED_PLAIN, stream=None, timing: bool = False):
+                 schedule: int = SCHED_PLAIN, stream=None, timing: bool = False, corr_variant: int = 0):
         self.dic = dic
         self._keep = list(images)
         imgs = (Image * len(images))(*[make_image(t) for t in images])
@@ -216,6 +216,7 @@ class Code:
         opt = Options()
         opt.precision, opt.schedule = int(precision), int(schedule)
         opt.flags = OPT_TIMING if timing else 0
+        opt.corr_variant = int(corr_variant)
         h = C.c_void_p()
         _check(lib.aqmp_encode(dic.h, imgs, len(images), prms, len(params), jbs, len(jobs), C.byref(opt),
                                _stream_handle(stream), C.byref(h)))

@@ -103,6 +103,8 @@ int validate(const aqmp_dict* d, const aqmp_image* imgs, int n_imgs, const aqmp_
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad precision");
     if (opt->schedule != AQMP_SCHED_PLAIN && opt->schedule != AQMP_SCHED_BATCHED)
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad schedule");
+    if (opt->corr_variant < 0 || opt->corr_variant > 3)
+      AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad corr_variant");
   }
   for (int i = 0; i < n_imgs; ++i) {
     const aqmp_image& im = imgs[i];
@@ -373,7 +375,7 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
       a.act_count = &cnt->act[cur];
       const aqmp_code::StepEv* se = timing ? &c->sev[c->sev_pos++] : nullptr;
       if (se) AQMP_HIP(hipEventRecord(se->a, s));
-      AQMP_LAUNCH(launch_corr(n, c->opt.precision, atoms, a, D.m_pad, s));
+      AQMP_LAUNCH(launch_corr(n, c->opt.precision, c->opt.corr_variant, atoms, a, D.m_pad, s));
       if (se) AQMP_HIP(hipEventRecord(se->b, s));
       AQMP_LAUNCH(launch_select(n, a, s));
       if (se) AQMP_HIP(hipEventRecord(se->c, s));

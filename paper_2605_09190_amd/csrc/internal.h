@@ -103,7 +103,7 @@ hipError_t launch_compact(const int32_t* in_list, const int32_t* in_count, const
 hipError_t launch_split_emit(const JobDev* jobs, LevelDev parent, const int32_t* parent_count,
                              LevelDev child, int32_t child_ntop, int32_t* child_count,
                              int32_t lg, int64_t cap, ScanState ss, int32_t* err, hipStream_t s);
-hipError_t launch_corr(int n, int precision, const void* dict_atoms, const StepArgs& a,
+hipError_t launch_corr(int n, int precision, int variant, const void* dict_atoms, const StepArgs& a,
                        int32_t m_pad, hipStream_t s);
 hipError_t launch_select(int n, const StepArgs& a, hipStream_t s);
 hipError_t launch_decode(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t job,

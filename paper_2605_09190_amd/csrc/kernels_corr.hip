@@ -281,133 +281,141 @@ __global__ __launch_bounds__(256, 1) void k_corr_bf16(const uint16_t* __restrict
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) const void gbl_void_t;
 
-namespace dma {
-constexpr int BA = 256, BB = 128, BK = 64, WA = 2, WB = 2;
-constexpr int WTA = BA / WA, WTB = BB / WB, MA = WTA / 32, MB = WTB / 32;
-constexpr int ROWB = BK * 2;                  // bytes per LDS row
-constexpr int A_BYTES = BA * ROWB, B_BYTES = BB * ROWB;
-constexpr int A_INS = BA / 8 / 4, B_INS = BB / 8 / 4;   // 1 KB blocks per wave
-constexpr int INS = A_INS + B_INS;                       // DMA instructions per wave per stage
-}  // namespace dma
+// Geometry of the direct-to-LDS kernel for a stage depth BK (64 or 32).
+template <int BK_>
+struct DmaGeo {
+  static constexpr int BA = 256, BB = 128, BK = BK_, WA = 2, WB = 2;
+  static constexpr int WTA = BA / WA, WTB = BB / WB, MA = WTA / 32, MB = WTB / 32;
+  static constexpr int ROWB = BK * 2;              // bytes per LDS row
+  static constexpr int CPR = ROWB / 16;            // 16-byte chunks per row
+  static constexpr int RPB = 1024 / ROWB;          // rows per 1 KB block (one wave DMA)
+  static constexpr int A_BYTES = BA * ROWB, B_BYTES = BB * ROWB;
+  static constexpr int A_INS = BA / RPB / 4, B_INS = BB / RPB / 4;   // DMA per wave per stage
+  static constexpr int INS = A_INS + B_INS;
+  static_assert(A_INS % 2 == 0, "block parity of a wave's first block is even");
+  using C = Cfg<BA, BB, BK, WA, WB>;
+  // Slot swizzle of row r: the rows one LDS phase reads (8 rows of a 128-byte
+  // phase or 16 rows of a 256-byte phase) land in distinct banks.
+  __device__ static int swz(int r) {
+    if constexpr (BK == 64) return (r & 7) ^ ((r >> 3) & 1);
+    else return ((r >> 1) ^ (r >> 2)) & 3;
+  }
+};
 
 // vmcnt(n) with the other counters left alone (gfx9 encoding).
 #define AQMP_WAIT_VM(n) __builtin_amdgcn_s_waitcnt(((n) & 0xF) | (0x7 << 4) | (0xF << 8) | ((((n) >> 4) & 0x3) << 14))
 
+template <class G>
 struct DmaPtrs {
-  const char* a_lane[2];     // A: lane part for even / odd blocks (bytes, stage 0)
-  const char* b_lane[dma::B_INS];
+  const char* a_lane[2];     // A: this lane's address in even / odd blocks (stage 0)
+  const char* b_lane[G::B_INS];
 };
 
-template <int K>
-__device__ inline void dma_issue(const DmaPtrs& p, char* sa, char* sb, int s) {
-  using namespace dma;
+template <class G, int K>
+__device__ inline void dma_issue(const DmaPtrs<G>& p, char* sa, char* sb, int s) {
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const size_t kofs = (size_t)s * BK * 2;
+  const size_t kofs = (size_t)s * G::BK * 2;
 #pragma unroll
-  for (int i = 0; i < A_INS; ++i) {
-    const int blk = w * A_INS + i;
-    const char* g = p.a_lane[i & 1] + (size_t)i * 8 * K * 2 + kofs;
+  for (int i = 0; i < G::A_INS; ++i) {
+    const int blk = w * G::A_INS + i;
+    const char* g = p.a_lane[i & 1] + (size_t)i * G::RPB * K * 2 + kofs;
     __builtin_amdgcn_global_load_lds((gbl_void_t*)g, (lds_void_t*)(sa + blk * 1024), 16, 0, 0);
   }
 #pragma unroll
-  for (int i = 0; i < B_INS; ++i) {
-    const int blk = w * B_INS + i;
+  for (int i = 0; i < G::B_INS; ++i) {
+    const int blk = w * G::B_INS + i;
     __builtin_amdgcn_global_load_lds((gbl_void_t*)(p.b_lane[i] + kofs), (lds_void_t*)(sb + blk * 1024), 16, 0, 0);
   }
 }
 
-__device__ inline void dma_compute(f32x16 (&acc)[dma::MA][dma::MB], const char* sa, const char* sb,
-                                   const int (&off)[dma::BK / 16]) {
-  using namespace dma;
+template <class G>
+__device__ inline void dma_compute(f32x16 (&acc)[G::MA][G::MB], const char* sa, const char* sb,
+                                   const int (&off)[G::BK / 16]) {
   const int w = threadIdx.x >> 6;
-  const int wa = w % WA, wb = w / WA;
-  const char* pa = sa + wa * WTA * ROWB;
-  const char* pb = sb + wb * WTB * ROWB;
-  bf16x8 fa[2][MA], fb[2][MB];
+  const int wa = w % G::WA, wb = w / G::WA;
+  const char* pa = sa + wa * G::WTA * G::ROWB;
+  const char* pb = sb + wb * G::WTB * G::ROWB;
+  bf16x8 fa[2][G::MA], fb[2][G::MB];
 #pragma unroll
-  for (int ma = 0; ma < MA; ++ma) fa[0][ma] = *(const bf16x8*)(pa + ma * 32 * ROWB + off[0]);
+  for (int ma = 0; ma < G::MA; ++ma) fa[0][ma] = *(const bf16x8*)(pa + ma * 32 * G::ROWB + off[0]);
 #pragma unroll
-  for (int mb = 0; mb < MB; ++mb) fb[0][mb] = *(const bf16x8*)(pb + mb * 32 * ROWB + off[0]);
+  for (int mb = 0; mb < G::MB; ++mb) fb[0][mb] = *(const bf16x8*)(pb + mb * 32 * G::ROWB + off[0]);
 #pragma unroll
-  for (int kk = 0; kk < BK / 16; ++kk) {
+  for (int kk = 0; kk < G::BK / 16; ++kk) {
     const int cur = kk & 1, nxt = cur ^ 1;
-    if (kk + 1 < BK / 16) {
+    if (kk + 1 < G::BK / 16) {
 #pragma unroll
-      for (int ma = 0; ma < MA; ++ma) fa[nxt][ma] = *(const bf16x8*)(pa + ma * 32 * ROWB + off[kk + 1]);
+      for (int ma = 0; ma < G::MA; ++ma) fa[nxt][ma] = *(const bf16x8*)(pa + ma * 32 * G::ROWB + off[kk + 1]);
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) fb[nxt][mb] = *(const bf16x8*)(pb + mb * 32 * ROWB + off[kk + 1]);
+      for (int mb = 0; mb < G::MB; ++mb) fb[nxt][mb] = *(const bf16x8*)(pb + mb * 32 * G::ROWB + off[kk + 1]);
     }
 #pragma unroll
-    for (int ma = 0; ma < MA; ++ma)
+    for (int ma = 0; ma < G::MA; ++ma)
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb)
+      for (int mb = 0; mb < G::MB; ++mb)
         acc[ma][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[cur][ma], fb[cur][mb], acc[ma][mb], 0, 0, 0);
   }
 }
 
-template <int N>
-__global__ __launch_bounds__(256, 1) void k_corr_bf16_dma(const uint16_t* __restrict__ D,
-                                                          const uint16_t* __restrict__ X,
-                                                          const int32_t* __restrict__ act,
-                                                          const int32_t* __restrict__ act_count,
-                                                          unsigned long long* __restrict__ keys,
-                                                          int n_atom_tiles) {
-  using namespace dma;
+template <int N, int BK, int MINB>
+__global__ __launch_bounds__(256, MINB) void k_corr_bf16_dma(const uint16_t* __restrict__ D,
+                                                             const uint16_t* __restrict__ X,
+                                                             const int32_t* __restrict__ act,
+                                                             const int32_t* __restrict__ act_count,
+                                                             unsigned long long* __restrict__ keys,
+                                                             int n_atom_tiles) {
+  using G = DmaGeo<BK>;
   constexpr int K = N * N;
   constexpr int NST = K / BK;
   static_assert(K % BK == 0 && NST >= 1, "stages");
-  using C = Cfg<BA, BB, BK, WA, WB>;
-  __shared__ __attribute__((aligned(1024))) char sA0[A_BYTES];
-  __shared__ __attribute__((aligned(1024))) char sA1[A_BYTES];
-  __shared__ __attribute__((aligned(1024))) char sA2[A_BYTES];
-  __shared__ __attribute__((aligned(1024))) char sB0[B_BYTES];
-  __shared__ __attribute__((aligned(1024))) char sB1[B_BYTES];
-  __shared__ __attribute__((aligned(1024))) char sB2[B_BYTES];
+  __shared__ __attribute__((aligned(1024))) char sA0[G::A_BYTES];
+  __shared__ __attribute__((aligned(1024))) char sA1[G::A_BYTES];
+  __shared__ __attribute__((aligned(1024))) char sA2[G::A_BYTES];
+  __shared__ __attribute__((aligned(1024))) char sB0[G::B_BYTES];
+  __shared__ __attribute__((aligned(1024))) char sB1[G::B_BYTES];
+  __shared__ __attribute__((aligned(1024))) char sB2[G::B_BYTES];
+  static_assert(G::WA * G::BB * kTopR * 4 <= G::A_BYTES, "epilogue scratch fits one A buffer");
   uint32_t* sK = (uint32_t*)sA0;   // epilogue scratch, after the ring drains
 
   const int count = *act_count;
-  const int ntB = (count + BB - 1) / BB;
+  const int ntB = (count + G::BB - 1) / G::BB;
   const int ntiles = n_atom_tiles * ntB;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  // swizzle of this lane's MFMA rows (row & 31 == lane & 31)
-  const int fr = (lane & 7) ^ ((lane >> 3) & 1);
-  int off[BK / 16];
+  const int fr = G::swz(lane & 31);   // MFMA rows of this lane: row & 31 == lane & 31
+  int off[G::BK / 16];
 #pragma unroll
-  for (int kk = 0; kk < BK / 16; ++kk) off[kk] = (lane & 31) * ROWB + (((2 * kk + (lane >> 5)) ^ fr) << 4);
-  // DMA lane geometry: lane l of a 1 KB block fills row (l >> 3), slot (l & 7)
-  const int drow = lane >> 3, dslot = lane & 7;
+  for (int kk = 0; kk < G::BK / 16; ++kk) off[kk] = (lane & 31) * G::ROWB + (((2 * kk + (lane >> 5)) ^ fr) << 4);
+  const int drow = lane / G::CPR, dslot = lane % G::CPR;   // DMA: row within block, slot
   TileWalk walk(ntiles);
   for (int j = walk.slot; j < walk.chunk; j += walk.per) {
     const int tile = walk.tile(j);
     if (tile >= ntiles) break;
     const int a_tile = tile / ntB, b_tile = tile % ntB;
-    const int a0 = a_tile * BA, b0 = b_tile * BB;
-    DmaPtrs p;
+    const int a0 = a_tile * G::BA, b0 = b_tile * G::BB;
+    DmaPtrs<G> p;
 #pragma unroll
     for (int par = 0; par < 2; ++par) {
-      // block parity flips f(r) by (r >> 3) & 1 == block & 1
-      const int gc = dslot ^ drow ^ par;
-      p.a_lane[par] = (const char*)(D + (size_t)(a0 + w * A_INS * 8 + drow) * K + gc * 8);
+      const int gc = dslot ^ G::swz(par * G::RPB + drow);
+      p.a_lane[par] = (const char*)(D + (size_t)(a0 + w * G::A_INS * G::RPB + drow) * K + gc * 8);
     }
 #pragma unroll
-    for (int i = 0; i < B_INS; ++i) {
-      const int blk = w * B_INS + i;
-      const int row = blk * 8 + drow;
-      const int gc = dslot ^ drow ^ (blk & 1);
+    for (int i = 0; i < G::B_INS; ++i) {
+      const int row = (w * G::B_INS + i) * G::RPB + drow;
+      const int gc = dslot ^ G::swz(row);
       const int pos = min(b0 + row, count - 1);
       p.b_lane[i] = (const char*)(X + (size_t)act[pos] * K + gc * 8);
     }
-    f32x16 acc[MA][MB];
+    f32x16 acc[G::MA][G::MB];
 #pragma unroll
-    for (int ma = 0; ma < MA; ++ma)
+    for (int ma = 0; ma < G::MA; ++ma)
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb)
+      for (int mb = 0; mb < G::MB; ++mb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[ma][mb][r] = 0.f;
 
     __syncthreads();   // previous tile's epilogue is done with sK (= sA0)
-    dma_issue<K>(p, sA0, sB0, 0);
-    if constexpr (NST > 1) dma_issue<K>(p, sA1, sB1, 1);
+    dma_issue<G, K>(p, sA0, sB0, 0);
+    if constexpr (NST > 1) dma_issue<G, K>(p, sA1, sB1, 1);
     // Steady state: every stage waits for its own loads (the next stage's
     // stay in flight), passes the barrier, issues stage s + 2 and computes.
     // Three stages per trip so that the buffers are compile-time.
@@ -415,28 +423,28 @@ __global__ __launch_bounds__(256, 1) void k_corr_bf16_dma(const uint16_t* __rest
     constexpr int TRIPS = FULL / 3;
     for (int t = 0; t < TRIPS; ++t) {
       const int s = 3 * t;
-      AQMP_WAIT_VM(dma::INS);
+      AQMP_WAIT_VM(G::INS);
       __builtin_amdgcn_s_barrier();
-      dma_issue<K>(p, sA2, sB2, s + 2);
-      dma_compute(acc, sA0, sB0, off);
-      AQMP_WAIT_VM(dma::INS);
+      dma_issue<G, K>(p, sA2, sB2, s + 2);
+      dma_compute<G>(acc, sA0, sB0, off);
+      AQMP_WAIT_VM(G::INS);
       __builtin_amdgcn_s_barrier();
-      dma_issue<K>(p, sA0, sB0, s + 3);
-      dma_compute(acc, sA1, sB1, off);
-      AQMP_WAIT_VM(dma::INS);
+      dma_issue<G, K>(p, sA0, sB0, s + 3);
+      dma_compute<G>(acc, sA1, sB1, off);
+      AQMP_WAIT_VM(G::INS);
       __builtin_amdgcn_s_barrier();
-      dma_issue<K>(p, sA1, sB1, s + 4);
-      dma_compute(acc, sA2, sB2, off);
+      dma_issue<G, K>(p, sA1, sB1, s + 4);
+      dma_compute<G>(acc, sA2, sB2, off);
     }
     // Tail: the last (at most four) stages, all decisions compile-time.
     constexpr int S0 = 3 * TRIPS;
-#define AQMP_DMA_TAIL(I, SA, SB, NA, NB)                                  \
-    if constexpr (S0 + (I) < NST) {                                       \
-      if constexpr (S0 + (I) + 1 < NST) AQMP_WAIT_VM(dma::INS);           \
-      else AQMP_WAIT_VM(0);                                               \
-      __builtin_amdgcn_s_barrier();                                       \
-      if constexpr (S0 + (I) + 2 < NST) dma_issue<K>(p, NA, NB, S0 + (I) + 2); \
-      dma_compute(acc, SA, SB, off);                                      \
+#define AQMP_DMA_TAIL(I, SA, SB, NA, NB)                                    \
+    if constexpr (S0 + (I) < NST) {                                         \
+      if constexpr (S0 + (I) + 1 < NST) AQMP_WAIT_VM(G::INS);               \
+      else AQMP_WAIT_VM(0);                                                 \
+      __builtin_amdgcn_s_barrier();                                         \
+      if constexpr (S0 + (I) + 2 < NST) dma_issue<G, K>(p, NA, NB, S0 + (I) + 2); \
+      dma_compute<G>(acc, SA, SB, off);                                     \
     }
     AQMP_DMA_TAIL(0, sA0, sB0, sA2, sB2)
     AQMP_DMA_TAIL(1, sA1, sB1, sA0, sB0)
@@ -445,7 +453,7 @@ __global__ __launch_bounds__(256, 1) void k_corr_bf16_dma(const uint16_t* __rest
     static_assert(NST - S0 <= 4, "tail covers the remaining stages");
 #undef AQMP_DMA_TAIL
     __syncthreads();   // all waves done reading the ring before sK reuses sA0
-    epilogue<C>(acc, sK, a0, a_tile, n_atom_tiles, b0, count, keys);
+    epilogue<typename G::C>(acc, sK, a0, a_tile, n_atom_tiles, b0, count, keys);
   }
 }
 
@@ -566,6 +574,7 @@ using CfgMidF = Cfg<128, 128, 32, 2, 2>;    // N = 8, FP32
 using CfgSmallF = Cfg<32, 256, 16, 1, 4>;   // N = 4, FP32
 
 constexpr int kCorrGrid = 256;   // one persistent workgroup per CU
+constexpr int kDefaultVariant = 2;
 
 }  // namespace
 
@@ -573,32 +582,45 @@ int corr_atom_tile(int n) { return n >= 16 ? 256 : (n == 8 ? 128 : 32); }
 
 int corr_grid(int, int) { return kCorrGrid; }
 
+// Correlation kernel variants (BF16, N >= 16); 0 picks the default.
+//   1: direct-to-LDS, BK 64, three stages, one workgroup per CU;
+//   2: direct-to-LDS, BK 32, three stages, two workgroups per CU (default);
+//   3: register-staged loads, BK 64, double-buffered LDS.
 template <int N>
-static void launch_corr_n(int precision, const void* atoms, const StepArgs& a, int nat, hipStream_t s) {
+static void launch_corr_n(int precision, int variant, const void* atoms, const StepArgs& a, int nat, hipStream_t s) {
   using CB = typename std::conditional<(N >= 16), CfgBig, typename std::conditional<(N == 8), CfgMid, CfgSmall>::type>::type;
   using CF = typename std::conditional<(N >= 16), CfgBigF, typename std::conditional<(N == 8), CfgMidF, CfgSmallF>::type>::type;
   if (precision == AQMP_PREC_BF16) {
-    if constexpr (N >= 16)
-      hipLaunchKernelGGL((k_corr_bf16_dma<N>), dim3(kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms, a.r16,
-                         a.act, a.act_count, a.keys, nat);
-    else
+    if constexpr (N >= 16) {
+      if (variant == 0) variant = kDefaultVariant;
+      if (variant == 1)
+        hipLaunchKernelGGL((k_corr_bf16_dma<N, 64, 1>), dim3(kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms,
+                           a.r16, a.act, a.act_count, a.keys, nat);
+      else if (variant == 2)
+        hipLaunchKernelGGL((k_corr_bf16_dma<N, 32, 2>), dim3(2 * kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms,
+                           a.r16, a.act, a.act_count, a.keys, nat);
+      else
+        hipLaunchKernelGGL((k_corr_bf16<N, CB>), dim3(kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms, a.r16,
+                           a.act, a.act_count, a.keys, nat);
+    } else {
       hipLaunchKernelGGL((k_corr_bf16<N, CB>), dim3(kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms, a.r16,
                          a.act, a.act_count, a.keys, nat);
-  }
-  else
+    }
+  } else {
     hipLaunchKernelGGL((k_corr_f32<N, CF>), dim3(kCorrGrid), dim3(256), 0, s, (const float*)atoms, a.r32, a.act,
                        a.act_count, a.keys, nat);
+  }
 }
 
-hipError_t launch_corr(int n, int precision, const void* dict_atoms, const StepArgs& a, int32_t m_pad,
-                       hipStream_t s) {
+hipError_t launch_corr(int n, int precision, int variant, const void* dict_atoms, const StepArgs& a,
+                       int32_t m_pad, hipStream_t s) {
   const int nat = m_pad / corr_atom_tile(n);
   switch (n) {
-    case 4: launch_corr_n<4>(precision, dict_atoms, a, nat, s); break;
-    case 8: launch_corr_n<8>(precision, dict_atoms, a, nat, s); break;
-    case 16: launch_corr_n<16>(precision, dict_atoms, a, nat, s); break;
-    case 32: launch_corr_n<32>(precision, dict_atoms, a, nat, s); break;
-    case 64: launch_corr_n<64>(precision, dict_atoms, a, nat, s); break;
+    case 4: launch_corr_n<4>(precision, variant, dict_atoms, a, nat, s); break;
+    case 8: launch_corr_n<8>(precision, variant, dict_atoms, a, nat, s); break;
+    case 16: launch_corr_n<16>(precision, variant, dict_atoms, a, nat, s); break;
+    case 32: launch_corr_n<32>(precision, variant, dict_atoms, a, nat, s); break;
+    case 64: launch_corr_n<64>(precision, variant, dict_atoms, a, nat, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

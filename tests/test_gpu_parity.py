@@ -131,3 +131,35 @@ def test_mixed_jobs_small_sizes(A, dic, prec):
     rep = _check(A, code, chans, params, jobs, prec)
     _say(rep.summary())
     assert rep.ok(), rep.summary()
+
+
+def test_corr_variants_bit_identical(A, dic):
+    """Every BF16 correlation kernel variant sums the same products in the same
+    k order: the exported trees, atoms and coefficients are bit-identical."""
+    w = workload("c1")
+    img = w["channels"][0]
+    ref = None
+    for v in (1, 2, 3):
+        _say("variant", v)
+        imgs = [_dev(img)]
+        code = A.Code(dic, imgs, w["params"], [(0, 0)], precision=1, schedule=1, corr_variant=v)
+        e = code.export_nodes()
+        cur = (e.leaves.tobytes(), e.atom_idx.tobytes(), e.coef.tobytes())
+        if ref is None:
+            ref = cur
+        assert cur == ref, f"variant {v} differs"
+        code.free()
+
+
+def test_reencode_deterministic(A, dic):
+    """Re-encoding (graph replay) reproduces the first encode bit for bit."""
+    w = workload("c1")
+    imgs = [_dev(w["channels"][0])]
+    code = A.Code(dic, imgs, w["params"], [(0, 0)], precision=1, schedule=1)
+    e1 = code.export_nodes()
+    for _ in range(3):
+        code.reencode(imgs)
+        e2 = code.export_nodes()
+        assert e1.leaves.tobytes() == e2.leaves.tobytes()
+        assert e1.atom_idx.tobytes() == e2.atom_idx.tobytes()
+        assert e1.coef.tobytes() == e2.coef.tobytes()
