@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libaqmp.so")
 OBJ = os.path.join(ROOT, "_build")
-SOURCES = ["api.hip", "dict.hip", "encode.hip", "kernels_tree.hip", "kernels_mp.hip", "kernels_corr.hip"]
+SOURCES = ["api.hip", "dict.hip", "encode.hip", "kernels_tree.hip", "kernels_mp.hip", "kernels_corr.hip",
+           "kernels_fused.hip"]
 ARCH = "gfx950"
 
 

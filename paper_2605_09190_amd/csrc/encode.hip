@@ -103,7 +103,7 @@ int validate(const aqmp_dict* d, const aqmp_image* imgs, int n_imgs, const aqmp_
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad precision");
     if (opt->schedule != AQMP_SCHED_PLAIN && opt->schedule != AQMP_SCHED_BATCHED)
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad schedule");
-    if (opt->corr_variant < 0 || opt->corr_variant > 3)
+    if (opt->corr_variant < 0 || opt->corr_variant > 4)
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad corr_variant");
   }
   for (int i = 0; i < n_imgs; ++i) {
@@ -323,6 +323,7 @@ int build_plan(aqmp_code* c) {
         AQMP_HIP(hipEventCreate(&le.start));
         AQMP_HIP(hipEventCreate(&le.end));
         c->lev.push_back(le);
+        if ((1 << l) <= kFusedMaxN) continue;   // whole level in one launch
         for (int t = 0; t < pp.kmax[l]; ++t) {
           aqmp_code::StepEv se{l, nullptr, nullptr, nullptr};
           AQMP_HIP(hipEventCreate(&se.a));
@@ -365,6 +366,15 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
     const bool timing = (c->opt.flags & AQMP_OPT_TIMING) != 0;
     const aqmp_code::LevelEv* le = timing ? &c->lev[c->lev_pos++] : nullptr;
     if (le) AQMP_HIP(hipEventRecord(le->start, s));
+    if (n <= kFusedMaxN) {
+      // Small blocks: each node's whole pursuit in one launch (dictionary in LDS).
+      AQMP_LAUNCH(launch_mp_fused(n, c->djobs, a.lv, count, l, D.m, D.d_tab, s));
+      if (l > pp.lg_lo && pp.cap[l - 1] > 0)
+        AQMP_LAUNCH(launch_split_emit(c->djobs, a.lv, count, level_at(c, l - 1, pp.base[l - 1]), pp.ntop[l - 1],
+                                      &cnt->count[l - 1], l, pp.cap[l], c->ss, &cnt->scan_error, s));
+      if (le) AQMP_HIP(hipEventRecord(le->end, s));
+      continue;
+    }
     AQMP_LAUNCH(launch_gather(n, a, count, s));
     AQMP_LAUNCH(launch_compact(nullptr, count, a.lv.st, c->act[0], &cnt->act[0], pp.cap[l], c->ss,
                                &cnt->scan_error, s));

@@ -26,6 +26,7 @@ constexpr int kLevels = 7;        // log2(N) for N = 1 .. 64
 constexpr int kCand = AQMP_CANDIDATES;
 constexpr int kTopR = 8;          // keys kept per node per atom tile
 constexpr int kScanTile = 1024;   // items per block of the stable scans
+constexpr int kFusedMaxN = 8;     // levels up to this size run the fused per-node pursuit
 
 inline int ilog2(int n) {
   int l = 0;
@@ -106,6 +107,8 @@ hipError_t launch_split_emit(const JobDev* jobs, LevelDev parent, const int32_t*
 hipError_t launch_corr(int n, int precision, int variant, const void* dict_atoms, const StepArgs& a,
                        int32_t m_pad, hipStream_t s);
 hipError_t launch_select(int n, const StepArgs& a, hipStream_t s);
+hipError_t launch_mp_fused(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t lg, int32_t n_atoms,
+                           const double* tab, hipStream_t s);
 hipError_t launch_decode(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t job,
                          int32_t nfam, const double* tab, void* out, int32_t dtype,
                          int64_t row_stride, hipStream_t s);

@@ -567,6 +567,8 @@ __global__ __launch_bounds__(256, 1) void k_corr_f32(const float* __restrict__ D
 }
 
 using CfgBig = Cfg<256, 128, 64, 2, 2>;     // N >= 16, BF16
+using CfgNarrow = Cfg<256, 32, 64, 4, 1>;   // N = 16, 32, BF16, narrow node tiles
+using CfgNarrow8 = Cfg<128, 32, 64, 4, 1>;  // N = 8, BF16, narrow node tiles
 using CfgMid = Cfg<128, 128, 64, 2, 2>;     // N = 8, BF16
 using CfgSmall = Cfg<32, 256, 16, 1, 4>;    // N = 4, BF16
 using CfgBigF = Cfg<256, 128, 32, 2, 2>;    // N >= 16, FP32
@@ -582,17 +584,29 @@ int corr_atom_tile(int n) { return n >= 16 ? 256 : (n == 8 ? 128 : 32); }
 
 int corr_grid(int, int) { return kCorrGrid; }
 
-// Correlation kernel variants (BF16, N >= 16); 0 picks the default.
-//   1: direct-to-LDS, BK 64, three stages, one workgroup per CU;
-//   2: direct-to-LDS, BK 32, three stages, two workgroups per CU (default);
-//   3: register-staged loads, BK 64, double-buffered LDS.
+// Correlation kernel variants (BF16); 0 picks the default.
+//   1: direct-to-LDS, BK 64, three stages, one workgroup per CU (N >= 16);
+//   2: direct-to-LDS, BK 32, three stages, two workgroups per CU (N >= 16);
+//   3: register-staged loads, BK 64, 256 x 128 tiles;
+//   4: as 2 for N = 64; register-staged narrow node tiles (32 nodes) for
+//      N <= 32, so that the few nodes x atoms of the small levels still
+//      spread over every CU.
 template <int N>
 static void launch_corr_n(int precision, int variant, const void* atoms, const StepArgs& a, int nat, hipStream_t s) {
   using CB = typename std::conditional<(N >= 16), CfgBig, typename std::conditional<(N == 8), CfgMid, CfgSmall>::type>::type;
   using CF = typename std::conditional<(N >= 16), CfgBigF, typename std::conditional<(N == 8), CfgMidF, CfgSmallF>::type>::type;
+  if (variant == 0) variant = kDefaultVariant;
+  if constexpr (N <= 32 && N >= 8) {
+    if (precision == AQMP_PREC_BF16 && variant == 4) {
+      using CN = typename std::conditional<(N == 8), CfgNarrow8, CfgNarrow>::type;
+      hipLaunchKernelGGL((k_corr_bf16<N, CN>), dim3(2 * kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms, a.r16,
+                         a.act, a.act_count, a.keys, nat);
+      return;
+    }
+  }
+  if (variant == 4) variant = 2;
   if (precision == AQMP_PREC_BF16) {
     if constexpr (N >= 16) {
-      if (variant == 0) variant = kDefaultVariant;
       if (variant == 1)
         hipLaunchKernelGGL((k_corr_bf16_dma<N, 64, 1>), dim3(kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms,
                            a.r16, a.act, a.act_count, a.keys, nat);
