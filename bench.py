@@ -152,6 +152,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--corr-variant", type=int, default=0, help="BF16 correlation kernel variant (0 = default)")
+    ap.add_argument("--schedule", default="batched", choices=["batched", "concurrent"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the encoder is a single-GPU path (--gpus {args.gpus} "
@@ -177,7 +178,8 @@ def main():
 
     # Headline: batched BF16, all jobs in one captured graph, replayed.
     log("batched bf16: build + capture")
-    code = A.Code(dic, imgs, w["params"], w["jobs"], precision=A.PREC_BF16, schedule=A.SCHED_BATCHED,
+    sched = A.SCHED_BATCHED if args.schedule == "batched" else A.SCHED_CONCURRENT
+    code = A.Code(dic, imgs, w["params"], w["jobs"], precision=A.PREC_BF16, schedule=sched,
                   corr_variant=args.corr_variant)
     torch.cuda.synchronize()
     sec = time_steps(code, imgs, args.steps, args.warmup)
@@ -189,7 +191,7 @@ def main():
     # around every MP-step launch (events cannot be timed inside a graph, so
     # this encode is issued on the stream), K steps, then the roofline of the
     # dominant kernel from the summed event times.
-    code_t = A.Code(dic, imgs, w["params"], w["jobs"], precision=A.PREC_BF16, schedule=A.SCHED_BATCHED,
+    code_t = A.Code(dic, imgs, w["params"], w["jobs"], precision=A.PREC_BF16, schedule=sched,
                     timing=True, corr_variant=args.corr_variant)
     sec_t = time_steps(code_t, imgs, args.steps, args.warmup)
     roof = roofline(code_t.stats(), code_t.timing(), A.PREC_BF16)

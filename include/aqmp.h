@@ -59,7 +59,7 @@ enum { AQMP_F32 = 0, AQMP_F64 = 1 };              /* sample types          */
 enum { AQMP_TOL_RMS = 0, AQMP_TOL_ABS = 1 };      /* tolerance modes       */
 enum { AQMP_SPLIT_R1 = 0, AQMP_SPLIT_R2 = 1 };    /* split rules           */
 enum { AQMP_PREC_FP32 = 0, AQMP_PREC_BF16 = 1 };  /* correlation precision */
-enum { AQMP_SCHED_PLAIN = 0, AQMP_SCHED_BATCHED = 1 };
+enum { AQMP_SCHED_PLAIN = 0, AQMP_SCHED_BATCHED = 1, AQMP_SCHED_CONCURRENT = 2 };
 
 #define AQMP_MIN_N 4
 #define AQMP_MAX_N 64
@@ -119,7 +119,11 @@ typedef struct {
   int32_t schedule;    /* AQMP_SCHED_PLAIN: jobs one after another,
                           stream-ordered launches;
                           AQMP_SCHED_BATCHED: every job in one pass,
-                          captured once as a HIP graph and replayed. */
+                          captured once as a HIP graph and replayed;
+                          AQMP_SCHED_CONCURRENT: the jobs split into up to
+                          four groups of consecutive jobs, each group one
+                          pass, captured as parallel branches of one graph
+                          so that their launches overlap. */
   int32_t flags;       /* AQMP_OPT_TIMING: record HIP events around every
                           launch of an MP step (see aqmp_code_timing).
                           Events cannot be timed inside a graph, so a timed

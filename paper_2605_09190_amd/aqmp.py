@@ -27,7 +27,7 @@ F32, F64 = 0, 1
 TOL_RMS, TOL_ABS = 0, 1
 SPLIT_R1, SPLIT_R2 = 0, 1
 PREC_FP32, PREC_BF16 = 0, 1
-SCHED_PLAIN, SCHED_BATCHED = 0, 1
+SCHED_PLAIN, SCHED_BATCHED, SCHED_CONCURRENT = 0, 1, 2
 OPT_TIMING = 1
 MAX_ATOMS = 256
 CANDIDATES = 8

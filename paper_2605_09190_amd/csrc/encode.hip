@@ -52,11 +52,17 @@ struct aqmp_code {
   int64_t cap_total[aqmp::kLevels] = {};
   int32_t kmax_total[aqmp::kLevels] = {};
   aqmp::LevelDev lv[aqmp::kLevels] = {};
-  float* r32 = nullptr;
-  uint16_t* r16 = nullptr;
-  unsigned long long* keys = nullptr;
-  int32_t* act[2] = {nullptr, nullptr};
-  aqmp::ScanState ss{};
+  // Working buffers of a pass (residuals, keys, active lists, scan state).
+  // Passes that run one after another share one set; passes captured as
+  // parallel graph branches get one set each.
+  struct Work {
+    float* r32 = nullptr;
+    uint16_t* r16 = nullptr;
+    unsigned long long* keys = nullptr;
+    int32_t* act[2] = {nullptr, nullptr};
+    aqmp::ScanState ss{};
+  };
+  std::vector<Work> work;            // indexed by pass % work.size()
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   struct Alloc {
@@ -101,7 +107,8 @@ int validate(const aqmp_dict* d, const aqmp_image* imgs, int n_imgs, const aqmp_
   if (opt) {
     if (opt->precision != AQMP_PREC_FP32 && opt->precision != AQMP_PREC_BF16)
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad precision");
-    if (opt->schedule != AQMP_SCHED_PLAIN && opt->schedule != AQMP_SCHED_BATCHED)
+    if (opt->schedule != AQMP_SCHED_PLAIN && opt->schedule != AQMP_SCHED_BATCHED &&
+        opt->schedule != AQMP_SCHED_CONCURRENT)
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad schedule");
     if (opt->corr_variant < 0 || opt->corr_variant > 4)
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad corr_variant");
@@ -239,13 +246,35 @@ int build_plan(aqmp_code* c) {
   if (c->opt.schedule == AQMP_SCHED_BATCHED) {
     c->passes.resize(1);
     plan_pass(c, 0, nj, c->passes[0]);
+  } else if (c->opt.schedule == AQMP_SCHED_CONCURRENT) {
+    // Up to kBranches groups of consecutive jobs, balanced by pixel count.
+    const int nb = std::min(nj, kBranches);
+    int64_t total = 0;
+    for (int j = 0; j < nj; ++j) total += (int64_t)c->imgs[c->jobs[j].image].w * c->imgs[c->jobs[j].image].h;
+    int j0 = 0;
+    int64_t acc = 0;
+    for (int b = 0; b < nb; ++b) {
+      int j1 = j0;
+      const int64_t target = total * (b + 1) / nb;
+      while (j1 < nj && (j1 == j0 || acc < target) && nj - j1 > nb - b - 1) {
+        acc += (int64_t)c->imgs[c->jobs[j1].image].w * c->imgs[c->jobs[j1].image].h;
+        ++j1;
+      }
+      if (b == nb - 1) j1 = nj;
+      c->passes.emplace_back();
+      plan_pass(c, j0, j1, c->passes.back());
+      j0 = j1;
+    }
   } else {
     c->passes.resize(nj);
     for (int j = 0; j < nj; ++j) plan_pass(c, j, j + 1, c->passes[j]);
   }
   // Level arrays: the passes are laid out one after the other.
-  int64_t max_r = 0, max_keys = 0, max_cap = 0;
-  for (auto& pp : c->passes) {
+  const size_t nwork = c->opt.schedule == AQMP_SCHED_CONCURRENT ? c->passes.size() : 1;
+  std::vector<int64_t> max_r(nwork, 0), max_keys(nwork, 0), max_cap(nwork, 0);
+  for (size_t pi = 0; pi < c->passes.size(); ++pi) {
+    auto& pp = c->passes[pi];
+    const size_t wi = pi % nwork;
     for (int l = 0; l < kLevels; ++l) {
       pp.base[l] = c->cap_total[l];
       c->cap_total[l] += pp.cap[l];
@@ -253,9 +282,9 @@ int build_plan(aqmp_code* c) {
       const int64_t n = 1 << l;
       if (pp.cap[l] == 0) continue;
       const aqmp_dict::Level& D = c->dict->lv[l];
-      max_r = std::max(max_r, pp.cap[l] * n * n);
-      max_keys = std::max(max_keys, pp.cap[l] * (D.m_pad / corr_atom_tile((int)n)) * kTopR);
-      max_cap = std::max(max_cap, pp.cap[l]);
+      max_r[wi] = std::max(max_r[wi], pp.cap[l] * n * n);
+      max_keys[wi] = std::max(max_keys[wi], pp.cap[l] * (D.m_pad / corr_atom_tile((int)n)) * kTopR);
+      max_cap[wi] = std::max(max_cap[wi], pp.cap[l]);
       c->steps_launched += pp.kmax[l];
     }
   }
@@ -278,23 +307,29 @@ int build_plan(aqmp_code* c) {
     ALLOC(L.rec_idx, cap * L.kmax * 4);
     ALLOC(L.rec_coef, cap * L.kmax * 8);
   }
-  ALLOC(c->r32, max_r * 4);
-  if (c->opt.precision == AQMP_PREC_BF16) ALLOC(c->r16, max_r * 2);
-  ALLOC(c->keys, max_keys * 8);
-  ALLOC(c->act[0], max_cap * 4);
-  ALLOC(c->act[1], max_cap * 4);
+  c->work.resize(nwork);
+  for (size_t wi = 0; wi < nwork; ++wi) {
+    aqmp_code::Work& wk = c->work[wi];
+    ALLOC(wk.r32, max_r[wi] * 4);
+    if (c->opt.precision == AQMP_PREC_BF16) ALLOC(wk.r16, max_r[wi] * 2);
+    ALLOC(wk.keys, max_keys[wi] * 8);
+    ALLOC(wk.act[0], max_cap[wi] * 4);
+    ALLOC(wk.act[1], max_cap[wi] * 4);
+    // Tile words: one per scan tile of kScanTile items, or one per select
+    // chunk of at least 4 positions, whichever is more.
+    wk.ss.ntiles_max = (int32_t)(max_cap[wi] / 4 + 2);
+    ALLOC(wk.ss.tiles, sizeof(unsigned long long) * wk.ss.ntiles_max);
+    ALLOC(wk.ss.ticket, sizeof(int32_t) * 2);
+  }
   ALLOC(c->djobs, sizeof(JobDev) * nj);
   ALLOC(c->dcnt, sizeof(Counters) * c->passes.size());
   ALLOC(c->dntop, sizeof(int32_t) * kLevels * c->passes.size());
-  // Tile words: one per scan tile of kScanTile items, or one per select chunk
-  // of at least 4 positions, whichever is more.
-  c->ss.ntiles_max = (int32_t)(max_cap / 4 + 2);
-  ALLOC(c->ss.tiles, sizeof(unsigned long long) * c->ss.ntiles_max);
-  ALLOC(c->ss.ticket, sizeof(int32_t) * 2);
 #undef ALLOC
   hipStream_t s = c->stream;
-  AQMP_HIP(hipMemsetAsync(c->ss.tiles, 0, sizeof(unsigned long long) * c->ss.ntiles_max, s));
-  AQMP_HIP(hipMemsetAsync(c->ss.ticket, 0, sizeof(int32_t) * 2, s));
+  for (auto& wk : c->work) {
+    AQMP_HIP(hipMemsetAsync(wk.ss.tiles, 0, sizeof(unsigned long long) * wk.ss.ntiles_max, s));
+    AQMP_HIP(hipMemsetAsync(wk.ss.ticket, 0, sizeof(int32_t) * 2, s));
+  }
   AQMP_HIP(hipMemsetAsync(c->dcnt, 0, sizeof(Counters) * c->passes.size(), s));
   // Static top-level node lists.
   std::vector<int32_t> ntop_all(kLevels * c->passes.size(), 0);
@@ -344,6 +379,7 @@ int build_plan(aqmp_code* c) {
 
 int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
   const PassPlan& pp = c->passes[pi];
+  aqmp_code::Work& wk = c->work[pi % c->work.size()];
   Counters* cnt = c->dcnt + pi;
   const aqmp_dict* d = c->dict;
   AQMP_LAUNCH(launch_init_counts(cnt, c->dntop + pi * kLevels, s));
@@ -358,9 +394,9 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
     a.n_atoms = D.m;
     a.nfam = d->nfam;
     a.tab = D.d_tab;
-    a.r32 = c->r32;
-    a.r16 = c->opt.precision == AQMP_PREC_BF16 ? c->r16 : nullptr;
-    a.keys = c->keys;
+    a.r32 = wk.r32;
+    a.r16 = c->opt.precision == AQMP_PREC_BF16 ? wk.r16 : nullptr;
+    a.keys = wk.keys;
     a.n_atom_tiles = D.m_pad / corr_atom_tile(n);
     int32_t* count = &cnt->count[l];
     const bool timing = (c->opt.flags & AQMP_OPT_TIMING) != 0;
@@ -371,17 +407,17 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
       AQMP_LAUNCH(launch_mp_fused(n, c->djobs, a.lv, count, l, D.m, D.d_tab, s));
       if (l > pp.lg_lo && pp.cap[l - 1] > 0)
         AQMP_LAUNCH(launch_split_emit(c->djobs, a.lv, count, level_at(c, l - 1, pp.base[l - 1]), pp.ntop[l - 1],
-                                      &cnt->count[l - 1], l, pp.cap[l], c->ss, &cnt->scan_error, s));
+                                      &cnt->count[l - 1], l, pp.cap[l], wk.ss, &cnt->scan_error, s));
       if (le) AQMP_HIP(hipEventRecord(le->end, s));
       continue;
     }
     AQMP_LAUNCH(launch_gather(n, a, count, s));
-    AQMP_LAUNCH(launch_compact(nullptr, count, a.lv.st, c->act[0], &cnt->act[0], pp.cap[l], c->ss,
+    AQMP_LAUNCH(launch_compact(nullptr, count, a.lv.st, wk.act[0], &cnt->act[0], pp.cap[l], wk.ss,
                                &cnt->scan_error, s));
     int cur = 0;
     const void* atoms = c->opt.precision == AQMP_PREC_BF16 ? (const void*)D.d_bf16 : (const void*)D.d_f32;
     for (int t = 0; t < pp.kmax[l]; ++t) {
-      a.act = c->act[cur];
+      a.act = wk.act[cur];
       a.act_count = &cnt->act[cur];
       const aqmp_code::StepEv* se = timing ? &c->sev[c->sev_pos++] : nullptr;
       if (se) AQMP_HIP(hipEventRecord(se->a, s));
@@ -390,13 +426,13 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
       AQMP_LAUNCH(launch_select(n, a, s));
       if (se) AQMP_HIP(hipEventRecord(se->c, s));
       if (t + 1 < pp.kmax[l])
-        AQMP_LAUNCH(launch_compact(c->act[cur], &cnt->act[cur], a.lv.st, c->act[cur ^ 1], &cnt->act[cur ^ 1],
-                                   pp.cap[l], c->ss, &cnt->scan_error, s));
+        AQMP_LAUNCH(launch_compact(wk.act[cur], &cnt->act[cur], a.lv.st, wk.act[cur ^ 1], &cnt->act[cur ^ 1],
+                                   pp.cap[l], wk.ss, &cnt->scan_error, s));
       cur ^= 1;
     }
     if (l > pp.lg_lo && pp.cap[l - 1] > 0)
       AQMP_LAUNCH(launch_split_emit(c->djobs, a.lv, count, level_at(c, l - 1, pp.base[l - 1]), pp.ntop[l - 1],
-                                    &cnt->count[l - 1], l, pp.cap[l], c->ss, &cnt->scan_error, s));
+                                    &cnt->count[l - 1], l, pp.cap[l], wk.ss, &cnt->scan_error, s));
     if (le) AQMP_HIP(hipEventRecord(le->end, s));
   }
   return AQMP_OK;
@@ -407,7 +443,7 @@ int run(aqmp_code* c, hipStream_t s) {
   AQMP_HIP(hipMemcpyAsync(c->djobs, c->hjobs.data(), sizeof(JobDev) * c->hjobs.size(), hipMemcpyHostToDevice, s));
   // HIP events recorded inside a graph cannot be timed, so a timed encode
   // issues the same launch sequence directly on the stream.
-  if (c->opt.schedule == AQMP_SCHED_BATCHED && !(c->opt.flags & AQMP_OPT_TIMING)) {
+  if (c->opt.schedule != AQMP_SCHED_PLAIN && !(c->opt.flags & AQMP_OPT_TIMING)) {
     if (!c->gexec) {
       // Capture on a private stream (the caller's may be the null stream,
       // which cannot be captured); the graph is launched on the caller's.
@@ -418,9 +454,45 @@ int run(aqmp_code* c, hipStream_t s) {
         (void)hipStreamDestroy(cs);
         AQMP_FAIL(AQMP_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
       }
-      int rc = enqueue_pass(c, 0, cs);
+      int rc = AQMP_OK;
+      std::vector<hipStream_t> br;
+      std::vector<hipEvent_t> evs;
+      if (c->passes.size() == 1) {
+        rc = enqueue_pass(c, 0, cs);
+      } else {
+        // Parallel branches: fork from the capture stream, one pass per
+        // branch, join back.
+        hipEvent_t fork = nullptr;
+        e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+        if (e == hipSuccess) {
+          evs.push_back(fork);
+          e = hipEventRecord(fork, cs);
+        }
+        for (size_t pi = 0; pi < c->passes.size() && e == hipSuccess && rc == AQMP_OK; ++pi) {
+          hipStream_t bs = nullptr;
+          e = hipStreamCreateWithFlags(&bs, hipStreamNonBlocking);
+          if (e != hipSuccess) break;
+          br.push_back(bs);
+          e = hipStreamWaitEvent(bs, fork, 0);
+          if (e != hipSuccess) break;
+          rc = enqueue_pass(c, pi, bs);
+          if (rc != AQMP_OK) break;
+          hipEvent_t join = nullptr;
+          e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+          if (e != hipSuccess) break;
+          evs.push_back(join);
+          e = hipEventRecord(join, bs);
+          if (e == hipSuccess) e = hipStreamWaitEvent(cs, join, 0);
+        }
+        if (e != hipSuccess && rc == AQMP_OK) {
+          set_error(std::string("graph branches: ") + hipGetErrorString(e));
+          rc = AQMP_E_HIP;
+        }
+      }
       hipGraph_t g = nullptr;
       e = hipStreamEndCapture(cs, &g);
+      for (auto bs : br) (void)hipStreamDestroy(bs);
+      for (auto ev : evs) (void)hipEventDestroy(ev);
       (void)hipStreamDestroy(cs);
       if (rc != AQMP_OK) {
         if (g) (void)hipGraphDestroy(g);

@@ -27,6 +27,7 @@ constexpr int kCand = AQMP_CANDIDATES;
 constexpr int kTopR = 8;          // keys kept per node per atom tile
 constexpr int kScanTile = 1024;   // items per block of the stable scans
 constexpr int kFusedMaxN = 8;     // levels up to this size run the fused per-node pursuit
+constexpr int kBranches = 4;      // parallel graph branches of the concurrent schedule
 
 inline int ilog2(int n) {
   int l = 0;

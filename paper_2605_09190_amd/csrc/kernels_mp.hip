@@ -90,12 +90,33 @@ struct WGeo {
   static constexpr int PX = N / PW;
 };
 
-// Sum over the TPN lanes of a group (fixed butterfly: bit-reproducible).
-template <int TPN>
-__device__ inline double lanes_sum(double v) {
-#pragma unroll
-  for (int off = 1; off < TPN; off <<= 1) v += __shfl_xor(v, off, 64);
-  return v;
+// Whole-wave reductions with DPP row operations (quad swaps, row mirrors,
+// row broadcasts 15 and 31), then a read of lane 63: a fixed order, so the
+// results are bit-reproducible, and no LDS-crossbar round trips.
+template <int CTRL, int RM>
+__device__ inline unsigned long long dpp_u64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, RM, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, RM, 0xF, false);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+__device__ inline unsigned long long lane63_u64(unsigned long long v) {
+  const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)v, 63);
+  const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ inline unsigned long long wave_max_u64(unsigned long long v) {
+#define AQMP_MAXSTEP(C, RM) { const unsigned long long o = dpp_u64<C, RM>(v); v = o > v ? o : v; }
+  AQMP_MAXSTEP(0xB1, 0xF) AQMP_MAXSTEP(0x4E, 0xF) AQMP_MAXSTEP(0x141, 0xF)
+  AQMP_MAXSTEP(0x140, 0xF) AQMP_MAXSTEP(0x142, 0xA) AQMP_MAXSTEP(0x143, 0xC)
+#undef AQMP_MAXSTEP
+  return lane63_u64(v);
+}
+__device__ inline double wave_sum_f64(double d) {
+#define AQMP_SUMSTEP(C, RM) { d += __longlong_as_double((long long)dpp_u64<C, RM>((unsigned long long)__double_as_longlong(d))); }
+  AQMP_SUMSTEP(0xB1, 0xF) AQMP_SUMSTEP(0x4E, 0xF) AQMP_SUMSTEP(0x141, 0xF)
+  AQMP_SUMSTEP(0x140, 0xF) AQMP_SUMSTEP(0x142, 0xA) AQMP_SUMSTEP(0x143, 0xC)
+#undef AQMP_SUMSTEP
+  return __longlong_as_double((long long)lane63_u64((unsigned long long)__double_as_longlong(d)));
 }
 
 // ---------------------------------------------------------------------------
@@ -107,187 +128,182 @@ __device__ inline double lanes_sum(double v) {
 //   3. i = argmax |c| (lowest atom index on ties); stop if max |c| = 0;
 //   4. r <- r - c_i phi_i (FP64 arithmetic, stored in FP32), ||r||^2 in FP64;
 //   5. record (i, c_i), t <- t + 1, stop test of eq. (2).
-// A node is handled by one group of TPN lanes: no workgroup barriers and no
-// atomics, positions are walked grid-stride.  The stable compaction of the
-// nodes still running is a separate launch.
+// One wave per node (N >= 16), no workgroup barriers and no atomics;
+// positions are walked grid-stride.  The candidates' 1D table rows are
+// staged in the wave's LDS slice with one coalesced load, so nothing after
+// the merge waits on global memory.  The stable compaction of the nodes
+// still running is a separate launch.
 // ---------------------------------------------------------------------------
 template <int N>
 __global__ __launch_bounds__(256) void k_select(StepArgs a) {
   using G = WGeo<N>;
   constexpr int K = G::K, TPN = G::TPN;
+  static_assert(TPN == 64, "one wave per node");
   constexpr int KPL = 4;                   // keys per lane (<= 256 keys)
+  // per wave: rows [cand][0 = p row, 1 = q row][N] of the FP64 tables
+  __shared__ double sT[4][kCand][2][N];
   const int count = *a.act_count;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int g = lane / TPN, lt = lane % TPN;
   const int lg = a.lg;
   const int nkeys = a.n_atom_tiles * kTopR;
   const double inv_n = 1.0 / N;
-  const int py = (lt / G::PX) * G::PH;
-  const int px = (lt % G::PX) * G::PW;
-  const int stride = gridDim.x * 4 * G::NPI;
-  for (int pos0 = (blockIdx.x * 4 + w) * G::NPI; pos0 < count; pos0 += stride) {
-    {
-      const int pos = pos0 + g;
-      const bool valid = pos < count;
-      const int node = a.act[valid ? pos : pos0];
-      const int base = pos0;
+  const int py = (lane / G::PX) * G::PH;
+  const int px = (lane % G::PX) * G::PW;
+  const int stride = gridDim.x * 4;
+  for (int pos = blockIdx.x * 4 + w; pos < count; pos += stride) {
+    const int node = a.act[pos];
+    const JobDev& jb = a.jobs[a.lv.job[node]];
+    const int t = a.lv.t[node];
+    float* r = a.r32 + (size_t)node * K;
+    float rv[G::PH][G::PW];
+#pragma unroll
+    for (int dy = 0; dy < G::PH; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < G::PW; ++dx) rv[dy][dx] = r[(py + dy) * N + px + dx];
 
-      // 1. top kCand keys over the node's per-tile lists.
-      unsigned long long k[KPL];
-      const unsigned long long* kp = a.keys + (size_t)(valid ? pos : base) * nkeys;
+    // 1. top kCand keys over the node's per-tile lists.
+    unsigned long long k[KPL];
+    const unsigned long long* kp = a.keys + (size_t)pos * nkeys;
 #pragma unroll
-      for (int j = 0; j < KPL; ++j) {
-        const int idx = lt + j * TPN;
-        k[j] = idx < nkeys ? kp[idx] : 0ull;
-      }
+    for (int j = 0; j < KPL; ++j) {
+      const int idx = lane + j * 64;
+      k[j] = idx < nkeys ? kp[idx] : 0ull;
+    }
 #pragma unroll
-      for (int p0 = 0; p0 < KPL; ++p0)
+    for (int p0 = 0; p0 < KPL; ++p0)
 #pragma unroll
-        for (int p1 = 0; p1 < KPL - 1 - p0; ++p1)
-          if (k[p1] < k[p1 + 1]) {
-            const unsigned long long t = k[p1];
-            k[p1] = k[p1 + 1];
-            k[p1 + 1] = t;
-          }
-      int cand[kCand];
-#pragma unroll
-      for (int r = 0; r < kCand; ++r) {
-        unsigned long long mx = k[0];
-#pragma unroll
-        for (int off = 1; off < TPN; off <<= 1) {
-          const unsigned long long o = __shfl_xor(mx, off, 64);
-          mx = o > mx ? o : mx;
+      for (int p1 = 0; p1 < KPL - 1 - p0; ++p1)
+        if (k[p1] < k[p1 + 1]) {
+          const unsigned long long tt = k[p1];
+          k[p1] = k[p1 + 1];
+          k[p1 + 1] = tt;
         }
-        if (mx != 0ull && k[0] == mx) {
+    int cand[kCand];
 #pragma unroll
-          for (int j = 0; j < KPL - 1; ++j) k[j] = k[j + 1];
-          k[KPL - 1] = 0ull;
-        }
-        const unsigned atom = 0xFFFFFFFFu - (unsigned)(mx & 0xFFFFFFFFull);
-        cand[r] = (mx != 0ull && atom < (unsigned)a.n_atoms) ? (int)atom : -1;
+    for (int rr = 0; rr < kCand; ++rr) {
+      const unsigned long long mx = wave_max_u64(k[0]);
+      if (mx != 0ull && k[0] == mx) {
+#pragma unroll
+        for (int j = 0; j < KPL - 1; ++j) k[j] = k[j + 1];
+        k[KPL - 1] = 0ull;
       }
+      const unsigned atom = 0xFFFFFFFFu - (unsigned)(mx & 0xFFFFFFFFull);
+      cand[rr] = (mx != 0ull && atom < (unsigned)a.n_atoms) ? (int)atom : -1;
+    }
 
-      // 2. FP64 re-score of the candidates on this lane's patch.
-      float* r = a.r32 + (size_t)node * K;
-      float rv[G::PH][G::PW];
+    // Stage the candidates' table rows: 2 * kCand rows of N doubles.
+    for (int e = lane; e < kCand * 2 * N; e += 64) {
+      const int ci = e / (2 * N), which = (e / N) & 1, col = e % N;
+      const int atom = cand[0];
+      int at = atom;
 #pragma unroll
-      for (int dy = 0; dy < G::PH; ++dy)
+      for (int c2 = 1; c2 < kCand; ++c2)
+        if (ci == c2) at = cand[c2];
+      double v = 0.0;
+      if (at >= 0) {
+        const int f = at / K, q = (at % K) / N, p = at % N;
+        v = a.tab[(size_t)f * K + (which ? q : p) * N + col];
+      }
+      sT[w][ci][which][col] = v;
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    // 2. FP64 re-score of the candidates on this lane's patch.
+    double c[kCand];
 #pragma unroll
-        for (int dx = 0; dx < G::PW; ++dx) rv[dy][dx] = r[(py + dy) * N + px + dx];
-      double c[kCand];
+    for (int ci = 0; ci < kCand; ++ci) {
+      const int atom = cand[ci];
+      double part = 0.0;
+      if (atom >= 0) {
+        const int q = (atom % K) / N, p = atom % N;
+        if (p == 0 && q == 0) {
+          double s = 0.0;
 #pragma unroll
-      for (int ci = 0; ci < kCand; ++ci) {
-        const int atom = cand[ci];
-        double part = 0.0;
-        if (atom >= 0) {
-          const int f = atom / K, q = (atom % K) / N, p = atom % N;
-          const double* tf = a.tab + (size_t)f * K;
-          if (p == 0 && q == 0) {
+          for (int dy = 0; dy < G::PH; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < G::PW; ++dx) s += (double)rv[dy][dx];
+          part = s * inv_n;
+        } else {
+#pragma unroll
+          for (int dy = 0; dy < G::PH; ++dy) {
             double s = 0.0;
 #pragma unroll
-            for (int dy = 0; dy < G::PH; ++dy)
-#pragma unroll
-              for (int dx = 0; dx < G::PW; ++dx) s += (double)rv[dy][dx];
-            part = s * inv_n;
-          } else {
-            double tq[G::PW];
-#pragma unroll
-            for (int dx = 0; dx < G::PW; ++dx) tq[dx] = tf[q * N + px + dx];
-#pragma unroll
-            for (int dy = 0; dy < G::PH; ++dy) {
-              double s = 0.0;
-#pragma unroll
-              for (int dx = 0; dx < G::PW; ++dx) s = fma((double)rv[dy][dx], tq[dx], s);
-              part = fma(tf[p * N + py + dy], s, part);
-            }
+            for (int dx = 0; dx < G::PW; ++dx) s = fma((double)rv[dy][dx], sT[w][ci][1][px + dx], s);
+            part = fma(sT[w][ci][0][py + dy], s, part);
           }
         }
-        c[ci] = lanes_sum<TPN>(part);
+      }
+      c[ci] = wave_sum_f64(part);
+    }
+
+    // 3. arg-max over the re-scored candidates, lowest atom index on ties.
+    int best = -1;
+    double bmag = -1.0;
+#pragma unroll
+    for (int ci = 0; ci < kCand; ++ci) {
+      const int atom = cand[ci];
+      if (atom < 0) continue;
+      const double m = fabs(c[ci]);
+      if (best < 0 || m > bmag || (m == bmag && atom < cand[best])) {
+        best = ci;
+        bmag = m;
+      }
+    }
+    const bool zero = (best < 0 || bmag == 0.0);
+    int atom = 0, bsel = 0;
+    double coef = 0.0;
+#pragma unroll
+    for (int ci = 0; ci < kCand; ++ci)
+      if (ci == best) {
+        atom = cand[ci];
+        coef = c[ci];
+        bsel = ci;
       }
 
-      // 3. arg-max over the re-scored candidates, lowest atom index on ties.
-      int best = -1;
-      double bmag = -1.0;
-#pragma unroll
-      for (int ci = 0; ci < kCand; ++ci) {
-        const int atom = cand[ci];
-        if (atom < 0) continue;
-        const double m = fabs(c[ci]);
-        if (best < 0 || m > bmag || (m == bmag && atom < cand[best])) {
-          best = ci;
-          bmag = m;
-        }
-      }
-      const bool zero = (best < 0 || bmag == 0.0);
-      int atom = 0;
-      double coef = 0.0;
-#pragma unroll
-      for (int ci = 0; ci < kCand; ++ci)
-        if (ci == best) {
-          atom = cand[ci];
-          coef = c[ci];
-        }
-      if (zero) {
-        atom = 0;
-        coef = 0.0;
-      }
-
-      // 4. rank-1 update and the new squared norm.
-      const int f = atom / K, q = (atom % K) / N, p = atom % N;
-      const double* tf = a.tab + (size_t)f * K;
+    // 4. rank-1 update and the new squared norm.
+    double e = 0.0;
+    if (!zero) {
+      const int q = (atom % K) / N, p = atom % N;
       const bool dc = (p == 0 && q == 0);
-      double tq[G::PW];
-#pragma unroll
-      for (int dx = 0; dx < G::PW; ++dx) tq[dx] = tf[q * N + px + dx];
-      double e = 0.0;
-      const bool store = valid && !zero;
 #pragma unroll
       for (int dy = 0; dy < G::PH; ++dy) {
-        const double ty = tf[p * N + py + dy];
+        const double ty = sT[w][bsel][0][py + dy];
         float rn[G::PW];
 #pragma unroll
         for (int dx = 0; dx < G::PW; ++dx) {
-          const double phi = dc ? inv_n : ty * tq[dx];
+          const double phi = dc ? inv_n : ty * sT[w][bsel][1][px + dx];
           rn[dx] = (float)fma(-coef, phi, (double)rv[dy][dx]);
           e = fma((double)rn[dx], (double)rn[dx], e);
         }
-        if (store) {
-          const int o = (py + dy) * N + px;
+        const int o = (py + dy) * N + px;
 #pragma unroll
-          for (int dx = 0; dx < G::PW; ++dx) r[o + dx] = rn[dx];
-          if (a.r16) {
+        for (int dx = 0; dx < G::PW; ++dx) r[o + dx] = rn[dx];
+        if (a.r16) {
 #pragma unroll
-            for (int dx = 0; dx < G::PW; ++dx) a.r16[(size_t)node * K + o + dx] = f32_to_bf16(rn[dx]);
-          }
+          for (int dx = 0; dx < G::PW; ++dx) a.r16[(size_t)node * K + o + dx] = f32_to_bf16(rn[dx]);
         }
       }
-      e = lanes_sum<TPN>(e);
+      e = wave_sum_f64(e);
+    }
+    __builtin_amdgcn_wave_barrier();   // table rows consumed before the next node overwrites them
 
-      // 5. record and stop test (a zero correlation stops without a record).
-      bool run = false;
-      if (valid) {
-        const JobDev& jb = a.jobs[a.lv.job[node]];
-        const int t = a.lv.t[node];
-        if (zero) {
-          if (lt == 0) a.lv.st[node] = ST_ZERO;
-        } else {
-          uint8_t st = ST_RUN;
-          if (e < jb.eps2[lg])
-            st = ST_ACC;
-          else if (t + 1 >= jb.k[lg])
-            st = ST_SPARSE;
-          run = (st == ST_RUN);
-          if (lt == 0) {
-            const size_t rs = (size_t)node * a.lv.kmax + t;
-            a.lv.rec_idx[rs] = atom;
-            a.lv.rec_coef[rs] = coef;
-            a.lv.t[node] = t + 1;
-            a.lv.e[node] = e;
-            a.lv.st[node] = st;
-          }
-        }
+    // 5. record and stop test (a zero correlation stops without a record).
+    if (lane == 0) {
+      if (zero) {
+        a.lv.st[node] = ST_ZERO;
+      } else {
+        uint8_t st = ST_RUN;
+        if (e < jb.eps2[lg])
+          st = ST_ACC;
+        else if (t + 1 >= jb.k[lg])
+          st = ST_SPARSE;
+        const size_t rs = (size_t)node * a.lv.kmax + t;
+        a.lv.rec_idx[rs] = atom;
+        a.lv.rec_coef[rs] = coef;
+        a.lv.t[node] = t + 1;
+        a.lv.e[node] = e;
+        a.lv.st[node] = st;
       }
-      (void)run;
     }
   }
 }
@@ -372,7 +388,12 @@ hipError_t launch_gather(int n, const StepArgs& a, const int32_t* count, hipStre
 }
 
 hipError_t launch_select(int n, const StepArgs& a, hipStream_t s) {
-  AQMP_DISPATCH_N(n, hipLaunchKernelGGL(k_select<NN>, dim3(grid_for<NN>(4)), dim3(256), 0, s, a));
+  switch (n) {
+    case 16: hipLaunchKernelGGL(k_select<16>, dim3(grid_for<16>(4)), dim3(256), 0, s, a); break;
+    case 32: hipLaunchKernelGGL(k_select<32>, dim3(grid_for<32>(4)), dim3(256), 0, s, a); break;
+    case 64: hipLaunchKernelGGL(k_select<64>, dim3(grid_for<64>(4)), dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;   // smaller levels run the fused pursuit
+  }
   return hipGetLastError();
 }
 

@@ -65,7 +65,7 @@ def _check(A, code, chans, params, jobs, prec, blocks_per_job=None):
     return rep
 
 
-@pytest.mark.parametrize("prec,sched", [(0, 0), (1, 1), (0, 1), (1, 0)])
+@pytest.mark.parametrize("prec,sched", [(0, 0), (1, 1), (0, 1), (1, 0), (1, 2)])
 def test_c0_full_parity(A, dic, prec, sched):
     w = workload("c0")
     _say("c0", prec, sched)
@@ -117,8 +117,8 @@ def test_c1_sampled_parity(A, dic, prec):
     assert rep.ok(), rep.summary()
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_mixed_jobs_small_sizes(A, dic, prec):
+@pytest.mark.parametrize("prec,sched", [(0, 1), (1, 1), (1, 2)])
+def test_mixed_jobs_small_sizes(A, dic, prec, sched):
     """Several jobs with different block ranges (4..32), k, tolerances and both
     split rules in one batched pass, plus an FP64 input plane."""
     chans = [gradient_edges_image(64, 64, seed=3), piecewise_image(64, 128, seed=4)]
@@ -126,8 +126,8 @@ def test_mixed_jobs_small_sizes(A, dic, prec):
               dict(tol=0.01, max_atoms=20, n_min=8, n_max=32, split_rule="r2"),
               dict(tol=0.5, tol_mode="abs", max_atoms=40, n_min=4, n_max=32)]
     jobs = [(0, 0), (1, 1), (0, 2), (1, 0)]
-    _say("mixed", prec)
-    code, imgs = _encode(A, dic, chans, params, jobs, prec, 1, dtype="f64")
+    _say("mixed", prec, sched)
+    code, imgs = _encode(A, dic, chans, params, jobs, prec, sched, dtype="f64")
     rep = _check(A, code, chans, params, jobs, prec)
     _say(rep.summary())
     assert rep.ok(), rep.summary()
