@@ -129,7 +129,7 @@ typedef struct {
                           Events cannot be timed inside a graph, so a timed
                           batched encode issues the same launches directly
                           on the stream. */
-  int32_t corr_variant;  /* tuning: 0 = library default; 1..4 force one
+  int32_t corr_variant;  /* tuning: 0 = library default; 1..6 force one
                             family of BF16 correlation kernels (results
                             are identical, only speed differs) */
   int32_t reserved[4];

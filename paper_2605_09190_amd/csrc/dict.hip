@@ -9,9 +9,10 @@
 // Atom a = f N^2 + q N + p is T_f[p][y] T_f[q][x] (outer product of two 1D
 // rows, Section 2.1); the constant atom of every family is exactly 1/N so
 // that the two copies of it tie exactly in every precision.  The device keeps
-// the FP64 tables (re-score, update, decode) and the atoms rounded to FP32 and
-// BF16 (correlation), atom-major with pixels row-major, padded with zero
-// atoms to a whole number of correlation tiles.
+// the FP64 tables (re-score, update, decode) and the atoms in FP32 (the FP64
+// product rounded once) and BF16 (the FP32 product of the FP32-rounded table
+// entries, rounded to BF16), atom-major with pixels row-major, padded with
+// zero atoms to a whole number of correlation tiles.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -60,8 +61,21 @@ static double atom_value(const aqmp_dict::Level& L, int a, int y, int x) {
   return t[p * n + y] * t[q * n + x];
 }
 
+// BF16 atom value: the FP32 product of the two table entries rounded to FP32,
+// then rounded to BF16 (DC atoms exactly 1/N).  Kernels that build atoms from
+// the tables on the fly compute exactly this.
+static uint16_t atom_bf16(const aqmp_dict::Level& L, int a, int y, int x) {
+  const int n = L.n, k = L.k;
+  const int f = a / k, q = (a % k) / n, p = a % n;
+  if (p == 0 && q == 0) return f32_to_bf16(1.0f / (float)n);
+  const double* t = L.h_tab.data() + (size_t)f * k;
+  const float v = (float)t[p * n + y] * (float)t[q * n + x];
+  return f32_to_bf16(v);
+}
+
 static void free_level(aqmp_dict::Level& L) {
   if (L.d_tab) dev_free(L.d_tab, sizeof(double) * L.h_tab.size());
+  if (L.d_tabT32) dev_free(L.d_tabT32, sizeof(float) * L.h_tab.size());
   if (L.d_f32) dev_free(L.d_f32, sizeof(float) * (size_t)L.m_pad * L.k);
   if (L.d_bf16) dev_free(L.d_bf16, sizeof(uint16_t) * (size_t)L.m_pad * L.k);
   L = aqmp_dict::Level();
@@ -105,9 +119,15 @@ int dictionary_build(int n_min, int n_max, uint32_t families, hipStream_t s, aqm
         for (int x = 0; x < n; ++x) {
           const size_t o = (size_t)a * L.k + y * n + x;
           a32[o] = (float)atom_value(L, a, y, x);
-          a16[o] = f32_to_bf16(a32[o]);
+          a16[o] = atom_bf16(L, a, y, x);
         }
+    std::vector<float> tT(L.h_tab.size());
+    for (int fm = 0; fm < d->nfam; ++fm)
+      for (int y = 0; y < n; ++y)
+        for (int pp = 0; pp < n; ++pp)
+          tT[(size_t)fm * L.k + y * n + pp] = (float)L.h_tab[(size_t)fm * L.k + pp * n + y];
     int rc = dev_alloc((void**)&L.d_tab, sizeof(double) * L.h_tab.size());
+    if (rc == AQMP_OK) rc = dev_alloc((void**)&L.d_tabT32, sizeof(float) * tT.size());
     if (rc == AQMP_OK) rc = dev_alloc((void**)&L.d_f32, sizeof(float) * a32.size());
     if (rc == AQMP_OK) rc = dev_alloc((void**)&L.d_bf16, sizeof(uint16_t) * a16.size());
     if (rc != AQMP_OK) {
@@ -121,6 +141,8 @@ int dictionary_build(int n_min, int n_max, uint32_t families, hipStream_t s, aqm
       e = hipMemcpyAsync(L.d_f32, a32.data(), sizeof(float) * a32.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
       e = hipMemcpyAsync(L.d_bf16, a16.data(), sizeof(uint16_t) * a16.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(L.d_tabT32, tT.data(), sizeof(float) * tT.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
       dictionary_free(d);

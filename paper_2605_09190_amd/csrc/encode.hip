@@ -71,6 +71,7 @@ struct aqmp_code {
   };
   std::vector<Alloc> allocs;
   int64_t steps_launched = 0;
+  bool wide_residual = false;        // BF16 residual buffer of 4 GiB or more
   // Timing events (AQMP_OPT_TIMING): per level of every pass a start/end
   // pair, per MP step three events (before the correlation, after it, after
   // the select/update launch).
@@ -110,7 +111,7 @@ int validate(const aqmp_dict* d, const aqmp_image* imgs, int n_imgs, const aqmp_
     if (opt->schedule != AQMP_SCHED_PLAIN && opt->schedule != AQMP_SCHED_BATCHED &&
         opt->schedule != AQMP_SCHED_CONCURRENT)
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad schedule");
-    if (opt->corr_variant < 0 || opt->corr_variant > 4)
+    if (opt->corr_variant < 0 || opt->corr_variant > 6)
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad corr_variant");
   }
   for (int i = 0; i < n_imgs; ++i) {
@@ -307,6 +308,10 @@ int build_plan(aqmp_code* c) {
     ALLOC(L.rec_idx, cap * L.kmax * 4);
     ALLOC(L.rec_coef, cap * L.kmax * 8);
   }
+  // The direct-to-LDS correlation addresses residual rows with 32-bit byte
+  // offsets; larger passes use the register-staged kernel instead.
+  for (size_t wi = 0; wi < nwork; ++wi)
+    if (max_r[wi] * 2 >= (int64_t)1 << 32) c->wide_residual = true;
   c->work.resize(nwork);
   for (size_t wi = 0; wi < nwork; ++wi) {
     aqmp_code::Work& wk = c->work[wi];
@@ -394,6 +399,7 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
     a.n_atoms = D.m;
     a.nfam = d->nfam;
     a.tab = D.d_tab;
+    a.tabT32 = D.d_tabT32;
     a.r32 = wk.r32;
     a.r16 = c->opt.precision == AQMP_PREC_BF16 ? wk.r16 : nullptr;
     a.keys = wk.keys;
@@ -421,7 +427,8 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
       a.act_count = &cnt->act[cur];
       const aqmp_code::StepEv* se = timing ? &c->sev[c->sev_pos++] : nullptr;
       if (se) AQMP_HIP(hipEventRecord(se->a, s));
-      AQMP_LAUNCH(launch_corr(n, c->opt.precision, c->opt.corr_variant, atoms, a, D.m_pad, s));
+      const int variant = c->wide_residual ? 3 : c->opt.corr_variant;
+      AQMP_LAUNCH(launch_corr(n, c->opt.precision, variant, atoms, a, D.m_pad, s));
       if (se) AQMP_HIP(hipEventRecord(se->b, s));
       AQMP_LAUNCH(launch_select(n, a, s));
       if (se) AQMP_HIP(hipEventRecord(se->c, s));

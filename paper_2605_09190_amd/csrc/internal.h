@@ -86,6 +86,7 @@ struct StepArgs {
   int32_t n_atoms;        // M (real atoms; the correlation pads to its tile)
   int32_t nfam;
   const double* tab;      // FP64 1D tables [nfam][N][N]
+  const float* tabT32;    // the same rounded to FP32 and transposed, [nfam][pixel][row]
   float* r32;             // residual [node][N*N] FP32, row-major pixels
   uint16_t* r16;          // BF16 shadow of r32 (null in the FP32 form)
   const int32_t* act;     // active list (node slots within the pass)
@@ -130,6 +131,7 @@ struct aqmp_dict {
     int n = 0, k = 0, m = 0, m_pad = 0;
     std::vector<double> h_tab;     // [nfam][n][n]
     double* d_tab = nullptr;
+    float* d_tabT32 = nullptr;     // [nfam][y][p] = fl32(T_f[p][y])
     float* d_f32 = nullptr;        // [m_pad][k]
     uint16_t* d_bf16 = nullptr;    // [m_pad][k]
   } lv[aqmp::kLevels];

@@ -52,43 +52,73 @@ struct TileWalk {
   __device__ int tile(int j) const { return xcd * chunk + j; }
 };
 
-__device__ inline void insert_key(uint32_t* top, uint32_t v, int R) {
-  for (int j = 0; j < R; ++j) {
-    const uint32_t hi = top[j] > v ? top[j] : v;
-    v = top[j] > v ? v : top[j];
-    top[j] = hi;
-  }
+// Compare-exchange keeping the larger key first.
+__device__ inline void cx(uint32_t& a, uint32_t& b) {
+  const uint32_t hi = a > b ? a : b;
+  b = a > b ? b : a;
+  a = hi;
 }
 
-// Shared epilogue: accumulators -> per (node, atom tile) top-R keys.
+// Batcher's odd-even merge sort of eight keys, descending (19 exchanges).
+__device__ inline void sort8_desc(uint32_t (&v)[8]) {
+  cx(v[0], v[1]); cx(v[2], v[3]); cx(v[4], v[5]); cx(v[6], v[7]);
+  cx(v[0], v[2]); cx(v[1], v[3]); cx(v[4], v[6]); cx(v[5], v[7]);
+  cx(v[1], v[2]); cx(v[5], v[6]);
+  cx(v[0], v[4]); cx(v[1], v[5]); cx(v[2], v[6]); cx(v[3], v[7]);
+  cx(v[2], v[4]); cx(v[3], v[5]);
+  cx(v[1], v[2]); cx(v[3], v[4]); cx(v[5], v[6]);
+}
+
+// a, b sorted descending -> a = the eight largest of both, descending: the
+// pairwise maximum of a and reversed b is bitonic and holds the top eight;
+// a bitonic merger (distances 4, 2, 1) sorts it.
+__device__ inline void merge8_desc(uint32_t (&a)[8], const uint32_t (&b)[8]) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) a[i] = a[i] > b[7 - i] ? a[i] : b[7 - i];
+  cx(a[0], a[4]); cx(a[1], a[5]); cx(a[2], a[6]); cx(a[3], a[7]);
+  cx(a[0], a[2]); cx(a[1], a[3]); cx(a[4], a[6]); cx(a[5], a[7]);
+  cx(a[0], a[1]); cx(a[2], a[3]); cx(a[4], a[5]); cx(a[6], a[7]);
+}
+
+// Shared epilogue: accumulators -> per (node, atom tile) top-R keys.  Branch
+// free: every lane sorts its keys of a node column in groups of eight and
+// merges the groups, then the two half-waves and the WA waves are merged.
+// Keys are unique (they carry the atom), so the result is the exact top R.
 template <class C>
 __device__ inline void epilogue(f32x16 (&acc)[C::MA][C::MB], uint32_t* sK, int a0, int a_tile,
                                 int n_atom_tiles, int b0, int count, unsigned long long* keys) {
   constexpr int R = kTopR;
+  static_assert(R == 8, "the sorting networks handle eight keys");
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wa = w % C::WA, wb = w / C::WA;
+  // 255 - local atom of accumulator (ma, r) = lb - (32 ma + 8 (r >> 2) + (r & 3))
+  const uint32_t lb = 255u - (uint32_t)(wa * C::WTA + 4 * (lane >> 5));
 #pragma unroll
   for (int mb = 0; mb < C::MB; ++mb) {
     uint32_t top[R];
 #pragma unroll
-    for (int j = 0; j < R; ++j) top[j] = 0u;
+    for (int g = 0; g < 2 * C::MA; ++g) {
+      const int ma = g >> 1;
+      uint32_t v[8];
 #pragma unroll
-    for (int ma = 0; ma < C::MA; ++ma) {
+      for (int e = 0; e < 8; ++e) {
+        const int r = 8 * (g & 1) + e;
+        const uint32_t bits = __float_as_uint(acc[ma][mb][r]);
+        v[e] = (bits & 0x7FFFFF00u) | (lb - (uint32_t)(32 * ma + 8 * (r >> 2) + (r & 3)));
+      }
+      sort8_desc(v);
+      if (g == 0) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int loc = wa * C::WTA + ma * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const uint32_t bits = __float_as_uint(fabsf(acc[ma][mb][r]));
-        const uint32_t key = (bits & 0xFFFFFF00u) | (uint32_t)(255 - loc);
-        if (key > top[R - 1]) insert_key(top, key, R);
+        for (int j = 0; j < R; ++j) top[j] = v[j];
+      } else {
+        merge8_desc(top, v);
       }
     }
     // merge with the other half-wave (same node, other atom rows)
     uint32_t other[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) other[j] = __shfl_xor(top[j], 32, 64);
-#pragma unroll
-    for (int j = 0; j < R; ++j)
-      if (other[j] > top[R - 1]) insert_key(top, other[j], R);
+    merge8_desc(top, other);
     if (lane < 32) {
       const int nl = wb * C::WTB + mb * 32 + lane;
 #pragma unroll
@@ -102,12 +132,13 @@ __device__ inline void epilogue(f32x16 (&acc)[C::MA][C::MB], uint32_t* sK, int a
     uint32_t top[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) top[j] = sK[nl * R + j];
-    for (int q = 1; q < C::WA; ++q)
 #pragma unroll
-      for (int j = 0; j < R; ++j) {
-        const uint32_t v = sK[(q * C::BB + nl) * R + j];
-        if (v > top[R - 1]) insert_key(top, v, R);
-      }
+    for (int q = 1; q < C::WA; ++q) {
+      uint32_t v[R];
+#pragma unroll
+      for (int j = 0; j < R; ++j) v[j] = sK[(q * C::BB + nl) * R + j];
+      merge8_desc(top, v);
+    }
     unsigned long long* out = keys + ((size_t)pos * n_atom_tiles + a_tile) * R;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
@@ -305,26 +336,43 @@ struct DmaGeo {
 // vmcnt(n) with the other counters left alone (gfx9 encoding).
 #define AQMP_WAIT_VM(n) __builtin_amdgcn_s_waitcnt(((n) & 0xF) | (0x7 << 4) | (0xF << 8) | ((((n) >> 4) & 0x3) << 14))
 
+// DMA addressing: buffer loads with an SGPR resource per operand, a 32-bit
+// per-lane byte offset (one VGPR each) and a wave-uniform SGPR offset for the
+// row block and the k stage.  Out-of-range offsets read zeros, never fault.
+constexpr int kBufWord3 = 0x00020000;   // raw buffer, 32-bit data format (gfx9)
+
 template <class G>
 struct DmaPtrs {
-  const char* a_lane[2];     // A: this lane's address in even / odd blocks (stage 0)
-  const char* b_lane[G::B_INS];
+  const void* a_base;              // dictionary, all atoms
+  const void* b_base;              // residual buffer
+  int32_t a_bytes;                 // dictionary extent in bytes
+  uint32_t a_sofs;                 // byte offset of this wave's first A row block (uniform)
+  uint32_t a_off[2];               // lane offset in even / odd blocks
+  uint32_t b_off[G::B_INS];        // lane offset of its node row per block
 };
+
+// One 16-byte-per-lane buffer load into LDS (lane l lands at lds + 16 l).
+// Kept out of the templates: the host pass of the HIP compiler mishandles the
+// buffer-resource builtins inside function template specializations that are
+// reached from more than one call site.
+__device__ inline void lds_dma16(const void* base, int bytes, char* lds, int voff, int soff) {
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, kBufWord3);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t*)lds, 16, voff, soff, 0, 0);
+}
 
 template <class G, int K>
 __device__ inline void dma_issue(const DmaPtrs<G>& p, char* sa, char* sb, int s) {
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const size_t kofs = (size_t)s * G::BK * 2;
+  const int kofs = s * G::BK * 2;
 #pragma unroll
   for (int i = 0; i < G::A_INS; ++i) {
     const int blk = w * G::A_INS + i;
-    const char* g = p.a_lane[i & 1] + (size_t)i * G::RPB * K * 2 + kofs;
-    __builtin_amdgcn_global_load_lds((gbl_void_t*)g, (lds_void_t*)(sa + blk * 1024), 16, 0, 0);
+    lds_dma16(p.a_base, p.a_bytes, sa + blk * 1024, (int)p.a_off[i & 1], (int)p.a_sofs + i * G::RPB * K * 2 + kofs);
   }
 #pragma unroll
   for (int i = 0; i < G::B_INS; ++i) {
     const int blk = w * G::B_INS + i;
-    __builtin_amdgcn_global_load_lds((gbl_void_t*)(p.b_lane[i] + kofs), (lds_void_t*)(sb + blk * 1024), 16, 0, 0);
+    lds_dma16(p.b_base, (int)0xFFFFFFFFu, sb + blk * 1024, (int)p.b_off[i], kofs);
   }
 }
 
@@ -393,17 +441,22 @@ __global__ __launch_bounds__(256, MINB) void k_corr_bf16_dma(const uint16_t* __r
     const int a_tile = tile / ntB, b_tile = tile % ntB;
     const int a0 = a_tile * G::BA, b0 = b_tile * G::BB;
     DmaPtrs<G> p;
+    const int wu = __builtin_amdgcn_readfirstlane(w);
+    p.a_base = D;
+    p.b_base = X;
+    p.a_bytes = n_atom_tiles * G::BA * K * 2;
+    p.a_sofs = (uint32_t)((a0 + wu * G::A_INS * G::RPB) * K * 2);
 #pragma unroll
     for (int par = 0; par < 2; ++par) {
       const int gc = dslot ^ G::swz(par * G::RPB + drow);
-      p.a_lane[par] = (const char*)(D + (size_t)(a0 + w * G::A_INS * G::RPB + drow) * K + gc * 8);
+      p.a_off[par] = (uint32_t)((drow * K + gc * 8) * 2);
     }
 #pragma unroll
     for (int i = 0; i < G::B_INS; ++i) {
       const int row = (w * G::B_INS + i) * G::RPB + drow;
       const int gc = dslot ^ G::swz(row);
       const int pos = min(b0 + row, count - 1);
-      p.b_lane[i] = (const char*)(X + (size_t)act[pos] * K + gc * 8);
+      p.b_off[i] = (uint32_t)(((size_t)act[pos] * K + gc * 8) * 2);
     }
     f32x16 acc[G::MA][G::MB];
 #pragma unroll
@@ -453,6 +506,478 @@ __global__ __launch_bounds__(256, MINB) void k_corr_bf16_dma(const uint16_t* __r
     static_assert(NST - S0 <= 4, "tail covers the remaining stages");
 #undef AQMP_DMA_TAIL
     __syncthreads();   // all waves done reading the ring before sK reuses sA0
+    epilogue<typename G::C>(acc, sK, a0, a_tile, n_atom_tiles, b0, count, keys);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BF16, large blocks, software-pipelined form of the direct-to-LDS kernel.
+//
+// Same tile (256 x 128), BK = 64 (every lane request covers a whole 128-byte
+// line of a row slice) and three-stage ring, one workgroup per CU, but the
+// wave never stalls in long runs of memory instructions: the 12 loads of
+// stage s + 2 are spread over the MFMAs of the first three k-steps of stage
+// s (one after every second MFMA), and the wait + barrier that publishes
+// stage s + 1 sits inside the last k-step of stage s, so the first fragments
+// of stage s + 1 are read while the last MFMAs of stage s run.  Fragments are
+// double-buffered in registers across k-steps and across stages.  The MFMA
+// sequence (and so every accumulator bit) is the one of the other forms.
+// ---------------------------------------------------------------------------
+template <class G>
+struct PipeFrag {
+  bf16x8 a[2][G::MA];
+  bf16x8 b[2][G::MB];
+};
+
+// One DMA instruction (compile-time index I of the wave's 12) of stage s.
+template <class G, int K, int I>
+__device__ inline void dma_one(const DmaPtrs<G>& p, char* sa, char* sb, int s) {
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int kofs = s * G::BK * 2;
+  if constexpr (I < G::A_INS) {
+    lds_dma16(p.a_base, p.a_bytes, sa + (w * G::A_INS + I) * 1024, (int)p.a_off[I & 1],
+              (int)p.a_sofs + I * G::RPB * K * 2 + kofs);
+  } else {
+    constexpr int J = I - G::A_INS;
+    lds_dma16(p.b_base, (int)0xFFFFFFFFu, sb + (w * G::B_INS + J) * 1024, (int)p.b_off[J], kofs);
+  }
+}
+
+template <class G, int KK>
+__device__ inline void pipe_read(PipeFrag<G>& f, const char* sa, const char* sb, const int (&off)[G::BK / 16]) {
+  const int w = threadIdx.x >> 6;
+  const int wa = w % G::WA, wb = w / G::WA;
+  const char* pa = sa + wa * G::WTA * G::ROWB;
+  const char* pb = sb + wb * G::WTB * G::ROWB;
+  constexpr int P = KK & 1;
+#pragma unroll
+  for (int ma = 0; ma < G::MA; ++ma) f.a[P][ma] = *(const bf16x8*)(pa + ma * 32 * G::ROWB + off[KK]);
+#pragma unroll
+  for (int mb = 0; mb < G::MB; ++mb) f.b[P][mb] = *(const bf16x8*)(pb + mb * 32 * G::ROWB + off[KK]);
+  __builtin_amdgcn_sched_barrier(0);   // reads go out before the MFMAs that follow
+}
+
+// MFMAs of k-step KK; with DMA, loads KK*4 .. KK*4+3 of stage s_dma go out
+// after MFMAs 1, 3, 5 and 7.
+template <class G, int K, int KK, bool DMA>
+__device__ inline void pipe_mfma(f32x16 (&acc)[G::MA][G::MB], const PipeFrag<G>& f, const DmaPtrs<G>& p, char* da,
+                                 char* db, int s_dma) {
+  constexpr int P = KK & 1;
+  static_assert(G::MA * G::MB == 8 && G::INS == 12, "pipeline pattern: 8 MFMAs and 4 loads per k-step");
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int ma = i / G::MB, mb = i % G::MB;
+    acc[ma][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[P][ma], f.b[P][mb], acc[ma][mb], 0, 0, 0);
+    if constexpr (DMA && KK < 3) {
+      if ((i & 1) == 1) {
+        switch (KK * 4 + i / 2) {
+          case 0: dma_one<G, K, 0>(p, da, db, s_dma); break;
+          case 1: dma_one<G, K, 1>(p, da, db, s_dma); break;
+          case 2: dma_one<G, K, 2>(p, da, db, s_dma); break;
+          case 3: dma_one<G, K, 3>(p, da, db, s_dma); break;
+          case 4: dma_one<G, K, 4>(p, da, db, s_dma); break;
+          case 5: dma_one<G, K, 5>(p, da, db, s_dma); break;
+          case 6: dma_one<G, K, 6>(p, da, db, s_dma); break;
+          case 7: dma_one<G, K, 7>(p, da, db, s_dma); break;
+          case 8: dma_one<G, K, 8>(p, da, db, s_dma); break;
+          case 9: dma_one<G, K, 9>(p, da, db, s_dma); break;
+          case 10: dma_one<G, K, 10>(p, da, db, s_dma); break;
+          default: dma_one<G, K, 11>(p, da, db, s_dma); break;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+}
+
+// lgkmcnt(0) and vmcnt(n) together (gfx9 encoding, expcnt left alone).
+#define AQMP_WAIT_VM_LGKM0(n) __builtin_amdgcn_s_waitcnt(((n) & 0xF) | (0x7 << 4) | ((((n) >> 4) & 0x3) << 14))
+
+// Stage s computed from (ca, cb); DMA: loads of stage s + 2 into (da, db);
+// NEXT: stage s + 1 (in (na, nb)) follows and its first fragments are read
+// here.  Loads complete in order, so after this wave's loads of stage s + 2
+// are out, vmcnt(12) (vmcnt(0) without them) means stage s + 1 has landed.
+template <class G, int K, bool DMA, bool NEXT>
+__device__ inline void pipe_stage(f32x16 (&acc)[G::MA][G::MB], PipeFrag<G>& f, const DmaPtrs<G>& p,
+                                  const char* ca, const char* cb, const char* na, const char* nb, char* da, char* db,
+                                  int s, const int (&off)[G::BK / 16]) {
+  pipe_read<G, 1>(f, ca, cb, off);
+  pipe_mfma<G, K, 0, DMA>(acc, f, p, da, db, s + 2);
+  pipe_read<G, 2>(f, ca, cb, off);
+  pipe_mfma<G, K, 1, DMA>(acc, f, p, da, db, s + 2);
+  pipe_read<G, 3>(f, ca, cb, off);
+  pipe_mfma<G, K, 2, DMA>(acc, f, p, da, db, s + 2);
+  if constexpr (NEXT) {
+    // every wave is done with this stage's fragment reads before any wave
+    // passes, so the loads issued after the barrier may overwrite (ca, cb)
+    if constexpr (DMA) AQMP_WAIT_VM_LGKM0(G::INS);
+    else AQMP_WAIT_VM_LGKM0(0);
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    pipe_read<G, 0>(f, na, nb, off);
+  }
+  pipe_mfma<G, K, 3, DMA>(acc, f, p, da, db, s + 2);
+}
+
+template <int N, int BK>
+__global__ __launch_bounds__(256, 1) void k_corr_bf16_pipe(const uint16_t* __restrict__ D,
+                                                           const uint16_t* __restrict__ X,
+                                                           const int32_t* __restrict__ act,
+                                                           const int32_t* __restrict__ act_count,
+                                                           unsigned long long* __restrict__ keys, int n_atom_tiles) {
+  using G = DmaGeo<BK>;
+  constexpr int K = N * N;
+  constexpr int NST = K / G::BK;
+  static_assert(K % G::BK == 0 && NST >= 2, "stages");
+  __shared__ __attribute__((aligned(1024))) char sA0[G::A_BYTES];
+  __shared__ __attribute__((aligned(1024))) char sA1[G::A_BYTES];
+  __shared__ __attribute__((aligned(1024))) char sA2[G::A_BYTES];
+  __shared__ __attribute__((aligned(1024))) char sB0[G::B_BYTES];
+  __shared__ __attribute__((aligned(1024))) char sB1[G::B_BYTES];
+  __shared__ __attribute__((aligned(1024))) char sB2[G::B_BYTES];
+  static_assert(G::WA * G::BB * kTopR * 4 <= G::A_BYTES, "epilogue scratch fits one A buffer");
+  uint32_t* sK = (uint32_t*)sA0;
+
+  const int count = *act_count;
+  const int ntB = (count + G::BB - 1) / G::BB;
+  const int ntiles = n_atom_tiles * ntB;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int fr = G::swz(lane & 31);
+  int off[G::BK / 16];
+#pragma unroll
+  for (int kk = 0; kk < G::BK / 16; ++kk) off[kk] = (lane & 31) * G::ROWB + (((2 * kk + (lane >> 5)) ^ fr) << 4);
+  const int drow = lane / G::CPR, dslot = lane % G::CPR;
+  TileWalk walk(ntiles);
+  for (int j = walk.slot; j < walk.chunk; j += walk.per) {
+    const int tile = walk.tile(j);
+    if (tile >= ntiles) break;
+    const int a_tile = tile / ntB, b_tile = tile % ntB;
+    const int a0 = a_tile * G::BA, b0 = b_tile * G::BB;
+    DmaPtrs<G> p;
+    const int wu = __builtin_amdgcn_readfirstlane(w);
+    p.a_base = D;
+    p.b_base = X;
+    p.a_bytes = n_atom_tiles * G::BA * K * 2;
+    p.a_sofs = (uint32_t)((a0 + wu * G::A_INS * G::RPB) * K * 2);
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+      const int gc = dslot ^ G::swz(par * G::RPB + drow);
+      p.a_off[par] = (uint32_t)((drow * K + gc * 8) * 2);
+    }
+#pragma unroll
+    for (int i = 0; i < G::B_INS; ++i) {
+      const int row = (w * G::B_INS + i) * G::RPB + drow;
+      const int gc = dslot ^ G::swz(row);
+      const int pos = min(b0 + row, count - 1);
+      p.b_off[i] = (uint32_t)(((size_t)act[pos] * K + gc * 8) * 2);
+    }
+    f32x16 acc[G::MA][G::MB];
+#pragma unroll
+    for (int ma = 0; ma < G::MA; ++ma)
+#pragma unroll
+      for (int mb = 0; mb < G::MB; ++mb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[ma][mb][r] = 0.f;
+    PipeFrag<G> f;
+
+    __syncthreads();   // previous tile's epilogue is done with sK (= sA0)
+    dma_issue<G, K>(p, sA0, sB0, 0);
+    dma_issue<G, K>(p, sA1, sB1, 1);
+    AQMP_WAIT_VM(G::INS);
+    __builtin_amdgcn_s_barrier();
+    pipe_read<G, 0>(f, sA0, sB0, off);
+    // Steady state: stages that load stage s + 2 and hand over to s + 1.
+    constexpr int FULL = NST - 2;
+    constexpr int TRIPS = FULL / 3;
+    for (int t = 0; t < TRIPS; ++t) {
+      const int s = 3 * t;
+      pipe_stage<G, K, true, true>(acc, f, p, sA0, sB0, sA1, sB1, sA2, sB2, s, off);
+      pipe_stage<G, K, true, true>(acc, f, p, sA1, sB1, sA2, sB2, sA0, sB0, s + 1, off);
+      pipe_stage<G, K, true, true>(acc, f, p, sA2, sB2, sA0, sB0, sA1, sB1, s + 2, off);
+    }
+    constexpr int S0 = 3 * TRIPS;
+    static_assert(NST - S0 >= 2 && NST - S0 <= 4, "tail covers the remaining stages");
+#define AQMP_PIPE_TAIL(I, CA, CB, NA, NB, DA, DB)                                                     \
+    if constexpr (S0 + (I) < NST)                                                                     \
+      pipe_stage<G, K, (S0 + (I) + 2 < NST), (S0 + (I) + 1 < NST)>(acc, f, p, CA, CB, NA, NB, DA, DB, \
+                                                                    S0 + (I), off);
+    AQMP_PIPE_TAIL(0, sA0, sB0, sA1, sB1, sA2, sB2)
+    AQMP_PIPE_TAIL(1, sA1, sB1, sA2, sB2, sA0, sB0)
+    AQMP_PIPE_TAIL(2, sA2, sB2, sA0, sB0, sA1, sB1)
+    AQMP_PIPE_TAIL(3, sA0, sB0, sA1, sB1, sA2, sB2)
+#undef AQMP_PIPE_TAIL
+    __syncthreads();   // all waves done reading the ring before sK reuses sA0
+    epilogue<typename G::C>(acc, sK, a0, a_tile, n_atom_tiles, b0, count, keys);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BF16, N = 64: atoms generated in registers (no dictionary traffic).
+//
+// Atom (f, p, q) is the outer product of rows p and q of the 1D table T_f, so
+// its BF16 value at pixel (y, x) is RNE(fl32(T32_f[p][y] * T32_f[q][x])), the
+// canonical BF16 dictionary (T32 = the FP64 table rounded to FP32).  A lane's
+// MFMA rows keep the same (p, q) over the whole K loop: it holds the T32_f[q]
+// values it needs for its two q rows in registers and reads T32_f[p][y] from
+// LDS once per stage (one stage = one pixel row y), then builds each 8-value A
+// fragment with 8 multiplies and 4 packed conversions while the MFMAs of the
+// previous k-step run.  Only the residual tile goes through LDS (direct-to-LDS
+// loads, three-stage ring as in the pipelined kernel), so a CU fetches 16 KB
+// per stage instead of 48 KB.  The DC atoms come out as exactly 1/N because
+// T32_f[0][.] = 1/8 exactly at N = 64.  Same tile, k order and epilogue as the
+// other forms: the keys are bit-identical.
+// ---------------------------------------------------------------------------
+constexpr int kGenN = 64;
+
+// Geometry: tile 256 atoms x 128 nodes, BK = 64 (one pixel row), the four
+// waves side by side along the atoms (64 atoms x 128 nodes each), so a wave
+// makes only the A fragments of its own rows: 2 per k-step, 3 VALU per MFMA.
+struct GenGeo {
+  static constexpr int BA = 256, BB = 128, BK = 64, WA = 4, WB = 1;
+  static constexpr int WTA = BA / WA, WTB = BB / WB, MA = WTA / 32, MB = WTB / 32;
+  static constexpr int ROWB = BK * 2, CPR = ROWB / 16, RPB = 1024 / ROWB;
+  static constexpr int B_BYTES = BB * ROWB;
+  static constexpr int B_INS = BB / RPB / 4;
+  using C = Cfg<BA, BB, BK, WA, WB>;
+  __device__ static int swz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
+};
+
+struct GenFrag {
+  bf16x8 a[2][GenGeo::MA];
+  bf16x8 b[2][GenGeo::MB];
+};
+
+// B fragments of k-step KK into parity slot P.
+template <int KK, int P>
+__device__ inline void gen_read_b(GenFrag& f, const char* sb, const int (&off)[4]) {
+#pragma unroll
+  for (int mb = 0; mb < GenGeo::MB; ++mb) f.b[P][mb] = *(const bf16x8*)(sb + mb * 32 * GenGeo::ROWB + off[KK]);
+  __builtin_amdgcn_sched_barrier(0);   // the reads go out a whole k-step before their MFMAs
+}
+
+// A fragments of k-step KK (x = 16 KK + 8 h + j) for the row factors tp.
+template <int KK, int P>
+__device__ inline void gen_make_a(GenFrag& f, const float (&tp)[GenGeo::MA], const float (&tq)[32]) {
+#pragma unroll
+  for (int ma = 0; ma < GenGeo::MA; ++ma) {
+    bf16x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (__bf16)(tp[ma] * tq[KK * 8 + j]);
+    f.a[P][ma] = v;
+  }
+}
+
+template <int KK>
+__device__ inline void gen_mfma(f32x16 (&acc)[GenGeo::MA][GenGeo::MB], const GenFrag& f) {
+  constexpr int P = KK & 1;
+#pragma unroll
+  for (int mb = 0; mb < GenGeo::MB; ++mb)
+#pragma unroll
+    for (int ma = 0; ma < GenGeo::MA; ++ma)
+      acc[ma][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[P][ma], f.b[P][mb], acc[ma][mb], 0, 0, 0);
+}
+
+// Residual rows of stage s: loads [first, first + cnt) of the wave's B_INS.
+template <int K>
+__device__ inline void gen_dma(const DmaPtrs<GenGeo>& p, char* sb, int s, int first, int cnt) {
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int kofs = s * GenGeo::BK * 2;
+#pragma unroll
+  for (int i = 0; i < GenGeo::B_INS; ++i)
+    if (i >= first && i < first + cnt)
+      lds_dma16(p.b_base, (int)0xFFFFFFFFu, sb + (w * GenGeo::B_INS + i) * 1024, (int)p.b_off[i], kofs);
+}
+
+// One stage (pixel row y = s) computed from cb.  DMA: the loads of stage
+// s_dma go to db, spread over the first two k-steps.  NEXT: stage s + 1
+// follows in nb; its loads are complete once at most VMN of this wave's loads
+// are outstanding (loads complete in order), and its first fragments are made
+// here, under the last MFMAs of stage s.
+template <int K, bool DMA, bool NEXT, int VMN>
+__device__ inline void gen_stage(f32x16 (&acc)[GenGeo::MA][GenGeo::MB], GenFrag& f, const DmaPtrs<GenGeo>& p,
+                                 const float* sTf, const float (&tq)[32], float (&tp)[GenGeo::MA], const char* cb,
+                                 const char* nb, char* db, int s, int s_dma, const int (&off)[4]) {
+  const int rr = threadIdx.x & 31;
+  gen_read_b<1, 1>(f, cb, off);
+  gen_make_a<1, 1>(f, tp, tq);
+  if constexpr (DMA) gen_dma<K>(p, db, s_dma, 0, 2);
+  gen_mfma<0>(acc, f);
+  gen_read_b<2, 0>(f, cb, off);
+  gen_make_a<2, 0>(f, tp, tq);
+  if constexpr (DMA) gen_dma<K>(p, db, s_dma, 2, 2);
+  gen_mfma<1>(acc, f);
+  gen_read_b<3, 1>(f, cb, off);
+  gen_make_a<3, 1>(f, tp, tq);
+  float tpn[GenGeo::MA];
+  if constexpr (NEXT) {
+#pragma unroll
+    for (int ma = 0; ma < GenGeo::MA; ++ma) tpn[ma] = sTf[(s + 1) * kGenN + 32 * ma + rr];
+  }
+  gen_mfma<2>(acc, f);
+  if constexpr (NEXT) {
+    // every wave is done reading cb before any wave passes, so loads issued
+    // after this barrier may overwrite it
+    AQMP_WAIT_VM_LGKM0(VMN);
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int ma = 0; ma < GenGeo::MA; ++ma) tp[ma] = tpn[ma];
+    gen_read_b<0, 0>(f, nb, off);
+    gen_make_a<0, 0>(f, tp, tq);
+  }
+  gen_mfma<3>(acc, f);
+}
+
+// Ring of NB residual buffers: stage s is computed from buffer s % NB while
+// stages s + 1 .. s + NB - 1 are in flight (prefetch distance NB - 1).
+constexpr int kGenRing = 6;
+
+// The ring buffers are separate LDS arrays: the compiler then knows that a
+// load into one buffer cannot feed a read of another, and does not wait for
+// the loads in flight before every fragment read.
+struct GenArgs {
+  const DmaPtrs<GenGeo>* p;
+  const float* sTf;
+  char* r0;
+  char* r1;
+  char* r2;
+  char* r3;
+  char* r4;
+  char* r5;
+  template <int I>
+  __device__ char* buf() const {
+    static_assert(kGenRing == 6, "six ring buffers");
+    if constexpr (I == 0) return r0;
+    else if constexpr (I == 1) return r1;
+    else if constexpr (I == 2) return r2;
+    else if constexpr (I == 3) return r3;
+    else if constexpr (I == 4) return r4;
+    else return r5;
+  }
+};
+
+// Stages S .. NST - 1 with every decision at compile time.
+template <int K, int NST, int S>
+__device__ inline void gen_tail(f32x16 (&acc)[GenGeo::MA][GenGeo::MB], GenFrag& f, const GenArgs& g,
+                                const float (&tq)[32], float (&tp)[GenGeo::MA], const int (&off)[4]) {
+  if constexpr (S < NST) {
+    constexpr int NB = kGenRing;
+    constexpr bool DMA = S + NB - 1 < NST;
+    constexpr bool NEXT = S + 1 < NST;
+    constexpr int AHEAD = (NST - 2 - S) < (NB - 2) ? (NST - 2 - S) : (NB - 2);
+    constexpr int VMN = NEXT ? GenGeo::B_INS * (AHEAD > 0 ? AHEAD : 0) : 0;
+    gen_stage<K, DMA, NEXT, VMN>(acc, f, *g.p, g.sTf, tq, tp, g.template buf<S % NB>(),
+                                 g.template buf<(S + 1) % NB>(), g.template buf<(S + NB - 1) % NB>(), S,
+                                 S + NB - 1, off);
+    gen_tail<K, NST, S + 1>(acc, f, g, tq, tp, off);
+  }
+}
+
+// NB consecutive steady-state stages s0 + I (s0 a multiple of NB): buffers
+// are compile-time, stage indices run-time.
+template <int K, int I>
+__device__ inline void gen_trip(f32x16 (&acc)[GenGeo::MA][GenGeo::MB], GenFrag& f, const GenArgs& g,
+                                const float (&tq)[32], float (&tp)[GenGeo::MA], const int (&off)[4], int s0) {
+  if constexpr (I < kGenRing) {
+    constexpr int NB = kGenRing;
+    gen_stage<K, true, true, GenGeo::B_INS * (NB - 2)>(acc, f, *g.p, g.sTf, tq, tp, g.template buf<I>(),
+                                                        g.template buf<(I + 1) % NB>(),
+                                                        g.template buf<(I + NB - 1) % NB>(), s0 + I,
+                                                        s0 + I + NB - 1, off);
+    gen_trip<K, I + 1>(acc, f, g, tq, tp, off, s0);
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(256, 1) void k_corr_bf16_gen(const float* __restrict__ tabT32, int nfam,
+                                                          const uint16_t* __restrict__ X,
+                                                          const int32_t* __restrict__ act,
+                                                          const int32_t* __restrict__ act_count,
+                                                          unsigned long long* __restrict__ keys, int n_atom_tiles) {
+  static_assert(N == kGenN, "generated atoms: one stage is one pixel row of 64");
+  using G = GenGeo;
+  constexpr int K = N * N;
+  constexpr int NST = K / G::BK;
+  constexpr int NB = kGenRing;
+  static_assert(NST >= NB, "ring shorter than the K loop");
+  __shared__ __attribute__((aligned(1024))) char sR0[G::B_BYTES];
+  __shared__ __attribute__((aligned(1024))) char sR1[G::B_BYTES];
+  __shared__ __attribute__((aligned(1024))) char sR2[G::B_BYTES];
+  __shared__ __attribute__((aligned(1024))) char sR3[G::B_BYTES];
+  __shared__ __attribute__((aligned(1024))) char sR4[G::B_BYTES];
+  __shared__ __attribute__((aligned(1024))) char sR5[G::B_BYTES];
+  __shared__ float sT[2 * K];   // [f][y][p] = fl32(T_f[p][y])
+  static_assert(G::WA * G::BB * kTopR * 4 <= G::B_BYTES, "epilogue scratch fits one B buffer");
+  uint32_t* sK = (uint32_t*)sR0;
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int i = tid; i < nfam * K / 4; i += 256) ((float4*)sT)[i] = ((const float4*)tabT32)[i];
+  __syncthreads();
+
+  const int count = *act_count;
+  const int ntB = (count + G::BB - 1) / G::BB;
+  const int ntiles = n_atom_tiles * ntB;
+  const int wa = w, rr = lane & 31, hh = lane >> 5;
+  const int fr = G::swz(rr);
+  int off[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) off[kk] = rr * G::ROWB + (((2 * kk + hh) ^ fr) << 4);
+  const int drow = lane / G::CPR, dslot = lane % G::CPR;
+  TileWalk walk(ntiles);
+  for (int j = walk.slot; j < walk.chunk; j += walk.per) {
+    const int tile = walk.tile(j);
+    if (tile >= ntiles) break;
+    // node-major order: the workgroups of one XCD share a residual tile in
+    // its L2 (the atoms cost no memory traffic here)
+    const int a_tile = tile % n_atom_tiles, b_tile = tile / n_atom_tiles;
+    const int a0 = a_tile * G::BA, b0 = b_tile * G::BB;
+    DmaPtrs<G> p;
+    p.b_base = X;
+#pragma unroll
+    for (int i = 0; i < G::B_INS; ++i) {
+      const int row = (w * G::B_INS + i) * G::RPB + drow;
+      const int gc = dslot ^ G::swz(row);
+      const int pos = min(b0 + row, count - 1);
+      p.b_off[i] = (uint32_t)(((size_t)act[pos] * K + gc * 8) * 2);
+    }
+    // Rows of this lane: atom a0 + 64 wa + 32 ma + rr, i.e. family fam,
+    // q = qb + wa, p = 32 ma + rr.
+    const int fam = min(a0 / K, nfam - 1);
+    const int qb = (a0 % K) / N;
+    const float* sTf = sT + fam * K;
+    float tq[32];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) tq[kk * 8 + e] = sTf[(kk * 16 + 8 * hh + e) * N + qb + wa];
+    float tp[G::MA];
+#pragma unroll
+    for (int ma = 0; ma < G::MA; ++ma) tp[ma] = sTf[32 * ma + rr];
+    f32x16 acc[G::MA][G::MB];
+#pragma unroll
+    for (int ma = 0; ma < G::MA; ++ma)
+#pragma unroll
+      for (int mb = 0; mb < G::MB; ++mb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[ma][mb][r] = 0.f;
+    GenFrag f;
+
+    __syncthreads();   // previous tile's epilogue is done with sK (= buffer 0)
+    const GenArgs g{&p, sTf, sR0, sR1, sR2, sR3, sR4, sR5};
+    gen_dma<K>(p, g.buf<0>(), 0, 0, G::B_INS);
+    gen_dma<K>(p, g.buf<1>(), 1, 0, G::B_INS);
+    gen_dma<K>(p, g.buf<2>(), 2, 0, G::B_INS);
+    gen_dma<K>(p, g.buf<3>(), 3, 0, G::B_INS);
+    gen_dma<K>(p, g.buf<4>(), 4, 0, G::B_INS);
+    AQMP_WAIT_VM(G::B_INS * (NB - 2));
+    __builtin_amdgcn_s_barrier();
+    gen_read_b<0, 0>(f, g.buf<0>(), off);
+    gen_make_a<0, 0>(f, tp, tq);
+    constexpr int FULL = NST - (NB - 1);      // stages that issue a load
+    constexpr int TRIPS = FULL / NB;
+    for (int t = 0; t < TRIPS; ++t) gen_trip<K, 0>(acc, f, g, tq, tp, off, t * NB);
+    gen_tail<K, NST, TRIPS * NB>(acc, f, g, tq, tp, off);
+    __syncthreads();   // all waves done reading the ring before sK reuses buffer 0
     epilogue<typename G::C>(acc, sK, a0, a_tile, n_atom_tiles, b0, count, keys);
   }
 }
@@ -576,7 +1101,10 @@ using CfgMidF = Cfg<128, 128, 32, 2, 2>;    // N = 8, FP32
 using CfgSmallF = Cfg<32, 256, 16, 1, 4>;   // N = 4, FP32
 
 constexpr int kCorrGrid = 256;   // one persistent workgroup per CU
-constexpr int kDefaultVariant = 2;
+// Default BF16 kernel per block size (measured): generated atoms at N = 64,
+// the pipelined direct-to-LDS form at N = 32, two workgroups per CU at N = 16
+// where K (four stages) is too short for one workgroup's pipeline fill.
+constexpr int default_variant(int n) { return n >= 64 ? 6 : (n >= 32 ? 5 : 2); }
 
 }  // namespace
 
@@ -595,7 +1123,7 @@ template <int N>
 static void launch_corr_n(int precision, int variant, const void* atoms, const StepArgs& a, int nat, hipStream_t s) {
   using CB = typename std::conditional<(N >= 16), CfgBig, typename std::conditional<(N == 8), CfgMid, CfgSmall>::type>::type;
   using CF = typename std::conditional<(N >= 16), CfgBigF, typename std::conditional<(N == 8), CfgMidF, CfgSmallF>::type>::type;
-  if (variant == 0) variant = kDefaultVariant;
+  if (variant == 0) variant = default_variant(N);
   if constexpr (N <= 32 && N >= 8) {
     if (precision == AQMP_PREC_BF16 && variant == 4) {
       using CN = typename std::conditional<(N == 8), CfgNarrow8, CfgNarrow>::type;
@@ -610,6 +1138,12 @@ static void launch_corr_n(int precision, int variant, const void* atoms, const S
       if (variant == 1)
         hipLaunchKernelGGL((k_corr_bf16_dma<N, 64, 1>), dim3(kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms,
                            a.r16, a.act, a.act_count, a.keys, nat);
+      else if (variant == 6 && N == kGenN)
+        hipLaunchKernelGGL((k_corr_bf16_gen<(N == kGenN ? N : kGenN)>), dim3(kCorrGrid), dim3(256), 0, s,
+                           a.tabT32, a.nfam, a.r16, a.act, a.act_count, a.keys, nat);
+      else if (variant == 5)
+        hipLaunchKernelGGL((k_corr_bf16_pipe<N, 64>), dim3(kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms, a.r16,
+                           a.act, a.act_count, a.keys, nat);
       else if (variant == 2)
         hipLaunchKernelGGL((k_corr_bf16_dma<N, 32, 2>), dim3(2 * kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms,
                            a.r16, a.act, a.act_count, a.keys, nat);

@@ -139,7 +139,7 @@ def test_corr_variants_bit_identical(A, dic):
     w = workload("c1")
     img = w["channels"][0]
     ref = None
-    for v in (1, 2, 3, 4):
+    for v in (1, 2, 3, 4, 5, 6):
         _say("variant", v)
         imgs = [_dev(img)]
         code = A.Code(dic, imgs, w["params"], [(0, 0)], precision=1, schedule=1, corr_variant=v)
