@@ -60,7 +60,7 @@ def psnr_jobs(code, imgs, jobs):
     return out
 
 
-def roofline(stats, timing, precision):
+def roofline(stats, timing, precision, kernel_name=None):
     """Dominant kernel: the correlation of the largest block size.  Algorithmic
     work per node-iteration is 2*K*M = 4 N^4 flops (every atom correlated with
     the residual); one launch processes the nodes active in that MP step."""
@@ -84,7 +84,7 @@ def roofline(stats, timing, precision):
                                       avg_corr_us=round(1e3 * timing["corr_ms"][l] / max(1, timing["steps"][l]), 2))
     return dict(bound="mfma", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
                 frac=round(achieved / peak, 4), traffic=None,
-                kernel=f"k_corr_{'bf16' if precision == 1 else 'f32'}<N={n}>",
+                kernel=kernel_name(n) if kernel_name else f"correlation<N={n}>",
                 avg_launch_us=round(1e3 * ms / max(1, steps), 2), launches=int(steps),
                 flops_per_unit=4 * n ** 4, units=int(stats["iters_level"][lg]), per_level=per_level)
 
@@ -194,7 +194,8 @@ def main():
     code_t = A.Code(dic, imgs, w["params"], w["jobs"], precision=A.PREC_BF16, schedule=sched,
                     timing=True, corr_variant=args.corr_variant)
     sec_t = time_steps(code_t, imgs, args.steps, args.warmup)
-    roof = roofline(code_t.stats(), code_t.timing(), A.PREC_BF16)
+    roof = roofline(code_t.stats(), code_t.timing(), A.PREC_BF16,
+                    lambda n: A.corr_kernel(n, A.PREC_BF16, args.corr_variant))
     code_t.free()
     log(f"bf16 batched (stream, timed): {sec_t * 1e3:.3f} ms/step, corr {roof['achieved']} TFLOP/s")
 
@@ -207,7 +208,7 @@ def main():
         sec3 = time_steps(code3, imgs, args.fp32_steps, 1)
         st3 = code3.stats()
         psnr_f = psnr_jobs(code3, imgs, w["jobs"])
-        roof3 = roofline(st3, code3.timing(), A.PREC_FP32)
+        roof3 = roofline(st3, code3.timing(), A.PREC_FP32, lambda n: A.corr_kernel(n, A.PREC_FP32))
         fp32 = dict(value=round(npx / sec3 / 1e6, 3), ms_per_step=round(sec3 * 1e3, 3), steps=args.fp32_steps,
                     mp_iters_per_s=round(st3["iters_executed"] / sec3, 1), psnr_db=[round(p, 4) for p in psnr_f],
                     corr_tflops=roof3["achieved"], corr_frac_fp32_peak=roof3["frac"],

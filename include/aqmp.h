@@ -245,6 +245,15 @@ int aqmp_decode(const aqmp_dict* d, const aqmp_code* c, int job,
 /* Message for the calling thread's last failure ("" if none). */
 const char* aqmp_last_error(void);
 
+/* Name of the correlation kernel (MP step (b) of Section 2.2, c = D^T r) that
+ * an encode runs for block size n with the given precision (AQMP_PREC_*) and
+ * aqmp_options.corr_variant (0 = library default), e.g. for labelling
+ * profiles.  Static string owned by the library; "" for an invalid
+ * combination (n not a power of two in [AQMP_MIN_N, AQMP_MAX_N], unknown
+ * precision or variant).  Levels with n <= 8 run the fused per-level pursuit
+ * instead; their name is returned for those n. */
+const char* aqmp_corr_kernel(int n, int precision, int corr_variant);
+
 #ifdef __cplusplus
 }
 #endif

@@ -37,6 +37,7 @@ EXPORTS = [
     "aqmp_dictionary_build", "aqmp_dictionary_free", "aqmp_dictionary_atoms", "aqmp_dictionary_copy",
     "aqmp_encode", "aqmp_reencode", "aqmp_code_sizes", "aqmp_code_export", "aqmp_code_export_nodes",
     "aqmp_code_stats", "aqmp_code_timing", "aqmp_code_free", "aqmp_decode", "aqmp_last_error",
+    "aqmp_corr_kernel",
 ]
 
 
@@ -109,6 +110,8 @@ def _load() -> C.CDLL:
     lib.aqmp_decode.argtypes = [vp, vp, i32, vp, i32, i64, vp]
     lib.aqmp_last_error.argtypes = []
     lib.aqmp_last_error.restype = C.c_char_p
+    lib.aqmp_corr_kernel.argtypes = [i32, i32, i32]
+    lib.aqmp_corr_kernel.restype = C.c_char_p
     for name in EXPORTS:
         if not hasattr(lib, name):
             raise ImportError(f"{LIB_PATH} lacks {name}")
@@ -130,6 +133,11 @@ def _stream_handle(stream) -> int | None:
     if isinstance(stream, int):
         return stream
     return stream.cuda_stream
+
+
+def corr_kernel(n: int, precision: int, corr_variant: int = 0) -> str:
+    """Name of the correlation kernel an encode runs at block size n ("" if invalid)."""
+    return lib.aqmp_corr_kernel(int(n), int(precision), int(corr_variant)).decode()
 
 
 def make_params(tol: float, tol_mode: str = "rms", max_atoms: int = 32, n_min: int = 8, n_max: int = 64,

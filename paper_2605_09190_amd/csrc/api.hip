@@ -142,4 +142,8 @@ int aqmp_decode(const aqmp_dict* d, const aqmp_code* c, int job, void* dev_out, 
 
 const char* aqmp_last_error(void) { return last_error(); }
 
+const char* aqmp_corr_kernel(int n, int precision, int corr_variant) {
+  return aqmp::corr_kernel_name(n, precision, corr_variant);
+}
+
 }  // extern "C"

@@ -115,6 +115,10 @@ hipError_t launch_decode(int n, const JobDev* jobs, LevelDev lv, const int32_t* 
                          int32_t nfam, const double* tab, void* out, int32_t dtype,
                          int64_t row_stride, hipStream_t s);
 
+// Name of the correlation kernel launch_corr runs (or the fused pursuit for
+// n <= kFusedMaxN); "" when the combination is invalid.
+const char* corr_kernel_name(int n, int precision, int variant);
+
 // Tile geometry of the correlation kernel per block size (atoms per tile).
 int corr_atom_tile(int n);
 int corr_grid(int n, int precision);

@@ -1160,6 +1160,28 @@ static void launch_corr_n(int precision, int variant, const void* atoms, const S
   }
 }
 
+const char* corr_kernel_name(int n, int precision, int variant) {
+  if (n < AQMP_MIN_N || n > AQMP_MAX_N || (n & (n - 1))) return "";
+  if (variant < 0 || variant > 6) return "";
+  if (precision != AQMP_PREC_FP32 && precision != AQMP_PREC_BF16) return "";
+  static const char* const fused[] = {"", "", "k_mp_fused<4>", "k_mp_fused<8>"};
+  if (n <= kFusedMaxN) return fused[ilog2(n)];
+  static const char* const f32[] = {"k_corr_f32<16>", "k_corr_f32<32>", "k_corr_f32<64>"};
+  const int li = ilog2(n) - 4;
+  if (precision == AQMP_PREC_FP32) return f32[li];
+  if (variant == 0) variant = default_variant(n);
+  if (variant == 4) return n <= 32 ? (n == 16 ? "k_corr_bf16<16,narrow>" : "k_corr_bf16<32,narrow>") : "k_corr_bf16_dma<64,32,2>";
+  static const char* const v1[] = {"k_corr_bf16_dma<16,64,1>", "k_corr_bf16_dma<32,64,1>", "k_corr_bf16_dma<64,64,1>"};
+  static const char* const v2[] = {"k_corr_bf16_dma<16,32,2>", "k_corr_bf16_dma<32,32,2>", "k_corr_bf16_dma<64,32,2>"};
+  static const char* const v3[] = {"k_corr_bf16<16>", "k_corr_bf16<32>", "k_corr_bf16<64>"};
+  static const char* const v5[] = {"k_corr_bf16_pipe<16,64>", "k_corr_bf16_pipe<32,64>", "k_corr_bf16_pipe<64,64>"};
+  if (variant == 1) return v1[li];
+  if (variant == 2) return v2[li];
+  if (variant == 5) return v5[li];
+  if (variant == 6) return n == kGenN ? "k_corr_bf16_gen<64>" : v3[li];
+  return v3[li];
+}
+
 hipError_t launch_corr(int n, int precision, int variant, const void* dict_atoms, const StepArgs& a,
                        int32_t m_pad, hipStream_t s) {
   const int nat = m_pad / corr_atom_tile(n);

@@ -151,6 +151,14 @@ __global__ __launch_bounds__(256) void k_select(StepArgs a) {
   const int px = (lane % G::PX) * G::PW;
   const int stride = gridDim.x * 4;
   for (int pos = blockIdx.x * 4 + w; pos < count; pos += stride) {
+    // The keys depend only on the position: their loads go out first.
+    unsigned long long k[KPL];
+    const unsigned long long* kp = a.keys + (size_t)pos * nkeys;
+#pragma unroll
+    for (int j = 0; j < KPL; ++j) {
+      const int idx = lane + j * 64;
+      k[j] = idx < nkeys ? kp[idx] : 0ull;
+    }
     const int node = a.act[pos];
     const JobDev& jb = a.jobs[a.lv.job[node]];
     const int t = a.lv.t[node];
@@ -162,13 +170,6 @@ __global__ __launch_bounds__(256) void k_select(StepArgs a) {
       for (int dx = 0; dx < G::PW; ++dx) rv[dy][dx] = r[(py + dy) * N + px + dx];
 
     // 1. top kCand keys over the node's per-tile lists.
-    unsigned long long k[KPL];
-    const unsigned long long* kp = a.keys + (size_t)pos * nkeys;
-#pragma unroll
-    for (int j = 0; j < KPL; ++j) {
-      const int idx = lane + j * 64;
-      k[j] = idx < nkeys ? kp[idx] : 0ull;
-    }
 #pragma unroll
     for (int p0 = 0; p0 < KPL; ++p0)
 #pragma unroll
@@ -191,11 +192,16 @@ __global__ __launch_bounds__(256) void k_select(StepArgs a) {
       cand[rr] = (mx != 0ull && atom < (unsigned)a.n_atoms) ? (int)atom : -1;
     }
 
-    // Stage the candidates' table rows: 2 * kCand rows of N doubles.
-    for (int e = lane; e < kCand * 2 * N; e += 64) {
+    // Stage the candidates' table rows: 2 * kCand rows of N doubles, all
+    // loads issued before the first LDS write (one memory round trip).
+    constexpr int NSTG = kCand * 2 * N / 64;
+    static_assert(kCand * 2 * N % 64 == 0, "whole waves of table entries");
+    double stg[NSTG];
+#pragma unroll
+    for (int i = 0; i < NSTG; ++i) {
+      const int e = lane + 64 * i;
       const int ci = e / (2 * N), which = (e / N) & 1, col = e % N;
-      const int atom = cand[0];
-      int at = atom;
+      int at = cand[0];
 #pragma unroll
       for (int c2 = 1; c2 < kCand; ++c2)
         if (ci == c2) at = cand[c2];
@@ -204,7 +210,12 @@ __global__ __launch_bounds__(256) void k_select(StepArgs a) {
         const int f = at / K, q = (at % K) / N, p = at % N;
         v = a.tab[(size_t)f * K + (which ? q : p) * N + col];
       }
-      sT[w][ci][which][col] = v;
+      stg[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < NSTG; ++i) {
+      const int e = lane + 64 * i;
+      sT[w][e / (2 * N)][(e / N) & 1][e % N] = stg[i];
     }
     __builtin_amdgcn_wave_barrier();
 
@@ -279,8 +290,12 @@ __global__ __launch_bounds__(256) void k_select(StepArgs a) {
 #pragma unroll
         for (int dx = 0; dx < G::PW; ++dx) r[o + dx] = rn[dx];
         if (a.r16) {
+          // PW BF16 values (round to nearest even) as one vector store
+          typedef __bf16 bf16v __attribute__((ext_vector_type(G::PW)));
+          bf16v pk;
 #pragma unroll
-          for (int dx = 0; dx < G::PW; ++dx) a.r16[(size_t)node * K + o + dx] = f32_to_bf16(rn[dx]);
+          for (int dx = 0; dx < G::PW; ++dx) pk[dx] = (__bf16)rn[dx];
+          *(bf16v*)(a.r16 + (size_t)node * K + o) = pk;
         }
       }
       e = wave_sum_f64(e);

@@ -91,3 +91,19 @@ def test_invalid_arguments_fail_without_a_device():
     assert A.lib.aqmp_dictionary_atoms(None, 8, C.byref(m)) == A.E_INVALID
     A.lib.aqmp_dictionary_free(None)
     A.lib.aqmp_code_free(None)
+
+
+def test_corr_kernel_names():
+    """The kernel-name query is host-only and reflects the per-size defaults."""
+    from paper_2605_09190_amd import aqmp as A
+    assert A.corr_kernel(64, A.PREC_BF16) == "k_corr_bf16_gen<64>"
+    assert A.corr_kernel(32, A.PREC_BF16) == "k_corr_bf16_pipe<32,64>"
+    assert A.corr_kernel(16, A.PREC_BF16) == "k_corr_bf16_dma<16,32,2>"
+    assert A.corr_kernel(64, A.PREC_BF16, 5) == "k_corr_bf16_pipe<64,64>"
+    assert A.corr_kernel(64, A.PREC_FP32) == "k_corr_f32<64>"
+    assert A.corr_kernel(8, A.PREC_BF16) == "k_mp_fused<8>"
+    assert A.corr_kernel(4, A.PREC_FP32) == "k_mp_fused<4>"
+    assert A.corr_kernel(48, A.PREC_BF16) == ""
+    assert A.corr_kernel(128, A.PREC_BF16) == ""
+    assert A.corr_kernel(64, 7) == ""
+    assert A.corr_kernel(64, A.PREC_BF16, 9) == ""
