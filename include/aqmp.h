@@ -108,7 +108,7 @@ typedef struct {
   int32_t params;
 } aqmp_job;
 
-enum { AQMP_OPT_TIMING = 1 };   /* aqmp_options.flags */
+enum { AQMP_OPT_TIMING = 1, AQMP_OPT_STEPWISE = 2 };   /* aqmp_options.flags */
 
 typedef struct {
   int32_t precision;   /* AQMP_PREC_FP32: FP32 MFMA correlation;
@@ -128,7 +128,11 @@ typedef struct {
                           launch of an MP step (see aqmp_code_timing).
                           Events cannot be timed inside a graph, so a timed
                           batched encode issues the same launches directly
-                          on the stream. */
+                          on the stream.
+                          AQMP_OPT_STEPWISE: run the N = 16 level of the
+                          BF16 form one MP step per launch (correlation,
+                          select, compaction) instead of the whole-level
+                          pursuit; same method, for comparison. */
   int32_t corr_variant;  /* tuning: 0 = library default; 1..6 force one
                             family of BF16 correlation kernels (results
                             are identical, only speed differs) */

@@ -29,6 +29,7 @@ SPLIT_R1, SPLIT_R2 = 0, 1
 PREC_FP32, PREC_BF16 = 0, 1
 SCHED_PLAIN, SCHED_BATCHED, SCHED_CONCURRENT = 0, 1, 2
 OPT_TIMING = 1
+OPT_STEPWISE = 2
 MAX_ATOMS = 256
 CANDIDATES = 8
 
@@ -215,7 +216,8 @@ class Code:
     """An encode: the quadtree leaves and their atoms, kept on the device."""
 
     def __init__(self, dic: Dictionary, images, params, jobs, precision: int = PREC_FP32,
-                 schedule: int = SCHED_PLAIN, stream=None, timing: bool = False, corr_variant: int = 0):
+                 schedule: int = SCHED_PLAIN, stream=None, timing: bool = False, corr_variant: int = 0,
+                 stepwise: bool = False):
         self.dic = dic
         self._keep = list(images)
         imgs = (Image * len(images))(*[make_image(t) for t in images])
@@ -223,7 +225,7 @@ class Code:
         jbs = (Job * len(jobs))(*[Job(int(a), int(b)) for a, b in jobs])
         opt = Options()
         opt.precision, opt.schedule = int(precision), int(schedule)
-        opt.flags = OPT_TIMING if timing else 0
+        opt.flags = (OPT_TIMING if timing else 0) | (OPT_STEPWISE if stepwise else 0)
         opt.corr_variant = int(corr_variant)
         h = C.c_void_p()
         _check(lib.aqmp_encode(dic.h, imgs, len(images), prms, len(params), jbs, len(jobs), C.byref(opt),

@@ -111,6 +111,8 @@ int validate(const aqmp_dict* d, const aqmp_image* imgs, int n_imgs, const aqmp_
     if (opt->schedule != AQMP_SCHED_PLAIN && opt->schedule != AQMP_SCHED_BATCHED &&
         opt->schedule != AQMP_SCHED_CONCURRENT)
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad schedule");
+    if (opt->flags & ~(AQMP_OPT_TIMING | AQMP_OPT_STEPWISE))
+      AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: unknown option flags");
     if (opt->corr_variant < 0 || opt->corr_variant > 6)
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad corr_variant");
   }
@@ -240,6 +242,13 @@ void free_code(aqmp_code* c) {
   delete c;
 }
 
+// Levels that run as one launch: N <= kFusedMaxN in both forms (dense FP64
+// pursuit) and N = 16 in the BF16 form (whole-level MFMA pursuit).
+static bool whole_level(const aqmp_code* c, int n) {
+  if (n <= kFusedMaxN) return true;
+  return n == 16 && c->opt.precision == AQMP_PREC_BF16 && !(c->opt.flags & AQMP_OPT_STEPWISE);
+}
+
 int build_plan(aqmp_code* c) {
   const int nj = (int)c->jobs.size();
   c->hjobs.resize(nj);
@@ -363,7 +372,7 @@ int build_plan(aqmp_code* c) {
         AQMP_HIP(hipEventCreate(&le.start));
         AQMP_HIP(hipEventCreate(&le.end));
         c->lev.push_back(le);
-        if ((1 << l) <= kFusedMaxN) continue;   // whole level in one launch
+        if (whole_level(c, 1 << l)) continue;   // whole level in one launch
         for (int t = 0; t < pp.kmax[l]; ++t) {
           aqmp_code::StepEv se{l, nullptr, nullptr, nullptr};
           AQMP_HIP(hipEventCreate(&se.a));
@@ -408,9 +417,12 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
     const bool timing = (c->opt.flags & AQMP_OPT_TIMING) != 0;
     const aqmp_code::LevelEv* le = timing ? &c->lev[c->lev_pos++] : nullptr;
     if (le) AQMP_HIP(hipEventRecord(le->start, s));
-    if (n <= kFusedMaxN) {
-      // Small blocks: each node's whole pursuit in one launch (dictionary in LDS).
-      AQMP_LAUNCH(launch_mp_fused(n, c->djobs, a.lv, count, l, D.m, D.d_tab, s));
+    if (whole_level(c, n)) {
+      // Small blocks: each node's whole pursuit in one launch.
+      if (n <= kFusedMaxN)
+        AQMP_LAUNCH(launch_mp_fused(n, c->djobs, a.lv, count, l, D.m, D.d_tab, s));
+      else
+        AQMP_LAUNCH(launch_pursuit16_bf16(c->djobs, a.lv, count, D.m, d->nfam, D.d_tab, D.d_tabT32, s));
       if (l > pp.lg_lo && pp.cap[l - 1] > 0)
         AQMP_LAUNCH(launch_split_emit(c->djobs, a.lv, count, level_at(c, l - 1, pp.base[l - 1]), pp.ntop[l - 1],
                                       &cnt->count[l - 1], l, pp.cap[l], wk.ss, &cnt->scan_error, s));

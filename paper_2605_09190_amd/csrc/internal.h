@@ -111,6 +111,8 @@ hipError_t launch_corr(int n, int precision, int variant, const void* dict_atoms
 hipError_t launch_select(int n, const StepArgs& a, hipStream_t s);
 hipError_t launch_mp_fused(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t lg, int32_t n_atoms,
                            const double* tab, hipStream_t s);
+hipError_t launch_pursuit16_bf16(const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t n_atoms, int32_t nfam,
+                                 const double* tab, const float* tabT32, hipStream_t s);
 hipError_t launch_decode(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t job,
                          int32_t nfam, const double* tab, void* out, int32_t dtype,
                          int64_t row_stride, hipStream_t s);

@@ -728,38 +728,44 @@ __global__ __launch_bounds__(256, 1) void k_corr_bf16_pipe(const uint16_t* __res
 // other forms: the keys are bit-identical.
 // ---------------------------------------------------------------------------
 constexpr int kGenN = 64;
+constexpr int kGenRing = 4;                 // residual stages in LDS (prefetch distance 3)
+constexpr int kGenMBMin = 3, kGenMBMax = 7;  // node tile = 32 MB nodes
 
-// Geometry: tile 256 atoms x 128 nodes, BK = 64 (one pixel row), the four
-// waves side by side along the atoms (64 atoms x 128 nodes each), so a wave
-// makes only the A fragments of its own rows: 2 per k-step, 3 VALU per MFMA.
+// Geometry for a node tile of 32 MB nodes: tile 256 atoms x 32 MB nodes,
+// BK = 64 (one pixel row), the four waves side by side along the atoms
+// (64 atoms x 32 MB nodes each), so a wave makes only the A fragments of its
+// own rows: 2 per k-step, shared by MB MFMAs.
+template <int MB_>
 struct GenGeo {
-  static constexpr int BA = 256, BB = 128, BK = 64, WA = 4, WB = 1;
+  static constexpr int BA = 256, BB = 32 * MB_, BK = 64, WA = 4, WB = 1;
   static constexpr int WTA = BA / WA, WTB = BB / WB, MA = WTA / 32, MB = WTB / 32;
   static constexpr int ROWB = BK * 2, CPR = ROWB / 16, RPB = 1024 / ROWB;
   static constexpr int B_BYTES = BB * ROWB;
-  static constexpr int B_INS = BB / RPB / 4;
+  static constexpr int B_INS = BB / RPB / 4;   // = MB loads per wave per stage
   using C = Cfg<BA, BB, BK, WA, WB>;
   __device__ static int swz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
 };
+constexpr int kGenBufBytes = GenGeo<kGenMBMax>::B_BYTES;   // one ring buffer (28 KB)
 
+template <class G>
 struct GenFrag {
-  bf16x8 a[2][GenGeo::MA];
-  bf16x8 b[2][GenGeo::MB];
+  bf16x8 a[2][G::MA];
+  bf16x8 b[2][G::MB];
 };
 
 // B fragments of k-step KK into parity slot P.
-template <int KK, int P>
-__device__ inline void gen_read_b(GenFrag& f, const char* sb, const int (&off)[4]) {
+template <class G, int KK, int P>
+__device__ inline void gen_read_b(GenFrag<G>& f, const char* sb, const int (&off)[4]) {
 #pragma unroll
-  for (int mb = 0; mb < GenGeo::MB; ++mb) f.b[P][mb] = *(const bf16x8*)(sb + mb * 32 * GenGeo::ROWB + off[KK]);
+  for (int mb = 0; mb < G::MB; ++mb) f.b[P][mb] = *(const bf16x8*)(sb + mb * 32 * G::ROWB + off[KK]);
   __builtin_amdgcn_sched_barrier(0);   // the reads go out a whole k-step before their MFMAs
 }
 
 // A fragments of k-step KK (x = 16 KK + 8 h + j) for the row factors tp.
-template <int KK, int P>
-__device__ inline void gen_make_a(GenFrag& f, const float (&tp)[GenGeo::MA], const float (&tq)[32]) {
+template <class G, int KK, int P>
+__device__ inline void gen_make_a(GenFrag<G>& f, const float (&tp)[G::MA], const float (&tq)[32]) {
 #pragma unroll
-  for (int ma = 0; ma < GenGeo::MA; ++ma) {
+  for (int ma = 0; ma < G::MA; ++ma) {
     bf16x8 v;
 #pragma unroll
     for (int j = 0; j < 8; ++j) v[j] = (__bf16)(tp[ma] * tq[KK * 8 + j]);
@@ -767,25 +773,25 @@ __device__ inline void gen_make_a(GenFrag& f, const float (&tp)[GenGeo::MA], con
   }
 }
 
-template <int KK>
-__device__ inline void gen_mfma(f32x16 (&acc)[GenGeo::MA][GenGeo::MB], const GenFrag& f) {
+template <class G, int KK>
+__device__ inline void gen_mfma(f32x16 (&acc)[G::MA][G::MB], const GenFrag<G>& f) {
   constexpr int P = KK & 1;
 #pragma unroll
-  for (int mb = 0; mb < GenGeo::MB; ++mb)
+  for (int mb = 0; mb < G::MB; ++mb)
 #pragma unroll
-    for (int ma = 0; ma < GenGeo::MA; ++ma)
+    for (int ma = 0; ma < G::MA; ++ma)
       acc[ma][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[P][ma], f.b[P][mb], acc[ma][mb], 0, 0, 0);
 }
 
 // Residual rows of stage s: loads [first, first + cnt) of the wave's B_INS.
-template <int K>
-__device__ inline void gen_dma(const DmaPtrs<GenGeo>& p, char* sb, int s, int first, int cnt) {
+template <class G, int K>
+__device__ inline void gen_dma(const DmaPtrs<G>& p, char* sb, int s, int first, int cnt) {
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int kofs = s * GenGeo::BK * 2;
+  const int kofs = s * G::BK * 2;
 #pragma unroll
-  for (int i = 0; i < GenGeo::B_INS; ++i)
+  for (int i = 0; i < G::B_INS; ++i)
     if (i >= first && i < first + cnt)
-      lds_dma16(p.b_base, (int)0xFFFFFFFFu, sb + (w * GenGeo::B_INS + i) * 1024, (int)p.b_off[i], kofs);
+      lds_dma16(p.b_base, (int)0xFFFFFFFFu, sb + (w * G::B_INS + i) * 1024, (int)p.b_off[i], kofs);
 }
 
 // One stage (pixel row y = s) computed from cb.  DMA: the loads of stage
@@ -793,27 +799,28 @@ __device__ inline void gen_dma(const DmaPtrs<GenGeo>& p, char* sb, int s, int fi
 // follows in nb; its loads are complete once at most VMN of this wave's loads
 // are outstanding (loads complete in order), and its first fragments are made
 // here, under the last MFMAs of stage s.
-template <int K, bool DMA, bool NEXT, int VMN>
-__device__ inline void gen_stage(f32x16 (&acc)[GenGeo::MA][GenGeo::MB], GenFrag& f, const DmaPtrs<GenGeo>& p,
-                                 const float* sTf, const float (&tq)[32], float (&tp)[GenGeo::MA], const char* cb,
-                                 const char* nb, char* db, int s, int s_dma, const int (&off)[4]) {
+template <class G, int K, bool DMA, bool NEXT, int VMN>
+__device__ inline void gen_stage(f32x16 (&acc)[G::MA][G::MB], GenFrag<G>& f, const DmaPtrs<G>& p, const float* sTf,
+                                 const float (&tq)[32], float (&tp)[G::MA], const char* cb, const char* nb, char* db,
+                                 int s, int s_dma, const int (&off)[4]) {
+  constexpr int H1 = (G::B_INS + 1) / 2;
   const int rr = threadIdx.x & 31;
-  gen_read_b<1, 1>(f, cb, off);
-  gen_make_a<1, 1>(f, tp, tq);
-  if constexpr (DMA) gen_dma<K>(p, db, s_dma, 0, 2);
-  gen_mfma<0>(acc, f);
-  gen_read_b<2, 0>(f, cb, off);
-  gen_make_a<2, 0>(f, tp, tq);
-  if constexpr (DMA) gen_dma<K>(p, db, s_dma, 2, 2);
-  gen_mfma<1>(acc, f);
-  gen_read_b<3, 1>(f, cb, off);
-  gen_make_a<3, 1>(f, tp, tq);
-  float tpn[GenGeo::MA];
+  gen_read_b<G, 1, 1>(f, cb, off);
+  gen_make_a<G, 1, 1>(f, tp, tq);
+  if constexpr (DMA) gen_dma<G, K>(p, db, s_dma, 0, H1);
+  gen_mfma<G, 0>(acc, f);
+  gen_read_b<G, 2, 0>(f, cb, off);
+  gen_make_a<G, 2, 0>(f, tp, tq);
+  if constexpr (DMA) gen_dma<G, K>(p, db, s_dma, H1, G::B_INS - H1);
+  gen_mfma<G, 1>(acc, f);
+  gen_read_b<G, 3, 1>(f, cb, off);
+  gen_make_a<G, 3, 1>(f, tp, tq);
+  float tpn[G::MA];
   if constexpr (NEXT) {
 #pragma unroll
-    for (int ma = 0; ma < GenGeo::MA; ++ma) tpn[ma] = sTf[(s + 1) * kGenN + 32 * ma + rr];
+    for (int ma = 0; ma < G::MA; ++ma) tpn[ma] = sTf[(s + 1) * kGenN + 32 * ma + rr];
   }
-  gen_mfma<2>(acc, f);
+  gen_mfma<G, 2>(acc, f);
   if constexpr (NEXT) {
     // every wave is done reading cb before any wave passes, so loads issued
     // after this barrier may overwrite it
@@ -821,102 +828,77 @@ __device__ inline void gen_stage(f32x16 (&acc)[GenGeo::MA][GenGeo::MB], GenFrag&
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int ma = 0; ma < GenGeo::MA; ++ma) tp[ma] = tpn[ma];
-    gen_read_b<0, 0>(f, nb, off);
-    gen_make_a<0, 0>(f, tp, tq);
+    for (int ma = 0; ma < G::MA; ++ma) tp[ma] = tpn[ma];
+    gen_read_b<G, 0, 0>(f, nb, off);
+    gen_make_a<G, 0, 0>(f, tp, tq);
   }
-  gen_mfma<3>(acc, f);
+  gen_mfma<G, 3>(acc, f);
 }
-
-// Ring of NB residual buffers: stage s is computed from buffer s % NB while
-// stages s + 1 .. s + NB - 1 are in flight (prefetch distance NB - 1).
-constexpr int kGenRing = 6;
 
 // The ring buffers are separate LDS arrays: the compiler then knows that a
 // load into one buffer cannot feed a read of another, and does not wait for
 // the loads in flight before every fragment read.
-struct GenArgs {
-  const DmaPtrs<GenGeo>* p;
-  const float* sTf;
+struct GenRing {
   char* r0;
   char* r1;
   char* r2;
   char* r3;
-  char* r4;
-  char* r5;
   template <int I>
   __device__ char* buf() const {
-    static_assert(kGenRing == 6, "six ring buffers");
+    static_assert(kGenRing == 4, "four ring buffers");
     if constexpr (I == 0) return r0;
     else if constexpr (I == 1) return r1;
     else if constexpr (I == 2) return r2;
-    else if constexpr (I == 3) return r3;
-    else if constexpr (I == 4) return r4;
-    else return r5;
+    else return r3;
   }
 };
 
 // Stages S .. NST - 1 with every decision at compile time.
-template <int K, int NST, int S>
-__device__ inline void gen_tail(f32x16 (&acc)[GenGeo::MA][GenGeo::MB], GenFrag& f, const GenArgs& g,
-                                const float (&tq)[32], float (&tp)[GenGeo::MA], const int (&off)[4]) {
+template <class G, int K, int NST, int S>
+__device__ inline void gen_tail(f32x16 (&acc)[G::MA][G::MB], GenFrag<G>& f, const DmaPtrs<G>& p, const float* sTf,
+                                const GenRing& rg, const float (&tq)[32], float (&tp)[G::MA], const int (&off)[4]) {
   if constexpr (S < NST) {
     constexpr int NB = kGenRing;
     constexpr bool DMA = S + NB - 1 < NST;
     constexpr bool NEXT = S + 1 < NST;
     constexpr int AHEAD = (NST - 2 - S) < (NB - 2) ? (NST - 2 - S) : (NB - 2);
-    constexpr int VMN = NEXT ? GenGeo::B_INS * (AHEAD > 0 ? AHEAD : 0) : 0;
-    gen_stage<K, DMA, NEXT, VMN>(acc, f, *g.p, g.sTf, tq, tp, g.template buf<S % NB>(),
-                                 g.template buf<(S + 1) % NB>(), g.template buf<(S + NB - 1) % NB>(), S,
-                                 S + NB - 1, off);
-    gen_tail<K, NST, S + 1>(acc, f, g, tq, tp, off);
+    constexpr int VMN = NEXT ? G::B_INS * (AHEAD > 0 ? AHEAD : 0) : 0;
+    gen_stage<G, K, DMA, NEXT, VMN>(acc, f, p, sTf, tq, tp, rg.template buf<S % NB>(),
+                                    rg.template buf<(S + 1) % NB>(), rg.template buf<(S + NB - 1) % NB>(), S,
+                                    S + NB - 1, off);
+    gen_tail<G, K, NST, S + 1>(acc, f, p, sTf, rg, tq, tp, off);
   }
 }
 
-// NB consecutive steady-state stages s0 + I (s0 a multiple of NB): buffers
-// are compile-time, stage indices run-time.
-template <int K, int I>
-__device__ inline void gen_trip(f32x16 (&acc)[GenGeo::MA][GenGeo::MB], GenFrag& f, const GenArgs& g,
-                                const float (&tq)[32], float (&tp)[GenGeo::MA], const int (&off)[4], int s0) {
+// NB consecutive steady-state stages s0 + I (s0 a multiple of NB).
+template <class G, int K, int I>
+__device__ inline void gen_trip(f32x16 (&acc)[G::MA][G::MB], GenFrag<G>& f, const DmaPtrs<G>& p, const float* sTf,
+                                const GenRing& rg, const float (&tq)[32], float (&tp)[G::MA], const int (&off)[4],
+                                int s0) {
   if constexpr (I < kGenRing) {
     constexpr int NB = kGenRing;
-    gen_stage<K, true, true, GenGeo::B_INS * (NB - 2)>(acc, f, *g.p, g.sTf, tq, tp, g.template buf<I>(),
-                                                        g.template buf<(I + 1) % NB>(),
-                                                        g.template buf<(I + NB - 1) % NB>(), s0 + I,
-                                                        s0 + I + NB - 1, off);
-    gen_trip<K, I + 1>(acc, f, g, tq, tp, off, s0);
+    gen_stage<G, K, true, true, G::B_INS * (NB - 2)>(acc, f, p, sTf, tq, tp, rg.template buf<I>(),
+                                                      rg.template buf<(I + 1) % NB>(),
+                                                      rg.template buf<(I + NB - 1) % NB>(), s0 + I, s0 + I + NB - 1,
+                                                      off);
+    gen_trip<G, K, I + 1>(acc, f, p, sTf, rg, tq, tp, off, s0);
   }
 }
 
-template <int N>
-__global__ __launch_bounds__(256, 1) void k_corr_bf16_gen(const float* __restrict__ tabT32, int nfam,
-                                                          const uint16_t* __restrict__ X,
-                                                          const int32_t* __restrict__ act,
-                                                          const int32_t* __restrict__ act_count,
-                                                          unsigned long long* __restrict__ keys, int n_atom_tiles) {
-  static_assert(N == kGenN, "generated atoms: one stage is one pixel row of 64");
-  using G = GenGeo;
-  constexpr int K = N * N;
-  constexpr int NST = K / G::BK;
-  constexpr int NB = kGenRing;
+// Every tile of one launch with node tiles of 32 MB nodes.
+template <int MB>
+__device__ void gen_tiles(const uint16_t* __restrict__ X, const int32_t* __restrict__ act, int count,
+                          unsigned long long* __restrict__ keys, int n_atom_tiles, int nfam, const float* sT,
+                          const GenRing& rg) {
+  using G = GenGeo<MB>;
+  constexpr int N = kGenN, K = N * N, NST = K / G::BK, NB = kGenRing;
   static_assert(NST >= NB, "ring shorter than the K loop");
-  __shared__ __attribute__((aligned(1024))) char sR0[G::B_BYTES];
-  __shared__ __attribute__((aligned(1024))) char sR1[G::B_BYTES];
-  __shared__ __attribute__((aligned(1024))) char sR2[G::B_BYTES];
-  __shared__ __attribute__((aligned(1024))) char sR3[G::B_BYTES];
-  __shared__ __attribute__((aligned(1024))) char sR4[G::B_BYTES];
-  __shared__ __attribute__((aligned(1024))) char sR5[G::B_BYTES];
-  __shared__ float sT[2 * K];   // [f][y][p] = fl32(T_f[p][y])
-  static_assert(G::WA * G::BB * kTopR * 4 <= G::B_BYTES, "epilogue scratch fits one B buffer");
-  uint32_t* sK = (uint32_t*)sR0;
-
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int i = tid; i < nfam * K / 4; i += 256) ((float4*)sT)[i] = ((const float4*)tabT32)[i];
-  __syncthreads();
-
-  const int count = *act_count;
+  static_assert(G::B_BYTES <= kGenBufBytes, "stage fits a ring buffer");
+  static_assert(G::WA * G::BB * kTopR * 4 <= kGenBufBytes, "epilogue scratch fits one ring buffer");
+  uint32_t* sK = (uint32_t*)rg.r0;
   const int ntB = (count + G::BB - 1) / G::BB;
   const int ntiles = n_atom_tiles * ntB;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wa = w, rr = lane & 31, hh = lane >> 5;
   const int fr = G::swz(rr);
   int off[4];
@@ -960,25 +942,66 @@ __global__ __launch_bounds__(256, 1) void k_corr_bf16_gen(const float* __restric
       for (int mb = 0; mb < G::MB; ++mb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[ma][mb][r] = 0.f;
-    GenFrag f;
+    GenFrag<G> f;
 
     __syncthreads();   // previous tile's epilogue is done with sK (= buffer 0)
-    const GenArgs g{&p, sTf, sR0, sR1, sR2, sR3, sR4, sR5};
-    gen_dma<K>(p, g.buf<0>(), 0, 0, G::B_INS);
-    gen_dma<K>(p, g.buf<1>(), 1, 0, G::B_INS);
-    gen_dma<K>(p, g.buf<2>(), 2, 0, G::B_INS);
-    gen_dma<K>(p, g.buf<3>(), 3, 0, G::B_INS);
-    gen_dma<K>(p, g.buf<4>(), 4, 0, G::B_INS);
+    gen_dma<G, K>(p, rg.template buf<0>(), 0, 0, G::B_INS);
+    gen_dma<G, K>(p, rg.template buf<1>(), 1, 0, G::B_INS);
+    gen_dma<G, K>(p, rg.template buf<2>(), 2, 0, G::B_INS);
     AQMP_WAIT_VM(G::B_INS * (NB - 2));
     __builtin_amdgcn_s_barrier();
-    gen_read_b<0, 0>(f, g.buf<0>(), off);
-    gen_make_a<0, 0>(f, tp, tq);
+    gen_read_b<G, 0, 0>(f, rg.template buf<0>(), off);
+    gen_make_a<G, 0, 0>(f, tp, tq);
     constexpr int FULL = NST - (NB - 1);      // stages that issue a load
     constexpr int TRIPS = FULL / NB;
-    for (int t = 0; t < TRIPS; ++t) gen_trip<K, 0>(acc, f, g, tq, tp, off, t * NB);
-    gen_tail<K, NST, TRIPS * NB>(acc, f, g, tq, tp, off);
+    for (int t = 0; t < TRIPS; ++t) gen_trip<G, K, 0>(acc, f, p, sTf, rg, tq, tp, off, t * NB);
+    gen_tail<G, K, NST, TRIPS * NB>(acc, f, p, sTf, rg, tq, tp, off);
     __syncthreads();   // all waves done reading the ring before sK reuses buffer 0
     epilogue<typename G::C>(acc, sK, a0, a_tile, n_atom_tiles, b0, count, keys);
+  }
+}
+
+// Node-tile width for this launch: the fewest 32-node block-rounds over the
+// workgroups (rounds x MB), ties to the wider tile.  Every workgroup computes
+// the same value from the count.
+__device__ inline int gen_pick_mb(int count, int n_atom_tiles, int wgs) {
+  int best = kGenMBMax, best_cost = 0x7fffffff;
+  for (int mb = kGenMBMax; mb >= kGenMBMin; --mb) {
+    const int tiles = n_atom_tiles * ((count + 32 * mb - 1) / (32 * mb));
+    const int cost = ((tiles + wgs - 1) / wgs) * mb;
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = mb;
+    }
+  }
+  return best;
+}
+
+template <int N>
+__global__ __launch_bounds__(256, 1) void k_corr_bf16_gen(const float* __restrict__ tabT32, int nfam,
+                                                          const uint16_t* __restrict__ X,
+                                                          const int32_t* __restrict__ act,
+                                                          const int32_t* __restrict__ act_count,
+                                                          unsigned long long* __restrict__ keys, int n_atom_tiles) {
+  static_assert(N == kGenN, "generated atoms: one stage is one pixel row of 64");
+  constexpr int K = N * N;
+  __shared__ __attribute__((aligned(1024))) char sR0[kGenBufBytes];
+  __shared__ __attribute__((aligned(1024))) char sR1[kGenBufBytes];
+  __shared__ __attribute__((aligned(1024))) char sR2[kGenBufBytes];
+  __shared__ __attribute__((aligned(1024))) char sR3[kGenBufBytes];
+  __shared__ float sT[2 * K];   // [f][y][p] = fl32(T_f[p][y])
+  const int tid = threadIdx.x;
+  for (int i = tid; i < nfam * K / 4; i += 256) ((float4*)sT)[i] = ((const float4*)tabT32)[i];
+  __syncthreads();
+  const int count = *act_count;
+  if (count <= 0) return;
+  const GenRing rg{sR0, sR1, sR2, sR3};
+  switch (gen_pick_mb(count, n_atom_tiles, gridDim.x)) {
+    case 3: gen_tiles<3>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
+    case 4: gen_tiles<4>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
+    case 5: gen_tiles<5>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
+    case 6: gen_tiles<6>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
+    default: gen_tiles<7>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
   }
 }
 

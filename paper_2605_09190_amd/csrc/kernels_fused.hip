@@ -126,7 +126,410 @@ __global__ __launch_bounds__(256) void k_mp_fused(const JobDev* __restrict__ job
   }
 }
 
+// ---------------------------------------------------------------------------
+// Whole-level pursuit for N = 16 in the BF16 form.  At N = 16 one MP step of
+// a node is 262 K multiply-adds: a batched launch per step is mostly launch
+// latency and dependent memory chains.  One workgroup takes 32 nodes through
+// their whole pursuit (Section 2.2 steps (a)-(d), eq. (2)) with every array
+// in LDS:
+//   C   correlation of all 512 atoms with the 32 BF16 residuals by MFMA
+//       (32x32x16, FP32 accumulation, pixel order as in the batched kernels);
+//       the A operand is generated in registers from the FP32 1D tables,
+//       bf16(T32_f[p][y] * T32_f[q][x]), the canonical BF16 atom;
+//   E   each wave keeps, per node, the best 8 keys of its 128 atoms
+//       (branch-free sorting networks, as in the batched epilogue);
+//   M   the four wave lists are merged into the node's 8 candidates, ordered
+//       by (|c| key, lower atom), the same ranking as the batched path;
+//   S   one thread per (node, candidate) re-scores in FP64 against the FP32
+//       residual, separably (Section 2.1 outer product);
+//   A   arg-max (lowest atom on ties), rank-1 update in FP64 rounded to FP32,
+//       ||r||^2 in FP64, record (i, c_i), stop test of eq. (2).
+// Up to 32 MP steps run inside the kernel; a node that stops keeps its slot
+// (its correlation is still computed, its state no longer changes).
+// ---------------------------------------------------------------------------
+constexpr int kP16N = 16, kP16K = 256, kP16G = 32;   // block size, pixels, nodes per workgroup
+constexpr int kP16RS = kP16K + 4;                     // padded FP32 residual row (floats)
+
+typedef __bf16 p16_bf16x8 __attribute__((ext_vector_type(8)));
+typedef float p16_f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ inline void p16_cx(uint32_t& a, uint32_t& b) {
+  const uint32_t hi = a > b ? a : b;
+  b = a > b ? b : a;
+  a = hi;
+}
+__device__ inline void p16_sort8(uint32_t (&v)[8]) {
+  p16_cx(v[0], v[1]); p16_cx(v[2], v[3]); p16_cx(v[4], v[5]); p16_cx(v[6], v[7]);
+  p16_cx(v[0], v[2]); p16_cx(v[1], v[3]); p16_cx(v[4], v[6]); p16_cx(v[5], v[7]);
+  p16_cx(v[1], v[2]); p16_cx(v[5], v[6]);
+  p16_cx(v[0], v[4]); p16_cx(v[1], v[5]); p16_cx(v[2], v[6]); p16_cx(v[3], v[7]);
+  p16_cx(v[2], v[4]); p16_cx(v[3], v[5]);
+  p16_cx(v[1], v[2]); p16_cx(v[3], v[4]); p16_cx(v[5], v[6]);
+}
+template <class T>
+__device__ inline void p16_cxT(T& a, T& b) {
+  const T hi = a > b ? a : b;
+  b = a > b ? b : a;
+  a = hi;
+}
+// a, b descending -> a = top 8 of both, descending (bitonic merge)
+template <class T>
+__device__ inline void p16_merge8(T (&a)[8], const T (&b)[8]) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) a[i] = a[i] > b[7 - i] ? a[i] : b[7 - i];
+  p16_cxT(a[0], a[4]); p16_cxT(a[1], a[5]); p16_cxT(a[2], a[6]); p16_cxT(a[3], a[7]);
+  p16_cxT(a[0], a[2]); p16_cxT(a[1], a[3]); p16_cxT(a[4], a[6]); p16_cxT(a[5], a[7]);
+  p16_cxT(a[0], a[1]); p16_cxT(a[2], a[3]); p16_cxT(a[4], a[5]); p16_cxT(a[6], a[7]);
+}
+
+// 16-byte chunk c (8 pixels) of node row nl in the swizzled BF16 residual.
+__device__ inline int p16_chunk(int nl, int c) { return nl * 32 + (c ^ (nl & 15)); }
+
+__global__ __launch_bounds__(256, 1) void k_pursuit16_bf16(const JobDev* __restrict__ jobs, LevelDev lv,
+                                                           const int32_t* __restrict__ count_ptr, int32_t lg,
+                                                           int32_t n_atoms, int32_t nfam,
+                                                           const double* __restrict__ tab,
+                                                           const float* __restrict__ tabT32) {
+  constexpr int N = kP16N, K = kP16K, G = kP16G;
+  __shared__ __attribute__((aligned(16))) float sR[G][kP16RS];   // FP32 residual
+  __shared__ __attribute__((aligned(16))) uint4 sB[G * 32];  // BF16 residual, 32 chunks per node
+  __shared__ __attribute__((aligned(16))) double sTab[2][N][N];  // FP64 tables [f][p][y]
+  __shared__ float sT32[2][N][N];                            // FP32 tables [f][y][p]
+  __shared__ uint32_t sKey[4][G][8];
+  __shared__ __attribute__((aligned(16))) int sCand[G][8];
+  __shared__ __attribute__((aligned(16))) double sC[G][8];
+  __shared__ double sE[G], sEps[G];
+  __shared__ int sSt[G], sT[G], sKmax[G];
+  // records of the current 32-step window, flushed to global after it
+  constexpr int RW = 32;
+  __shared__ int sRecIdx[G][RW];
+  __shared__ double sRecCoef[G][RW];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int i = tid; i < nfam * K; i += 256) {
+    (&sTab[0][0][0])[i] = tab[i];
+    (&sT32[0][0][0])[i] = tabT32[i];
+  }
+  __syncthreads();
+  const double inv_n = 1.0 / N;
+  const int count = *count_ptr;
+
+  // Correlation geometry: wave w holds atoms [128 w, 128 w + 128); lane row
+  // 32 ma + rr is atom (fam, p = rr & 15, q = 8 (w & 1) + 2 ma + (rr >> 4)).
+  const int rr = lane & 31, hh = lane >> 5;
+  const int fam = min(w >> 1, nfam - 1);
+  const bool fam_ok = (w >> 1) < nfam;
+  float tq[4][8];
+#pragma unroll
+  for (int ma = 0; ma < 4; ++ma) {
+    const int q = 8 * (w & 1) + 2 * ma + (rr >> 4);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) tq[ma][j] = sT32[fam][8 * hh + j][q];
+  }
+  const float* tpcol = &sT32[fam][0][rr & 15];   // T32_f[p][y] at tpcol[y * N]
+  // Keys: the 23 bits of |c| that the batched path ranks on (exponent and 15
+  // mantissa bits), then 511 - atom: the same order as its 64-bit keys.
+  // 511 - atom of accumulator (ma, r) = lb - (32 ma + 8 (r >> 2) + (r & 3)).
+  const uint32_t lb = 511u - (uint32_t)(128 * w + 4 * hh);
+
+  // Update / gather geometry: thread = (node nl, part): 32 pixels, rows 2 part, 2 part + 1.
+  const int nl = tid >> 3, part = tid & 7;
+
+  for (int g0 = blockIdx.x * G; g0 < count; g0 += gridDim.x * G) {
+    // ---- gather (Algorithm 2: y = unravel(b)) and the first stop test ----
+    {
+      const int node = g0 + nl;
+      const bool valid = node < count;
+      const int nd = valid ? node : g0;
+      const JobDev& jb = jobs[lv.job[nd]];
+      const int bx = lv.x0[nd], by = lv.y0[nd];
+      double e = 0.0;
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy) {
+        const int y = 2 * part + dy;
+        const int64_t row = (int64_t)(by + y) * jb.row_stride + bx;
+        float f[N];
+#pragma unroll
+        for (int x = 0; x < N; ++x) {
+          const double v = jb.dtype == AQMP_F64 ? ((const double*)jb.img)[row + x]
+                                                : (double)((const float*)jb.img)[row + x];
+          f[x] = (float)v;
+          e += v * v;
+        }
+#pragma unroll
+        for (int x = 0; x < N; ++x) sR[nl][y * N + x] = valid ? f[x] : 0.f;
+#pragma unroll
+        for (int c2 = 0; c2 < 2; ++c2) {
+          p16_bf16x8 b;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) b[j] = (__bf16)(valid ? f[8 * c2 + j] : 0.f);
+          sB[p16_chunk(nl, 2 * y + c2)] = __builtin_bit_cast(uint4, b);
+        }
+      }
+      e += __shfl_xor(e, 1, 64);
+      e += __shfl_xor(e, 2, 64);
+      e += __shfl_xor(e, 4, 64);
+      if (part == 0) {
+        uint8_t st = ST_RUN;
+        if (!valid)
+          st = ST_SPARSE;
+        else if (e < jb.eps2[lg])
+          st = ST_ACC;
+        else if (jb.k[lg] <= 0)
+          st = ST_SPARSE;
+        sE[nl] = e;
+        sEps[nl] = jb.eps2[lg];
+        sKmax[nl] = jb.k[lg];
+        sT[nl] = 0;
+        sSt[nl] = st;
+      }
+    }
+    bool any = __syncthreads_or(part == 0 && sSt[nl] == ST_RUN);
+    int step = 0;   // MP steps made in this group (every running node makes one per step)
+
+    while (any) {
+      // ---- C: correlation (MFMA) ----
+      p16_f32x16 acc[4];
+#pragma unroll
+      for (int ma = 0; ma < 4; ++ma)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[ma][r] = 0.f;
+#pragma unroll
+      for (int kk = 0; kk < N; ++kk) {   // k-step kk = pixel row y
+        const p16_bf16x8 bf = __builtin_bit_cast(p16_bf16x8, sB[p16_chunk(rr, 2 * kk + hh)]);
+        const float tpk = tpcol[kk * N];
+#pragma unroll
+        for (int ma = 0; ma < 4; ++ma) {
+          p16_bf16x8 af;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) af[j] = (__bf16)(tpk * tq[ma][j]);
+          acc[ma] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bf, acc[ma], 0, 0, 0);
+        }
+      }
+      // ---- E: this wave's best 8 keys per node (node = rr) ----
+      {
+        uint32_t top[8];
+#pragma unroll
+        for (int gi = 0; gi < 8; ++gi) {
+          const int ma = gi >> 1;
+          uint32_t v[8];
+#pragma unroll
+          for (int e8 = 0; e8 < 8; ++e8) {
+            const int r = 8 * (gi & 1) + e8;
+            const uint32_t bits = __float_as_uint(acc[ma][r]);
+            v[e8] = ((bits & 0x7FFFFF00u) << 1) | (lb - (uint32_t)(32 * ma + 8 * (r >> 2) + (r & 3)));
+          }
+          p16_sort8(v);
+          if (gi == 0) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) top[j] = v[j];
+          } else {
+            p16_merge8(top, v);
+          }
+        }
+        uint32_t other[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) other[j] = __shfl_xor(top[j], 32, 64);
+        p16_merge8(top, other);
+        if (lane < 32) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) sKey[w][rr][j] = fam_ok ? top[j] : 0u;
+        }
+      }
+      __syncthreads();
+      // ---- M: the node's 8 candidates (wave 0: lane half hh merges waves 2 hh, 2 hh + 1) ----
+      if (w == 0) {
+        uint32_t top[8], v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          top[j] = sKey[2 * hh][rr][j];
+          v[j] = sKey[2 * hh + 1][rr][j];
+        }
+        p16_merge8(top, v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = __shfl_xor(top[j], 32, 64);
+        p16_merge8(top, v);
+        if (lane < 32) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const unsigned atom = 511u - (top[j] & 0x1FFu);
+            sCand[rr][j] = (top[j] != 0u && atom < (unsigned)n_atoms) ? (int)atom : -1;
+          }
+        }
+      }
+      __syncthreads();
+      // ---- S: FP64 re-score, thread = (node nl, candidate part) ----
+      {
+        const int atom = sCand[nl][part];
+        double c = 0.0;
+        if (sSt[nl] == ST_RUN && atom >= 0) {
+          const int f = atom / K, q = (atom % K) / N, p = atom % N;
+          const bool dc = (p == 0 && q == 0);
+          double tqx[N], tpy[N];
+          const double2* qrow = (const double2*)&sTab[f][q][0];
+          const double2* prow = (const double2*)&sTab[f][p][0];
+#pragma unroll
+          for (int i = 0; i < N / 2; ++i) {
+            const double2 u = qrow[i], v = prow[i];
+            tqx[2 * i] = dc ? 1.0 : u.x;
+            tqx[2 * i + 1] = dc ? 1.0 : u.y;
+            tpy[2 * i] = v.x;
+            tpy[2 * i + 1] = v.y;
+          }
+          const float4* rrow = (const float4*)&sR[nl][0];
+#pragma unroll 4
+          for (int y = 0; y < N; ++y) {
+            float rv[N];
+#pragma unroll
+            for (int i = 0; i < N / 4; ++i) {
+              const float4 t4 = rrow[y * (N / 4) + i];
+              rv[4 * i] = t4.x; rv[4 * i + 1] = t4.y; rv[4 * i + 2] = t4.z; rv[4 * i + 3] = t4.w;
+            }
+            double sum = 0.0;
+#pragma unroll
+            for (int x = 0; x < N; ++x) sum = fma((double)rv[x], tqx[x], sum);
+            c = dc ? c + sum : fma(tpy[y], sum, c);
+          }
+          if (dc) c *= inv_n;
+        }
+        sC[nl][part] = c;
+      }
+      __syncthreads();
+      // ---- A: arg-max, update, norm, record, stop test ----
+      {
+        const bool run = sSt[nl] == ST_RUN;
+        int cd[8];
+        double cv[8];
+        {
+          const int4* cp = (const int4*)&sCand[nl][0];
+          const double2* vp = (const double2*)&sC[nl][0];
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            const int4 t4 = cp[i];
+            cd[4 * i] = t4.x; cd[4 * i + 1] = t4.y; cd[4 * i + 2] = t4.z; cd[4 * i + 3] = t4.w;
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const double2 t2 = vp[i];
+            cv[2 * i] = t2.x; cv[2 * i + 1] = t2.y;
+          }
+        }
+        // arg-max |c| over the valid candidates, lowest atom on ties
+        int batom = -1;
+        double bmag = -1.0, bc = 0.0;
+#pragma unroll
+        for (int ci = 0; ci < 8; ++ci) {
+          const double m = fabs(cv[ci]);
+          const bool better = cd[ci] >= 0 && (batom < 0 || m > bmag || (m == bmag && cd[ci] < batom));
+          batom = better ? cd[ci] : batom;
+          bmag = better ? m : bmag;
+          bc = better ? cv[ci] : bc;
+        }
+        const bool zero = (batom < 0 || bmag == 0.0);
+        const int atom = zero ? 0 : batom;
+        const double coef = zero ? 0.0 : bc;
+        double e = 0.0;
+        if (run && !zero) {
+          const int f = atom / K, q = (atom % K) / N, p = atom % N;
+          const bool dc = (p == 0 && q == 0);
+          double tqx[N];
+          const double2* qrow = (const double2*)&sTab[f][q][0];
+#pragma unroll
+          for (int i = 0; i < N / 2; ++i) {
+            const double2 u = qrow[i];
+            tqx[2 * i] = u.x;
+            tqx[2 * i + 1] = u.y;
+          }
+          float rv[2][N];
+          float4* rrow = (float4*)&sR[nl][0];
+#pragma unroll
+          for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int i = 0; i < N / 4; ++i) {
+              const float4 t4 = rrow[(2 * part + dy) * (N / 4) + i];
+              rv[dy][4 * i] = t4.x; rv[dy][4 * i + 1] = t4.y; rv[dy][4 * i + 2] = t4.z; rv[dy][4 * i + 3] = t4.w;
+            }
+          double eh[2] = {0.0, 0.0};
+#pragma unroll
+          for (int dy = 0; dy < 2; ++dy) {
+            const int y = 2 * part + dy;
+            const double ty = sTab[f][p][y];
+            float rn[N];
+#pragma unroll
+            for (int x = 0; x < N; ++x) {
+              const double phi = dc ? inv_n : ty * tqx[x];
+              rn[x] = (float)fma(-coef, phi, (double)rv[dy][x]);
+              eh[dy] = fma((double)rn[x], (double)rn[x], eh[dy]);
+            }
+#pragma unroll
+            for (int i = 0; i < N / 4; ++i) rrow[y * (N / 4) + i] = make_float4(rn[4 * i], rn[4 * i + 1], rn[4 * i + 2], rn[4 * i + 3]);
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2) {
+              p16_bf16x8 b;
+#pragma unroll
+              for (int j = 0; j < 8; ++j) b[j] = (__bf16)rn[8 * c2 + j];
+              sB[p16_chunk(nl, 2 * y + c2)] = __builtin_bit_cast(uint4, b);
+            }
+          }
+          e = eh[0] + eh[1];
+        }
+        e += __shfl_xor(e, 1, 64);
+        e += __shfl_xor(e, 2, 64);
+        e += __shfl_xor(e, 4, 64);
+        bool still = false;
+        if (part == 0 && run) {
+          const int t = sT[nl];
+          if (zero) {
+            sSt[nl] = ST_ZERO;
+          } else {
+            sRecIdx[nl][t % RW] = atom;
+            sRecCoef[nl][t % RW] = coef;
+            uint8_t st = ST_RUN;
+            if (e < sEps[nl])
+              st = ST_ACC;
+            else if (t + 1 >= sKmax[nl])
+              st = ST_SPARSE;
+            sE[nl] = e;
+            sT[nl] = t + 1;
+            sSt[nl] = st;
+            still = st == ST_RUN;
+          }
+        }
+        any = __syncthreads_or(still);
+        // every RW steps (all running nodes share the step count) and at the
+        // end, the window's records go to global memory
+        ++step;
+        if (step % RW == 0 || !any) {
+          const int base = (step - 1) / RW * RW;
+          for (int i = tid; i < G * RW; i += 256) {
+            const int n2 = i / RW, j = i % RW, ts = base + j;
+            if (g0 + n2 < count && ts < sT[n2]) {
+              const size_t slot = (size_t)(g0 + n2) * lv.kmax + ts;
+              lv.rec_idx[slot] = sRecIdx[n2][j];
+              lv.rec_coef[slot] = sRecCoef[n2][j];
+            }
+          }
+          __syncthreads();
+        }
+      }
+    }
+    // ---- node state for the split test ----
+    if (tid < G && g0 + tid < count) {
+      lv.e[g0 + tid] = sE[tid];
+      lv.t[g0 + tid] = sT[tid];
+      lv.st[g0 + tid] = (uint8_t)sSt[tid];
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
+
+hipError_t launch_pursuit16_bf16(const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t n_atoms, int32_t nfam,
+                                 const double* tab, const float* tabT32, hipStream_t s) {
+  hipLaunchKernelGGL(k_pursuit16_bf16, dim3(512), dim3(256), 0, s, jobs, lv, count, 4, n_atoms, nfam, tab, tabT32);
+  return hipGetLastError();
+}
 
 hipError_t launch_mp_fused(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t lg, int32_t n_atoms,
                            const double* tab, hipStream_t s) {

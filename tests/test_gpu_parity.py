@@ -46,9 +46,9 @@ def _dev(img, dtype="f32"):
     return t.cuda()
 
 
-def _encode(A, dic, chans, params, jobs, prec, sched, dtype="f32"):
+def _encode(A, dic, chans, params, jobs, prec, sched, dtype="f32", stepwise=False):
     imgs = [_dev(c, dtype) for c in chans]
-    code = A.Code(dic, imgs, params, jobs, precision=prec, schedule=sched)
+    code = A.Code(dic, imgs, params, jobs, precision=prec, schedule=sched, stepwise=stepwise)
     return code, imgs
 
 
@@ -65,11 +65,14 @@ def _check(A, code, chans, params, jobs, prec, blocks_per_job=None):
     return rep
 
 
-@pytest.mark.parametrize("prec,sched", [(0, 0), (1, 1), (0, 1), (1, 0), (1, 2)])
-def test_c0_full_parity(A, dic, prec, sched):
+@pytest.mark.parametrize("prec,sched,stepwise", [(0, 0, False), (1, 1, False), (0, 1, False), (1, 0, False),
+                                                  (1, 2, False), (1, 1, True)])
+def test_c0_full_parity(A, dic, prec, sched, stepwise):
+    """The BF16 form runs its N = 16 level as one whole-level pursuit unless
+    stepwise is set; both must match the oracle."""
     w = workload("c0")
-    _say("c0", prec, sched)
-    code, imgs = _encode(A, dic, w["channels"], w["params"], w["jobs"], prec, sched)
+    _say("c0", prec, sched, stepwise)
+    code, imgs = _encode(A, dic, w["channels"], w["params"], w["jobs"], prec, sched, stepwise=stepwise)
     rep = _check(A, code, w["channels"], w["params"], w["jobs"], prec)
     _say(rep.summary())
     assert rep.ok(), rep.summary()
@@ -135,14 +138,15 @@ def test_mixed_jobs_small_sizes(A, dic, prec, sched):
 
 def test_corr_variants_bit_identical(A, dic):
     """Every BF16 correlation kernel variant sums the same products in the same
-    k order: the exported trees, atoms and coefficients are bit-identical."""
+    k order: the exported trees, atoms and coefficients are bit-identical
+    (stepwise, so that every level of 16 and up runs the variant kernels)."""
     w = workload("c1")
     img = w["channels"][0]
     ref = None
     for v in (1, 2, 3, 4, 5, 6):
         _say("variant", v)
         imgs = [_dev(img)]
-        code = A.Code(dic, imgs, w["params"], [(0, 0)], precision=1, schedule=1, corr_variant=v)
+        code = A.Code(dic, imgs, w["params"], [(0, 0)], precision=1, schedule=1, corr_variant=v, stepwise=True)
         e = code.export_nodes()
         cur = (e.leaves.tobytes(), e.atom_idx.tobytes(), e.coef.tobytes())
         if ref is None:
