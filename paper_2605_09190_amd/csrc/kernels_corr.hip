@@ -712,40 +712,50 @@ __global__ __launch_bounds__(256, 1) void k_corr_bf16_pipe(const uint16_t* __res
 }
 
 // ---------------------------------------------------------------------------
-// BF16, N = 64: atoms generated in registers (no dictionary traffic).
+// BF16, N = 32 and 64: atoms generated in registers (no dictionary traffic).
 //
 // Atom (f, p, q) is the outer product of rows p and q of the 1D table T_f, so
 // its BF16 value at pixel (y, x) is RNE(fl32(T32_f[p][y] * T32_f[q][x])), the
-// canonical BF16 dictionary (T32 = the FP64 table rounded to FP32).  A lane's
-// MFMA rows keep the same (p, q) over the whole K loop: it holds the T32_f[q]
-// values it needs for its two q rows in registers and reads T32_f[p][y] from
-// LDS once per stage (one stage = one pixel row y), then builds each 8-value A
-// fragment with 8 multiplies and 4 packed conversions while the MFMAs of the
-// previous k-step run.  Only the residual tile goes through LDS (direct-to-LDS
-// loads, three-stage ring as in the pipelined kernel), so a CU fetches 16 KB
-// per stage instead of 48 KB.  The DC atoms come out as exactly 1/N because
-// T32_f[0][.] = 1/8 exactly at N = 64.  Same tile, k order and epilogue as the
-// other forms: the keys are bit-identical.
+// canonical BF16 dictionary (T32 = the FP64 table rounded to FP32; for the
+// constant atom the product rounds to exactly 1/N in BF16).  A lane's MFMA
+// rows keep the same (p, q) over the whole K loop: it holds the T32_f[q][x]
+// values it needs in registers and reads T32_f[p][y] from LDS once per
+// stage, then builds each 8-value A fragment with 8 multiplies and 4 packed
+// conversions while the MFMAs of the previous k-step run.  A stage is 64
+// pixels: one row at N = 64, two rows at N = 32.  Only the residual tile goes
+// through LDS (direct-to-LDS buffer loads, four-buffer ring, the barrier
+// that publishes stage s + 1 inside the last k-step of stage s).  The node
+// tile is 32 MB nodes, MB picked per launch from the node count so that the
+// tiles fill the workgroups in as few rounds as possible.  Same k order and
+// epilogue as the other forms: the keys are bit-identical.
 // ---------------------------------------------------------------------------
-constexpr int kGenN = 64;
-constexpr int kGenRing = 4;                 // residual stages in LDS (prefetch distance 3)
-constexpr int kGenMBMin = 3, kGenMBMax = 7;  // node tile = 32 MB nodes
+constexpr int kGenRing = 4;      // residual stages in LDS (prefetch distance 3)
+constexpr int kGenMBMax = 7;     // node tile = 32 MB nodes, MB <= 7
 
-// Geometry for a node tile of 32 MB nodes: tile 256 atoms x 32 MB nodes,
-// BK = 64 (one pixel row), the four waves side by side along the atoms
-// (64 atoms x 32 MB nodes each), so a wave makes only the A fragments of its
-// own rows: 2 per k-step, shared by MB MFMAs.
-template <int MB_>
+// Geometry for block size N and a node tile of 32 MB nodes: tile 256 atoms x
+// 32 MB nodes, BK = 64, the four waves side by side along the atoms (64
+// atoms x 32 MB nodes each), so a wave makes only the A fragments of its own
+// rows: 2 per k-step, shared by MB MFMAs.
+template <int N_, int MB_>
 struct GenGeo {
+  static constexpr int N = N_, K = N * N;
   static constexpr int BA = 256, BB = 32 * MB_, BK = 64, WA = 4, WB = 1;
   static constexpr int WTA = BA / WA, WTB = BB / WB, MA = WTA / 32, MB = WTB / 32;
   static constexpr int ROWB = BK * 2, CPR = ROWB / 16, RPB = 1024 / ROWB;
   static constexpr int B_BYTES = BB * ROWB;
   static constexpr int B_INS = BB / RPB / 4;   // = MB loads per wave per stage
+  static constexpr int RPS = BK / N;           // pixel rows per stage
+  static constexpr int XPL = N >= 64 ? 32 : N / 2;   // distinct x per lane
+  static constexpr bool QSHARED = N >= 64;     // both of a lane's rows share q
+  static constexpr int NQ = QSHARED ? 1 : MA;
+  static_assert(N == 32 || N == 64, "generated atoms for N = 32, 64");
   using C = Cfg<BA, BB, BK, WA, WB>;
   __device__ static int swz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
+  // x index (into the lane's XPL values) of element j of k-step KK
+  __device__ static constexpr int xi(int kk) { return ((kk * 16) % N) / 16 * 8; }
+  __device__ static constexpr int row(int kk) { return (kk * 16) / N; }   // row within the stage
 };
-constexpr int kGenBufBytes = GenGeo<kGenMBMax>::B_BYTES;   // one ring buffer (28 KB)
+constexpr int kGenBufBytes = 32 * kGenMBMax * 128;   // one ring buffer (28 KB)
 
 template <class G>
 struct GenFrag {
@@ -761,14 +771,15 @@ __device__ inline void gen_read_b(GenFrag<G>& f, const char* sb, const int (&off
   __builtin_amdgcn_sched_barrier(0);   // the reads go out a whole k-step before their MFMAs
 }
 
-// A fragments of k-step KK (x = 16 KK + 8 h + j) for the row factors tp.
+// A fragments of k-step KK for the row factors tp[ma][row in stage].
 template <class G, int KK, int P>
-__device__ inline void gen_make_a(GenFrag<G>& f, const float (&tp)[G::MA], const float (&tq)[32]) {
+__device__ inline void gen_make_a(GenFrag<G>& f, const float (&tp)[G::MA][G::RPS], const float (&tq)[G::NQ][G::XPL]) {
 #pragma unroll
   for (int ma = 0; ma < G::MA; ++ma) {
     bf16x8 v;
+    const int qi = G::QSHARED ? 0 : ma;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = (__bf16)(tp[ma] * tq[KK * 8 + j]);
+    for (int j = 0; j < 8; ++j) v[j] = (__bf16)(tp[ma][G::row(KK)] * tq[qi][G::xi(KK) + j]);
     f.a[P][ma] = v;
   }
 }
@@ -784,7 +795,7 @@ __device__ inline void gen_mfma(f32x16 (&acc)[G::MA][G::MB], const GenFrag<G>& f
 }
 
 // Residual rows of stage s: loads [first, first + cnt) of the wave's B_INS.
-template <class G, int K>
+template <class G>
 __device__ inline void gen_dma(const DmaPtrs<G>& p, char* sb, int s, int first, int cnt) {
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int kofs = s * G::BK * 2;
@@ -794,32 +805,37 @@ __device__ inline void gen_dma(const DmaPtrs<G>& p, char* sb, int s, int first, 
       lds_dma16(p.b_base, (int)0xFFFFFFFFu, sb + (w * G::B_INS + i) * 1024, (int)p.b_off[i], kofs);
 }
 
-// One stage (pixel row y = s) computed from cb.  DMA: the loads of stage
-// s_dma go to db, spread over the first two k-steps.  NEXT: stage s + 1
-// follows in nb; its loads are complete once at most VMN of this wave's loads
-// are outstanding (loads complete in order), and its first fragments are made
-// here, under the last MFMAs of stage s.
-template <class G, int K, bool DMA, bool NEXT, int VMN>
+// Row factors T32_f[p_ma][y] of the rows of stage s.
+template <class G>
+__device__ inline void gen_row_factors(float (&tp)[G::MA][G::RPS], const float* sTf, const int (&pl)[G::MA], int s) {
+#pragma unroll
+  for (int ma = 0; ma < G::MA; ++ma)
+#pragma unroll
+    for (int r = 0; r < G::RPS; ++r) tp[ma][r] = sTf[(s * G::RPS + r) * G::N + pl[ma]];
+}
+
+// One stage s computed from cb.  DMA: the loads of stage s_dma go to db,
+// spread over the first two k-steps.  NEXT: stage s + 1 follows in nb; its
+// loads are complete once at most VMN of this wave's loads are outstanding
+// (loads complete in order), and its first fragments are made here, under
+// the last MFMAs of stage s.
+template <class G, bool DMA, bool NEXT, int VMN>
 __device__ inline void gen_stage(f32x16 (&acc)[G::MA][G::MB], GenFrag<G>& f, const DmaPtrs<G>& p, const float* sTf,
-                                 const float (&tq)[32], float (&tp)[G::MA], const char* cb, const char* nb, char* db,
-                                 int s, int s_dma, const int (&off)[4]) {
+                                 const int (&pl)[G::MA], const float (&tq)[G::NQ][G::XPL], float (&tp)[G::MA][G::RPS],
+                                 const char* cb, const char* nb, char* db, int s, int s_dma, const int (&off)[4]) {
   constexpr int H1 = (G::B_INS + 1) / 2;
-  const int rr = threadIdx.x & 31;
   gen_read_b<G, 1, 1>(f, cb, off);
   gen_make_a<G, 1, 1>(f, tp, tq);
-  if constexpr (DMA) gen_dma<G, K>(p, db, s_dma, 0, H1);
+  if constexpr (DMA) gen_dma<G>(p, db, s_dma, 0, H1);
   gen_mfma<G, 0>(acc, f);
   gen_read_b<G, 2, 0>(f, cb, off);
   gen_make_a<G, 2, 0>(f, tp, tq);
-  if constexpr (DMA) gen_dma<G, K>(p, db, s_dma, H1, G::B_INS - H1);
+  if constexpr (DMA) gen_dma<G>(p, db, s_dma, H1, G::B_INS - H1);
   gen_mfma<G, 1>(acc, f);
   gen_read_b<G, 3, 1>(f, cb, off);
   gen_make_a<G, 3, 1>(f, tp, tq);
-  float tpn[G::MA];
-  if constexpr (NEXT) {
-#pragma unroll
-    for (int ma = 0; ma < G::MA; ++ma) tpn[ma] = sTf[(s + 1) * kGenN + 32 * ma + rr];
-  }
+  float tpn[G::MA][G::RPS];
+  if constexpr (NEXT) gen_row_factors<G>(tpn, sTf, pl, s + 1);
   gen_mfma<G, 2>(acc, f);
   if constexpr (NEXT) {
     // every wave is done reading cb before any wave passes, so loads issued
@@ -828,7 +844,9 @@ __device__ inline void gen_stage(f32x16 (&acc)[G::MA][G::MB], GenFrag<G>& f, con
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int ma = 0; ma < G::MA; ++ma) tp[ma] = tpn[ma];
+    for (int ma = 0; ma < G::MA; ++ma)
+#pragma unroll
+      for (int r = 0; r < G::RPS; ++r) tp[ma][r] = tpn[ma][r];
     gen_read_b<G, 0, 0>(f, nb, off);
     gen_make_a<G, 0, 0>(f, tp, tq);
   }
@@ -853,45 +871,53 @@ struct GenRing {
   }
 };
 
+template <class G>
+struct GenLane {
+  const float* sTf;
+  int pl[G::MA];
+  float tq[G::NQ][G::XPL];
+};
+
 // Stages S .. NST - 1 with every decision at compile time.
-template <class G, int K, int NST, int S>
-__device__ inline void gen_tail(f32x16 (&acc)[G::MA][G::MB], GenFrag<G>& f, const DmaPtrs<G>& p, const float* sTf,
-                                const GenRing& rg, const float (&tq)[32], float (&tp)[G::MA], const int (&off)[4]) {
+template <class G, int NST, int S>
+__device__ inline void gen_tail(f32x16 (&acc)[G::MA][G::MB], GenFrag<G>& f, const DmaPtrs<G>& p,
+                                const GenLane<G>& ln, const GenRing& rg, float (&tp)[G::MA][G::RPS],
+                                const int (&off)[4]) {
   if constexpr (S < NST) {
     constexpr int NB = kGenRing;
     constexpr bool DMA = S + NB - 1 < NST;
     constexpr bool NEXT = S + 1 < NST;
     constexpr int AHEAD = (NST - 2 - S) < (NB - 2) ? (NST - 2 - S) : (NB - 2);
     constexpr int VMN = NEXT ? G::B_INS * (AHEAD > 0 ? AHEAD : 0) : 0;
-    gen_stage<G, K, DMA, NEXT, VMN>(acc, f, p, sTf, tq, tp, rg.template buf<S % NB>(),
-                                    rg.template buf<(S + 1) % NB>(), rg.template buf<(S + NB - 1) % NB>(), S,
-                                    S + NB - 1, off);
-    gen_tail<G, K, NST, S + 1>(acc, f, p, sTf, rg, tq, tp, off);
+    gen_stage<G, DMA, NEXT, VMN>(acc, f, p, ln.sTf, ln.pl, ln.tq, tp, rg.template buf<S % NB>(),
+                                 rg.template buf<(S + 1) % NB>(), rg.template buf<(S + NB - 1) % NB>(), S, S + NB - 1,
+                                 off);
+    gen_tail<G, NST, S + 1>(acc, f, p, ln, rg, tp, off);
   }
 }
 
 // NB consecutive steady-state stages s0 + I (s0 a multiple of NB).
-template <class G, int K, int I>
-__device__ inline void gen_trip(f32x16 (&acc)[G::MA][G::MB], GenFrag<G>& f, const DmaPtrs<G>& p, const float* sTf,
-                                const GenRing& rg, const float (&tq)[32], float (&tp)[G::MA], const int (&off)[4],
-                                int s0) {
+template <class G, int I>
+__device__ inline void gen_trip(f32x16 (&acc)[G::MA][G::MB], GenFrag<G>& f, const DmaPtrs<G>& p,
+                                const GenLane<G>& ln, const GenRing& rg, float (&tp)[G::MA][G::RPS],
+                                const int (&off)[4], int s0) {
   if constexpr (I < kGenRing) {
     constexpr int NB = kGenRing;
-    gen_stage<G, K, true, true, G::B_INS * (NB - 2)>(acc, f, p, sTf, tq, tp, rg.template buf<I>(),
-                                                      rg.template buf<(I + 1) % NB>(),
-                                                      rg.template buf<(I + NB - 1) % NB>(), s0 + I, s0 + I + NB - 1,
-                                                      off);
-    gen_trip<G, K, I + 1>(acc, f, p, sTf, rg, tq, tp, off, s0);
+    gen_stage<G, true, true, G::B_INS * (NB - 2)>(acc, f, p, ln.sTf, ln.pl, ln.tq, tp, rg.template buf<I>(),
+                                                   rg.template buf<(I + 1) % NB>(),
+                                                   rg.template buf<(I + NB - 1) % NB>(), s0 + I, s0 + I + NB - 1,
+                                                   off);
+    gen_trip<G, I + 1>(acc, f, p, ln, rg, tp, off, s0);
   }
 }
 
 // Every tile of one launch with node tiles of 32 MB nodes.
-template <int MB>
+template <int N, int MB>
 __device__ void gen_tiles(const uint16_t* __restrict__ X, const int32_t* __restrict__ act, int count,
                           unsigned long long* __restrict__ keys, int n_atom_tiles, int nfam, const float* sT,
                           const GenRing& rg) {
-  using G = GenGeo<MB>;
-  constexpr int N = kGenN, K = N * N, NST = K / G::BK, NB = kGenRing;
+  using G = GenGeo<N, MB>;
+  constexpr int K = G::K, NST = K / G::BK, NB = kGenRing;
   static_assert(NST >= NB, "ring shorter than the K loop");
   static_assert(G::B_BYTES <= kGenBufBytes, "stage fits a ring buffer");
   static_assert(G::WA * G::BB * kTopR * 4 <= kGenBufBytes, "epilogue scratch fits one ring buffer");
@@ -922,19 +948,27 @@ __device__ void gen_tiles(const uint16_t* __restrict__ X, const int32_t* __restr
       const int pos = min(b0 + row, count - 1);
       p.b_off[i] = (uint32_t)(((size_t)act[pos] * K + gc * 8) * 2);
     }
-    // Rows of this lane: atom a0 + 64 wa + 32 ma + rr, i.e. family fam,
-    // q = qb + wa, p = 32 ma + rr.
+    // Rows of this lane: atom a0 + 64 wa + 32 ma + rr of family fam, i.e.
+    // q = qb + (64 wa + 32 ma + rr) / N, p = (64 wa + 32 ma + rr) % N.
+    GenLane<G> ln;
     const int fam = min(a0 / K, nfam - 1);
     const int qb = (a0 % K) / N;
-    const float* sTf = sT + fam * K;
-    float tq[32];
+    ln.sTf = sT + fam * K;
+    int ql[G::MA];
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
+    for (int ma = 0; ma < G::MA; ++ma) {
+      const int ri = 64 * wa + 32 * ma + rr;
+      ql[ma] = qb + ri / N;
+      ln.pl[ma] = ri % N;
+    }
 #pragma unroll
-      for (int e = 0; e < 8; ++e) tq[kk * 8 + e] = sTf[(kk * 16 + 8 * hh + e) * N + qb + wa];
-    float tp[G::MA];
+    for (int qi = 0; qi < G::NQ; ++qi)
 #pragma unroll
-    for (int ma = 0; ma < G::MA; ++ma) tp[ma] = sTf[32 * ma + rr];
+      for (int kk = 0; kk < (G::XPL / 8); ++kk)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) ln.tq[qi][kk * 8 + e] = ln.sTf[(kk * 16 + 8 * hh + e) * N + ql[qi]];
+    float tp[G::MA][G::RPS];
+    gen_row_factors<G>(tp, ln.sTf, ln.pl, 0);
     f32x16 acc[G::MA][G::MB];
 #pragma unroll
     for (int ma = 0; ma < G::MA; ++ma)
@@ -945,17 +979,17 @@ __device__ void gen_tiles(const uint16_t* __restrict__ X, const int32_t* __restr
     GenFrag<G> f;
 
     __syncthreads();   // previous tile's epilogue is done with sK (= buffer 0)
-    gen_dma<G, K>(p, rg.template buf<0>(), 0, 0, G::B_INS);
-    gen_dma<G, K>(p, rg.template buf<1>(), 1, 0, G::B_INS);
-    gen_dma<G, K>(p, rg.template buf<2>(), 2, 0, G::B_INS);
+    gen_dma<G>(p, rg.template buf<0>(), 0, 0, G::B_INS);
+    gen_dma<G>(p, rg.template buf<1>(), 1, 0, G::B_INS);
+    gen_dma<G>(p, rg.template buf<2>(), 2, 0, G::B_INS);
     AQMP_WAIT_VM(G::B_INS * (NB - 2));
     __builtin_amdgcn_s_barrier();
     gen_read_b<G, 0, 0>(f, rg.template buf<0>(), off);
-    gen_make_a<G, 0, 0>(f, tp, tq);
+    gen_make_a<G, 0, 0>(f, tp, ln.tq);
     constexpr int FULL = NST - (NB - 1);      // stages that issue a load
     constexpr int TRIPS = FULL / NB;
-    for (int t = 0; t < TRIPS; ++t) gen_trip<G, K, 0>(acc, f, p, sTf, rg, tq, tp, off, t * NB);
-    gen_tail<G, K, NST, TRIPS * NB>(acc, f, p, sTf, rg, tq, tp, off);
+    for (int t = 0; t < TRIPS; ++t) gen_trip<G, 0>(acc, f, p, ln, rg, tp, off, t * NB);
+    gen_tail<G, NST, TRIPS * NB>(acc, f, p, ln, rg, tp, off);
     __syncthreads();   // all waves done reading the ring before sK reuses buffer 0
     epilogue<typename G::C>(acc, sK, a0, a_tile, n_atom_tiles, b0, count, keys);
   }
@@ -964,9 +998,9 @@ __device__ void gen_tiles(const uint16_t* __restrict__ X, const int32_t* __restr
 // Node-tile width for this launch: the fewest 32-node block-rounds over the
 // workgroups (rounds x MB), ties to the wider tile.  Every workgroup computes
 // the same value from the count.
-__device__ inline int gen_pick_mb(int count, int n_atom_tiles, int wgs) {
+__device__ inline int gen_pick_mb(int count, int n_atom_tiles, int wgs, int mb_min) {
   int best = kGenMBMax, best_cost = 0x7fffffff;
-  for (int mb = kGenMBMax; mb >= kGenMBMin; --mb) {
+  for (int mb = kGenMBMax; mb >= mb_min; --mb) {
     const int tiles = n_atom_tiles * ((count + 32 * mb - 1) / (32 * mb));
     const int cost = ((tiles + wgs - 1) / wgs) * mb;
     if (cost < best_cost) {
@@ -983,7 +1017,6 @@ __global__ __launch_bounds__(256, 1) void k_corr_bf16_gen(const float* __restric
                                                           const int32_t* __restrict__ act,
                                                           const int32_t* __restrict__ act_count,
                                                           unsigned long long* __restrict__ keys, int n_atom_tiles) {
-  static_assert(N == kGenN, "generated atoms: one stage is one pixel row of 64");
   constexpr int K = N * N;
   __shared__ __attribute__((aligned(1024))) char sR0[kGenBufBytes];
   __shared__ __attribute__((aligned(1024))) char sR1[kGenBufBytes];
@@ -996,12 +1029,24 @@ __global__ __launch_bounds__(256, 1) void k_corr_bf16_gen(const float* __restric
   const int count = *act_count;
   if (count <= 0) return;
   const GenRing rg{sR0, sR1, sR2, sR3};
-  switch (gen_pick_mb(count, n_atom_tiles, gridDim.x)) {
-    case 3: gen_tiles<3>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
-    case 4: gen_tiles<4>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
-    case 5: gen_tiles<5>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
-    case 6: gen_tiles<6>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
-    default: gen_tiles<7>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
+  if constexpr (N == 64) {
+    switch (gen_pick_mb(count, n_atom_tiles, gridDim.x, 3)) {
+      case 3: gen_tiles<N, 3>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
+      case 4: gen_tiles<N, 4>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
+      case 5: gen_tiles<N, 5>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
+      case 6: gen_tiles<N, 6>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
+      default: gen_tiles<N, 7>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
+    }
+  } else {
+    switch (gen_pick_mb(count, n_atom_tiles, gridDim.x, 1)) {
+      case 1: gen_tiles<N, 1>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
+      case 2: gen_tiles<N, 2>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
+      case 3: gen_tiles<N, 3>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
+      case 4: gen_tiles<N, 4>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
+      case 5: gen_tiles<N, 5>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
+      case 6: gen_tiles<N, 6>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
+      default: gen_tiles<N, 7>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
+    }
   }
 }
 
@@ -1124,10 +1169,10 @@ using CfgMidF = Cfg<128, 128, 32, 2, 2>;    // N = 8, FP32
 using CfgSmallF = Cfg<32, 256, 16, 1, 4>;   // N = 4, FP32
 
 constexpr int kCorrGrid = 256;   // one persistent workgroup per CU
-// Default BF16 kernel per block size (measured): generated atoms at N = 64,
-// the pipelined direct-to-LDS form at N = 32, two workgroups per CU at N = 16
+// Default BF16 kernel per block size (measured): generated atoms at N = 32
+// and 64; two workgroups per CU at N = 16 (used by the step-by-step path),
 // where K (four stages) is too short for one workgroup's pipeline fill.
-constexpr int default_variant(int n) { return n >= 64 ? 6 : (n >= 32 ? 5 : 2); }
+constexpr int default_variant(int n) { return n >= 32 ? 6 : 2; }
 
 }  // namespace
 
@@ -1161,9 +1206,9 @@ static void launch_corr_n(int precision, int variant, const void* atoms, const S
       if (variant == 1)
         hipLaunchKernelGGL((k_corr_bf16_dma<N, 64, 1>), dim3(kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms,
                            a.r16, a.act, a.act_count, a.keys, nat);
-      else if (variant == 6 && N == kGenN)
-        hipLaunchKernelGGL((k_corr_bf16_gen<(N == kGenN ? N : kGenN)>), dim3(kCorrGrid), dim3(256), 0, s,
-                           a.tabT32, a.nfam, a.r16, a.act, a.act_count, a.keys, nat);
+      else if (variant == 6 && N >= 32)
+        hipLaunchKernelGGL((k_corr_bf16_gen<(N >= 32 ? N : 32)>), dim3(kCorrGrid), dim3(256), 0, s, a.tabT32,
+                           a.nfam, a.r16, a.act, a.act_count, a.keys, nat);
       else if (variant == 5)
         hipLaunchKernelGGL((k_corr_bf16_pipe<N, 64>), dim3(kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms, a.r16,
                            a.act, a.act_count, a.keys, nat);
@@ -1201,7 +1246,7 @@ const char* corr_kernel_name(int n, int precision, int variant) {
   if (variant == 1) return v1[li];
   if (variant == 2) return v2[li];
   if (variant == 5) return v5[li];
-  if (variant == 6) return n == kGenN ? "k_corr_bf16_gen<64>" : v3[li];
+  if (variant == 6) return n == 64 ? "k_corr_bf16_gen<64>" : (n == 32 ? "k_corr_bf16_gen<32>" : v3[li]);
   return v3[li];
 }
 

@@ -97,7 +97,8 @@ def test_corr_kernel_names():
     """The kernel-name query is host-only and reflects the per-size defaults."""
     from paper_2605_09190_amd import aqmp as A
     assert A.corr_kernel(64, A.PREC_BF16) == "k_corr_bf16_gen<64>"
-    assert A.corr_kernel(32, A.PREC_BF16) == "k_corr_bf16_pipe<32,64>"
+    assert A.corr_kernel(32, A.PREC_BF16) == "k_corr_bf16_gen<32>"
+    assert A.corr_kernel(32, A.PREC_BF16, 5) == "k_corr_bf16_pipe<32,64>"
     assert A.corr_kernel(16, A.PREC_BF16) == "k_corr_bf16_dma<16,32,2>"
     assert A.corr_kernel(64, A.PREC_BF16, 5) == "k_corr_bf16_pipe<64,64>"
     assert A.corr_kernel(64, A.PREC_FP32) == "k_corr_f32<64>"
