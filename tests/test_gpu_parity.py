@@ -136,6 +136,27 @@ def test_mixed_jobs_small_sizes(A, dic, prec, sched):
     assert rep.ok(), rep.summary()
 
 
+@pytest.mark.parametrize("fam", ["dct", "haar"])
+def test_single_family_dictionary_bf16(A, fam):
+    """One-family dictionaries (M = N^2) through the BF16 form: generated-atom
+    correlation at N = 32, 64 and the whole-level pursuit at N = 16 must see
+    only the atoms that exist."""
+    F = O.DCT if fam == "dct" else O.HAAR
+    d = A.Dictionary(8, 64, families=(A.DCT if fam == "dct" else A.HAAR))
+    img = piecewise_image(128, 128, seed=21)
+    p = dict(tol=0.02, max_atoms=16, n_min=8, n_max=64)
+    _say("single family", fam)
+    imgs = [_dev(img)]
+    code = A.Code(d, imgs, [p], [(0, 0)], precision=1, schedule=1)
+    exp = code.export_nodes()
+    onodes = O.encode_channel(img, O.Params.from_dict(dict(p, families=F)))
+    rep = PU.compare_job(img, onodes, PU.gpu_nodes_by_key(exp, 0), COEF_TOL[1], 64, families=F)
+    _say(rep.summary())
+    code.free()
+    d.free()
+    assert rep.ok(), rep.summary()
+
+
 def test_corr_variants_bit_identical(A, dic):
     """Every BF16 correlation kernel variant sums the same products in the same
     k order: the exported trees, atoms and coefficients are bit-identical
