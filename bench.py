@@ -26,6 +26,27 @@ METRIC = "AQMP encode Mpixel/s (batched BF16 vs plain FP32) at equal PSNR; MP it
 PEAK_BF16_TFLOPS = 2500.0     # MI355X dense BF16 MFMA
 PEAK_FP32_TFLOPS = 157.3      # MI355X dense FP32 MFMA
 
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs, scaled by a copy-kernel calibration
+# (profiles/traffic_k_corr_bf16_gen64_2048x2048x3_ycbcr.md); valid only for
+# the kernel source they were taken on.
+TRAFFIC = {
+    "k_corr_bf16_gen<64>": dict(bytes_per_launch=15.69e6, fetch=13.28e6, write=2.41e6,
+                                src="paper_2605_09190_amd/csrc/kernels_corr.hip",
+                                sha256="b3775b1b9612aaa553e2368099a2a8d2248cdbfc322bcf852338f0733eb8661e"),
+}
+
+
+def measured_traffic(kernel):
+    import hashlib
+    t = TRAFFIC.get(kernel)
+    if t is None:
+        return None
+    with open(os.path.join(ROOT, t["src"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
+            return None
+    return t["bytes_per_launch"]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -82,9 +103,10 @@ def roofline(stats, timing, precision, kernel_name=None):
                                       level_ms=round(timing["level_ms"][l], 3),
                                       launches=int(timing["steps"][l]),
                                       avg_corr_us=round(1e3 * timing["corr_ms"][l] / max(1, timing["steps"][l]), 2))
+    kname = kernel_name(n) if kernel_name else f"correlation<N={n}>"
     return dict(bound="mfma", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
-                frac=round(achieved / peak, 4), traffic=None,
-                kernel=kernel_name(n) if kernel_name else f"correlation<N={n}>",
+                frac=round(achieved / peak, 4), traffic=measured_traffic(kname), traffic_unit="bytes per launch",
+                kernel=kname,
                 avg_launch_us=round(1e3 * ms / max(1, steps), 2), launches=int(steps),
                 flops_per_unit=4 * n ** 4, units=int(stats["iters_level"][lg]), per_level=per_level)
 
@@ -153,6 +175,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--corr-variant", type=int, default=0, help="BF16 correlation kernel variant (0 = default)")
     ap.add_argument("--schedule", default="batched", choices=["batched", "concurrent"])
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy 5 times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the encoder is a single-GPU path (--gpus {args.gpus} "
@@ -160,6 +184,18 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        # a plain copy of known size: what the memory counters read for it
+        # scales their per-kernel readings to bytes
+        n = 256 << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read_per_copy": n, "bytes_written_per_copy": n, "copies": 5}))
+        return
     from paper_2605_09190_amd import aqmp as A
     from workloads import workload
 
