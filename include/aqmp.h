@@ -110,6 +110,8 @@ typedef struct {
 
 enum { AQMP_OPT_TIMING = 1, AQMP_OPT_STEPWISE = 2 };   /* aqmp_options.flags */
 
+enum { AQMP_SOLVER_DENSE = 0, AQMP_SOLVER_GRAM = 1 };   /* aqmp_options.solver */
+
 typedef struct {
   int32_t precision;   /* AQMP_PREC_FP32: FP32 MFMA correlation;
                           AQMP_PREC_BF16: BF16 MFMA, FP32 accumulate.
@@ -136,7 +138,19 @@ typedef struct {
   int32_t corr_variant;  /* tuning: 0 = library default; 1..6 force one
                             family of BF16 correlation kernels (results
                             are identical, only speed differs) */
-  int32_t reserved[4];
+  int32_t solver;      /* AQMP_SOLVER_DENSE: every MP step correlates the
+                          residual with all M atoms (Section 2.2, eq. (1)),
+                          in the precision above.
+                          AQMP_SOLVER_GRAM: the same MP, computed exactly
+                          through the dictionary's structure: the
+                          correlations of y as separable products
+                          T_f Y T_f^T, then per step c <- c - c_i G[:, i]
+                          and ||r||^2 <- ||r||^2 - c_i^2, all in FP64
+                          (precision and corr_variant do not apply; levels
+                          with N <= 8 run the dense FP64 pursuit as in the
+                          dense solver).  A labelled variant: the paper
+                          states the dense correlation. */
+  int32_t reserved[3];
 } aqmp_options;
 
 /* A leaf of the quadtree (or, from aqmp_code_export_nodes, any visited

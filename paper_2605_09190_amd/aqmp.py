@@ -30,6 +30,7 @@ PREC_FP32, PREC_BF16 = 0, 1
 SCHED_PLAIN, SCHED_BATCHED, SCHED_CONCURRENT = 0, 1, 2
 OPT_TIMING = 1
 OPT_STEPWISE = 2
+SOLVER_DENSE, SOLVER_GRAM = 0, 1
 MAX_ATOMS = 256
 CANDIDATES = 8
 
@@ -59,7 +60,8 @@ class Job(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("schedule", C.c_int32), ("flags", C.c_int32),
-                ("corr_variant", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("corr_variant", C.c_int32), ("solver", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class Leaf(C.Structure):
@@ -217,7 +219,7 @@ class Code:
 
     def __init__(self, dic: Dictionary, images, params, jobs, precision: int = PREC_FP32,
                  schedule: int = SCHED_PLAIN, stream=None, timing: bool = False, corr_variant: int = 0,
-                 stepwise: bool = False):
+                 stepwise: bool = False, solver: int = 0):
         self.dic = dic
         self._keep = list(images)
         imgs = (Image * len(images))(*[make_image(t) for t in images])
@@ -227,6 +229,7 @@ class Code:
         opt.precision, opt.schedule = int(precision), int(schedule)
         opt.flags = (OPT_TIMING if timing else 0) | (OPT_STEPWISE if stepwise else 0)
         opt.corr_variant = int(corr_variant)
+        opt.solver = int(solver)
         h = C.c_void_p()
         _check(lib.aqmp_encode(dic.h, imgs, len(images), prms, len(params), jbs, len(jobs), C.byref(opt),
                                _stream_handle(stream), C.byref(h)))

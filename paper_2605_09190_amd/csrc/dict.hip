@@ -76,6 +76,7 @@ static uint16_t atom_bf16(const aqmp_dict::Level& L, int a, int y, int x) {
 static void free_level(aqmp_dict::Level& L) {
   if (L.d_tab) dev_free(L.d_tab, sizeof(double) * L.h_tab.size());
   if (L.d_tabT32) dev_free(L.d_tabT32, sizeof(float) * L.h_tab.size());
+  if (L.d_xg) dev_free(L.d_xg, sizeof(double) * L.k);
   if (L.d_f32) dev_free(L.d_f32, sizeof(float) * (size_t)L.m_pad * L.k);
   if (L.d_bf16) dev_free(L.d_bf16, sizeof(uint16_t) * (size_t)L.m_pad * L.k);
   L = aqmp_dict::Level();
@@ -126,8 +127,23 @@ int dictionary_build(int n_min, int n_max, uint32_t families, hipStream_t s, aqm
       for (int y = 0; y < n; ++y)
         for (int pp = 0; pp < n; ++pp)
           tT[(size_t)fm * L.k + y * n + pp] = (float)L.h_tab[(size_t)fm * L.k + pp * n + y];
+    // Cross-family table of the Gram form: X[p][p'] = <T_0[p], T_1[p']>.
+    // Both constant rows equal 1/sqrt(N) and every other row of either table
+    // sums to zero, so row and column 0 are set exactly.
+    std::vector<double> xg;
+    if (d->nfam == 2) {
+      xg.assign(L.k, 0.0);
+      for (int p0 = 0; p0 < n; ++p0)
+        for (int p1 = 0; p1 < n; ++p1) {
+          long double acc = 0.0L;
+          for (int y = 0; y < n; ++y)
+            acc += (long double)L.h_tab[(size_t)p0 * n + y] * (long double)L.h_tab[(size_t)L.k + p1 * n + y];
+          xg[(size_t)p0 * n + p1] = (p0 == 0 || p1 == 0) ? ((p0 == 0 && p1 == 0) ? 1.0 : 0.0) : (double)acc;
+        }
+    }
     int rc = dev_alloc((void**)&L.d_tab, sizeof(double) * L.h_tab.size());
     if (rc == AQMP_OK) rc = dev_alloc((void**)&L.d_tabT32, sizeof(float) * tT.size());
+    if (rc == AQMP_OK && !xg.empty()) rc = dev_alloc((void**)&L.d_xg, sizeof(double) * xg.size());
     if (rc == AQMP_OK) rc = dev_alloc((void**)&L.d_f32, sizeof(float) * a32.size());
     if (rc == AQMP_OK) rc = dev_alloc((void**)&L.d_bf16, sizeof(uint16_t) * a16.size());
     if (rc != AQMP_OK) {
@@ -143,6 +159,8 @@ int dictionary_build(int n_min, int n_max, uint32_t families, hipStream_t s, aqm
       e = hipMemcpyAsync(L.d_bf16, a16.data(), sizeof(uint16_t) * a16.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
       e = hipMemcpyAsync(L.d_tabT32, tT.data(), sizeof(float) * tT.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && L.d_xg)
+      e = hipMemcpyAsync(L.d_xg, xg.data(), sizeof(double) * xg.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
       dictionary_free(d);

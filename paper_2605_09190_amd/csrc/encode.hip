@@ -60,6 +60,7 @@ struct aqmp_code {
     uint16_t* r16 = nullptr;
     unsigned long long* keys = nullptr;
     int32_t* act[2] = {nullptr, nullptr};
+    double* cbuf = nullptr;          // Gram form: FP64 correlations [node][M]
     aqmp::ScanState ss{};
   };
   std::vector<Work> work;            // indexed by pass % work.size()
@@ -115,6 +116,8 @@ int validate(const aqmp_dict* d, const aqmp_image* imgs, int n_imgs, const aqmp_
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: unknown option flags");
     if (opt->corr_variant < 0 || opt->corr_variant > 6)
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad corr_variant");
+    if (opt->solver != AQMP_SOLVER_DENSE && opt->solver != AQMP_SOLVER_GRAM)
+      AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad solver");
   }
   for (int i = 0; i < n_imgs; ++i) {
     const aqmp_image& im = imgs[i];
@@ -242,10 +245,11 @@ void free_code(aqmp_code* c) {
   delete c;
 }
 
-// Levels that run as one launch: N <= kFusedMaxN in both forms (dense FP64
-// pursuit) and N = 16 in the BF16 form (whole-level MFMA pursuit).
+// Levels that run without per-step launches: N <= kFusedMaxN in both forms
+// (dense FP64 pursuit), N = 16 in the BF16 form (whole-level MFMA pursuit),
+// and every level of the Gram solver.
 static bool whole_level(const aqmp_code* c, int n) {
-  if (n <= kFusedMaxN) return true;
+  if (n <= kFusedMaxN || c->opt.solver == AQMP_SOLVER_GRAM) return true;
   return n == 16 && c->opt.precision == AQMP_PREC_BF16 && !(c->opt.flags & AQMP_OPT_STEPWISE);
 }
 
@@ -281,7 +285,7 @@ int build_plan(aqmp_code* c) {
   }
   // Level arrays: the passes are laid out one after the other.
   const size_t nwork = c->opt.schedule == AQMP_SCHED_CONCURRENT ? c->passes.size() : 1;
-  std::vector<int64_t> max_r(nwork, 0), max_keys(nwork, 0), max_cap(nwork, 0);
+  std::vector<int64_t> max_r(nwork, 0), max_keys(nwork, 0), max_cap(nwork, 0), max_cbuf(nwork, 0);
   for (size_t pi = 0; pi < c->passes.size(); ++pi) {
     auto& pp = c->passes[pi];
     const size_t wi = pi % nwork;
@@ -295,6 +299,8 @@ int build_plan(aqmp_code* c) {
       max_r[wi] = std::max(max_r[wi], pp.cap[l] * n * n);
       max_keys[wi] = std::max(max_keys[wi], pp.cap[l] * (D.m_pad / corr_atom_tile((int)n)) * kTopR);
       max_cap[wi] = std::max(max_cap[wi], pp.cap[l]);
+      if (c->opt.solver == AQMP_SOLVER_GRAM && n > kFusedMaxN)
+        max_cbuf[wi] = std::max(max_cbuf[wi], pp.cap[l] * D.m);
       c->steps_launched += pp.kmax[l];
     }
   }
@@ -324,11 +330,16 @@ int build_plan(aqmp_code* c) {
   c->work.resize(nwork);
   for (size_t wi = 0; wi < nwork; ++wi) {
     aqmp_code::Work& wk = c->work[wi];
-    ALLOC(wk.r32, max_r[wi] * 4);
-    if (c->opt.precision == AQMP_PREC_BF16) ALLOC(wk.r16, max_r[wi] * 2);
-    ALLOC(wk.keys, max_keys[wi] * 8);
-    ALLOC(wk.act[0], max_cap[wi] * 4);
-    ALLOC(wk.act[1], max_cap[wi] * 4);
+    if (c->opt.solver == AQMP_SOLVER_GRAM) {
+      // No per-step launches: no residual, key or active-list buffers.
+      ALLOC(wk.cbuf, max_cbuf[wi] * 8);
+    } else {
+      ALLOC(wk.r32, max_r[wi] * 4);
+      if (c->opt.precision == AQMP_PREC_BF16) ALLOC(wk.r16, max_r[wi] * 2);
+      ALLOC(wk.keys, max_keys[wi] * 8);
+      ALLOC(wk.act[0], max_cap[wi] * 4);
+      ALLOC(wk.act[1], max_cap[wi] * 4);
+    }
     // Tile words: one per scan tile of kScanTile items, or one per select
     // chunk of at least 4 positions, whichever is more.
     wk.ss.ntiles_max = (int32_t)(max_cap[wi] / 4 + 2);
@@ -421,6 +432,8 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
       // Small blocks: each node's whole pursuit in one launch.
       if (n <= kFusedMaxN)
         AQMP_LAUNCH(launch_mp_fused(n, c->djobs, a.lv, count, l, D.m, D.d_tab, s));
+      else if (c->opt.solver == AQMP_SOLVER_GRAM)
+        AQMP_LAUNCH(launch_mp_gram(n, c->djobs, a.lv, count, l, d->nfam, D.d_tab, D.d_xg, wk.cbuf, s));
       else
         AQMP_LAUNCH(launch_pursuit16_bf16(c->djobs, a.lv, count, D.m, d->nfam, D.d_tab, D.d_tabT32, s));
       if (l > pp.lg_lo && pp.cap[l - 1] > 0)

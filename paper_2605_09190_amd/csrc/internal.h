@@ -113,6 +113,10 @@ hipError_t launch_mp_fused(int n, const JobDev* jobs, LevelDev lv, const int32_t
                            const double* tab, hipStream_t s);
 hipError_t launch_pursuit16_bf16(const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t n_atoms, int32_t nfam,
                                  const double* tab, const float* tabT32, hipStream_t s);
+// Gram form (FP64): correlations of every node of the level into cbuf
+// ([node][nfam * n * n]), then each node's whole pursuit by Gram updates.
+hipError_t launch_mp_gram(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t lg, int32_t nfam,
+                          const double* tab, const double* xg, double* cbuf, hipStream_t s);
 hipError_t launch_decode(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t job,
                          int32_t nfam, const double* tab, void* out, int32_t dtype,
                          int64_t row_stride, hipStream_t s);
@@ -138,6 +142,7 @@ struct aqmp_dict {
     std::vector<double> h_tab;     // [nfam][n][n]
     double* d_tab = nullptr;
     float* d_tabT32 = nullptr;     // [nfam][y][p] = fl32(T_f[p][y])
+    double* d_xg = nullptr;        // [n][n] <T_0[p], T_1[p']> (two families only)
     float* d_f32 = nullptr;        // [m_pad][k]
     uint16_t* d_bf16 = nullptr;    // [m_pad][k]
   } lv[aqmp::kLevels];

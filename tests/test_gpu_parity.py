@@ -46,13 +46,13 @@ def _dev(img, dtype="f32"):
     return t.cuda()
 
 
-def _encode(A, dic, chans, params, jobs, prec, sched, dtype="f32", stepwise=False):
+def _encode(A, dic, chans, params, jobs, prec, sched, dtype="f32", stepwise=False, solver=0):
     imgs = [_dev(c, dtype) for c in chans]
-    code = A.Code(dic, imgs, params, jobs, precision=prec, schedule=sched, stepwise=stepwise)
+    code = A.Code(dic, imgs, params, jobs, precision=prec, schedule=sched, stepwise=stepwise, solver=solver)
     return code, imgs
 
 
-def _check(A, code, chans, params, jobs, prec, blocks_per_job=None):
+def _check(A, code, chans, params, jobs, prec, blocks_per_job=None, tol=None):
     exp = code.export_nodes()
     rep = PU.Report()
     for j, (ci, pi) in enumerate(jobs):
@@ -61,7 +61,7 @@ def _check(A, code, chans, params, jobs, prec, blocks_per_job=None):
         blocks = None if blocks_per_job is None else blocks_per_job[j]
         onodes = O.encode_channel(img, p, blocks=blocks)
         gpu = PU.gpu_nodes_by_key(exp, j)
-        PU.compare_job(img, onodes, gpu, COEF_TOL[prec], p.n_max, rep=rep)
+        PU.compare_job(img, onodes, gpu, COEF_TOL[prec] if tol is None else tol, p.n_max, rep=rep)
     return rep
 
 
@@ -134,6 +134,25 @@ def test_mixed_jobs_small_sizes(A, dic, prec, sched):
     rep = _check(A, code, chans, params, jobs, prec)
     _say(rep.summary())
     assert rep.ok(), rep.summary()
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_full_size_sampled_parity(A, dic, prec):
+    """The benchmark workload at its full size (2048x2048 RGB -> YCbCr, three
+    jobs, blocks 64 -> 8, k = 32) in the launch configuration the benchmark
+    times (one batched graph), checked on a seeded sample of top-level blocks
+    per job against the oracle."""
+    w = workload("c3")
+    rng = np.random.default_rng(2024)
+    tops = O.top_blocks(2048, 2048, 64)
+    samples = [[tops[i] for i in sorted(rng.choice(len(tops), size=3, replace=False))] for _ in w["jobs"]]
+    _say("full size", prec, samples)
+    code, imgs = _encode(A, dic, w["channels"], w["params"], w["jobs"], prec, 1)
+    rep = _check(A, code, w["channels"], w["params"], w["jobs"], prec, blocks_per_job=samples)
+    _say(rep.summary())
+    code.free()
+    assert rep.ok(), rep.summary()
+    assert rep.nodes >= 9
 
 
 @pytest.mark.parametrize("fam", ["dct", "haar"])
