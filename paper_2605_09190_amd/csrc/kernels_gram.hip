@@ -19,12 +19,13 @@
 // FMAs, the residual itself is never formed, and the constant atoms (exactly
 // 1/N) are handled exactly.
 //
-// k_gram_init: one workgroup per node: gather, ||y||^2, the first stop test,
-// and the correlations (separable products in FP64), written to a per-node
-// buffer.
-// k_gram_iter: one workgroup per node: the whole pursuit (selection with
-// the lowest index on ties, records, stop test of eq. (2)), correlations
-// held in registers.
+// k_gram_init: gather, ||y||^2, the first stop test, and the correlations of
+// every node as two FP64 matrix-core products per family (Z^T = Y^T T_f^T,
+// then C^T = T_f Z^T), written to a per-node buffer.  N / 16 waves per node,
+// each owning one 16-wide strip of the row index p.
+// k_gram_pursuit: the whole pursuit of every node (selection with the lowest
+// index on ties, records, stop test of eq. (2)) with the correlations held
+// in registers: one wave per node for N <= 32, four for N = 64.
 #include "internal.h"
 #include "dev_common.h"
 
@@ -32,139 +33,201 @@ namespace aqmp {
 
 namespace {
 
-template <int N>
-struct GramGeo {
-  static constexpr int K = N * N;
-  static constexpr int TB = N / 16;          // output block per thread (TB x TB)
-  static constexpr int NP = N + 1;           // padded LDS row (doubles)
-};
+typedef double d4 __attribute__((ext_vector_type(4)));
 
-// Fixed-order sum over the workgroup (4 waves), result in every thread.
-__device__ inline double wg_sum(double v, double* red) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[w] = v;
-  __syncthreads();
-  return (red[0] + red[1]) + (red[2] + red[3]);
+// LDS index of element (row, col) of an N x N FP64 tile.  The matrix-core
+// operands are read as four rows of 16 consecutive doubles; for N >= 32 the
+// odd rows swap their 16-column halves so that two such rows fall on
+// different banks.
+template <int N>
+__device__ inline int sw(int row, int col) {
+  if constexpr (N >= 32)
+    return row * N + (col ^ ((row & 1) << 4));
+  else
+    return row * N + col;
 }
 
-template <int N>
+// v_mfma_f64_16x16x4_f64: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; it holds D[l / 16 + 4 r][l % 16], r = 0..3.
+__device__ inline d4 mfma64(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+template <int N, int NFAM>
+struct InitGeo {
+  static constexpr int K = N * N;
+  static constexpr int M = NFAM * K;
+  static constexpr int WPN = N / 16;        // waves per node
+  static constexpr int GPW = 4 / WPN;       // nodes per workgroup
+  static constexpr int TPN = 64 * WPN;      // threads per node
+  static constexpr int T = N / 16;          // 16 x 16 output tiles along x (or q)
+};
+
+template <int N, int NFAM>
 __global__ __launch_bounds__(256) void k_gram_init(const JobDev* __restrict__ jobs, LevelDev lv,
-                                                   const int32_t* __restrict__ count_ptr, int32_t lg, int32_t nfam,
+                                                   const int32_t* __restrict__ count_ptr, int32_t lg,
                                                    const double* __restrict__ tab, double* __restrict__ cbuf) {
-  using G = GramGeo<N>;
-  constexpr int K = G::K, TB = G::TB, NP = G::NP;
-  __shared__ double sT[2][N][N];    // T_f[p][y]
-  __shared__ double sY[N][NP];      // block pixels
-  __shared__ double sZ[N][NP];      // T_f Y
-  __shared__ double sRed[4];
-  const int tid = threadIdx.x;
-  for (int i = tid; i < nfam * K; i += 256) (&sT[0][0][0])[i] = tab[i];
+  using G = InitGeo<N, NFAM>;
+  constexpr int K = G::K, M = G::M, WPN = G::WPN, GPW = G::GPW, TPN = G::TPN, T = G::T;
+  __shared__ double sTt[NFAM][K];           // sTt[f][sw(y, p)] = T_f[p][y]
+  __shared__ double sY[GPW][K];             // sY[g][sw(y, x)] = pixel (y, x)
+  __shared__ double sZt[GPW][K];            // sZt[g][sw(x, p)] = (T_f Y)[p][x]
+  __shared__ double sRed[GPW][WPN][2];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int g = tid / TPN, tn = tid % TPN, wn = tn >> 6;
+  for (int i = tid; i < NFAM * K; i += 256) {
+    const int f = i / K, pp = (i % K) / N, y = i % N;
+    sTt[f][sw<N>(y, pp)] = tab[i];
+  }
   const int count = *count_ptr;
-  const int b0 = tid / 16, b1 = tid % 16;   // this thread's output block
-  const int M = nfam * K;
-  for (int node = blockIdx.x; node < count; node += gridDim.x) {
-    __syncthreads();   // sT ready / previous node done with sY, sZ
-    const JobDev& jb = jobs[lv.job[node]];
-    const int bx = lv.x0[node], by = lv.y0[node];
+  const int p0 = 16 * wn;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int base = blockIdx.x * GPW; base < count; base += gridDim.x * GPW) {
+    const int node = base + g;
+    const bool live = node < count;
     double e = 0.0, s = 0.0;
-    for (int i = tid; i < K; i += 256) {
-      const int y = i / N, x = i % N;
-      const int64_t idx = (int64_t)(by + y) * jb.row_stride + bx + x;
-      const double v = jb.dtype == AQMP_F64 ? ((const double*)jb.img)[idx] : (double)((const float*)jb.img)[idx];
-      sY[y][x] = v;
-      e += v * v;
-      s += v;
-    }
-    e = wg_sum(e, sRed);   // (its barriers also publish sY)
-    s = wg_sum(s, sRed);
-    if (tid == 0) {
-      lv.e[node] = e;
-      lv.t[node] = 0;
-      uint8_t st = ST_RUN;
-      if (e < jb.eps2[lg])
-        st = ST_ACC;
-      else if (jb.k[lg] <= 0)
-        st = ST_SPARSE;
-      lv.st[node] = st;
-    }
-    double* cn = cbuf + (size_t)node * M;
-    for (int f = 0; f < nfam; ++f) {
-      // Z = T_f Y (rows b0 TB.., columns b1 TB..)
-      double z[TB][TB];
+    const JobDev* jb = nullptr;
+    if (live) {
+      jb = &jobs[lv.job[node]];
+      const int bx = lv.x0[node], by = lv.y0[node];
 #pragma unroll
-      for (int i = 0; i < TB; ++i)
-#pragma unroll
-        for (int j = 0; j < TB; ++j) z[i][j] = 0.0;
-      for (int y = 0; y < N; ++y) {
-        double tv[TB], yv[TB];
-#pragma unroll
-        for (int i = 0; i < TB; ++i) tv[i] = sT[f][b0 * TB + i][y];
-#pragma unroll
-        for (int j = 0; j < TB; ++j) yv[j] = sY[y][b1 * TB + j];
-#pragma unroll
-        for (int i = 0; i < TB; ++i)
-#pragma unroll
-          for (int j = 0; j < TB; ++j) z[i][j] = fma(tv[i], yv[j], z[i][j]);
+      for (int i = tn; i < K; i += TPN) {
+        const int y = i / N, x = i % N;
+        const int64_t idx = (int64_t)(by + y) * jb->row_stride + bx + x;
+        const double v = jb->dtype == AQMP_F64 ? ((const double*)jb->img)[idx] : (double)((const float*)jb->img)[idx];
+        sY[g][sw<N>(y, x)] = v;
+        e = fma(v, v, e);
+        s += v;
       }
+    }
 #pragma unroll
-      for (int i = 0; i < TB; ++i)
+    for (int off = 1; off < 64; off <<= 1) {
+      e += __shfl_xor(e, off, 64);
+      s += __shfl_xor(s, off, 64);
+    }
+    if (lane == 0) {
+      sRed[g][wn][0] = e;
+      sRed[g][wn][1] = s;
+    }
+    __syncthreads();   // sTt (first round), sY, sRed ready
+    if (live) {
+      e = sRed[g][0][0];
+      s = sRed[g][0][1];
 #pragma unroll
-        for (int j = 0; j < TB; ++j) sZ[b0 * TB + i][b1 * TB + j] = z[i][j];
-      __syncthreads();
-      // C[p][q] = sum_x Z[p][x] T_f[q][x] (p = b0 TB + i, q = b1 TB + j): atom f K + q N + p
-      double c[TB][TB];
-#pragma unroll
-      for (int i = 0; i < TB; ++i)
-#pragma unroll
-        for (int j = 0; j < TB; ++j) c[i][j] = 0.0;
-      for (int x = 0; x < N; ++x) {
-        double zv[TB], tv[TB];
-#pragma unroll
-        for (int i = 0; i < TB; ++i) zv[i] = sZ[b0 * TB + i][x];
-#pragma unroll
-        for (int j = 0; j < TB; ++j) tv[j] = sT[f][b1 * TB + j][x];
-#pragma unroll
-        for (int i = 0; i < TB; ++i)
-#pragma unroll
-          for (int j = 0; j < TB; ++j) c[i][j] = fma(zv[i], tv[j], c[i][j]);
+      for (int q = 1; q < WPN; ++q) {
+        e += sRed[g][q][0];
+        s += sRed[g][q][1];
       }
+      if (tn == 0) {
+        lv.e[node] = e;
+        lv.t[node] = 0;
+        uint8_t st = ST_RUN;
+        if (e < jb->eps2[lg])
+          st = ST_ACC;
+        else if (jb->k[lg] <= 0)
+          st = ST_SPARSE;
+        lv.st[node] = st;
+      }
+      double* cn = cbuf + (size_t)node * M;
 #pragma unroll
-      for (int i = 0; i < TB; ++i)
+      for (int f = 0; f < NFAM; ++f) {
+        // Z^T[x][p] = sum_y Y[y][x] T_f[p][y] for this wave's strip of p
+        d4 acc[T];
 #pragma unroll
-        for (int j = 0; j < TB; ++j) {
-          const int p = b0 * TB + i, q = b1 * TB + j;
-          cn[f * K + q * N + p] = (p == 0 && q == 0) ? s / N : c[i][j];
+        for (int tx = 0; tx < T; ++tx) acc[tx] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int ks = 0; ks < N / 4; ++ks) {
+          const int k = 4 * ks + lk;
+          const double b = sTt[f][sw<N>(k, p0 + li)];
+#pragma unroll
+          for (int tx = 0; tx < T; ++tx) acc[tx] = mfma64(sY[g][sw<N>(k, 16 * tx + li)], b, acc[tx]);
         }
-      __syncthreads();   // sZ is rewritten by the next family
+#pragma unroll
+        for (int tx = 0; tx < T; ++tx)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) sZt[g][sw<N>(16 * tx + lk + 4 * r, p0 + li)] = acc[tx][r];
+        // The strip is private to this wave: its own LDS writes are seen by
+        // its later reads.
+        __builtin_amdgcn_wave_barrier();
+        // C^T[q][p] = sum_x T_f[q][x] Z^T[x][p]
+#pragma unroll
+        for (int tq = 0; tq < T; ++tq) acc[tq] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int ks = 0; ks < N / 4; ++ks) {
+          const int k = 4 * ks + lk;
+          const double b = sZt[g][sw<N>(k, p0 + li)];
+#pragma unroll
+          for (int tq = 0; tq < T; ++tq) acc[tq] = mfma64(sTt[f][sw<N>(k, 16 * tq + li)], b, acc[tq]);
+        }
+        __builtin_amdgcn_wave_barrier();
+        // atom f K + q N + p; the constant atom (p = q = 0) is exactly 1/N
+#pragma unroll
+        for (int tq = 0; tq < T; ++tq)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int q = 16 * tq + lk + 4 * r, pp = p0 + li;
+            cn[f * K + q * N + pp] = (q == 0 && pp == 0) ? s / N : acc[tq][r];
+          }
+      }
     }
+    __syncthreads();   // sY and sRed are rewritten by the next round
   }
 }
 
-template <int N>
-__global__ __launch_bounds__(256) void k_gram_iter(const JobDev* __restrict__ jobs, LevelDev lv,
-                                                   const int32_t* __restrict__ count_ptr, int32_t lg, int32_t nfam,
-                                                   const double* __restrict__ xg, const double* __restrict__ cbuf) {
-  constexpr int K = N * N;
-  constexpr int APT = 2 * K / 256;      // atoms per thread (both families)
-  constexpr int RW = 64;                // records held in registers between flushes
-  constexpr int NP = N + 1;
-  __shared__ double sX[N][NP];          // cross-family table X[p][p'] = <T_0[p], T_1[p']>
-  __shared__ double sBc[2][4];          // per-wave best (signed) correlation, double-buffered
+template <int N, int NFAM>
+struct PurGeo {
+  static constexpr int K = N * N;
+  static constexpr int M = NFAM * K;
+  static constexpr int TPN = N == 64 ? 256 : 64;   // threads per node
+  static constexpr int WPN = TPN / 64;
+  static constexpr int APT = M / TPN;              // atoms per thread
+  static constexpr int NPW = 256 / TPN;            // nodes per workgroup
+};
+
+// Best atom of a wave: largest |c|, lowest atom index among equal
+// magnitudes; the result is uniform across the wave.
+__device__ inline void wave_best(double bc, int bi, double& wbc, int& wbi) {
+  double m = fabs(bc);
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  unsigned long long ball = __ballot(fabs(bc) == m);
+  int best = 0x7fffffff, L = 0;
+  while (ball) {
+    const int l = __builtin_ctzll(ball);
+    const int cand = __builtin_amdgcn_readlane(bi, l);
+    if (cand < best) { best = cand; L = l; }
+    ball &= ball - 1;
+  }
+  const long long v = __double_as_longlong(bc);
+  const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffLL), L);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), L);
+  wbc = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  wbi = best;
+}
+
+template <int N, int NFAM>
+__global__ __launch_bounds__(256) void k_gram_pursuit(const JobDev* __restrict__ jobs, LevelDev lv,
+                                                      const int32_t* __restrict__ count_ptr, int32_t lg,
+                                                      const double* __restrict__ xg, const double* __restrict__ cbuf) {
+  using G = PurGeo<N, NFAM>;
+  constexpr int K = G::K, M = G::M, TPN = G::TPN, WPN = G::WPN, APT = G::APT, NPW = G::NPW;
+  constexpr int AF = APT / NFAM;          // atoms per thread per family
+  constexpr int RW = 64;                  // records held in registers between flushes
+  constexpr int NX = NFAM == 2 ? N : 1;
+  __shared__ double sX[NX][NX + 1];       // X[p][p'] = <T_0[p], T_1[p']>
+  __shared__ double sBc[2][4];            // per-wave best, double-buffered (N = 64)
   __shared__ int sBi[2][4];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  if (nfam == 2)
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int g = tid / TPN, tn = tid % TPN, wn = tn >> 6;
+  if constexpr (NFAM == 2)
     for (int i = tid; i < K; i += 256) sX[i / N][i % N] = xg[i];
   __syncthreads();
   const int count = *count_ptr;
-  const int M = nfam * K;
-  // This thread's atoms a = tid + 256 j: p_a = tid mod N for every j (256 is
-  // a multiple of N); q_a and the family depend on j only through 256 j.
-  const int pa = tid % N;
+  // This thread's atoms: a = tn + TPN j.  TPN is a multiple of N, so p_a =
+  // tn mod N for every j, q_a = (tn / N + (TPN / N) j) mod N and the family
+  // is j / AF.
+  const int pa = tn % N;
+  const int qb = tn / N;
   int ph = 0;
-  for (int node = blockIdx.x; node < count; node += gridDim.x) {
+  for (int node = blockIdx.x * NPW + g; node < count; node += gridDim.x * NPW) {
     const JobDev& jb = jobs[lv.job[node]];
     const double eps2 = jb.eps2[lg];
     const int kmax = jb.k[lg];
@@ -176,73 +239,90 @@ __global__ __launch_bounds__(256) void k_gram_iter(const JobDev* __restrict__ jo
     double c[APT];
     const double* cn = cbuf + (size_t)node * M;
 #pragma unroll
-    for (int j = 0; j < APT; ++j) {
-      const int a = tid + 256 * j;
-      c[j] = a < M ? cn[a] : 0.0;
-    }
+    for (int j = 0; j < APT; ++j) c[j] = cn[tn + TPN * j];
     const size_t rec0 = (size_t)node * lv.kmax;
     while (st == ST_RUN) {
-      // arg-max |c|, lowest atom index among equal magnitudes
-      double bc = 0.0;
-      int bi = 0x7fffffff;
+      // this thread's best: ascending j is ascending atom index, so a strict
+      // comparison keeps the lowest index
+      double bc = c[0];
+      int bj = 0;
 #pragma unroll
-      for (int j = 0; j < APT; ++j) {
-        const int a = tid + 256 * j;
-        if (a < M && fabs(c[j]) > fabs(bc)) { bc = c[j]; bi = a; }
+      for (int j = 1; j < APT; ++j) {
+        const bool take = fabs(c[j]) > fabs(bc);
+        bc = take ? c[j] : bc;
+        bj = take ? j : bj;
       }
-      if (bi == 0x7fffffff) bi = tid;   // all zero: lowest own index
+      int bi = tn + TPN * bj;
+      wave_best(bc, bi, bc, bi);
+      if constexpr (WPN > 1) {
+        if (lane == 0) {
+          sBc[ph][wn] = bc;
+          sBi[ph][wn] = bi;
+        }
+        __syncthreads();
+        bc = sBc[ph][0];
+        bi = sBi[ph][0];
 #pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const double oc = __shfl_xor(bc, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (fabs(oc) > fabs(bc) || (fabs(oc) == fabs(bc) && oi < bi)) { bc = oc; bi = oi; }
+        for (int q = 1; q < WPN; ++q) {
+          const double oc = sBc[ph][q];
+          const int oi = sBi[ph][q];
+          if (fabs(oc) > fabs(bc) || (fabs(oc) == fabs(bc) && oi < bi)) {
+            bc = oc;
+            bi = oi;
+          }
+        }
+        ph ^= 1;
       }
-      if (lane == 0) { sBc[ph][w] = bc; sBi[ph][w] = bi; }
-      __syncthreads();
-      bc = sBc[ph][0];
-      bi = sBi[ph][0];
-#pragma unroll
-      for (int q = 1; q < 4; ++q) {
-        const double oc = sBc[ph][q];
-        const int oi = sBi[ph][q];
-        if (fabs(oc) > fabs(bc) || (fabs(oc) == fabs(bc) && oi < bi)) { bc = oc; bi = oi; }
+      if (bc == 0.0) {
+        st = ST_ZERO;
+        break;
       }
-      ph ^= 1;
-      if (bc == 0.0) { st = ST_ZERO; break; }
-      if (tid == t % RW) { rec_i = bi; rec_c = bc; }
-      // c_a <- c_a - c_i <phi_a, phi_i>: same family -> Kronecker delta
-      // (orthonormal basis); other family -> X[p_a][p_i] X[q_a][q_i] (or
-      // its transpose), which also covers the constant atoms exactly.
+      if (tn == t % RW) {
+        rec_i = bi;
+        rec_c = bc;
+      }
+      // c_a <- c_a - c_i <phi_a, phi_i>: a Kronecker delta within the chosen
+      // atom's family (only c_i itself changes, to zero); across families
+      // X[p_a][p_i] X[q_a][q_i] (or its transpose), exact for the constant
+      // atoms.
       const int fi = bi / K, pi = bi % N, qi = (bi % K) / N;
-      const double vp = fi ? sX[pa][pi] : sX[pi][pa];
+      const bool mine = tn == bi % TPN;
+      const int jb_ = bi / TPN;
 #pragma unroll
-      for (int j = 0; j < APT; ++j) {
-        const int a = tid + 256 * j;
-        const int fa = a / K;
-        if (fa == fi) {
-          if (a == bi) c[j] = 0.0;
-        } else if (a < M) {
-          const int qa = (a % K) / N;
-          const double vq = fi ? sX[qa][qi] : sX[qi][qa];
-          c[j] = fma(-bc, vp * vq, c[j]);
+      for (int j = 0; j < APT; ++j) c[j] = (mine && j == jb_) ? 0.0 : c[j];
+      if constexpr (NFAM == 2) {
+        if (fi == 0) {
+          const double bv = -bc * sX[pi][pa];
+#pragma unroll
+          for (int j = AF; j < APT; ++j) {
+            const int qa = (qb + (TPN / N) * j) % N;
+            c[j] = fma(bv, sX[qi][qa], c[j]);
+          }
+        } else {
+          const double bv = -bc * sX[pa][pi];
+#pragma unroll
+          for (int j = 0; j < AF; ++j) {
+            const int qa = (qb + (TPN / N) * j) % N;
+            c[j] = fma(bv, sX[qa][qi], c[j]);
+          }
         }
       }
       e = fma(-bc, bc, e);
       ++t;
-      if (t % RW == 0 && tid < RW) {
-        lv.rec_idx[rec0 + (t - RW) + tid] = rec_i;
-        lv.rec_coef[rec0 + (t - RW) + tid] = rec_c;
+      if (t % RW == 0 && tn < RW) {
+        lv.rec_idx[rec0 + (t - RW) + tn] = rec_i;
+        lv.rec_coef[rec0 + (t - RW) + tn] = rec_c;
       }
       if (e < eps2)
         st = ST_ACC;
       else if (t >= kmax)
         st = ST_SPARSE;
     }
-    if (tid < t % RW) {
-      lv.rec_idx[rec0 + (t - t % RW) + tid] = rec_i;
-      lv.rec_coef[rec0 + (t - t % RW) + tid] = rec_c;
+    if (tn < t % RW) {
+      lv.rec_idx[rec0 + (t - t % RW) + tn] = rec_i;
+      lv.rec_coef[rec0 + (t - t % RW) + tn] = rec_c;
     }
-    if (tid == 0) {
+    if (tn == 0) {
       lv.e[node] = e;
       lv.t[node] = t;
       lv.st[node] = st;
@@ -250,23 +330,31 @@ __global__ __launch_bounds__(256) void k_gram_iter(const JobDev* __restrict__ jo
   }
 }
 
+template <int N, int NFAM>
+void launch_gram_n(const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t lg, const double* tab,
+                   const double* xg, double* cbuf, int init_grid, int pur_grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_gram_init<N, NFAM>), dim3(init_grid), dim3(256), 0, s, jobs, lv, count, lg, tab, cbuf);
+  hipLaunchKernelGGL((k_gram_pursuit<N, NFAM>), dim3(pur_grid), dim3(256), 0, s, jobs, lv, count, lg, xg, cbuf);
+}
+
 }  // namespace
 
 hipError_t launch_mp_gram(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t lg, int32_t nfam,
                           const double* tab, const double* xg, double* cbuf, hipStream_t s) {
   if (nfam == 2 && !xg) return hipErrorInvalidValue;
+  if (nfam != 1 && nfam != 2) return hipErrorInvalidValue;
   switch (n) {
     case 16:
-      hipLaunchKernelGGL(k_gram_init<16>, dim3(2048), dim3(256), 0, s, jobs, lv, count, lg, nfam, tab, cbuf);
-      hipLaunchKernelGGL(k_gram_iter<16>, dim3(2048), dim3(256), 0, s, jobs, lv, count, lg, nfam, xg, cbuf);
+      if (nfam == 2) launch_gram_n<16, 2>(jobs, lv, count, lg, tab, xg, cbuf, 2048, 2048, s);
+      else launch_gram_n<16, 1>(jobs, lv, count, lg, tab, xg, cbuf, 2048, 2048, s);
       break;
     case 32:
-      hipLaunchKernelGGL(k_gram_init<32>, dim3(1024), dim3(256), 0, s, jobs, lv, count, lg, nfam, tab, cbuf);
-      hipLaunchKernelGGL(k_gram_iter<32>, dim3(1024), dim3(256), 0, s, jobs, lv, count, lg, nfam, xg, cbuf);
+      if (nfam == 2) launch_gram_n<32, 2>(jobs, lv, count, lg, tab, xg, cbuf, 1024, 2048, s);
+      else launch_gram_n<32, 1>(jobs, lv, count, lg, tab, xg, cbuf, 1024, 2048, s);
       break;
     case 64:
-      hipLaunchKernelGGL(k_gram_init<64>, dim3(256), dim3(256), 0, s, jobs, lv, count, lg, nfam, tab, cbuf);
-      hipLaunchKernelGGL(k_gram_iter<64>, dim3(512), dim3(256), 0, s, jobs, lv, count, lg, nfam, xg, cbuf);
+      if (nfam == 2) launch_gram_n<64, 2>(jobs, lv, count, lg, tab, xg, cbuf, 256, 1024, s);
+      else launch_gram_n<64, 1>(jobs, lv, count, lg, tab, xg, cbuf, 256, 1024, s);
       break;
     default:
       return hipErrorInvalidValue;
