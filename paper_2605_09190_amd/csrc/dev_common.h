@@ -130,4 +130,34 @@ __device__ inline int lookback_wave(unsigned long long* tiles, int tile, int agg
   return prefix;
 }
 
+// Whole-wave reductions with DPP row operations (quad swaps, row mirrors,
+// row broadcasts 15 and 31), then a read of lane 63: a fixed order, so the
+// results are bit-reproducible, and no LDS-crossbar round trips.
+template <int CTRL, int RM>
+__device__ inline unsigned long long dpp_u64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, RM, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, RM, 0xF, false);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+__device__ inline unsigned long long lane63_u64(unsigned long long v) {
+  const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)v, 63);
+  const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ inline unsigned long long wave_max_u64(unsigned long long v) {
+#define AQMP_MAXSTEP(C, RM) { const unsigned long long o = dpp_u64<C, RM>(v); v = o > v ? o : v; }
+  AQMP_MAXSTEP(0xB1, 0xF) AQMP_MAXSTEP(0x4E, 0xF) AQMP_MAXSTEP(0x141, 0xF)
+  AQMP_MAXSTEP(0x140, 0xF) AQMP_MAXSTEP(0x142, 0xA) AQMP_MAXSTEP(0x143, 0xC)
+#undef AQMP_MAXSTEP
+  return lane63_u64(v);
+}
+__device__ inline double wave_sum_f64(double d) {
+#define AQMP_SUMSTEP(C, RM) { d += __longlong_as_double((long long)dpp_u64<C, RM>((unsigned long long)__double_as_longlong(d))); }
+  AQMP_SUMSTEP(0xB1, 0xF) AQMP_SUMSTEP(0x4E, 0xF) AQMP_SUMSTEP(0x141, 0xF)
+  AQMP_SUMSTEP(0x140, 0xF) AQMP_SUMSTEP(0x142, 0xA) AQMP_SUMSTEP(0x143, 0xC)
+#undef AQMP_SUMSTEP
+  return __longlong_as_double((long long)lane63_u64((unsigned long long)__double_as_longlong(d)));
+}
+
+
 }  // namespace aqmp

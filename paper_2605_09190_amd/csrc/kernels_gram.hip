@@ -58,28 +58,35 @@ struct InitGeo {
   static constexpr int WPN = N / 16;        // waves per node
   static constexpr int GPW = 4 / WPN;       // nodes per workgroup
   static constexpr int TPN = 64 * WPN;      // threads per node
-  static constexpr int T = N / 16;          // 16 x 16 output tiles along x (or q)
+  static constexpr int T = N / 16;          // 16 x 16 output tiles along x (or p)
+  static constexpr int KS = N / 4;          // k-steps of one product
 };
 
+// Wave wn of a node owns the 16-row strip s0 = 16 wn of the 1D tables.  It
+// computes Z^T[x][p] for p in its strip (first product, all x) and C^T[q][p]
+// for q in its strip (second product, all p).  Both products read the same
+// table entries T_f[s0 + l % 16][4 ks + l / 16] (the B operand of the first,
+// the A operand of the second), which the lane keeps in registers for the
+// whole kernel; only Y and Z^T go through LDS.
 template <int N, int NFAM>
 __global__ __launch_bounds__(256) void k_gram_init(const JobDev* __restrict__ jobs, LevelDev lv,
                                                    const int32_t* __restrict__ count_ptr, int32_t lg,
                                                    const double* __restrict__ tab, double* __restrict__ cbuf) {
   using G = InitGeo<N, NFAM>;
-  constexpr int K = G::K, M = G::M, WPN = G::WPN, GPW = G::GPW, TPN = G::TPN, T = G::T;
-  __shared__ double sTt[NFAM][K];           // sTt[f][sw(y, p)] = T_f[p][y]
+  constexpr int K = G::K, M = G::M, WPN = G::WPN, GPW = G::GPW, TPN = G::TPN, T = G::T, KS = G::KS;
   __shared__ double sY[GPW][K];             // sY[g][sw(y, x)] = pixel (y, x)
   __shared__ double sZt[GPW][K];            // sZt[g][sw(x, p)] = (T_f Y)[p][x]
   __shared__ double sRed[GPW][WPN][2];
   const int tid = threadIdx.x, lane = tid & 63;
   const int g = tid / TPN, tn = tid % TPN, wn = tn >> 6;
-  for (int i = tid; i < NFAM * K; i += 256) {
-    const int f = i / K, pp = (i % K) / N, y = i % N;
-    sTt[f][sw<N>(y, pp)] = tab[i];
-  }
-  const int count = *count_ptr;
-  const int p0 = 16 * wn;
+  const int s0 = 16 * wn;
   const int li = lane & 15, lk = lane >> 4;
+  double tr[NFAM][KS];
+#pragma unroll
+  for (int f = 0; f < NFAM; ++f)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) tr[f][ks] = tab[(size_t)f * K + (s0 + li) * N + 4 * ks + lk];
+  const int count = *count_ptr;
   for (int base = blockIdx.x * GPW; base < count; base += gridDim.x * GPW) {
     const int node = base + g;
     const bool live = node < count;
@@ -98,16 +105,13 @@ __global__ __launch_bounds__(256) void k_gram_init(const JobDev* __restrict__ jo
         s += v;
       }
     }
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      e += __shfl_xor(e, off, 64);
-      s += __shfl_xor(s, off, 64);
-    }
+    e = wave_sum_f64(e);
+    s = wave_sum_f64(s);
     if (lane == 0) {
       sRed[g][wn][0] = e;
       sRed[g][wn][1] = s;
     }
-    __syncthreads();   // sTt (first round), sY, sRed ready
+    __syncthreads();   // sY, sRed ready
     if (live) {
       e = sRed[g][0][0];
       s = sRed[g][0][1];
@@ -126,49 +130,52 @@ __global__ __launch_bounds__(256) void k_gram_init(const JobDev* __restrict__ jo
           st = ST_SPARSE;
         lv.st[node] = st;
       }
-      double* cn = cbuf + (size_t)node * M;
+    }
+    double* cn = cbuf + (size_t)node * M;
 #pragma unroll
-      for (int f = 0; f < NFAM; ++f) {
-        // Z^T[x][p] = sum_y Y[y][x] T_f[p][y] for this wave's strip of p
-        d4 acc[T];
+    for (int f = 0; f < NFAM; ++f) {
+      // Z^T[x][p] = sum_y Y[y][x] T_f[p][y], p in this wave's strip
+      d4 acc[T];
 #pragma unroll
-        for (int tx = 0; tx < T; ++tx) acc[tx] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-        for (int ks = 0; ks < N / 4; ++ks) {
+      for (int tx = 0; tx < T; ++tx) acc[tx] = d4{0.0, 0.0, 0.0, 0.0};
+      if (live) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
           const int k = 4 * ks + lk;
-          const double b = sTt[f][sw<N>(k, p0 + li)];
 #pragma unroll
-          for (int tx = 0; tx < T; ++tx) acc[tx] = mfma64(sY[g][sw<N>(k, 16 * tx + li)], b, acc[tx]);
+          for (int tx = 0; tx < T; ++tx) acc[tx] = mfma64(sY[g][sw<N>(k, 16 * tx + li)], tr[f][ks], acc[tx]);
         }
+      }
+      __syncthreads();   // the previous family's second product is done with sZt
+      if (live) {
 #pragma unroll
         for (int tx = 0; tx < T; ++tx)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) sZt[g][sw<N>(16 * tx + lk + 4 * r, p0 + li)] = acc[tx][r];
-        // The strip is private to this wave: its own LDS writes are seen by
-        // its later reads.
-        __builtin_amdgcn_wave_barrier();
-        // C^T[q][p] = sum_x T_f[q][x] Z^T[x][p]
+          for (int r = 0; r < 4; ++r) sZt[g][sw<N>(16 * tx + lk + 4 * r, s0 + li)] = acc[tx][r];
+      }
+      __syncthreads();   // Z^T complete
+      if (live) {
+        // C^T[q][p] = sum_x T_f[q][x] Z^T[x][p], q in this wave's strip
 #pragma unroll
-        for (int tq = 0; tq < T; ++tq) acc[tq] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-        for (int ks = 0; ks < N / 4; ++ks) {
+        for (int tp = 0; tp < T; ++tp) acc[tp] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
           const int k = 4 * ks + lk;
-          const double b = sZt[g][sw<N>(k, p0 + li)];
 #pragma unroll
-          for (int tq = 0; tq < T; ++tq) acc[tq] = mfma64(sTt[f][sw<N>(k, 16 * tq + li)], b, acc[tq]);
+          for (int tp = 0; tp < T; ++tp) acc[tp] = mfma64(tr[f][ks], sZt[g][sw<N>(k, 16 * tp + li)], acc[tp]);
         }
-        __builtin_amdgcn_wave_barrier();
         // atom f K + q N + p; the constant atom (p = q = 0) is exactly 1/N
 #pragma unroll
-        for (int tq = 0; tq < T; ++tq)
+        for (int tp = 0; tp < T; ++tp)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int q = 16 * tq + lk + 4 * r, pp = p0 + li;
-            cn[f * K + q * N + pp] = (q == 0 && pp == 0) ? s / N : acc[tq][r];
+            const int q = s0 + lk + 4 * r, pp = 16 * tp + li;
+            cn[f * K + q * N + pp] = (q == 0 && pp == 0) ? s / N : acc[tp][r];
           }
       }
     }
-    __syncthreads();   // sY and sRed are rewritten by the next round
+    // The next round's gather writes sY: every wave has passed the barriers
+    // after its last read of sY (first product of the last family).
   }
 }
 
@@ -183,17 +190,20 @@ struct PurGeo {
 };
 
 // Best atom of a wave: largest |c|, lowest atom index among equal
-// magnitudes; the result is uniform across the wave.
+// magnitudes; the result is uniform across the wave.  |c| is non-negative,
+// so its bit pattern orders like its value.
 __device__ inline void wave_best(double bc, int bi, double& wbc, int& wbi) {
-  double m = fabs(bc);
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) m = fmax(m, __shfl_xor(m, off, 64));
-  unsigned long long ball = __ballot(fabs(bc) == m);
+  const unsigned long long mb = (unsigned long long)__double_as_longlong(fabs(bc));
+  const unsigned long long m = wave_max_u64(mb);
+  unsigned long long ball = __ballot(mb == m);
   int best = 0x7fffffff, L = 0;
   while (ball) {
     const int l = __builtin_ctzll(ball);
     const int cand = __builtin_amdgcn_readlane(bi, l);
-    if (cand < best) { best = cand; L = l; }
+    if (cand < best) {
+      best = cand;
+      L = l;
+    }
     ball &= ball - 1;
   }
   const long long v = __double_as_longlong(bc);
@@ -201,6 +211,29 @@ __device__ inline void wave_best(double bc, int bi, double& wbc, int& wbi) {
   const int hi = __builtin_amdgcn_readlane((int)(v >> 32), L);
   wbc = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
   wbi = best;
+}
+
+// Largest |v[j]| of a register array and its position, lowest j among equal
+// magnitudes (pairwise tree: the left operand always holds lower positions).
+template <int A>
+__device__ inline void lane_best(const double (&c)[A], double& bc, int& bj) {
+  double v[A];
+  int ix[A];
+#pragma unroll
+  for (int j = 0; j < A; ++j) {
+    v[j] = c[j];
+    ix[j] = j;
+  }
+#pragma unroll
+  for (int w = 1; w < A; w *= 2)
+#pragma unroll
+    for (int i = 0; i + w < A; i += 2 * w) {
+      const bool take = fabs(v[i + w]) > fabs(v[i]);
+      v[i] = take ? v[i + w] : v[i];
+      ix[i] = take ? ix[i + w] : ix[i];
+    }
+  bc = v[0];
+  bj = ix[0];
 }
 
 template <int N, int NFAM>
@@ -242,16 +275,10 @@ __global__ __launch_bounds__(256) void k_gram_pursuit(const JobDev* __restrict__
     for (int j = 0; j < APT; ++j) c[j] = cn[tn + TPN * j];
     const size_t rec0 = (size_t)node * lv.kmax;
     while (st == ST_RUN) {
-      // this thread's best: ascending j is ascending atom index, so a strict
-      // comparison keeps the lowest index
-      double bc = c[0];
-      int bj = 0;
-#pragma unroll
-      for (int j = 1; j < APT; ++j) {
-        const bool take = fabs(c[j]) > fabs(bc);
-        bc = take ? c[j] : bc;
-        bj = take ? j : bj;
-      }
+      // this thread's best (ascending j is ascending atom index)
+      double bc;
+      int bj;
+      lane_best(c, bc, bj);
       int bi = tn + TPN * bj;
       wave_best(bc, bi, bc, bi);
       if constexpr (WPN > 1) {
@@ -289,7 +316,8 @@ __global__ __launch_bounds__(256) void k_gram_pursuit(const JobDev* __restrict__
       const bool mine = tn == bi % TPN;
       const int jb_ = bi / TPN;
 #pragma unroll
-      for (int j = 0; j < APT; ++j) c[j] = (mine && j == jb_) ? 0.0 : c[j];
+      for (int j = 0; j < APT; ++j)
+        if (j == jb_ && mine) c[j] = 0.0;
       if constexpr (NFAM == 2) {
         if (fi == 0) {
           const double bv = -bc * sX[pi][pa];
@@ -353,8 +381,8 @@ hipError_t launch_mp_gram(int n, const JobDev* jobs, LevelDev lv, const int32_t*
       else launch_gram_n<32, 1>(jobs, lv, count, lg, tab, xg, cbuf, 1024, 2048, s);
       break;
     case 64:
-      if (nfam == 2) launch_gram_n<64, 2>(jobs, lv, count, lg, tab, xg, cbuf, 256, 1024, s);
-      else launch_gram_n<64, 1>(jobs, lv, count, lg, tab, xg, cbuf, 256, 1024, s);
+      if (nfam == 2) launch_gram_n<64, 2>(jobs, lv, count, lg, tab, xg, cbuf, 512, 1024, s);
+      else launch_gram_n<64, 1>(jobs, lv, count, lg, tab, xg, cbuf, 512, 1024, s);
       break;
     default:
       return hipErrorInvalidValue;
