@@ -430,10 +430,10 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
     if (le) AQMP_HIP(hipEventRecord(le->start, s));
     if (whole_level(c, n)) {
       // Small blocks: each node's whole pursuit in one launch.
-      if (n <= kFusedMaxN)
-        AQMP_LAUNCH(launch_mp_fused(n, c->djobs, a.lv, count, l, D.m, D.d_tab, s));
-      else if (c->opt.solver == AQMP_SOLVER_GRAM)
+      if (c->opt.solver == AQMP_SOLVER_GRAM)
         AQMP_LAUNCH(launch_mp_gram(n, c->djobs, a.lv, count, l, d->nfam, D.d_tab, D.d_xg, wk.cbuf, s));
+      else if (n <= kFusedMaxN)
+        AQMP_LAUNCH(launch_mp_fused(n, c->djobs, a.lv, count, l, D.m, D.d_tab, s));
       else
         AQMP_LAUNCH(launch_pursuit16_bf16(c->djobs, a.lv, count, D.m, d->nfam, D.d_tab, D.d_tabT32, s));
       if (l > pp.lg_lo && pp.cap[l - 1] > 0)

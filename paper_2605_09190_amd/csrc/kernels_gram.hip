@@ -358,6 +358,161 @@ __global__ __launch_bounds__(256) void k_gram_pursuit(const JobDev* __restrict__
   }
 }
 
+// ---------------------------------------------------------------------------
+// Small blocks (N = 4, 8): one group of K = N^2 lanes per node (a whole wave
+// at N = 8, a row of 16 lanes at N = 4), lane = pixel for the gather and
+// lane = (p, q) for the atoms, one atom per family per lane.  The
+// correlations come from the separable sum sum_y T_f[p][y] sum_x T_f[q][x]
+// Y[y][x]; the pursuit then runs on the Gram updates as above.  Selection
+// reductions stay inside the group (DPP row operations; the wave-wide form
+// at N = 8): the largest |c|, then the lowest atom index among the lanes
+// holding it, then that lane's c.
+// ---------------------------------------------------------------------------
+template <int LPN>
+__device__ inline unsigned long long grp_max_u64(unsigned long long v) {
+  if constexpr (LPN == 64) {
+    return wave_max_u64(v);
+  } else {
+    static_assert(LPN == 16, "groups of 16 or 64 lanes");
+#define AQMP_GMAX(C) { const unsigned long long o = dpp_u64<C, 0xF>(v); v = o > v ? o : v; }
+    AQMP_GMAX(0xB1) AQMP_GMAX(0x4E) AQMP_GMAX(0x141) AQMP_GMAX(0x140)
+#undef AQMP_GMAX
+    return v;
+  }
+}
+template <int LPN>
+__device__ inline double grp_sum_f64(double d) {
+  if constexpr (LPN == 64) {
+    return wave_sum_f64(d);
+  } else {
+#define AQMP_GSUM(C) { d += __longlong_as_double((long long)dpp_u64<C, 0xF>((unsigned long long)__double_as_longlong(d))); }
+    AQMP_GSUM(0xB1) AQMP_GSUM(0x4E) AQMP_GSUM(0x141) AQMP_GSUM(0x140)
+#undef AQMP_GSUM
+    return d;
+  }
+}
+// Minimum of non-negative 32-bit values over the group (lanes that a row
+// operation leaves without a source keep their own value).
+template <int CTRL, int RM>
+__device__ inline int dpp_keep(int v) { return __builtin_amdgcn_update_dpp(v, v, CTRL, RM, 0xF, false); }
+template <int LPN>
+__device__ inline int grp_min_i32(int v) {
+#define AQMP_GMIN(C, RM) { const int o = dpp_keep<C, RM>(v); v = o < v ? o : v; }
+  AQMP_GMIN(0xB1, 0xF) AQMP_GMIN(0x4E, 0xF) AQMP_GMIN(0x141, 0xF) AQMP_GMIN(0x140, 0xF)
+  if constexpr (LPN == 64) {
+    AQMP_GMIN(0x142, 0xA) AQMP_GMIN(0x143, 0xC)
+    v = __builtin_amdgcn_readlane(v, 63);
+  }
+#undef AQMP_GMIN
+  return v;
+}
+
+template <int N, int NFAM>
+__global__ __launch_bounds__(256) void k_gram_small(const JobDev* __restrict__ jobs, LevelDev lv,
+                                                    const int32_t* __restrict__ count_ptr, int32_t lg,
+                                                    const double* __restrict__ tab, const double* __restrict__ xg) {
+  constexpr int K = N * N;
+  constexpr int LPN = K;                 // lanes per node
+  constexpr int GPW = 64 / LPN;          // nodes per wave
+  constexpr int NG = 4 * GPW;            // nodes per workgroup
+  constexpr int NX = NFAM == 2 ? N : 1;
+  __shared__ double sT[NFAM][K];         // T_f[p][y] at [f][p N + y]
+  __shared__ double sX[NX][NX + 1];      // X[p][p'] = <T_0[p], T_1[p']>
+  __shared__ double sY[NG][K];           // the node's pixels (group-private)
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int grp = (tid >> 6) * GPW + lane / LPN, lt = lane % LPN;
+  for (int i = tid; i < NFAM * K; i += 256) (&sT[0][0])[i] = tab[i];
+  if constexpr (NFAM == 2)
+    for (int i = tid; i < K; i += 256) sX[i / N][i % N] = xg[i];
+  __syncthreads();
+  const int count = *count_ptr;
+  const int pa = lt % N, qa = lt / N;    // this lane's atoms f K + lt
+  for (int node = blockIdx.x * NG + grp; node < count; node += gridDim.x * NG) {
+    const JobDev& jb = jobs[lv.job[node]];
+    const double eps2 = jb.eps2[lg];
+    const int kmax = jb.k[lg];
+    const int64_t idx = (int64_t)(lv.y0[node] + qa) * jb.row_stride + lv.x0[node] + pa;   // pixel (lt / N, lt % N)
+    const double v = jb.dtype == AQMP_F64 ? ((const double*)jb.img)[idx] : (double)((const float*)jb.img)[idx];
+    sY[grp][lt] = v;
+    __builtin_amdgcn_wave_barrier();     // group-private: the wave's own writes are seen by its reads
+    double e = grp_sum_f64<LPN>(v * v);
+    const double s = grp_sum_f64<LPN>(v);
+    uint8_t st = ST_RUN;
+    if (e < eps2)
+      st = ST_ACC;
+    else if (kmax <= 0)
+      st = ST_SPARSE;
+    double c[NFAM];
+#pragma unroll
+    for (int f = 0; f < NFAM; ++f) {
+      double acc = 0.0;
+#pragma unroll
+      for (int y = 0; y < N; ++y) {
+        double u = 0.0;
+#pragma unroll
+        for (int x = 0; x < N; ++x) u = fma(sT[f][qa * N + x], sY[grp][y * N + x], u);
+        acc = fma(sT[f][pa * N + y], u, acc);
+      }
+      c[f] = lt == 0 ? s / N : acc;
+    }
+    __builtin_amdgcn_wave_barrier();     // sY is rewritten by the next node
+    int t = 0, rec_i = 0;
+    double rec_c = 0.0;
+    const size_t rec0 = (size_t)node * lv.kmax;
+    while (st == ST_RUN) {
+      double bc = c[0];
+      int bi = lt;
+      if constexpr (NFAM == 2) {
+        const bool take = fabs(c[1]) > fabs(bc);
+        bc = take ? c[1] : bc;
+        bi = take ? K + lt : bi;
+      }
+      const unsigned long long mb = (unsigned long long)__double_as_longlong(fabs(bc));
+      const unsigned long long m = grp_max_u64<LPN>(mb);
+      bi = grp_min_i32<LPN>(mb == m ? bi : 0x7fffffff);
+      if (m == 0ull) {
+        st = ST_ZERO;
+        break;
+      }
+      bc = grp_sum_f64<LPN>((lt == bi % K) ? (bi >= K ? c[NFAM - 1] : c[0]) : 0.0);
+      if (lt == t % LPN) {
+        rec_i = bi;
+        rec_c = bc;
+      }
+      const int fi = bi / K, pi = bi % N, qi = (bi % K) / N;
+      // same family: only c_i changes (to zero); other family: X products
+#pragma unroll
+      for (int f = 0; f < NFAM; ++f) {
+        if (f == fi) {
+          c[f] = (lt == bi % K) ? 0.0 : c[f];
+        } else if constexpr (NFAM == 2) {
+          const double g = fi ? sX[pa][pi] * sX[qa][qi] : sX[pi][pa] * sX[qi][qa];
+          c[f] = fma(-bc, g, c[f]);
+        }
+      }
+      e = fma(-bc, bc, e);
+      ++t;
+      if (t % LPN == 0) {
+        lv.rec_idx[rec0 + (t - LPN) + lt] = rec_i;
+        lv.rec_coef[rec0 + (t - LPN) + lt] = rec_c;
+      }
+      if (e < eps2)
+        st = ST_ACC;
+      else if (t >= kmax)
+        st = ST_SPARSE;
+    }
+    if (lt < t % LPN) {
+      lv.rec_idx[rec0 + (t - t % LPN) + lt] = rec_i;
+      lv.rec_coef[rec0 + (t - t % LPN) + lt] = rec_c;
+    }
+    if (lt == 0) {
+      lv.e[node] = e;
+      lv.t[node] = t;
+      lv.st[node] = st;
+    }
+  }
+}
+
 template <int N, int NFAM>
 void launch_gram_n(const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t lg, const double* tab,
                    const double* xg, double* cbuf, int init_grid, int pur_grid, hipStream_t s) {
@@ -372,6 +527,18 @@ hipError_t launch_mp_gram(int n, const JobDev* jobs, LevelDev lv, const int32_t*
   if (nfam == 2 && !xg) return hipErrorInvalidValue;
   if (nfam != 1 && nfam != 2) return hipErrorInvalidValue;
   switch (n) {
+    case 4:
+      if (nfam == 2)
+        hipLaunchKernelGGL((k_gram_small<4, 2>), dim3(1024), dim3(256), 0, s, jobs, lv, count, lg, tab, xg);
+      else
+        hipLaunchKernelGGL((k_gram_small<4, 1>), dim3(1024), dim3(256), 0, s, jobs, lv, count, lg, tab, xg);
+      break;
+    case 8:
+      if (nfam == 2)
+        hipLaunchKernelGGL((k_gram_small<8, 2>), dim3(2048), dim3(256), 0, s, jobs, lv, count, lg, tab, xg);
+      else
+        hipLaunchKernelGGL((k_gram_small<8, 1>), dim3(2048), dim3(256), 0, s, jobs, lv, count, lg, tab, xg);
+      break;
     case 16:
       if (nfam == 2) launch_gram_n<16, 2>(jobs, lv, count, lg, tab, xg, cbuf, 2048, 2048, s);
       else launch_gram_n<16, 1>(jobs, lv, count, lg, tab, xg, cbuf, 2048, 2048, s);
