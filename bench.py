@@ -267,7 +267,8 @@ def main():
         psnr_g = psnr_jobs(codeg, imgs, w["jobs"])
         gram = dict(value=round(npx / secg / 1e6, 3), ms_per_step=round(secg * 1e3, 4), steps=args.steps,
                     mp_iters_per_s=round(stg["iters_executed"] / secg, 1), psnr_db=[round(p, 4) for p in psnr_g],
-                    leaves=int(sum(stg["leaves"])),
+                    leaves=int(sum(stg["leaves"])), iters_level={str(1 << l): int(v) for l, v in
+                                                                  enumerate(stg["iters_level"]) if v},
                     form="labelled variant: exact Gram-update MP in FP64 (not the dense per-step correlation)")
         codeg.free()
         log(f"gram fp64 batched (graph): {secg * 1e3:.3f} ms/step")

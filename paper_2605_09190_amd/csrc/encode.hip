@@ -431,7 +431,7 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
     if (whole_level(c, n)) {
       // Small blocks: each node's whole pursuit in one launch.
       if (c->opt.solver == AQMP_SOLVER_GRAM)
-        AQMP_LAUNCH(launch_mp_gram(n, c->djobs, a.lv, count, l, d->nfam, D.d_tab, D.d_xg, wk.cbuf, s));
+        AQMP_LAUNCH(launch_mp_gram(n, c->djobs, a.lv, count, &cnt->next[l], l, d->nfam, D.d_tab, D.d_xg, wk.cbuf, s));
       else if (n <= kFusedMaxN)
         AQMP_LAUNCH(launch_mp_fused(n, c->djobs, a.lv, count, l, D.m, D.d_tab, s));
       else

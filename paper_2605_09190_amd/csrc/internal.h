@@ -67,7 +67,7 @@ struct Counters {
   int32_t count[kLevels];   // nodes present at each level
   int32_t act[2];           // active-list lengths (ping-pong)
   int32_t scan_error;       // set if a bounded scan wait ran out
-  int32_t pad[7];
+  int32_t next[kLevels];    // work counter of the dynamically scheduled kernels per level
 };
 
 // Look-back scan bookkeeping: one 64-bit word per tile plus two counters.
@@ -115,8 +115,9 @@ hipError_t launch_pursuit16_bf16(const JobDev* jobs, LevelDev lv, const int32_t*
                                  const double* tab, const float* tabT32, hipStream_t s);
 // Gram form (FP64): correlations of every node of the level into cbuf
 // ([node][nfam * n * n]), then each node's whole pursuit by Gram updates.
-hipError_t launch_mp_gram(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t lg, int32_t nfam,
-                          const double* tab, const double* xg, double* cbuf, hipStream_t s);
+// `next` is a zero-initialised work counter the pursuit hands out nodes from.
+hipError_t launch_mp_gram(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int32_t lg,
+                          int32_t nfam, const double* tab, const double* xg, double* cbuf, hipStream_t s);
 hipError_t launch_decode(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t job,
                          int32_t nfam, const double* tab, void* out, int32_t dtype,
                          int64_t row_stride, hipStream_t s);

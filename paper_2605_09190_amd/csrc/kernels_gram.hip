@@ -238,7 +238,7 @@ __device__ inline void lane_best(const double (&c)[A], double& bc, int& bj) {
 
 template <int N, int NFAM>
 __global__ __launch_bounds__(256) void k_gram_pursuit(const JobDev* __restrict__ jobs, LevelDev lv,
-                                                      const int32_t* __restrict__ count_ptr, int32_t lg,
+                                                      const int32_t* __restrict__ count_ptr, int32_t* next, int32_t lg,
                                                       const double* __restrict__ xg, const double* __restrict__ cbuf) {
   using G = PurGeo<N, NFAM>;
   constexpr int K = G::K, M = G::M, TPN = G::TPN, WPN = G::WPN, APT = G::APT, NPW = G::NPW;
@@ -248,8 +248,9 @@ __global__ __launch_bounds__(256) void k_gram_pursuit(const JobDev* __restrict__
   __shared__ double sX[NX][NX + 1];       // X[p][p'] = <T_0[p], T_1[p']>
   __shared__ double sBc[2][4];            // per-wave best, double-buffered (N = 64)
   __shared__ int sBi[2][4];
+  __shared__ int sNode[2];                // node handed to the workgroup (N = 64), double-buffered
   const int tid = threadIdx.x, lane = tid & 63;
-  const int g = tid / TPN, tn = tid % TPN, wn = tn >> 6;
+  const int tn = tid % TPN, wn = tn >> 6;
   if constexpr (NFAM == 2)
     for (int i = tid; i < K; i += 256) sX[i / N][i % N] = xg[i];
   __syncthreads();
@@ -259,8 +260,26 @@ __global__ __launch_bounds__(256) void k_gram_pursuit(const JobDev* __restrict__
   // is j / AF.
   const int pa = tn % N;
   const int qb = tn / N;
-  int ph = 0;
-  for (int node = blockIdx.x * NPW + g; node < count; node += gridDim.x * NPW) {
+  int ph = 0, np = 0;
+  // Nodes are handed out one at a time from a counter: their pursuits differ
+  // in length by up to k steps, and neighbouring node indices (the same
+  // block in the channels of one image) tend to be long together.
+  for (;;) {
+    // N = 64: one thread fetches, the workgroup reads the value after the
+    // barrier.  Smaller blocks (one wave per node, short pursuits): a fixed
+    // grid-stride assignment, since a fetch per node would cost more than
+    // the imbalance it removes.
+    int node;
+    if constexpr (NPW == 1) {
+      if (tid == 0) sNode[np] = atomicAdd(next, 1);
+      __syncthreads();
+      node = sNode[np];
+      np ^= 1;
+    } else {
+      node = (blockIdx.x + gridDim.x * np) * NPW + (tid >> 6);
+      ++np;
+    }
+    if (node >= count) break;
     const JobDev& jb = jobs[lv.job[node]];
     const double eps2 = jb.eps2[lg];
     const int kmax = jb.k[lg];
@@ -308,19 +327,21 @@ __global__ __launch_bounds__(256) void k_gram_pursuit(const JobDev* __restrict__
         rec_i = bi;
         rec_c = bc;
       }
-      // c_a <- c_a - c_i <phi_a, phi_i>: a Kronecker delta within the chosen
-      // atom's family (only c_i itself changes, to zero); across families
+      // c_a <- c_a - c_i <phi_a, phi_i>.  Across families the Gram entry is
       // X[p_a][p_i] X[q_a][q_i] (or its transpose), exact for the constant
-      // atoms.
+      // atoms.  Within the chosen atom's family it is a Kronecker delta, so
+      // only c_i changes, to zero: c_j += z s_j with z = -c_i on the thread
+      // holding it (0 elsewhere) and s_j = [j = j_i] a scalar 0 or 1 gives
+      // exactly 0 there and leaves every other value unchanged, at one FMA
+      // per atom.
       const int fi = bi / K, pi = bi % N, qi = (bi % K) / N;
-      const bool mine = tn == bi % TPN;
-      const int jb_ = bi / TPN;
-#pragma unroll
-      for (int j = 0; j < APT; ++j)
-        if (j == jb_ && mine) c[j] = 0.0;
+      const double z = (tn == bi % TPN) ? -bc : 0.0;
+      const int jsel = __builtin_amdgcn_readfirstlane(bi / TPN);
       if constexpr (NFAM == 2) {
         if (fi == 0) {
           const double bv = -bc * sX[pi][pa];
+#pragma unroll
+          for (int j = 0; j < AF; ++j) c[j] = fma(z, j == jsel ? 1.0 : 0.0, c[j]);
 #pragma unroll
           for (int j = AF; j < APT; ++j) {
             const int qa = (qb + (TPN / N) * j) % N;
@@ -333,7 +354,12 @@ __global__ __launch_bounds__(256) void k_gram_pursuit(const JobDev* __restrict__
             const int qa = (qb + (TPN / N) * j) % N;
             c[j] = fma(bv, sX[qa][qi], c[j]);
           }
+#pragma unroll
+          for (int j = AF; j < APT; ++j) c[j] = fma(z, j == jsel ? 1.0 : 0.0, c[j]);
         }
+      } else {
+#pragma unroll
+        for (int j = 0; j < APT; ++j) c[j] = fma(z, j == jsel ? 1.0 : 0.0, c[j]);
       }
       e = fma(-bc, bc, e);
       ++t;
@@ -514,16 +540,17 @@ __global__ __launch_bounds__(256) void k_gram_small(const JobDev* __restrict__ j
 }
 
 template <int N, int NFAM>
-void launch_gram_n(const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t lg, const double* tab,
-                   const double* xg, double* cbuf, int init_grid, int pur_grid, hipStream_t s) {
+void launch_gram_n(const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int32_t lg,
+                   const double* tab, const double* xg, double* cbuf, int init_grid, int pur_grid, hipStream_t s) {
   hipLaunchKernelGGL((k_gram_init<N, NFAM>), dim3(init_grid), dim3(256), 0, s, jobs, lv, count, lg, tab, cbuf);
-  hipLaunchKernelGGL((k_gram_pursuit<N, NFAM>), dim3(pur_grid), dim3(256), 0, s, jobs, lv, count, lg, xg, cbuf);
+  hipLaunchKernelGGL((k_gram_pursuit<N, NFAM>), dim3(pur_grid), dim3(256), 0, s, jobs, lv, count, next, lg, xg,
+                     cbuf);
 }
 
 }  // namespace
 
-hipError_t launch_mp_gram(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t lg, int32_t nfam,
-                          const double* tab, const double* xg, double* cbuf, hipStream_t s) {
+hipError_t launch_mp_gram(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int32_t lg,
+                          int32_t nfam, const double* tab, const double* xg, double* cbuf, hipStream_t s) {
   if (nfam == 2 && !xg) return hipErrorInvalidValue;
   if (nfam != 1 && nfam != 2) return hipErrorInvalidValue;
   switch (n) {
@@ -540,16 +567,16 @@ hipError_t launch_mp_gram(int n, const JobDev* jobs, LevelDev lv, const int32_t*
         hipLaunchKernelGGL((k_gram_small<8, 1>), dim3(2048), dim3(256), 0, s, jobs, lv, count, lg, tab, xg);
       break;
     case 16:
-      if (nfam == 2) launch_gram_n<16, 2>(jobs, lv, count, lg, tab, xg, cbuf, 2048, 2048, s);
-      else launch_gram_n<16, 1>(jobs, lv, count, lg, tab, xg, cbuf, 2048, 2048, s);
+      if (nfam == 2) launch_gram_n<16, 2>(jobs, lv, count, next, lg, tab, xg, cbuf, 2048, 2048, s);
+      else launch_gram_n<16, 1>(jobs, lv, count, next, lg, tab, xg, cbuf, 2048, 2048, s);
       break;
     case 32:
-      if (nfam == 2) launch_gram_n<32, 2>(jobs, lv, count, lg, tab, xg, cbuf, 1024, 2048, s);
-      else launch_gram_n<32, 1>(jobs, lv, count, lg, tab, xg, cbuf, 1024, 2048, s);
+      if (nfam == 2) launch_gram_n<32, 2>(jobs, lv, count, next, lg, tab, xg, cbuf, 1024, 2048, s);
+      else launch_gram_n<32, 1>(jobs, lv, count, next, lg, tab, xg, cbuf, 1024, 2048, s);
       break;
     case 64:
-      if (nfam == 2) launch_gram_n<64, 2>(jobs, lv, count, lg, tab, xg, cbuf, 512, 1024, s);
-      else launch_gram_n<64, 1>(jobs, lv, count, lg, tab, xg, cbuf, 512, 1024, s);
+      if (nfam == 2) launch_gram_n<64, 2>(jobs, lv, count, next, lg, tab, xg, cbuf, 512, 1024, s);
+      else launch_gram_n<64, 1>(jobs, lv, count, next, lg, tab, xg, cbuf, 512, 1024, s);
       break;
     default:
       return hipErrorInvalidValue;

@@ -142,7 +142,10 @@ __global__ __launch_bounds__(256) void k_split_emit(SplitOp op, ScanState ss, in
 
 __global__ void k_init_counts(Counters* c, const int32_t* ntop) {
   const int i = threadIdx.x;
-  if (i < kLevels) c->count[i] = ntop[i];
+  if (i < kLevels) {
+    c->count[i] = ntop[i];
+    c->next[i] = 0;
+  }
   if (i < 2) c->act[i] = 0;
   if (i == 0) c->scan_error = 0;
 }
