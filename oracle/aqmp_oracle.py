@@ -19,6 +19,10 @@ Sources in the paper (AQMP, arXiv 2605.09190):
   the signal, arg-max of the absolute correlation, rank-1 residual update,
   stop when the residual norm falls below the tolerance or after k steps.
 * Algorithms 1-2 (encoder) and 3 (decoder) of Section 2.3.
+* Section 2.2 (the solver the authors' code ran) and the original OMP
+  definition it cites: Orthogonal Matching Pursuit selects as MP does, then
+  re-fits every selected coefficient by least squares; available as the
+  solver "omp" of the encoder.
 
 Readings taken where the paper is silent or inconsistent (each one is listed
 with its reason in the design notes of the repository):
@@ -189,6 +193,49 @@ def top2_gap(c_abs: np.ndarray, rep: np.ndarray, i: int) -> float:
     return float((c_abs[i] - max(second, 0.0)) / c_abs[i])
 
 
+def omp(dic: Dict, y: np.ndarray, eps2: float, k: int) -> MPResult:
+    """Orthogonal Matching Pursuit on one signal (Section 2.2; the OMP of the
+    cited Pati et al. paper).
+
+    ``r = y``, ``S = []``; before every iteration stop if ``||r||^2 < eps2``
+    (eq. (2), accuracy) or if ``|S| = k`` (eq. (2), sparsity); otherwise
+    ``c = D^T r``, ``i = argmax |c|`` (lowest index among equal values; a zero
+    maximum stops), ``S <- S + [i]``, ``x_S = argmin_x ||y - D_S x||_2`` (least
+    squares over the selected atoms), ``r = y - D_S x_S``.  ``coef`` holds the
+    final least-squares coefficients in selection order.
+    """
+    y = np.array(y, dtype=np.float64, copy=True)
+    r = y.copy()
+    out = MPResult()
+    sel: list[int] = []
+    x = np.zeros(0)
+    e = float(r @ r)
+    out.e.append(e)
+    while True:
+        if e < eps2:
+            out.stop = "accuracy"
+            break
+        if len(sel) >= k:
+            out.stop = "sparsity"
+            break
+        c = dic.Dt @ r
+        c_abs = np.abs(c)
+        i = int(np.argmax(c_abs))          # first maximal index
+        if c_abs[i] == 0.0:
+            out.stop = "zero"
+            break
+        out.gap.append(top2_gap(c_abs, dic.rep, i))
+        sel.append(i)
+        a = dic.D[:, sel]
+        x = np.linalg.lstsq(a, y, rcond=None)[0]
+        r = y - a @ x
+        e = float(r @ r)
+        out.e.append(e)
+    out.idx = list(sel)
+    out.coef = [float(v) for v in x[:len(sel)]]
+    return out
+
+
 def mp(dic: Dict, y: np.ndarray, eps2: float, k: int) -> MPResult:
     """Plain Matching Pursuit on one signal.
 
@@ -238,6 +285,7 @@ class Params:
     split_rule: str = "r1"         # "r1" accuracy not met ; "r2" ||x||_0 >= k literal
     k_per_level: dict | None = None
     families: int = DCT | HAAR
+    solver: str = "mp"             # "mp": Section 2.2 steps (a)-(d) ; "omp": least-squares refit
 
     def eps2(self, n: int) -> float:
         eps = self.tol * n if self.tol_mode == "rms" else self.tol
@@ -251,7 +299,7 @@ class Params:
     @staticmethod
     def from_dict(d: dict) -> "Params":
         keys = {"tol", "tol_mode", "max_atoms", "n_min", "n_max", "split_rule",
-                "k_per_level", "families"}
+                "k_per_level", "families", "solver"}
         return Params(**{k: v for k, v in d.items() if k in keys})
 
 
@@ -285,7 +333,7 @@ def encode_block(img: np.ndarray, p: Params, x0: int, y0: int, n: int,
     block = img[y0:y0 + n, x0:x0 + n]
     y = unravel(block)
     dic = get_dict(n, p.families)
-    res = mp(dic, y, p.eps2(n), p.k(n))
+    res = (omp if p.solver == "omp" else mp)(dic, y, p.eps2(n), p.k(n))
     sp = split_decision(p, n, res)
     nodes.append(Node(x0, y0, n, res, sp, p.eps2(n), float(y @ y)))
     if sp:

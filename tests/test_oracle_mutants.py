@@ -112,3 +112,42 @@ def test_inverted_split_rule_caught(monkeypatch):
         return n > p.n_min and res.e_final < p.eps2(n)   # planted: inverted test
     monkeypatch.setattr(O, "split_decision", bad_split)
     assert not pin_split_invariant()
+
+
+def pin_omp_sklearn(n=8):
+    from sklearn.linear_model import orthogonal_mp
+    rng = np.random.default_rng(4)
+    y = rng.normal(size=n * n)
+    d = O.get_dict(n)
+    res = O.omp(d, y, 0.0, 10)
+    x = np.zeros(d.m)
+    x[res.idx] = res.coef
+    return np.abs(orthogonal_mp(d.D, y, n_nonzero_coefs=10) - x).max() < 1e-10
+
+
+def test_omp_pin_holds_on_unpatched_oracle():
+    assert pin_omp_sklearn()
+
+
+def test_omp_without_refit_caught(monkeypatch):
+    """Planted: OMP that keeps MP's coefficients (no least-squares refit)."""
+    monkeypatch.setattr(O, "omp", lambda dic, y, eps2, k: O.mp(dic, y, eps2, k))
+    assert not pin_omp_sklearn()
+
+
+def test_omp_refit_on_last_atom_only_caught(monkeypatch):
+    """Planted: the refit solves only for the newest atom against the residual."""
+    def bad_omp(dic, y, eps2, k):
+        r = np.array(y, dtype=float)
+        out = O.MPResult()
+        out.e.append(float(r @ r))
+        while out.t < k:
+            c = dic.Dt @ r
+            i = int(np.argmax(np.abs(c)))
+            out.gap.append(0.0)
+            ci = float(dic.D[:, i] @ r)
+            r = r - ci * dic.D[:, i]
+            out.idx.append(i); out.coef.append(ci); out.e.append(float(r @ r))
+        return out
+    monkeypatch.setattr(O, "omp", bad_omp)
+    assert not pin_omp_sklearn()
