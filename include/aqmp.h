@@ -65,6 +65,7 @@ enum { AQMP_SCHED_PLAIN = 0, AQMP_SCHED_BATCHED = 1, AQMP_SCHED_CONCURRENT = 2 }
 #define AQMP_MAX_N 64
 #define AQMP_MAX_ATOMS 256     /* largest k (iterations per node)          */
 #define AQMP_CANDIDATES 8      /* candidates re-scored per MP iteration    */
+#define AQMP_OMP_MAX_ATOMS 64  /* largest k with AQMP_SOLVER_OMP            */
 
 typedef struct aqmp_dict aqmp_dict;
 typedef struct aqmp_code aqmp_code;
@@ -110,7 +111,7 @@ typedef struct {
 
 enum { AQMP_OPT_TIMING = 1, AQMP_OPT_STEPWISE = 2 };   /* aqmp_options.flags */
 
-enum { AQMP_SOLVER_DENSE = 0, AQMP_SOLVER_GRAM = 1 };   /* aqmp_options.solver */
+enum { AQMP_SOLVER_DENSE = 0, AQMP_SOLVER_GRAM = 1, AQMP_SOLVER_OMP = 2 };   /* aqmp_options.solver */
 
 typedef struct {
   int32_t precision;   /* AQMP_PREC_FP32: FP32 MFMA correlation;
@@ -149,7 +150,15 @@ typedef struct {
                           (precision and corr_variant do not apply; levels
                           with N <= 8 run the dense FP64 pursuit as in the
                           dense solver).  A labelled variant: the paper
-                          states the dense correlation. */
+                          states the dense correlation.
+                          AQMP_SOLVER_OMP: Orthogonal Matching Pursuit, the
+                          solver the authors' implementation ran (Section
+                          2.2): MP's selection, then all selected
+                          coefficients re-fit by least squares each step
+                          (FP64, Cholesky-updated; records hold the final
+                          coefficients in selection order).  k may not
+                          exceed AQMP_OMP_MAX_ATOMS; precision and
+                          corr_variant do not apply. */
   int32_t reserved[3];
 } aqmp_options;
 

@@ -30,7 +30,7 @@ PREC_FP32, PREC_BF16 = 0, 1
 SCHED_PLAIN, SCHED_BATCHED, SCHED_CONCURRENT = 0, 1, 2
 OPT_TIMING = 1
 OPT_STEPWISE = 2
-SOLVER_DENSE, SOLVER_GRAM = 0, 1
+SOLVER_DENSE, SOLVER_GRAM, SOLVER_OMP = 0, 1, 2
 MAX_ATOMS = 256
 CANDIDATES = 8
 

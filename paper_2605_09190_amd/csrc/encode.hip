@@ -116,7 +116,7 @@ int validate(const aqmp_dict* d, const aqmp_image* imgs, int n_imgs, const aqmp_
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: unknown option flags");
     if (opt->corr_variant < 0 || opt->corr_variant > 6)
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad corr_variant");
-    if (opt->solver != AQMP_SOLVER_DENSE && opt->solver != AQMP_SOLVER_GRAM)
+    if (opt->solver != AQMP_SOLVER_DENSE && opt->solver != AQMP_SOLVER_GRAM && opt->solver != AQMP_SOLVER_OMP)
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad solver");
   }
   for (int i = 0; i < n_imgs; ++i) {
@@ -140,9 +140,14 @@ int validate(const aqmp_dict* d, const aqmp_image* imgs, int n_imgs, const aqmp_
     for (int l = 0; l < kLevels; ++l)
       if (p.k_per_level[l] < -1 || p.k_per_level[l] > AQMP_MAX_ATOMS)
         AQMP_FAIL(AQMP_E_INVALID, tag + "k_per_level out of range");
-    for (int n = p.n_min; n <= p.n_max; n *= 2)
+    for (int n = p.n_min; n <= p.n_max; n *= 2) {
       if (!d->lv[ilog2(n)].have)
         AQMP_FAIL(AQMP_E_NODICT, tag + "the dictionary has no block size " + std::to_string(n));
+      const int kl = p.k_per_level[ilog2(n)] >= 0 ? p.k_per_level[ilog2(n)] : p.max_atoms;
+      if (opt && opt->solver == AQMP_SOLVER_OMP && kl > AQMP_OMP_MAX_ATOMS)
+        AQMP_FAIL(AQMP_E_INVALID, tag + "OMP supports at most " + std::to_string(AQMP_OMP_MAX_ATOMS) +
+                                      " atoms per node (k = " + std::to_string(kl) + ")");
+    }
   }
   for (int i = 0; i < n_jobs; ++i) {
     const aqmp_job& j = jobs[i];
@@ -249,7 +254,7 @@ void free_code(aqmp_code* c) {
 // (dense FP64 pursuit), N = 16 in the BF16 form (whole-level MFMA pursuit),
 // and every level of the Gram solver.
 static bool whole_level(const aqmp_code* c, int n) {
-  if (n <= kFusedMaxN || c->opt.solver == AQMP_SOLVER_GRAM) return true;
+  if (n <= kFusedMaxN || c->opt.solver != AQMP_SOLVER_DENSE) return true;
   return n == 16 && c->opt.precision == AQMP_PREC_BF16 && !(c->opt.flags & AQMP_OPT_STEPWISE);
 }
 
@@ -299,7 +304,7 @@ int build_plan(aqmp_code* c) {
       max_r[wi] = std::max(max_r[wi], pp.cap[l] * n * n);
       max_keys[wi] = std::max(max_keys[wi], pp.cap[l] * (D.m_pad / corr_atom_tile((int)n)) * kTopR);
       max_cap[wi] = std::max(max_cap[wi], pp.cap[l]);
-      if (c->opt.solver == AQMP_SOLVER_GRAM && n > kFusedMaxN)
+      if (c->opt.solver != AQMP_SOLVER_DENSE && n > kFusedMaxN)
         max_cbuf[wi] = std::max(max_cbuf[wi], pp.cap[l] * D.m);
       c->steps_launched += pp.kmax[l];
     }
@@ -330,7 +335,7 @@ int build_plan(aqmp_code* c) {
   c->work.resize(nwork);
   for (size_t wi = 0; wi < nwork; ++wi) {
     aqmp_code::Work& wk = c->work[wi];
-    if (c->opt.solver == AQMP_SOLVER_GRAM) {
+    if (c->opt.solver != AQMP_SOLVER_DENSE) {
       // No per-step launches: no residual, key or active-list buffers.
       ALLOC(wk.cbuf, max_cbuf[wi] * 8);
     } else {
@@ -430,7 +435,9 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
     if (le) AQMP_HIP(hipEventRecord(le->start, s));
     if (whole_level(c, n)) {
       // Small blocks: each node's whole pursuit in one launch.
-      if (c->opt.solver == AQMP_SOLVER_GRAM)
+      if (c->opt.solver == AQMP_SOLVER_OMP)
+        AQMP_LAUNCH(launch_omp(n, c->djobs, a.lv, count, &cnt->next[l], l, d->nfam, D.d_tab, D.d_xg, wk.cbuf, s));
+      else if (c->opt.solver == AQMP_SOLVER_GRAM)
         AQMP_LAUNCH(launch_mp_gram(n, c->djobs, a.lv, count, &cnt->next[l], l, d->nfam, D.d_tab, D.d_xg, wk.cbuf, s));
       else if (n <= kFusedMaxN)
         AQMP_LAUNCH(launch_mp_fused(n, c->djobs, a.lv, count, l, D.m, D.d_tab, s));

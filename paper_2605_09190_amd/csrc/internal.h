@@ -28,6 +28,7 @@ constexpr int kTopR = 8;          // keys kept per node per atom tile
 constexpr int kScanTile = 1024;   // items per block of the stable scans
 constexpr int kFusedMaxN = 8;     // levels up to this size run the fused per-node pursuit
 constexpr int kBranches = 4;      // parallel graph branches of the concurrent schedule
+constexpr int kOmpMaxAtoms = AQMP_OMP_MAX_ATOMS;   // OMP: selected atoms per node (LDS factor size)
 
 inline int ilog2(int n) {
   int l = 0;
@@ -118,6 +119,10 @@ hipError_t launch_pursuit16_bf16(const JobDev* jobs, LevelDev lv, const int32_t*
 // `next` is a zero-initialised work counter the pursuit hands out nodes from.
 hipError_t launch_mp_gram(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int32_t lg,
                           int32_t nfam, const double* tab, const double* xg, double* cbuf, hipStream_t s);
+// OMP (FP64): for N >= 16 the Gram initial correlations into cbuf, then the
+// pursuit with least-squares refits; N <= 8 in one launch.
+hipError_t launch_omp(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int32_t lg,
+                      int32_t nfam, const double* tab, const double* xg, double* cbuf, hipStream_t s);
 hipError_t launch_decode(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t job,
                          int32_t nfam, const double* tab, void* out, int32_t dtype,
                          int64_t row_stride, hipStream_t s);

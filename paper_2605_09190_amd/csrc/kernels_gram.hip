@@ -539,6 +539,261 @@ __global__ __launch_bounds__(256) void k_gram_small(const JobDev* __restrict__ j
   }
 }
 
+// ---------------------------------------------------------------------------
+// Orthogonal Matching Pursuit (the solver of the authors' implementation,
+// Section 2.2): the selection of MP, then every selected coefficient re-fit by
+// least squares, x_S = argmin ||y - D_S x||.  Computed in correlation space
+// with the same Gram structure:
+//   * L = the inverse of the Cholesky factor of the selected atoms' Gram
+//     matrix G_SS (lower triangular, in LDS), one new row per step: with
+//     g = G_{S,i} and w = L g, d = sqrt(1 - w.w), the row is (-w^T L, 1) / d;
+//   * z = L D_S^T y grows by z_t = (<y, phi_i> - w.z) / d, so
+//     ||r||^2 = ||y||^2 - ||z||^2 drops by z_t^2, and x_S = L^T z;
+//   * c = D^T r = c0 - G_{:,S} x_S: within a family the Gram column is a
+//     Kronecker delta (the selected atoms' own correlations are exactly zero,
+//     r being orthogonal to them), across families the X products.
+// One workgroup per node at every N (the per-step solves are small and
+// serial), nodes handed out from a counter.  c0 = D^T y comes from
+// k_gram_init for N >= 16 and is computed here for N <= 8.
+// ---------------------------------------------------------------------------
+template <int N, int NFAM>
+struct OmpGeo {
+  static constexpr int K = N * N;
+  static constexpr int M = NFAM * K;
+  static constexpr int APT = M >= 256 ? M / 256 : 1;   // atoms per thread: a = tid + 256 j
+  static constexpr int AF = APT / NFAM;                // per family when M >= 256
+  static constexpr bool SMALL = N <= 8;                // M <= 128: one atom per thread, c0 computed here
+};
+
+template <int N, int NFAM>
+__global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, LevelDev lv,
+                                             const int32_t* __restrict__ count_ptr, int32_t* next, int32_t lg,
+                                             const double* __restrict__ tab, const double* __restrict__ xg,
+                                             const double* __restrict__ cbuf) {
+  using G = OmpGeo<N, NFAM>;
+  constexpr int K = G::K, M = G::M, APT = G::APT, AF = G::AF;
+  constexpr bool SMALL = G::SMALL;
+  constexpr int KC = kOmpMaxAtoms;
+  constexpr int NX = NFAM == 2 ? N : 1;
+  __shared__ double sX[NX][NX + 1];                    // X[p][p'] = <T_0[p], T_1[p']>
+  __shared__ double sT[SMALL ? NFAM : 1][SMALL ? K : 1];
+  __shared__ double sY[SMALL ? K : 1];
+  __shared__ double sL[KC][KC + 1];                    // L = chol(G_SS)^-1, lower triangular
+  __shared__ int sS[KC];                               // selected atoms in order
+  __shared__ double sZ[KC], sXc[KC], sG[KC], sW[KC];   // z, x_S, g, w
+  __shared__ double sBc[2][4];
+  __shared__ int sBi[2][4];
+  __shared__ double sScal[4];                          // <y, phi_i>, 1 / d, new ||r||^2, dependence flag
+  __shared__ double sRed[2];
+  __shared__ int sNode[2];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if constexpr (NFAM == 2)
+    for (int i = tid; i < K; i += 256) sX[i / N][i % N] = xg[i];
+  if constexpr (SMALL)
+    for (int i = tid; i < NFAM * K; i += 256) (&sT[0][0])[i] = tab[i];
+  __syncthreads();
+  const int count = *count_ptr;
+  const int pa = tid % N;                              // p of every atom of this thread (256 = 0 mod N)
+  int ph = 0, np = 0;
+  for (;;) {
+    if (tid == 0) sNode[np] = atomicAdd(next, 1);
+    __syncthreads();
+    const int node = sNode[np];
+    np ^= 1;
+    if (node >= count) break;
+    const JobDev& jb = jobs[lv.job[node]];
+    const double eps2 = jb.eps2[lg];
+    const int kmax = jb.k[lg];
+    double e;
+    uint8_t st;
+    double c0[APT], c[APT];
+    if constexpr (SMALL) {
+      // gather (pixel k in thread k), ||y||^2, sum y, first stop test, c0
+      double v = 0.0;
+      if (tid < K) {
+        const int64_t idx = (int64_t)(lv.y0[node] + tid / N) * jb.row_stride + lv.x0[node] + tid % N;
+        v = jb.dtype == AQMP_F64 ? ((const double*)jb.img)[idx] : (double)((const float*)jb.img)[idx];
+        sY[tid] = v;
+      }
+      if (wv == 0) {
+        const double ee = wave_sum_f64(v * v), ss = wave_sum_f64(v);
+        if (lane == 0) {
+          sRed[0] = ee;
+          sRed[1] = ss;
+        }
+      }
+      __syncthreads();
+      e = sRed[0];
+      const double ssum = sRed[1];
+      st = e < eps2 ? ST_ACC : (kmax <= 0 ? ST_SPARSE : ST_RUN);
+      double acc = 0.0;
+      if (tid < M) {
+        const int f = tid / K, q = (tid % K) / N;
+#pragma unroll
+        for (int y = 0; y < N; ++y) {
+          double u = 0.0;
+#pragma unroll
+          for (int x = 0; x < N; ++x) u = fma(sT[f][q * N + x], sY[y * N + x], u);
+          acc = fma(sT[f][pa * N + y], u, acc);
+        }
+        if (tid % K == 0) acc = ssum / N;
+      }
+      c0[0] = acc;
+    } else {
+      e = lv.e[node];
+      st = lv.st[node];
+      const double* cn = cbuf + (size_t)node * M;
+#pragma unroll
+      for (int j = 0; j < APT; ++j) c0[j] = cn[tid + 256 * j];
+    }
+#pragma unroll
+    for (int j = 0; j < APT; ++j) c[j] = c0[j];
+    uint32_t selm = 0;   // bit j: atom tid + 256 j is selected
+    int t = 0;
+    while (st == ST_RUN) {
+      // (1) arg-max |c| (lowest index on ties); selected atoms hold exact zeros
+      double bc;
+      int bj;
+      lane_best(c, bc, bj);
+      int bi = tid + 256 * bj;
+      if (bi >= M) bi = M;   // threads without atoms (N <= 8) hold c = 0
+      wave_best(bc, bi, bc, bi);
+      if (lane == 0) {
+        sBc[ph][wv] = bc;
+        sBi[ph][wv] = bi;
+      }
+      __syncthreads();
+      bc = sBc[ph][0];
+      bi = sBi[ph][0];
+#pragma unroll
+      for (int q = 1; q < 4; ++q) {
+        const double oc = sBc[ph][q];
+        const int oi = sBi[ph][q];
+        if (fabs(oc) > fabs(bc) || (fabs(oc) == fabs(bc) && oi < bi)) {
+          bc = oc;
+          bi = oi;
+        }
+      }
+      ph ^= 1;
+      if (bc == 0.0) {
+        st = ST_ZERO;
+        break;
+      }
+      const int fi = bi / K, pi = bi % N, qi = (bi % K) / N;
+      // (2) <y, phi_i> from its thread; g_r = <phi_{S_r}, phi_i>
+      if (tid == bi % 256) {
+        double v0 = c0[0];
+#pragma unroll
+        for (int j = 1; j < APT; ++j) v0 = (j == bi / 256) ? c0[j] : v0;
+        sScal[0] = v0;
+      }
+      if (tid < t) {
+        const int as = sS[tid];
+        const int fs = as / K, ps = as % N, qs = (as % K) / N;
+        double g = 0.0;
+        if constexpr (NFAM == 2)
+          if (fs != fi) g = fi == 0 ? sX[pi][ps] * sX[qi][qs] : sX[ps][pi] * sX[qs][qi];
+        sG[tid] = g;
+      }
+      __syncthreads();
+      // (3) w = L g, d, z_t, new ||r||^2 (one wave; t <= 64)
+      if (wv == 0) {
+        double wr = 0.0;
+        if (lane < t) {
+          for (int cc = 0; cc <= lane; ++cc) wr = fma(sL[lane][cc], sG[cc], wr);
+          sW[lane] = wr;
+        }
+        const double s1 = wave_sum_f64(wr * wr);
+        const double s2 = wave_sum_f64(lane < t ? wr * sZ[lane] : 0.0);
+        if (lane == 0) {
+          const double d2 = 1.0 - s1;
+          const bool dep = !(d2 > 1e-24);
+          const double d = dep ? 1.0 : sqrt(d2);
+          const double zt = (sScal[0] - s2) / d;
+          sZ[t] = zt;
+          sS[t] = bi;
+          sScal[1] = 1.0 / d;
+          sScal[2] = fma(-zt, zt, e);
+          sScal[3] = dep ? 1.0 : 0.0;
+        }
+      }
+      __syncthreads();
+      if (sScal[3] != 0.0) {   // chosen atom (numerically) in the span of the selected ones
+        st = ST_ZERO;
+        break;
+      }
+      // (4) new row t of L
+      const double invd = sScal[1];
+      if (tid < t) {
+        double acc = 0.0;
+        for (int r = tid; r < t; ++r) acc = fma(sW[r], sL[r][tid], acc);
+        sL[t][tid] = -acc * invd;
+      } else if (tid == t) {
+        sL[t][t] = invd;
+      }
+      e = sScal[2];
+      ++t;
+      if (tid == bi % 256) selm |= 1u << (bi / 256);
+      __syncthreads();
+      // (5) x_S = L^T z
+      if (tid < t) {
+        double acc = 0.0;
+        for (int r = tid; r < t; ++r) acc = fma(sL[r][tid], sZ[r], acc);
+        sXc[tid] = acc;
+      }
+      __syncthreads();
+      if (e < eps2)
+        st = ST_ACC;
+      else if (t >= kmax)
+        st = ST_SPARSE;
+      if (st != ST_RUN) break;
+      // (6) c = c0 - G_{:,S} x_S
+#pragma unroll
+      for (int j = 0; j < APT; ++j) c[j] = c0[j];
+      if constexpr (NFAM == 2) {
+        for (int s = 0; s < t; ++s) {
+          const int as = sS[s];
+          const double xs = sXc[s];
+          const int fs = as / K, ps = as % N, qs = (as % K) / N;
+          if constexpr (SMALL) {
+            const int fa = tid / K, qa = (tid % K) / N;
+            if (tid < M && fa != fs) {
+              const double g = fs == 0 ? sX[ps][pa] * sX[qs][qa] : sX[pa][ps] * sX[qa][qs];
+              c[0] = fma(-xs, g, c[0]);
+            }
+          } else if (fs == 0) {   // atoms of family 1: <T_1[p], T_0[ps]> = X[ps][p]
+            const double al = xs * sX[ps][pa];
+#pragma unroll
+            for (int j = AF; j < APT; ++j) {
+              const int qa = ((tid + 256 * j) % K) / N;
+              c[j] = fma(-al, sX[qs][qa], c[j]);
+            }
+          } else {                // atoms of family 0: X[p][ps]
+            const double al = xs * sX[pa][ps];
+#pragma unroll
+            for (int j = 0; j < AF; ++j) {
+              const int qa = ((tid + 256 * j) % K) / N;
+              c[j] = fma(-al, sX[qa][qs], c[j]);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < APT; ++j) c[j] = ((selm >> j) & 1u) ? 0.0 : c[j];
+    }
+    // records: the atoms in selection order with their final coefficients
+    if (tid < t) {
+      lv.rec_idx[(size_t)node * lv.kmax + tid] = sS[tid];
+      lv.rec_coef[(size_t)node * lv.kmax + tid] = sXc[tid];
+    }
+    if (tid == 0) {
+      lv.e[node] = e;
+      lv.t[node] = t;
+      lv.st[node] = st;
+    }
+  }
+}
+
 template <int N, int NFAM>
 void launch_gram_n(const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int32_t lg,
                    const double* tab, const double* xg, double* cbuf, int init_grid, int pur_grid, hipStream_t s) {
@@ -581,6 +836,38 @@ hipError_t launch_mp_gram(int n, const JobDev* jobs, LevelDev lv, const int32_t*
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_omp(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int32_t lg,
+                      int32_t nfam, const double* tab, const double* xg, double* cbuf, hipStream_t s) {
+  if (nfam == 2 && !xg) return hipErrorInvalidValue;
+  if (nfam != 1 && nfam != 2) return hipErrorInvalidValue;
+#define AQMP_OMP(NN)                                                                                            \
+  case NN:                                                                                                     \
+    if (NN >= 16) {                                                                                            \
+      if (nfam == 2)                                                                                           \
+        hipLaunchKernelGGL((k_gram_init<NN >= 16 ? NN : 16, 2>), dim3(NN == 64 ? 512 : 1024), dim3(256), 0, s, \
+                           jobs, lv, count, lg, tab, cbuf);                                                    \
+      else                                                                                                     \
+        hipLaunchKernelGGL((k_gram_init<NN >= 16 ? NN : 16, 1>), dim3(NN == 64 ? 512 : 1024), dim3(256), 0, s, \
+                           jobs, lv, count, lg, tab, cbuf);                                                    \
+    }                                                                                                          \
+    if (nfam == 2)                                                                                             \
+      hipLaunchKernelGGL((k_omp<NN, 2>), dim3(1024), dim3(256), 0, s, jobs, lv, count, next, lg, tab, xg, cbuf); \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_omp<NN, 1>), dim3(1024), dim3(256), 0, s, jobs, lv, count, next, lg, tab, xg, cbuf); \
+    break;
+  switch (n) {
+    AQMP_OMP(4)
+    AQMP_OMP(8)
+    AQMP_OMP(16)
+    AQMP_OMP(32)
+    AQMP_OMP(64)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef AQMP_OMP
   return hipGetLastError();
 }
 

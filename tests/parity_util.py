@@ -57,19 +57,26 @@ def gpu_nodes_by_key(exp, job: int) -> dict:
     return out
 
 
-def _is_near_tie_member(img, nd: O.Node, t: int, gpu_atom: int, families: int) -> bool:
-    """Replays the oracle's MP on the node up to step t and checks that the GPU's
-    atom is within the 1e-6 relative window of the best |correlation|."""
+def _is_near_tie_member(img, nd: O.Node, t: int, gpu_atom: int, families: int, solver: str = "mp") -> bool:
+    """Replays the oracle's pursuit on the node up to step t and checks that the
+    GPU's atom is within the 1e-6 relative window of the best |correlation|
+    (MP: the rank-1 updates; OMP: the least-squares residual of the first t
+    atoms)."""
     dic = O.get_dict(nd.n, families)
-    r = O.unravel(img[nd.y0:nd.y0 + nd.n, nd.x0:nd.x0 + nd.n]).copy()
-    for i, c in zip(nd.mp.idx[:t], nd.mp.coef[:t]):
-        r = r - c * dic.D[:, i]
+    y = O.unravel(img[nd.y0:nd.y0 + nd.n, nd.x0:nd.x0 + nd.n]).astype(np.float64)
+    if solver == "omp":
+        sel = list(nd.mp.idx[:t])
+        r = y - dic.D[:, sel] @ np.linalg.lstsq(dic.D[:, sel], y, rcond=None)[0] if sel else y.copy()
+    else:
+        r = y.copy()
+        for i, c in zip(nd.mp.idx[:t], nd.mp.coef[:t]):
+            r = r - c * dic.D[:, i]
     c = np.abs(dic.Dt @ r)
     return c[gpu_atom] >= c.max() * (1.0 - GAP_TIE)
 
 
 def compare_job(img, onodes: list, gpu: dict, coef_tol: float, n_max: int, families: int = O.DCT | O.HAAR,
-                rep: Report | None = None) -> Report:
+                rep: Report | None = None, solver: str = "mp") -> Report:
     """Compares the oracle's visited nodes (one job; possibly a subset of top
     blocks) with the GPU's nodes of that job."""
     rep = rep or Report()
@@ -98,7 +105,7 @@ def compare_job(img, onodes: list, gpu: dict, coef_tol: float, n_max: int, famil
         diverged = False
         for t in range(min(len(o_idx), len(g_idx))):
             if o_idx[t] != g_idx[t]:
-                if nd.mp.gap[t] < GAP_TIE and _is_near_tie_member(img, nd, t, g_idx[t], families):
+                if nd.mp.gap[t] < GAP_TIE and _is_near_tie_member(img, nd, t, g_idx[t], families, solver):
                     rep.atom_ties += 1
                     excluded.append(key)
                 else:
