@@ -29,18 +29,18 @@ PEAK_FP32_TFLOPS = 157.3      # MI355X dense FP32 MFMA
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs, scaled by a copy-kernel calibration
 # (profiles/traffic_k_corr_bf16_gen64_2048x2048x3_ycbcr.md); valid only for
-# the kernel source they were taken on.
+# the kernel source and the workload they were taken on.
 TRAFFIC = {
-    "k_corr_bf16_gen<64>": dict(bytes_per_launch=15.69e6, fetch=13.28e6, write=2.41e6,
+    "k_corr_bf16_gen<64>": dict(bytes_per_launch=15.69e6, fetch=13.28e6, write=2.41e6, workload="c3",
                                 src="paper_2605_09190_amd/csrc/kernels_corr.hip",
                                 sha256="b3775b1b9612aaa553e2368099a2a8d2248cdbfc322bcf852338f0733eb8661e"),
 }
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload):
     import hashlib
     t = TRAFFIC.get(kernel)
-    if t is None:
+    if t is None or t["workload"] != workload:
         return None
     with open(os.path.join(ROOT, t["src"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
@@ -81,7 +81,7 @@ def psnr_jobs(code, imgs, jobs):
     return out
 
 
-def roofline(stats, timing, precision, kernel_name=None):
+def roofline(stats, timing, precision, kernel_name=None, workload=None):
     """Dominant kernel: the correlation of the largest block size.  Algorithmic
     work per node-iteration is 2*K*M = 4 N^4 flops (every atom correlated with
     the residual); one launch processes the nodes active in that MP step."""
@@ -105,7 +105,7 @@ def roofline(stats, timing, precision, kernel_name=None):
                                       avg_corr_us=round(1e3 * timing["corr_ms"][l] / max(1, timing["steps"][l]), 2))
     kname = kernel_name(n) if kernel_name else f"correlation<N={n}>"
     return dict(bound="mfma", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
-                frac=round(achieved / peak, 4), traffic=measured_traffic(kname), traffic_unit="bytes per launch",
+                frac=round(achieved / peak, 4), traffic=measured_traffic(kname, workload), traffic_unit="bytes per launch",
                 kernel=kname,
                 avg_launch_us=round(1e3 * ms / max(1, steps), 2), launches=int(steps),
                 flops_per_unit=4 * n ** 4, units=int(stats["iters_level"][lg]), per_level=per_level)
@@ -130,17 +130,16 @@ def cpu_baseline(w, budget_s=15.0):
     from threadpoolctl import threadpool_limits
     from oracle import aqmp_oracle as O
     _ORACLE_CHANS = w["channels"]
-    prm = dict(w["params"][0])
-    nmax = prm["n_max"]
     cores = max(1, min(16, len(os.sched_getaffinity(0))))
-    for n in (8, 16, 32, 64):
-        if prm["n_min"] <= n <= nmax:
-            O.get_dict(n)        # built once, shared with the workers by fork
+    sizes = sorted({n for p in w["params"] for n in (4, 8, 16, 32, 64) if p["n_min"] <= n <= p["n_max"]})
+    for n in sizes:
+        O.get_dict(n)            # built once, shared with the workers by fork
     rng = np.random.default_rng(1234)
     blocks = []
-    for j, (ci, _) in enumerate(w["jobs"]):
+    for j, (ci, pi) in enumerate(w["jobs"]):
+        prm = dict(w["params"][pi])
         h, wd = w["channels"][ci].shape
-        for (x0, y0) in O.top_blocks(h, wd, nmax):
+        for (x0, y0) in O.top_blocks(h, wd, prm["n_max"]):
             blocks.append((ci, x0, y0, prm))
     order = rng.permutation(len(blocks))
     # calibrate on a few blocks, then size the sample to the time budget
@@ -153,13 +152,16 @@ def cpu_baseline(w, budget_s=15.0):
             per_round = max(t1, 1e-3)
             rounds = max(1, int(round(budget_s / per_round)))
             rest = [blocks[i] for i in order[cores:cores * (1 + rounds)]]
-            t2 = time.perf_counter()
-            it2 = pool.map(_oracle_block, rest)
-            t3 = time.perf_counter() - t2
+            if rest:
+                t2 = time.perf_counter()
+                it2 = pool.map(_oracle_block, rest)
+                t3 = time.perf_counter() - t2
+            else:                 # the calibration round already covered every block
+                rest, it2, t3 = calib, it, t1
     nb = len(rest)
-    px = nb * nmax * nmax
+    px = sum(b[3]["n_max"] ** 2 for b in rest)
     return dict(value=round(px / t3 / 1e6, 6), unit="Mpixel/s", cores=cores, kind="oracle",
-                sample=f"{nb} of {len(blocks)} top-level {nmax}x{nmax} blocks (seed 1234), all levels below them, "
+                sample=f"{nb} of {len(blocks)} top-level blocks ({px} pixels; seed 1234), all levels below them, "
                        f"FP64 NumPy, one process per core, {t3:.1f} s",
                 mp_iters_per_s=round(sum(it2) / t3, 1))
 
@@ -223,6 +225,7 @@ def main():
     sec = time_steps(code, imgs, args.steps, args.warmup)
     stats = code.stats()
     psnr_b = psnr_jobs(code, imgs, w["jobs"])
+    code.free()   # every form below allocates its own buffers
     log(f"bf16 batched (graph): {sec * 1e3:.3f} ms/step")
 
     # Kernel durations: the same batched launch sequence with HIP events
@@ -233,7 +236,7 @@ def main():
                     timing=True, corr_variant=args.corr_variant)
     sec_t = time_steps(code_t, imgs, args.steps, args.warmup)
     roof = roofline(code_t.stats(), code_t.timing(), A.PREC_BF16,
-                    lambda n: A.corr_kernel(n, A.PREC_BF16, args.corr_variant))
+                    lambda n: A.corr_kernel(n, A.PREC_BF16, args.corr_variant), workload=args.workload)
     code_t.free()
     log(f"bf16 batched (stream, timed): {sec_t * 1e3:.3f} ms/step, corr {roof['achieved']} TFLOP/s")
 
@@ -325,7 +328,6 @@ def main():
     if fp32:
         res["speedup_vs_fp32_plain"] = round(value / fp32["value"], 2)
         res["max_abs_psnr_delta_db"] = round(max(abs(a - b) for a, b in zip(psnr_b, fp32["psnr_db"])), 5)
-    code.free()
     dic.free()
     if cpu is not None:
         res["cpu_baseline"] = cpu
