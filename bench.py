@@ -114,7 +114,7 @@ def roofline(stats, timing, precision, kernel_name=None, workload=None):
 def _oracle_block(args):
     ci, x0, y0, prm = args
     from oracle import aqmp_oracle as O
-    img = _ORACLE_CHANS[ci]
+    img = O.pad_edge(np.asarray(_ORACLE_CHANS[ci], dtype=np.float64), prm["n_max"])
     nodes = O.encode_block(img, O.Params.from_dict(prm), x0, y0, prm["n_max"])
     return sum(nd.mp.t for nd in nodes)
 

@@ -45,7 +45,7 @@ enum {
   AQMP_OK = 0,
   AQMP_E_INVALID = -1,   /* null pointer, bad enum, n not a power of two,
                             n_min > n_max, tol < 0, k out of range ...     */
-  AQMP_E_SHAPE = -2,     /* width or height not a multiple of n_max        */
+  AQMP_E_SHAPE = -2,     /* reserved (non-multiple sizes are padded)      */
   AQMP_E_NODICT = -3,    /* the dictionary lacks a block size the jobs use */
   AQMP_E_NOMEM = -4,     /* device or host allocation failed, or the
                             AQMP_MAX_DEVICE_BYTES environment cap is hit   */
@@ -216,7 +216,11 @@ int aqmp_dictionary_copy(const aqmp_dict* d, int n, double* host_out);
 /* ---- encoder (Algorithms 1-2, MP of Section 2.2) ----------------------- */
 
 /* Encodes n_jobs jobs.  Every image, parameter set and job is validated on
- * the host first (AQMP_E_INVALID, AQMP_E_SHAPE, AQMP_E_NODICT).  The call
+ * the host first (AQMP_E_INVALID, AQMP_E_NODICT).  A plane whose width or
+ * height is not a multiple of the job's n_max is tiled as if padded up to
+ * the next multiple by repeating its last row and column; the padding's
+ * blocks are coded like the others and aqmp_decode writes only the image's
+ * own pixels.  The call
  * allocates the code's device buffers (worst case for these shapes), then
  * enqueues the encode on hip_stream and returns; *out is valid once that
  * stream's work has completed (the aqmp_code_* readers synchronise it).

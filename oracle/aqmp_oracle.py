@@ -43,7 +43,11 @@ with its reason in the design notes of the repository):
   ties exactly; arg-max ties go to the lowest atom index;
 * stop when the largest absolute correlation is exactly zero;
 * children encode the original pixels of their quadrant (Algorithm 2
-  recurses on the block ``b``) in the order TL, TR, BL, BR.
+  recurses on the block ``b``) in the order TL, TR, BL, BR;
+* a plane whose width or height is not a multiple of N_max is padded up to
+  the next multiple by repeating its last row and column; the padding's
+  blocks are coded like any other and the decoder keeps the image's own
+  pixels.
 """
 from __future__ import annotations
 
@@ -343,17 +347,23 @@ def encode_block(img: np.ndarray, p: Params, x0: int, y0: int, n: int,
     return nodes
 
 
+def pad_edge(img: np.ndarray, n: int) -> np.ndarray:
+    """The plane padded up to a multiple of ``n`` in both directions by
+    repeating its last row and column."""
+    h, w = img.shape
+    return np.pad(img, ((0, -h % n), (0, -w % n)), mode="edge")
+
+
 def top_blocks(h: int, w: int, n_max: int) -> list[tuple[int, int]]:
-    """Top-level blocks of size n_max in raster order, as (x0, y0)."""
-    if h % n_max or w % n_max:
-        raise ValueError("image size must be a multiple of n_max")
+    """Top-level blocks of size n_max in raster order, as (x0, y0), over the
+    plane padded up to a multiple of n_max."""
     return [(x, y) for y in range(0, h, n_max) for x in range(0, w, n_max)]
 
 
 def encode_channel(img: np.ndarray, p: Params, blocks=None) -> list[Node]:
     """Algorithm 2 started at N_max on every top-level block (or on the given
     subset of top-level blocks)."""
-    img = np.asarray(img, dtype=np.float64)
+    img = pad_edge(np.asarray(img, dtype=np.float64), p.n_max)
     if blocks is None:
         blocks = top_blocks(img.shape[0], img.shape[1], p.n_max)
     nodes: list[Node] = []
@@ -374,14 +384,17 @@ def leaves(nodes: list[Node]) -> list[Node]:
 def decode(nodes: list[Node], h: int, w: int, families: int = DCT | HAAR) -> np.ndarray:
     """Algorithm 3: every leaf's block is ``unravel^-1(D_N x)`` placed at its
     position.  Pixels not covered by a leaf stay zero."""
-    out = np.zeros((h, w))
-    for nd in leaves(nodes):
+    lv = leaves(nodes)
+    hp = max([h] + [nd.y0 + nd.n for nd in lv])
+    wp = max([w] + [nd.x0 + nd.n for nd in lv])
+    out = np.zeros((hp, wp))
+    for nd in lv:
         dic = get_dict(nd.n, families)
         x = np.zeros(dic.m)
         for i, c in zip(nd.mp.idx, nd.mp.coef):
             x[i] += c
         out[nd.y0:nd.y0 + nd.n, nd.x0:nd.x0 + nd.n] = unravel_inv(dic.D @ x, nd.n)
-    return out
+    return out[:h, :w]
 
 
 def psnr(ref: np.ndarray, rec: np.ndarray, peak: float = 1.0) -> float:

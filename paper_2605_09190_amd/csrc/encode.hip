@@ -95,6 +95,10 @@ namespace {
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// Image extent rounded up to a multiple of the top-level block size: the
+// blocks tile the padded plane (edge replication, see job_pixel).
+int64_t padded(int v, int n) { return ((int64_t)v + n - 1) / n * n; }
+
 int k_of(const aqmp_params& p, int lg) {
   const int k = p.k_per_level[lg];
   return k >= 0 ? k : p.max_atoms;
@@ -153,11 +157,6 @@ int validate(const aqmp_dict* d, const aqmp_image* imgs, int n_imgs, const aqmp_
     const aqmp_job& j = jobs[i];
     if (j.image < 0 || j.image >= n_imgs || j.params < 0 || j.params >= n_prm)
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: job " + std::to_string(i) + " refers to a missing image or params");
-    const aqmp_image& im = imgs[j.image];
-    const aqmp_params& p = prm[j.params];
-    if (im.w % p.n_max || im.h % p.n_max)
-      AQMP_FAIL(AQMP_E_SHAPE, "aqmp_encode: job " + std::to_string(i) + ": image " + std::to_string(im.w) + "x" +
-                                  std::to_string(im.h) + " is not a multiple of n_max " + std::to_string(p.n_max));
   }
   return AQMP_OK;
 }
@@ -199,12 +198,13 @@ void plan_pass(const aqmp_code* c, int j0, int j1, PassPlan& pp) {
     const int hi = ilog2(p.n_max), lo = ilog2(p.n_min);
     pp.lg_hi = std::max(pp.lg_hi, hi);
     pp.lg_lo = std::min(pp.lg_lo, lo);
+    const int64_t wp = padded(im.w, p.n_max), hp = padded(im.h, p.n_max);
     for (int l = lo; l <= hi; ++l) {
       const int64_t n = 1 << l;
-      pp.cap[l] += (int64_t)(im.w / n) * (im.h / n);
+      pp.cap[l] += (wp / n) * (hp / n);
       pp.kmax[l] = std::max(pp.kmax[l], k_of(p, l));
     }
-    pp.ntop[hi] += (im.w >> hi) * (im.h >> hi);
+    pp.ntop[hi] += (int32_t)((wp >> hi) * (hp >> hi));
   }
 }
 
@@ -216,8 +216,8 @@ void top_nodes(const aqmp_code* c, const PassPlan& pp, int lg, std::vector<int32
     const aqmp_image& im = c->imgs[c->jobs[j].image];
     const aqmp_params& p = c->prm[c->jobs[j].params];
     if (p.n_max != n) continue;
-    for (int y = 0; y < im.h; y += n)
-      for (int x = 0; x < im.w; x += n) {
+    for (int y = 0; y < padded(im.h, n); y += n)
+      for (int x = 0; x < padded(im.w, n); x += n) {
         job.push_back(j);
         x0.push_back(x);
         y0.push_back(y);

@@ -49,6 +49,16 @@ struct JobDev {
   int32_t pad;
 };
 
+// Pixel (y, x) of a job's plane in FP64.  Blocks tile the plane padded up
+// to a multiple of N_max; rows and columns past the image repeat its last
+// row and column (edge replication).
+__device__ inline double job_pixel(const JobDev& jb, int y, int x) {
+  y = y < jb.h ? y : jb.h - 1;
+  x = x < jb.w ? x : jb.w - 1;
+  const int64_t idx = (int64_t)y * jb.row_stride + x;
+  return jb.dtype == AQMP_F64 ? ((const double*)jb.img)[idx] : (double)((const float*)jb.img)[idx];
+}
+
 // Device-side arrays of one quadtree level (block size N = 1 << lg).  The
 // node arrays are shared by all passes; a pass owns [base, base + cap).
 struct LevelDev {

@@ -71,8 +71,7 @@ __global__ __launch_bounds__(256) void k_mp_fused(const JobDev* __restrict__ job
     const int k = jb.k[lg];
     // gather (Algorithm 2: y = unravel(b))
     const int y = lt / N, x = lt % N;
-    const int64_t idx = (int64_t)(lv.y0[nd] + y) * jb.row_stride + lv.x0[nd] + x;
-    double r = jb.dtype == AQMP_F64 ? ((const double*)jb.img)[idx] : (double)((const float*)jb.img)[idx];
+    double r = job_pixel(jb, lv.y0[nd] + y, lv.x0[nd] + x);
     double e = grp_sum<TPN>(r * r);
     int t = 0;
     uint8_t st = ST_RUN;
@@ -247,12 +246,10 @@ __global__ __launch_bounds__(256, 1) void k_pursuit16_bf16(const JobDev* __restr
 #pragma unroll
       for (int dy = 0; dy < 2; ++dy) {
         const int y = 2 * part + dy;
-        const int64_t row = (int64_t)(by + y) * jb.row_stride + bx;
         float f[N];
 #pragma unroll
         for (int x = 0; x < N; ++x) {
-          const double v = jb.dtype == AQMP_F64 ? ((const double*)jb.img)[row + x]
-                                                : (double)((const float*)jb.img)[row + x];
+          const double v = job_pixel(jb, by + y, bx + x);
           f[x] = (float)v;
           e += v * v;
         }

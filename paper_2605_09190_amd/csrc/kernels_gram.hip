@@ -98,8 +98,7 @@ __global__ __launch_bounds__(256) void k_gram_init(const JobDev* __restrict__ jo
 #pragma unroll
       for (int i = tn; i < K; i += TPN) {
         const int y = i / N, x = i % N;
-        const int64_t idx = (int64_t)(by + y) * jb->row_stride + bx + x;
-        const double v = jb->dtype == AQMP_F64 ? ((const double*)jb->img)[idx] : (double)((const float*)jb->img)[idx];
+        const double v = job_pixel(*jb, by + y, bx + x);
         sY[g][sw<N>(y, x)] = v;
         e = fma(v, v, e);
         s += v;
@@ -457,8 +456,7 @@ __global__ __launch_bounds__(256) void k_gram_small(const JobDev* __restrict__ j
     const JobDev& jb = jobs[lv.job[node]];
     const double eps2 = jb.eps2[lg];
     const int kmax = jb.k[lg];
-    const int64_t idx = (int64_t)(lv.y0[node] + qa) * jb.row_stride + lv.x0[node] + pa;   // pixel (lt / N, lt % N)
-    const double v = jb.dtype == AQMP_F64 ? ((const double*)jb.img)[idx] : (double)((const float*)jb.img)[idx];
+    const double v = job_pixel(jb, lv.y0[node] + qa, lv.x0[node] + pa);   // pixel (lt / N, lt % N)
     sY[grp][lt] = v;
     __builtin_amdgcn_wave_barrier();     // group-private: the wave's own writes are seen by its reads
     double e = grp_sum_f64<LPN>(v * v);
@@ -611,8 +609,7 @@ __global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, Le
       // gather (pixel k in thread k), ||y||^2, sum y, first stop test, c0
       double v = 0.0;
       if (tid < K) {
-        const int64_t idx = (int64_t)(lv.y0[node] + tid / N) * jb.row_stride + lv.x0[node] + tid % N;
-        v = jb.dtype == AQMP_F64 ? ((const double*)jb.img)[idx] : (double)((const float*)jb.img)[idx];
+        v = job_pixel(jb, lv.y0[node] + tid / N, lv.x0[node] + tid % N);
         sY[tid] = v;
       }
       if (wv == 0) {

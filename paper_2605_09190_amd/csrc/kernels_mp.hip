@@ -46,14 +46,9 @@ __global__ __launch_bounds__(256) void k_gather(StepArgs a, const int32_t* count
     double e = 0.0;
 #pragma unroll
     for (int dy = 0; dy < G::PH; ++dy) {
-      const int64_t row = (int64_t)(by + py + dy) * jb.row_stride + bx + px;
 #pragma unroll
       for (int dx = 0; dx < G::PW; ++dx) {
-        double v;
-        if (jb.dtype == AQMP_F64)
-          v = ((const double*)jb.img)[row + dx];
-        else
-          v = (double)((const float*)jb.img)[row + dx];
+        const double v = job_pixel(jb, by + py + dy, bx + px + dx);
         const float f = (float)v;
         const int o = (py + dy) * N + px + dx;
         if (valid) {
@@ -336,12 +331,16 @@ __global__ __launch_bounds__(256) void k_decode(const JobDev* jobs, LevelDev lv,
         }
       }
     }
+    // Pixels of the padding (past the image) are not written.
     const int bx = lv.x0[i], by = lv.y0[i];
+    const int w = jobs[job].w, h = jobs[job].h;
 #pragma unroll
     for (int dy = 0; dy < G::PH; ++dy) {
-      const int64_t row = (int64_t)(by + py + dy) * row_stride + bx + px;
+      const int y = by + py + dy;
+      const int64_t row = (int64_t)y * row_stride + bx + px;
 #pragma unroll
       for (int dx = 0; dx < G::PW; ++dx) {
+        if (y >= h || bx + px + dx >= w) continue;
         if (dtype == AQMP_F64)
           ((double*)out)[row + dx] = acc[dy][dx];
         else

@@ -63,6 +63,7 @@ def _is_near_tie_member(img, nd: O.Node, t: int, gpu_atom: int, families: int, s
     (MP: the rank-1 updates; OMP: the least-squares residual of the first t
     atoms)."""
     dic = O.get_dict(nd.n, families)
+    img = O.pad_edge(np.asarray(img, dtype=np.float64), 64)   # nodes may lie in the padding
     y = O.unravel(img[nd.y0:nd.y0 + nd.n, nd.x0:nd.x0 + nd.n]).astype(np.float64)
     if solver == "omp":
         sel = list(nd.mp.idx[:t])

@@ -105,15 +105,16 @@ def test_decode_psnr_matches_oracle(A, dic):
         assert abs(ps_g - ps_o) < 0.01
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_c1_sampled_parity(A, dic, prec):
-    w = workload("c1")
+@pytest.mark.parametrize("prec,tau", [(0, 0.02), (1, 0.02), (0, 0.01), (1, 0.01), (0, 0.04), (1, 0.04)])
+def test_c1_sampled_parity(A, dic, prec, tau):
+    """The 512 x 512 image at the three RMS tolerances of its configuration."""
+    w = workload("c1", tau=tau)
     img = w["channels"][0]
     p = w["params"][0]
     rng = np.random.default_rng(11)
     tops = O.top_blocks(512, 512, 64)
     sample = [tops[i] for i in sorted(rng.choice(len(tops), size=6, replace=False))]
-    _say("c1 sample", prec, sample)
+    _say("c1 sample", prec, tau, sample)
     code, imgs = _encode(A, dic, [img], [p], [(0, 0)], prec, 1)
     rep = _check(A, code, [img], [p], [(0, 0)], prec, blocks_per_job=[sample])
     _say(rep.summary())
@@ -207,3 +208,47 @@ def test_reencode_deterministic(A, dic):
         assert e1.leaves.tobytes() == e2.leaves.tobytes()
         assert e1.atom_idx.tobytes() == e2.atom_idx.tobytes()
         assert e1.coef.tobytes() == e2.coef.tobytes()
+
+
+@pytest.mark.parametrize("form", ["fp32", "bf16", "gram", "omp"])
+def test_non_multiple_plane_edge_padded(A, dic, form):
+    """A 100 x 70 plane with N_max = 32 (tiled as 128 x 96, last row and
+    column repeated) and a 72 x 72 FP64 plane with N_max = 64: same nodes and
+    atoms as the oracle on the padded plane; the decode writes the plane's own
+    pixels only (a guard band around it stays untouched)."""
+    import torch
+    chans = [piecewise_image(70, 100, seed=31), gradient_edges_image(72, 72, seed=32)]
+    params = [dict(tol=0.02, max_atoms=12, n_min=4, n_max=32), dict(tol=0.02, max_atoms=16, n_min=8, n_max=64)]
+    jobs = [(0, 0), (1, 1)]
+    solver = {"gram": A.SOLVER_GRAM, "omp": A.SOLVER_OMP}.get(form, A.SOLVER_DENSE)
+    prec = 1 if form == "bf16" else 0
+    imgs = [_dev(chans[0]), _dev(chans[1], "f64")]
+    code = A.Code(dic, imgs, params, jobs, precision=prec, schedule=1, solver=solver)
+    exp = code.export_nodes()
+    rep = PU.Report()
+    osolver = "omp" if form == "omp" else "mp"
+    tol = {"fp32": 1e-5, "bf16": 2e-3, "gram": 1e-9, "omp": 1e-8}[form]
+    onodes = []
+    for j, (ci, pi) in enumerate(jobs):
+        p = O.Params.from_dict(dict(params[pi], solver=osolver))
+        on = O.encode_channel(chans[ci], p)
+        onodes.append(on)
+        PU.compare_job(chans[ci], on, PU.gpu_nodes_by_key(exp, j), tol, p.n_max, rep=rep, solver=osolver)
+    _say("non-multiple", form, rep.summary())
+    assert rep.ok(), rep.summary()
+    # decode into the middle of a larger buffer: the guard band must stay NaN
+    for j, (ci, pi) in enumerate(jobs):
+        h, w = chans[ci].shape
+        buf = torch.full((h + 8, w + 16), float("nan"), dtype=torch.float64, device="cuda")
+        view = buf[4:4 + h, 8:8 + w]
+        code.decode(j, view)
+        torch.cuda.synchronize()
+        b = buf.cpu().numpy()
+        assert np.isnan(b[:4]).all() and np.isnan(b[4 + h:]).all()
+        assert np.isnan(b[:, :8]).all() and np.isnan(b[:, 8 + w:]).all()
+        rec = b[4:4 + h, 8:8 + w]
+        assert np.isfinite(rec).all()
+        ps_g = O.psnr(chans[ci], rec)
+        ps_o = O.psnr(chans[ci], O.decode(onodes[j], h, w))
+        assert abs(ps_g - ps_o) < 0.01, (ps_g, ps_o)
+    code.free()

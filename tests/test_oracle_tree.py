@@ -140,3 +140,28 @@ def test_decode_matches_residual_energy():
         assert abs(float(np.sum(d * d)) - nd.mp.e_final) < 1e-12 * max(1.0, nd.norm2)
     mse = np.mean((img - rec) ** 2)
     assert O.psnr(img, rec) == pytest.approx(10 * np.log10(1 / mse))
+
+
+def test_non_multiple_plane_is_edge_padded():
+    """A plane that is not a multiple of N_max is coded as its edge-padded
+    version (last row and column repeated), and the decode keeps the plane's
+    own pixels."""
+    rng = np.random.default_rng(9)
+    img = rng.uniform(size=(40, 52))
+    p = O.Params(tol=0.03, max_atoms=6, n_min=8, n_max=16)
+    padded = np.vstack([img, np.repeat(img[-1:], 8, axis=0)])
+    padded = np.hstack([padded, np.repeat(padded[:, -1:], 12, axis=1)])
+    assert padded.shape == (48, 64)
+    assert np.array_equal(O.pad_edge(img, 16), padded)
+    a = O.encode_channel(img, p)
+    b = O.encode_channel(padded, p)
+    assert [(n.x0, n.y0, n.n, n.mp.idx, n.split) for n in a] == [(n.x0, n.y0, n.n, n.mp.idx, n.split) for n in b]
+    ra, rb = O.decode(a, 40, 52), O.decode(b, 48, 64)
+    assert ra.shape == (40, 52)
+    assert np.array_equal(ra, rb[:40, :52])
+    assert len(O.top_blocks(40, 52, 16)) == 3 * 4
+
+
+def test_multiple_plane_unchanged_by_padding():
+    img = np.random.default_rng(10).uniform(size=(32, 48))
+    assert O.pad_edge(img, 16) is not img and np.array_equal(O.pad_edge(img, 16), img)
