@@ -255,6 +255,27 @@ int aqmp_code_export_nodes(const aqmp_code* c, aqmp_leaf* nodes, int32_t* atom_i
 
 int aqmp_code_stats(const aqmp_code* c, aqmp_stats* s);
 
+/* ---- bitstream (encoder step (iii), Section 2.3; CR of Section 3) ------- */
+
+/* Packs the given jobs, as the channels of one image (same plane size and
+ * block range), into the AQMP bitstream and compresses it with DEFLATE
+ * (zlib compress2 at `level` 0..9; -1 leaves the stream uncompressed).
+ * Format (version 1, little-endian): header "AQMP", u8 version, u8
+ * families, u8 coefficient format (0 = binary32), u8 channels, u32 width,
+ * u32 height, u8 log2 N_min, u8 log2 N_max, u8 bytes per atom count, u8 0;
+ * then per channel, nodes in depth-first order (top-level blocks in raster
+ * order over the padded plane, children TL, TR, BL, BR): u32 nodes, u32
+ * leaves, u32 atoms, the split flags of the nodes with N > N_min (one bit
+ * each, LSB first), the atom count of every leaf, the u16 index of every
+ * atom, the binary32 coefficient of every atom.  The compression rate of
+ * Section 3 is (width x height x channels bytes of 8-bit samples) / size.
+ * out == NULL: *size_out receives the exact raw size (level -1) or an upper
+ * bound of the compressed size.  Otherwise out (host memory, capacity bytes)
+ * receives the stream and *size_out its size; AQMP_E_CAPACITY if it does
+ * not fit.  Synchronises the encode stream. */
+int aqmp_code_pack(const aqmp_code* c, const int32_t* jobs, int n_jobs, int level,
+                   uint8_t* out, int64_t capacity, int64_t* size_out);
+
 /* Synchronises the encode stream and sums the per-launch event times of the
  * last encode or re-encode.  AQMP_E_INVALID if the code was not made with
  * AQMP_OPT_TIMING. */

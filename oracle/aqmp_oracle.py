@@ -397,6 +397,97 @@ def decode(nodes: list[Node], h: int, w: int, families: int = DCT | HAAR) -> np.
     return out[:h, :w]
 
 
+# ---------------------------------------------------------------------------
+# Bitstream and compression rate (Section 2.3 encoder step (iii), decoder
+# step (i); Section 3, the CR definition).  The paper names DEFLATE over the
+# sparse vectors but no byte layout; this is the layout the encoder library
+# writes (version 1, little-endian, described in its public header).
+# ---------------------------------------------------------------------------
+
+def pack_stream(channels: Sequence[list], w: int, h: int, n_min: int, n_max: int,
+                families: int = DCT | HAAR) -> bytes:
+    """The uncompressed bitstream of one image: a header, then per channel
+    (each a node list in depth-first order as ``encode_channel`` returns it)
+    the split flags of the nodes with N > N_min, the leaves' atom counts,
+    their atom indices (u16) and coefficients (binary32)."""
+    import struct
+    counts = [nd.mp.t for nodes in channels for nd in nodes if not nd.split]
+    cb = 2 if counts and max(counts) > 255 else 1
+    out = bytearray(b"AQMP")
+    out += struct.pack("<BBBBIIBBBB", 1, families, 0, len(channels), w, h,
+                       n_min.bit_length() - 1, n_max.bit_length() - 1, cb, 0)
+    for nodes in channels:
+        lv = [nd for nd in nodes if not nd.split]
+        out += struct.pack("<III", len(nodes), len(lv), sum(nd.mp.t for nd in lv))
+        bits = np.array([1 if nd.split else 0 for nd in nodes if nd.n > n_min], dtype=np.uint8)
+        out += np.packbits(bits, bitorder="little").tobytes()
+        out += np.array([nd.mp.t for nd in lv], dtype="<u1" if cb == 1 else "<u2").tobytes()
+        out += np.array([i for nd in lv for i in nd.mp.idx], dtype="<u2").tobytes()
+        out += np.array([c for nd in lv for c in nd.mp.coef], dtype="<f4").tobytes()
+    return bytes(out)
+
+
+def unpack_stream(data: bytes) -> dict:
+    """Inverse of ``pack_stream``: the header fields and, per channel, the
+    leaves ``(x0, y0, n, idx, coef)`` in depth-first order, recovered by
+    walking the quadtree with the split flags."""
+    import struct
+    assert data[:4] == b"AQMP"
+    ver, fam, fmt, nch, w, h, lmin, lmax, cb, _ = struct.unpack_from("<BBBBIIBBBB", data, 4)
+    assert ver == 1 and fmt == 0
+    n_min, n_max = 1 << lmin, 1 << lmax
+    pos = 20
+    chans = []
+    for _ in range(nch):
+        n_nodes, n_leaves, n_atoms = struct.unpack_from("<III", data, pos)
+        pos += 12
+        shape = []                      # (x0, y0, n) of every leaf, depth-first
+        nbits = 0
+        bitbuf = np.frombuffer(data, dtype=np.uint8, offset=pos)
+        bit_at = lambda i: (int(bitbuf[i >> 3]) >> (i & 7)) & 1
+
+        def walk(x0, y0, n):
+            nonlocal nbits
+            split = 0
+            if n > n_min:
+                split = bit_at(nbits)
+                nbits += 1
+            if split:
+                hh = n // 2
+                for dy, dx in ((0, 0), (0, hh), (hh, 0), (hh, hh)):
+                    walk(x0 + dx, y0 + dy, hh)
+            else:
+                shape.append((x0, y0, n))
+
+        for (x0, y0) in top_blocks(h, w, n_max):
+            walk(x0, y0, n_max)
+        pos += (nbits + 7) // 8
+        assert len(shape) == n_leaves
+        cnt = np.frombuffer(data, dtype="<u1" if cb == 1 else "<u2", count=n_leaves, offset=pos).astype(int)
+        pos += cb * n_leaves
+        idx = np.frombuffer(data, dtype="<u2", count=n_atoms, offset=pos).astype(int)
+        pos += 2 * n_atoms
+        coef = np.frombuffer(data, dtype="<f4", count=n_atoms, offset=pos).astype(np.float64)
+        pos += 4 * n_atoms
+        off = np.concatenate([[0], np.cumsum(cnt)])
+        chans.append([(x0, y0, n, idx[off[i]:off[i + 1]].tolist(), coef[off[i]:off[i + 1]].tolist())
+                      for i, (x0, y0, n) in enumerate(shape)])
+    assert pos == len(data)
+    return dict(families=fam, w=w, h=h, n_min=n_min, n_max=n_max, channels=chans)
+
+
+def compress_stream(raw: bytes, level: int = 9) -> bytes:
+    """Encoder step (iii): DEFLATE (zlib container) over the bitstream."""
+    import zlib
+    return zlib.compress(raw, level)
+
+
+def compression_rate(compressed_size: int, w: int, h: int, channels: int) -> float:
+    """CR = size_original / size_compressed (Section 3), the original being
+    8-bit samples: w * h * channels bytes."""
+    return float(w * h * channels) / float(compressed_size)
+
+
 def psnr(ref: np.ndarray, rec: np.ndarray, peak: float = 1.0) -> float:
     """PSNR in dB with the given peak; the MSE is taken in float64 over all
     samples, without clipping the reconstruction."""

@@ -39,7 +39,7 @@ EXPORTS = [
     "aqmp_dictionary_build", "aqmp_dictionary_free", "aqmp_dictionary_atoms", "aqmp_dictionary_copy",
     "aqmp_encode", "aqmp_reencode", "aqmp_code_sizes", "aqmp_code_export", "aqmp_code_export_nodes",
     "aqmp_code_stats", "aqmp_code_timing", "aqmp_code_free", "aqmp_decode", "aqmp_last_error",
-    "aqmp_corr_kernel",
+    "aqmp_corr_kernel", "aqmp_code_pack",
 ]
 
 
@@ -115,6 +115,7 @@ def _load() -> C.CDLL:
     lib.aqmp_last_error.restype = C.c_char_p
     lib.aqmp_corr_kernel.argtypes = [i32, i32, i32]
     lib.aqmp_corr_kernel.restype = C.c_char_p
+    lib.aqmp_code_pack.argtypes = [vp, C.POINTER(C.c_int32), i32, i32, vp, i64, C.POINTER(C.c_int64)]
     for name in EXPORTS:
         if not hasattr(lib, name):
             raise ImportError(f"{LIB_PATH} lacks {name}")
@@ -269,6 +270,16 @@ class Code:
     def export(self) -> Export:
         n_leaves, n_atoms = self.sizes()
         return self._export(lib.aqmp_code_export, n_leaves, n_atoms)
+
+    def pack(self, jobs, level: int = 9) -> bytes:
+        """The AQMP bitstream of the given jobs (the channels of one image),
+        DEFLATE-compressed at `level` (0..9) or raw (-1)."""
+        arr = (C.c_int32 * len(jobs))(*[int(j) for j in jobs])
+        size = C.c_int64()
+        _check(lib.aqmp_code_pack(self.h, arr, len(jobs), int(level), None, 0, C.byref(size)))
+        buf = (C.c_uint8 * max(1, size.value))()
+        _check(lib.aqmp_code_pack(self.h, arr, len(jobs), int(level), buf, size.value, C.byref(size)))
+        return bytes(buf[:size.value])
 
     def export_nodes(self) -> Export:
         s = self.stats()

@@ -21,6 +21,8 @@ void code_free(aqmp_code* c);
 int code_stats(const aqmp_code* c, aqmp_stats* s);
 int code_timing(const aqmp_code* c, aqmp_timing* t);
 int code_sizes(const aqmp_code* c, int64_t* n_leaves, int64_t* n_atoms);
+int code_pack(const aqmp_code* c, const int32_t* jobs, int n_jobs, int level, uint8_t* out, int64_t capacity,
+              int64_t* size_out);
 int code_export(const aqmp_code* c, bool leaves_only, aqmp_leaf* leaves, int32_t* atom_idx, double* coef,
                 int64_t cap_leaves, int64_t cap_atoms);
 int decode(const aqmp_dict* d, const aqmp_code* c, int job, void* out, int dtype, int64_t row_stride,
@@ -117,6 +119,11 @@ int aqmp_code_sizes(const aqmp_code* c, int64_t* n_leaves, int64_t* n_atoms) {
 int aqmp_code_export(const aqmp_code* c, aqmp_leaf* leaves, int32_t* atom_idx, double* coef, int64_t cap_leaves,
                      int64_t cap_atoms) {
   AQMP_ENTRY(code_export(c, true, leaves, atom_idx, coef, cap_leaves, cap_atoms));
+}
+
+int aqmp_code_pack(const aqmp_code* c, const int32_t* jobs, int n_jobs, int level, uint8_t* out, int64_t capacity,
+                   int64_t* size_out) {
+  AQMP_ENTRY(code_pack(c, jobs, n_jobs, level, out, capacity, size_out));
 }
 
 int aqmp_code_export_nodes(const aqmp_code* c, aqmp_leaf* nodes, int32_t* atom_idx, double* coef, int64_t cap_nodes,

@@ -20,6 +20,8 @@
 #include <new>
 #include <vector>
 
+#include <zlib.h>
+
 #include "host_util.h"
 #include "internal.h"
 
@@ -613,8 +615,8 @@ int collect(const aqmp_code* c, bool leaves_only, std::vector<HostNode>& out,
         h.leaf.n_atoms = t[i];
         h.leaf.flags = split ? 1 : 0;
         h.leaf.resid_sq = e[i];
-        const int64_t img_w = c->imgs[c->jobs[job[i]].image].w;
-        h.key_hi = ((int64_t)job[i] << 40) | ((int64_t)(y0[i] / nm) * (img_w / nm) + x0[i] / nm);
+        const int64_t cols = padded(c->imgs[c->jobs[job[i]].image].w, nm) / nm;   // top-level blocks per row
+        h.key_hi = ((int64_t)job[i] << 40) | ((int64_t)(y0[i] / nm) * cols + x0[i] / nm);
         h.key_lo = (int64_t)(morton((uint32_t)(x0[i] % nm), (uint32_t)(y0[i] % nm)) << 8) | (255 - l);
         h.idx = idx_store.back().data() + (size_t)i * L.kmax;
         h.coef = coef_store.back().data() + (size_t)i * L.kmax;
@@ -755,6 +757,127 @@ int code_export(const aqmp_code* c, bool leaves_only, aqmp_leaf* leaves, int32_t
     off += L.n_atoms;
     leaves[i] = L;
   }
+  return AQMP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Bitstream (encoder step (iii), Section 2.3: the sparse vectors of every
+// channel, then a lossless DEFLATE pass).  Version 1, little-endian:
+//   header  "AQMP" | u8 version=1 | u8 families | u8 coef format (0: binary32)
+//           | u8 channels | u32 width | u32 height | u8 log2 N_min
+//           | u8 log2 N_max | u8 bytes per atom count (1 or 2) | u8 0
+//   per channel, nodes in depth-first order (top-level blocks in raster
+//   order over the padded plane, children TL, TR, BL, BR):
+//           u32 nodes | u32 leaves | u32 atoms
+//           | split flags of the nodes with N > N_min, one bit each, LSB first
+//           | atom count of every leaf | u16 atom index of every atom
+//           | binary32 coefficient of every atom (selection order per leaf)
+// Grouping like values together is what lets DEFLATE find the redundancy.
+// ---------------------------------------------------------------------------
+namespace {
+
+template <class T>
+void put(std::vector<uint8_t>& b, T v) {
+  uint8_t tmp[sizeof(T)];
+  __builtin_memcpy(tmp, &v, sizeof(T));
+  b.insert(b.end(), tmp, tmp + sizeof(T));
+}
+
+}  // namespace
+
+int code_pack(const aqmp_code* c, const int32_t* jobs, int n_jobs, int level, uint8_t* out, int64_t capacity,
+              int64_t* size_out) {
+  if (!c || !jobs || !size_out) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_pack: null argument");
+  if (n_jobs < 1 || n_jobs > 255) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_pack: 1..255 channels per stream");
+  if (level < -1 || level > 9) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_pack: level must be -1 (raw) or 0..9");
+  const int nj = (int)c->jobs.size();
+  for (int i = 0; i < n_jobs; ++i)
+    if (jobs[i] < 0 || jobs[i] >= nj) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_pack: job out of range");
+  const aqmp_image& im0 = c->imgs[c->jobs[jobs[0]].image];
+  const aqmp_params& p0 = c->prm[c->jobs[jobs[0]].params];
+  for (int i = 1; i < n_jobs; ++i) {
+    const aqmp_image& im = c->imgs[c->jobs[jobs[i]].image];
+    const aqmp_params& p = c->prm[c->jobs[jobs[i]].params];
+    if (im.w != im0.w || im.h != im0.h || p.n_min != p0.n_min || p.n_max != p0.n_max)
+      AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_pack: the channels of a stream need one size and one block range");
+  }
+  std::vector<HostNode> nodes;
+  std::vector<std::vector<int32_t>> is;
+  std::vector<std::vector<double>> cs;
+  const int rc = collect(c, false, nodes, is, cs);
+  if (rc != AQMP_OK) return rc;
+  int max_count = 0;
+  for (const auto& h : nodes) max_count = std::max(max_count, h.leaf.n_atoms);
+  const int cb = max_count > 255 ? 2 : 1;
+  std::vector<uint8_t> raw;
+  raw.insert(raw.end(), {'A', 'Q', 'M', 'P'});
+  put<uint8_t>(raw, 1);
+  put<uint8_t>(raw, (uint8_t)c->dict->families);
+  put<uint8_t>(raw, 0);
+  put<uint8_t>(raw, (uint8_t)n_jobs);
+  put<uint32_t>(raw, (uint32_t)im0.w);
+  put<uint32_t>(raw, (uint32_t)im0.h);
+  put<uint8_t>(raw, (uint8_t)ilog2(p0.n_min));
+  put<uint8_t>(raw, (uint8_t)ilog2(p0.n_max));
+  put<uint8_t>(raw, (uint8_t)cb);
+  put<uint8_t>(raw, 0);
+  for (int i = 0; i < n_jobs; ++i) {
+    // the job's nodes are contiguous in the canonical order
+    const int64_t jk = (int64_t)jobs[i] << 40;
+    auto lo = std::lower_bound(nodes.begin(), nodes.end(), jk,
+                               [](const HostNode& a, int64_t k) { return a.key_hi < k; });
+    auto hi = std::lower_bound(lo, nodes.end(), jk + ((int64_t)1 << 40),
+                               [](const HostNode& a, int64_t k) { return a.key_hi < k; });
+    uint32_t n_leaves = 0, n_atoms = 0;
+    std::vector<uint8_t> bits;
+    int nbits = 0;
+    for (auto it = lo; it != hi; ++it) {
+      if (it->leaf.n > p0.n_min) {
+        if (nbits % 8 == 0) bits.push_back(0);
+        if (it->leaf.flags & 1) bits.back() |= (uint8_t)(1u << (nbits % 8));
+        ++nbits;
+      }
+      if (!(it->leaf.flags & 1)) {
+        ++n_leaves;
+        n_atoms += (uint32_t)it->leaf.n_atoms;
+      }
+    }
+    put<uint32_t>(raw, (uint32_t)(hi - lo));
+    put<uint32_t>(raw, n_leaves);
+    put<uint32_t>(raw, n_atoms);
+    raw.insert(raw.end(), bits.begin(), bits.end());
+    for (auto it = lo; it != hi; ++it)
+      if (!(it->leaf.flags & 1)) {
+        if (cb == 1)
+          put<uint8_t>(raw, (uint8_t)it->leaf.n_atoms);
+        else
+          put<uint16_t>(raw, (uint16_t)it->leaf.n_atoms);
+      }
+    for (auto it = lo; it != hi; ++it)
+      if (!(it->leaf.flags & 1))
+        for (int t = 0; t < it->leaf.n_atoms; ++t) put<uint16_t>(raw, (uint16_t)it->idx[t]);
+    for (auto it = lo; it != hi; ++it)
+      if (!(it->leaf.flags & 1))
+        for (int t = 0; t < it->leaf.n_atoms; ++t) put<float>(raw, (float)it->coef[t]);
+  }
+  if (level < 0) {
+    *size_out = (int64_t)raw.size();
+    if (!out) return AQMP_OK;
+    if (capacity < (int64_t)raw.size()) AQMP_FAIL(AQMP_E_CAPACITY, "aqmp_code_pack: output buffer too small");
+    std::copy(raw.begin(), raw.end(), out);
+    return AQMP_OK;
+  }
+  uLongf bound = compressBound((uLong)raw.size());
+  if (!out) {
+    *size_out = (int64_t)bound;
+    return AQMP_OK;
+  }
+  std::vector<uint8_t> z(bound);
+  if (compress2(z.data(), &bound, raw.data(), (uLong)raw.size(), level) != Z_OK)
+    AQMP_FAIL(AQMP_E_NOMEM, "aqmp_code_pack: DEFLATE failed");
+  *size_out = (int64_t)bound;
+  if (capacity < (int64_t)bound) AQMP_FAIL(AQMP_E_CAPACITY, "aqmp_code_pack: output buffer too small");
+  std::copy(z.begin(), z.begin() + bound, out);
   return AQMP_OK;
 }
 

@@ -1,0 +1,149 @@
+"""Bitstream of the encoder library (Section 2.3 step (iii)) vs the oracle's
+packer, and the compression rate of Section 3.
+
+Packing is byte work: the library's uncompressed stream of a code must equal,
+byte for byte, the oracle's packing of the same tree (the code's exported
+nodes); its DEFLATE output must equal zlib's on those bytes (same library,
+same level).  The compression rate of the library's own encode is then
+compared with the oracle's own encode.
+"""
+import sys
+import zlib
+
+import numpy as np
+import pytest
+
+from oracle import aqmp_oracle as O
+from workloads import workload, piecewise_image
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_09190_amd import aqmp
+    return aqmp
+
+
+@pytest.fixture(scope="module")
+def dic(A):
+    d = A.Dictionary(4, 64)
+    yield d
+    d.free()
+
+
+def _dev(img):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(img)).to(torch.float32).cuda()
+
+
+def _oracle_nodes(exp, job):
+    """The code's visited nodes of one job as oracle nodes, in export order
+    (depth-first)."""
+    lv = exp.leaves
+    out = []
+    for r in np.nonzero(lv["job"] == job)[0]:
+        rec = lv[r]
+        o, na = int(rec["atom_off"]), int(rec["n_atoms"])
+        res = O.MPResult(idx=exp.atom_idx[o:o + na].tolist(), coef=exp.coef[o:o + na].tolist())
+        out.append(O.Node(int(rec["x0"]), int(rec["y0"]), int(rec["n"]), res, bool(rec["flags"] & 1), 0.0, 0.0))
+    return out
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_stream_bytes_match_oracle_packer(A, dic, prec):
+    w = workload("c0")
+    img = w["channels"][0]
+    p = w["params"][0]
+    code = A.Code(dic, [_dev(img)], [p], [(0, 0)], precision=prec, schedule=1)
+    raw = code.pack([0], level=-1)
+    exp = code.export_nodes()
+    want = O.pack_stream([_oracle_nodes(exp, 0)], img.shape[1], img.shape[0], p["n_min"], p["n_max"])
+    assert raw == want
+    z = code.pack([0], level=9)
+    assert z == zlib.compress(raw, 9)
+    assert zlib.decompress(z) == raw
+    code.free()
+
+
+def test_three_channel_stream_and_cr(A, dic):
+    """The 2048 x 2048 YCbCr image as one three-channel stream: byte-identical
+    to the oracle packer, decodable, and its blocks (binary32 coefficients)
+    equal to the library's FP64 decode to binary32 rounding."""
+    import torch
+    w = workload("c3")
+    imgs = [_dev(c) for c in w["channels"]]
+    p = w["params"][0]
+    code = A.Code(dic, imgs, w["params"], w["jobs"], precision=1, schedule=1)
+    raw = code.pack([0, 1, 2], level=-1)
+    exp = code.export_nodes()
+    chans = [_oracle_nodes(exp, j) for j in range(3)]
+    assert raw == O.pack_stream(chans, 2048, 2048, p["n_min"], p["n_max"])
+    z = code.pack([0, 1, 2], level=9)
+    cr = O.compression_rate(len(z), 2048, 2048, 3)
+    back = O.unpack_stream(zlib.decompress(z))
+    _say("cr", cr, "raw", len(raw), "deflated", len(z))
+    assert cr > 1.0
+    # decode a seeded sample of channel-0 leaves from the stream on the host
+    # (binary32 coefficients) and compare with the library's FP64 decode
+    out = torch.zeros(2048, 2048, dtype=torch.float64, device="cuda")
+    code.decode(0, out)
+    torch.cuda.synchronize()
+    lib = out.cpu().numpy()
+    leaves = back["channels"][0]
+    rng = np.random.default_rng(3)
+    for i in rng.choice(len(leaves), size=min(120, len(leaves)), replace=False):
+        x0, y0, n, idx, coef = leaves[i]
+        d = O.get_dict(n)
+        x = np.zeros(d.m)
+        np.add.at(x, idx, coef)
+        blk = O.unravel_inv(d.D @ x, n)
+        err = np.abs(blk - lib[y0:y0 + n, x0:x0 + n]).max()
+        assert err < 1e-5 * max(1.0, float(np.abs(coef).sum())), (x0, y0, n, err)
+    code.free()
+
+
+def test_padded_plane_stream_round_trip(A, dic):
+    img = piecewise_image(70, 100, seed=31)
+    p = dict(tol=0.02, max_atoms=12, n_min=4, n_max=32)
+    code = A.Code(dic, [_dev(img)], [p], [(0, 0)], precision=0, schedule=1)
+    raw = code.pack([0], level=-1)
+    exp = code.export_nodes()
+    assert raw == O.pack_stream([_oracle_nodes(exp, 0)], 100, 70, 4, 32)
+    back = O.unpack_stream(raw)
+    lv = [(nd.x0, nd.y0, nd.n, nd.mp.idx) for nd in O.leaves(_oracle_nodes(exp, 0))]
+    assert [(g[0], g[1], g[2], g[3]) for g in back["channels"][0]] == lv
+    code.free()
+
+
+def test_cr_matches_oracle_encode(A, dic):
+    """The Gram solver (FP64 throughout) codes the same trees as the oracle;
+    the compression rates of the two encodes agree to 1%."""
+    w = workload("c1")
+    img = w["channels"][0]
+    p = w["params"][0]
+    code = A.Code(dic, [_dev(img)], [p], [(0, 0)], schedule=1, solver=A.SOLVER_GRAM)
+    z = code.pack([0], level=9)
+    code.free()
+    onodes = O.encode_channel(img, O.Params.from_dict(p))
+    zo = O.compress_stream(O.pack_stream([onodes], 512, 512, p["n_min"], p["n_max"]))
+    cr_g, cr_o = O.compression_rate(len(z), 512, 512, 1), O.compression_rate(len(zo), 512, 512, 1)
+    _say("cr gpu / oracle", cr_g, cr_o)
+    assert abs(cr_g / cr_o - 1.0) < 0.01
+
+
+def test_pack_rejects_mismatched_channels(A, dic):
+    imgs = [_dev(piecewise_image(64, 64, seed=1)), _dev(piecewise_image(64, 128, seed=2))]
+    p = dict(tol=0.02, max_atoms=8, n_min=8, n_max=32)
+    code = A.Code(dic, imgs, [p], [(0, 0), (1, 0)], precision=0, schedule=1)
+    with pytest.raises(Exception, match="one size"):
+        code.pack([0, 1])
+    code.free()
