@@ -488,6 +488,45 @@ def compression_rate(compressed_size: int, w: int, h: int, channels: int) -> flo
     return float(w * h * channels) / float(compressed_size)
 
 
+# ---------------------------------------------------------------------------
+# SSIM (Section 3's quality measure)
+# ---------------------------------------------------------------------------
+
+SSIM_K1, SSIM_K2 = 0.01, 0.03
+
+
+def ssim(x: np.ndarray, y: np.ndarray, mode: str = "window7", data_range: float = 1.0) -> float:
+    """SSIM(x, y) = (2 mu_x mu_y + C1)(2 s_xy + C2) / ((mu_x^2 + mu_y^2 + C1)(s_x^2 + s_y^2 + C2))
+    with C1 = (K1 L)^2, C2 = (K2 L)^2, K1 = 0.01, K2 = 0.03, L = data_range.
+
+    ``mode="global"``: the equation as written, with the means, variances and
+    covariance of the whole planes (population moments).
+    ``mode="window7"``: the equation on every 7 x 7 window lying inside the
+    plane (uniform weights, sample variances and covariance with the 49/48
+    factor), averaged over the windows (one per interior pixel)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    c1, c2 = (SSIM_K1 * data_range) ** 2, (SSIM_K2 * data_range) ** 2
+
+    def s(mx, my, vx, vy, cxy):
+        return ((2 * mx * my + c1) * (2 * cxy + c2)) / ((mx * mx + my * my + c1) * (vx + vy + c2))
+
+    if mode == "global":
+        mx, my = x.mean(), y.mean()
+        return float(s(mx, my, ((x - mx) ** 2).mean(), ((y - my) ** 2).mean(), ((x - mx) * (y - my)).mean()))
+    assert mode == "window7"
+    win = 7
+    from numpy.lib.stride_tricks import sliding_window_view as swv
+    wx, wy = swv(x, (win, win)), swv(y, (win, win))        # [H-6, W-6, 7, 7]
+    n = win * win
+    mx, my = wx.mean(axis=(2, 3)), wy.mean(axis=(2, 3))
+    dx, dy = wx - mx[..., None, None], wy - my[..., None, None]
+    vx = (dx * dx).sum(axis=(2, 3)) / (n - 1)
+    vy = (dy * dy).sum(axis=(2, 3)) / (n - 1)
+    cxy = (dx * dy).sum(axis=(2, 3)) / (n - 1)
+    return float(s(mx, my, vx, vy, cxy).mean())
+
+
 def psnr(ref: np.ndarray, rec: np.ndarray, peak: float = 1.0) -> float:
     """PSNR in dB with the given peak; the MSE is taken in float64 over all
     samples, without clipping the reconstruction."""
