@@ -255,6 +255,21 @@ int aqmp_code_export_nodes(const aqmp_code* c, aqmp_leaf* nodes, int32_t* atom_i
 
 int aqmp_code_stats(const aqmp_code* c, aqmp_stats* s);
 
+/* ---- quality (Section 3) ------------------------------------------------ */
+
+enum { AQMP_SSIM_GLOBAL = 0, AQMP_SSIM_WINDOW7 = 1 };
+
+/* SSIM of two device planes of one size and dtype (Section 3's equation,
+ * C1 = (0.01 L)^2, C2 = (0.03 L)^2 with L = data_range).  AQMP_SSIM_GLOBAL:
+ * the equation with the means, variances and covariance of the whole planes
+ * (population moments).  AQMP_SSIM_WINDOW7: the equation on every 7 x 7
+ * window inside the planes (uniform weights, sample moments), averaged over
+ * the windows; planes of at least 7 x 7.  Enqueued on hip_stream, then
+ * synchronised; *out (host) receives the value.  Allocates a small device
+ * buffer per call. */
+int aqmp_ssim(const aqmp_image* x, const aqmp_image* y, int mode, double data_range,
+              double* out, void* hip_stream);
+
 /* ---- bitstream (encoder step (iii), Section 2.3; CR of Section 3) ------- */
 
 /* Packs the given jobs, as the channels of one image (same plane size and

@@ -39,7 +39,7 @@ EXPORTS = [
     "aqmp_dictionary_build", "aqmp_dictionary_free", "aqmp_dictionary_atoms", "aqmp_dictionary_copy",
     "aqmp_encode", "aqmp_reencode", "aqmp_code_sizes", "aqmp_code_export", "aqmp_code_export_nodes",
     "aqmp_code_stats", "aqmp_code_timing", "aqmp_code_free", "aqmp_decode", "aqmp_last_error",
-    "aqmp_corr_kernel", "aqmp_code_pack",
+    "aqmp_corr_kernel", "aqmp_code_pack", "aqmp_ssim",
 ]
 
 
@@ -115,6 +115,7 @@ def _load() -> C.CDLL:
     lib.aqmp_last_error.restype = C.c_char_p
     lib.aqmp_corr_kernel.argtypes = [i32, i32, i32]
     lib.aqmp_corr_kernel.restype = C.c_char_p
+    lib.aqmp_ssim.argtypes = [C.POINTER(Image), C.POINTER(Image), i32, C.c_double, C.POINTER(C.c_double), vp]
     lib.aqmp_code_pack.argtypes = [vp, C.POINTER(C.c_int32), i32, i32, vp, i64, C.POINTER(C.c_int64)]
     for name in EXPORTS:
         if not hasattr(lib, name):
@@ -173,6 +174,17 @@ def make_image(t) -> Image:
     im.h, im.w = int(t.shape[0]), int(t.shape[1])
     im.row_stride = int(t.stride(0))
     return im
+
+
+SSIM_GLOBAL, SSIM_WINDOW7 = 0, 1
+
+
+def ssim(x, y, mode: int = SSIM_WINDOW7, data_range: float = 1.0, stream=None) -> float:
+    """SSIM of two 2D CUDA tensors of one shape and dtype (Section 3)."""
+    a, b = make_image(x), make_image(y)
+    out = C.c_double()
+    _check(lib.aqmp_ssim(C.byref(a), C.byref(b), int(mode), float(data_range), C.byref(out), _stream_handle(stream)))
+    return out.value
 
 
 class Dictionary:

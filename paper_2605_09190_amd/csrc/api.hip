@@ -121,6 +121,11 @@ int aqmp_code_export(const aqmp_code* c, aqmp_leaf* leaves, int32_t* atom_idx, d
   AQMP_ENTRY(code_export(c, true, leaves, atom_idx, coef, cap_leaves, cap_atoms));
 }
 
+int aqmp_ssim(const aqmp_image* x, const aqmp_image* y, int mode, double data_range, double* out,
+              void* hip_stream) {
+  AQMP_ENTRY(ssim_planes(x, y, mode, data_range, out, (hipStream_t)hip_stream));
+}
+
 int aqmp_code_pack(const aqmp_code* c, const int32_t* jobs, int n_jobs, int level, uint8_t* out, int64_t capacity,
                    int64_t* size_out) {
   AQMP_ENTRY(code_pack(c, jobs, n_jobs, level, out, capacity, size_out));

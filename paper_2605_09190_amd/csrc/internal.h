@@ -29,6 +29,7 @@ constexpr int kScanTile = 1024;   // items per block of the stable scans
 constexpr int kFusedMaxN = 8;     // levels up to this size run the fused per-node pursuit
 constexpr int kBranches = 4;      // parallel graph branches of the concurrent schedule
 constexpr int kOmpMaxAtoms = AQMP_OMP_MAX_ATOMS;   // OMP: selected atoms per node (LDS factor size)
+constexpr int kSsimMomentBlocks = 1024;   // workgroups of the whole-plane SSIM moments
 
 inline int ilog2(int n) {
   int l = 0;
@@ -133,6 +134,11 @@ hipError_t launch_mp_gram(int n, const JobDev* jobs, LevelDev lv, const int32_t*
 // pursuit with least-squares refits; N <= 8 in one launch.
 hipError_t launch_omp(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int32_t lg,
                       int32_t nfam, const double* tab, const double* xg, double* cbuf, hipStream_t s);
+// SSIM partials: one FP64 per workgroup (window7) or five plane sums per
+// workgroup (global); *n_partial receives the workgroup count.
+hipError_t launch_ssim(const aqmp_image& x, const aqmp_image& y, int mode, double c1, double c2, double* partial,
+                       int* n_partial, hipStream_t s);
+int ssim_planes(const aqmp_image* x, const aqmp_image* y, int mode, double data_range, double* out, hipStream_t s);
 hipError_t launch_decode(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t job,
                          int32_t nfam, const double* tab, void* out, int32_t dtype,
                          int64_t row_stride, hipStream_t s);
