@@ -81,6 +81,26 @@ def psnr_jobs(code, imgs, jobs):
     return out
 
 
+def quality(A, code, imgs, w):
+    """SSIM (7x7 windows) of every job's reconstruction, and the compression
+    rate of the DEFLATE-compressed bitstream with each image's jobs as its
+    channels (jobs that share an image and parameters; otherwise one stream
+    per job)."""
+    import torch
+    ssim = []
+    for j, (ci, _) in enumerate(w["jobs"]):
+        rec = torch.empty_like(imgs[ci])
+        code.decode(j, rec)
+        ssim.append(round(A.ssim(imgs[ci], rec, A.SSIM_WINDOW7), 6))
+    same = len({pi for _, pi in w["jobs"]}) == 1 and len({w["channels"][ci].shape for ci, _ in w["jobs"]}) == 1
+    groups = [list(range(len(w["jobs"])))] if same and len(w["jobs"]) <= 255 else [[j] for j in range(len(w["jobs"]))]
+    orig = comp = 0
+    for g in groups:
+        comp += len(code.pack(g, level=9))
+        orig += sum(int(w["channels"][w["jobs"][j][0]].size) for j in g)
+    return ssim, round(orig / comp, 4)
+
+
 def roofline(stats, timing, precision, kernel_name=None, workload=None):
     """Dominant kernel: the correlation of the largest block size.  Algorithmic
     work per node-iteration is 2*K*M = 4 N^4 flops (every atom correlated with
@@ -177,6 +197,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-gram", action="store_true", help="skip the Gram-solver variant line")
     ap.add_argument("--no-omp", action="store_true", help="skip the OMP-solver variant line")
+    ap.add_argument("--hpo-rounds", type=int, default=0,
+                    help="also time this many rounds of the TPE search (8 trials per round) on the workload's images")
     ap.add_argument("--corr-variant", type=int, default=0, help="BF16 correlation kernel variant (0 = default)")
     ap.add_argument("--schedule", default="batched", choices=["batched", "concurrent"])
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -225,6 +247,7 @@ def main():
     sec = time_steps(code, imgs, args.steps, args.warmup)
     stats = code.stats()
     psnr_b = psnr_jobs(code, imgs, w["jobs"])
+    ssim_b, cr_b = quality(A, code, imgs, w)
     code.free()   # every form below allocates its own buffers
     log(f"bf16 batched (graph): {sec * 1e3:.3f} ms/step")
 
@@ -298,6 +321,24 @@ def main():
         codeo.free()
         log(f"omp fp64 batched (graph): {seco * 1e3:.3f} ms/step")
 
+    hpo_res = None
+    if args.hpo_rounds > 0:
+        from paper_2605_09190_amd import hpo
+        uniq = sorted({ci for ci, _ in w["jobs"]})
+        log(f"hpo: {args.hpo_rounds} rounds x 8 trials on {len(uniq)} images")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dic_h = A.Dictionary(4, 64)       # the search space reaches N_min = 4
+        r = hpo.run(A, dic_h, [imgs[ci] for ci in uniq], rounds=args.hpo_rounds, batch=8, sampler="tpe", seed=0)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        dic_h.free()
+        front = sorted((round(r["history"][i][1][0], 4), round(r["history"][i][1][1], 3)) for i in r["pareto"])
+        hpo_res = dict(rounds=args.hpo_rounds, trials=len(r["history"]), seconds=round(dt, 3),
+                       trials_per_s=round(len(r["history"]) / dt, 2), hypervolume=round(r["hypervolume"], 4),
+                       pareto_ssim_cr=front,
+                       form="TPE, every trial of a round one job of one BF16 batched graph; SSIM 7x7 and DEFLATE CR")
+
     value = npx / sec / 1e6
     res = {
         "metric": METRIC,
@@ -320,9 +361,12 @@ def main():
         "leaves": int(sum(stats["leaves"])),
         "ms_per_step_stream_timed": round(sec_t * 1e3, 4),
         "psnr_db": [round(p, 4) for p in psnr_b],
+        "ssim_window7": ssim_b,
+        "cr": cr_b,
         "fp32_plain": fp32,
         "gram_fp64": gram,
         "omp_fp64": omp,
+        "hpo": hpo_res,
         "roofline": roof,
     }
     if fp32:
