@@ -19,6 +19,8 @@
  *     Encode and decode are stream-ordered and asynchronous.
  *   - Same inputs give bit-identical outputs (all reductions have a fixed
  *     order; compaction is a stable prefix sum).
+ *   - A handle may be used by one thread at a time (the readers of a code
+ *     keep a host copy of its nodes until the next encode of that code).
  *   - Block sizes N are powers of two with 4 <= N <= 64.
  *
  * Pixel and atom layout.  A block b of size N is the N x N sub-matrix of a

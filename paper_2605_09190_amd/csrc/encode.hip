@@ -36,6 +36,14 @@ struct PassPlan {
   int lg_hi = 0, lg_lo = 0;
 };
 
+// A node copied back to the host, with its place in the canonical order.
+struct HostNode {
+  aqmp_leaf leaf;
+  int64_t key_hi, key_lo;      // canonical order
+  const int32_t* idx;
+  const double* coef;
+};
+
 }  // namespace aqmp
 
 struct aqmp_code {
@@ -89,6 +97,12 @@ struct aqmp_code {
   std::vector<LevelEv> lev;
   std::vector<StepEv> sev;
   size_t lev_pos = 0, sev_pos = 0;
+  // Every visited node of the last encode in canonical order, copied back on
+  // the first read (stats, export, pack) and kept until the next encode.
+  bool nodes_ok = false;
+  std::vector<aqmp::HostNode> nodes;
+  std::vector<std::vector<int32_t>> node_idx;
+  std::vector<std::vector<double>> node_coef;
 };
 
 namespace aqmp {
@@ -481,6 +495,7 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
 
 int run(aqmp_code* c, hipStream_t s) {
   c->lev_pos = c->sev_pos = 0;
+  c->nodes_ok = false;
   AQMP_HIP(hipMemcpyAsync(c->djobs, c->hjobs.data(), sizeof(JobDev) * c->hjobs.size(), hipMemcpyHostToDevice, s));
   // HIP events recorded inside a graph cannot be timed, so a timed encode
   // issues the same launch sequence directly on the stream.
@@ -555,13 +570,6 @@ int run(aqmp_code* c, hipStream_t s) {
   return AQMP_OK;
 }
 
-struct HostNode {
-  aqmp_leaf leaf;
-  int64_t key_hi, key_lo;      // canonical order
-  const int32_t* idx;
-  const double* coef;
-};
-
 uint64_t morton(uint32_t x, uint32_t y) {
   uint64_t m = 0;
   for (int b = 0; b < 16; ++b) {
@@ -574,8 +582,8 @@ uint64_t morton(uint32_t x, uint32_t y) {
 // Copies every visited node back and orders them canonically: job, top-level
 // block in raster order, then depth-first (Morton order of the corner, the
 // larger node first).
-int collect(const aqmp_code* c, bool leaves_only, std::vector<HostNode>& out,
-            std::vector<std::vector<int32_t>>& idx_store, std::vector<std::vector<double>>& coef_store) {
+int collect_all(aqmp_code* c, std::vector<HostNode>& out, std::vector<std::vector<int32_t>>& idx_store,
+                std::vector<std::vector<double>>& coef_store) {
   AQMP_HIP(hipStreamSynchronize(c->stream));
   std::vector<Counters> cnt(c->passes.size());
   AQMP_HIP(hipMemcpy(cnt.data(), c->dcnt, sizeof(Counters) * cnt.size(), hipMemcpyDeviceToHost));
@@ -605,7 +613,6 @@ int collect(const aqmp_code* c, bool leaves_only, std::vector<HostNode>& out,
       AQMP_HIP(hipMemcpy(coef_store.back().data(), L.rec_coef, 8 * n * L.kmax, hipMemcpyDeviceToHost));
       for (int64_t i = 0; i < n; ++i) {
         const bool split = (st[i] & ST_SPLIT) != 0;
-        if (leaves_only && split) continue;
         const int nm = c->prm[c->jobs[job[i]].params].n_max;
         HostNode h{};
         h.leaf.job = job[i];
@@ -627,6 +634,22 @@ int collect(const aqmp_code* c, bool leaves_only, std::vector<HostNode>& out,
   std::sort(out.begin(), out.end(), [](const HostNode& a, const HostNode& b) {
     return a.key_hi != b.key_hi ? a.key_hi < b.key_hi : a.key_lo < b.key_lo;
   });
+  return AQMP_OK;
+}
+
+// The code's visited nodes (or leaves) in canonical order; the device copy is
+// made once per encode.
+int collect(const aqmp_code* cc, bool leaves_only, std::vector<HostNode>& out) {
+  aqmp_code* c = const_cast<aqmp_code*>(cc);   // the cache is not part of the code's observable state
+  if (!c->nodes_ok) {
+    c->nodes.clear();
+    const int rc = collect_all(c, c->nodes, c->node_idx, c->node_coef);
+    if (rc != AQMP_OK) return rc;
+    c->nodes_ok = true;
+  }
+  out.clear();
+  for (const auto& h : c->nodes)
+    if (!(leaves_only && (h.leaf.flags & 1))) out.push_back(h);
   return AQMP_OK;
 }
 
@@ -683,9 +706,7 @@ void code_free(aqmp_code* c) { free_code(c); }
 int code_stats(const aqmp_code* c, aqmp_stats* s) {
   if (!c || !s) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_stats: null argument");
   std::vector<HostNode> nodes;
-  std::vector<std::vector<int32_t>> is;
-  std::vector<std::vector<double>> cs;
-  const int rc = collect(c, false, nodes, is, cs);
+  const int rc = collect(c, false, nodes);
   if (rc != AQMP_OK) return rc;
   std::memset(s, 0, sizeof(*s));
   for (const auto& h : nodes) {
@@ -737,9 +758,7 @@ int code_export(const aqmp_code* c, bool leaves_only, aqmp_leaf* leaves, int32_t
                 int64_t cap_leaves, int64_t cap_atoms) {
   if (!c || !leaves || !atom_idx || !coef) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_export: null argument");
   std::vector<HostNode> nodes;
-  std::vector<std::vector<int32_t>> is;
-  std::vector<std::vector<double>> cs;
-  const int rc = collect(c, leaves_only, nodes, is, cs);
+  const int rc = collect(c, leaves_only, nodes);
   if (rc != AQMP_OK) return rc;
   int64_t na = 0;
   for (const auto& h : nodes) na += h.leaf.n_atoms;
@@ -802,9 +821,7 @@ int code_pack(const aqmp_code* c, const int32_t* jobs, int n_jobs, int level, ui
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_pack: the channels of a stream need one size and one block range");
   }
   std::vector<HostNode> nodes;
-  std::vector<std::vector<int32_t>> is;
-  std::vector<std::vector<double>> cs;
-  const int rc = collect(c, false, nodes, is, cs);
+  const int rc = collect(c, false, nodes);
   if (rc != AQMP_OK) return rc;
   int max_count = 0;
   for (const auto& h : nodes) max_count = std::max(max_count, h.leaf.n_atoms);

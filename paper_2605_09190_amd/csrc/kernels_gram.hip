@@ -96,7 +96,8 @@ __global__ __launch_bounds__(256) void k_gram_init(const JobDev* __restrict__ jo
       jb = &jobs[lv.job[node]];
       const int bx = lv.x0[node], by = lv.y0[node];
 #pragma unroll
-      for (int i = tn; i < K; i += TPN) {
+      for (int i0 = 0; i0 < K; i0 += TPN) {
+        const int i = i0 + tn;
         const int y = i / N, x = i % N;
         const double v = job_pixel(*jb, by + y, bx + x);
         sY[g][sw<N>(y, x)] = v;
