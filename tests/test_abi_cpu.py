@@ -109,3 +109,22 @@ def test_corr_kernel_names():
     assert A.corr_kernel(128, A.PREC_BF16) == ""
     assert A.corr_kernel(64, 7) == ""
     assert A.corr_kernel(64, A.PREC_BF16, 9) == ""
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without the built library the binding raises; it has no fallback."""
+    from paper_2605_09190_amd import aqmp as A
+    monkeypatch.setattr(A, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libaqmp.so"))
+    with pytest.raises(ImportError):
+        A._load()
+
+
+def test_product_never_uses_the_oracle():
+    """The package (binding, search loop, build) does not import, call or
+    read anything under oracle/."""
+    pkg = os.path.join(ROOT, "paper_2605_09190_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f), encoding="utf-8").read()
+                assert not re.search(r"\boracle\b", src), f
