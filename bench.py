@@ -101,6 +101,46 @@ def quality(A, code, imgs, w):
     return ssim, round(orig / comp, 4)
 
 
+PEAK_FP64_TFLOPS = 78.6       # MI355X FP64 (matrix and vector)
+
+
+def solver_roofline(A, dic, imgs, w, solver, sched, steps, warmup):
+    """Dominant kernel of a labelled solver, timed live with the library's HIP
+    events (a separate encode issued on the stream, like the headline's).
+
+    Gram: the initial correlations of the largest blocks, k_gram_init<N>,
+    8 N^3 flop per node (two N^3 products per family, FMA = 2 flop) on the
+    FP64 matrix cores.  OMP: its pursuit k_omp<N>, whose correlation refresh
+    after step s costs s * N^2 FMA (each selected atom updates the N^2 atoms
+    of the other family), i.e. N^2 T (T - 1) flop for a node of T atoms, on
+    the FP64 vector units."""
+    code_t = A.Code(dic, imgs, w["params"], w["jobs"], schedule=sched, solver=solver, timing=True)
+    time_steps(code_t, imgs, steps, warmup)
+    tm, st = code_t.timing(), code_t.stats()
+    lg = max(l for l in range(7) if st["nodes"][l] > 0)
+    n = 1 << lg
+    fam = 2
+    if solver == A.SOLVER_GRAM:
+        flops = 8.0 * n ** 3 * st["nodes"][lg]
+        ms = tm["corr_ms"][lg]
+        name, bound = f"k_gram_init<{n}, {fam}>", "mfma"
+        other = dict(kernel=f"k_gram_pursuit<{n}, {fam}>", ms=round(tm["select_ms"][lg], 4),
+                     flops=2.0 * n * n * st["iters_level"][lg])
+        other["frac"] = round(other["flops"] / (other["ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)
+    else:
+        exp = code_t.export_nodes()
+        t = exp.leaves["n_atoms"][exp.leaves["n"] == n].astype(np.float64)
+        flops = float(n * n * np.sum(t * (t - 1)))
+        ms = tm["select_ms"][lg]
+        name, bound = f"k_omp<{n}, {fam}>", "alu"
+        other = dict(kernel=f"k_gram_init<{n}, {fam}>", ms=round(tm["corr_ms"][lg], 4))
+    code_t.free()
+    achieved = flops / (ms * 1e-3) / 1e12
+    return dict(bound=bound, achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                frac=round(achieved / PEAK_FP64_TFLOPS, 4), kernel=name, kernel_ms=round(ms, 4),
+                flops_per_launch=flops, nodes=int(st["nodes"][lg]), other=other)
+
+
 def roofline(stats, timing, precision, kernel_name=None, workload=None):
     """Dominant kernel: the correlation of the largest block size.  Algorithmic
     work per node-iteration is 2*K*M = 4 N^4 flops (every atom correlated with
@@ -142,7 +182,7 @@ def _oracle_block(args):
 _ORACLE_CHANS = None
 
 
-def cpu_baseline(w, budget_s=15.0):
+def cpu_baseline(w, budget_s=25.0):
     """The FP64 oracle on a seeded sample of top-level blocks of the same
     workload, process-parallel over blocks on the host cores."""
     global _ORACLE_CHANS
@@ -228,10 +268,15 @@ def main():
     log("generating workload", args.workload)
     w = workload(args.workload)
     cpu = None
+    cpu_omp = None
     if not args.no_cpu_baseline:
         # before any device call: the oracle's worker processes are forked
         log("cpu baseline (oracle)")
         cpu = cpu_baseline(w)
+        if not args.no_omp:
+            log("cpu baseline (oracle OMP)")
+            w_omp = dict(w, params=[dict(p, solver="omp") for p in w["params"]])
+            cpu_omp = cpu_baseline(w_omp, budget_s=12.0)
     imgs = to_device(w["channels"])
     npx = sum(int(w["channels"][ci].size) for ci, _ in w["jobs"])
     nmin = min(p["n_min"] for p in w["params"])
@@ -292,7 +337,9 @@ def main():
         secg = time_steps(codeg, imgs, args.steps, args.warmup)
         stg = codeg.stats()
         psnr_g = psnr_jobs(codeg, imgs, w["jobs"])
+        roof_g = solver_roofline(A, dic, imgs, w, A.SOLVER_GRAM, sched, args.steps, args.warmup)
         gram = dict(value=round(npx / secg / 1e6, 3), ms_per_step=round(secg * 1e3, 4), steps=args.steps,
+                    roofline=roof_g,
                     mp_iters_per_s=round(stg["iters_executed"] / secg, 1), psnr_db=[round(p, 4) for p in psnr_g],
                     leaves=int(sum(stg["leaves"])), iters_level={str(1 << l): int(v) for l, v in
                                                                   enumerate(stg["iters_level"]) if v},
@@ -312,7 +359,9 @@ def main():
         seco = time_steps(codeo, imgs, args.steps, args.warmup)
         sto = codeo.stats()
         psnr_o = psnr_jobs(codeo, imgs, w["jobs"])
+        roof_o = solver_roofline(A, dic, imgs, w, A.SOLVER_OMP, sched, args.steps, args.warmup)
         omp = dict(value=round(npx / seco / 1e6, 3), ms_per_step=round(seco * 1e3, 4), steps=args.steps,
+                   roofline=roof_o, cpu_baseline=cpu_omp,
                    mp_iters_per_s=round(sto["iters_executed"] / seco, 1), psnr_db=[round(p, 4) for p in psnr_o],
                    leaves=int(sum(sto["leaves"])), atoms_emitted=int(sto["iters_emitted"]),
                    iters_level={str(1 << l): int(v) for l, v in enumerate(sto["iters_level"]) if v},

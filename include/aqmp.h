@@ -188,10 +188,14 @@ typedef struct {
 /* Device time of the last encode, per log2(N), from HIP events recorded
  * around the launches (only with AQMP_OPT_TIMING). */
 typedef struct {
-  double corr_ms[7];        /* correlation + top-R key launches             */
-  double select_ms[7];      /* re-score / update / norm launches            */
+  double corr_ms[7];        /* correlation + top-R key launches (Gram and
+                               OMP solvers, N >= 16: the initial-
+                               correlation launch)                         */
+  double select_ms[7];      /* re-score / update / norm launches (Gram and
+                               OMP solvers, N >= 16: the pursuit launch)    */
   double level_ms[7];       /* whole level: gather .. split/emit            */
-  int64_t steps[7];         /* MP steps timed                               */
+  int64_t steps[7];         /* MP steps timed (Gram and OMP solvers: one
+                               per level)                                   */
 } aqmp_timing;
 
 /* ---- dictionaries (Section 2.1; Section 2.3 "D_N assumed available") --- */

@@ -404,7 +404,18 @@ int build_plan(aqmp_code* c) {
         AQMP_HIP(hipEventCreate(&le.start));
         AQMP_HIP(hipEventCreate(&le.end));
         c->lev.push_back(le);
-        if (whole_level(c, 1 << l)) continue;   // whole level in one launch
+        if (whole_level(c, 1 << l)) {
+          // Gram and OMP levels with N >= 16: one event triple around the
+          // initial-correlation and pursuit launches.
+          if (c->opt.solver != AQMP_SOLVER_DENSE && (1 << l) > kFusedMaxN) {
+            aqmp_code::StepEv se{l, nullptr, nullptr, nullptr};
+            AQMP_HIP(hipEventCreate(&se.a));
+            AQMP_HIP(hipEventCreate(&se.b));
+            AQMP_HIP(hipEventCreate(&se.c));
+            c->sev.push_back(se);
+          }
+          continue;
+        }
         for (int t = 0; t < pp.kmax[l]; ++t) {
           aqmp_code::StepEv se{l, nullptr, nullptr, nullptr};
           AQMP_HIP(hipEventCreate(&se.a));
@@ -451,11 +462,20 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
     if (le) AQMP_HIP(hipEventRecord(le->start, s));
     if (whole_level(c, n)) {
       // Small blocks: each node's whole pursuit in one launch.
-      if (c->opt.solver == AQMP_SOLVER_OMP)
-        AQMP_LAUNCH(launch_omp(n, c->djobs, a.lv, count, &cnt->next[l], l, d->nfam, D.d_tab, D.d_xg, wk.cbuf, s));
-      else if (c->opt.solver == AQMP_SOLVER_GRAM)
-        AQMP_LAUNCH(launch_mp_gram(n, c->djobs, a.lv, count, &cnt->next[l], l, d->nfam, D.d_tab, D.d_xg, wk.cbuf, s));
-      else if (n <= kFusedMaxN)
+      if (c->opt.solver != AQMP_SOLVER_DENSE) {
+        const aqmp_code::StepEv* se = timing && n > kFusedMaxN ? &c->sev[c->sev_pos++] : nullptr;
+        if (se) AQMP_HIP(hipEventRecord(se->a, s));
+        if (n > kFusedMaxN)
+          AQMP_LAUNCH(launch_gram_init(n, c->djobs, a.lv, count, l, d->nfam, D.d_tab, wk.cbuf, s));
+        if (se) AQMP_HIP(hipEventRecord(se->b, s));
+        if (c->opt.solver == AQMP_SOLVER_OMP)
+          AQMP_LAUNCH(launch_omp_pursuit(n, c->djobs, a.lv, count, &cnt->next[l], l, d->nfam, D.d_tab, D.d_xg,
+                                         wk.cbuf, s));
+        else
+          AQMP_LAUNCH(launch_gram_pursuit(n, c->djobs, a.lv, count, &cnt->next[l], l, d->nfam, D.d_tab, D.d_xg,
+                                          wk.cbuf, s));
+        if (se) AQMP_HIP(hipEventRecord(se->c, s));
+      } else if (n <= kFusedMaxN)
         AQMP_LAUNCH(launch_mp_fused(n, c->djobs, a.lv, count, l, D.m, D.d_tab, s));
       else
         AQMP_LAUNCH(launch_pursuit16_bf16(c->djobs, a.lv, count, D.m, d->nfam, D.d_tab, D.d_tabT32, s));

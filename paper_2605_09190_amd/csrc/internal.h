@@ -125,15 +125,18 @@ hipError_t launch_mp_fused(int n, const JobDev* jobs, LevelDev lv, const int32_t
                            const double* tab, hipStream_t s);
 hipError_t launch_pursuit16_bf16(const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t n_atoms, int32_t nfam,
                                  const double* tab, const float* tabT32, hipStream_t s);
-// Gram form (FP64): correlations of every node of the level into cbuf
-// ([node][nfam * n * n]), then each node's whole pursuit by Gram updates.
-// `next` is a zero-initialised work counter the pursuit hands out nodes from.
-hipError_t launch_mp_gram(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int32_t lg,
-                          int32_t nfam, const double* tab, const double* xg, double* cbuf, hipStream_t s);
-// OMP (FP64): for N >= 16 the Gram initial correlations into cbuf, then the
-// pursuit with least-squares refits; N <= 8 in one launch.
-hipError_t launch_omp(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int32_t lg,
-                      int32_t nfam, const double* tab, const double* xg, double* cbuf, hipStream_t s);
+// Gram and OMP forms (FP64).  For N >= 16 launch_gram_init writes the
+// correlations of every node of the level to cbuf ([node][nfam * n * n]) and
+// sets its ||y||^2 and first stop test; the pursuit launches then take each
+// node through its whole MP (Gram updates) or OMP (least-squares refits);
+// for N <= 8 the pursuit launch does everything.  `next` is a zero-
+// initialised work counter the pursuits hand out nodes from.
+hipError_t launch_gram_init(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t lg, int32_t nfam,
+                            const double* tab, double* cbuf, hipStream_t s);
+hipError_t launch_gram_pursuit(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int32_t lg,
+                               int32_t nfam, const double* tab, const double* xg, const double* cbuf, hipStream_t s);
+hipError_t launch_omp_pursuit(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int32_t lg,
+                              int32_t nfam, const double* tab, const double* xg, const double* cbuf, hipStream_t s);
 // SSIM partials: one FP64 per workgroup (window7) or five plane sums per
 // workgroup (global); *n_partial receives the workgroup count.
 hipError_t launch_ssim(const aqmp_image& x, const aqmp_image& y, int mode, double c1, double c2, double* partial,

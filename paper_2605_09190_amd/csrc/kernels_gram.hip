@@ -792,65 +792,69 @@ __global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, Le
   }
 }
 
-template <int N, int NFAM>
-void launch_gram_n(const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int32_t lg,
-                   const double* tab, const double* xg, double* cbuf, int init_grid, int pur_grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_gram_init<N, NFAM>), dim3(init_grid), dim3(256), 0, s, jobs, lv, count, lg, tab, cbuf);
-  hipLaunchKernelGGL((k_gram_pursuit<N, NFAM>), dim3(pur_grid), dim3(256), 0, s, jobs, lv, count, next, lg, xg,
-                     cbuf);
-}
-
 }  // namespace
 
-hipError_t launch_mp_gram(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int32_t lg,
-                          int32_t nfam, const double* tab, const double* xg, double* cbuf, hipStream_t s) {
-  if (nfam == 2 && !xg) return hipErrorInvalidValue;
+hipError_t launch_gram_init(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t lg, int32_t nfam,
+                            const double* tab, double* cbuf, hipStream_t s) {
   if (nfam != 1 && nfam != 2) return hipErrorInvalidValue;
+#define AQMP_GINIT(NN, GRID)                                                                                  \
+  case NN:                                                                                                    \
+    if (nfam == 2)                                                                                            \
+      hipLaunchKernelGGL((k_gram_init<NN, 2>), dim3(GRID), dim3(256), 0, s, jobs, lv, count, lg, tab, cbuf); \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_gram_init<NN, 1>), dim3(GRID), dim3(256), 0, s, jobs, lv, count, lg, tab, cbuf); \
+    break;
   switch (n) {
-    case 4:
-      if (nfam == 2)
-        hipLaunchKernelGGL((k_gram_small<4, 2>), dim3(1024), dim3(256), 0, s, jobs, lv, count, lg, tab, xg);
-      else
-        hipLaunchKernelGGL((k_gram_small<4, 1>), dim3(1024), dim3(256), 0, s, jobs, lv, count, lg, tab, xg);
-      break;
-    case 8:
-      if (nfam == 2)
-        hipLaunchKernelGGL((k_gram_small<8, 2>), dim3(2048), dim3(256), 0, s, jobs, lv, count, lg, tab, xg);
-      else
-        hipLaunchKernelGGL((k_gram_small<8, 1>), dim3(2048), dim3(256), 0, s, jobs, lv, count, lg, tab, xg);
-      break;
-    case 16:
-      if (nfam == 2) launch_gram_n<16, 2>(jobs, lv, count, next, lg, tab, xg, cbuf, 2048, 2048, s);
-      else launch_gram_n<16, 1>(jobs, lv, count, next, lg, tab, xg, cbuf, 2048, 2048, s);
-      break;
-    case 32:
-      if (nfam == 2) launch_gram_n<32, 2>(jobs, lv, count, next, lg, tab, xg, cbuf, 1024, 2048, s);
-      else launch_gram_n<32, 1>(jobs, lv, count, next, lg, tab, xg, cbuf, 1024, 2048, s);
-      break;
-    case 64:
-      if (nfam == 2) launch_gram_n<64, 2>(jobs, lv, count, next, lg, tab, xg, cbuf, 512, 1024, s);
-      else launch_gram_n<64, 1>(jobs, lv, count, next, lg, tab, xg, cbuf, 512, 1024, s);
-      break;
+    AQMP_GINIT(16, 2048)
+    AQMP_GINIT(32, 1024)
+    AQMP_GINIT(64, 512)
     default:
       return hipErrorInvalidValue;
   }
+#undef AQMP_GINIT
   return hipGetLastError();
 }
 
-hipError_t launch_omp(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int32_t lg,
-                      int32_t nfam, const double* tab, const double* xg, double* cbuf, hipStream_t s) {
+hipError_t launch_gram_pursuit(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int32_t lg,
+                               int32_t nfam, const double* tab, const double* xg, const double* cbuf, hipStream_t s) {
   if (nfam == 2 && !xg) return hipErrorInvalidValue;
   if (nfam != 1 && nfam != 2) return hipErrorInvalidValue;
-#define AQMP_OMP(NN)                                                                                            \
+#define AQMP_GSMALL(NN, GRID)                                                                                  \
   case NN:                                                                                                     \
-    if (NN >= 16) {                                                                                            \
-      if (nfam == 2)                                                                                           \
-        hipLaunchKernelGGL((k_gram_init<NN >= 16 ? NN : 16, 2>), dim3(NN == 64 ? 512 : 1024), dim3(256), 0, s, \
-                           jobs, lv, count, lg, tab, cbuf);                                                    \
-      else                                                                                                     \
-        hipLaunchKernelGGL((k_gram_init<NN >= 16 ? NN : 16, 1>), dim3(NN == 64 ? 512 : 1024), dim3(256), 0, s, \
-                           jobs, lv, count, lg, tab, cbuf);                                                    \
-    }                                                                                                          \
+    if (nfam == 2)                                                                                             \
+      hipLaunchKernelGGL((k_gram_small<NN, 2>), dim3(GRID), dim3(256), 0, s, jobs, lv, count, lg, tab, xg);   \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_gram_small<NN, 1>), dim3(GRID), dim3(256), 0, s, jobs, lv, count, lg, tab, xg);   \
+    break;
+#define AQMP_GPUR(NN, GRID)                                                                                    \
+  case NN:                                                                                                     \
+    if (nfam == 2)                                                                                             \
+      hipLaunchKernelGGL((k_gram_pursuit<NN, 2>), dim3(GRID), dim3(256), 0, s, jobs, lv, count, next, lg, xg, \
+                         cbuf);                                                                                \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_gram_pursuit<NN, 1>), dim3(GRID), dim3(256), 0, s, jobs, lv, count, next, lg, xg, \
+                         cbuf);                                                                                \
+    break;
+  switch (n) {
+    AQMP_GSMALL(4, 1024)
+    AQMP_GSMALL(8, 2048)
+    AQMP_GPUR(16, 2048)
+    AQMP_GPUR(32, 2048)
+    AQMP_GPUR(64, 1024)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef AQMP_GSMALL
+#undef AQMP_GPUR
+  return hipGetLastError();
+}
+
+hipError_t launch_omp_pursuit(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int32_t lg,
+                              int32_t nfam, const double* tab, const double* xg, const double* cbuf, hipStream_t s) {
+  if (nfam == 2 && !xg) return hipErrorInvalidValue;
+  if (nfam != 1 && nfam != 2) return hipErrorInvalidValue;
+#define AQMP_OMP(NN)                                                                                           \
+  case NN:                                                                                                     \
     if (nfam == 2)                                                                                             \
       hipLaunchKernelGGL((k_omp<NN, 2>), dim3(1024), dim3(256), 0, s, jobs, lv, count, next, lg, tab, xg, cbuf); \
     else                                                                                                       \
