@@ -252,3 +252,55 @@ def test_non_multiple_plane_edge_padded(A, dic, form):
         ps_o = O.psnr(chans[ci], O.decode(onodes[j], h, w))
         assert abs(ps_g - ps_o) < 0.01, (ps_g, ps_o)
     code.free()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_degenerate_blocks_dense(A, dic, prec):
+    """Dense forms on a constant plane (one constant atom per top block, then
+    an exact-zero residual), an all-zero plane (first stop test) and k = 0
+    (sparsity stop before any step)."""
+    const = np.full((128, 128), 0.37)
+    zero = np.zeros((64, 64))
+    rng = np.random.default_rng(5)
+    noise = rng.standard_normal((64, 64)) * 0.1
+    params = [dict(tol=1e-6, tol_mode="abs", max_atoms=8, n_min=8, n_max=64),
+              dict(tol=0.01, max_atoms=0, n_min=8, n_max=64)]
+    jobs = [(0, 0), (1, 0), (2, 1), (2, 0)]
+    _say("degenerate dense", prec)
+    code, imgs = _encode(A, dic, [const, zero, noise], params, jobs, prec, 1, dtype="f64")
+    rep = _check(A, code, [const, zero, noise], params, jobs, prec)
+    _say(rep.summary())
+    assert rep.ok(), rep.summary()
+    code.free()
+
+
+@pytest.mark.parametrize("form", ["fp32", "bf16", "gram"])
+def test_maximum_sparsity(A, dic, form):
+    """k = 256 (AQMP_MAX_ATOMS) with a tolerance no block meets, on a
+    noise-dominated plane: every node runs all 256 steps (MP may pick an atom
+    again) and crosses every record window.  The dense forms keep the residual
+    in FP32, whose drift against the FP64 oracle grows as the residual
+    shrinks, so they run N = 32 only (the residual keeps >= 1.6% of its
+    energy and no top-2 gap falls below 1e-5); the Gram solver (FP64) also
+    runs N = 16 (down to 1e-4 of the block's energy).  Deeper still (N = 8
+    here reaches 1e-15) two FP64 computations in different orders differ by
+    about the tie window, so that case is not a parity case.  The plane is
+    rounded to FP32 values: the library reads it as FP32."""
+    rng = np.random.default_rng(78)
+    img = np.clip(piecewise_image(64, 64, seed=77) + rng.normal(0, 0.2, size=(64, 64)), 0, 1)
+    img = img.astype(np.float32).astype(np.float64)
+    params = [dict(tol=1e-9, max_atoms=256, n_min=32, n_max=32), dict(tol=1e-9, max_atoms=256, n_min=16, n_max=16)]
+    jobs = [(0, 0), (0, 1)] if form == "gram" else [(0, 0)]
+    solver = A.SOLVER_GRAM if form == "gram" else A.SOLVER_DENSE
+    prec = 1 if form == "bf16" else 0
+    code = A.Code(dic, [_dev(img)], params, jobs, precision=prec, schedule=1, solver=solver)
+    exp = code.export_nodes()
+    tol = {"fp32": 1e-5, "bf16": 2e-3, "gram": 1e-9}[form]
+    rep = PU.Report()
+    for j, (ci, pi) in enumerate(jobs):
+        p = O.Params.from_dict(params[pi])
+        PU.compare_job(img, O.encode_channel(img, p), PU.gpu_nodes_by_key(exp, j), tol, p.n_max, rep=rep)
+    _say("max k", form, rep.summary())
+    assert rep.ok(), rep.summary()
+    assert rep.iters >= 256 * 4
+    code.free()
