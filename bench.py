@@ -2,7 +2,7 @@
 
 A step is one complete encode of the workload (every job, every quadtree
 level, every MP step: gather, correlation + top-R, re-score / update / norm,
-compaction, split / emit) with the input planes already in HBM.  The headline
+active-list append, split / emit) with the input planes already in HBM.  The headline
 form is the batched BF16 encode (one graph for all jobs); the plain FP32 form
 (jobs one after another, FP32 correlation) runs on the same input for the
 comparison at equal PSNR.  One JSON line is printed on stdout.

@@ -17,8 +17,9 @@
  *     buffer it passes in; the library owns the handles it returns.
  *   - hip_stream is a hipStream_t passed as void* (NULL = the null stream).
  *     Encode and decode are stream-ordered and asynchronous.
- *   - Same inputs give bit-identical outputs (all reductions have a fixed
- *     order; compaction is a stable prefix sum).
+ *   - Same inputs give bit-identical outputs: all reductions have a fixed
+ *     order, and no result depends on the order of the active-node list
+ *     (which the select step builds by atomic append).
  *   - A handle may be used by one thread at a time (the readers of a code
  *     keep a host copy of its nodes until the next encode of that code).
  *   - Block sizes N are powers of two with 4 <= N <= 64.
@@ -135,8 +136,8 @@ typedef struct {
                           batched encode issues the same launches directly
                           on the stream.
                           AQMP_OPT_STEPWISE: run the N = 16 level of the
-                          BF16 form one MP step per launch (correlation,
-                          select, compaction) instead of the whole-level
+                          BF16 form one MP step per launch (correlation
+                          and select) instead of the whole-level
                           pursuit; same method, for comparison. */
   int32_t corr_variant;  /* tuning: 0 = library default; 1..6 force one
                             family of BF16 correlation kernels (results

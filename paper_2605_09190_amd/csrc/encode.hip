@@ -6,8 +6,8 @@
 //   init counts; for each block size N from the largest to the smallest:
 //     gather the level's nodes -> residuals, norms, first stop test;
 //     compact the running nodes into the active list;
-//     k_N times: correlation + top-R keys (MFMA), select/update (FP64),
-//                compact the still-running nodes;
+//     k_N times: correlation + top-R keys (MFMA), select/update (FP64)
+//                that appends the still-running nodes to the next list;
 //     split test, stable scan, emit the children into the next level.
 // All data-dependent counts live in device memory: kernels read them and
 // idle when there is no work, so the sequence is fixed and can be captured
@@ -486,24 +486,26 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
       continue;
     }
     AQMP_LAUNCH(launch_gather(n, a, count, s));
-    AQMP_LAUNCH(launch_compact(nullptr, count, a.lv.st, wk.act[0], &cnt->act[0], pp.cap[l], wk.ss,
-                               &cnt->scan_error, s));
-    int cur = 0;
+    // Step t reads list t % 2 with counter t % 3 and appends to list
+    // (t + 1) % 2 with counter (t + 1) % 3, which must be zero: the initial
+    // compaction clears counter 1, and step t clears counter (t + 2) % 3.
+    AQMP_LAUNCH(launch_compact(nullptr, count, a.lv.st, wk.act[0], &cnt->act[0], &cnt->act[1], pp.cap[l],
+                               wk.ss, &cnt->scan_error, s));
     const void* atoms = c->opt.precision == AQMP_PREC_BF16 ? (const void*)D.d_bf16 : (const void*)D.d_f32;
     for (int t = 0; t < pp.kmax[l]; ++t) {
-      a.act = wk.act[cur];
-      a.act_count = &cnt->act[cur];
+      a.act = wk.act[t & 1];
+      a.act_count = &cnt->act[t % 3];
+      const bool more = t + 1 < pp.kmax[l];
+      a.next_act = more ? wk.act[(t + 1) & 1] : nullptr;
+      a.next_count = &cnt->act[(t + 1) % 3];
+      a.clear_count = &cnt->act[(t + 2) % 3];
       const aqmp_code::StepEv* se = timing ? &c->sev[c->sev_pos++] : nullptr;
       if (se) AQMP_HIP(hipEventRecord(se->a, s));
       const int variant = c->wide_residual ? 3 : c->opt.corr_variant;
       AQMP_LAUNCH(launch_corr(n, c->opt.precision, variant, atoms, a, D.m_pad, s));
       if (se) AQMP_HIP(hipEventRecord(se->b, s));
-      AQMP_LAUNCH(launch_select(n, a, s));
+      AQMP_LAUNCH(launch_select(n, a, pp.cap[l], s));
       if (se) AQMP_HIP(hipEventRecord(se->c, s));
-      if (t + 1 < pp.kmax[l])
-        AQMP_LAUNCH(launch_compact(wk.act[cur], &cnt->act[cur], a.lv.st, wk.act[cur ^ 1], &cnt->act[cur ^ 1],
-                                   pp.cap[l], wk.ss, &cnt->scan_error, s));
-      cur ^= 1;
     }
     if (l > pp.lg_lo && pp.cap[l - 1] > 0)
       AQMP_LAUNCH(launch_split_emit(c->djobs, a.lv, count, level_at(c, l - 1, pp.base[l - 1]), pp.ntop[l - 1],

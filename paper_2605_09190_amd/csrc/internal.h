@@ -77,7 +77,7 @@ struct LevelDev {
 // Per-pass counters in device memory.
 struct Counters {
   int32_t count[kLevels];   // nodes present at each level
-  int32_t act[2];           // active-list lengths (ping-pong)
+  int32_t act[3];           // active-list lengths (rotating: in, out, cleared)
   int32_t scan_error;       // set if a bounded scan wait ran out
   int32_t next[kLevels];    // work counter of the dynamically scheduled kernels per level
 };
@@ -105,6 +105,12 @@ struct StepArgs {
   const int32_t* act_count;
   unsigned long long* keys;   // [pos][atom tile][kTopR]
   int32_t n_atom_tiles;
+  // The select step appends the nodes still running to next_act (any
+  // order; zero on entry) and zeroes clear_count, the counter the step
+  // after the next one appends to.  next_act is null on a level's last step.
+  int32_t* next_act;
+  int32_t* next_count;
+  int32_t* clear_count;
 };
 
 // ---------------------------------------------------------------------------
@@ -113,14 +119,14 @@ struct StepArgs {
 hipError_t launch_init_counts(Counters* c, const int32_t* ntop_dev, hipStream_t s);
 hipError_t launch_gather(int n, const StepArgs& a, const int32_t* count, hipStream_t s);
 hipError_t launch_compact(const int32_t* in_list, const int32_t* in_count, const uint8_t* st,
-                          int32_t* out_list, int32_t* out_count, int64_t cap, ScanState ss,
-                          int32_t* err, hipStream_t s);
+                          int32_t* out_list, int32_t* out_count, int32_t* clear_count, int64_t cap,
+                          ScanState ss, int32_t* err, hipStream_t s);
 hipError_t launch_split_emit(const JobDev* jobs, LevelDev parent, const int32_t* parent_count,
                              LevelDev child, int32_t child_ntop, int32_t* child_count,
                              int32_t lg, int64_t cap, ScanState ss, int32_t* err, hipStream_t s);
 hipError_t launch_corr(int n, int precision, int variant, const void* dict_atoms, const StepArgs& a,
                        int32_t m_pad, hipStream_t s);
-hipError_t launch_select(int n, const StepArgs& a, hipStream_t s);
+hipError_t launch_select(int n, const StepArgs& a, int64_t cap, hipStream_t s);
 hipError_t launch_mp_fused(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t lg, int32_t n_atoms,
                            const double* tab, hipStream_t s);
 hipError_t launch_pursuit16_bf16(const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t n_atoms, int32_t nfam,

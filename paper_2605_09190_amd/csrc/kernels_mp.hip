@@ -94,11 +94,15 @@ struct WGeo {
 //   3. i = argmax |c| (lowest atom index on ties); stop if max |c| = 0;
 //   4. r <- r - c_i phi_i (FP64 arithmetic, stored in FP32), ||r||^2 in FP64;
 //   5. record (i, c_i), t <- t + 1, stop test of eq. (2).
-// One wave per node (N >= 16), no workgroup barriers and no atomics;
-// positions are walked grid-stride.  The candidates' 1D table rows are
-// staged in the wave's LDS slice with one coalesced load, so nothing after
-// the merge waits on global memory.  The stable compaction of the nodes
-// still running is a separate launch.
+// One wave per node (N >= 16); positions are walked grid-stride.  The
+// candidates' 1D table rows are staged in the wave's LDS slice with one
+// coalesced load, so nothing after the merge waits on global memory.
+// The nodes still running form the next step's active list: each wave holds
+// its survivors in registers (one per lane; the launch gives every wave at
+// most 64 positions), and after the loop the workgroup appends them with a
+// single atomic.  The list order then varies from run to run; no result
+// depends on it, since every node's arithmetic is independent of its list
+// position.
 // ---------------------------------------------------------------------------
 template <int N>
 __global__ __launch_bounds__(256) void k_select(StepArgs a) {
@@ -116,6 +120,7 @@ __global__ __launch_bounds__(256) void k_select(StepArgs a) {
   const int py = (lane / G::PX) * G::PH;
   const int px = (lane % G::PX) * G::PW;
   const int stride = gridDim.x * 4;
+  int held = -1, n_held = 0;   // survivors of this wave, lane j holds the j-th
   for (int pos = blockIdx.x * 4 + w; pos < count; pos += stride) {
     // The keys depend only on the position: their loads go out first.
     unsigned long long k[KPL];
@@ -269,24 +274,43 @@ __global__ __launch_bounds__(256) void k_select(StepArgs a) {
     __builtin_amdgcn_wave_barrier();   // table rows consumed before the next node overwrites them
 
     // 5. record and stop test (a zero correlation stops without a record).
+    // Every input of the test is uniform over the wave.
+    uint8_t st = ST_ZERO;
+    if (!zero) {
+      st = ST_RUN;
+      if (e < jb.eps2[lg])
+        st = ST_ACC;
+      else if (t + 1 >= jb.k[lg])
+        st = ST_SPARSE;
+    }
     if (lane == 0) {
-      if (zero) {
-        a.lv.st[node] = ST_ZERO;
-      } else {
-        uint8_t st = ST_RUN;
-        if (e < jb.eps2[lg])
-          st = ST_ACC;
-        else if (t + 1 >= jb.k[lg])
-          st = ST_SPARSE;
+      if (!zero) {
         const size_t rs = (size_t)node * a.lv.kmax + t;
         a.lv.rec_idx[rs] = atom;
         a.lv.rec_coef[rs] = coef;
         a.lv.t[node] = t + 1;
         a.lv.e[node] = e;
-        a.lv.st[node] = st;
       }
+      a.lv.st[node] = st;
+    }
+    if (st == ST_RUN) {
+      if (lane == n_held) held = node;
+      ++n_held;
     }
   }
+  if (a.next_act == nullptr) return;   // uniform: the level's last step
+  __shared__ int s_held[4], s_base;
+  if (lane == 0) s_held[w] = n_held;
+  __syncthreads();
+  if (tid == 0) {
+    const int tot = s_held[0] + s_held[1] + s_held[2] + s_held[3];
+    s_base = tot > 0 ? atomicAdd(a.next_count, tot) : 0;
+    if (blockIdx.x == 0) *a.clear_count = 0;
+  }
+  __syncthreads();
+  int off = s_base;
+  for (int j = 0; j < w; ++j) off += s_held[j];
+  if (lane < n_held) a.next_act[off + lane] = held;
 }
 
 // ---------------------------------------------------------------------------
@@ -372,11 +396,16 @@ hipError_t launch_gather(int n, const StepArgs& a, const int32_t* count, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_select(int n, const StepArgs& a, hipStream_t s) {
+hipError_t launch_select(int n, const StepArgs& a, int64_t cap, hipStream_t s) {
+  // At most 64 positions per wave (4 waves per workgroup): one register per
+  // lane holds a survivor.
+  int64_t g = grid_for<16>(4);
+  if (g * 4 * 64 < cap) g = (cap + 255) / 256;
+  const dim3 grid((unsigned)g);
   switch (n) {
-    case 16: hipLaunchKernelGGL(k_select<16>, dim3(grid_for<16>(4)), dim3(256), 0, s, a); break;
-    case 32: hipLaunchKernelGGL(k_select<32>, dim3(grid_for<32>(4)), dim3(256), 0, s, a); break;
-    case 64: hipLaunchKernelGGL(k_select<64>, dim3(grid_for<64>(4)), dim3(256), 0, s, a); break;
+    case 16: hipLaunchKernelGGL(k_select<16>, grid, dim3(256), 0, s, a); break;
+    case 32: hipLaunchKernelGGL(k_select<32>, grid, dim3(256), 0, s, a); break;
+    case 64: hipLaunchKernelGGL(k_select<64>, grid, dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;   // smaller levels run the fused pursuit
   }
   return hipGetLastError();

@@ -86,11 +86,15 @@ struct CompactOp {
   const uint8_t* st;
   int32_t* out_list;
   int32_t* out_count;
+  int32_t* clear;           // optional counter set to zero with the total
   __device__ int count() const { return *in_count; }
   __device__ int node(int i) const { return in_list ? in_list[i] : i; }
   __device__ int keep(int i) const { return st[node(i)] == ST_RUN ? 1 : 0; }
   __device__ void emit(int i, int pos) const { out_list[pos] = node(i); }
-  __device__ void total(int t) const { *out_count = t; }
+  __device__ void total(int t) const {
+    *out_count = t;
+    if (clear) *clear = 0;
+  }
 };
 
 struct SplitOp {
@@ -146,7 +150,7 @@ __global__ void k_init_counts(Counters* c, const int32_t* ntop) {
     c->count[i] = ntop[i];
     c->next[i] = 0;
   }
-  if (i < 2) c->act[i] = 0;
+  if (i < 3) c->act[i] = 0;
   if (i == 0) c->scan_error = 0;
 }
 
@@ -163,9 +167,9 @@ static int scan_blocks(int64_t cap) {
 }
 
 hipError_t launch_compact(const int32_t* in_list, const int32_t* in_count, const uint8_t* st,
-                          int32_t* out_list, int32_t* out_count, int64_t cap, ScanState ss,
-                          int32_t* err, hipStream_t s) {
-  CompactOp op{in_list, in_count, st, out_list, out_count};
+                          int32_t* out_list, int32_t* out_count, int32_t* clear_count, int64_t cap,
+                          ScanState ss, int32_t* err, hipStream_t s) {
+  CompactOp op{in_list, in_count, st, out_list, out_count, clear_count};
   hipLaunchKernelGGL(k_compact, dim3(scan_blocks(cap)), dim3(256), 0, s, op, ss, err);
   return hipGetLastError();
 }

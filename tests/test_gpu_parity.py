@@ -210,6 +210,22 @@ def test_reencode_deterministic(A, dic):
         assert e1.coef.tobytes() == e2.coef.tobytes()
 
 
+def test_reencode_deterministic_full_size(A, dic):
+    """The 2048 x 2048 three-channel encode: the active lists are rebuilt by
+    atomic appends in a different order on every replay, and the exported
+    trees, atoms and coefficients stay bit-identical."""
+    w = workload("c3")
+    imgs = [_dev(c) for c in w["channels"]]
+    code = A.Code(dic, imgs, w["params"], w["jobs"], precision=1, schedule=1)
+    e1 = code.export_nodes()
+    ref = (e1.leaves.tobytes(), e1.atom_idx.tobytes(), e1.coef.tobytes())
+    for i in range(3):
+        code.reencode(imgs)
+        e2 = code.export_nodes()
+        assert (e2.leaves.tobytes(), e2.atom_idx.tobytes(), e2.coef.tobytes()) == ref, f"replay {i}"
+    code.free()
+
+
 @pytest.mark.parametrize("form", ["fp32", "bf16", "gram", "omp"])
 def test_non_multiple_plane_edge_padded(A, dic, form):
     """A 100 x 70 plane with N_max = 32 (tiled as 128 x 96, last row and
