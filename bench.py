@@ -25,15 +25,20 @@ sys.path.insert(0, ROOT)
 METRIC = "AQMP encode Mpixel/s (batched BF16 vs plain FP32) at equal PSNR; MP iters/s"
 PEAK_BF16_TFLOPS = 2500.0     # MI355X dense BF16 MFMA
 PEAK_FP32_TFLOPS = 157.3      # MI355X dense FP32 MFMA
+PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
 
-# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE runs, scaled by a copy-kernel calibration
-# (profiles/traffic_k_corr_bf16_gen64_2048x2048x3_ycbcr.md); valid only for
-# the kernel source and the workload they were taken on.
+# HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE runs, scaled
+# by a copy-kernel calibration (profiles/traffic_k_corr_bf16_gen64_2048x2048x3_ycbcr.md,
+# profiles/traffic_k_select_2048x2048x3_ycbcr.md); valid only for the kernel
+# source and the workload they were taken on.
+_MP_SRC = dict(workload="c3", src="paper_2605_09190_amd/csrc/kernels_mp.hip",
+               sha256="ecd76772af81045c0455edbe793c529c7112737d79c93236870109480a1fba56")
 TRAFFIC = {
     "k_corr_bf16_gen<64>": dict(bytes_per_launch=15.69e6, fetch=13.28e6, write=2.41e6, workload="c3",
                                 src="paper_2605_09190_amd/csrc/kernels_corr.hip",
                                 sha256="b3775b1b9612aaa553e2368099a2a8d2248cdbfc322bcf852338f0733eb8661e"),
+    "k_select<64>": dict(bytes_per_launch=51.59e6, fetch=22.56e6, write=29.04e6, **_MP_SRC),
+    "k_select<32>": dict(bytes_per_launch=21.09e6, fetch=9.25e6, write=11.83e6, **_MP_SRC),
 }
 
 
@@ -141,10 +146,22 @@ def solver_roofline(A, dic, imgs, w, solver, sched, steps, warmup):
                 flops_per_launch=flops, nodes=int(st["nodes"][lg]), other=other)
 
 
+def select_bytes(n, precision):
+    """Algorithmic HBM bytes of one node-iteration of the select/update step
+    at block size n: the FP32 residual read and written back (4K + 4K), its
+    BF16 copy written in the BF16 form (2K), the node's top-R keys of every
+    atom tile (8 B each, M = 2K atoms in tiles of 256) and the record
+    (4 B index + 8 B coefficient)."""
+    k = n * n
+    tiles = max(1, (2 * k + 255) // 256)
+    return 8 * k + (2 * k if precision == 1 else 0) + tiles * 8 * 8 + 12
+
+
 def roofline(stats, timing, precision, kernel_name=None, workload=None):
     """Dominant kernel: the correlation of the largest block size.  Algorithmic
     work per node-iteration is 2*K*M = 4 N^4 flops (every atom correlated with
-    the residual); one launch processes the nodes active in that MP step."""
+    the residual); one launch processes the nodes active in that MP step.
+    Each level also reports the select/update step against HBM bandwidth."""
     lg = max(l for l in range(7) if stats["iters_level"][l] > 0)
     n = 1 << lg
     flops = 4.0 * n ** 4 * stats["iters_level"][lg]
@@ -163,6 +180,13 @@ def roofline(stats, timing, precision, kernel_name=None, workload=None):
                                       level_ms=round(timing["level_ms"][l], 3),
                                       launches=int(timing["steps"][l]),
                                       avg_corr_us=round(1e3 * timing["corr_ms"][l] / max(1, timing["steps"][l]), 2))
+            if timing["select_ms"][l] > 0:
+                b = select_bytes(nn, precision) * stats["iters_level"][l]
+                gbs = b / (timing["select_ms"][l] * 1e-3) / 1e9
+                per_level[str(nn)].update(select_bytes_per_iter=select_bytes(nn, precision),
+                                          select_gbs=round(gbs, 1), select_hbm_frac=round(gbs / PEAK_HBM_GBS, 4),
+                                          select_traffic=(measured_traffic(f"k_select<{nn}>", workload)
+                                                          if precision == 1 else None))
     kname = kernel_name(n) if kernel_name else f"correlation<N={n}>"
     return dict(bound="mfma", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
                 frac=round(achieved / peak, 4), traffic=measured_traffic(kname, workload), traffic_unit="bytes per launch",
