@@ -74,6 +74,46 @@ def time_steps(code, imgs, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+def end_to_end(code, imgs, w, npx, steps):
+    """The encode as a host caller sees it: the FP32 planes copied from
+    pinned host memory, the encode (graph replay) and the export of the
+    leaves, atom indices and coefficients into host memory, one after the
+    other.  Reported beside the headline, never as its value."""
+    import torch
+    host = [torch.from_numpy(np.ascontiguousarray(c)).to(torch.float32).pin_memory() for c in w["channels"]]
+    acc = np.zeros(3)
+    n_leaves = n_atoms = 0
+    for i in range(steps + 1):              # the first pass is a warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for d, h in zip(imgs, host):
+            d.copy_(h, non_blocking=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        code.reencode(imgs)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        e = code.export()
+        t3 = time.perf_counter()
+        if i:
+            acc += (t1 - t0, t2 - t1, t3 - t2)
+        n_leaves, n_atoms = len(e.leaves), len(e.atom_idx)
+    acc /= steps
+    tot = float(acc.sum())
+    h2d = sum(int(h.numel()) * 4 for h in host)
+    d2h = n_leaves * code_leaf_bytes() + n_atoms * (4 + 8)
+    return dict(value=round(npx / tot / 1e6, 3), unit="Mpixel/s", ms_per_step=round(tot * 1e3, 3), steps=steps,
+                h2d_ms=round(acc[0] * 1e3, 3), encode_ms=round(acc[1] * 1e3, 3), export_ms=round(acc[2] * 1e3, 3),
+                h2d_bytes=h2d, result_bytes=d2h,
+                includes="H2D of the FP32 planes from pinned host memory, encode (graph replay), export of leaves, "
+                         "atom indices and coefficients to host memory; sequential")
+
+
+def code_leaf_bytes():
+    from paper_2605_09190_amd import aqmp as A
+    return A.LEAF_DTYPE.itemsize
+
+
 def psnr_jobs(code, imgs, jobs):
     import torch
     out = []
@@ -317,6 +357,8 @@ def main():
     stats = code.stats()
     psnr_b = psnr_jobs(code, imgs, w["jobs"])
     ssim_b, cr_b = quality(A, code, imgs, w)
+    e2e = end_to_end(code, imgs, w, npx, max(3, args.steps // 4))
+    log(f"end to end (H2D + encode + export): {e2e['ms_per_step']} ms/step")
     code.free()   # every form below allocates its own buffers
     log(f"bf16 batched (graph): {sec * 1e3:.3f} ms/step")
 
@@ -433,6 +475,7 @@ def main():
         "mp_iters_emitted": int(stats["iters_emitted"]),
         "leaves": int(sum(stats["leaves"])),
         "ms_per_step_stream_timed": round(sec_t * 1e3, 4),
+        "end_to_end": e2e,
         "psnr_db": [round(p, 4) for p in psnr_b],
         "ssim_window7": ssim_b,
         "cr": cr_b,

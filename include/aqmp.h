@@ -20,8 +20,11 @@
  *   - Same inputs give bit-identical outputs: all reductions have a fixed
  *     order, and no result depends on the order of the active-node list
  *     (which the select step builds by atomic append).
- *   - A handle may be used by one thread at a time (the readers of a code
- *     keep a host copy of its nodes until the next encode of that code).
+ *   - A handle may be used by one thread at a time.  The first read of a
+ *     code after an encode (sizes, stats, export, pack) sorts its visited
+ *     nodes into canonical order on the device, on the encode stream, and
+ *     copies them once into page-locked host memory owned by the handle;
+ *     later reads use that copy until the next encode of that code.
  *   - Block sizes N are powers of two with 4 <= N <= 64.
  *
  * Pixel and atom layout.  A block b of size N is the N x N sub-matrix of a

@@ -39,9 +39,14 @@ struct PassPlan {
 // A node copied back to the host, with its place in the canonical order.
 struct HostNode {
   aqmp_leaf leaf;
-  int64_t key_hi, key_lo;      // canonical order
   const int32_t* idx;
   const double* coef;
+};
+
+// Grow-only device (or pinned host) buffer of a code's result gather.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
 };
 
 }  // namespace aqmp
@@ -97,12 +102,22 @@ struct aqmp_code {
   std::vector<LevelEv> lev;
   std::vector<StepEv> sev;
   size_t lev_pos = 0, sev_pos = 0;
-  // Every visited node of the last encode in canonical order, copied back on
-  // the first read (stats, export, pack) and kept until the next encode.
+  // Every visited node of the last encode in canonical order, gathered on
+  // the device and copied back on the first read (stats, export, pack), kept
+  // until the next encode.
   bool nodes_ok = false;
-  std::vector<aqmp::HostNode> nodes;
-  std::vector<std::vector<int32_t>> node_idx;
-  std::vector<std::vector<double>> node_coef;
+  std::vector<aqmp::HostNode> nodes;   // records and atoms point into `pinned`
+  aqmp::DevBuf pinned;                 // page-locked host copy of ex_out
+  // Device side of the gather: segment and job tables (built once), keys,
+  // flat ids, scan and output buffers (grown as needed).
+  bool ex_ready = false;
+  int ex_nseg = 0;
+  int ex_end_bit = 0;
+  int64_t ex_max_cap = 0;
+  aqmp::ExportSeg* d_ex_segs = nullptr;
+  aqmp::ExportJob* d_ex_jobs = nullptr;
+  // ex_out: node records, then atom indices, then coefficients (8-byte aligned)
+  aqmp::DevBuf ex_keys, ex_keys2, ex_vals, ex_vals2, ex_tot, ex_tmp, ex_t, ex_off, ex_out;
 };
 
 namespace aqmp {
@@ -263,6 +278,10 @@ void free_code(aqmp_code* c) {
   for (auto& e : c->lev) (void)hipEventDestroy(e.start), (void)hipEventDestroy(e.end);
   for (auto& e : c->sev) (void)hipEventDestroy(e.a), (void)hipEventDestroy(e.b), (void)hipEventDestroy(e.c);
   for (auto& a : c->allocs) dev_free(a.p, a.bytes);
+  for (DevBuf* b : {&c->ex_keys, &c->ex_keys2, &c->ex_vals, &c->ex_vals2, &c->ex_tot, &c->ex_tmp, &c->ex_t,
+                    &c->ex_off, &c->ex_out})
+    if (b->p) dev_free(b->p, b->bytes);
+  if (c->pinned.p) (void)hipHostFree(c->pinned.p);
   delete c;
 }
 
@@ -592,80 +611,172 @@ int run(aqmp_code* c, hipStream_t s) {
   return AQMP_OK;
 }
 
-uint64_t morton(uint32_t x, uint32_t y) {
-  uint64_t m = 0;
-  for (int b = 0; b < 16; ++b) {
-    m |= (uint64_t)((x >> b) & 1u) << (2 * b);
-    m |= (uint64_t)((y >> b) & 1u) << (2 * b + 1);
-  }
-  return m;
+int ensure(DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes && b.p) return AQMP_OK;
+  if (b.p) dev_free(b.p, b.bytes);
+  b.p = nullptr;
+  b.bytes = 0;
+  const size_t nb = std::max<size_t>(bytes + bytes / 4, 256);
+  const int rc = dev_alloc(&b.p, nb);
+  if (rc != AQMP_OK) return rc;
+  b.bytes = nb;
+  return AQMP_OK;
 }
 
-// Copies every visited node back and orders them canonically: job, top-level
-// block in raster order, then depth-first (Morton order of the corner, the
-// larger node first).
-int collect_all(aqmp_code* c, std::vector<HostNode>& out, std::vector<std::vector<int32_t>>& idx_store,
-                std::vector<std::vector<double>>& coef_store) {
-  AQMP_HIP(hipStreamSynchronize(c->stream));
-  std::vector<Counters> cnt(c->passes.size());
-  AQMP_HIP(hipMemcpy(cnt.data(), c->dcnt, sizeof(Counters) * cnt.size(), hipMemcpyDeviceToHost));
-  for (auto& k : cnt)
-    if (k.scan_error) AQMP_FAIL(AQMP_E_HIP, "aqmp_encode: a device scan exceeded its bounded wait");
-  idx_store.clear();
-  coef_store.clear();
+int ensure_pinned(DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes && b.p) return AQMP_OK;
+  if (b.p) AQMP_HIP(hipHostFree(b.p));
+  b.p = nullptr;
+  b.bytes = 0;
+  const size_t nb = std::max<size_t>(bytes + bytes / 4, 256);
+  AQMP_HIP(hipHostMalloc(&b.p, nb, hipHostMallocDefault));
+  b.bytes = nb;
+  return AQMP_OK;
+}
+
+// Segment table (one entry per level of every pass) and job table of the
+// device gather; built on the first read of a code.
+int export_tables(aqmp_code* c) {
+  std::vector<ExportSeg> segs;
+  uint64_t flat = 0;
+  int64_t max_cap = 0;
   for (size_t pi = 0; pi < c->passes.size(); ++pi) {
     const PassPlan& pp = c->passes[pi];
     for (int l = pp.lg_hi; l >= pp.lg_lo; --l) {
-      const int64_t n = cnt[pi].count[l];
-      if (pp.cap[l] == 0 || n <= 0) continue;
-      if (n > pp.cap[l]) AQMP_FAIL(AQMP_E_HIP, "aqmp_encode: level count exceeds its capacity");
-      const LevelDev L = level_at(c, l, pp.base[l]);
-      std::vector<int32_t> job(n), x0(n), y0(n), t(n);
-      std::vector<double> e(n);
-      std::vector<uint8_t> st(n);
-      AQMP_HIP(hipMemcpy(job.data(), L.job, 4 * n, hipMemcpyDeviceToHost));
-      AQMP_HIP(hipMemcpy(x0.data(), L.x0, 4 * n, hipMemcpyDeviceToHost));
-      AQMP_HIP(hipMemcpy(y0.data(), L.y0, 4 * n, hipMemcpyDeviceToHost));
-      AQMP_HIP(hipMemcpy(t.data(), L.t, 4 * n, hipMemcpyDeviceToHost));
-      AQMP_HIP(hipMemcpy(e.data(), L.e, 8 * n, hipMemcpyDeviceToHost));
-      AQMP_HIP(hipMemcpy(st.data(), L.st, n, hipMemcpyDeviceToHost));
-      idx_store.emplace_back((size_t)n * L.kmax);
-      coef_store.emplace_back((size_t)n * L.kmax);
-      AQMP_HIP(hipMemcpy(idx_store.back().data(), L.rec_idx, 4 * n * L.kmax, hipMemcpyDeviceToHost));
-      AQMP_HIP(hipMemcpy(coef_store.back().data(), L.rec_coef, 8 * n * L.kmax, hipMemcpyDeviceToHost));
-      for (int64_t i = 0; i < n; ++i) {
-        const bool split = (st[i] & ST_SPLIT) != 0;
-        const int nm = c->prm[c->jobs[job[i]].params].n_max;
-        HostNode h{};
-        h.leaf.job = job[i];
-        h.leaf.x0 = x0[i];
-        h.leaf.y0 = y0[i];
-        h.leaf.n = 1 << l;
-        h.leaf.n_atoms = t[i];
-        h.leaf.flags = split ? 1 : 0;
-        h.leaf.resid_sq = e[i];
-        const int64_t cols = padded(c->imgs[c->jobs[job[i]].image].w, nm) / nm;   // top-level blocks per row
-        h.key_hi = ((int64_t)job[i] << 40) | ((int64_t)(y0[i] / nm) * cols + x0[i] / nm);
-        h.key_lo = (int64_t)(morton((uint32_t)(x0[i] % nm), (uint32_t)(y0[i] % nm)) << 8) | (255 - l);
-        h.idx = idx_store.back().data() + (size_t)i * L.kmax;
-        h.coef = coef_store.back().data() + (size_t)i * L.kmax;
-        out.push_back(h);
-      }
+      if (pp.cap[l] == 0) continue;
+      ExportSeg sg;
+      sg.L = level_at(c, l, pp.base[l]);
+      sg.count = &c->dcnt[pi].count[l];
+      sg.lg = l;
+      sg.flat_base = (uint32_t)flat;
+      segs.push_back(sg);
+      flat += (uint64_t)pp.cap[l];
+      max_cap = std::max<int64_t>(max_cap, pp.cap[l]);
     }
   }
-  std::sort(out.begin(), out.end(), [](const HostNode& a, const HostNode& b) {
-    return a.key_hi != b.key_hi ? a.key_hi < b.key_hi : a.key_lo < b.key_lo;
-  });
+  if (flat >= (1ull << 32) || segs.size() > 65535)
+    AQMP_FAIL(AQMP_E_CAPACITY, "aqmp_code: too many node slots for the result gather");
+  std::vector<ExportJob> jx(c->jobs.size());
+  long long tops = 0;
+  for (size_t j = 0; j < c->jobs.size(); ++j) {
+    const int nm = c->prm[c->jobs[j].params].n_max;
+    const aqmp_image& im = c->imgs[c->jobs[j].image];
+    jx[j].top_base = tops;
+    jx[j].nm = nm;
+    jx[j].cols = (int32_t)(padded(im.w, nm) / nm);
+    tops += (long long)jx[j].cols * (padded(im.h, nm) / nm);
+  }
+  int bits = 1;
+  while (bits < 63 && (1ll << bits) < tops) ++bits;
+  if (bits + kExportLowBits > 64) AQMP_FAIL(AQMP_E_CAPACITY, "aqmp_code: too many top-level blocks for the result gather");
+  c->ex_end_bit = bits + kExportLowBits;
+  c->ex_nseg = (int)segs.size();
+  c->ex_max_cap = max_cap;
+  if (!segs.empty()) {
+    const int rc1 = alloc(c, (void**)&c->d_ex_segs, sizeof(ExportSeg) * segs.size());
+    if (rc1 != AQMP_OK) return rc1;
+    const int rc2 = alloc(c, (void**)&c->d_ex_jobs, sizeof(ExportJob) * jx.size());
+    if (rc2 != AQMP_OK) return rc2;
+    AQMP_HIP(hipMemcpy(c->d_ex_segs, segs.data(), sizeof(ExportSeg) * segs.size(), hipMemcpyHostToDevice));
+    AQMP_HIP(hipMemcpy(c->d_ex_jobs, jx.data(), sizeof(ExportJob) * jx.size(), hipMemcpyHostToDevice));
+    int rc = ensure(c->ex_keys, sizeof(unsigned long long) * flat);
+    if (rc == AQMP_OK) rc = ensure(c->ex_vals, sizeof(uint32_t) * flat);
+    if (rc == AQMP_OK) rc = ensure(c->ex_tot, 2 * sizeof(unsigned long long));
+    if (rc != AQMP_OK) return rc;
+  }
+  c->ex_ready = true;
   return AQMP_OK;
 }
+
+#define AQMP_ENSURE(buf, bytes)                 \
+  do {                                          \
+    const int rc_ = ensure((buf), (bytes));     \
+    if (rc_ != AQMP_OK) return rc_;             \
+  } while (0)
+
+// Gathers every visited node on the device in canonical order (job, top-level
+// block in raster order, then depth-first: Morton order of the corner, the
+// larger node first) and copies three dense arrays back: node records, atom
+// indices, coefficients.
+int collect_all(aqmp_code* c) {
+  hipStream_t s = c->stream;
+  AQMP_HIP(hipStreamSynchronize(s));
+  std::vector<Counters> cnt(c->passes.size());
+  AQMP_HIP(hipMemcpy(cnt.data(), c->dcnt, sizeof(Counters) * cnt.size(), hipMemcpyDeviceToHost));
+  for (size_t pi = 0; pi < cnt.size(); ++pi) {
+    if (cnt[pi].scan_error) AQMP_FAIL(AQMP_E_HIP, "aqmp_encode: a device scan exceeded its bounded wait");
+    for (int l = 0; l < kLevels; ++l)
+      if (cnt[pi].count[l] > c->passes[pi].cap[l])
+        AQMP_FAIL(AQMP_E_HIP, "aqmp_encode: level count exceeds its capacity");
+  }
+  c->nodes.clear();
+  if (!c->ex_ready) {
+    const int rc = export_tables(c);
+    if (rc != AQMP_OK) return rc;
+  }
+  if (c->ex_nseg == 0) return AQMP_OK;
+  auto* keys = (unsigned long long*)c->ex_keys.p;
+  auto* vals = (uint32_t*)c->ex_vals.p;
+  auto* tot = (unsigned long long*)c->ex_tot.p;
+  AQMP_HIP(hipMemsetAsync(tot, 0, 2 * sizeof(unsigned long long), s));
+  AQMP_HIP(launch_export_keys(c->d_ex_segs, c->ex_nseg, c->ex_max_cap, c->d_ex_jobs, keys, vals, tot, s));
+  unsigned long long ht[2] = {0, 0};
+  AQMP_HIP(hipMemcpyAsync(ht, tot, sizeof(ht), hipMemcpyDeviceToHost, s));
+  AQMP_HIP(hipStreamSynchronize(s));
+  const int64_t n = (int64_t)ht[0], na = (int64_t)ht[1];
+  if (n == 0) return AQMP_OK;
+  AQMP_ENSURE(c->ex_keys2, sizeof(unsigned long long) * n);
+  AQMP_ENSURE(c->ex_vals2, sizeof(uint32_t) * n);
+  AQMP_ENSURE(c->ex_t, sizeof(int64_t) * n);
+  AQMP_ENSURE(c->ex_off, sizeof(int64_t) * n);
+  auto* keys2 = (unsigned long long*)c->ex_keys2.p;
+  auto* vals2 = (uint32_t*)c->ex_vals2.p;
+  auto* tcount = (int64_t*)c->ex_t.p;
+  auto* off = (int64_t*)c->ex_off.p;
+  size_t sort_bytes = 0, scan_bytes = 0;
+  AQMP_HIP(export_sort(nullptr, sort_bytes, keys, keys2, vals, vals2, n, c->ex_end_bit, s));
+  AQMP_HIP(export_scan(nullptr, scan_bytes, tcount, off, n, s));
+  AQMP_ENSURE(c->ex_tmp, std::max(sort_bytes, scan_bytes));
+  sort_bytes = scan_bytes = c->ex_tmp.bytes;
+  AQMP_HIP(export_sort(c->ex_tmp.p, sort_bytes, keys, keys2, vals, vals2, n, c->ex_end_bit, s));
+  AQMP_HIP(launch_export_counts(c->d_ex_segs, c->ex_nseg, vals2, n, tcount, s));
+  AQMP_HIP(export_scan(c->ex_tmp.p, scan_bytes, tcount, off, n, s));
+  // one output block, one copy into page-locked memory
+  const size_t idx_at = sizeof(aqmp_leaf) * n;
+  const size_t coef_at = idx_at + (sizeof(int32_t) * na + 7) / 8 * 8;
+  const size_t total = coef_at + sizeof(double) * na;
+  AQMP_ENSURE(c->ex_out, total);
+  {
+    const int rc = ensure_pinned(c->pinned, total);
+    if (rc != AQMP_OK) return rc;
+  }
+  char* dout = (char*)c->ex_out.p;
+  AQMP_HIP(launch_export_write(c->d_ex_segs, c->ex_nseg, vals2, off, n, (aqmp_leaf*)dout, (int32_t*)(dout + idx_at),
+                               (double*)(dout + coef_at), s));
+  AQMP_HIP(hipMemcpyAsync(c->pinned.p, dout, total, hipMemcpyDeviceToHost, s));
+  AQMP_HIP(hipStreamSynchronize(s));
+  const char* hout = (const char*)c->pinned.p;
+  const aqmp_leaf* rec = (const aqmp_leaf*)hout;
+  const int32_t* idx = (const int32_t*)(hout + idx_at);
+  const double* coef = (const double*)(hout + coef_at);
+  c->nodes.resize(n);
+  for (int64_t i = 0; i < n; ++i) {
+    HostNode& h = c->nodes[i];
+    h.leaf = rec[i];
+    h.idx = idx + h.leaf.atom_off;
+    h.coef = coef + h.leaf.atom_off;
+  }
+  return AQMP_OK;
+}
+
+#undef AQMP_ENSURE
 
 // The code's visited nodes (or leaves) in canonical order; the device copy is
 // made once per encode.
 int collect(const aqmp_code* cc, bool leaves_only, std::vector<HostNode>& out) {
   aqmp_code* c = const_cast<aqmp_code*>(cc);   // the cache is not part of the code's observable state
   if (!c->nodes_ok) {
-    c->nodes.clear();
-    const int rc = collect_all(c, c->nodes, c->node_idx, c->node_coef);
+    const int rc = collect_all(c);
     if (rc != AQMP_OK) return rc;
     c->nodes_ok = true;
   }
@@ -791,10 +902,8 @@ int code_export(const aqmp_code* c, bool leaves_only, aqmp_leaf* leaves, int32_t
   for (size_t i = 0; i < nodes.size(); ++i) {
     aqmp_leaf L = nodes[i].leaf;
     L.atom_off = off;
-    for (int t = 0; t < L.n_atoms; ++t) {
-      atom_idx[off + t] = nodes[i].idx[t];
-      coef[off + t] = nodes[i].coef[t];
-    }
+    std::memcpy(atom_idx + off, nodes[i].idx, sizeof(int32_t) * L.n_atoms);
+    std::memcpy(coef + off, nodes[i].coef, sizeof(double) * L.n_atoms);
     off += L.n_atoms;
     leaves[i] = L;
   }
@@ -862,11 +971,10 @@ int code_pack(const aqmp_code* c, const int32_t* jobs, int n_jobs, int level, ui
   put<uint8_t>(raw, 0);
   for (int i = 0; i < n_jobs; ++i) {
     // the job's nodes are contiguous in the canonical order
-    const int64_t jk = (int64_t)jobs[i] << 40;
-    auto lo = std::lower_bound(nodes.begin(), nodes.end(), jk,
-                               [](const HostNode& a, int64_t k) { return a.key_hi < k; });
-    auto hi = std::lower_bound(lo, nodes.end(), jk + ((int64_t)1 << 40),
-                               [](const HostNode& a, int64_t k) { return a.key_hi < k; });
+    auto lo = std::lower_bound(nodes.begin(), nodes.end(), jobs[i],
+                               [](const HostNode& a, int32_t j) { return a.leaf.job < j; });
+    auto hi = std::lower_bound(lo, nodes.end(), jobs[i] + 1,
+                               [](const HostNode& a, int32_t j) { return a.leaf.job < j; });
     uint32_t n_leaves = 0, n_atoms = 0;
     std::vector<uint8_t> bits;
     int nbits = 0;

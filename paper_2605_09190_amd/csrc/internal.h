@@ -152,6 +152,32 @@ hipError_t launch_decode(int n, const JobDev* jobs, LevelDev lv, const int32_t* 
                          int32_t nfam, const double* tab, void* out, int32_t dtype,
                          int64_t row_stride, hipStream_t s);
 
+// Device gather of a code's visited nodes in canonical order.  Sort key of a
+// node: global top-level block ordinal << kExportLowBits | Morton code of its
+// corner inside that block << 3 | (7 - log2 N).
+constexpr int kExportCornerBits = 6;                       // corner coordinates < 64
+constexpr int kExportLowBits = 2 * kExportCornerBits + 3;
+struct ExportSeg {          // one level of one pass
+  LevelDev L;               // offset by the pass base
+  const int32_t* count;     // nodes present (device)
+  int32_t lg;
+  uint32_t flat_base;       // first flat node id of the segment
+};
+struct ExportJob {
+  long long top_base;       // global ordinal of the job's first top-level block
+  int32_t nm;               // N_max of the job
+  int32_t cols;             // top-level blocks per row of the padded plane
+};
+hipError_t launch_export_keys(const ExportSeg* segs, int nseg, int64_t max_cap, const ExportJob* jx,
+                              unsigned long long* keys, uint32_t* vals, unsigned long long* totals, hipStream_t s);
+hipError_t export_sort(void* tmp, size_t& tmp_bytes, unsigned long long* keys, unsigned long long* keys_out,
+                       uint32_t* vals, uint32_t* vals_out, int64_t n, int end_bit, hipStream_t s);
+hipError_t export_scan(void* tmp, size_t& tmp_bytes, const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
+hipError_t launch_export_counts(const ExportSeg* segs, int nseg, const uint32_t* vals, int64_t n, int64_t* t_out,
+                                hipStream_t s);
+hipError_t launch_export_write(const ExportSeg* segs, int nseg, const uint32_t* vals, const int64_t* off, int64_t n,
+                               aqmp_leaf* out, int32_t* idx, double* coef, hipStream_t s);
+
 // Name of the correlation kernel launch_corr runs (or the fused pursuit for
 // n <= kFusedMaxN); "" when the combination is invalid.
 const char* corr_kernel_name(int n, int precision, int variant);
