@@ -151,6 +151,15 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long v) {
 #undef AQMP_MAXSTEP
   return lane63_u64(v);
 }
+// Orders the LDS writes of a wave's lanes before its later LDS reads by
+// other lanes of the same wave (no workgroup barrier): the wave's LDS
+// operations complete before it goes on.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 __device__ inline double wave_sum_f64(double d) {
 #define AQMP_SUMSTEP(C, RM) { d += __longlong_as_double((long long)dpp_u64<C, RM>((unsigned long long)__double_as_longlong(d))); }
   AQMP_SUMSTEP(0xB1, 0xF) AQMP_SUMSTEP(0x4E, 0xF) AQMP_SUMSTEP(0x141, 0xF)

@@ -559,9 +559,30 @@ template <int N, int NFAM>
 struct OmpGeo {
   static constexpr int K = N * N;
   static constexpr int M = NFAM * K;
-  static constexpr int APT = M >= 256 ? M / 256 : 1;   // atoms per thread: a = tid + 256 j
-  static constexpr int AF = APT / NFAM;                // per family when M >= 256
-  static constexpr bool SMALL = N <= 8;                // M <= 128: one atom per thread, c0 computed here
+  static constexpr bool SMALL = N <= 8;                // M <= 128: atom tid in thread tid, c0 computed here
+  // N >= 16: thread tid owns, in each family, the TP x TP tile of atoms
+  // p = (tid % 16) TP + dp, q = (tid / 16) TP + dq, as j = f AF + dq TP + dp
+  // (the atom index grows with j, so the per-thread arg-max keeps the lowest
+  // index on ties).  The cross-family correlation refresh of one selected
+  // atom then reads 2 TP table entries for TP^2 multiply-adds.
+  static constexpr int TP = SMALL ? 1 : N / 16;
+  static constexpr int AF = TP * TP;
+  static constexpr int APT = SMALL ? 1 : NFAM * AF;
+  __device__ static int atom(int tid, int j) {
+    if constexpr (SMALL) return tid;
+    const int f = j / AF, r = j % AF;
+    return f * K + ((tid / 16) * TP + r / TP) * N + (tid % 16) * TP + r % TP;
+  }
+  __device__ static int owner(int a) {
+    if constexpr (SMALL) return a;
+    const int q = (a % K) / N, p = a % N;
+    return (q / TP) * 16 + p / TP;
+  }
+  __device__ static int slot(int a) {
+    if constexpr (SMALL) return 0;
+    const int q = (a % K) / N, p = a % N;
+    return (a / K) * AF + (q % TP) * TP + p % TP;
+  }
 };
 
 template <int N, int NFAM>
@@ -580,9 +601,13 @@ __global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, Le
   __shared__ double sL[KC][KC + 1];                    // L = chol(G_SS)^-1, lower triangular
   __shared__ int sS[KC];                               // selected atoms in order
   __shared__ double sZ[KC], sXc[KC], sG[KC], sW[KC];   // z, x_S, g, w
-  __shared__ double sBc[2][4];
+  // the selected atoms split by family, in selection order: p | q << 8 and x
+  __shared__ int sPQ[NFAM][KC];
+  __shared__ double sXF[NFAM][KC];
+  __shared__ int sNF[NFAM];
+  __shared__ double sBc[2][4], sB0[2][4];             // per-wave best |c| and its c0
   __shared__ int sBi[2][4];
-  __shared__ double sScal[4];                          // <y, phi_i>, 1 / d, new ||r||^2, dependence flag
+  __shared__ double sScal[2];                          // dependence flag, new ||r||^2
   __shared__ double sRed[2];
   __shared__ int sNode[2];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -592,7 +617,8 @@ __global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, Le
     for (int i = tid; i < NFAM * K; i += 256) (&sT[0][0])[i] = tab[i];
   __syncthreads();
   const int count = *count_ptr;
-  const int pa = tid % N;                              // p of every atom of this thread (256 = 0 mod N)
+  const int pa = tid % N;                              // p of the thread's atom (N <= 8)
+  const int pb = (tid % 16) * G::TP, qb = (tid / 16) * G::TP;   // tile corner (N >= 16)
   int ph = 0, np = 0;
   for (;;) {
     if (tid == 0) sNode[np] = atomicAdd(next, 1);
@@ -642,27 +668,36 @@ __global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, Le
       st = lv.st[node];
       const double* cn = cbuf + (size_t)node * M;
 #pragma unroll
-      for (int j = 0; j < APT; ++j) c0[j] = cn[tid + 256 * j];
+      for (int j = 0; j < APT; ++j) c0[j] = cn[G::atom(tid, j)];
     }
 #pragma unroll
     for (int j = 0; j < APT; ++j) c[j] = c0[j];
-    uint32_t selm = 0;   // bit j: atom tid + 256 j is selected
+    uint32_t selm = 0;   // bit j: the thread's atom j is selected
     int t = 0;
     while (st == ST_RUN) {
-      // (1) arg-max |c| (lowest index on ties); selected atoms hold exact zeros
+      // (1) arg-max |c| (lowest index on ties); selected atoms hold exact
+      // zeros.  Each wave's winner brings its <y, phi_i> (its c0) along.
       double bc;
       int bj;
       lane_best(c, bc, bj);
-      int bi = tid + 256 * bj;
+      int bi = G::atom(tid, bj);
       if (bi >= M) bi = M;   // threads without atoms (N <= 8) hold c = 0
       wave_best(bc, bi, bc, bi);
       if (lane == 0) {
         sBc[ph][wv] = bc;
         sBi[ph][wv] = bi;
       }
+      if (tid == G::owner(bi)) {   // in this wave whenever its winner is a real atom
+        const int js = G::slot(bi);
+        double v0 = c0[0];
+#pragma unroll
+        for (int j = 1; j < APT; ++j) v0 = (j == js) ? c0[j] : v0;
+        sB0[ph][wv] = v0;
+      }
       __syncthreads();
       bc = sBc[ph][0];
       bi = sBi[ph][0];
+      int ww = 0;
 #pragma unroll
       for (int q = 1; q < 4; ++q) {
         const double oc = sBc[ph][q];
@@ -670,76 +705,96 @@ __global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, Le
         if (fabs(oc) > fabs(bc) || (fabs(oc) == fabs(bc) && oi < bi)) {
           bc = oc;
           bi = oi;
+          ww = q;
         }
       }
+      const double yi = sB0[ph][ww];
       ph ^= 1;
       if (bc == 0.0) {
         st = ST_ZERO;
         break;
       }
-      const int fi = bi / K, pi = bi % N, qi = (bi % K) / N;
-      // (2) <y, phi_i> from its thread; g_r = <phi_{S_r}, phi_i>
-      if (tid == bi % 256) {
-        double v0 = c0[0];
-#pragma unroll
-        for (int j = 1; j < APT; ++j) v0 = (j == bi / 256) ? c0[j] : v0;
-        sScal[0] = v0;
-      }
-      if (tid < t) {
-        const int as = sS[tid];
-        const int fs = as / K, ps = as % N, qs = (as % K) / N;
-        double g = 0.0;
-        if constexpr (NFAM == 2)
-          if (fs != fi) g = fi == 0 ? sX[pi][ps] * sX[qi][qs] : sX[ps][pi] * sX[qs][qi];
-        sG[tid] = g;
-      }
-      __syncthreads();
-      // (3) w = L g, d, z_t, new ||r||^2 (one wave; t <= 64)
+      // (2)-(5) in wave 0 (t <= 64 lanes), synchronised within the wave:
+      // g_r = <phi_{S_r}, phi_i>; w = L g; d = sqrt(1 - w.w);
+      // z_t = (<y, phi_i> - w.z) / d; the new row t of L, (-w^T L, 1) / d;
+      // x_S updated in place (x_r += z_t L[t][r], x_t = z_t / d, since
+      // x = L^T z); the selected atoms listed per family for the refresh.
       if (wv == 0) {
-        double wr = 0.0;
-        if (lane < t) {
-          for (int cc = 0; cc <= lane; ++cc) wr = fma(sL[lane][cc], sG[cc], wr);
-          sW[lane] = wr;
+        const int fi = bi / K, pi = bi % N, qi = (bi % K) / N;
+        const bool act = lane < t;
+        int as = bi;
+        double g = 0.0;
+        if (act) {
+          as = sS[lane];
+          if constexpr (NFAM == 2) {
+            const int fs = as / K, ps = as % N, qs = (as % K) / N;
+            if (fs != fi) g = fi == 0 ? sX[pi][ps] * sX[qi][qs] : sX[ps][pi] * sX[qs][qi];
+          }
         }
+        sG[lane] = g;
+        wave_sync();
+        double wr = 0.0;
+        if (act) {
+#pragma unroll 4
+          for (int cc = 0; cc <= lane; ++cc) wr = fma(sL[lane][cc], sG[cc], wr);
+        }
+        sW[lane] = wr;
         const double s1 = wave_sum_f64(wr * wr);
-        const double s2 = wave_sum_f64(lane < t ? wr * sZ[lane] : 0.0);
+        const double s2 = wave_sum_f64(act ? wr * sZ[lane] : 0.0);
+        const double d2 = 1.0 - s1;
+        const bool dep = !(d2 > 1e-24);   // chosen atom (numerically) in the span of the selected ones
+        double enew = e;
+        if (!dep) {
+          const double d = sqrt(d2);
+          const double invd = 1.0 / d;
+          const double zt = (yi - s2) / d;
+          enew = fma(-zt, zt, e);
+          wave_sync();
+          double lr = invd, xn = zt * invd;
+          if (act) {
+            double acc = 0.0;
+#pragma unroll 4
+            for (int r = lane; r < t; ++r) acc = fma(sW[r], sL[r][lane], acc);
+            lr = -acc * invd;
+            xn = fma(zt, lr, sXc[lane]);
+          }
+          const bool in = lane <= t;
+          if (in) {
+            sL[t][lane] = lr;
+            sXc[lane] = xn;
+          }
+          if (lane == 0) {
+            sZ[t] = zt;
+            sS[t] = bi;
+          }
+          if constexpr (NFAM == 2) {
+            const int f = as / K;
+            const unsigned long long m1 = __ballot(in && f == 1), m0 = __ballot(in && f == 0);
+            const unsigned long long below = (1ull << lane) - 1ull;
+            if (in) {
+              const int rk = __popcll((f ? m1 : m0) & below);
+              sPQ[f][rk] = (as % N) | (((as % K) / N) << 8);
+              sXF[f][rk] = xn;
+            }
+            if (lane == 0) {
+              sNF[0] = __popcll(m0);
+              sNF[1] = __popcll(m1);
+            }
+          }
+        }
         if (lane == 0) {
-          const double d2 = 1.0 - s1;
-          const bool dep = !(d2 > 1e-24);
-          const double d = dep ? 1.0 : sqrt(d2);
-          const double zt = (sScal[0] - s2) / d;
-          sZ[t] = zt;
-          sS[t] = bi;
-          sScal[1] = 1.0 / d;
-          sScal[2] = fma(-zt, zt, e);
-          sScal[3] = dep ? 1.0 : 0.0;
+          sScal[0] = dep ? 1.0 : 0.0;
+          sScal[1] = enew;
         }
       }
       __syncthreads();
-      if (sScal[3] != 0.0) {   // chosen atom (numerically) in the span of the selected ones
+      if (sScal[0] != 0.0) {
         st = ST_ZERO;
         break;
       }
-      // (4) new row t of L
-      const double invd = sScal[1];
-      if (tid < t) {
-        double acc = 0.0;
-        for (int r = tid; r < t; ++r) acc = fma(sW[r], sL[r][tid], acc);
-        sL[t][tid] = -acc * invd;
-      } else if (tid == t) {
-        sL[t][t] = invd;
-      }
-      e = sScal[2];
+      e = sScal[1];
+      if (tid == G::owner(bi)) selm |= 1u << G::slot(bi);
       ++t;
-      if (tid == bi % 256) selm |= 1u << (bi / 256);
-      __syncthreads();
-      // (5) x_S = L^T z
-      if (tid < t) {
-        double acc = 0.0;
-        for (int r = tid; r < t; ++r) acc = fma(sL[r][tid], sZ[r], acc);
-        sXc[tid] = acc;
-      }
-      __syncthreads();
       if (e < eps2)
         st = ST_ACC;
       else if (t >= kmax)
@@ -748,32 +803,54 @@ __global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, Le
       // (6) c = c0 - G_{:,S} x_S
 #pragma unroll
       for (int j = 0; j < APT; ++j) c[j] = c0[j];
-      if constexpr (NFAM == 2) {
+      if constexpr (NFAM == 2 && SMALL) {
         for (int s = 0; s < t; ++s) {
           const int as = sS[s];
           const double xs = sXc[s];
           const int fs = as / K, ps = as % N, qs = (as % K) / N;
-          if constexpr (SMALL) {
-            const int fa = tid / K, qa = (tid % K) / N;
-            if (tid < M && fa != fs) {
-              const double g = fs == 0 ? sX[ps][pa] * sX[qs][qa] : sX[pa][ps] * sX[qa][qs];
-              c[0] = fma(-xs, g, c[0]);
-            }
-          } else if (fs == 0) {   // atoms of family 1: <T_1[p], T_0[ps]> = X[ps][p]
-            const double al = xs * sX[ps][pa];
-#pragma unroll
-            for (int j = AF; j < APT; ++j) {
-              const int qa = ((tid + 256 * j) % K) / N;
-              c[j] = fma(-al, sX[qs][qa], c[j]);
-            }
-          } else {                // atoms of family 0: X[p][ps]
-            const double al = xs * sX[pa][ps];
-#pragma unroll
-            for (int j = 0; j < AF; ++j) {
-              const int qa = ((tid + 256 * j) % K) / N;
-              c[j] = fma(-al, sX[qa][qs], c[j]);
-            }
+          const int fa = tid / K, qa = (tid % K) / N;
+          if (tid < M && fa != fs) {
+            const double g = fs == 0 ? sX[ps][pa] * sX[qs][qa] : sX[pa][ps] * sX[qa][qs];
+            c[0] = fma(-xs, g, c[0]);
           }
+        }
+      } else if constexpr (NFAM == 2) {
+        // Each family's atoms take the other family's selections, in
+        // selection order: no branch per selected atom, and the loads of
+        // several selections are in flight together.
+        constexpr int TP = G::TP;
+        const int n0 = sNF[0], n1 = sNF[1];
+#pragma unroll 4
+        for (int k = 0; k < n0; ++k) {   // family-1 atoms: <T_1[p]T_1[q], T_0[ps]T_0[qs]> = X[ps][p] X[qs][q]
+          const int pq = sPQ[0][k];
+          const double xs = sXF[0][k];
+          const int ps = pq & 255, qs = pq >> 8;
+          double a[TP], b[TP];
+#pragma unroll
+          for (int d = 0; d < TP; ++d) {
+            a[d] = xs * sX[ps][pb + d];
+            b[d] = sX[qs][qb + d];
+          }
+#pragma unroll
+          for (int dq = 0; dq < TP; ++dq)
+#pragma unroll
+            for (int dp = 0; dp < TP; ++dp) c[AF + dq * TP + dp] = fma(-a[dp], b[dq], c[AF + dq * TP + dp]);
+        }
+#pragma unroll 4
+        for (int k = 0; k < n1; ++k) {   // family-0 atoms: X[p][ps] X[q][qs]
+          const int pq = sPQ[1][k];
+          const double xs = sXF[1][k];
+          const int ps = pq & 255, qs = pq >> 8;
+          double a[TP], b[TP];
+#pragma unroll
+          for (int d = 0; d < TP; ++d) {
+            a[d] = xs * sX[pb + d][ps];
+            b[d] = sX[qb + d][qs];
+          }
+#pragma unroll
+          for (int dq = 0; dq < TP; ++dq)
+#pragma unroll
+            for (int dp = 0; dp < TP; ++dp) c[dq * TP + dp] = fma(-a[dp], b[dq], c[dq * TP + dp]);
         }
       }
 #pragma unroll
