@@ -489,7 +489,7 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
         if (se) AQMP_HIP(hipEventRecord(se->b, s));
         if (c->opt.solver == AQMP_SOLVER_OMP)
           AQMP_LAUNCH(launch_omp_pursuit(n, c->djobs, a.lv, count, &cnt->next[l], l, d->nfam, D.d_tab, D.d_xg,
-                                         wk.cbuf, s));
+                                         wk.cbuf, pp.kmax[l], s));
         else
           AQMP_LAUNCH(launch_gram_pursuit(n, c->djobs, a.lv, count, &cnt->next[l], l, d->nfam, D.d_tab, D.d_xg,
                                           wk.cbuf, s));

@@ -141,8 +141,11 @@ hipError_t launch_gram_init(int n, const JobDev* jobs, LevelDev lv, const int32_
                             const double* tab, double* cbuf, hipStream_t s);
 hipError_t launch_gram_pursuit(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int32_t lg,
                                int32_t nfam, const double* tab, const double* xg, const double* cbuf, hipStream_t s);
+// kmax: the largest k among the level's jobs (at most kOmpMaxAtoms); it
+// sizes the factor in LDS.
 hipError_t launch_omp_pursuit(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int32_t lg,
-                              int32_t nfam, const double* tab, const double* xg, const double* cbuf, hipStream_t s);
+                              int32_t nfam, const double* tab, const double* xg, const double* cbuf, int32_t kmax,
+                              hipStream_t s);
 // SSIM partials: one FP64 per workgroup (window7) or five plane sums per
 // workgroup (global); *n_partial receives the workgroup count.
 hipError_t launch_ssim(const aqmp_image& x, const aqmp_image& y, int mode, double c1, double c2, double* partial,

@@ -565,6 +565,7 @@ struct OmpGeo {
   // (the atom index grows with j, so the per-thread arg-max keeps the lowest
   // index on ties).  The cross-family correlation refresh of one selected
   // atom then reads 2 TP table entries for TP^2 multiply-adds.
+  static constexpr int NT = SMALL ? 128 : 256;         // threads per node
   static constexpr int TP = SMALL ? 1 : N / 16;
   static constexpr int AF = TP * TP;
   static constexpr int APT = SMALL ? 1 : NFAM * AF;
@@ -589,7 +590,7 @@ template <int N, int NFAM>
 __global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, LevelDev lv,
                                              const int32_t* __restrict__ count_ptr, int32_t* next, int32_t lg,
                                              const double* __restrict__ tab, const double* __restrict__ xg,
-                                             const double* __restrict__ cbuf) {
+                                             const double* __restrict__ cbuf, int kcap) {
   using G = OmpGeo<N, NFAM>;
   constexpr int K = G::K, M = G::M, APT = G::APT, AF = G::AF;
   constexpr bool SMALL = G::SMALL;
@@ -598,23 +599,26 @@ __global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, Le
   __shared__ double sX[NX][NX + 1];                    // X[p][p'] = <T_0[p], T_1[p']>
   __shared__ double sT[SMALL ? NFAM : 1][SMALL ? K : 1];
   __shared__ double sY[SMALL ? K : 1];
-  __shared__ double sL[KC][KC + 1];                    // L = chol(G_SS)^-1, lower triangular
+  // L = chol(G_SS)^-1, lower triangular, kcap x (kcap + 1) doubles sized at
+  // launch by the largest k of the level (smaller k: more workgroups per CU)
+  extern __shared__ double sLdyn[];
+  const int ldl = kcap + 1;
   __shared__ int sS[KC];                               // selected atoms in order
-  __shared__ double sZ[KC], sXc[KC], sG[KC], sW[KC];   // z, x_S, g, w
+  __shared__ double sXc[KC], sG[KC], sW[KC];           // x_S, g, w
   // the selected atoms split by family, in selection order: p | q << 8 and x
   __shared__ int sPQ[NFAM][KC];
   __shared__ double sXF[NFAM][KC];
   __shared__ int sNF[NFAM];
-  __shared__ double sBc[2][4], sB0[2][4];             // per-wave best |c| and its c0
+  __shared__ double sBc[2][4];                         // per-wave best c
   __shared__ int sBi[2][4];
   __shared__ double sScal[2];                          // dependence flag, new ||r||^2
   __shared__ double sRed[2];
   __shared__ int sNode[2];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if constexpr (NFAM == 2)
-    for (int i = tid; i < K; i += 256) sX[i / N][i % N] = xg[i];
+    for (int i = tid; i < K; i += G::NT) sX[i / N][i % N] = xg[i];
   if constexpr (SMALL)
-    for (int i = tid; i < NFAM * K; i += 256) (&sT[0][0])[i] = tab[i];
+    for (int i = tid; i < NFAM * K; i += G::NT) (&sT[0][0])[i] = tab[i];
   __syncthreads();
   const int count = *count_ptr;
   const int pa = tid % N;                              // p of the thread's atom (N <= 8)
@@ -631,7 +635,10 @@ __global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, Le
     const int kmax = jb.k[lg];
     double e;
     uint8_t st;
-    double c0[APT], c[APT];
+    // c: the current correlations <r, phi_a> of the thread's atoms.  Small
+    // blocks recompute them from c0 = D^T y each step; larger ones update
+    // them in place (see the refresh).
+    double c0[1] = {0.0}, c[APT];
     if constexpr (SMALL) {
       // gather (pixel k in thread k), ||y||^2, sum y, first stop test, c0
       double v = 0.0;
@@ -663,20 +670,19 @@ __global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, Le
         if (tid % K == 0) acc = ssum / N;
       }
       c0[0] = acc;
+      c[0] = acc;
     } else {
       e = lv.e[node];
       st = lv.st[node];
       const double* cn = cbuf + (size_t)node * M;
 #pragma unroll
-      for (int j = 0; j < APT; ++j) c0[j] = cn[G::atom(tid, j)];
+      for (int j = 0; j < APT; ++j) c[j] = cn[G::atom(tid, j)];
     }
-#pragma unroll
-    for (int j = 0; j < APT; ++j) c[j] = c0[j];
     uint32_t selm = 0;   // bit j: the thread's atom j is selected
     int t = 0;
     while (st == ST_RUN) {
       // (1) arg-max |c| (lowest index on ties); selected atoms hold exact
-      // zeros.  Each wave's winner brings its <y, phi_i> (its c0) along.
+      // zeros.
       double bc;
       int bj;
       lane_best(c, bc, bj);
@@ -687,28 +693,18 @@ __global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, Le
         sBc[ph][wv] = bc;
         sBi[ph][wv] = bi;
       }
-      if (tid == G::owner(bi)) {   // in this wave whenever its winner is a real atom
-        const int js = G::slot(bi);
-        double v0 = c0[0];
-#pragma unroll
-        for (int j = 1; j < APT; ++j) v0 = (j == js) ? c0[j] : v0;
-        sB0[ph][wv] = v0;
-      }
       __syncthreads();
       bc = sBc[ph][0];
       bi = sBi[ph][0];
-      int ww = 0;
 #pragma unroll
-      for (int q = 1; q < 4; ++q) {
+      for (int q = 1; q < G::NT / 64; ++q) {
         const double oc = sBc[ph][q];
         const int oi = sBi[ph][q];
         if (fabs(oc) > fabs(bc) || (fabs(oc) == fabs(bc) && oi < bi)) {
           bc = oc;
           bi = oi;
-          ww = q;
         }
       }
-      const double yi = sB0[ph][ww];
       ph ^= 1;
       if (bc == 0.0) {
         st = ST_ZERO;
@@ -716,9 +712,12 @@ __global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, Le
       }
       // (2)-(5) in wave 0 (t <= 64 lanes), synchronised within the wave:
       // g_r = <phi_{S_r}, phi_i>; w = L g; d = sqrt(1 - w.w);
-      // z_t = (<y, phi_i> - w.z) / d; the new row t of L, (-w^T L, 1) / d;
-      // x_S updated in place (x_r += z_t L[t][r], x_t = z_t / d, since
-      // x = L^T z); the selected atoms listed per family for the refresh.
+      // z_t = <y, q_t> = <r, phi_i> / d (q_t, the new orthonormal direction,
+      // is phi_i minus its projection on the selected atoms, over d, and r
+      // is orthogonal to those); the new row t of L, (-w^T L, 1) / d;
+      // x_S = L^T z updated in place, dx = z_t L[t][:] (x_r += dx_r,
+      // x_t = dx_t); the selected atoms listed per family with dx (with x
+      // for small blocks) for the refresh.
       if (wv == 0) {
         const int fi = bi / K, pi = bi % N, qi = (bi % K) / N;
         const bool act = lane < t;
@@ -736,35 +735,34 @@ __global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, Le
         double wr = 0.0;
         if (act) {
 #pragma unroll 4
-          for (int cc = 0; cc <= lane; ++cc) wr = fma(sL[lane][cc], sG[cc], wr);
+          for (int cc = 0; cc <= lane; ++cc) wr = fma(sLdyn[lane * ldl + cc], sG[cc], wr);
         }
         sW[lane] = wr;
         const double s1 = wave_sum_f64(wr * wr);
-        const double s2 = wave_sum_f64(act ? wr * sZ[lane] : 0.0);
         const double d2 = 1.0 - s1;
         const bool dep = !(d2 > 1e-24);   // chosen atom (numerically) in the span of the selected ones
         double enew = e;
         if (!dep) {
           const double d = sqrt(d2);
           const double invd = 1.0 / d;
-          const double zt = (yi - s2) / d;
+          const double zt = bc / d;
           enew = fma(-zt, zt, e);
           wave_sync();
-          double lr = invd, xn = zt * invd;
+          double lr = invd, dx = zt * invd, xn = dx;
           if (act) {
             double acc = 0.0;
 #pragma unroll 4
-            for (int r = lane; r < t; ++r) acc = fma(sW[r], sL[r][lane], acc);
+            for (int r = lane; r < t; ++r) acc = fma(sW[r], sLdyn[r * ldl + lane], acc);
             lr = -acc * invd;
-            xn = fma(zt, lr, sXc[lane]);
+            dx = zt * lr;
+            xn = sXc[lane] + dx;
           }
           const bool in = lane <= t;
           if (in) {
-            sL[t][lane] = lr;
+            sLdyn[t * ldl + lane] = lr;
             sXc[lane] = xn;
           }
           if (lane == 0) {
-            sZ[t] = zt;
             sS[t] = bi;
           }
           if constexpr (NFAM == 2) {
@@ -774,7 +772,7 @@ __global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, Le
             if (in) {
               const int rk = __popcll((f ? m1 : m0) & below);
               sPQ[f][rk] = (as % N) | (((as % K) / N) << 8);
-              sXF[f][rk] = xn;
+              sXF[f][rk] = SMALL ? xn : dx;
             }
             if (lane == 0) {
               sNF[0] = __popcll(m0);
@@ -800,9 +798,9 @@ __global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, Le
       else if (t >= kmax)
         st = ST_SPARSE;
       if (st != ST_RUN) break;
-      // (6) c = c0 - G_{:,S} x_S
-#pragma unroll
-      for (int j = 0; j < APT; ++j) c[j] = c0[j];
+      // (6) refresh: small blocks c = c0 - G_{:,S} x_S, larger ones
+      // c -= G_{:,S} dx (c = c0 - G x at every step either way)
+      if constexpr (SMALL) c[0] = c0[0];
       if constexpr (NFAM == 2 && SMALL) {
         for (int s = 0; s < t; ++s) {
           const int as = sS[s];
@@ -927,15 +925,36 @@ hipError_t launch_gram_pursuit(int n, const JobDev* jobs, LevelDev lv, const int
 }
 
 hipError_t launch_omp_pursuit(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int32_t lg,
-                              int32_t nfam, const double* tab, const double* xg, const double* cbuf, hipStream_t s) {
+                              int32_t nfam, const double* tab, const double* xg, const double* cbuf, int32_t kmax,
+                              hipStream_t s) {
   if (nfam == 2 && !xg) return hipErrorInvalidValue;
   if (nfam != 1 && nfam != 2) return hipErrorInvalidValue;
-#define AQMP_OMP(NN)                                                                                           \
-  case NN:                                                                                                     \
-    if (nfam == 2)                                                                                             \
-      hipLaunchKernelGGL((k_omp<NN, 2>), dim3(1024), dim3(256), 0, s, jobs, lv, count, next, lg, tab, xg, cbuf); \
-    else                                                                                                       \
-      hipLaunchKernelGGL((k_omp<NN, 1>), dim3(1024), dim3(256), 0, s, jobs, lv, count, next, lg, tab, xg, cbuf); \
+  if (kmax > kOmpMaxAtoms) return hipErrorInvalidValue;
+  const int kcap = kmax < 1 ? 1 : kmax;
+  int dev = 0, n_cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const size_t smem = sizeof(double) * (size_t)kcap * (kcap + 1);
+  // Nodes come from a counter, so the grid is as many workgroups as fit on
+  // the device at once (registers and LDS decide; more would only start
+  // after the work is gone).
+#define AQMP_OMP_F(NN, FF)                                                                                     \
+  {                                                                                                            \
+    int per_cu = 0;                                                                                            \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_omp<NN, FF>, OmpGeo<NN, FF>::NT, smem) !=     \
+            hipSuccess ||                                                                                      \
+        per_cu < 1)                                                                                            \
+      per_cu = 1;                                                                                              \
+    hipLaunchKernelGGL((k_omp<NN, FF>), dim3(n_cus * per_cu), dim3(OmpGeo<NN, FF>::NT), smem, s, jobs, lv,  \
+                       count, next, lg, tab, xg, cbuf, kcap);                                                  \
+  }
+#define AQMP_OMP(NN)             \
+  case NN:                       \
+    if (nfam == 2)               \
+      AQMP_OMP_F(NN, 2)          \
+    else                         \
+      AQMP_OMP_F(NN, 1)          \
     break;
   switch (n) {
     AQMP_OMP(4)
@@ -947,6 +966,7 @@ hipError_t launch_omp_pursuit(int n, const JobDev* jobs, LevelDev lv, const int3
       return hipErrorInvalidValue;
   }
 #undef AQMP_OMP
+#undef AQMP_OMP_F
   return hipGetLastError();
 }
 
