@@ -380,8 +380,9 @@ int build_plan(aqmp_code* c) {
       ALLOC(wk.act[0], max_cap[wi] * 4);
       ALLOC(wk.act[1], max_cap[wi] * 4);
     }
-    // Tile words: one per scan tile of kScanTile items, or one per select
-    // chunk of at least 4 positions, whichever is more.
+    // Tile words of the look-back scans: one per scan tile of kScanTile
+    // items and at least one per workgroup of a scan launch (both far below
+    // this bound).
     wk.ss.ntiles_max = (int32_t)(max_cap[wi] / 4 + 2);
     ALLOC(wk.ss.tiles, sizeof(unsigned long long) * wk.ss.ntiles_max);
     ALLOC(wk.ss.ticket, sizeof(int32_t) * 2);
