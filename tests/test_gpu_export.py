@@ -5,7 +5,7 @@ the canonical order: job, then top-level block in raster order over the
 padded plane, then depth-first with children TL, TR, BL, BR (Alg. 2), i.e.
 Morton order of the node's corner inside its top-level block with the larger
 node first.  Checked here against that order computed independently on the
-host, for both schedules and mixed jobs; the leaf export must be the
+host, for all three schedules and mixed jobs; the leaf export must be the
 visited-node export restricted to leaves, atom for atom; and the tree must
 match the oracle's (Alg. 2) node for node, in the oracle's own depth-first
 order.
@@ -76,7 +76,7 @@ def _images():
     return out
 
 
-@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("schedule", [0, 1, 2])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_export_canonical_order_and_consistency(A, dic, schedule, prec):
     chans = _images()
@@ -151,4 +151,26 @@ def test_export_empty_and_repeat(A, dic):
     e = code.export()
     assert len(e.leaves) == 4 and len(e.atom_idx) == 0
     assert (e.leaves["n_atoms"] == 0).all() and (e.leaves["n"] == 32).all()
+    code.free()
+
+
+def test_export_capacity_error_writes_nothing(A, dic):
+    """Buffers one record or one atom too small: AQMP_E_CAPACITY, nothing
+    written, and the same call with the right sizes still succeeds."""
+    import ctypes as C
+    img = _dev(piecewise_image(64, 128, seed=6))
+    code = A.Code(dic, [img], [dict(tol=0.02, max_atoms=8, n_min=8, n_max=32)], [(0, 0)], precision=1, schedule=1)
+    nl, na = code.sizes()
+    assert nl > 0 and na > 0
+    for cl, ca in ((nl - 1, na), (nl, na - 1)):
+        leaves = np.zeros(nl, dtype=A.LEAF_DTYPE)
+        leaves["job"] = -7
+        idx = np.full(na, -7, dtype=np.int32)
+        coef = np.full(na, -7.0)
+        rc = A.lib.aqmp_code_export(code.h, leaves.ctypes.data_as(C.c_void_p), idx.ctypes.data_as(C.c_void_p),
+                                    coef.ctypes.data_as(C.c_void_p), C.c_int64(cl), C.c_int64(ca))
+        assert rc == A.E_CAPACITY
+        assert (leaves["job"] == -7).all() and (idx == -7).all() and (coef == -7.0).all()
+    e = code.export()
+    assert len(e.leaves) == nl and len(e.atom_idx) == na
     code.free()
