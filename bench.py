@@ -316,7 +316,10 @@ def main():
     ap.add_argument("--hpo-rounds", type=int, default=0,
                     help="also time this many rounds of the TPE search (8 trials per round) on the workload's images")
     ap.add_argument("--corr-variant", type=int, default=0, help="BF16 correlation kernel variant (0 = default)")
-    ap.add_argument("--schedule", default="batched", choices=["batched", "concurrent"])
+    ap.add_argument("--schedule", default=None, choices=["batched", "concurrent"],
+                    help="force a schedule (default: the autotuner's choice)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuner: library default kernels, batched schedule")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -359,11 +362,33 @@ def main():
     nmax = max(p["n_max"] for p in w["params"])
     dic = A.Dictionary(nmin, nmax)
 
+    # Kernels and schedule of the headline: the autotuner's choice on this
+    # workload (timed candidates; a choice replaces the library default only
+    # when it is clearly faster), unless a variant or schedule is forced.
+    tuned = None
+    levels_v, stepwise = {}, False
+    sched = A.SCHED_BATCHED
+    if not args.no_autotune and args.corr_variant == 0:
+        from paper_2605_09190_amd import autotune
+        log("autotune")
+        t0 = time.perf_counter()
+        tuned = autotune.tune(A, dic, imgs, w["params"], w["jobs"], schedules=args.schedule is None)
+        tuned["seconds"] = round(time.perf_counter() - t0, 2)
+        levels_v, stepwise, sched = (tuned["options"]["corr_variant_levels"], tuned["options"]["stepwise"],
+                                     tuned["options"]["schedule"])
+        log(f"autotune: {tuned['options']} in {tuned['seconds']} s")
+    if args.schedule is not None:
+        sched = A.SCHED_BATCHED if args.schedule == "batched" else A.SCHED_CONCURRENT
+    head_kw = dict(corr_variant=args.corr_variant, corr_variant_levels=levels_v, stepwise=stepwise)
+    # the labelled solvers run batched unless a schedule is forced
+    var_sched = A.SCHED_CONCURRENT if args.schedule == "concurrent" else A.SCHED_BATCHED
+
+    def head_kernel(n):
+        return A.corr_kernel(n, A.PREC_BF16, levels_v.get(n, args.corr_variant))
+
     # Headline: batched BF16, all jobs in one captured graph, replayed.
     log("batched bf16: build + capture")
-    sched = A.SCHED_BATCHED if args.schedule == "batched" else A.SCHED_CONCURRENT
-    code = A.Code(dic, imgs, w["params"], w["jobs"], precision=A.PREC_BF16, schedule=sched,
-                  corr_variant=args.corr_variant)
+    code = A.Code(dic, imgs, w["params"], w["jobs"], precision=A.PREC_BF16, schedule=sched, **head_kw)
     torch.cuda.synchronize()
     sec = time_steps(code, imgs, args.steps, args.warmup)
     stats = code.stats()
@@ -379,10 +404,9 @@ def main():
     # this encode is issued on the stream), K steps, then the roofline of the
     # dominant kernel from the summed event times.
     code_t = A.Code(dic, imgs, w["params"], w["jobs"], precision=A.PREC_BF16, schedule=sched,
-                    timing=True, corr_variant=args.corr_variant)
+                    timing=True, **head_kw)
     sec_t = time_steps(code_t, imgs, args.steps, args.warmup)
-    roof = roofline(code_t.stats(), code_t.timing(), A.PREC_BF16,
-                    lambda n: A.corr_kernel(n, A.PREC_BF16, args.corr_variant), workload=args.workload)
+    roof = roofline(code_t.stats(), code_t.timing(), A.PREC_BF16, head_kernel, workload=args.workload)
     code_t.free()
     log(f"bf16 batched (stream, timed): {sec_t * 1e3:.3f} ms/step, corr {roof['achieved']} TFLOP/s")
 
@@ -410,12 +434,12 @@ def main():
         # updates per step), not the per-step dense correlation the method
         # states.
         log("gram fp64: build + capture")
-        codeg = A.Code(dic, imgs, w["params"], w["jobs"], schedule=sched, solver=A.SOLVER_GRAM)
+        codeg = A.Code(dic, imgs, w["params"], w["jobs"], schedule=var_sched, solver=A.SOLVER_GRAM)
         torch.cuda.synchronize()
         secg = time_steps(codeg, imgs, args.steps, args.warmup)
         stg = codeg.stats()
         psnr_g = psnr_jobs(codeg, imgs, w["jobs"])
-        roof_g = solver_roofline(A, dic, imgs, w, A.SOLVER_GRAM, sched, args.steps, args.warmup)
+        roof_g = solver_roofline(A, dic, imgs, w, A.SOLVER_GRAM, var_sched, args.steps, args.warmup)
         gram = dict(value=round(npx / secg / 1e6, 3), ms_per_step=round(secg * 1e3, 4), steps=args.steps,
                     roofline=roof_g,
                     mp_iters_per_s=round(stg["iters_executed"] / secg, 1), psnr_db=[round(p, 4) for p in psnr_g],
@@ -432,12 +456,12 @@ def main():
         # implementation; a different method from the MP headline, so its
         # trees and PSNR differ.
         log("omp fp64: build + capture")
-        codeo = A.Code(dic, imgs, w["params"], w["jobs"], schedule=sched, solver=A.SOLVER_OMP)
+        codeo = A.Code(dic, imgs, w["params"], w["jobs"], schedule=var_sched, solver=A.SOLVER_OMP)
         torch.cuda.synchronize()
         seco = time_steps(codeo, imgs, args.steps, args.warmup)
         sto = codeo.stats()
         psnr_o = psnr_jobs(codeo, imgs, w["jobs"])
-        roof_o = solver_roofline(A, dic, imgs, w, A.SOLVER_OMP, sched, args.steps, args.warmup)
+        roof_o = solver_roofline(A, dic, imgs, w, A.SOLVER_OMP, var_sched, args.steps, args.warmup)
         omp = dict(value=round(npx / seco / 1e6, 3), ms_per_step=round(seco * 1e3, 4), steps=args.steps,
                    roofline=roof_o, cpu_baseline=cpu_omp,
                    mp_iters_per_s=round(sto["iters_executed"] / seco, 1), psnr_db=[round(p, 4) for p in psnr_o],
@@ -495,6 +519,10 @@ def main():
         "gram_fp64": gram,
         "omp_fp64": omp,
         "hpo": hpo_res,
+        "autotune": (dict(options=dict(corr_variant_levels={str(k): v for k, v in levels_v.items()},
+                                       stepwise=stepwise,
+                                       schedule="batched" if sched == A.SCHED_BATCHED else "concurrent"),
+                          measured=tuned["measured"], seconds=tuned["seconds"]) if tuned else None),
         "roofline": roof,
     }
     if fp32:

@@ -165,7 +165,12 @@ typedef struct {
                           coefficients in selection order).  k may not
                           exceed AQMP_OMP_MAX_ATOMS; precision and
                           corr_variant do not apply. */
-  int32_t reserved[3];
+  uint32_t corr_variant_levels;  /* tuning, per block size: bits 4 lg .. 4 lg + 3
+                                    hold the BF16 correlation variant (0..6) for
+                                    N = 2^lg, 2 <= lg <= 6; a zero nibble takes
+                                    corr_variant.  An autotuner fills it from
+                                    timed encodes of the caller's workload. */
+  int32_t reserved[2];
 } aqmp_options;
 
 /* A leaf of the quadtree (or, from aqmp_code_export_nodes, any visited

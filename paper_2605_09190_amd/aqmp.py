@@ -61,7 +61,7 @@ class Job(C.Structure):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("schedule", C.c_int32), ("flags", C.c_int32),
                 ("corr_variant", C.c_int32), ("solver", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("corr_variant_levels", C.c_uint32), ("reserved", C.c_int32 * 2)]
 
 
 class Leaf(C.Structure):
@@ -138,6 +138,18 @@ def _stream_handle(stream) -> int | None:
     if isinstance(stream, int):
         return stream
     return stream.cuda_stream
+
+
+def pack_variant_levels(per_n) -> int:
+    """{N: variant} -> the aqmp_options.corr_variant_levels word (one nibble
+    per block size, at bits 4 log2(N))."""
+    word = 0
+    for n, v in dict(per_n).items():
+        lg = int(n).bit_length() - 1
+        if 1 << lg != int(n) or not 2 <= lg <= 6 or not 0 <= int(v) <= 6:
+            raise ValueError(f"bad per-level variant {n}: {v}")
+        word |= int(v) << (4 * lg)
+    return word
 
 
 def corr_kernel(n: int, precision: int, corr_variant: int = 0) -> str:
@@ -232,7 +244,7 @@ class Code:
 
     def __init__(self, dic: Dictionary, images, params, jobs, precision: int = PREC_FP32,
                  schedule: int = SCHED_PLAIN, stream=None, timing: bool = False, corr_variant: int = 0,
-                 stepwise: bool = False, solver: int = 0):
+                 stepwise: bool = False, solver: int = 0, corr_variant_levels=None):
         self.dic = dic
         self._keep = list(images)
         imgs = (Image * len(images))(*[make_image(t) for t in images])
@@ -242,6 +254,7 @@ class Code:
         opt.precision, opt.schedule = int(precision), int(schedule)
         opt.flags = (OPT_TIMING if timing else 0) | (OPT_STEPWISE if stepwise else 0)
         opt.corr_variant = int(corr_variant)
+        opt.corr_variant_levels = pack_variant_levels(corr_variant_levels or {})
         opt.solver = int(solver)
         h = C.c_void_p()
         _check(lib.aqmp_encode(dic.h, imgs, len(images), prms, len(params), jbs, len(jobs), C.byref(opt),

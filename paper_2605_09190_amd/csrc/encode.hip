@@ -151,6 +151,11 @@ int validate(const aqmp_dict* d, const aqmp_image* imgs, int n_imgs, const aqmp_
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: unknown option flags");
     if (opt->corr_variant < 0 || opt->corr_variant > 6)
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad corr_variant");
+    if (opt->corr_variant_levels & ~0x7FFFF00u)
+      AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: corr_variant_levels has bits outside the block sizes 4..64");
+    for (int lg = 2; lg <= 6; ++lg)
+      if (((opt->corr_variant_levels >> (4 * lg)) & 0xFu) > 6)
+        AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad corr_variant_levels entry for N = " + std::to_string(1 << lg));
     if (opt->solver != AQMP_SOLVER_DENSE && opt->solver != AQMP_SOLVER_GRAM && opt->solver != AQMP_SOLVER_OMP)
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad solver");
   }
@@ -521,7 +526,8 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
       a.clear_count = &cnt->act[(t + 2) % 3];
       const aqmp_code::StepEv* se = timing ? &c->sev[c->sev_pos++] : nullptr;
       if (se) AQMP_HIP(hipEventRecord(se->a, s));
-      const int variant = c->wide_residual ? 3 : c->opt.corr_variant;
+      const int lv_var = (int)((c->opt.corr_variant_levels >> (4 * l)) & 0xFu);
+      const int variant = c->wide_residual ? 3 : (lv_var ? lv_var : c->opt.corr_variant);
       AQMP_LAUNCH(launch_corr(n, c->opt.precision, variant, atoms, a, D.m_pad, s));
       if (se) AQMP_HIP(hipEventRecord(se->b, s));
       AQMP_LAUNCH(launch_select(n, a, pp.cap[l], s));

@@ -50,7 +50,7 @@ int main(void) {
   printf("aqmp_image %zu\n", sizeof(aqmp_image)); P(aqmp_image, dtype); P(aqmp_image, row_stride);
   printf("aqmp_params %zu\n", sizeof(aqmp_params)); P(aqmp_params, tol_mode); P(aqmp_params, k_per_level);
   printf("aqmp_job %zu\n", sizeof(aqmp_job));
-  printf("aqmp_options %zu\n", sizeof(aqmp_options)); P(aqmp_options, solver);
+  printf("aqmp_options %zu\n", sizeof(aqmp_options)); P(aqmp_options, solver); P(aqmp_options, corr_variant_levels);
   printf("aqmp_leaf %zu\n", sizeof(aqmp_leaf)); P(aqmp_leaf, atom_off); P(aqmp_leaf, resid_sq);
   printf("aqmp_stats %zu\n", sizeof(aqmp_stats)); P(aqmp_stats, iters_executed);
   return 0;
@@ -72,6 +72,7 @@ def test_struct_layouts_match_ctypes(tmp_path):
     assert c["aqmp_job"] == C.sizeof(A.Job)
     assert c["aqmp_options"] == C.sizeof(A.Options)
     assert c["aqmp_options.solver"] == A.Options.solver.offset
+    assert c["aqmp_options.corr_variant_levels"] == A.Options.corr_variant_levels.offset
     assert c["aqmp_leaf"] == C.sizeof(A.Leaf) == A.LEAF_DTYPE.itemsize
     assert c["aqmp_leaf.atom_off"] == A.Leaf.atom_off.offset
     assert c["aqmp_stats"] == C.sizeof(A.Stats)

@@ -1,0 +1,95 @@
+"""The autotuner and the per-level kernel choice, on the GPU.
+
+Every BF16 correlation kernel family computes the same keys, so forcing a
+family per block size must leave the code bit-identical; the tuner's choice
+on a workload must run and match the oracle like the default does.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import aqmp_oracle as O
+from tests import parity_util as PU
+from workloads import workload, piecewise_image
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_09190_amd import aqmp
+    return aqmp
+
+
+@pytest.fixture(scope="module")
+def dic(A):
+    d = A.Dictionary(8, 64)
+    yield d
+    d.free()
+
+
+def _dev(img):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(img)).to(torch.float32).cuda()
+
+
+def _bytes(code):
+    e = code.export_nodes()
+    return e.leaves.tobytes(), e.atom_idx.tobytes(), e.coef.tobytes()
+
+
+@pytest.mark.parametrize("levels", [{64: 5, 32: 1}, {64: 2, 32: 4}, {64: 3, 32: 5, 16: 1}])
+def test_per_level_variants_are_bit_identical(A, dic, levels):
+    w = workload("c1")
+    imgs = [_dev(w["channels"][0])]
+    ref = A.Code(dic, imgs, w["params"], [(0, 0)], precision=1, schedule=1, stepwise=True)
+    want = _bytes(ref)
+    ref.free()
+    code = A.Code(dic, imgs, w["params"], [(0, 0)], precision=1, schedule=1, stepwise=True,
+                  corr_variant_levels=levels)
+    assert _bytes(code) == want, levels
+    code.free()
+
+
+def test_bad_level_word_is_rejected(A, dic, monkeypatch):
+    imgs = [_dev(piecewise_image(64, 64, seed=2))]
+    p = dict(tol=0.02, max_atoms=8, n_min=8, n_max=32)
+    for word in (7 << 24, 1 << 4, 1 << 28):
+        monkeypatch.setattr(A, "pack_variant_levels", lambda _d, word=word: word)
+        with pytest.raises(Exception, match="corr_variant_levels"):
+            A.Code(dic, imgs, [p], [(0, 0)], precision=1, schedule=1, corr_variant_levels={64: 1})
+
+
+def test_tuned_options_run_and_match_the_oracle(A, dic):
+    from paper_2605_09190_amd import autotune
+    w = workload("c1")
+    img = w["channels"][0]
+    p = w["params"][0]
+    imgs = [_dev(img)]
+    tuned = autotune.tune(A, dic, imgs, w["params"], [(0, 0)], reps=2, steps=3)
+    _say("tuned", tuned)
+    opt = tuned["options"]
+    assert opt["schedule"] == A.SCHED_BATCHED            # one job: nothing to split
+    for n, v in opt["corr_variant_levels"].items():
+        assert n in (16, 32, 64) and v in autotune.CANDIDATES[n]
+    assert set(tuned["measured"]["corr_ms"]) <= {"32", "64"}
+    code = A.Code(dic, imgs, w["params"], [(0, 0)], precision=1, **opt)
+    exp = code.export_nodes()
+    code.free()
+    rng = np.random.default_rng(12)
+    tops = O.top_blocks(512, 512, 64)
+    sample = [tops[i] for i in sorted(rng.choice(len(tops), size=4, replace=False))]
+    onodes = O.encode_channel(img, O.Params.from_dict(p), blocks=sample)
+    rep = PU.Report()
+    PU.compare_job(img, onodes, PU.gpu_nodes_by_key(exp, 0), 2e-3, p["n_max"], rep=rep)
+    _say(rep.summary())
+    assert rep.ok(), rep.summary()
