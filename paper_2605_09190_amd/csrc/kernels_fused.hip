@@ -148,6 +148,7 @@ __global__ __launch_bounds__(256) void k_mp_fused(const JobDev* __restrict__ job
 // ---------------------------------------------------------------------------
 constexpr int kP16N = 16, kP16K = 256, kP16G = 32;   // block size, pixels, nodes per workgroup
 constexpr int kP16RS = kP16K + 4;                     // padded FP32 residual row (floats)
+constexpr int kP16AC = 3;                             // A tiles whose fragments stay in registers
 
 typedef __bf16 p16_bf16x8 __attribute__((ext_vector_type(8)));
 typedef float p16_f32x16 __attribute__((ext_vector_type(16)));
@@ -226,6 +227,19 @@ __global__ __launch_bounds__(256, 1) void k_pursuit16_bf16(const JobDev* __restr
     for (int j = 0; j < 8; ++j) tq[ma][j] = sT32[fam][8 * hh + j][q];
   }
   const float* tpcol = &sT32[fam][0][rr & 15];   // T32_f[p][y] at tpcol[y * N]
+  // The A fragments do not change between steps or groups: those of the
+  // first kP16AC tiles are generated once and held in registers, the others
+  // each step.
+  constexpr int AC = kP16AC;
+  p16_bf16x8 afc[N][AC];
+#pragma unroll
+  for (int kk = 0; kk < N; ++kk) {
+    const float tpk = tpcol[kk * N];
+#pragma unroll
+    for (int ma = 0; ma < AC; ++ma)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) afc[kk][ma][j] = (__bf16)(tpk * tq[ma][j]);
+  }
   // Keys: the 23 bits of |c| that the batched path ranks on (exponent and 15
   // mantissa bits), then 511 - atom: the same order as its 64-bit keys.
   // 511 - atom of accumulator (ma, r) = lb - (32 ma + 8 (r >> 2) + (r & 3)).
@@ -298,8 +312,12 @@ __global__ __launch_bounds__(256, 1) void k_pursuit16_bf16(const JobDev* __restr
 #pragma unroll
         for (int ma = 0; ma < 4; ++ma) {
           p16_bf16x8 af;
+          if (ma < AC) {
+            af = afc[kk][ma < AC ? ma : 0];
+          } else {
 #pragma unroll
-          for (int j = 0; j < 8; ++j) af[j] = (__bf16)(tpk * tq[ma][j]);
+            for (int j = 0; j < 8; ++j) af[j] = (__bf16)(tpk * tq[ma][j]);
+          }
           acc[ma] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bf, acc[ma], 0, 0, 0);
         }
       }
