@@ -99,19 +99,25 @@ struct WGeo {
 // coalesced load, so nothing after the merge waits on global memory.
 // The nodes still running form the next step's active list: each wave holds
 // its survivors in registers (one per lane; the launch gives every wave at
-// most 64 positions), and after the loop the workgroup appends them with a
-// single atomic.  The list order then varies from run to run; no result
-// depends on it, since every node's arithmetic is independent of its list
-// position.
+// most 64 positions), and after the loop the workgroup (4 or 8 waves)
+// appends them with a single atomic.  The list order then varies from run to
+// run; no result depends on it, since every node's arithmetic is independent
+// of its list position.
 // ---------------------------------------------------------------------------
+// Waves (nodes) per workgroup: 8 where the staging fits in LDS, so that one
+// atomic appends the survivors of 8 nodes.
 template <int N>
-__global__ __launch_bounds__(256) void k_select(StepArgs a) {
+constexpr int sel_waves() { return N >= 64 ? 4 : 8; }
+
+template <int N>
+__global__ __launch_bounds__(64 * sel_waves<N>()) void k_select(StepArgs a) {
+  constexpr int W = sel_waves<N>();
   using G = WGeo<N>;
   constexpr int K = G::K, TPN = G::TPN;
   static_assert(TPN == 64, "one wave per node");
   constexpr int KPL = 4;                   // keys per lane (<= 256 keys)
   // per wave: rows [cand][0 = p row, 1 = q row][N] of the FP64 tables
-  __shared__ double sT[4][kCand][2][N];
+  __shared__ double sT[W][kCand][2][N];
   const int count = *a.act_count;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lg = a.lg;
@@ -119,9 +125,9 @@ __global__ __launch_bounds__(256) void k_select(StepArgs a) {
   const double inv_n = 1.0 / N;
   const int py = (lane / G::PX) * G::PH;
   const int px = (lane % G::PX) * G::PW;
-  const int stride = gridDim.x * 4;
+  const int stride = gridDim.x * W;
   int held = -1, n_held = 0;   // survivors of this wave, lane j holds the j-th
-  for (int pos = blockIdx.x * 4 + w; pos < count; pos += stride) {
+  for (int pos = blockIdx.x * W + w; pos < count; pos += stride) {
     // The keys depend only on the position: their loads go out first.
     unsigned long long k[KPL];
     const unsigned long long* kp = a.keys + (size_t)pos * nkeys;
@@ -299,11 +305,13 @@ __global__ __launch_bounds__(256) void k_select(StepArgs a) {
     }
   }
   if (a.next_act == nullptr) return;   // uniform: the level's last step
-  __shared__ int s_held[4], s_base;
+  __shared__ int s_held[W], s_base;
   if (lane == 0) s_held[w] = n_held;
   __syncthreads();
   if (tid == 0) {
-    const int tot = s_held[0] + s_held[1] + s_held[2] + s_held[3];
+    int tot = 0;
+#pragma unroll
+    for (int j = 0; j < W; ++j) tot += s_held[j];
     s_base = tot > 0 ? atomicAdd(a.next_count, tot) : 0;
     if (blockIdx.x == 0) *a.clear_count = 0;
   }
@@ -396,16 +404,21 @@ hipError_t launch_gather(int n, const StepArgs& a, const int32_t* count, hipStre
   return hipGetLastError();
 }
 
+template <int N>
+static void launch_select_n(const StepArgs& a, int64_t cap, hipStream_t s) {
+  // 4096 waves, and at most 64 positions per wave: one register per lane
+  // holds a survivor.
+  constexpr int W = sel_waves<N>();
+  int64_t g = 4096 / W;
+  if (g * W * 64 < cap) g = (cap + 64 * W - 1) / (64 * W);
+  hipLaunchKernelGGL(k_select<N>, dim3((unsigned)g), dim3(64 * W), 0, s, a);
+}
+
 hipError_t launch_select(int n, const StepArgs& a, int64_t cap, hipStream_t s) {
-  // At most 64 positions per wave (4 waves per workgroup): one register per
-  // lane holds a survivor.
-  int64_t g = grid_for<16>(4);
-  if (g * 4 * 64 < cap) g = (cap + 255) / 256;
-  const dim3 grid((unsigned)g);
   switch (n) {
-    case 16: hipLaunchKernelGGL(k_select<16>, grid, dim3(256), 0, s, a); break;
-    case 32: hipLaunchKernelGGL(k_select<32>, grid, dim3(256), 0, s, a); break;
-    case 64: hipLaunchKernelGGL(k_select<64>, grid, dim3(256), 0, s, a); break;
+    case 16: launch_select_n<16>(a, cap, s); break;
+    case 32: launch_select_n<32>(a, cap, s); break;
+    case 64: launch_select_n<64>(a, cap, s); break;
     default: return hipErrorInvalidValue;   // smaller levels run the fused pursuit
   }
   return hipGetLastError();
