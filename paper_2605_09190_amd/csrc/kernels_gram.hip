@@ -560,29 +560,51 @@ struct OmpGeo {
   static constexpr int K = N * N;
   static constexpr int M = NFAM * K;
   static constexpr bool SMALL = N <= 8;                // M <= 128: atom tid in thread tid, c0 computed here
-  // N >= 16: thread tid owns, in each family, the TP x TP tile of atoms
-  // p = (tid % 16) TP + dp, q = (tid / 16) TP + dq, as j = f AF + dq TP + dp
-  // (the atom index grows with j, so the per-thread arg-max keeps the lowest
-  // index on ties).  The cross-family correlation refresh of one selected
-  // atom then reads 2 TP table entries for TP^2 multiply-adds.
   static constexpr int NT = SMALL ? 128 : 256;         // threads per node
-  static constexpr int TP = SMALL ? 1 : N / 16;
-  static constexpr int AF = TP * TP;
+  // N >= 32 (MF): a family's N x N grid of (p, q) is cut into 16 x 16 tiles,
+  // TPW consecutive tiles per wave; a lane holds, per tile, the four atoms of
+  // the FP64 MFMA output layout: p = 16 tp + lane / 16 + 4 r,
+  // q = 16 tq + lane % 16, as j = f AF + 4 i + r, so the cross-family refresh
+  // is a rank-4 MFMA update per four selected atoms.
+  // N = 16: thread tid owns, in each family, the atom p = tid % 16,
+  // q = tid / 16 (j = f).
+  // Either way the atom index grows with j, so the per-thread arg-max keeps
+  // the lowest index on ties.
+  static constexpr bool MF = N >= 32;
+  static constexpr int NT16 = N / 16;                  // tiles per row of a family's grid
+  static constexpr int TPW = MF ? NT16 * NT16 / 4 : 1; // tiles per wave per family
+  static constexpr int AF = MF ? 4 * TPW : 1;          // atoms per thread per family
   static constexpr int APT = SMALL ? 1 : NFAM * AF;
   __device__ static int atom(int tid, int j) {
     if constexpr (SMALL) return tid;
-    const int f = j / AF, r = j % AF;
-    return f * K + ((tid / 16) * TP + r / TP) * N + (tid % 16) * TP + r % TP;
+    const int f = j / AF;
+    if constexpr (MF) {
+      const int rem = j % AF, i = rem / 4, r = rem % 4, l = tid & 63;
+      const int t = (tid >> 6) * TPW + i, tp = t / NT16, tq = t % NT16;
+      return f * K + (16 * tq + (l & 15)) * N + 16 * tp + (l >> 4) + 4 * r;
+    } else {
+      return f * K + (tid / 16) * N + tid % 16;
+    }
   }
   __device__ static int owner(int a) {
     if constexpr (SMALL) return a;
     const int q = (a % K) / N, p = a % N;
-    return (q / TP) * 16 + p / TP;
+    if constexpr (MF) {
+      const int t = (p / 16) * NT16 + q / 16;
+      return 64 * (t / TPW) + 16 * ((p % 16) % 4) + q % 16;
+    } else {
+      return q * 16 + p;
+    }
   }
   __device__ static int slot(int a) {
     if constexpr (SMALL) return 0;
     const int q = (a % K) / N, p = a % N;
-    return (a / K) * AF + (q % TP) * TP + p % TP;
+    if constexpr (MF) {
+      const int t = (p / 16) * NT16 + q / 16;
+      return (a / K) * AF + 4 * (t % TPW) + (p % 16) / 4;
+    } else {
+      return a / K;
+    }
   }
 };
 
@@ -622,7 +644,6 @@ __global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, Le
   __syncthreads();
   const int count = *count_ptr;
   const int pa = tid % N;                              // p of the thread's atom (N <= 8)
-  const int pb = (tid % 16) * G::TP, qb = (tid / 16) * G::TP;   // tile corner (N >= 16)
   int ph = 0, np = 0;
   for (;;) {
     if (tid == 0) sNode[np] = atomicAdd(next, 1);
@@ -812,43 +833,54 @@ __global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, Le
             c[0] = fma(-xs, g, c[0]);
           }
         }
-      } else if constexpr (NFAM == 2) {
-        // Each family's atoms take the other family's selections, in
-        // selection order: no branch per selected atom, and the loads of
-        // several selections are in flight together.
-        constexpr int TP = G::TP;
-        const int n0 = sNF[0], n1 = sNF[1];
-#pragma unroll 4
-        for (int k = 0; k < n0; ++k) {   // family-1 atoms: <T_1[p]T_1[q], T_0[ps]T_0[qs]> = X[ps][p] X[qs][q]
-          const int pq = sPQ[0][k];
-          const double xs = sXF[0][k];
-          const int ps = pq & 255, qs = pq >> 8;
-          double a[TP], b[TP];
+      } else if constexpr (NFAM == 2 && G::MF) {
+        // Each family's atoms take the other family's selections, four at a
+        // time as one rank-4 FP64 MFMA update per 16 x 16 tile:
+        // C[p][q] += A[p][k] B[k][q] with A = -dx_k X(p part), B = X(q part)
+        // (lane: A[lane % 16][lane / 16], B[lane / 16][lane % 16]).
+        constexpr int TPW = G::TPW, NT16 = G::NT16;
+        const int lk = lane >> 4, li = lane & 15;
 #pragma unroll
-          for (int d = 0; d < TP; ++d) {
-            a[d] = xs * sX[ps][pb + d];
-            b[d] = sX[qs][qb + d];
+        for (int fs = 0; fs < 2; ++fs) {
+          const int ns = sNF[fs];
+          const int fa = 1 - fs;   // the family whose atoms change
+          for (int kb = 0; kb < ns; kb += 4) {
+            const int k = kb + lk;
+            const bool ok = k < ns;
+            const int pq = ok ? sPQ[fs][k] : 0;
+            const double xs = ok ? sXF[fs][k] : 0.0;
+            const int ps = pq & 255, qs = pq >> 8;
+#pragma unroll
+            for (int i = 0; i < TPW; ++i) {
+              const int tt = wv * TPW + i, tp = tt / NT16, tq = tt % NT16;
+              // family-1 atoms: X[ps][p] X[qs][q]; family-0 atoms: X[p][ps] X[q][qs]
+              const double av = -xs * (fs == 0 ? sX[ps][16 * tp + li] : sX[16 * tp + li][ps]);
+              const double bv = fs == 0 ? sX[qs][16 * tq + li] : sX[16 * tq + li][qs];
+              const int j0 = fa * G::AF + 4 * i;
+              d4 cv = d4{c[j0], c[j0 + 1], c[j0 + 2], c[j0 + 3]};
+              cv = mfma64(av, bv, cv);
+              c[j0] = cv[0];
+              c[j0 + 1] = cv[1];
+              c[j0 + 2] = cv[2];
+              c[j0 + 3] = cv[3];
+            }
           }
-#pragma unroll
-          for (int dq = 0; dq < TP; ++dq)
-#pragma unroll
-            for (int dp = 0; dp < TP; ++dp) c[AF + dq * TP + dp] = fma(-a[dp], b[dq], c[AF + dq * TP + dp]);
+        }
+      } else if constexpr (NFAM == 2) {
+        // N = 16: each thread's two atoms (one per family) take the other
+        // family's selections one at a time.
+        const int pa16 = tid % 16, qa16 = tid / 16;
+#pragma unroll 4
+        for (int k = 0; k < sNF[0]; ++k) {   // family-1 atom: X[ps][p] X[qs][q]
+          const int pq = sPQ[0][k];
+          const int ps = pq & 255, qs = pq >> 8;
+          c[1] = fma(-sXF[0][k] * sX[ps][pa16], sX[qs][qa16], c[1]);
         }
 #pragma unroll 4
-        for (int k = 0; k < n1; ++k) {   // family-0 atoms: X[p][ps] X[q][qs]
+        for (int k = 0; k < sNF[1]; ++k) {   // family-0 atom: X[p][ps] X[q][qs]
           const int pq = sPQ[1][k];
-          const double xs = sXF[1][k];
           const int ps = pq & 255, qs = pq >> 8;
-          double a[TP], b[TP];
-#pragma unroll
-          for (int d = 0; d < TP; ++d) {
-            a[d] = xs * sX[pb + d][ps];
-            b[d] = sX[qb + d][qs];
-          }
-#pragma unroll
-          for (int dq = 0; dq < TP; ++dq)
-#pragma unroll
-            for (int dp = 0; dp < TP; ++dp) c[dq * TP + dp] = fma(-a[dp], b[dq], c[dq * TP + dp]);
+          c[0] = fma(-sXF[1][k] * sX[pa16][ps], sX[qa16][qs], c[0]);
         }
       }
 #pragma unroll
