@@ -560,19 +560,18 @@ struct OmpGeo {
   static constexpr int K = N * N;
   static constexpr int M = NFAM * K;
   static constexpr bool SMALL = N <= 8;                // M <= 128: atom tid in thread tid, c0 computed here
-  static constexpr int NT = SMALL ? 128 : 256;         // threads per node
-  // N >= 32 (MF): a family's N x N grid of (p, q) is cut into 16 x 16 tiles,
+  // threads per node: one wave at N = 16 (no workgroup barriers inside a
+  // step), four waves at N >= 32
+  static constexpr int NT = SMALL ? 128 : (N == 16 ? 64 : 256);
+  // N >= 16 (MF): a family's N x N grid of (p, q) is cut into 16 x 16 tiles,
   // TPW consecutive tiles per wave; a lane holds, per tile, the four atoms of
   // the FP64 MFMA output layout: p = 16 tp + lane / 16 + 4 r,
   // q = 16 tq + lane % 16, as j = f AF + 4 i + r, so the cross-family refresh
-  // is a rank-4 MFMA update per four selected atoms.
-  // N = 16: thread tid owns, in each family, the atom p = tid % 16,
-  // q = tid / 16 (j = f).
-  // Either way the atom index grows with j, so the per-thread arg-max keeps
-  // the lowest index on ties.
-  static constexpr bool MF = N >= 32;
+  // is a rank-4 MFMA update per four selected atoms.  The atom index grows
+  // with j, so the per-thread arg-max keeps the lowest index on ties.
+  static constexpr bool MF = !SMALL;
   static constexpr int NT16 = N / 16;                  // tiles per row of a family's grid
-  static constexpr int TPW = MF ? NT16 * NT16 / 4 : 1; // tiles per wave per family
+  static constexpr int TPW = MF ? NT16 * NT16 / (NT / 64) : 1;   // tiles per wave per family
   static constexpr int AF = MF ? 4 * TPW : 1;          // atoms per thread per family
   static constexpr int APT = SMALL ? 1 : NFAM * AF;
   __device__ static int atom(int tid, int j) {
@@ -865,22 +864,6 @@ __global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, Le
               c[j0 + 3] = cv[3];
             }
           }
-        }
-      } else if constexpr (NFAM == 2) {
-        // N = 16: each thread's two atoms (one per family) take the other
-        // family's selections one at a time.
-        const int pa16 = tid % 16, qa16 = tid / 16;
-#pragma unroll 4
-        for (int k = 0; k < sNF[0]; ++k) {   // family-1 atom: X[ps][p] X[qs][q]
-          const int pq = sPQ[0][k];
-          const int ps = pq & 255, qs = pq >> 8;
-          c[1] = fma(-sXF[0][k] * sX[ps][pa16], sX[qs][qa16], c[1]);
-        }
-#pragma unroll 4
-        for (int k = 0; k < sNF[1]; ++k) {   // family-0 atom: X[p][ps] X[q][qs]
-          const int pq = sPQ[1][k];
-          const int ps = pq & 255, qs = pq >> 8;
-          c[0] = fma(-sXF[1][k] * sX[pa16][ps], sX[qa16][qs], c[0]);
         }
       }
 #pragma unroll
