@@ -560,9 +560,10 @@ struct OmpGeo {
   static constexpr int K = N * N;
   static constexpr int M = NFAM * K;
   static constexpr bool SMALL = N <= 8;                // M <= 128: atom tid in thread tid, c0 computed here
-  // threads per node: one wave at N = 16 (no workgroup barriers inside a
-  // step), four waves at N >= 32
-  static constexpr int NT = SMALL ? 128 : (N == 16 ? 64 : 256);
+  // threads per node: one wave at N = 16 (its workgroup barriers are the
+  // wave's own ordering), two waves at N = 32, eight at N = 64 (two 16 x 16
+  // tiles per wave and family at either)
+  static constexpr int NT = SMALL ? 128 : (N == 16 ? 64 : (N == 32 ? 128 : 512));
   // N >= 16 (MF): a family's N x N grid of (p, q) is cut into 16 x 16 tiles,
   // TPW consecutive tiles per wave; a lane holds, per tile, the four atoms of
   // the FP64 MFMA output layout: p = 16 tp + lane / 16 + 4 r,
@@ -574,6 +575,10 @@ struct OmpGeo {
   static constexpr int TPW = MF ? NT16 * NT16 / (NT / 64) : 1;   // tiles per wave per family
   static constexpr int AF = MF ? 4 * TPW : 1;          // atoms per thread per family
   static constexpr int APT = SMALL ? 1 : NFAM * AF;
+  // a wave's tiles cover the grid once and lie in one tile row (so that the
+  // atom index grows with j); at most eight waves (the per-wave best slots)
+  static_assert(!MF || (TPW * (NT / 64) == NT16 * NT16 && NT16 % TPW == 0), "tile split");
+  static_assert(NT <= 512, "per-wave slots");
   __device__ static int atom(int tid, int j) {
     if constexpr (SMALL) return tid;
     const int f = j / AF;
@@ -608,7 +613,7 @@ struct OmpGeo {
 };
 
 template <int N, int NFAM>
-__global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, LevelDev lv,
+__global__ __launch_bounds__((OmpGeo<N, NFAM>::NT)) void k_omp(const JobDev* __restrict__ jobs, LevelDev lv,
                                              const int32_t* __restrict__ count_ptr, int32_t* next, int32_t lg,
                                              const double* __restrict__ tab, const double* __restrict__ xg,
                                              const double* __restrict__ cbuf, int kcap) {
@@ -630,8 +635,8 @@ __global__ __launch_bounds__(256) void k_omp(const JobDev* __restrict__ jobs, Le
   __shared__ int sPQ[NFAM][KC];
   __shared__ double sXF[NFAM][KC];
   __shared__ int sNF[NFAM];
-  __shared__ double sBc[2][4];                         // per-wave best c
-  __shared__ int sBi[2][4];
+  __shared__ double sBc[2][8];                         // per-wave best c
+  __shared__ int sBi[2][8];
   __shared__ double sScal[2];                          // dependence flag, new ||r||^2
   __shared__ double sRed[2];
   __shared__ int sNode[2];
