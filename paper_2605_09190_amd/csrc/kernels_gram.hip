@@ -559,11 +559,11 @@ template <int N, int NFAM>
 struct OmpGeo {
   static constexpr int K = N * N;
   static constexpr int M = NFAM * K;
-  static constexpr bool SMALL = N <= 8;                // M <= 128: atom tid in thread tid, c0 computed here
-  // threads per node: one wave at N = 16 (its workgroup barriers are the
+  static constexpr bool SMALL = N <= 8;                // K <= 64: one wave, lane k holds atom (f, k) of each family, c0 computed here
+  // threads per node: one wave at N <= 16 (its workgroup barriers are the
   // wave's own ordering), two waves at N = 32, eight at N = 64 (two 16 x 16
   // tiles per wave and family at either)
-  static constexpr int NT = SMALL ? 128 : (N == 16 ? 64 : (N == 32 ? 128 : 512));
+  static constexpr int NT = N <= 16 ? 64 : (N == 32 ? 128 : 512);
   // N >= 16 (MF): a family's N x N grid of (p, q) is cut into 16 x 16 tiles,
   // TPW consecutive tiles per wave; a lane holds, per tile, the four atoms of
   // the FP64 MFMA output layout: p = 16 tp + lane / 16 + 4 r,
@@ -574,13 +574,13 @@ struct OmpGeo {
   static constexpr int NT16 = N / 16;                  // tiles per row of a family's grid
   static constexpr int TPW = MF ? NT16 * NT16 / (NT / 64) : 1;   // tiles per wave per family
   static constexpr int AF = MF ? 4 * TPW : 1;          // atoms per thread per family
-  static constexpr int APT = SMALL ? 1 : NFAM * AF;
+  static constexpr int APT = SMALL ? NFAM : NFAM * AF;
   // a wave's tiles cover the grid once and lie in one tile row (so that the
   // atom index grows with j); at most eight waves (the per-wave best slots)
   static_assert(!MF || (TPW * (NT / 64) == NT16 * NT16 && NT16 % TPW == 0), "tile split");
   static_assert(NT <= 512, "per-wave slots");
   __device__ static int atom(int tid, int j) {
-    if constexpr (SMALL) return tid;
+    if constexpr (SMALL) return tid < K ? j * K + tid : M;   // lanes past K hold no atom
     const int f = j / AF;
     if constexpr (MF) {
       const int rem = j % AF, i = rem / 4, r = rem % 4, l = tid & 63;
@@ -591,7 +591,7 @@ struct OmpGeo {
     }
   }
   __device__ static int owner(int a) {
-    if constexpr (SMALL) return a;
+    if constexpr (SMALL) return a % K;
     const int q = (a % K) / N, p = a % N;
     if constexpr (MF) {
       const int t = (p / 16) * NT16 + q / 16;
@@ -601,7 +601,7 @@ struct OmpGeo {
     }
   }
   __device__ static int slot(int a) {
-    if constexpr (SMALL) return 0;
+    if constexpr (SMALL) return a / K;
     const int q = (a % K) / N, p = a % N;
     if constexpr (MF) {
       const int t = (p / 16) * NT16 + q / 16;
@@ -663,7 +663,7 @@ __global__ __launch_bounds__((OmpGeo<N, NFAM>::NT)) void k_omp(const JobDev* __r
     // c: the current correlations <r, phi_a> of the thread's atoms.  Small
     // blocks recompute them from c0 = D^T y each step; larger ones update
     // them in place (see the refresh).
-    double c0[1] = {0.0}, c[APT];
+    double c0[SMALL ? APT : 1], c[APT];
     if constexpr (SMALL) {
       // gather (pixel k in thread k), ||y||^2, sum y, first stop test, c0
       double v = 0.0;
@@ -682,20 +682,23 @@ __global__ __launch_bounds__((OmpGeo<N, NFAM>::NT)) void k_omp(const JobDev* __r
       e = sRed[0];
       const double ssum = sRed[1];
       st = e < eps2 ? ST_ACC : (kmax <= 0 ? ST_SPARSE : ST_RUN);
-      double acc = 0.0;
-      if (tid < M) {
-        const int f = tid / K, q = (tid % K) / N;
 #pragma unroll
-        for (int y = 0; y < N; ++y) {
-          double u = 0.0;
+      for (int f = 0; f < APT; ++f) {   // the lane's atom (f, p = tid % N, q = tid / N)
+        double acc = 0.0;
+        if (tid < K) {
+          const int q = tid / N;
 #pragma unroll
-          for (int x = 0; x < N; ++x) u = fma(sT[f][q * N + x], sY[y * N + x], u);
-          acc = fma(sT[f][pa * N + y], u, acc);
+          for (int y = 0; y < N; ++y) {
+            double u = 0.0;
+#pragma unroll
+            for (int x = 0; x < N; ++x) u = fma(sT[f][q * N + x], sY[y * N + x], u);
+            acc = fma(sT[f][pa * N + y], u, acc);
+          }
+          if (tid == 0) acc = ssum / N;
         }
-        if (tid % K == 0) acc = ssum / N;
+        c0[f] = acc;
+        c[f] = acc;
       }
-      c0[0] = acc;
-      c[0] = acc;
     } else {
       e = lv.e[node];
       st = lv.st[node];
@@ -825,16 +828,24 @@ __global__ __launch_bounds__((OmpGeo<N, NFAM>::NT)) void k_omp(const JobDev* __r
       if (st != ST_RUN) break;
       // (6) refresh: small blocks c = c0 - G_{:,S} x_S, larger ones
       // c -= G_{:,S} dx (c = c0 - G x at every step either way)
-      if constexpr (SMALL) c[0] = c0[0];
+      if constexpr (SMALL) {
+#pragma unroll
+        for (int f = 0; f < APT; ++f) c[f] = c0[f];
+      }
       if constexpr (NFAM == 2 && SMALL) {
-        for (int s = 0; s < t; ++s) {
-          const int as = sS[s];
-          const double xs = sXc[s];
-          const int fs = as / K, ps = as % N, qs = (as % K) / N;
-          const int fa = tid / K, qa = (tid % K) / N;
-          if (tid < M && fa != fs) {
-            const double g = fs == 0 ? sX[ps][pa] * sX[qs][qa] : sX[pa][ps] * sX[qa][qs];
-            c[0] = fma(-xs, g, c[0]);
+        // each of the lane's atoms takes the other family's selections, in
+        // selection order, with their current coefficients
+        const int qa = tid / N;
+        if (tid < K) {
+#pragma unroll
+          for (int fs = 0; fs < 2; ++fs) {
+            const int fa = 1 - fs;
+            for (int k = 0; k < sNF[fs]; ++k) {
+              const int pq = sPQ[fs][k];
+              const int ps = pq & 255, qs = pq >> 8;
+              const double g = fs == 0 ? sX[ps][pa] * sX[qs][qa] : sX[pa][ps] * sX[qa][qs];
+              c[fa] = fma(-sXF[fs][k], g, c[fa]);
+            }
           }
         }
       } else if constexpr (NFAM == 2 && G::MF) {
