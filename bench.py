@@ -325,7 +325,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the encoder is a single-GPU path (--gpus {args.gpus} "
-              f"requested); see the sharding notes in DESIGN.md", file=sys.stderr)
+              f"requested)", file=sys.stderr)
         sys.exit(2)
 
     import torch
