@@ -32,13 +32,13 @@ PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
 # profiles/traffic_k_select_2048x2048x3_ycbcr.md); valid only for the kernel
 # source and the workload they were taken on.
 _MP_SRC = dict(workload="c3", src="paper_2605_09190_amd/csrc/kernels_mp.hip",
-               sha256="d14daede8efc47bb617c676cd5ad9198fda8b9117d44d82fd55c2b3eccb0bcd6")
+               sha256="15c6ff00192a461ad4dd60ad1e0a99d86bfda611ace6221666c81c68447adfc4")
 TRAFFIC = {
     "k_corr_bf16_gen<64>": dict(bytes_per_launch=15.69e6, fetch=13.28e6, write=2.41e6, workload="c3",
                                 src="paper_2605_09190_amd/csrc/kernels_corr.hip",
                                 sha256="b3775b1b9612aaa553e2368099a2a8d2248cdbfc322bcf852338f0733eb8661e"),
-    "k_select<64>": dict(bytes_per_launch=51.59e6, fetch=22.56e6, write=29.04e6, **_MP_SRC),
-    "k_select<32>": dict(bytes_per_launch=21.03e6, fetch=9.21e6, write=11.82e6, **_MP_SRC),
+    "k_select<64>": dict(bytes_per_launch=51.61e6, fetch=22.57e6, write=29.04e6, **_MP_SRC),
+    "k_select<32>": dict(bytes_per_launch=21.04e6, fetch=9.22e6, write=11.82e6, **_MP_SRC),
 }
 
 

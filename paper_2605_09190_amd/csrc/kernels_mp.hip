@@ -44,18 +44,24 @@ __global__ __launch_bounds__(256) void k_gather(StepArgs a, const int32_t* count
     patch_origin<N>(lt, py, px);
     float* r = a.r32 + (size_t)node * K;
     double e = 0.0;
+    // a patch row of PW pixels: one FP32 and one BF16 vector store
+    typedef float f32v __attribute__((ext_vector_type(G::PW)));
+    typedef uint16_t u16v __attribute__((ext_vector_type(G::PW)));
 #pragma unroll
     for (int dy = 0; dy < G::PH; ++dy) {
+      f32v fv;
+      u16v bv;
 #pragma unroll
       for (int dx = 0; dx < G::PW; ++dx) {
         const double v = job_pixel(jb, by + py + dy, bx + px + dx);
-        const float f = (float)v;
-        const int o = (py + dy) * N + px + dx;
-        if (valid) {
-          r[o] = f;
-          if (a.r16) a.r16[(size_t)node * K + o] = f32_to_bf16(f);
-        }
+        fv[dx] = (float)v;
+        bv[dx] = f32_to_bf16(fv[dx]);
         e += v * v;
+      }
+      const int o = (py + dy) * N + px;
+      if (valid) {
+        *(f32v*)(r + o) = fv;
+        if (a.r16) *(u16v*)(a.r16 + (size_t)node * K + o) = bv;
       }
     }
     e = group_sum<G::TPN>(e, s_red[g]);
