@@ -581,34 +581,19 @@ struct OmpGeo {
   static_assert(NT <= 512, "per-wave slots");
   __device__ static int atom(int tid, int j) {
     if constexpr (SMALL) return tid < K ? j * K + tid : M;   // lanes past K hold no atom
-    const int f = j / AF;
-    if constexpr (MF) {
-      const int rem = j % AF, i = rem / 4, r = rem % 4, l = tid & 63;
-      const int t = (tid >> 6) * TPW + i, tp = t / NT16, tq = t % NT16;
-      return f * K + (16 * tq + (l & 15)) * N + 16 * tp + (l >> 4) + 4 * r;
-    } else {
-      return f * K + (tid / 16) * N + tid % 16;
-    }
+    const int f = j / AF, rem = j % AF, i = rem / 4, r = rem % 4, l = tid & 63;
+    const int t = (tid >> 6) * TPW + i, tp = t / NT16, tq = t % NT16;
+    return f * K + (16 * tq + (l & 15)) * N + 16 * tp + (l >> 4) + 4 * r;
   }
   __device__ static int owner(int a) {
     if constexpr (SMALL) return a % K;
-    const int q = (a % K) / N, p = a % N;
-    if constexpr (MF) {
-      const int t = (p / 16) * NT16 + q / 16;
-      return 64 * (t / TPW) + 16 * ((p % 16) % 4) + q % 16;
-    } else {
-      return q * 16 + p;
-    }
+    const int q = (a % K) / N, p = a % N, t = (p / 16) * NT16 + q / 16;
+    return 64 * (t / TPW) + 16 * ((p % 16) % 4) + q % 16;
   }
   __device__ static int slot(int a) {
     if constexpr (SMALL) return a / K;
-    const int q = (a % K) / N, p = a % N;
-    if constexpr (MF) {
-      const int t = (p / 16) * NT16 + q / 16;
-      return (a / K) * AF + 4 * (t % TPW) + (p % 16) / 4;
-    } else {
-      return a / K;
-    }
+    const int q = (a % K) / N, p = a % N, t = (p / 16) * NT16 + q / 16;
+    return (a / K) * AF + 4 * (t % TPW) + (p % 16) / 4;
   }
 };
 
