@@ -324,6 +324,43 @@ void aqmp_code_free(aqmp_code* c);
 int aqmp_decode(const aqmp_dict* d, const aqmp_code* c, int job,
                 void* dev_out, int dtype, int64_t row_stride, void* hip_stream);
 
+/* ---- the integer worklist steps on their own ----------------------------
+ * The encoder's active-list compaction and split/emit kernels, applied to
+ * caller arrays, so that this integer work can be checked bit for bit.  Both
+ * calls allocate a small device scan state per call (a few bytes per 1024
+ * items), run on hip_stream, and synchronise it before returning. */
+
+/* Active list (Section 2.2 step (d): the nodes whose pursuit has not stopped
+ * go on).  dev_status: n node status bytes (device), 0 = running, any other
+ * value = stopped.  Writes to dev_out (device, room for n int32), in
+ * increasing order, every i in [0, n) with dev_status[i] == 0, and their
+ * number to *dev_count (device int32).  dev_out past the count is not
+ * written.  0 <= n <= 2^28.  AQMP_E_HIP if a bounded device wait ran out. */
+int aqmp_worklist_compact(const uint8_t* dev_status, int64_t n, int32_t* dev_out, int32_t* dev_count,
+                          void* hip_stream);
+
+/* Split test and child emission of one quadtree level of block size n
+ * (Algorithm 2: a block that misses its target is refined into the four
+ * quadrants of its original pixels).  Node i (0 <= i < n_nodes) uses the
+ * parameter set prm[dev_node_prm[i]] (host array prm of n_prm sets); it is
+ * split when n > n_min and, under AQMP_SPLIT_R1, dev_e[i] (its ||r||^2 after
+ * MP) >= eps_n^2, or under AQMP_SPLIT_R2, dev_t[i] (its iterations) >= k_n,
+ * with eps_n and k_n as in aqmp_params.  For a split node, bit 4 (0x10) of
+ * dev_status[i] is set (the other bits are kept), and its four children,
+ * of size n/2, in the order top-left, top-right, bottom-left, bottom-right,
+ * go to positions child_base + 4 p .. child_base + 4 p + 3 of dev_child_prm
+ * (the node's parameter set), dev_child_x0 and dev_child_y0, where p counts
+ * the split nodes before i.  *dev_child_count receives child_base + 4 x (split
+ * nodes).  All node and child arrays are device memory; the child arrays
+ * need room for child_base + 4 n_nodes entries; entries before child_base and
+ * past the count are not written.  n is a power of two in [8, 64],
+ * 0 <= n_nodes <= 2^28.  AQMP_E_HIP if a node names a parameter set outside
+ * [0, n_prm) (that node is not split) or a bounded device wait ran out. */
+int aqmp_worklist_split(const aqmp_params* prm, int n_prm, int n, const int32_t* dev_node_prm, const int32_t* dev_x0,
+                        const int32_t* dev_y0, const double* dev_e, const int32_t* dev_t, int64_t n_nodes,
+                        int32_t child_base, uint8_t* dev_status, int32_t* dev_child_prm, int32_t* dev_child_x0,
+                        int32_t* dev_child_y0, int32_t* dev_child_count, void* hip_stream);
+
 /* Message for the calling thread's last failure ("" if none). */
 const char* aqmp_last_error(void);
 

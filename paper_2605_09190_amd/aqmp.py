@@ -39,7 +39,7 @@ EXPORTS = [
     "aqmp_dictionary_build", "aqmp_dictionary_free", "aqmp_dictionary_atoms", "aqmp_dictionary_copy",
     "aqmp_encode", "aqmp_reencode", "aqmp_code_sizes", "aqmp_code_export", "aqmp_code_export_nodes",
     "aqmp_code_stats", "aqmp_code_timing", "aqmp_code_free", "aqmp_decode", "aqmp_last_error",
-    "aqmp_corr_kernel", "aqmp_code_pack", "aqmp_ssim",
+    "aqmp_corr_kernel", "aqmp_code_pack", "aqmp_ssim", "aqmp_worklist_compact", "aqmp_worklist_split",
 ]
 
 
@@ -117,6 +117,9 @@ def _load() -> C.CDLL:
     lib.aqmp_corr_kernel.restype = C.c_char_p
     lib.aqmp_ssim.argtypes = [C.POINTER(Image), C.POINTER(Image), i32, C.c_double, C.POINTER(C.c_double), vp]
     lib.aqmp_code_pack.argtypes = [vp, C.POINTER(C.c_int32), i32, i32, vp, i64, C.POINTER(C.c_int64)]
+    lib.aqmp_worklist_compact.argtypes = [vp, i64, vp, vp, vp]
+    lib.aqmp_worklist_split.argtypes = [C.POINTER(Params), i32, i32, vp, vp, vp, vp, vp, i64, C.c_int32, vp, vp, vp,
+                                        vp, vp, vp]
     for name in EXPORTS:
         if not hasattr(lib, name):
             raise ImportError(f"{LIB_PATH} lacks {name}")
@@ -199,6 +202,48 @@ def ssim(x, y, mode: int = SSIM_WINDOW7, data_range: float = 1.0, stream=None) -
     return out.value
 
 
+def _dev_tensor(t, dtype, name):
+    import torch
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous CUDA {dtype} tensor")
+    return t.data_ptr()
+
+
+def worklist_compact(status, out, count, stream=None) -> None:
+    """Active-list compaction: out[:count] = indices of the zero bytes of
+    status, in order (aqmp_worklist_compact).  status uint8, out int32 with
+    room for len(status), count one int32; all CUDA tensors."""
+    import torch
+    n = int(status.numel())
+    if out.numel() < n or count.numel() < 1:
+        raise ValueError("out needs room for every item and count one element")
+    _check(lib.aqmp_worklist_compact(_dev_tensor(status, torch.uint8, "status"), n,
+                                     _dev_tensor(out, torch.int32, "out"), _dev_tensor(count, torch.int32, "count"),
+                                     _stream_handle(stream)))
+
+
+def worklist_split(params, n: int, node_prm, x0, y0, e, t, status, child_prm, child_x0, child_y0, child_count,
+                   child_base: int = 0, stream=None) -> None:
+    """Split test and child emission of one level (aqmp_worklist_split)."""
+    import torch
+    nn = int(node_prm.numel())
+    for name, a in (("x0", x0), ("y0", y0), ("e", e), ("t", t), ("status", status)):
+        if a.numel() != nn:
+            raise ValueError(f"{name} must have one entry per node")
+    for name, a in (("child_prm", child_prm), ("child_x0", child_x0), ("child_y0", child_y0)):
+        if a.numel() < child_base + 4 * nn:
+            raise ValueError(f"{name} needs child_base + 4 entries per node")
+    prms = (Params * len(params))(*[p if isinstance(p, Params) else make_params(**p) for p in params])
+    i32 = torch.int32
+    _check(lib.aqmp_worklist_split(prms, len(params), int(n), _dev_tensor(node_prm, i32, "node_prm"),
+                                   _dev_tensor(x0, i32, "x0"), _dev_tensor(y0, i32, "y0"),
+                                   _dev_tensor(e, torch.float64, "e"), _dev_tensor(t, i32, "t"), nn, int(child_base),
+                                   _dev_tensor(status, torch.uint8, "status"),
+                                   _dev_tensor(child_prm, i32, "child_prm"), _dev_tensor(child_x0, i32, "child_x0"),
+                                   _dev_tensor(child_y0, i32, "child_y0"),
+                                   _dev_tensor(child_count, i32, "child_count"), _stream_handle(stream)))
+
+
 class Dictionary:
     """D_N for N = n_min .. n_max (powers of two), DCT and/or Haar families."""
 
@@ -261,6 +306,8 @@ class Code:
                                _stream_handle(stream), C.byref(h)))
         self.h = h
         self.n_jobs = len(jobs)
+        # (rows, columns) of each job's plane: the decode writes that many samples
+        self._job_shape = [(int(images[int(a)].shape[0]), int(images[int(a)].shape[1])) for a, _ in jobs]
 
     def reencode(self, images, stream=None) -> None:
         self._keep = list(images)
@@ -311,9 +358,20 @@ class Code:
         return self._export(lib.aqmp_code_export_nodes, int(sum(s["nodes"])), int(s["iters_executed"]))
 
     def decode(self, job: int, out, stream=None) -> None:
+        """Writes job's reconstruction into out (a 2D float32 or float64 CUDA
+        tensor on the code's device, at least as large as the job's plane)."""
         import torch
+        if not 0 <= int(job) < self.n_jobs:
+            raise ValueError(f"job {job} out of range (0..{self.n_jobs - 1})")
         if out.dim() != 2 or not out.is_cuda or out.stride(1) != 1:
             raise ValueError("out must be a 2D CUDA tensor with unit column stride")
+        if out.dtype not in (torch.float32, torch.float64):
+            raise ValueError("out must be float32 or float64")
+        h, w = self._job_shape[int(job)]
+        if out.shape[0] < h or out.shape[1] < w:
+            raise ValueError(f"out is {tuple(out.shape)}; the job's plane is {h} x {w}")
+        if out.device != self._keep[0].device:
+            raise ValueError(f"out is on {out.device}; the code is on {self._keep[0].device}")
         dt = F32 if out.dtype == torch.float32 else F64
         _check(lib.aqmp_decode(self.dic.h, self.h, job, out.data_ptr(), dt, int(out.stride(0)),
                                _stream_handle(stream)))

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libaqmp.so")
 OBJ = os.path.join(ROOT, "_build")
 SOURCES = ["api.hip", "dict.hip", "encode.hip", "kernels_tree.hip", "kernels_mp.hip", "kernels_corr.hip",
-           "kernels_fused.hip", "kernels_gram.hip", "kernels_ssim.hip", "kernels_export.hip"]
+           "kernels_fused.hip", "kernels_gram.hip", "kernels_ssim.hip", "kernels_export.hip", "worklist.hip"]
 ARCH = "gfx950"
 
 

@@ -27,6 +27,11 @@ int code_export(const aqmp_code* c, bool leaves_only, aqmp_leaf* leaves, int32_t
                 int64_t cap_leaves, int64_t cap_atoms);
 int decode(const aqmp_dict* d, const aqmp_code* c, int job, void* out, int dtype, int64_t row_stride,
            hipStream_t s);
+int worklist_compact(const uint8_t* st, int64_t n, int32_t* out, int32_t* count, hipStream_t s);
+int worklist_split(const aqmp_params* prm, int n_prm, int n, const int32_t* node_prm, const int32_t* x0,
+                   const int32_t* y0, const double* e, const int32_t* t, int64_t n_nodes, int32_t child_base,
+                   uint8_t* st, int32_t* child_prm, int32_t* child_x0, int32_t* child_y0, int32_t* child_count,
+                   hipStream_t s);
 
 namespace {
 thread_local std::string g_error;
@@ -150,6 +155,20 @@ void aqmp_code_free(aqmp_code* c) {
 int aqmp_decode(const aqmp_dict* d, const aqmp_code* c, int job, void* dev_out, int dtype, int64_t row_stride,
                 void* hip_stream) {
   AQMP_ENTRY(decode(d, c, job, dev_out, dtype, row_stride, (hipStream_t)hip_stream));
+}
+
+int aqmp_worklist_compact(const uint8_t* dev_status, int64_t n, int32_t* dev_out, int32_t* dev_count,
+                          void* hip_stream) {
+  AQMP_ENTRY(worklist_compact(dev_status, n, dev_out, dev_count, (hipStream_t)hip_stream));
+}
+
+int aqmp_worklist_split(const aqmp_params* prm, int n_prm, int n, const int32_t* dev_node_prm, const int32_t* dev_x0,
+                        const int32_t* dev_y0, const double* dev_e, const int32_t* dev_t, int64_t n_nodes,
+                        int32_t child_base, uint8_t* dev_status, int32_t* dev_child_prm, int32_t* dev_child_x0,
+                        int32_t* dev_child_y0, int32_t* dev_child_count, void* hip_stream) {
+  AQMP_ENTRY(worklist_split(prm, n_prm, n, dev_node_prm, dev_x0, dev_y0, dev_e, dev_t, n_nodes, child_base,
+                            dev_status, dev_child_prm, dev_child_x0, dev_child_y0, dev_child_count,
+                            (hipStream_t)hip_stream));
 }
 
 const char* aqmp_last_error(void) { return last_error(); }

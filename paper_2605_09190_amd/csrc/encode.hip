@@ -122,18 +122,51 @@ struct aqmp_code {
 
 namespace aqmp {
 
-namespace {
+static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+static int k_of(const aqmp_params& p, int lg) {
+  const int k = p.k_per_level[lg];
+  return k >= 0 ? k : p.max_atoms;
+}
+
+int check_params(const aqmp_params& p, const std::string& tag) {
+  if (!pow2(p.n_min) || !pow2(p.n_max) || p.n_min < AQMP_MIN_N || p.n_max > AQMP_MAX_N || p.n_min > p.n_max)
+    AQMP_FAIL(AQMP_E_INVALID, tag + "need powers of two 4 <= n_min <= n_max <= 64");
+  if (!(p.tol >= 0.0) || !std::isfinite(p.tol)) AQMP_FAIL(AQMP_E_INVALID, tag + "tol must be finite and >= 0");
+  if (p.tol_mode != AQMP_TOL_RMS && p.tol_mode != AQMP_TOL_ABS) AQMP_FAIL(AQMP_E_INVALID, tag + "bad tol_mode");
+  if (p.split_rule != AQMP_SPLIT_R1 && p.split_rule != AQMP_SPLIT_R2)
+    AQMP_FAIL(AQMP_E_INVALID, tag + "bad split_rule");
+  if (p.max_atoms < 0 || p.max_atoms > AQMP_MAX_ATOMS) AQMP_FAIL(AQMP_E_INVALID, tag + "max_atoms out of range");
+  for (int l = 0; l < kLevels; ++l)
+    if (p.k_per_level[l] < -1 || p.k_per_level[l] > AQMP_MAX_ATOMS)
+      AQMP_FAIL(AQMP_E_INVALID, tag + "k_per_level out of range");
+  return AQMP_OK;
+}
+
+JobDev make_jobdev(const aqmp_image& im, const aqmp_params& p) {
+  JobDev j{};
+  j.img = im.dev_ptr;
+  j.dtype = im.dtype;
+  j.w = im.w;
+  j.h = im.h;
+  j.row_stride = im.row_stride;
+  j.n_min = p.n_min;
+  j.n_max = p.n_max;
+  j.split_rule = p.split_rule;
+  for (int l = 0; l < kLevels; ++l) {
+    const double n = (double)(1 << l);
+    const double eps = p.tol_mode == AQMP_TOL_RMS ? p.tol * n : p.tol;
+    j.eps2[l] = eps * eps;
+    j.k[l] = k_of(p, l);
+  }
+  return j;
+}
+
+namespace {
 
 // Image extent rounded up to a multiple of the top-level block size: the
 // blocks tile the padded plane (edge replication, see job_pixel).
 int64_t padded(int v, int n) { return ((int64_t)v + n - 1) / n * n; }
-
-int k_of(const aqmp_params& p, int lg) {
-  const int k = p.k_per_level[lg];
-  return k >= 0 ? k : p.max_atoms;
-}
 
 int validate(const aqmp_dict* d, const aqmp_image* imgs, int n_imgs, const aqmp_params* prm, int n_prm,
              const aqmp_job* jobs, int n_jobs, const aqmp_options* opt) {
@@ -170,16 +203,8 @@ int validate(const aqmp_dict* d, const aqmp_image* imgs, int n_imgs, const aqmp_
   for (int i = 0; i < n_prm; ++i) {
     const aqmp_params& p = prm[i];
     const std::string tag = "aqmp_encode: params " + std::to_string(i) + ": ";
-    if (!pow2(p.n_min) || !pow2(p.n_max) || p.n_min < AQMP_MIN_N || p.n_max > AQMP_MAX_N || p.n_min > p.n_max)
-      AQMP_FAIL(AQMP_E_INVALID, tag + "need powers of two 4 <= n_min <= n_max <= 64");
-    if (!(p.tol >= 0.0) || !std::isfinite(p.tol)) AQMP_FAIL(AQMP_E_INVALID, tag + "tol must be finite and >= 0");
-    if (p.tol_mode != AQMP_TOL_RMS && p.tol_mode != AQMP_TOL_ABS) AQMP_FAIL(AQMP_E_INVALID, tag + "bad tol_mode");
-    if (p.split_rule != AQMP_SPLIT_R1 && p.split_rule != AQMP_SPLIT_R2)
-      AQMP_FAIL(AQMP_E_INVALID, tag + "bad split_rule");
-    if (p.max_atoms < 0 || p.max_atoms > AQMP_MAX_ATOMS) AQMP_FAIL(AQMP_E_INVALID, tag + "max_atoms out of range");
-    for (int l = 0; l < kLevels; ++l)
-      if (p.k_per_level[l] < -1 || p.k_per_level[l] > AQMP_MAX_ATOMS)
-        AQMP_FAIL(AQMP_E_INVALID, tag + "k_per_level out of range");
+    const int rc = check_params(p, tag);
+    if (rc != AQMP_OK) return rc;
     for (int n = p.n_min; n <= p.n_max; n *= 2) {
       if (!d->lv[ilog2(n)].have)
         AQMP_FAIL(AQMP_E_NODICT, tag + "the dictionary has no block size " + std::to_string(n));
@@ -202,25 +227,6 @@ int alloc(aqmp_code* c, void** p, size_t bytes) {
   const int rc = dev_alloc(p, bytes);
   if (rc == AQMP_OK) c->allocs.push_back({*p, bytes});
   return rc;
-}
-
-JobDev make_jobdev(const aqmp_image& im, const aqmp_params& p) {
-  JobDev j{};
-  j.img = im.dev_ptr;
-  j.dtype = im.dtype;
-  j.w = im.w;
-  j.h = im.h;
-  j.row_stride = im.row_stride;
-  j.n_min = p.n_min;
-  j.n_max = p.n_max;
-  j.split_rule = p.split_rule;
-  for (int l = 0; l < kLevels; ++l) {
-    const double n = (double)(1 << l);
-    const double eps = p.tol_mode == AQMP_TOL_RMS ? p.tol * n : p.tol;
-    j.eps2[l] = eps * eps;
-    j.k[l] = k_of(p, l);
-  }
-  return j;
 }
 
 void plan_pass(const aqmp_code* c, int j0, int j1, PassPlan& pp) {
@@ -505,7 +511,7 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
       else
         AQMP_LAUNCH(launch_pursuit16_bf16(c->djobs, a.lv, count, D.m, d->nfam, D.d_tab, D.d_tabT32, s));
       if (l > pp.lg_lo && pp.cap[l - 1] > 0)
-        AQMP_LAUNCH(launch_split_emit(c->djobs, a.lv, count, level_at(c, l - 1, pp.base[l - 1]), pp.ntop[l - 1],
+        AQMP_LAUNCH(launch_split_emit(c->djobs, (int32_t)c->jobs.size(), a.lv, count, level_at(c, l - 1, pp.base[l - 1]), pp.ntop[l - 1],
                                       &cnt->count[l - 1], l, pp.cap[l], wk.ss, &cnt->scan_error, s));
       if (le) AQMP_HIP(hipEventRecord(le->end, s));
       continue;
@@ -534,7 +540,7 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
       if (se) AQMP_HIP(hipEventRecord(se->c, s));
     }
     if (l > pp.lg_lo && pp.cap[l - 1] > 0)
-      AQMP_LAUNCH(launch_split_emit(c->djobs, a.lv, count, level_at(c, l - 1, pp.base[l - 1]), pp.ntop[l - 1],
+      AQMP_LAUNCH(launch_split_emit(c->djobs, (int32_t)c->jobs.size(), a.lv, count, level_at(c, l - 1, pp.base[l - 1]), pp.ntop[l - 1],
                                     &cnt->count[l - 1], l, pp.cap[l], wk.ss, &cnt->scan_error, s));
     if (le) AQMP_HIP(hipEventRecord(le->end, s));
   }

@@ -60,6 +60,11 @@ __device__ inline double job_pixel(const JobDev& jb, int y, int x) {
   return jb.dtype == AQMP_F64 ? ((const double*)jb.img)[idx] : (double)((const float*)jb.img)[idx];
 }
 
+// Host checks of one parameter set (AQMP_E_INVALID with tag + reason), and
+// the per-job table entry the kernels read for a plane and a parameter set.
+int check_params(const aqmp_params& p, const std::string& tag);
+JobDev make_jobdev(const aqmp_image& im, const aqmp_params& p);
+
 // Device-side arrays of one quadtree level (block size N = 1 << lg).  The
 // node arrays are shared by all passes; a pass owns [base, base + cap).
 struct LevelDev {
@@ -117,11 +122,15 @@ struct StepArgs {
 // Launch wrappers (defined in the kernel translation units).
 // ---------------------------------------------------------------------------
 hipError_t launch_init_counts(Counters* c, const int32_t* ntop_dev, hipStream_t s);
+// Sets n 32-bit words to zero with a fill kernel (no memset node in a graph).
+hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_gather(int n, const StepArgs& a, const int32_t* count, hipStream_t s);
 hipError_t launch_compact(const int32_t* in_list, const int32_t* in_count, const uint8_t* st,
                           int32_t* out_list, int32_t* out_count, int32_t* clear_count, int64_t cap,
                           ScanState ss, int32_t* err, hipStream_t s);
-hipError_t launch_split_emit(const JobDev* jobs, LevelDev parent, const int32_t* parent_count,
+// Split test and child emission of one level.  A node whose job index is not
+// below n_jobs is not split and sets *err.
+hipError_t launch_split_emit(const JobDev* jobs, int32_t n_jobs, LevelDev parent, const int32_t* parent_count,
                              LevelDev child, int32_t child_ntop, int32_t* child_count,
                              int32_t lg, int64_t cap, ScanState ss, int32_t* err, hipStream_t s);
 hipError_t launch_corr(int n, int precision, int variant, const void* dict_atoms, const StepArgs& a,

@@ -99,6 +99,8 @@ struct CompactOp {
 
 struct SplitOp {
   const JobDev* jobs;
+  int32_t n_jobs;
+  int32_t* bad;             // set when a node names a job outside the table
   LevelDev parent;
   const int32_t* parent_count;
   LevelDev child;
@@ -109,7 +111,12 @@ struct SplitOp {
   // Algorithm 2: refine when N > N_min and the node failed the test of its
   // split rule; the node's own atoms are then discarded by the exporter.
   __device__ int keep(int i) const {
-    const JobDev& j = jobs[parent.job[i]];
+    const int jb = parent.job[i];
+    if ((unsigned)jb >= (unsigned)n_jobs) {
+      atomicExch(bad, 1);
+      return 0;
+    }
+    const JobDev& j = jobs[jb];
     const int n = 1 << lg;
     int s = 0;
     if (n > j.n_min) {
@@ -144,6 +151,11 @@ __global__ __launch_bounds__(256) void k_split_emit(SplitOp op, ScanState ss, in
   stable_scan(op, ss, err);
 }
 
+__global__ __launch_bounds__(256) void k_zero_u32(uint32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
 __global__ void k_init_counts(Counters* c, const int32_t* ntop) {
   const int i = threadIdx.x;
   if (i < kLevels) {
@@ -161,6 +173,14 @@ hipError_t launch_init_counts(Counters* c, const int32_t* ntop_dev, hipStream_t 
   return hipGetLastError();
 }
 
+hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t b = (n + 255) / 256;
+  if (b > 1024) b = 1024;
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)b), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
 static int scan_blocks(int64_t cap) {
   int64_t b = (cap + kScanTile - 1) / kScanTile;
   return (int)(b < 1 ? 1 : b);
@@ -174,10 +194,10 @@ hipError_t launch_compact(const int32_t* in_list, const int32_t* in_count, const
   return hipGetLastError();
 }
 
-hipError_t launch_split_emit(const JobDev* jobs, LevelDev parent, const int32_t* parent_count,
+hipError_t launch_split_emit(const JobDev* jobs, int32_t n_jobs, LevelDev parent, const int32_t* parent_count,
                              LevelDev child, int32_t child_ntop, int32_t* child_count,
                              int32_t lg, int64_t cap, ScanState ss, int32_t* err, hipStream_t s) {
-  SplitOp op{jobs, parent, parent_count, child, child_ntop, child_count, lg};
+  SplitOp op{jobs, n_jobs, err, parent, parent_count, child, child_ntop, child_count, lg};
   hipLaunchKernelGGL(k_split_emit, dim3(scan_blocks(cap)), dim3(256), 0, s, op, ss, err);
   return hipGetLastError();
 }
