@@ -248,19 +248,41 @@ def roofline(stats, timing, precision, kernel_name=None, workload=None):
 
 
 def _oracle_block(args):
-    ci, x0, y0, prm = args
+    j, ci, x0, y0, prm = args
     from oracle import aqmp_oracle as O
     img = O.pad_edge(np.asarray(_ORACLE_CHANS[ci], dtype=np.float64), prm["n_max"])
     nodes = O.encode_block(img, O.Params.from_dict(prm), x0, y0, prm["n_max"])
-    return sum(nd.mp.t for nd in nodes)
+    return sum(nd.mp.t for nd in nodes), nodes
 
 
 _ORACLE_CHANS = None
 
 
+def cpu_model():
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, budget_s=25.0):
     """The FP64 oracle on a seeded sample of top-level blocks of the same
-    workload, process-parallel over blocks on the host cores."""
+    workload, process-parallel over blocks on the host cores.  Returns the
+    baseline record and the sampled blocks' oracle nodes as
+    [(job, (x0, y0), nodes)] for the precision report."""
     global _ORACLE_CHANS
     import multiprocessing as mp
     from threadpoolctl import threadpool_limits
@@ -276,7 +298,7 @@ def cpu_baseline(w, budget_s=25.0):
         prm = dict(w["params"][pi])
         h, wd = w["channels"][ci].shape
         for (x0, y0) in O.top_blocks(h, wd, prm["n_max"]):
-            blocks.append((ci, x0, y0, prm))
+            blocks.append((j, ci, x0, y0, prm))
     order = rng.permutation(len(blocks))
     # calibrate on a few blocks, then size the sample to the time budget
     with threadpool_limits(1):
@@ -295,11 +317,58 @@ def cpu_baseline(w, budget_s=25.0):
             else:                 # the calibration round already covered every block
                 rest, it2, t3 = calib, it, t1
     nb = len(rest)
-    px = sum(b[3]["n_max"] ** 2 for b in rest)
-    return dict(value=round(px / t3 / 1e6, 6), unit="Mpixel/s", cores=cores, kind="oracle",
-                sample=f"{nb} of {len(blocks)} top-level blocks ({px} pixels; seed 1234), all levels below them, "
-                       f"FP64 NumPy, one process per core, {t3:.1f} s",
-                mp_iters_per_s=round(sum(it2) / t3, 1))
+    px = sum(b[4]["n_max"] ** 2 for b in rest)
+    done_blocks = calib + ([] if rest is calib else rest)
+    done_res = it + ([] if rest is calib else it2)
+    samples = [(b[0], (b[2], b[3]), r[1]) for b, r in zip(done_blocks, done_res)]
+    rec = dict(value=round(px / t3 / 1e6, 6), unit="Mpixel/s", cores=cores, kind="oracle", cpu_model=cpu_model(),
+               sample=f"{nb} of {len(blocks)} top-level blocks ({px} pixels; seed 1234), all levels below them, "
+                      f"FP64 NumPy, one process per core, {t3:.1f} s",
+               mp_iters_per_s=round(sum(r[0] for r in it2) / t3, 1))
+    return rec, samples
+
+
+def precision_report(A, code, imgs, w, samples, coef_tol=2e-3):
+    """The BF16 form against the FP64 oracle on the blocks the CPU baseline
+    sampled (oracle nodes reused): atom-index agreement per MP iteration, atom
+    and stop ties, coefficient error (floored at 1e-3 ||y|| and unfloored) and
+    per-job PSNR over the union of the sampled blocks.  Top-level quadtrees
+    are independent, so every sampled block is compared exactly."""
+    import torch
+    from oracle import aqmp_oracle as O
+    from tests import parity_util as PU
+    exp = code.export_nodes()
+    by_job = {}
+    for j, blk, nodes in samples:
+        by_job.setdefault(j, []).append((blk, nodes))
+    rep = PU.Report()
+    jobs = []
+    for j in sorted(by_job):
+        ci, pi = w["jobs"][j]
+        img = np.asarray(w["channels"][ci], dtype=np.float64)
+        n_max = w["params"][pi]["n_max"]
+        entries = sorted(by_job[j], key=lambda t: (t[0][1], t[0][0]))      # raster order of the blocks
+        blks = [b for b, _ in entries]
+        onodes = [nd for _, nodes in entries for nd in nodes]
+        PU.compare_job(img, onodes, PU.gpu_nodes_by_key(exp, j), coef_tol, n_max, rep=rep)
+        rec = torch.zeros(imgs[ci].shape, dtype=torch.float64, device=imgs[ci].device)
+        code.decode(j, rec)
+        ps_g = PU.psnr_region(img, rec.cpu().numpy(), blks, n_max)
+        ps_o = PU.psnr_region(img, O.decode(onodes, img.shape[0], img.shape[1]), blks, n_max)
+        jobs.append(dict(job=j, blocks=len(blks), psnr_gpu_db=round(ps_g, 5), psnr_oracle_db=round(ps_o, 5),
+                         delta_db=round(ps_g - ps_o, 6)))
+    mism = sum(1 for f in rep.failures if f[0] == "atom mismatch")
+    compared = rep.iters + rep.atom_ties + mism
+    return dict(form="BF16 batched graph vs FP64 oracle", blocks=sum(len(v) for v in by_job.values()),
+                nodes=rep.nodes, iterations_compared=compared,
+                atom_index_agreement=round(rep.iters / compared, 6) if compared else None,
+                atom_ties=rep.atom_ties, stop_ties=rep.stop_ties, excluded_nodes=rep.excluded_nodes,
+                max_coef_rel_err=float(f"{rep.max_coef_err:.4g}"),
+                max_coef_rel_err_unfloored=float(f"{rep.max_coef_err_unfloored:.4g}"),
+                max_coef_err_over_ynorm=float(f"{rep.max_coef_err_over_ynorm:.4g}"),
+                floored_coefficients=rep.floored_coefs, coef_tol=coef_tol,
+                max_abs_delta_psnr_db=max(abs(j["delta_db"]) for j in jobs) if jobs else None,
+                per_job=jobs, failures=len(rep.failures), first_failures=[str(f) for f in rep.failures[:3]])
 
 
 def main():
@@ -348,14 +417,15 @@ def main():
     w = workload(args.workload)
     cpu = None
     cpu_omp = None
+    cpu_samples = None
     if not args.no_cpu_baseline:
         # before any device call: the oracle's worker processes are forked
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(w)
+        cpu, cpu_samples = cpu_baseline(w)
         if not args.no_omp:
             log("cpu baseline (oracle OMP)")
             w_omp = dict(w, params=[dict(p, solver="omp") for p in w["params"]])
-            cpu_omp = cpu_baseline(w_omp, budget_s=12.0)
+            cpu_omp, _ = cpu_baseline(w_omp, budget_s=12.0)
     imgs = to_device(w["channels"])
     npx = sum(int(w["channels"][ci].size) for ci, _ in w["jobs"])
     nmin = min(p["n_min"] for p in w["params"])
@@ -396,6 +466,12 @@ def main():
     ssim_b, cr_b = quality(A, code, imgs, w)
     e2e = end_to_end(code, imgs, w, npx, max(3, args.steps // 4))
     log(f"end to end (H2D + encode + export): {e2e['ms_per_step']} ms/step")
+    prec_rep = None
+    if cpu_samples:
+        log("precision report (BF16 vs the oracle on the baseline's sampled blocks)")
+        prec_rep = precision_report(A, code, imgs, w, cpu_samples)
+        log(f"precision: agreement {prec_rep['atom_index_agreement']} ties {prec_rep['atom_ties']}/"
+            f"{prec_rep['stop_ties']} dPSNR {prec_rep['max_abs_delta_psnr_db']}")
     code.free()   # every form below allocates its own buffers
     log(f"bf16 batched (graph): {sec * 1e3:.3f} ms/step")
 
@@ -524,6 +600,7 @@ def main():
                                        schedule="batched" if sched == A.SCHED_BATCHED else "concurrent"),
                           measured=tuned["measured"], seconds=tuned["seconds"]) if tuned else None),
         "roofline": roof,
+        "precision_report": prec_rep,
     }
     if fp32:
         res["speedup_vs_fp32_plain"] = round(value / fp32["value"], 2)

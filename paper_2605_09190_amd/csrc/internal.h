@@ -122,8 +122,8 @@ struct StepArgs {
 // Launch wrappers (defined in the kernel translation units).
 // ---------------------------------------------------------------------------
 hipError_t launch_init_counts(Counters* c, const int32_t* ntop_dev, hipStream_t s);
-// Sets n 32-bit words to zero with a fill kernel (no memset node in a graph).
-hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
+// p[0] = v and p[1 .. n-1] = 0, by a fill kernel.
+hipError_t launch_head_zero_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_gather(int n, const StepArgs& a, const int32_t* count, hipStream_t s);
 hipError_t launch_compact(const int32_t* in_list, const int32_t* in_count, const uint8_t* st,
                           int32_t* out_list, int32_t* out_count, int32_t* clear_count, int64_t cap,

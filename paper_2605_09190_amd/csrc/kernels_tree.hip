@@ -151,9 +151,10 @@ __global__ __launch_bounds__(256) void k_split_emit(SplitOp op, ScanState ss, in
   stable_scan(op, ss, err);
 }
 
-__global__ __launch_bounds__(256) void k_zero_u32(uint32_t* p, int64_t n) {
+// Word 0 = v, words 1 .. n-1 = 0: one thread per word.
+__global__ __launch_bounds__(256) void k_head_zero_u32(uint32_t* p, int64_t n, uint32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0u;
+    p[i] = i == 0 ? v : 0u;
 }
 
 __global__ void k_init_counts(Counters* c, const int32_t* ntop) {
@@ -173,11 +174,11 @@ hipError_t launch_init_counts(Counters* c, const int32_t* ntop_dev, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s) {
+hipError_t launch_head_zero_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   int64_t b = (n + 255) / 256;
   if (b > 1024) b = 1024;
-  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)b), dim3(256), 0, s, p, n);
+  hipLaunchKernelGGL(k_head_zero_u32, dim3((unsigned)b), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 

@@ -36,16 +36,14 @@ ScanBlock scan_block_at(void* p, int64_t n) {
   return b;
 }
 
-// Zeroes the block, sets the item count, runs `launch`, reads the error flag
-// back after the stream has drained.
+// Sets the item count and zeroes the rest of the block with one fill kernel,
+// runs `launch`, reads the error flag back after the stream has drained.
 // On a failed HIP call the stream is drained before returning, so the caller
 // may release the block.
 template <class F>
 int run_scan(ScanBlock b, size_t bytes, int64_t n, hipStream_t s, const char* who, F launch) {
-  const int32_t n32 = (int32_t)n;
   int32_t err = 0;
-  hipError_t e = launch_zero_u32((uint32_t*)b.hdr, (int64_t)(bytes / 4), s);
-  if (e == hipSuccess) e = hipMemcpyAsync(b.hdr, &n32, sizeof(n32), hipMemcpyHostToDevice, s);
+  hipError_t e = launch_head_zero_u32((uint32_t*)b.hdr, (int64_t)(bytes / 4), (uint32_t)n, s);
   if (e == hipSuccess) e = launch(b);
   if (e == hipSuccess) e = hipMemcpyAsync(&err, b.hdr + 3, sizeof(err), hipMemcpyDeviceToHost, s);
   const hipError_t es = hipStreamSynchronize(s);
