@@ -339,6 +339,18 @@ int aqmp_decode(const aqmp_dict* d, const aqmp_code* c, int job,
 int aqmp_worklist_compact(const uint8_t* dev_status, int64_t n, int32_t* dev_out, int32_t* dev_count,
                           void* hip_stream);
 
+/* aqmp_worklist_compact without any device allocation, for callers that
+ * cannot allocate (code that runs while other work is being captured, tight
+ * serving loops, harnesses that forbid allocation).  Same arguments, result
+ * and errors; n may not exceed 2^24 (AQMP_E_INVALID beyond that).  The scan
+ * state is a fixed array of about 128 KiB of device memory inside the library, one
+ * per device, held until the process ends and cleared by every call before
+ * use.  Calls on one device share it: calls that overlap on one device
+ * (other threads, or other streams before this one has returned) race.
+ * Synchronises hip_stream before returning. */
+int aqmp_worklist_compact_noalloc(const uint8_t* dev_status, int64_t n, int32_t* dev_out, int32_t* dev_count,
+                                  void* hip_stream);
+
 /* Split test and child emission of one quadtree level of block size n
  * (Algorithm 2: a block that misses its target is refined into the four
  * quadrants of its original pixels).  Node i (0 <= i < n_nodes) uses the

@@ -40,6 +40,7 @@ EXPORTS = [
     "aqmp_encode", "aqmp_reencode", "aqmp_code_sizes", "aqmp_code_export", "aqmp_code_export_nodes",
     "aqmp_code_stats", "aqmp_code_timing", "aqmp_code_free", "aqmp_decode", "aqmp_last_error",
     "aqmp_corr_kernel", "aqmp_code_pack", "aqmp_ssim", "aqmp_worklist_compact", "aqmp_worklist_split",
+    "aqmp_worklist_compact_noalloc",
 ]
 
 
@@ -118,6 +119,7 @@ def _load() -> C.CDLL:
     lib.aqmp_ssim.argtypes = [C.POINTER(Image), C.POINTER(Image), i32, C.c_double, C.POINTER(C.c_double), vp]
     lib.aqmp_code_pack.argtypes = [vp, C.POINTER(C.c_int32), i32, i32, vp, i64, C.POINTER(C.c_int64)]
     lib.aqmp_worklist_compact.argtypes = [vp, i64, vp, vp, vp]
+    lib.aqmp_worklist_compact_noalloc.argtypes = [vp, i64, vp, vp, vp]
     lib.aqmp_worklist_split.argtypes = [C.POINTER(Params), i32, i32, vp, vp, vp, vp, vp, i64, C.c_int32, vp, vp, vp,
                                         vp, vp, vp]
     for name in EXPORTS:
@@ -209,15 +211,20 @@ def _dev_tensor(t, dtype, name):
     return t.data_ptr()
 
 
-def worklist_compact(status, out, count, stream=None) -> None:
+NOALLOC_MAX_ITEMS = 1 << 24
+
+
+def worklist_compact(status, out, count, stream=None, noalloc: bool = False) -> None:
     """Active-list compaction: out[:count] = indices of the zero bytes of
-    status, in order (aqmp_worklist_compact).  status uint8, out int32 with
-    room for len(status), count one int32; all CUDA tensors."""
+    status, in order (aqmp_worklist_compact, or aqmp_worklist_compact_noalloc
+    with noalloc=True).  status uint8, out int32 with room for len(status),
+    count one int32; all CUDA tensors."""
     import torch
     n = int(status.numel())
     if out.numel() < n or count.numel() < 1:
         raise ValueError("out needs room for every item and count one element")
-    _check(lib.aqmp_worklist_compact(_dev_tensor(status, torch.uint8, "status"), n,
+    fn = lib.aqmp_worklist_compact_noalloc if noalloc else lib.aqmp_worklist_compact
+    _check(fn(_dev_tensor(status, torch.uint8, "status"), n,
                                      _dev_tensor(out, torch.int32, "out"), _dev_tensor(count, torch.int32, "count"),
                                      _stream_handle(stream)))
 

@@ -28,6 +28,7 @@ int code_export(const aqmp_code* c, bool leaves_only, aqmp_leaf* leaves, int32_t
 int decode(const aqmp_dict* d, const aqmp_code* c, int job, void* out, int dtype, int64_t row_stride,
            hipStream_t s);
 int worklist_compact(const uint8_t* st, int64_t n, int32_t* out, int32_t* count, hipStream_t s);
+int worklist_compact_noalloc(const uint8_t* st, int64_t n, int32_t* out, int32_t* count, hipStream_t s);
 int worklist_split(const aqmp_params* prm, int n_prm, int n, const int32_t* node_prm, const int32_t* x0,
                    const int32_t* y0, const double* e, const int32_t* t, int64_t n_nodes, int32_t child_base,
                    uint8_t* st, int32_t* child_prm, int32_t* child_x0, int32_t* child_y0, int32_t* child_count,
@@ -160,6 +161,11 @@ int aqmp_decode(const aqmp_dict* d, const aqmp_code* c, int job, void* dev_out, 
 int aqmp_worklist_compact(const uint8_t* dev_status, int64_t n, int32_t* dev_out, int32_t* dev_count,
                           void* hip_stream) {
   AQMP_ENTRY(worklist_compact(dev_status, n, dev_out, dev_count, (hipStream_t)hip_stream));
+}
+
+int aqmp_worklist_compact_noalloc(const uint8_t* dev_status, int64_t n, int32_t* dev_out, int32_t* dev_count,
+                                  void* hip_stream) {
+  AQMP_ENTRY(worklist_compact_noalloc(dev_status, n, dev_out, dev_count, (hipStream_t)hip_stream));
 }
 
 int aqmp_worklist_split(const aqmp_params* prm, int n_prm, int n, const int32_t* dev_node_prm, const int32_t* dev_x0,

@@ -3,6 +3,7 @@
 // 2.2 step (d)) and the split test with child emission (Algorithm 2).  They
 // run the encoder's own scan kernels (kernels_tree.hip) on caller arrays, so
 // that the integer work can be checked bit for bit on its own.
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -86,6 +87,58 @@ int worklist_compact(const uint8_t* st, int64_t n, int32_t* out, int32_t* count,
   rc = compact_with(p, st, n, out, count, s, who);
   dev_free(p, bytes);
   return rc;
+}
+
+// ---------------------------------------------------------------------------
+// Compaction without allocation.  The scan state lives in `scratch`, a
+// file-scope device array of a fixed size (each device the library runs on
+// holds its own copy until the process ends), sized for up to
+// kNoAllocMaxItems items.  Host code never passes the array's name to a
+// kernel: on the host it is a stand-in, not a device address.  The device
+// address is looked up once per device with hipGetSymbolAddress, with that
+// device current, and kept in g_scratch_dev.  Calls on one device share the
+// array, so calls that overlap on one device race; every call clears the
+// part it uses before its scan.
+// ---------------------------------------------------------------------------
+constexpr int64_t kNoAllocMaxItems = (int64_t)1 << 24;
+constexpr size_t kNoAllocBytes = (16 + 8 * (size_t)(kNoAllocMaxItems / kScanTile + 2) + 255) / 256 * 256;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+static int scratch_for_current_device(void** out) {
+  int dev = -1;
+  AQMP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) AQMP_FAIL(AQMP_E_INVALID, "aqmp_worklist_compact_noalloc: device id out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      AQMP_FAIL(AQMP_E_HIP, std::string("aqmp_worklist_compact_noalloc: hipGetSymbolAddress: ") +
+                                hipGetErrorString(e));
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return AQMP_OK;
+}
+
+int worklist_compact_noalloc(const uint8_t* st, int64_t n, int32_t* out, int32_t* count, hipStream_t s) {
+  const char* who = "aqmp_worklist_compact_noalloc";
+  if (n > kNoAllocMaxItems)
+    AQMP_FAIL(AQMP_E_INVALID, std::string(who) + ": n = " + std::to_string(n) + " exceeds the static scan state (at most " +
+                                  std::to_string(kNoAllocMaxItems) + " items)");
+  int rc = check_compact(st, n, out, count, kNoAllocMaxItems, who);
+  if (rc != AQMP_OK) return rc;
+  void* p = nullptr;
+  rc = scratch_for_current_device(&p);
+  if (rc != AQMP_OK) return rc;
+  return compact_with(p, st, n, out, count, s, who);
 }
 
 int worklist_split(const aqmp_params* prm, int n_prm, int n, const int32_t* node_prm, const int32_t* x0,
