@@ -78,19 +78,6 @@ __global__ __launch_bounds__(256) void k_gather(StepArgs a, const int32_t* count
   }
 }
 
-// Lane groups of the select kernel: TPN lanes (at most one wave) per node,
-// each lane owning a PH x PW patch of the block.
-template <int N>
-struct WGeo {
-  static constexpr int K = N * N;
-  static constexpr int TPN = K < 64 ? K : 64;
-  static constexpr int NPI = 64 / TPN;               // nodes per wave per iteration
-  static constexpr int PPT = K / TPN;
-  static constexpr int PH = PPT == 64 ? 8 : (PPT == 16 ? 4 : (PPT == 4 ? 2 : 1));
-  static constexpr int PW = PPT / PH;
-  static constexpr int PX = N / PW;
-};
-
 // ---------------------------------------------------------------------------
 // Select/update: one MP iteration for every active node after the
 // correlation pass has left each node's best keys per atom tile.
@@ -100,231 +87,344 @@ struct WGeo {
 //   3. i = argmax |c| (lowest atom index on ties); stop if max |c| = 0;
 //   4. r <- r - c_i phi_i (FP64 arithmetic, stored in FP32), ||r||^2 in FP64;
 //   5. record (i, c_i), t <- t + 1, stop test of eq. (2).
-// One wave per node (N >= 16); positions are walked grid-stride.  The
-// candidates' 1D table rows are staged in the wave's LDS slice with one
-// coalesced load, so nothing after the merge waits on global memory.
-// The nodes still running form the next step's active list: each wave holds
-// its survivors in registers (one per lane; the launch gives every wave at
-// most 64 positions), and after the loop the workgroup (4 or 8 waves)
+// With about one active node per SIMD at the large block sizes, the time of
+// a step is the length of one node's chain of dependent loads and FP64
+// arithmetic, so a node is split over WPN waves: wave h of a node owns rows
+// [h N / WPN, (h + 1) N / WPN) of the block, each lane a PH x PW patch.  The
+// partial candidate sums and squared norms of a node's waves meet in LDS and
+// are added in wave order, so every wave of a node sees the same totals.  A
+// workgroup holds NPG nodes; all of them take the same barriers (positions
+// past the active count take part without work).  Each wave merges the
+// node's keys itself (no barrier) with two 32-bit wave maxima per candidate
+// (high word = |c| bits, then the low word = ~atom among the lanes holding
+// that high word), the same order as the 64-bit keys.  The candidates' 1D
+// table rows a wave needs (its p-rows, all q-rows) are staged in its LDS
+// slice with one coalesced load.
+// The nodes still running form the next step's active list: the lead wave of
+// each node slot holds its survivors in registers (one per lane; the launch
+// gives a slot at most 64 positions), and after the loop the workgroup
 // appends them with a single atomic.  The list order then varies from run to
 // run; no result depends on it, since every node's arithmetic is independent
 // of its list position.
 // ---------------------------------------------------------------------------
-// Waves (nodes) per workgroup: 8 where the staging fits in LDS, so that one
-// atomic appends the survivors of 8 nodes.
+// Measured on the 2048 x 2048 x 3 encode: one wave per node is fastest at
+// every block size (two or four waves per node at N = 64 took 0.82-0.84 ms
+// per encode instead of 0.72: more barriers, redundant key merges and twice
+// the appends), and 4 (N = 64) or 8 nodes per workgroup, i.e. per append.
 template <int N>
-constexpr int sel_waves() { return N >= 64 ? 4 : 8; }
+struct SelCfg {
+  static constexpr int WPN = 1;                 // waves per node
+  static constexpr int NPG = N >= 64 ? 4 : 8;   // nodes per workgroup
+};
+
+template <int N, int WPN>
+struct SGeo {
+  static constexpr int K = N * N;
+  static constexpr int PW = N / 8;              // columns per lane
+  static constexpr int PH = N / (8 * WPN);      // rows per lane
+  static constexpr int ROWS = N / WPN;          // rows per wave
+  static_assert(PW >= 1 && PH >= 1, "at least one pixel per lane");
+  static constexpr int NKEYL = 4;               // keys per lane (<= 256 keys per node)
+  static_assert(kCand * N % 64 == 0 && kCand * ROWS % 64 == 0, "whole waves of table entries");
+};
+
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+#define AQMP_MAXSTEP32(C, RM) { const uint32_t o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, C, RM, 0xF, false); v = o > v ? o : v; }
+  AQMP_MAXSTEP32(0xB1, 0xF) AQMP_MAXSTEP32(0x4E, 0xF) AQMP_MAXSTEP32(0x141, 0xF)
+  AQMP_MAXSTEP32(0x140, 0xF) AQMP_MAXSTEP32(0x142, 0xA) AQMP_MAXSTEP32(0x143, 0xC)
+#undef AQMP_MAXSTEP32
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
 
 template <int N>
-__global__ __launch_bounds__(64 * sel_waves<N>()) void k_select(StepArgs a) {
-  constexpr int W = sel_waves<N>();
-  using G = WGeo<N>;
-  constexpr int K = G::K, TPN = G::TPN;
-  static_assert(TPN == 64, "one wave per node");
-  constexpr int KPL = 4;                   // keys per lane (<= 256 keys)
-  // per wave: rows [cand][0 = p row, 1 = q row][N] of the FP64 tables
-  __shared__ double sT[W][kCand][2][N];
+__global__ __launch_bounds__(64 * SelCfg<N>::WPN * SelCfg<N>::NPG) void k_select(StepArgs a) {
+  constexpr int WPN = SelCfg<N>::WPN, NPG = SelCfg<N>::NPG, W = WPN * NPG;
+  using G = SGeo<N, WPN>;
+  constexpr int K = G::K, PH = G::PH, PW = G::PW, KPL = G::NKEYL;
+  // per wave and candidate: the p-row over the wave's rows, the whole q-row
+  // (FP64 tables)
+  __shared__ double sP[W][kCand][G::ROWS];
+  __shared__ double sQ[W][kCand][N];
+  __shared__ double sPart[NPG][kCand][WPN];
+  __shared__ double sE[NPG][WPN];
   const int count = *a.act_count;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int slot = w / WPN, h = w % WPN;         // node slot, wave of the node
   const int lg = a.lg;
   const int nkeys = a.n_atom_tiles * kTopR;
   const double inv_n = 1.0 / N;
-  const int py = (lane / G::PX) * G::PH;
-  const int px = (lane % G::PX) * G::PW;
-  const int stride = gridDim.x * W;
-  int held = -1, n_held = 0;   // survivors of this wave, lane j holds the j-th
-  for (int pos = blockIdx.x * W + w; pos < count; pos += stride) {
-    // The keys depend only on the position: their loads go out first.
-    unsigned long long k[KPL];
-    const unsigned long long* kp = a.keys + (size_t)pos * nkeys;
-#pragma unroll
-    for (int j = 0; j < KPL; ++j) {
-      const int idx = lane + j * 64;
-      k[j] = idx < nkeys ? kp[idx] : 0ull;
-    }
-    const int node = a.act[pos];
-    const JobDev& jb = a.jobs[a.lv.job[node]];
-    const int t = a.lv.t[node];
-    float* r = a.r32 + (size_t)node * K;
-    float rv[G::PH][G::PW];
-#pragma unroll
-    for (int dy = 0; dy < G::PH; ++dy)
-#pragma unroll
-      for (int dx = 0; dx < G::PW; ++dx) rv[dy][dx] = r[(py + dy) * N + px + dx];
-
-    // 1. top kCand keys over the node's per-tile lists.
-#pragma unroll
-    for (int p0 = 0; p0 < KPL; ++p0)
-#pragma unroll
-      for (int p1 = 0; p1 < KPL - 1 - p0; ++p1)
-        if (k[p1] < k[p1 + 1]) {
-          const unsigned long long tt = k[p1];
-          k[p1] = k[p1 + 1];
-          k[p1 + 1] = tt;
-        }
+  const int ry = (lane >> 3) * PH;               // patch row inside the wave's rows
+  const int py = h * G::ROWS + ry;               // patch row inside the block
+  const int px = (lane & 7) * PW;
+  const int stride = gridDim.x * NPG;
+  typedef float f32v __attribute__((ext_vector_type(PW)));
+  int held = -1, n_held = 0;   // survivors of this slot (lead wave), lane j holds the j-th
+  // The trip count is uniform over the workgroup (barriers inside); slots past
+  // the active count take part without work.
+  for (int base = blockIdx.x * NPG; base < count; base += stride) {
+    const int pos = base + slot;
+    const bool valid = pos < count;               // uniform over the node's waves
+    int node = 0, t = 0;
     int cand[kCand];
-#pragma unroll
-    for (int rr = 0; rr < kCand; ++rr) {
-      const unsigned long long mx = wave_max_u64(k[0]);
-      if (mx != 0ull && k[0] == mx) {
-#pragma unroll
-        for (int j = 0; j < KPL - 1; ++j) k[j] = k[j + 1];
-        k[KPL - 1] = 0ull;
-      }
-      const unsigned atom = 0xFFFFFFFFu - (unsigned)(mx & 0xFFFFFFFFull);
-      cand[rr] = (mx != 0ull && atom < (unsigned)a.n_atoms) ? (int)atom : -1;
-    }
-
-    // Stage the candidates' table rows: 2 * kCand rows of N doubles, all
-    // loads issued before the first LDS write (one memory round trip).
-    constexpr int NSTG = kCand * 2 * N / 64;
-    static_assert(kCand * 2 * N % 64 == 0, "whole waves of table entries");
-    double stg[NSTG];
-#pragma unroll
-    for (int i = 0; i < NSTG; ++i) {
-      const int e = lane + 64 * i;
-      const int ci = e / (2 * N), which = (e / N) & 1, col = e % N;
-      int at = cand[0];
-#pragma unroll
-      for (int c2 = 1; c2 < kCand; ++c2)
-        if (ci == c2) at = cand[c2];
-      double v = 0.0;
-      if (at >= 0) {
-        const int f = at / K, q = (at % K) / N, p = at % N;
-        v = a.tab[(size_t)f * K + (which ? q : p) * N + col];
-      }
-      stg[i] = v;
-    }
-#pragma unroll
-    for (int i = 0; i < NSTG; ++i) {
-      const int e = lane + 64 * i;
-      sT[w][e / (2 * N)][(e / N) & 1][e % N] = stg[i];
-    }
-    __builtin_amdgcn_wave_barrier();
-
-    // 2. FP64 re-score of the candidates on this lane's patch.
+    double rv[PH][PW];
     double c[kCand];
 #pragma unroll
     for (int ci = 0; ci < kCand; ++ci) {
-      const int atom = cand[ci];
-      double part = 0.0;
-      if (atom >= 0) {
-        const int q = (atom % K) / N, p = atom % N;
-        if (p == 0 && q == 0) {
-          double s = 0.0;
+      cand[ci] = -1;
+      c[ci] = 0.0;
+    }
+    if (valid) {
+      // The keys depend only on the position: their loads go out first.
+      unsigned long long k[KPL];
+      const unsigned long long* kp = a.keys + (size_t)pos * nkeys;
 #pragma unroll
-          for (int dy = 0; dy < G::PH; ++dy)
+      for (int j = 0; j < KPL; ++j) {
+        const int idx = lane + j * 64;
+        k[j] = idx < nkeys ? kp[idx] : 0ull;
+      }
+      node = a.act[pos];
+      t = a.lv.t[node];
+      const float* r = a.r32 + (size_t)node * K;
 #pragma unroll
-            for (int dx = 0; dx < G::PW; ++dx) s += (double)rv[dy][dx];
-          part = s * inv_n;
-        } else {
+      for (int dy = 0; dy < PH; ++dy) {
+        const f32v v = *(const f32v*)(r + (py + dy) * N + px);
 #pragma unroll
-          for (int dy = 0; dy < G::PH; ++dy) {
-            double s = 0.0;
+        for (int dx = 0; dx < PW; ++dx) rv[dy][dx] = (double)v[dx];
+      }
+
+      // 1. the kCand best keys: each lane sorts its own keys, then each
+      // round takes the wave maximum of the lane heads (high word, then low
+      // word among the lanes holding that high word) and pops it.
 #pragma unroll
-            for (int dx = 0; dx < G::PW; ++dx) s = fma((double)rv[dy][dx], sT[w][ci][1][px + dx], s);
-            part = fma(sT[w][ci][0][py + dy], s, part);
+      for (int p0 = 0; p0 < KPL; ++p0)
+#pragma unroll
+        for (int p1 = 0; p1 < KPL - 1 - p0; ++p1)
+          if (k[p1] < k[p1 + 1]) {
+            const unsigned long long tt = k[p1];
+            k[p1] = k[p1 + 1];
+            k[p1 + 1] = tt;
+          }
+#pragma unroll
+      for (int rr = 0; rr < kCand; ++rr) {
+        const uint32_t hi = (uint32_t)(k[0] >> 32), lo = (uint32_t)k[0];
+        const uint32_t mhi = wave_max_u32(hi);
+        const uint32_t mlo = wave_max_u32(hi == mhi ? lo : 0u);
+        const bool nonempty = (mhi | mlo) != 0u;
+        if (nonempty && hi == mhi && lo == mlo) {
+#pragma unroll
+          for (int j = 0; j < KPL - 1; ++j) k[j] = k[j + 1];
+          k[KPL - 1] = 0ull;
+        }
+        const unsigned at = 0xFFFFFFFFu - mlo;
+        cand[rr] = (nonempty && at < (unsigned)a.n_atoms) ? (int)at : -1;
+      }
+
+      // Stage the candidates' table rows this wave needs: for every
+      // candidate its p-row over the wave's rows and its whole q-row; all
+      // loads are issued before the first LDS write (one memory round trip).
+      constexpr int NQ = kCand * N / 64, NP = kCand * G::ROWS / 64;
+      double sq[NQ], sp[NP];
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) {
+        const int e2 = lane + 64 * i, ci = e2 / N, col = e2 % N;
+        int at = -1;
+#pragma unroll
+        for (int c2 = 0; c2 < kCand; ++c2)
+          if (c2 * N <= 64 * i + 63 && (c2 + 1) * N > 64 * i && ci == c2) at = cand[c2];
+        const int f = at / K, q = (at % K) / N;
+        sq[i] = at >= 0 ? a.tab[(size_t)f * K + q * N + col] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        const int e2 = lane + 64 * i, ci = e2 / G::ROWS, col = e2 % G::ROWS;
+        int at = -1;
+#pragma unroll
+        for (int c2 = 0; c2 < kCand; ++c2)
+          if (c2 * G::ROWS <= 64 * i + 63 && (c2 + 1) * G::ROWS > 64 * i && ci == c2) at = cand[c2];
+        const int f = at / K, p = at % N;
+        sp[i] = at >= 0 ? a.tab[(size_t)f * K + p * N + h * G::ROWS + col] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) (&sQ[w][0][0])[lane + 64 * i] = sq[i];
+#pragma unroll
+      for (int i = 0; i < NP; ++i) (&sP[w][0][0])[lane + 64 * i] = sp[i];
+      __builtin_amdgcn_wave_barrier();
+
+      // 2. FP64 re-score of the candidates: this lane's patch, row sums kept
+      // apart so that the FMA chains are short, then the wave sum.
+#pragma unroll
+      for (int ci = 0; ci < kCand; ++ci) {
+        const int at = cand[ci];
+        double part = 0.0;
+        if (at >= 0) {
+          const int q = (at % K) / N, p = at % N;
+          double sr[PH];
+          if (p == 0 && q == 0) {
+#pragma unroll
+            for (int dy = 0; dy < PH; ++dy) {
+              sr[dy] = 0.0;
+#pragma unroll
+              for (int dx = 0; dx < PW; ++dx) sr[dy] += rv[dy][dx];
+            }
+#pragma unroll
+            for (int dy = 0; dy < PH; ++dy) part += sr[dy];
+            part *= inv_n;
+          } else {
+#pragma unroll
+            for (int dy = 0; dy < PH; ++dy) {
+              sr[dy] = 0.0;
+#pragma unroll
+              for (int dx = 0; dx < PW; ++dx) sr[dy] = fma(rv[dy][dx], sQ[w][ci][px + dx], sr[dy]);
+            }
+#pragma unroll
+            for (int dy = 0; dy < PH; ++dy) part = fma(sP[w][ci][ry + dy], sr[dy], part);
           }
         }
+        c[ci] = wave_sum_f64(part);
+        // one candidate at a time: keeps the scheduler from holding every
+        // candidate's table entries in registers at once
+        __builtin_amdgcn_sched_barrier(0);
       }
-      c[ci] = wave_sum_f64(part);
     }
-
-    // 3. arg-max over the re-scored candidates, lowest atom index on ties.
-    int best = -1;
-    double bmag = -1.0;
+    // the node's candidate totals (a barrier when a node spans several waves)
 #pragma unroll
     for (int ci = 0; ci < kCand; ++ci) {
-      const int atom = cand[ci];
-      if (atom < 0) continue;
-      const double m = fabs(c[ci]);
-      if (best < 0 || m > bmag || (m == bmag && atom < cand[best])) {
-        best = ci;
-        bmag = m;
+      if constexpr (WPN > 1) {
+        if (valid && lane == 0) sPart[slot][ci][h] = c[ci];
       }
     }
-    const bool zero = (best < 0 || bmag == 0.0);
-    int atom = 0, bsel = 0;
+    if constexpr (WPN > 1) {
+      __syncthreads();
+#pragma unroll
+      for (int ci = 0; ci < kCand; ++ci) {
+        double v = sPart[slot][ci][0];
+#pragma unroll
+        for (int hh = 1; hh < WPN; ++hh) v += sPart[slot][ci][hh];
+        c[ci] = v;
+      }
+    }
+    bool zero = true;
+    int atom = 0;
     double coef = 0.0;
+    double ew = 0.0;
+    if (valid) {
+      // 3. arg-max over the re-scored candidates, lowest atom index on ties.
+      int best = -1;
+      double bmag = -1.0;
 #pragma unroll
-    for (int ci = 0; ci < kCand; ++ci)
-      if (ci == best) {
-        atom = cand[ci];
-        coef = c[ci];
-        bsel = ci;
-      }
-
-    // 4. rank-1 update and the new squared norm.
-    double e = 0.0;
-    if (!zero) {
-      const int q = (atom % K) / N, p = atom % N;
-      const bool dc = (p == 0 && q == 0);
-#pragma unroll
-      for (int dy = 0; dy < G::PH; ++dy) {
-        const double ty = sT[w][bsel][0][py + dy];
-        float rn[G::PW];
-#pragma unroll
-        for (int dx = 0; dx < G::PW; ++dx) {
-          const double phi = dc ? inv_n : ty * sT[w][bsel][1][px + dx];
-          rn[dx] = (float)fma(-coef, phi, (double)rv[dy][dx]);
-          e = fma((double)rn[dx], (double)rn[dx], e);
-        }
-        const int o = (py + dy) * N + px;
-#pragma unroll
-        for (int dx = 0; dx < G::PW; ++dx) r[o + dx] = rn[dx];
-        if (a.r16) {
-          // PW BF16 values (round to nearest even) as one vector store
-          typedef __bf16 bf16v __attribute__((ext_vector_type(G::PW)));
-          bf16v pk;
-#pragma unroll
-          for (int dx = 0; dx < G::PW; ++dx) pk[dx] = (__bf16)rn[dx];
-          *(bf16v*)(a.r16 + (size_t)node * K + o) = pk;
+      for (int ci = 0; ci < kCand; ++ci) {
+        const int at = cand[ci];
+        if (at < 0) continue;
+        const double m = fabs(c[ci]);
+        if (best < 0 || m > bmag || (m == bmag && at < cand[best])) {
+          best = ci;
+          bmag = m;
         }
       }
-      e = wave_sum_f64(e);
-    }
-    __builtin_amdgcn_wave_barrier();   // table rows consumed before the next node overwrites them
+      zero = (best < 0 || bmag == 0.0);
+      int bsel = 0;
+#pragma unroll
+      for (int ci = 0; ci < kCand; ++ci)
+        if (ci == best) {
+          atom = cand[ci];
+          coef = c[ci];
+          bsel = ci;
+        }
 
-    // 5. record and stop test (a zero correlation stops without a record).
-    // Every input of the test is uniform over the wave.
-    uint8_t st = ST_ZERO;
-    if (!zero) {
-      st = ST_RUN;
-      if (e < jb.eps2[lg])
-        st = ST_ACC;
-      else if (t + 1 >= jb.k[lg])
-        st = ST_SPARSE;
-    }
-    if (lane == 0) {
+      // 4. rank-1 update of this wave's rows and their squared norm.
       if (!zero) {
-        const size_t rs = (size_t)node * a.lv.kmax + t;
-        a.lv.rec_idx[rs] = atom;
-        a.lv.rec_coef[rs] = coef;
-        a.lv.t[node] = t + 1;
-        a.lv.e[node] = e;
+        const int q = (atom % K) / N, p = atom % N;
+        const bool dc = (p == 0 && q == 0);
+        float* rw = a.r32 + (size_t)node * K;
+        double eh[PH];
+#pragma unroll
+        for (int dy = 0; dy < PH; ++dy) {
+          const double ty = sP[w][bsel][ry + dy];
+          f32v rn;
+          eh[dy] = 0.0;
+#pragma unroll
+          for (int dx = 0; dx < PW; ++dx) {
+            const double phi = dc ? inv_n : ty * sQ[w][bsel][px + dx];
+            rn[dx] = (float)fma(-coef, phi, rv[dy][dx]);
+            eh[dy] = fma((double)rn[dx], (double)rn[dx], eh[dy]);
+          }
+          const int o = (py + dy) * N + px;
+          *(f32v*)(rw + o) = rn;
+          if (a.r16) {
+            // PW BF16 values (round to nearest even) as one vector store
+            typedef __bf16 bf16v __attribute__((ext_vector_type(PW)));
+            bf16v pk;
+#pragma unroll
+            for (int dx = 0; dx < PW; ++dx) pk[dx] = (__bf16)rn[dx];
+            *(bf16v*)(a.r16 + (size_t)node * K + o) = pk;
+          }
+        }
+#pragma unroll
+        for (int dy = 0; dy < PH; ++dy) ew += eh[dy];
+        ew = wave_sum_f64(ew);
       }
-      a.lv.st[node] = st;
     }
-    if (st == ST_RUN) {
-      if (lane == n_held) held = node;
-      ++n_held;
+    // the node's squared norm (uniform: zero is uniform over the node's waves)
+    double e = 0.0;
+    if constexpr (WPN > 1) {
+      if (valid && lane == 0) sE[slot][h] = ew;
+      __syncthreads();   // also: the table rows are consumed before the next position
+      if (valid && !zero) {
+        e = sE[slot][0];
+#pragma unroll
+        for (int hh = 1; hh < WPN; ++hh) e += sE[slot][hh];
+      }
+    } else {
+      e = ew;
+      __builtin_amdgcn_wave_barrier();   // table rows consumed before the next position overwrites them
+    }
+    if (valid) {
+      // 5. record and stop test (a zero correlation stops without a record).
+      // Every input of the test is uniform over the node's waves.
+      const JobDev& jb = a.jobs[a.lv.job[node]];
+      uint8_t st = ST_ZERO;
+      if (!zero) {
+        st = ST_RUN;
+        if (e < jb.eps2[lg])
+          st = ST_ACC;
+        else if (t + 1 >= jb.k[lg])
+          st = ST_SPARSE;
+      }
+      if (h == 0) {
+        if (lane == 0) {
+          if (!zero) {
+            const size_t rs = (size_t)node * a.lv.kmax + t;
+            a.lv.rec_idx[rs] = atom;
+            a.lv.rec_coef[rs] = coef;
+            a.lv.t[node] = t + 1;
+            a.lv.e[node] = e;
+          }
+          a.lv.st[node] = st;
+        }
+        if (st == ST_RUN) {
+          if (lane == n_held) held = node;
+          ++n_held;
+        }
+      }
     }
   }
   if (a.next_act == nullptr) return;   // uniform: the level's last step
-  __shared__ int s_held[W], s_base;
-  if (lane == 0) s_held[w] = n_held;
+  __shared__ int s_held[NPG], s_base;
+  if (h == 0 && lane == 0) s_held[slot] = n_held;
   __syncthreads();
   if (tid == 0) {
     int tot = 0;
 #pragma unroll
-    for (int j = 0; j < W; ++j) tot += s_held[j];
+    for (int j = 0; j < NPG; ++j) tot += s_held[j];
     s_base = tot > 0 ? atomicAdd(a.next_count, tot) : 0;
     if (blockIdx.x == 0) *a.clear_count = 0;
   }
   __syncthreads();
-  int off = s_base;
-  for (int j = 0; j < w; ++j) off += s_held[j];
-  if (lane < n_held) a.next_act[off + lane] = held;
+  if (h == 0) {
+    int off = s_base;
+    for (int j = 0; j < slot; ++j) off += s_held[j];
+    if (lane < n_held) a.next_act[off + lane] = held;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -412,11 +512,11 @@ hipError_t launch_gather(int n, const StepArgs& a, const int32_t* count, hipStre
 
 template <int N>
 static void launch_select_n(const StepArgs& a, int64_t cap, hipStream_t s) {
-  // 4096 waves, and at most 64 positions per wave: one register per lane
-  // holds a survivor.
-  constexpr int W = sel_waves<N>();
-  int64_t g = 4096 / W;
-  if (g * W * 64 < cap) g = (cap + 64 * W - 1) / (64 * W);
+  // 4096 node slots, and at most 64 positions per slot: one register per
+  // lane of the slot's lead wave holds a survivor.
+  constexpr int NPG = SelCfg<N>::NPG, W = SelCfg<N>::WPN * NPG;
+  int64_t g = 4096 / NPG;
+  if (g * NPG * 64 < cap) g = (cap + 64 * NPG - 1) / (64 * NPG);
   hipLaunchKernelGGL(k_select<N>, dim3((unsigned)g), dim3(64 * W), 0, s, a);
 }
 

@@ -208,12 +208,12 @@ def _c1(tau=0.02):
                 jobs=[(0, 0)])
 
 
-def _c2(size=2048):
+def _c2(size=2048, tau=0.02):
     rgb = np.stack([piecewise_image(size, size, seed=s, as_f32=False) for s in (2, 3, 4)], axis=-1)
     ycc = rgb_to_ycbcr(rgb).astype(np.float32).astype(np.float64)
-    return dict(name=f"piecewise {size}x{size} RGB->YCbCr (3 jobs), blocks 64->8, k=32, rms 0.02",
+    return dict(name=f"piecewise {size}x{size} RGB->YCbCr (3 jobs), blocks 64->8, k=32, rms {tau}",
                 channels=[ycc[0], ycc[1], ycc[2]],
-                params=[dict(tol=0.02, tol_mode="rms", max_atoms=32, n_min=8, n_max=64)],
+                params=[dict(tol=tau, tol_mode="rms", max_atoms=32, n_min=8, n_max=64)],
                 jobs=[(0, 0), (1, 0), (2, 0)])
 
 
