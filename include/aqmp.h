@@ -133,11 +133,12 @@ typedef struct {
                           four groups of consecutive jobs, each group one
                           pass, captured as parallel branches of one graph
                           so that their launches overlap. */
-  int32_t flags;       /* AQMP_OPT_TIMING: record HIP events around every
-                          launch of an MP step (see aqmp_code_timing).
-                          Events cannot be timed inside a graph, so a timed
-                          batched encode issues the same launches directly
-                          on the stream.
+  int32_t flags;       /* AQMP_OPT_TIMING: time every launch of an MP step
+                          with HIP events that the dispatch itself records at
+                          the kernel's start and end (see
+                          aqmp_code_timing).  Events cannot be timed inside
+                          a graph, so a timed batched encode issues the same
+                          launches directly on the stream.
                           AQMP_OPT_STEPWISE: run the N = 16 level of the
                           BF16 form one MP step per launch (correlation
                           and select) instead of the whole-level
@@ -194,8 +195,10 @@ typedef struct {
   int64_t steps_launched;   /* MP steps issued (levels x k)                 */
 } aqmp_stats;
 
-/* Device time of the last encode, per log2(N), from HIP events recorded
- * around the launches (only with AQMP_OPT_TIMING). */
+/* Device time of the last encode, per log2(N), from HIP events (only with
+ * AQMP_OPT_TIMING): correlation and select times are kernel execution times
+ * (start and end recorded by each dispatch); level times span the level's
+ * launches on the stream. */
 typedef struct {
   double corr_ms[7];        /* correlation + top-R key launches (Gram and
                                OMP solvers, N >= 16: the initial-

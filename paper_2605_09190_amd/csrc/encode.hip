@@ -89,15 +89,16 @@ struct aqmp_code {
   int64_t steps_launched = 0;
   bool wide_residual = false;        // BF16 residual buffer of 4 GiB or more
   // Timing events (AQMP_OPT_TIMING): per level of every pass a start/end
-  // pair, per MP step three events (before the correlation, after it, after
-  // the select/update launch).
+  // pair; per MP step the start and end of the correlation (a, b) and of the
+  // select/update launch (c, d), recorded by the dispatches themselves.  The
+  // Gram and OMP solvers' levels use a, b, c around their two launches.
   struct LevelEv {
     int lg;
     hipEvent_t start, end;
   };
   struct StepEv {
     int lg;
-    hipEvent_t a, b, c;
+    hipEvent_t a, b, c, d;
   };
   std::vector<LevelEv> lev;
   std::vector<StepEv> sev;
@@ -287,7 +288,8 @@ void free_code(aqmp_code* c) {
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->done) (void)hipEventDestroy(c->done);
   for (auto& e : c->lev) (void)hipEventDestroy(e.start), (void)hipEventDestroy(e.end);
-  for (auto& e : c->sev) (void)hipEventDestroy(e.a), (void)hipEventDestroy(e.b), (void)hipEventDestroy(e.c);
+  for (auto& e : c->sev)
+    (void)hipEventDestroy(e.a), (void)hipEventDestroy(e.b), (void)hipEventDestroy(e.c), (void)hipEventDestroy(e.d);
   for (auto& a : c->allocs) dev_free(a.p, a.bytes);
   for (DevBuf* b : {&c->ex_keys, &c->ex_keys2, &c->ex_vals, &c->ex_vals2, &c->ex_tot, &c->ex_tmp, &c->ex_t,
                     &c->ex_off, &c->ex_out})
@@ -439,7 +441,7 @@ int build_plan(aqmp_code* c) {
           // Gram and OMP levels with N >= 16: one event triple around the
           // initial-correlation and pursuit launches.
           if (c->opt.solver != AQMP_SOLVER_DENSE && (1 << l) > kFusedMaxN) {
-            aqmp_code::StepEv se{l, nullptr, nullptr, nullptr};
+            aqmp_code::StepEv se{l, nullptr, nullptr, nullptr, nullptr};
             AQMP_HIP(hipEventCreate(&se.a));
             AQMP_HIP(hipEventCreate(&se.b));
             AQMP_HIP(hipEventCreate(&se.c));
@@ -448,10 +450,11 @@ int build_plan(aqmp_code* c) {
           continue;
         }
         for (int t = 0; t < pp.kmax[l]; ++t) {
-          aqmp_code::StepEv se{l, nullptr, nullptr, nullptr};
+          aqmp_code::StepEv se{l, nullptr, nullptr, nullptr, nullptr};
           AQMP_HIP(hipEventCreate(&se.a));
           AQMP_HIP(hipEventCreate(&se.b));
           AQMP_HIP(hipEventCreate(&se.c));
+          AQMP_HIP(hipEventCreate(&se.d));
           c->sev.push_back(se);
         }
       }
@@ -531,13 +534,11 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
       a.next_count = &cnt->act[(t + 1) % 3];
       a.clear_count = &cnt->act[(t + 2) % 3];
       const aqmp_code::StepEv* se = timing ? &c->sev[c->sev_pos++] : nullptr;
-      if (se) AQMP_HIP(hipEventRecord(se->a, s));
       const int lv_var = (int)((c->opt.corr_variant_levels >> (4 * l)) & 0xFu);
       const int variant = c->wide_residual ? 3 : (lv_var ? lv_var : c->opt.corr_variant);
-      AQMP_LAUNCH(launch_corr(n, c->opt.precision, variant, atoms, a, D.m_pad, s));
-      if (se) AQMP_HIP(hipEventRecord(se->b, s));
-      AQMP_LAUNCH(launch_select(n, a, pp.cap[l], s));
-      if (se) AQMP_HIP(hipEventRecord(se->c, s));
+      AQMP_LAUNCH(launch_corr(n, c->opt.precision, variant, atoms, a, D.m_pad, s, se ? se->a : nullptr,
+                              se ? se->b : nullptr));
+      AQMP_LAUNCH(launch_select(n, a, pp.cap[l], s, se ? se->c : nullptr, se ? se->d : nullptr));
     }
     if (l > pp.lg_lo && pp.cap[l - 1] > 0)
       AQMP_LAUNCH(launch_split_emit(c->djobs, (int32_t)c->jobs.size(), a.lv, count, level_at(c, l - 1, pp.base[l - 1]), pp.ntop[l - 1],
@@ -882,7 +883,7 @@ int code_timing(const aqmp_code* c, aqmp_timing* t) {
   for (const auto& e : c->sev) {
     AQMP_HIP(hipEventElapsedTime(&ms, e.a, e.b));
     t->corr_ms[e.lg] += ms;
-    AQMP_HIP(hipEventElapsedTime(&ms, e.b, e.c));
+    AQMP_HIP(hipEventElapsedTime(&ms, e.d ? e.c : e.b, e.d ? e.d : e.c));
     t->select_ms[e.lg] += ms;
     t->steps[e.lg] += 1;
   }

@@ -2,6 +2,7 @@
 // of the AQMP encoder library.  Not part of the public ABI (see aqmp.h).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -30,6 +31,16 @@ constexpr int kFusedMaxN = 8;     // levels up to this size run the fused per-no
 constexpr int kBranches = 4;      // parallel graph branches of the concurrent schedule
 constexpr int kOmpMaxAtoms = AQMP_OMP_MAX_ATOMS;   // OMP: selected atoms per node (LDS factor size)
 constexpr int kSsimMomentBlocks = 1024;   // workgroups of the whole-plane SSIM moments
+
+// Kernel launch, with start/end events recorded by the dispatch when given.
+template <typename F, typename... Args>
+inline void launch_timed(F kernel, dim3 grid, dim3 block, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                         Args... args) {
+  if (ev0 || ev1)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, ev0, ev1, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
 
 inline int ilog2(int n) {
   int l = 0;
@@ -133,9 +144,13 @@ hipError_t launch_compact(const int32_t* in_list, const int32_t* in_count, const
 hipError_t launch_split_emit(const JobDev* jobs, int32_t n_jobs, LevelDev parent, const int32_t* parent_count,
                              LevelDev child, int32_t child_ntop, int32_t* child_count,
                              int32_t lg, int64_t cap, ScanState ss, int32_t* err, hipStream_t s);
+// ev0 / ev1, when given, are recorded by the dispatch itself at the kernel's
+// start and end (hipExtLaunchKernel), so their elapsed time is the kernel's
+// execution time without the launch gap.
 hipError_t launch_corr(int n, int precision, int variant, const void* dict_atoms, const StepArgs& a,
-                       int32_t m_pad, hipStream_t s);
-hipError_t launch_select(int n, const StepArgs& a, int64_t cap, hipStream_t s);
+                       int32_t m_pad, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+hipError_t launch_select(int n, const StepArgs& a, int64_t cap, hipStream_t s, hipEvent_t ev0 = nullptr,
+                         hipEvent_t ev1 = nullptr);
 hipError_t launch_mp_fused(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t lg, int32_t n_atoms,
                            const double* tab, hipStream_t s);
 hipError_t launch_pursuit16_bf16(const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t n_atoms, int32_t nfam,

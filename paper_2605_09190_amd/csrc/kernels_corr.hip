@@ -1188,14 +1188,15 @@ int corr_grid(int, int) { return kCorrGrid; }
 //      N <= 32, so that the few nodes x atoms of the small levels still
 //      spread over every CU.
 template <int N>
-static void launch_corr_n(int precision, int variant, const void* atoms, const StepArgs& a, int nat, hipStream_t s) {
+static void launch_corr_n(int precision, int variant, const void* atoms, const StepArgs& a, int nat, hipStream_t s,
+                          hipEvent_t e0, hipEvent_t e1) {
   using CB = typename std::conditional<(N >= 16), CfgBig, typename std::conditional<(N == 8), CfgMid, CfgSmall>::type>::type;
   using CF = typename std::conditional<(N >= 16), CfgBigF, typename std::conditional<(N == 8), CfgMidF, CfgSmallF>::type>::type;
   if (variant == 0) variant = default_variant(N);
   if constexpr (N <= 32 && N >= 8) {
     if (precision == AQMP_PREC_BF16 && variant == 4) {
       using CN = typename std::conditional<(N == 8), CfgNarrow8, CfgNarrow>::type;
-      hipLaunchKernelGGL((k_corr_bf16<N, CN>), dim3(2 * kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms, a.r16,
+      launch_timed((k_corr_bf16<N, CN>), dim3(2 * kCorrGrid), dim3(256), s, e0, e1, (const uint16_t*)atoms, a.r16,
                          a.act, a.act_count, a.keys, nat);
       return;
     }
@@ -1204,26 +1205,26 @@ static void launch_corr_n(int precision, int variant, const void* atoms, const S
   if (precision == AQMP_PREC_BF16) {
     if constexpr (N >= 16) {
       if (variant == 1)
-        hipLaunchKernelGGL((k_corr_bf16_dma<N, 64, 1>), dim3(kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms,
+        launch_timed((k_corr_bf16_dma<N, 64, 1>), dim3(kCorrGrid), dim3(256), s, e0, e1, (const uint16_t*)atoms,
                            a.r16, a.act, a.act_count, a.keys, nat);
       else if (variant == 6 && N >= 32)
-        hipLaunchKernelGGL((k_corr_bf16_gen<(N >= 32 ? N : 32)>), dim3(kCorrGrid), dim3(256), 0, s, a.tabT32,
+        launch_timed((k_corr_bf16_gen<(N >= 32 ? N : 32)>), dim3(kCorrGrid), dim3(256), s, e0, e1, a.tabT32,
                            a.nfam, a.r16, a.act, a.act_count, a.keys, nat);
       else if (variant == 5)
-        hipLaunchKernelGGL((k_corr_bf16_pipe<N, 64>), dim3(kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms, a.r16,
+        launch_timed((k_corr_bf16_pipe<N, 64>), dim3(kCorrGrid), dim3(256), s, e0, e1, (const uint16_t*)atoms, a.r16,
                            a.act, a.act_count, a.keys, nat);
       else if (variant == 2)
-        hipLaunchKernelGGL((k_corr_bf16_dma<N, 32, 2>), dim3(2 * kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms,
+        launch_timed((k_corr_bf16_dma<N, 32, 2>), dim3(2 * kCorrGrid), dim3(256), s, e0, e1, (const uint16_t*)atoms,
                            a.r16, a.act, a.act_count, a.keys, nat);
       else
-        hipLaunchKernelGGL((k_corr_bf16<N, CB>), dim3(kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms, a.r16,
+        launch_timed((k_corr_bf16<N, CB>), dim3(kCorrGrid), dim3(256), s, e0, e1, (const uint16_t*)atoms, a.r16,
                            a.act, a.act_count, a.keys, nat);
     } else {
-      hipLaunchKernelGGL((k_corr_bf16<N, CB>), dim3(kCorrGrid), dim3(256), 0, s, (const uint16_t*)atoms, a.r16,
+      launch_timed((k_corr_bf16<N, CB>), dim3(kCorrGrid), dim3(256), s, e0, e1, (const uint16_t*)atoms, a.r16,
                          a.act, a.act_count, a.keys, nat);
     }
   } else {
-    hipLaunchKernelGGL((k_corr_f32<N, CF>), dim3(kCorrGrid), dim3(256), 0, s, (const float*)atoms, a.r32, a.act,
+    launch_timed((k_corr_f32<N, CF>), dim3(kCorrGrid), dim3(256), s, e0, e1, (const float*)atoms, a.r32, a.act,
                        a.act_count, a.keys, nat);
   }
 }
@@ -1251,14 +1252,14 @@ const char* corr_kernel_name(int n, int precision, int variant) {
 }
 
 hipError_t launch_corr(int n, int precision, int variant, const void* dict_atoms, const StepArgs& a,
-                       int32_t m_pad, hipStream_t s) {
+                       int32_t m_pad, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const int nat = m_pad / corr_atom_tile(n);
   switch (n) {
-    case 4: launch_corr_n<4>(precision, variant, dict_atoms, a, nat, s); break;
-    case 8: launch_corr_n<8>(precision, variant, dict_atoms, a, nat, s); break;
-    case 16: launch_corr_n<16>(precision, variant, dict_atoms, a, nat, s); break;
-    case 32: launch_corr_n<32>(precision, variant, dict_atoms, a, nat, s); break;
-    case 64: launch_corr_n<64>(precision, variant, dict_atoms, a, nat, s); break;
+    case 4: launch_corr_n<4>(precision, variant, dict_atoms, a, nat, s, ev0, ev1); break;
+    case 8: launch_corr_n<8>(precision, variant, dict_atoms, a, nat, s, ev0, ev1); break;
+    case 16: launch_corr_n<16>(precision, variant, dict_atoms, a, nat, s, ev0, ev1); break;
+    case 32: launch_corr_n<32>(precision, variant, dict_atoms, a, nat, s, ev0, ev1); break;
+    case 64: launch_corr_n<64>(precision, variant, dict_atoms, a, nat, s, ev0, ev1); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -511,20 +511,20 @@ hipError_t launch_gather(int n, const StepArgs& a, const int32_t* count, hipStre
 }
 
 template <int N>
-static void launch_select_n(const StepArgs& a, int64_t cap, hipStream_t s) {
+static void launch_select_n(const StepArgs& a, int64_t cap, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   // 4096 node slots, and at most 64 positions per slot: one register per
   // lane of the slot's lead wave holds a survivor.
   constexpr int NPG = SelCfg<N>::NPG, W = SelCfg<N>::WPN * NPG;
   int64_t g = 4096 / NPG;
   if (g * NPG * 64 < cap) g = (cap + 64 * NPG - 1) / (64 * NPG);
-  hipLaunchKernelGGL(k_select<N>, dim3((unsigned)g), dim3(64 * W), 0, s, a);
+  launch_timed(k_select<N>, dim3((unsigned)g), dim3(64 * W), s, e0, e1, a);
 }
 
-hipError_t launch_select(int n, const StepArgs& a, int64_t cap, hipStream_t s) {
+hipError_t launch_select(int n, const StepArgs& a, int64_t cap, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   switch (n) {
-    case 16: launch_select_n<16>(a, cap, s); break;
-    case 32: launch_select_n<32>(a, cap, s); break;
-    case 64: launch_select_n<64>(a, cap, s); break;
+    case 16: launch_select_n<16>(a, cap, s, ev0, ev1); break;
+    case 32: launch_select_n<32>(a, cap, s, ev0, ev1); break;
+    case 64: launch_select_n<64>(a, cap, s, ev0, ev1); break;
     default: return hipErrorInvalidValue;   // smaller levels run the fused pursuit
   }
   return hipGetLastError();
