@@ -252,13 +252,13 @@ def roofline(stats, timing, precision, kernel_name=None, workload=None):
                                           select_gbs=round(gbs, 1), select_hbm_frac=round(gbs / PEAK_HBM_GBS, 4),
                                           select_traffic=(measured_traffic(f"k_select<{nn}>", workload)
                                                           if precision == 1 else None))
-    # Levels run as one launch (N = 16 in the BF16 form: MFMA pursuit; N <= 8:
-    # dense FP64 pursuit): the whole level's time against the flops of the
-    # method's per-step correlation, 4 N^4 per node-iteration.
+    # Levels run as one launch (N = 8, 16 in the BF16 form: MFMA pursuits;
+    # otherwise N <= 8: dense FP64 pursuit): the whole level's time against
+    # the flops of the method's per-step correlation, 4 N^4 per node-iteration.
     for l in range(7):
         if stats["iters_level"][l] and timing["corr_ms"][l] == 0 and timing["level_ms"][l] > 0:
             nn = 1 << l
-            bf16 = precision == 1 and nn == 16
+            bf16 = precision == 1 and nn in (8, 16)
             pk = peak if bf16 else PEAK_FP64_TFLOPS
             a = 4.0 * nn ** 4 * stats["iters_level"][l] / (timing["level_ms"][l] * 1e-3) / 1e12
             per_level[str(nn)] = dict(kernel="whole-level pursuit", level_ms=round(timing["level_ms"][l], 3),

@@ -509,7 +509,9 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
           AQMP_LAUNCH(launch_gram_pursuit(n, c->djobs, a.lv, count, &cnt->next[l], l, d->nfam, D.d_tab, D.d_xg,
                                           wk.cbuf, s));
         if (se) AQMP_HIP(hipEventRecord(se->c, s));
-      } else if (n <= kFusedMaxN)
+      } else if (n == 8 && c->opt.precision == AQMP_PREC_BF16)
+        AQMP_LAUNCH(launch_pursuit8_bf16(c->djobs, a.lv, count, pp.cap[l], D.m, d->nfam, D.d_tab, D.d_tabT32, s));
+      else if (n <= kFusedMaxN)
         AQMP_LAUNCH(launch_mp_fused(n, c->djobs, a.lv, count, l, D.m, D.d_tab, s));
       else
         AQMP_LAUNCH(launch_pursuit16_bf16(c->djobs, a.lv, count, D.m, d->nfam, D.d_tab, D.d_tabT32, s));

@@ -1,4 +1,6 @@
-// kernels_fused.hip - whole-level Matching Pursuit for small blocks (N <= 8).
+// kernels_fused.hip - whole-level Matching Pursuit for small blocks: the dense
+// FP64 pursuit (N <= 8, the FP32 form and N = 4), and the BF16 MFMA pursuits
+// of the BF16 form at N = 8 and N = 16.
 //
 // For N <= 8 the dictionary (M <= 128 atoms of K <= 64 pixels) fits in LDS
 // even in FP64 (64 KB), while one MP step of one node is only K*M = 8192
@@ -147,6 +149,7 @@ __global__ __launch_bounds__(256) void k_mp_fused(const JobDev* __restrict__ job
 // (its correlation is still computed, its state no longer changes).
 // ---------------------------------------------------------------------------
 constexpr int kP16N = 16, kP16K = 256, kP16G = 32;   // block size, pixels, nodes per workgroup
+constexpr int kP8Nodes = 16;                          // nodes per wave of the N = 8 BF16 pursuit
 constexpr int kP16RS = kP16K + 4;                     // padded FP32 residual row (floats)
 constexpr int kP16AC = 3;                             // A tiles whose fragments stay in registers
 
@@ -538,11 +541,299 @@ __global__ __launch_bounds__(256, 1) void k_pursuit16_bf16(const JobDev* __restr
   }
 }
 
+// ---------------------------------------------------------------------------
+// Whole-level pursuit for N = 8 in the BF16 form.  One wave takes G <= 16
+// nodes through their whole pursuit (Section 2.2 steps (a)-(d), eq. (2)),
+// with no workgroup barrier: the waves of a workgroup are independent.
+// Lane l serves node l % 16 and holds rows 2 (l / 16), 2 (l / 16) + 1 of its
+// FP32 residual in registers for the whole pursuit.
+//   C  correlation of all M <= 128 atoms with the G BF16 residuals by
+//      v_mfma_f32_16x16x32_bf16 (A = 16 atoms x 32 pixels, B = 32 pixels x
+//      16 nodes, FP32 accumulation; output row 4 (l / 16) + r, column
+//      l % 16).  The BF16 atoms never change, so the wave builds all 16 A
+//      fragments (8 atom tiles x 2 pixel halves) once, in registers: atom
+//      a = 16 ma + row, family a / 64, q = (a % 64) / 8, p = a % 8, value
+//      bf16(fl32(T_f[p][y]) fl32(T_f[q][x])), constant atom exactly 1/8.  The
+//      B fragments (BF16 residual rows) go through LDS;
+//   E  each lane ranks the 32 correlations it holds of its node (4 per atom
+//      tile) as 32-bit keys (|c| bits, then 127 - atom: a larger key is a
+//      larger |c|, then the lower atom), keeps its best 8 with sorting
+//      networks and merges them with the node's other three lanes;
+//   S  FP64 re-score of the 8 candidates: each lane sums over its own 16
+//      pixels (sum_y T[p][y] sum_x r[y][x] T[q][x], the table rows read from
+//      LDS in one batch), then the node's four lanes add their partials;
+//   A  arg-max (lowest atom on ties), rank-1 update of the lane's pixels in
+//      FP64 rounded to FP32, ||r||^2 in FP64, record (i, c_i) straight to
+//      memory, stop test.
+// ---------------------------------------------------------------------------
+typedef __bf16 p8_bf16x8 __attribute__((ext_vector_type(8)));
+typedef float p8_f32x4 __attribute__((ext_vector_type(4)));
+
+// Sum over the four lanes l % 16 + 16 j of a node (a fixed order: the
+// partner 16 lanes away, then the partner 32 lanes away).
+__device__ inline double quad_sum(double v) {
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_pursuit8_bf16(const JobDev* __restrict__ jobs, LevelDev lv,
+                                                       const int32_t* __restrict__ count_ptr, int32_t n_atoms,
+                                                       int32_t nfam, const double* __restrict__ tab,
+                                                       const float* __restrict__ tabT32) {
+  constexpr int N = 8, K = 64;
+  static_assert(G >= 1 && G <= 16, "at most 16 nodes per wave (the B operand's columns)");
+  __shared__ __attribute__((aligned(16))) double sTab[2][N][N];   // [f][p][y] FP64
+  __shared__ float sT32[2][N][N];                                 // [f][y][p] FP32
+  __shared__ __attribute__((aligned(16))) uint4 sB[4][N][16];     // BF16 residual rows [wave][row][node]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int i = tid; i < nfam * K; i += 256) {
+    (&sTab[0][0][0])[i] = tab[i];
+    (&sT32[0][0][0])[i] = tabT32[i];
+  }
+  __syncthreads();
+  const int count = *count_ptr;
+  const int c = lane & 15, quad = lane >> 4;      // node column, lane group of the node
+  const int y0 = 2 * quad;                        // the lane's rows y0, y0 + 1
+  const double inv_n = 1.0 / N;
+
+  // A fragments: tile ma (16 atoms), pixel half kh (rows 4 kh .. 4 kh + 3).
+  p8_bf16x8 afr[8][2];
+#pragma unroll
+  for (int ma = 0; ma < 8; ++ma) {
+    const int a = 16 * ma + c;
+    const int f = a / K, q = (a % K) / N, p = a % N;
+    const bool ok = a < n_atoms;
+    const int ff = ok ? f : 0;
+#pragma unroll
+    for (int kh = 0; kh < 2; ++kh) {
+      const int y = 4 * kh + quad;
+      const float tpy = sT32[ff][y][p];
+      p8_bf16x8 v;
+#pragma unroll
+      for (int x = 0; x < N; ++x) {
+        const float prod = (p == 0 && q == 0) ? 0.125f : tpy * sT32[ff][x][q];
+        v[x] = (__bf16)(ok ? prod : 0.f);
+      }
+      afr[ma][kh] = v;
+    }
+  }
+  // atom of accumulator element r of tile ma: 16 ma + 4 quad + r
+  const uint32_t kb = 127u - (uint32_t)(4 * quad);
+
+  const int ngroups = (count + G - 1) / G;
+  for (int grp = blockIdx.x * 4 + w; grp < ngroups; grp += gridDim.x * 4) {
+    const int g0 = grp * G;
+    const int node = g0 + c;
+    const bool mine = c < G && node < count;      // a real node behind this lane's column
+    // ---- gather (Algorithm 2: y = unravel(b)), the lane's two rows ----
+    float rr[2][N];
+    double eps2 = 0.0, e = 0.0;
+    int kmax = 0, t = 0;
+    uint8_t st = ST_SPARSE;
+    {
+      const int nd = mine ? node : g0;
+      const JobDev& jb = jobs[lv.job[nd]];
+      const int bx = lv.x0[nd], by = lv.y0[nd];
+      double ep = 0.0;
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy) {
+        p8_bf16x8 b;
+#pragma unroll
+        for (int x = 0; x < N; ++x) {
+          const double v = mine ? job_pixel(jb, by + y0 + dy, bx + x) : 0.0;
+          rr[dy][x] = (float)v;
+          ep += v * v;
+          b[x] = (__bf16)rr[dy][x];
+        }
+        sB[w][y0 + dy][c] = __builtin_bit_cast(uint4, b);
+      }
+      e = quad_sum(ep);
+      eps2 = jb.eps2[3];
+      kmax = jb.k[3];
+      if (mine) st = e < eps2 ? ST_ACC : (kmax <= 0 ? ST_SPARSE : ST_RUN);
+    }
+    wave_sync();
+    while (__ballot(st == ST_RUN) != 0ull) {
+      // ---- C: correlation of every atom with the G residuals ----
+      p8_f32x4 acc[8];
+#pragma unroll
+      for (int ma = 0; ma < 8; ++ma) acc[ma] = p8_f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kh = 0; kh < 2; ++kh) {
+        const p8_bf16x8 bf = __builtin_bit_cast(p8_bf16x8, sB[w][4 * kh + quad][c]);
+#pragma unroll
+        for (int ma = 0; ma < 8; ++ma)
+          acc[ma] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[ma][kh], bf, acc[ma], 0, 0, 0);
+      }
+      // ---- E: the node's best 8 keys ----
+      uint32_t top[8];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        uint32_t v[8];
+#pragma unroll
+        for (int e8 = 0; e8 < 8; ++e8) {
+          const int ma = 2 * g + (e8 >> 2), r = e8 & 3;
+          const uint32_t bits = __float_as_uint(acc[ma][r]) & 0x7FFFFF80u;
+          const uint32_t atom_low = kb - (uint32_t)(16 * ma + r);     // 127 - atom
+          v[e8] = (16 * ma + 4 * quad + r < n_atoms) ? (bits | atom_low) : 0u;
+        }
+        p16_sort8(v);
+        if (g == 0) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) top[j] = v[j];
+        } else {
+          p16_merge8(top, v);
+        }
+      }
+#pragma unroll
+      for (int sh = 16; sh <= 32; sh <<= 1) {
+        uint32_t o[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) o[j] = __shfl_xor(top[j], sh, 64);
+        p16_merge8(top, o);
+      }
+      // ---- S: FP64 re-score of the 8 candidates on the lane's 16 pixels ----
+      double rd[2][N];
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int x = 0; x < N; ++x) rd[dy][x] = (double)rr[dy][x];
+      int cand[8];
+      double cv[8];
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        // table rows of four candidates, read before any arithmetic
+        double tq[4][N], tp[4][2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int j = 4 * half + i;
+          const int at = top[j] != 0u ? (int)(127u - (top[j] & 0x7Fu)) : -1;
+          cand[j] = at;
+          const int aa = at < 0 ? 0 : at;
+          const int f = aa / K, q = (aa % K) / N, p = aa % N;
+          const double2* qr = (const double2*)&sTab[f][q][0];
+#pragma unroll
+          for (int x2 = 0; x2 < N / 2; ++x2) {
+            const double2 u = qr[x2];
+            tq[i][2 * x2] = u.x;
+            tq[i][2 * x2 + 1] = u.y;
+          }
+          const double2 pr = *(const double2*)&sTab[f][p][y0];
+          tp[i][0] = pr.x;
+          tp[i][1] = pr.y;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int j = 4 * half + i;
+          const int aa = cand[j] < 0 ? 0 : cand[j];
+          const bool dc = (aa % K) == 0;            // p = q = 0: the constant atom
+          double part = 0.0;
+#pragma unroll
+          for (int dy = 0; dy < 2; ++dy) {
+            double sx = 0.0;
+#pragma unroll
+            for (int x = 0; x < N; ++x) sx = fma(rd[dy][x], dc ? 1.0 : tq[i][x], sx);
+            part = dc ? part + sx : fma(tp[i][dy], sx, part);
+          }
+          cv[j] = dc ? part * inv_n : part;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) cv[j] = quad_sum(cv[j]);
+      // ---- A: arg-max (lowest atom on ties), update, norm, record, stop ----
+      int best = -1;
+      double bmag = -1.0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const double m = fabs(cv[j]);
+        const bool better = cand[j] >= 0 && (best < 0 || m > bmag || (m == bmag && cand[j] < cand[best < 0 ? 0 : best]));
+        if (better) {
+          best = j;
+          bmag = m;
+        }
+      }
+      const bool zero = best < 0 || bmag == 0.0;
+      int atom = 0;
+      double coef = 0.0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (j == best) {
+          atom = cand[j];
+          coef = cv[j];
+        }
+      const bool run = st == ST_RUN;
+      double en = 0.0;
+      if (run && !zero) {
+        const int f = atom / K, q = (atom % K) / N, p = atom % N;
+        const bool dc = (p == 0 && q == 0);
+        double tqx[N];
+        const double2* qr = (const double2*)&sTab[f][q][0];
+#pragma unroll
+        for (int x2 = 0; x2 < N / 2; ++x2) {
+          const double2 u = qr[x2];
+          tqx[2 * x2] = u.x;
+          tqx[2 * x2 + 1] = u.y;
+        }
+        const double2 pr = *(const double2*)&sTab[f][p][y0];
+        const double tpy[2] = {pr.x, pr.y};
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+          p8_bf16x8 b;
+#pragma unroll
+          for (int x = 0; x < N; ++x) {
+            const double phi = dc ? inv_n : tpy[dy] * tqx[x];
+            rr[dy][x] = (float)fma(-coef, phi, rd[dy][x]);
+            en = fma((double)rr[dy][x], (double)rr[dy][x], en);
+            b[x] = (__bf16)rr[dy][x];
+          }
+          sB[w][y0 + dy][c] = __builtin_bit_cast(uint4, b);
+        }
+      }
+      en = quad_sum(en);
+      if (run) {
+        if (zero) {
+          st = ST_ZERO;
+        } else {
+          if (quad == 0) {
+            const size_t slot = (size_t)node * lv.kmax + t;
+            lv.rec_idx[slot] = atom;
+            lv.rec_coef[slot] = coef;
+          }
+          e = en;
+          ++t;
+          st = e < eps2 ? ST_ACC : (t >= kmax ? ST_SPARSE : ST_RUN);
+        }
+      }
+      wave_sync();   // the new BF16 rows are in LDS before the next correlation reads them
+    }
+    if (mine && quad == 0) {
+      lv.e[node] = e;
+      lv.t[node] = t;
+      lv.st[node] = st;
+    }
+    wave_sync();   // the next group overwrites this group's rows
+  }
+}
+
 }  // namespace
 
 hipError_t launch_pursuit16_bf16(const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t n_atoms, int32_t nfam,
                                  const double* tab, const float* tabT32, hipStream_t s) {
   hipLaunchKernelGGL(k_pursuit16_bf16, dim3(512), dim3(256), 0, s, jobs, lv, count, 4, n_atoms, nfam, tab, tabT32);
+  return hipGetLastError();
+}
+
+hipError_t launch_pursuit8_bf16(const JobDev* jobs, LevelDev lv, const int32_t* count, int64_t cap, int32_t n_atoms,
+                                int32_t nfam, const double* tab, const float* tabT32, hipStream_t s) {
+  constexpr int G = kP8Nodes;
+  int64_t groups = (cap + G - 1) / G;
+  int64_t wgs = (groups + 3) / 4;
+  if (wgs > 4096) wgs = 4096;
+  if (wgs < 1) wgs = 1;
+  hipLaunchKernelGGL(k_pursuit8_bf16<G>, dim3((unsigned)wgs), dim3(256), 0, s, jobs, lv, count, n_atoms, nfam, tab,
+                     tabT32);
   return hipGetLastError();
 }
 

@@ -104,7 +104,9 @@ def test_corr_kernel_names():
     assert A.corr_kernel(16, A.PREC_BF16) == "k_corr_bf16_dma<16,32,2>"
     assert A.corr_kernel(64, A.PREC_BF16, 5) == "k_corr_bf16_pipe<64,64>"
     assert A.corr_kernel(64, A.PREC_FP32) == "k_corr_f32<64>"
-    assert A.corr_kernel(8, A.PREC_BF16) == "k_mp_fused<8>"
+    assert A.corr_kernel(8, A.PREC_BF16) == "k_pursuit8_bf16<16>"
+    assert A.corr_kernel(8, A.PREC_FP32) == "k_mp_fused<8>"
+    assert A.corr_kernel(4, A.PREC_BF16) == "k_mp_fused<4>"
     assert A.corr_kernel(4, A.PREC_FP32) == "k_mp_fused<4>"
     assert A.corr_kernel(48, A.PREC_BF16) == ""
     assert A.corr_kernel(128, A.PREC_BF16) == ""
