@@ -172,6 +172,30 @@ def quality(A, code, imgs, w):
 
 
 PEAK_FP64_TFLOPS = 78.6       # MI355X FP64 (matrix and vector)
+QUANT_STEPS_PER_TAU = (0.0, 0.5, 1.0, 2.0, 4.0)   # coefficient quantiser steps, in units of the RMS tolerance
+
+
+def rate_distortion(A, code, imgs, w, steps_per_tau=QUANT_STEPS_PER_TAU):
+    """Compression rate of the DEFLATE-compressed stream (all jobs of an
+    image as its channels) and PSNR per job of the decode of that stream, for
+    coefficient quantiser steps d = s * tau (s = 0: binary32 coefficients,
+    the unquantised stream)."""
+    import torch
+    tau = w["params"][0]["tol"]
+    jobs = list(range(len(w["jobs"])))
+    orig = sum(int(w["channels"][w["jobs"][j][0]].size) for j in jobs)
+    out = []
+    for sp in steps_per_tau:
+        step = sp * tau
+        size = len(code.pack(jobs, level=9, step=step))
+        ps = []
+        for j, (ci, _) in enumerate(w["jobs"]):
+            rec = torch.zeros_like(imgs[ci], dtype=torch.float64)
+            code.decode(j, rec, step=step)
+            d = rec - imgs[ci].to(torch.float64)
+            ps.append(round(10.0 * float(np.log10(1.0 / float((d * d).mean()))), 4))
+        out.append(dict(step=step, step_per_tau=sp, bytes=size, cr=round(orig / size, 3), psnr_db=ps))
+    return out
 
 
 def solver_roofline(A, dic, imgs, w, solver, sched, steps, warmup):
@@ -540,6 +564,7 @@ def main():
     stats = code.stats()
     psnr_b = psnr_jobs(code, imgs, w["jobs"])
     ssim_b, cr_b = quality(A, code, imgs, w)
+    rd_b = rate_distortion(A, code, imgs, w) if len({p["tol"] for p in w["params"]}) == 1 else None
     e2e = end_to_end(code, imgs, w, npx, max(3, args.steps // 4))
     log(f"end to end (H2D + encode + export): {e2e['ms_per_step']} ms/step")
     prec_rep = None
@@ -635,6 +660,13 @@ def main():
         codeo.free()
         log(f"omp fp64 batched (graph): {seco * 1e3:.3f} ms/step")
 
+    rd_c1 = None
+    if args.workload == "c3":
+        w1 = workload("c1")
+        imgs1 = to_device(w1["channels"])
+        code1 = A.Code(dic, imgs1, w1["params"], w1["jobs"], precision=A.PREC_BF16, schedule=A.SCHED_BATCHED)
+        rd_c1 = dict(workload=w1["name"], points=rate_distortion(A, code1, imgs1, w1))
+        code1.free()
     sweep_res = None
     if not args.no_sweep and args.workload == "c3":
         # the paper's search space encoded together: 16 images x 32 trials
@@ -688,6 +720,10 @@ def main():
         "psnr_db": [round(p, 4) for p in psnr_b],
         "ssim_window7": ssim_b,
         "cr": cr_b,
+        "rate_distortion": dict(workload=w["name"], points=rd_b,
+                                form="coefficient format 1: q = round-half-even(c / d), d = step in binary32; "
+                                     "CR of the DEFLATE stream (8-bit original), PSNR of its decode"),
+        "rate_distortion_c1": rd_c1,
         "fp32_plain": fp32,
         "gram_fp64": gram,
         "omp_fp64": omp,

@@ -294,8 +294,9 @@ int aqmp_ssim(const aqmp_image* x, const aqmp_image* y, int mode, double data_ra
  * block range), into the AQMP bitstream and compresses it with DEFLATE
  * (zlib compress2 at `level` 0..9; -1 leaves the stream uncompressed).
  * Format (version 1, little-endian): header "AQMP", u8 version, u8
- * families, u8 coefficient format (0 = binary32), u8 channels, u32 width,
- * u32 height, u8 log2 N_min, u8 log2 N_max, u8 bytes per atom count, u8 0;
+ * families, u8 coefficient format (0 = binary32; 1 = quantised, see
+ * aqmp_code_pack_quantized), u8 channels, u32 width, u32 height, u8 log2
+ * N_min, u8 log2 N_max, u8 bytes per atom count, u8 0 (format 0);
  * then per channel, nodes in depth-first order (top-level blocks in raster
  * order over the padded plane, children TL, TR, BL, BR): u32 nodes, u32
  * leaves, u32 atoms, the split flags of the nodes with N > N_min (one bit
@@ -308,6 +309,20 @@ int aqmp_ssim(const aqmp_image* x, const aqmp_image* y, int mode, double data_ra
  * not fit.  Synchronises the encode stream. */
 int aqmp_code_pack(const aqmp_code* c, const int32_t* jobs, int n_jobs, int level,
                    uint8_t* out, int64_t capacity, int64_t* size_out);
+
+/* aqmp_code_pack with the coefficients quantised (coefficient format 1):
+ * the lossy part of encoder step (ii), Section 2.3, which the paper does not
+ * specify; this uniform scalar quantiser is the library's reading.  With d
+ * the step rounded to binary32, each coefficient c is stored as the integer
+ * q = round-half-to-even(c / d), computed in FP64; the decoder's value is
+ * q * d, within d / 2 of c.  Format 1 differs from format 0 in: the
+ * coefficient format byte is 1, the header's last byte is the integer width
+ * (2 when every |q| <= 32767, else 4), the binary32 step d follows the
+ * 20-byte header, and the coefficients are signed little-endian integers of
+ * that width.  step > 0, finite; AQMP_E_INVALID if a |q| exceeds 2^31 - 1.
+ * step = 0 gives exactly aqmp_code_pack's stream. */
+int aqmp_code_pack_quantized(const aqmp_code* c, const int32_t* jobs, int n_jobs, int level, double step,
+                             uint8_t* out, int64_t capacity, int64_t* size_out);
 
 /* Synchronises the encode stream and sums the per-launch event times of the
  * last encode or re-encode.  AQMP_E_INVALID if the code was not made with
@@ -326,6 +341,13 @@ void aqmp_code_free(aqmp_code* c);
  * Stream-ordered on hip_stream, after the encode's stream work. */
 int aqmp_decode(const aqmp_dict* d, const aqmp_code* c, int job,
                 void* dev_out, int dtype, int64_t row_stride, void* hip_stream);
+
+/* aqmp_decode with every coefficient replaced by its quantised value q * d
+ * (d = step rounded to binary32, q as in aqmp_code_pack_quantized): the
+ * image a decoder of the format 1 stream reconstructs.  step > 0, finite;
+ * step = 0 is aqmp_decode. */
+int aqmp_decode_quantized(const aqmp_dict* d, const aqmp_code* c, int job, double step, void* dev_out, int dtype,
+                          int64_t row_stride, void* hip_stream);
 
 /* ---- the integer worklist steps on their own ----------------------------
  * The encoder's active-list compaction and split/emit kernels, applied to

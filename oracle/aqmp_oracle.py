@@ -404,26 +404,56 @@ def decode(nodes: list[Node], h: int, w: int, families: int = DCT | HAAR) -> np.
 # writes (version 1, little-endian, described in its public header).
 # ---------------------------------------------------------------------------
 
+def quantize(coef, step: float) -> np.ndarray:
+    """Uniform scalar quantiser of the coefficients (the lossy part of encoder
+    step (ii), Section 2.3; the paper names no quantiser, this one is stated
+    by the stream format): q = round-half-to-even(c / d), with d the step
+    rounded to binary32 (the value the stream stores), computed in FP64.  The
+    decoder reconstructs q * d."""
+    d = float(np.float32(step))
+    if not d > 0.0:
+        raise ValueError("the quantiser step must be positive")
+    return np.rint(np.asarray(coef, dtype=np.float64) / d).astype(np.int64)
+
+
+def dequantize(q, step: float) -> np.ndarray:
+    return np.asarray(q, dtype=np.float64) * float(np.float32(step))
+
+
 def pack_stream(channels: Sequence[list], w: int, h: int, n_min: int, n_max: int,
-                families: int = DCT | HAAR) -> bytes:
+                families: int = DCT | HAAR, step: float | None = None) -> bytes:
     """The uncompressed bitstream of one image: a header, then per channel
     (each a node list in depth-first order as ``encode_channel`` returns it)
     the split flags of the nodes with N > N_min, the leaves' atom counts,
-    their atom indices (u16) and coefficients (binary32)."""
+    their atom indices (u16) and coefficients: binary32 (coefficient format
+    0), or with ``step`` (format 1) the quantised values q of ``quantize`` as
+    signed little-endian integers of the header's width (2 bytes when every
+    |q| <= 32767, else 4), the binary32 step following the 20-byte header."""
     import struct
     counts = [nd.mp.t for nodes in channels for nd in nodes if not nd.split]
     cb = 2 if counts and max(counts) > 255 else 1
+    qs = None
+    qb = 0
+    if step is not None:
+        qs = [quantize([c for nd in nodes if not nd.split for c in nd.mp.coef], step) for nodes in channels]
+        big = max([int(np.max(np.abs(q))) for q in qs if q.size] + [0])
+        qb = 2 if big <= 32767 else 4
     out = bytearray(b"AQMP")
-    out += struct.pack("<BBBBIIBBBB", 1, families, 0, len(channels), w, h,
-                       n_min.bit_length() - 1, n_max.bit_length() - 1, cb, 0)
-    for nodes in channels:
+    out += struct.pack("<BBBBIIBBBB", 1, families, 0 if step is None else 1, len(channels), w, h,
+                       n_min.bit_length() - 1, n_max.bit_length() - 1, cb, qb)
+    if step is not None:
+        out += struct.pack("<f", float(np.float32(step)))
+    for ci, nodes in enumerate(channels):
         lv = [nd for nd in nodes if not nd.split]
         out += struct.pack("<III", len(nodes), len(lv), sum(nd.mp.t for nd in lv))
         bits = np.array([1 if nd.split else 0 for nd in nodes if nd.n > n_min], dtype=np.uint8)
         out += np.packbits(bits, bitorder="little").tobytes()
         out += np.array([nd.mp.t for nd in lv], dtype="<u1" if cb == 1 else "<u2").tobytes()
         out += np.array([i for nd in lv for i in nd.mp.idx], dtype="<u2").tobytes()
-        out += np.array([c for nd in lv for c in nd.mp.coef], dtype="<f4").tobytes()
+        if step is None:
+            out += np.array([c for nd in lv for c in nd.mp.coef], dtype="<f4").tobytes()
+        else:
+            out += qs[ci].astype("<i2" if qb == 2 else "<i4").tobytes()
     return bytes(out)
 
 
@@ -433,10 +463,15 @@ def unpack_stream(data: bytes) -> dict:
     walking the quadtree with the split flags."""
     import struct
     assert data[:4] == b"AQMP"
-    ver, fam, fmt, nch, w, h, lmin, lmax, cb, _ = struct.unpack_from("<BBBBIIBBBB", data, 4)
-    assert ver == 1 and fmt == 0
+    ver, fam, fmt, nch, w, h, lmin, lmax, cb, qb = struct.unpack_from("<BBBBIIBBBB", data, 4)
+    assert ver == 1 and fmt in (0, 1)
     n_min, n_max = 1 << lmin, 1 << lmax
     pos = 20
+    step = None
+    if fmt == 1:
+        assert qb in (2, 4)
+        step = float(struct.unpack_from("<f", data, pos)[0])
+        pos += 4
     chans = []
     for _ in range(nch):
         n_nodes, n_leaves, n_atoms = struct.unpack_from("<III", data, pos)
@@ -467,13 +502,18 @@ def unpack_stream(data: bytes) -> dict:
         pos += cb * n_leaves
         idx = np.frombuffer(data, dtype="<u2", count=n_atoms, offset=pos).astype(int)
         pos += 2 * n_atoms
-        coef = np.frombuffer(data, dtype="<f4", count=n_atoms, offset=pos).astype(np.float64)
-        pos += 4 * n_atoms
+        if fmt == 0:
+            coef = np.frombuffer(data, dtype="<f4", count=n_atoms, offset=pos).astype(np.float64)
+            pos += 4 * n_atoms
+        else:
+            q = np.frombuffer(data, dtype="<i2" if qb == 2 else "<i4", count=n_atoms, offset=pos)
+            coef = q.astype(np.float64) * step
+            pos += qb * n_atoms
         off = np.concatenate([[0], np.cumsum(cnt)])
         chans.append([(x0, y0, n, idx[off[i]:off[i + 1]].tolist(), coef[off[i]:off[i + 1]].tolist())
                       for i, (x0, y0, n) in enumerate(shape)])
     assert pos == len(data)
-    return dict(families=fam, w=w, h=h, n_min=n_min, n_max=n_max, channels=chans)
+    return dict(families=fam, w=w, h=h, n_min=n_min, n_max=n_max, channels=chans, step=step)
 
 
 def compress_stream(raw: bytes, level: int = 9) -> bytes:

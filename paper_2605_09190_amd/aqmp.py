@@ -40,7 +40,7 @@ EXPORTS = [
     "aqmp_encode", "aqmp_reencode", "aqmp_code_sizes", "aqmp_code_export", "aqmp_code_export_nodes",
     "aqmp_code_stats", "aqmp_code_timing", "aqmp_code_free", "aqmp_decode", "aqmp_last_error",
     "aqmp_corr_kernel", "aqmp_code_pack", "aqmp_ssim", "aqmp_worklist_compact", "aqmp_worklist_split",
-    "aqmp_worklist_compact_noalloc",
+    "aqmp_worklist_compact_noalloc", "aqmp_code_pack_quantized", "aqmp_decode_quantized",
 ]
 
 
@@ -118,6 +118,9 @@ def _load() -> C.CDLL:
     lib.aqmp_corr_kernel.restype = C.c_char_p
     lib.aqmp_ssim.argtypes = [C.POINTER(Image), C.POINTER(Image), i32, C.c_double, C.POINTER(C.c_double), vp]
     lib.aqmp_code_pack.argtypes = [vp, C.POINTER(C.c_int32), i32, i32, vp, i64, C.POINTER(C.c_int64)]
+    lib.aqmp_code_pack_quantized.argtypes = [vp, C.POINTER(C.c_int32), i32, i32, C.c_double, vp, i64,
+                                             C.POINTER(C.c_int64)]
+    lib.aqmp_decode_quantized.argtypes = [vp, vp, i32, C.c_double, vp, i32, i64, vp]
     lib.aqmp_worklist_compact.argtypes = [vp, i64, vp, vp, vp]
     lib.aqmp_worklist_compact_noalloc.argtypes = [vp, i64, vp, vp, vp]
     lib.aqmp_worklist_split.argtypes = [C.POINTER(Params), i32, i32, vp, vp, vp, vp, vp, i64, C.c_int32, vp, vp, vp,
@@ -350,23 +353,26 @@ class Code:
         n_leaves, n_atoms = self.sizes()
         return self._export(lib.aqmp_code_export, n_leaves, n_atoms)
 
-    def pack(self, jobs, level: int = 9) -> bytes:
+    def pack(self, jobs, level: int = 9, step: float = 0.0) -> bytes:
         """The AQMP bitstream of the given jobs (the channels of one image),
-        DEFLATE-compressed at `level` (0..9) or raw (-1)."""
+        DEFLATE-compressed at `level` (0..9) or raw (-1); step > 0 quantises
+        the coefficients (coefficient format 1)."""
         arr = (C.c_int32 * len(jobs))(*[int(j) for j in jobs])
         size = C.c_int64()
-        _check(lib.aqmp_code_pack(self.h, arr, len(jobs), int(level), None, 0, C.byref(size)))
+        st = C.c_double(float(step))
+        _check(lib.aqmp_code_pack_quantized(self.h, arr, len(jobs), int(level), st, None, 0, C.byref(size)))
         buf = (C.c_uint8 * max(1, size.value))()
-        _check(lib.aqmp_code_pack(self.h, arr, len(jobs), int(level), buf, size.value, C.byref(size)))
+        _check(lib.aqmp_code_pack_quantized(self.h, arr, len(jobs), int(level), st, buf, size.value, C.byref(size)))
         return bytes(buf[:size.value])
 
     def export_nodes(self) -> Export:
         s = self.stats()
         return self._export(lib.aqmp_code_export_nodes, int(sum(s["nodes"])), int(s["iters_executed"]))
 
-    def decode(self, job: int, out, stream=None) -> None:
+    def decode(self, job: int, out, stream=None, step: float = 0.0) -> None:
         """Writes job's reconstruction into out (a 2D float32 or float64 CUDA
-        tensor on the code's device, at least as large as the job's plane)."""
+        tensor on the code's device, at least as large as the job's plane);
+        step > 0 decodes the quantised coefficients of a format 1 stream."""
         import torch
         if not 0 <= int(job) < self.n_jobs:
             raise ValueError(f"job {job} out of range (0..{self.n_jobs - 1})")
@@ -380,8 +386,8 @@ class Code:
         if out.device != self._keep[0].device:
             raise ValueError(f"out is on {out.device}; the code is on {self._keep[0].device}")
         dt = F32 if out.dtype == torch.float32 else F64
-        _check(lib.aqmp_decode(self.dic.h, self.h, job, out.data_ptr(), dt, int(out.stride(0)),
-                               _stream_handle(stream)))
+        _check(lib.aqmp_decode_quantized(self.dic.h, self.h, job, float(step), out.data_ptr(), dt,
+                                         int(out.stride(0)), _stream_handle(stream)))
 
     def free(self) -> None:
         if self.h:

@@ -21,11 +21,11 @@ void code_free(aqmp_code* c);
 int code_stats(const aqmp_code* c, aqmp_stats* s);
 int code_timing(const aqmp_code* c, aqmp_timing* t);
 int code_sizes(const aqmp_code* c, int64_t* n_leaves, int64_t* n_atoms);
-int code_pack(const aqmp_code* c, const int32_t* jobs, int n_jobs, int level, uint8_t* out, int64_t capacity,
-              int64_t* size_out);
+int code_pack(const aqmp_code* c, const int32_t* jobs, int n_jobs, int level, double step, uint8_t* out,
+              int64_t capacity, int64_t* size_out);
 int code_export(const aqmp_code* c, bool leaves_only, aqmp_leaf* leaves, int32_t* atom_idx, double* coef,
                 int64_t cap_leaves, int64_t cap_atoms);
-int decode(const aqmp_dict* d, const aqmp_code* c, int job, void* out, int dtype, int64_t row_stride,
+int decode(const aqmp_dict* d, const aqmp_code* c, int job, double step, void* out, int dtype, int64_t row_stride,
            hipStream_t s);
 int worklist_compact(const uint8_t* st, int64_t n, int32_t* out, int32_t* count, hipStream_t s);
 int worklist_compact_noalloc(const uint8_t* st, int64_t n, int32_t* out, int32_t* count, hipStream_t s);
@@ -134,7 +134,12 @@ int aqmp_ssim(const aqmp_image* x, const aqmp_image* y, int mode, double data_ra
 
 int aqmp_code_pack(const aqmp_code* c, const int32_t* jobs, int n_jobs, int level, uint8_t* out, int64_t capacity,
                    int64_t* size_out) {
-  AQMP_ENTRY(code_pack(c, jobs, n_jobs, level, out, capacity, size_out));
+  AQMP_ENTRY(code_pack(c, jobs, n_jobs, level, 0.0, out, capacity, size_out));
+}
+
+int aqmp_code_pack_quantized(const aqmp_code* c, const int32_t* jobs, int n_jobs, int level, double step,
+                             uint8_t* out, int64_t capacity, int64_t* size_out) {
+  AQMP_ENTRY(code_pack(c, jobs, n_jobs, level, step, out, capacity, size_out));
 }
 
 int aqmp_code_export_nodes(const aqmp_code* c, aqmp_leaf* nodes, int32_t* atom_idx, double* coef, int64_t cap_nodes,
@@ -155,7 +160,12 @@ void aqmp_code_free(aqmp_code* c) {
 
 int aqmp_decode(const aqmp_dict* d, const aqmp_code* c, int job, void* dev_out, int dtype, int64_t row_stride,
                 void* hip_stream) {
-  AQMP_ENTRY(decode(d, c, job, dev_out, dtype, row_stride, (hipStream_t)hip_stream));
+  AQMP_ENTRY(decode(d, c, job, 0.0, dev_out, dtype, row_stride, (hipStream_t)hip_stream));
+}
+
+int aqmp_decode_quantized(const aqmp_dict* d, const aqmp_code* c, int job, double step, void* dev_out, int dtype,
+                          int64_t row_stride, void* hip_stream) {
+  AQMP_ENTRY(decode(d, c, job, step, dev_out, dtype, row_stride, (hipStream_t)hip_stream));
 }
 
 int aqmp_worklist_compact(const uint8_t* dev_status, int64_t n, int32_t* dev_out, int32_t* dev_count,

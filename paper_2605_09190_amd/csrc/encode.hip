@@ -287,9 +287,12 @@ void free_code(aqmp_code* c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->done) (void)hipEventDestroy(c->done);
-  for (auto& e : c->lev) (void)hipEventDestroy(e.start), (void)hipEventDestroy(e.end);
-  for (auto& e : c->sev)
-    (void)hipEventDestroy(e.a), (void)hipEventDestroy(e.b), (void)hipEventDestroy(e.c), (void)hipEventDestroy(e.d);
+  // (destroying a null event would leave an error for the next HIP call to report)
+  auto destroy = [](hipEvent_t ev) {
+    if (ev) (void)hipEventDestroy(ev);
+  };
+  for (auto& e : c->lev) destroy(e.start), destroy(e.end);
+  for (auto& e : c->sev) destroy(e.a), destroy(e.b), destroy(e.c), destroy(e.d);
   for (auto& a : c->allocs) dev_free(a.p, a.bytes);
   for (DevBuf* b : {&c->ex_keys, &c->ex_keys2, &c->ex_vals, &c->ex_vals2, &c->ex_tot, &c->ex_tmp, &c->ex_t,
                     &c->ex_off, &c->ex_out})
@@ -951,9 +954,16 @@ void put(std::vector<uint8_t>& b, T v) {
 
 }  // namespace
 
-int code_pack(const aqmp_code* c, const int32_t* jobs, int n_jobs, int level, uint8_t* out, int64_t capacity,
-              int64_t* size_out) {
+int code_pack(const aqmp_code* c, const int32_t* jobs, int n_jobs, int level, double step, uint8_t* out,
+              int64_t capacity, int64_t* size_out) {
   if (!c || !jobs || !size_out) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_pack: null argument");
+  if (!(step >= 0.0) || !std::isfinite(step)) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_pack: step must be finite and >= 0");
+  // Coefficient format 1: q = round-half-to-even(c / d) in FP64, d = the
+  // step rounded to binary32 (the value the stream stores).
+  const bool quant = step > 0.0;
+  const float step32 = (float)step;
+  const double d = (double)step32;
+  if (quant && !(d > 0.0)) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_pack: step rounds to zero in binary32");
   if (n_jobs < 1 || n_jobs > 255) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_pack: 1..255 channels per stream");
   if (level < -1 || level > 9) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_pack: level must be -1 (raw) or 0..9");
   const int nj = (int)c->jobs.size();
@@ -973,18 +983,30 @@ int code_pack(const aqmp_code* c, const int32_t* jobs, int n_jobs, int level, ui
   int max_count = 0;
   for (const auto& h : nodes) max_count = std::max(max_count, h.leaf.n_atoms);
   const int cb = max_count > 255 ? 2 : 1;
+  // widest quantised value over the packed channels' leaves: 2 or 4 bytes
+  int qb = 0;
+  if (quant) {
+    double big = 0.0;
+    for (int i = 0; i < n_jobs; ++i)
+      for (const auto& h : nodes)
+        if (h.leaf.job == jobs[i] && !(h.leaf.flags & 1))
+          for (int t = 0; t < h.leaf.n_atoms; ++t) big = std::max(big, std::fabs(std::nearbyint(h.coef[t] / d)));
+    if (big > 2147483647.0) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_pack: step too small for 32-bit quantised values");
+    qb = big <= 32767.0 ? 2 : 4;
+  }
   std::vector<uint8_t> raw;
   raw.insert(raw.end(), {'A', 'Q', 'M', 'P'});
   put<uint8_t>(raw, 1);
   put<uint8_t>(raw, (uint8_t)c->dict->families);
-  put<uint8_t>(raw, 0);
+  put<uint8_t>(raw, quant ? 1 : 0);
   put<uint8_t>(raw, (uint8_t)n_jobs);
   put<uint32_t>(raw, (uint32_t)im0.w);
   put<uint32_t>(raw, (uint32_t)im0.h);
   put<uint8_t>(raw, (uint8_t)ilog2(p0.n_min));
   put<uint8_t>(raw, (uint8_t)ilog2(p0.n_max));
   put<uint8_t>(raw, (uint8_t)cb);
-  put<uint8_t>(raw, 0);
+  put<uint8_t>(raw, (uint8_t)qb);
+  if (quant) put<float>(raw, step32);
   for (int i = 0; i < n_jobs; ++i) {
     // the job's nodes are contiguous in the canonical order
     auto lo = std::lower_bound(nodes.begin(), nodes.end(), jobs[i],
@@ -1021,7 +1043,17 @@ int code_pack(const aqmp_code* c, const int32_t* jobs, int n_jobs, int level, ui
         for (int t = 0; t < it->leaf.n_atoms; ++t) put<uint16_t>(raw, (uint16_t)it->idx[t]);
     for (auto it = lo; it != hi; ++it)
       if (!(it->leaf.flags & 1))
-        for (int t = 0; t < it->leaf.n_atoms; ++t) put<float>(raw, (float)it->coef[t]);
+        for (int t = 0; t < it->leaf.n_atoms; ++t) {
+          if (!quant) {
+            put<float>(raw, (float)it->coef[t]);
+          } else {
+            const double q = std::nearbyint(it->coef[t] / d);
+            if (qb == 2)
+              put<int16_t>(raw, (int16_t)q);
+            else
+              put<int32_t>(raw, (int32_t)q);
+          }
+        }
   }
   if (level < 0) {
     *size_out = (int64_t)raw.size();
@@ -1044,9 +1076,11 @@ int code_pack(const aqmp_code* c, const int32_t* jobs, int n_jobs, int level, ui
   return AQMP_OK;
 }
 
-int decode(const aqmp_dict* d, const aqmp_code* c, int job, void* out, int dtype, int64_t row_stride,
+int decode(const aqmp_dict* d, const aqmp_code* c, int job, double step, void* out, int dtype, int64_t row_stride,
            hipStream_t s) {
   if (!d || !c || !out) AQMP_FAIL(AQMP_E_INVALID, "aqmp_decode: null argument");
+  if (!(step >= 0.0) || !std::isfinite(step)) AQMP_FAIL(AQMP_E_INVALID, "aqmp_decode: step must be finite and >= 0");
+  if (step > 0.0 && !((double)(float)step > 0.0)) AQMP_FAIL(AQMP_E_INVALID, "aqmp_decode: step rounds to zero in binary32");
   if (d != c->dict) AQMP_FAIL(AQMP_E_INVALID, "aqmp_decode: code was made with another dictionary");
   if (job < 0 || job >= (int)c->jobs.size()) AQMP_FAIL(AQMP_E_INVALID, "aqmp_decode: job out of range");
   if (dtype != AQMP_F32 && dtype != AQMP_F64) AQMP_FAIL(AQMP_E_INVALID, "aqmp_decode: bad dtype");
@@ -1058,7 +1092,7 @@ int decode(const aqmp_dict* d, const aqmp_code* c, int job, void* out, int dtype
   for (int l = pp.lg_hi; l >= pp.lg_lo; --l) {
     if (pp.cap[l] == 0) continue;
     AQMP_LAUNCH(launch_decode(1 << l, c->djobs, level_at(c, l, pp.base[l]), &c->dcnt[pi].count[l], job, d->nfam,
-                              d->lv[l].d_tab, out, dtype, row_stride, s));
+                              d->lv[l].d_tab, step > 0.0 ? (double)(float)step : 0.0, out, dtype, row_stride, s));
   }
   return AQMP_OK;
 }

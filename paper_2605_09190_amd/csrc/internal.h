@@ -178,8 +178,10 @@ hipError_t launch_omp_pursuit(int n, const JobDev* jobs, LevelDev lv, const int3
 hipError_t launch_ssim(const aqmp_image& x, const aqmp_image& y, int mode, double c1, double c2, double* partial,
                        int* n_partial, hipStream_t s);
 int ssim_planes(const aqmp_image* x, const aqmp_image* y, int mode, double data_range, double* out, hipStream_t s);
+// step > 0: every coefficient is replaced by its quantised value
+// rint(c / step) * step first (the stream's coefficient format 1).
 hipError_t launch_decode(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t job,
-                         int32_t nfam, const double* tab, void* out, int32_t dtype,
+                         int32_t nfam, const double* tab, double step, void* out, int32_t dtype,
                          int64_t row_stride, hipStream_t s);
 
 // Device gather of a code's visited nodes in canonical order.  Sort key of a

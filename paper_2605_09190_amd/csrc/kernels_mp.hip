@@ -433,8 +433,8 @@ __global__ __launch_bounds__(64 * SelCfg<N>::WPN * SelCfg<N>::NPG) void k_select
 // ---------------------------------------------------------------------------
 template <int N>
 __global__ __launch_bounds__(256) void k_decode(const JobDev* jobs, LevelDev lv, const int32_t* count_ptr,
-                                                int32_t job, const double* tab, void* out, int32_t dtype,
-                                                int64_t row_stride) {
+                                                int32_t job, const double* tab, double step, void* out,
+                                                int32_t dtype, int64_t row_stride) {
   using G = Geo<N>;
   constexpr int K = G::K;
   const int count = *count_ptr;
@@ -455,7 +455,8 @@ __global__ __launch_bounds__(256) void k_decode(const JobDev* jobs, LevelDev lv,
     for (int s = 0; s < na; ++s) {
       const size_t slot = (size_t)i * lv.kmax + s;
       const int atom = lv.rec_idx[slot];
-      const double coef = lv.rec_coef[slot];
+      const double c0 = lv.rec_coef[slot];
+      const double coef = step > 0.0 ? rint(c0 / step) * step : c0;
       const int f = atom / K, q = (atom % K) / N, p = atom % N;
       const double* tf = tab + (size_t)f * K;
       const bool dc = (p == 0 && q == 0);
@@ -531,11 +532,11 @@ hipError_t launch_select(int n, const StepArgs& a, int64_t cap, hipStream_t s, h
 }
 
 hipError_t launch_decode(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t job,
-                         int32_t nfam, const double* tab, void* out, int32_t dtype, int64_t row_stride,
+                         int32_t nfam, const double* tab, double step, void* out, int32_t dtype, int64_t row_stride,
                          hipStream_t s) {
   (void)nfam;
   AQMP_DISPATCH_N(n, hipLaunchKernelGGL(k_decode<NN>, dim3(grid_for<NN>(4)), dim3(256), 0, s, jobs, lv,
-                                        count, job, tab, out, dtype, row_stride));
+                                        count, job, tab, step, out, dtype, row_stride));
   return hipGetLastError();
 }
 

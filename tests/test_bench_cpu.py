@@ -50,8 +50,12 @@ def test_roofline_per_level_report(bench):
     lv = r["per_level"]
     assert set(lv) == {"8", "16", "32", "64"}
     assert lv["64"]["select_gbs"] == pytest.approx(43020 * 4000 / 0.6e-3 / 1e9, rel=1e-3)
-    assert lv["16"]["peak"] == "bf16 mfma" and lv["8"]["peak"] == "fp64"
-    assert lv["8"]["frac"] == pytest.approx(4 * 8 ** 4 * 1000 / 0.1e-3 / 1e12 / bench.PEAK_FP64_TFLOPS, abs=1e-4)
+    assert lv["16"]["peak"] == "bf16 mfma" and lv["8"]["peak"] == "bf16 mfma"
+    assert lv["8"]["frac"] == pytest.approx(4 * 8 ** 4 * 1000 / 0.1e-3 / 1e12 / bench.PEAK_BF16_TFLOPS, abs=1e-4)
+    r32 = bench.roofline(stats, timing, 0, lambda n: f"k<{n}>", workload="none")
+    assert r32["per_level"]["8"]["peak"] == "fp64"
+    assert r32["per_level"]["8"]["frac"] == pytest.approx(4 * 8 ** 4 * 1000 / 0.1e-3 / 1e12 / bench.PEAK_FP64_TFLOPS,
+                                                          abs=1e-4)
 
 
 def test_more_than_one_gpu_is_refused(bench, monkeypatch):

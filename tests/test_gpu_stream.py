@@ -147,3 +147,71 @@ def test_pack_rejects_mismatched_channels(A, dic):
     with pytest.raises(Exception, match="one size"):
         code.pack([0, 1])
     code.free()
+
+
+# -- coefficient format 1 (uniform quantiser) --------------------------------
+
+@pytest.mark.parametrize("prec,step", [(1, 0.02), (0, 0.005), (1, 0.25), (1, 1e-4)])
+def test_quantized_stream_bytes_match_oracle_packer(A, dic, prec, step):
+    """The library's format 1 stream of a code equals, byte for byte, the
+    oracle's packing of the same tree with the same step (the quantiser is
+    byte work once the coefficients are given); step 1e-4 needs 4-byte
+    values.  DEFLATE equals zlib's on those bytes."""
+    w = workload("c1", tau=0.02)
+    img = w["channels"][0]
+    p = w["params"][0]
+    code = A.Code(dic, [_dev(img)], [p], [(0, 0)], precision=prec, schedule=1)
+    raw = code.pack([0], level=-1, step=step)
+    exp = code.export_nodes()
+    nodes = _oracle_nodes(exp, 0)
+    want = O.pack_stream([nodes], img.shape[1], img.shape[0], p["n_min"], p["n_max"], step=step)
+    _say("format 1", prec, step, len(raw), "bytes; width", raw[19])
+    assert raw[6] == 1 and raw == want
+    assert raw[19] == (4 if step == 1e-4 else 2)
+    z = code.pack([0], level=9, step=step)
+    assert z == zlib.compress(raw, 9)
+    # step 0 is the binary32 stream
+    assert code.pack([0], level=-1, step=0.0) == code.pack([0], level=-1)
+    code.free()
+
+
+@pytest.mark.parametrize("step", [0.01, 0.05])
+def test_quantized_decode_matches_the_unpacked_stream(A, dic, step):
+    """The library's decode with a step reconstructs what a decoder of the
+    format 1 stream reconstructs: the oracle unpacks the library's stream and
+    decodes its leaves (q * d coefficients) in FP64; the two planes agree to
+    FP64 rounding, and the quantised PSNR is below the unquantised one."""
+    import torch
+    w = workload("c1", tau=0.02)
+    img = w["channels"][0]
+    p = w["params"][0]
+    code = A.Code(dic, [_dev(img)], [p], [(0, 0)], precision=1, schedule=1)
+    back = O.unpack_stream(code.pack([0], level=-1, step=step))
+    leaves = [O.Node(x0, y0, n, O.MPResult(idx=idx, coef=coef), False, 0.0, 0.0)
+              for (x0, y0, n, idx, coef) in back["channels"][0]]
+    rec_o = O.decode(leaves, 512, 512)
+    out = torch.zeros(512, 512, dtype=torch.float64, device="cuda")
+    code.decode(0, out, step=step)
+    out0 = torch.zeros(512, 512, dtype=torch.float64, device="cuda")
+    code.decode(0, out0)
+    torch.cuda.synchronize()
+    rec_g = out.cpu().numpy()
+    err = np.abs(rec_g - rec_o).max()
+    ps_q, ps_0 = O.psnr(img, rec_g), O.psnr(img, out0.cpu().numpy())
+    _say("quantized decode", step, "max err", err, "psnr", ps_q, "unquantized", ps_0)
+    assert err < 1e-9
+    assert ps_q < ps_0
+    code.free()
+
+
+def test_quantized_pack_rejects_bad_steps(A, dic):
+    w = workload("c0")
+    code = A.Code(dic, [_dev(w["channels"][0])], w["params"], [(0, 0)], precision=1, schedule=1)
+    for bad in (-1.0, float("nan"), float("inf"), 1e-50):
+        with pytest.raises(A.AqmpError) as ei:
+            code.pack([0], level=-1, step=bad)
+        assert ei.value.code == A.E_INVALID
+    with pytest.raises(A.AqmpError) as ei:
+        code.pack([0], level=-1, step=1e-9)        # |q| beyond 2^31 - 1
+    assert ei.value.code == A.E_INVALID
+    code.free()
