@@ -76,6 +76,27 @@ __device__ inline double job_pixel(const JobDev& jb, int y, int x) {
 int check_params(const aqmp_params& p, const std::string& tag);
 JobDev make_jobdev(const aqmp_image& im, const aqmp_params& p);
 
+// Pixels (y, x0 .. x0 + W - 1) of a job's plane in FP64, edge-replicated
+// like job_pixel.  The sample type is tested once and the W loads are
+// independent, so they are all in flight together.
+template <int W>
+__device__ inline void job_pixels(const JobDev& jb, int y, int x0, double (&v)[W]) {
+  const int yy = y < jb.h ? y : jb.h - 1;
+  const int64_t row = (int64_t)yy * jb.row_stride;
+  int xs[W];
+#pragma unroll
+  for (int j = 0; j < W; ++j) xs[j] = x0 + j < jb.w ? x0 + j : jb.w - 1;
+  if (jb.dtype == AQMP_F64) {
+    const double* p = (const double*)jb.img + row;
+#pragma unroll
+    for (int j = 0; j < W; ++j) v[j] = p[xs[j]];
+  } else {
+    const float* p = (const float*)jb.img + row;
+#pragma unroll
+    for (int j = 0; j < W; ++j) v[j] = (double)p[xs[j]];
+  }
+}
+
 // Device-side arrays of one quadtree level (block size N = 1 << lg).  The
 // node arrays are shared by all passes; a pass owns [base, base + cap).
 struct LevelDev {

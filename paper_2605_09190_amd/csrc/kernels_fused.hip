@@ -260,13 +260,16 @@ __global__ __launch_bounds__(256, 1) void k_pursuit16_bf16(const JobDev* __restr
       const JobDev& jb = jobs[lv.job[nd]];
       const int bx = lv.x0[nd], by = lv.y0[nd];
       double e = 0.0;
+      const JobDev jl = jb;   // one copy of the job's fields in registers
 #pragma unroll
       for (int dy = 0; dy < 2; ++dy) {
         const int y = 2 * part + dy;
         float f[N];
+        double pv[N];
+        job_pixels<N>(jl, by + y, bx, pv);
 #pragma unroll
         for (int x = 0; x < N; ++x) {
-          const double v = job_pixel(jb, by + y, bx + x);
+          const double v = pv[x];
           f[x] = (float)v;
           e += v * v;
         }
@@ -637,12 +640,16 @@ __global__ __launch_bounds__(256) void k_pursuit8_bf16(const JobDev* __restrict_
       const JobDev& jb = jobs[lv.job[nd]];
       const int bx = lv.x0[nd], by = lv.y0[nd];
       double ep = 0.0;
+      const JobDev jl = jb;   // one copy of the job's fields in registers
+      double pv[2][N];
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy) job_pixels<N>(jl, by + y0 + dy, bx, pv[dy]);
 #pragma unroll
       for (int dy = 0; dy < 2; ++dy) {
         p8_bf16x8 b;
 #pragma unroll
         for (int x = 0; x < N; ++x) {
-          const double v = mine ? job_pixel(jb, by + y0 + dy, bx + x) : 0.0;
+          const double v = mine ? pv[dy][x] : 0.0;
           rr[dy][x] = (float)v;
           ep += v * v;
           b[x] = (__bf16)rr[dy][x];

@@ -47,13 +47,18 @@ __global__ __launch_bounds__(256) void k_gather(StepArgs a, const int32_t* count
     // a patch row of PW pixels: one FP32 and one BF16 vector store
     typedef float f32v __attribute__((ext_vector_type(G::PW)));
     typedef uint16_t u16v __attribute__((ext_vector_type(G::PW)));
+    // every load of the patch is issued before the first is used
+    const JobDev jl = jb;
+    double pv[G::PH][G::PW];
+#pragma unroll
+    for (int dy = 0; dy < G::PH; ++dy) job_pixels<G::PW>(jl, by + py + dy, bx + px, pv[dy]);
 #pragma unroll
     for (int dy = 0; dy < G::PH; ++dy) {
       f32v fv;
       u16v bv;
 #pragma unroll
       for (int dx = 0; dx < G::PW; ++dx) {
-        const double v = job_pixel(jb, by + py + dy, bx + px + dx);
+        const double v = pv[dy][dx];
         fv[dx] = (float)v;
         bv[dx] = f32_to_bf16(fv[dx]);
         e += v * v;
