@@ -536,7 +536,7 @@ def main():
     # workload (timed candidates; a choice replaces the library default only
     # when it is clearly faster), unless a variant or schedule is forced.
     tuned = None
-    levels_v, stepwise = {}, False
+    levels_v, stepwise, tiles_v = {}, False, {}
     sched = A.SCHED_BATCHED
     if not args.no_autotune and args.corr_variant == 0:
         from paper_2605_09190_amd import autotune
@@ -546,10 +546,12 @@ def main():
         tuned["seconds"] = round(time.perf_counter() - t0, 2)
         levels_v, stepwise, sched = (tuned["options"]["corr_variant_levels"], tuned["options"]["stepwise"],
                                      tuned["options"]["schedule"])
+        tiles_v = tuned["options"]["corr_tile_levels"]
         log(f"autotune: {tuned['options']} in {tuned['seconds']} s")
     if args.schedule is not None:
         sched = A.SCHED_BATCHED if args.schedule == "batched" else A.SCHED_CONCURRENT
-    head_kw = dict(corr_variant=args.corr_variant, corr_variant_levels=levels_v, stepwise=stepwise)
+    head_kw = dict(corr_variant=args.corr_variant, corr_variant_levels=levels_v, stepwise=stepwise,
+                   corr_tile_levels=tiles_v)
     # the labelled solvers run batched unless a schedule is forced
     var_sched = A.SCHED_CONCURRENT if args.schedule == "concurrent" else A.SCHED_BATCHED
 
@@ -731,6 +733,7 @@ def main():
         "c4_sweep": sweep_res,
         "c3_40k_leaves": leaves40k,
         "autotune": (dict(options=dict(corr_variant_levels={str(k): v for k, v in levels_v.items()},
+                                       corr_tile_levels={str(k): list(v) for k, v in tiles_v.items()},
                                        stepwise=stepwise,
                                        schedule="batched" if sched == A.SCHED_BATCHED else "concurrent"),
                           measured=tuned["measured"], seconds=tuned["seconds"]) if tuned else None),

@@ -171,7 +171,16 @@ typedef struct {
                                     N = 2^lg, 2 <= lg <= 6; a zero nibble takes
                                     corr_variant.  An autotuner fills it from
                                     timed encodes of the caller's workload. */
-  int32_t reserved[2];
+  uint32_t corr_tile_levels;     /* tuning of the generated-atom correlation
+                                    (variant 6, N = 32 and 64): the node tile of
+                                    a launch is 32 MB nodes, MB chosen from the
+                                    active-node count inside [lo, hi].  Byte
+                                    8 (lg - 5) holds lo in its low nibble and hi
+                                    in its high nibble for N = 2^lg; a zero byte
+                                    takes the library's range (3..7 at N = 64,
+                                    1..7 at N = 32); 1 <= lo <= hi <= 7.  Results
+                                    do not depend on it. */
+  int32_t reserved;
 } aqmp_options;
 
 /* A leaf of the quadtree (or, from aqmp_code_export_nodes, any visited

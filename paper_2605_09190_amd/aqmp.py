@@ -62,7 +62,7 @@ class Job(C.Structure):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("schedule", C.c_int32), ("flags", C.c_int32),
                 ("corr_variant", C.c_int32), ("solver", C.c_int32),
-                ("corr_variant_levels", C.c_uint32), ("reserved", C.c_int32 * 2)]
+                ("corr_variant_levels", C.c_uint32), ("corr_tile_levels", C.c_uint32), ("reserved", C.c_int32)]
 
 
 class Leaf(C.Structure):
@@ -157,6 +157,17 @@ def pack_variant_levels(per_n) -> int:
         if 1 << lg != int(n) or not 2 <= lg <= 6 or not 0 <= int(v) <= 6:
             raise ValueError(f"bad per-level variant {n}: {v}")
         word |= int(v) << (4 * lg)
+    return word
+
+
+def pack_tile_levels(per_n) -> int:
+    """{N: (lo, hi)} -> the aqmp_options.corr_tile_levels word (byte 8 (log2 N - 5)
+    = lo | hi << 4, for N = 32, 64)."""
+    word = 0
+    for n, (lo, hi) in dict(per_n).items():
+        if int(n) not in (32, 64) or not 1 <= int(lo) <= int(hi) <= 7:
+            raise ValueError(f"bad node-tile range {n}: {(lo, hi)}")
+        word |= (int(lo) | int(hi) << 4) << (8 * (int(n).bit_length() - 1 - 5))
     return word
 
 
@@ -299,7 +310,7 @@ class Code:
 
     def __init__(self, dic: Dictionary, images, params, jobs, precision: int = PREC_FP32,
                  schedule: int = SCHED_PLAIN, stream=None, timing: bool = False, corr_variant: int = 0,
-                 stepwise: bool = False, solver: int = 0, corr_variant_levels=None):
+                 stepwise: bool = False, solver: int = 0, corr_variant_levels=None, corr_tile_levels=None):
         self.dic = dic
         self._keep = list(images)
         imgs = (Image * len(images))(*[make_image(t) for t in images])
@@ -310,6 +321,7 @@ class Code:
         opt.flags = (OPT_TIMING if timing else 0) | (OPT_STEPWISE if stepwise else 0)
         opt.corr_variant = int(corr_variant)
         opt.corr_variant_levels = pack_variant_levels(corr_variant_levels or {})
+        opt.corr_tile_levels = pack_tile_levels(corr_tile_levels or {})
         opt.solver = int(solver)
         h = C.c_void_p()
         _check(lib.aqmp_encode(dic.h, imgs, len(images), prms, len(params), jbs, len(jobs), C.byref(opt),

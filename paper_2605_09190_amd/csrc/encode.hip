@@ -192,6 +192,13 @@ int validate(const aqmp_dict* d, const aqmp_image* imgs, int n_imgs, const aqmp_
         AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad corr_variant_levels entry for N = " + std::to_string(1 << lg));
     if (opt->solver != AQMP_SOLVER_DENSE && opt->solver != AQMP_SOLVER_GRAM && opt->solver != AQMP_SOLVER_OMP)
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad solver");
+    if (opt->corr_tile_levels & ~0xFFFFu)
+      AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: corr_tile_levels has bits outside the block sizes 32, 64");
+    for (int b = 0; b < 2; ++b) {
+      const uint32_t v = (opt->corr_tile_levels >> (8 * b)) & 0xFFu, lo = v & 0xFu, hi = v >> 4;
+      if (v && !(lo >= 1 && lo <= hi && hi <= 7))
+        AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad corr_tile_levels entry for N = " + std::to_string(32 << b));
+    }
   }
   for (int i = 0; i < n_imgs; ++i) {
     const aqmp_image& im = imgs[i];
@@ -539,6 +546,7 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
       a.next_count = &cnt->act[(t + 1) % 3];
       a.clear_count = &cnt->act[(t + 2) % 3];
       const aqmp_code::StepEv* se = timing ? &c->sev[c->sev_pos++] : nullptr;
+      a.corr_tile = l >= 5 ? (int32_t)((c->opt.corr_tile_levels >> (8 * (l - 5))) & 0xFFu) : 0;
       const int lv_var = (int)((c->opt.corr_variant_levels >> (4 * l)) & 0xFu);
       const int variant = c->wide_residual ? 3 : (lv_var ? lv_var : c->opt.corr_variant);
       AQMP_LAUNCH(launch_corr(n, c->opt.precision, variant, atoms, a, D.m_pad, s, se ? se->a : nullptr,

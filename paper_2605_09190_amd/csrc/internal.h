@@ -148,6 +148,9 @@ struct StepArgs {
   int32_t* next_act;
   int32_t* next_count;
   int32_t* clear_count;
+  // Node-tile range of the generated-atom correlation: lo | hi << 4, 0 =
+  // the kernel's own range.
+  int32_t corr_tile;
 };
 
 // ---------------------------------------------------------------------------

@@ -998,9 +998,9 @@ __device__ void gen_tiles(const uint16_t* __restrict__ X, const int32_t* __restr
 // Node-tile width for this launch: the fewest 32-node block-rounds over the
 // workgroups (rounds x MB), ties to the wider tile.  Every workgroup computes
 // the same value from the count.
-__device__ inline int gen_pick_mb(int count, int n_atom_tiles, int wgs, int mb_min) {
-  int best = kGenMBMax, best_cost = 0x7fffffff;
-  for (int mb = kGenMBMax; mb >= mb_min; --mb) {
+__device__ inline int gen_pick_mb(int count, int n_atom_tiles, int wgs, int mb_min, int mb_max) {
+  int best = mb_max, best_cost = 0x7fffffff;
+  for (int mb = mb_max; mb >= mb_min; --mb) {
     const int tiles = n_atom_tiles * ((count + 32 * mb - 1) / (32 * mb));
     const int cost = ((tiles + wgs - 1) / wgs) * mb;
     if (cost < best_cost) {
@@ -1016,7 +1016,8 @@ __global__ __launch_bounds__(256, 1) void k_corr_bf16_gen(const float* __restric
                                                           const uint16_t* __restrict__ X,
                                                           const int32_t* __restrict__ act,
                                                           const int32_t* __restrict__ act_count,
-                                                          unsigned long long* __restrict__ keys, int n_atom_tiles) {
+                                                          unsigned long long* __restrict__ keys, int n_atom_tiles,
+                                                          int tile_range) {
   constexpr int K = N * N;
   __shared__ __attribute__((aligned(1024))) char sR0[kGenBufBytes];
   __shared__ __attribute__((aligned(1024))) char sR1[kGenBufBytes];
@@ -1029,8 +1030,13 @@ __global__ __launch_bounds__(256, 1) void k_corr_bf16_gen(const float* __restric
   const int count = *act_count;
   if (count <= 0) return;
   const GenRing rg{sR0, sR1, sR2, sR3};
+  // node-tile range: the tuned one when given, else 3..7 (N = 64), 1..7 (N = 32)
+  const int mb_lo = tile_range ? (tile_range & 0xF) : (N == 64 ? 3 : 1);
+  const int mb_hi = tile_range ? (tile_range >> 4) : kGenMBMax;
   if constexpr (N == 64) {
-    switch (gen_pick_mb(count, n_atom_tiles, gridDim.x, 3)) {
+    switch (gen_pick_mb(count, n_atom_tiles, gridDim.x, mb_lo, mb_hi)) {
+      case 1: gen_tiles<N, 1>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
+      case 2: gen_tiles<N, 2>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
       case 3: gen_tiles<N, 3>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
       case 4: gen_tiles<N, 4>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
       case 5: gen_tiles<N, 5>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
@@ -1038,7 +1044,7 @@ __global__ __launch_bounds__(256, 1) void k_corr_bf16_gen(const float* __restric
       default: gen_tiles<N, 7>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
     }
   } else {
-    switch (gen_pick_mb(count, n_atom_tiles, gridDim.x, 1)) {
+    switch (gen_pick_mb(count, n_atom_tiles, gridDim.x, mb_lo, mb_hi)) {
       case 1: gen_tiles<N, 1>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
       case 2: gen_tiles<N, 2>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
       case 3: gen_tiles<N, 3>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
@@ -1209,7 +1215,7 @@ static void launch_corr_n(int precision, int variant, const void* atoms, const S
                            a.r16, a.act, a.act_count, a.keys, nat);
       else if (variant == 6 && N >= 32)
         launch_timed((k_corr_bf16_gen<(N >= 32 ? N : 32)>), dim3(kCorrGrid), dim3(256), s, e0, e1, a.tabT32,
-                           a.nfam, a.r16, a.act, a.act_count, a.keys, nat);
+                           a.nfam, a.r16, a.act, a.act_count, a.keys, nat, (int)a.corr_tile);
       else if (variant == 5)
         launch_timed((k_corr_bf16_pipe<N, 64>), dim3(kCorrGrid), dim3(256), s, e0, e1, (const uint16_t*)atoms, a.r16,
                            a.act, a.act_count, a.keys, nat);

@@ -30,3 +30,46 @@ def test_pack_variant_levels():
     for bad in ({48: 1}, {128: 1}, {2: 1}, {64: 7}, {64: -1}):
         with pytest.raises(ValueError):
             A.pack_variant_levels(bad)
+
+
+def test_tile_candidates_include_the_defaults():
+    for n, rng in T.DEFAULT_TILE.items():
+        assert rng in T.TILE_CANDIDATES[n]
+        for lo, hi in T.TILE_CANDIDATES[n]:
+            assert 1 <= lo <= hi <= 7
+
+
+def test_cache_key_and_round_trip(tmp_path):
+    class Img:
+        def __init__(self, h, w, dt):
+            self.shape, self.dtype = (h, w), dt
+    prm = [dict(tol=0.02, max_atoms=32, n_min=8, n_max=64, k_per_level={16: 4})]
+    k1 = T.cache_key([Img(64, 48, "float32")], prm, [(0, 0)], "gpu", "abc")
+    assert k1 == T.cache_key([Img(64, 48, "float32")], [dict(reversed(list(prm[0].items())))], [(0, 0)], "gpu", "abc")
+    assert k1 != T.cache_key([Img(64, 49, "float32")], prm, [(0, 0)], "gpu", "abc")
+    assert k1 != T.cache_key([Img(64, 48, "float32")], prm, [(0, 0)], "gpu", "abd")
+    assert k1 != T.cache_key([Img(64, 48, "float32")], prm, [(0, 0)], "other", "abc")
+    path = str(tmp_path / "c.json")
+    assert T.cache_load(path, k1) is None
+    opt = dict(corr_variant_levels={64: 5}, corr_tile_levels={32: (2, 5)}, stepwise=False, schedule=1)
+    T.cache_store(path, k1, dict(options=T._options_to_json(opt), measured={}))
+    T.cache_store(path, "other", dict(options=T._options_to_json(opt), measured={}))
+    got = T.cache_load(path, k1)
+    assert T._options_from_json(got["options"]) == opt
+
+
+def test_source_hash_is_stable():
+    assert T.source_hash() == T.source_hash() and len(T.source_hash()) == 64
+
+
+def test_pack_tile_levels():
+    import importlib
+    try:
+        A = importlib.import_module("paper_2605_09190_amd.aqmp")
+    except ImportError:
+        pytest.skip("library not built")
+    assert A.pack_tile_levels({}) == 0
+    assert A.pack_tile_levels({32: (2, 5), 64: (3, 7)}) == (2 | 5 << 4) | (3 | 7 << 4) << 8
+    for bad in ({16: (1, 2)}, {64: (0, 3)}, {64: (4, 3)}, {32: (1, 8)}):
+        with pytest.raises(ValueError):
+            A.pack_tile_levels(bad)

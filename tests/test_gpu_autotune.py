@@ -93,3 +93,53 @@ def test_tuned_options_run_and_match_the_oracle(A, dic):
     PU.compare_job(img, onodes, PU.gpu_nodes_by_key(exp, 0), 2e-3, p["n_max"], rep=rep)
     _say(rep.summary())
     assert rep.ok(), rep.summary()
+
+
+@pytest.mark.parametrize("tiles", [{64: (1, 1), 32: (7, 7)}, {64: (7, 7), 32: (1, 2)}, {64: (2, 4)}])
+def test_node_tile_ranges_are_bit_identical(A, dic, tiles):
+    """Every node-tile width of the generated-atom kernel gives the same keys
+    per node, so forced ranges leave the code bit-identical (full size: the
+    widths then really differ between steps)."""
+    w = workload("c3")
+    imgs = [_dev(c) for c in w["channels"]]
+    ref = A.Code(dic, imgs, w["params"], w["jobs"], precision=1, schedule=1)
+    want = _bytes(ref)
+    ref.free()
+    code = A.Code(dic, imgs, w["params"], w["jobs"], precision=1, schedule=1, corr_tile_levels=tiles)
+    _say("tiles", tiles)
+    assert _bytes(code) == want, tiles
+    code.free()
+
+
+def test_bad_tile_word_is_rejected(A, dic, monkeypatch):
+    imgs = [_dev(piecewise_image(64, 64, seed=2))]
+    p = dict(tol=0.02, max_atoms=8, n_min=8, n_max=32)
+    for word in (1 << 16, 0x12, 0x81, 0x10):       # outside N = 32, 64; lo > hi; hi = 8; lo = 0
+        monkeypatch.setattr(A, "pack_tile_levels", lambda _d, word=word: word)
+        with pytest.raises(Exception, match="corr_tile_levels"):
+            A.Code(dic, imgs, [p], [(0, 0)], precision=1, schedule=1, corr_tile_levels={32: (1, 2)})
+
+
+def test_tuner_cache_round_trip(A, dic, tmp_path):
+    """The tuned options are stored under the workload's key and returned
+    from the cache the second time, without timing anything."""
+    import time
+    from paper_2605_09190_amd import autotune
+    w = workload("c1")
+    imgs = [_dev(w["channels"][0])]
+    path = str(tmp_path / "tune.json")
+    t0 = time.perf_counter()
+    first = autotune.tune(A, dic, imgs, w["params"], [(0, 0)], reps=1, steps=2, cache=path)
+    t1 = time.perf_counter()
+    second = autotune.tune(A, dic, imgs, w["params"], [(0, 0)], reps=1, steps=2, cache=path)
+    t2 = time.perf_counter()
+    _say("tune", first["options"], "measured", first["measured"].get("tile_ms"), t1 - t0, t2 - t1)
+    assert not first["cached"] and second["cached"]
+    assert second["options"] == first["options"]
+    assert t2 - t1 < (t1 - t0) / 4
+    for n, rng in first["options"]["corr_tile_levels"].items():
+        assert rng in autotune.TILE_CANDIDATES[n]
+    # another workload (other shape) misses the cache
+    imgs2 = [_dev(piecewise_image(256, 256, seed=9))]
+    third = autotune.tune(A, dic, imgs2, w["params"], [(0, 0)], reps=1, steps=2, cache=path)
+    assert not third["cached"]
