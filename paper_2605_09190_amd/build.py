@@ -18,7 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libaqmp.so")
 OBJ = os.path.join(ROOT, "_build")
 SOURCES = ["api.hip", "dict.hip", "encode.hip", "kernels_tree.hip", "kernels_mp.hip", "kernels_corr.hip",
-           "kernels_fused.hip", "kernels_gram.hip", "kernels_ssim.hip", "kernels_export.hip", "worklist.hip"]
+           "kernels_fused.hip", "kernels_gram.hip", "kernels_ssim.hip", "kernels_export.hip", "worklist.hip",
+           "host_core.cpp"]
 ARCH = "gfx950"
 
 
@@ -41,7 +42,7 @@ def build(verbose: bool = False) -> str:
     cc = hipcc()
 
     def compile_one(src: str) -> str:
-        obj = os.path.join(OBJ, src.replace(".hip", ".o"))
+        obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
         cmd = [cc, *flags(), "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:

@@ -1,7 +1,7 @@
 // dict.hip - dictionaries D_N (Section 2.1; Section 2.3 and Appendix A: a DCT
 // basis concatenated with a Haar basis, one dictionary per block size).
 //
-// The 1D tables are computed on the host in FP64:
+// The 1D tables are computed on the host in FP64 (host_core.cpp):
 //   DCT-II:  C[k][m] = alpha_k cos(pi/N (m + 1/2) k), alpha_0 = sqrt(1/N),
 //            alpha_k = sqrt(2/N) (Section 2.1);
 //   Haar:    H_1 = [1], H_2m = [H_m (x) (1, 1); I_m (x) (1, -1)] / sqrt(2)
@@ -18,40 +18,11 @@
 #include <vector>
 
 #include "dev_common.h"
+#include "host_core.h"
 #include "host_util.h"
 #include "internal.h"
 
 namespace aqmp {
-
-static void dct_table(int n, double* t) {
-  const double pi = 3.14159265358979323846;
-  for (int k = 0; k < n; ++k) {
-    const double alpha = k == 0 ? std::sqrt(1.0 / n) : std::sqrt(2.0 / n);
-    for (int m = 0; m < n; ++m) t[k * n + m] = alpha * std::cos(pi / n * (m + 0.5) * k);
-  }
-}
-
-static void haar_table(int n, double* t) {
-  std::vector<double> h(1, 1.0);
-  int m = 1;
-  const double s2 = std::sqrt(2.0);
-  while (m < n) {
-    const int m2 = 2 * m;
-    std::vector<double> g((size_t)m2 * m2, 0.0);
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) {
-        g[(size_t)i * m2 + 2 * j] = h[(size_t)i * m + j] / s2;
-        g[(size_t)i * m2 + 2 * j + 1] = h[(size_t)i * m + j] / s2;
-      }
-    for (int i = 0; i < m; ++i) {
-      g[(size_t)(m + i) * m2 + 2 * i] = 1.0 / s2;
-      g[(size_t)(m + i) * m2 + 2 * i + 1] = -1.0 / s2;
-    }
-    h.swap(g);
-    m = m2;
-  }
-  std::memcpy(t, h.data(), sizeof(double) * n * n);
-}
 
 static double atom_value(const aqmp_dict::Level& L, int a, int y, int x) {
   const int n = L.n, k = L.k;

@@ -20,8 +20,8 @@
 #include <new>
 #include <vector>
 
-#include <zlib.h>
 
+#include "host_core.h"
 #include "host_util.h"
 #include "internal.h"
 
@@ -938,40 +938,15 @@ int code_export(const aqmp_code* c, bool leaves_only, aqmp_leaf* leaves, int32_t
 }
 
 // ---------------------------------------------------------------------------
-// Bitstream (encoder step (iii), Section 2.3: the sparse vectors of every
-// channel, then a lossless DEFLATE pass).  Version 1, little-endian:
-//   header  "AQMP" | u8 version=1 | u8 families | u8 coef format (0: binary32)
-//           | u8 channels | u32 width | u32 height | u8 log2 N_min
-//           | u8 log2 N_max | u8 bytes per atom count (1 or 2) | u8 0
-//   per channel, nodes in depth-first order (top-level blocks in raster
-//   order over the padded plane, children TL, TR, BL, BR):
-//           u32 nodes | u32 leaves | u32 atoms
-//           | split flags of the nodes with N > N_min, one bit each, LSB first
-//           | atom count of every leaf | u16 atom index of every atom
-//           | binary32 coefficient of every atom (selection order per leaf)
-// Grouping like values together is what lets DEFLATE find the redundancy.
+// Bitstream (encoder step (iii), Section 2.3): the sparse vectors of every
+// channel, then a lossless DEFLATE pass.  The byte layout is stream_write's
+// (host_core.h); here the nodes of each packed job are taken in the
+// canonical depth-first order (top-level blocks in raster order over the
+// padded plane, children TL, TR, BL, BR).
 // ---------------------------------------------------------------------------
-namespace {
-
-template <class T>
-void put(std::vector<uint8_t>& b, T v) {
-  uint8_t tmp[sizeof(T)];
-  __builtin_memcpy(tmp, &v, sizeof(T));
-  b.insert(b.end(), tmp, tmp + sizeof(T));
-}
-
-}  // namespace
-
 int code_pack(const aqmp_code* c, const int32_t* jobs, int n_jobs, int level, double step, uint8_t* out,
               int64_t capacity, int64_t* size_out) {
   if (!c || !jobs || !size_out) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_pack: null argument");
-  if (!(step >= 0.0) || !std::isfinite(step)) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_pack: step must be finite and >= 0");
-  // Coefficient format 1: q = round-half-to-even(c / d) in FP64, d = the
-  // step rounded to binary32 (the value the stream stores).
-  const bool quant = step > 0.0;
-  const float step32 = (float)step;
-  const double d = (double)step32;
-  if (quant && !(d > 0.0)) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_pack: step rounds to zero in binary32");
   if (n_jobs < 1 || n_jobs > 255) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_pack: 1..255 channels per stream");
   if (level < -1 || level > 9) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_pack: level must be -1 (raw) or 0..9");
   const int nj = (int)c->jobs.size();
@@ -988,99 +963,38 @@ int code_pack(const aqmp_code* c, const int32_t* jobs, int n_jobs, int level, do
   std::vector<HostNode> nodes;
   const int rc = collect(c, false, nodes);
   if (rc != AQMP_OK) return rc;
-  int max_count = 0;
-  for (const auto& h : nodes) max_count = std::max(max_count, h.leaf.n_atoms);
-  const int cb = max_count > 255 ? 2 : 1;
-  // widest quantised value over the packed channels' leaves: 2 or 4 bytes
-  int qb = 0;
-  if (quant) {
-    double big = 0.0;
-    for (int i = 0; i < n_jobs; ++i)
-      for (const auto& h : nodes)
-        if (h.leaf.job == jobs[i] && !(h.leaf.flags & 1))
-          for (int t = 0; t < h.leaf.n_atoms; ++t) big = std::max(big, std::fabs(std::nearbyint(h.coef[t] / d)));
-    if (big > 2147483647.0) AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_pack: step too small for 32-bit quantised values");
-    qb = big <= 32767.0 ? 2 : 4;
-  }
-  std::vector<uint8_t> raw;
-  raw.insert(raw.end(), {'A', 'Q', 'M', 'P'});
-  put<uint8_t>(raw, 1);
-  put<uint8_t>(raw, (uint8_t)c->dict->families);
-  put<uint8_t>(raw, quant ? 1 : 0);
-  put<uint8_t>(raw, (uint8_t)n_jobs);
-  put<uint32_t>(raw, (uint32_t)im0.w);
-  put<uint32_t>(raw, (uint32_t)im0.h);
-  put<uint8_t>(raw, (uint8_t)ilog2(p0.n_min));
-  put<uint8_t>(raw, (uint8_t)ilog2(p0.n_max));
-  put<uint8_t>(raw, (uint8_t)cb);
-  put<uint8_t>(raw, (uint8_t)qb);
-  if (quant) put<float>(raw, step32);
+  std::vector<std::vector<StreamNode>> sn(n_jobs);
+  std::vector<StreamChannel> ch(n_jobs);
   for (int i = 0; i < n_jobs; ++i) {
     // the job's nodes are contiguous in the canonical order
     auto lo = std::lower_bound(nodes.begin(), nodes.end(), jobs[i],
                                [](const HostNode& a, int32_t j) { return a.leaf.job < j; });
     auto hi = std::lower_bound(lo, nodes.end(), jobs[i] + 1,
                                [](const HostNode& a, int32_t j) { return a.leaf.job < j; });
-    uint32_t n_leaves = 0, n_atoms = 0;
-    std::vector<uint8_t> bits;
-    int nbits = 0;
-    for (auto it = lo; it != hi; ++it) {
-      if (it->leaf.n > p0.n_min) {
-        if (nbits % 8 == 0) bits.push_back(0);
-        if (it->leaf.flags & 1) bits.back() |= (uint8_t)(1u << (nbits % 8));
-        ++nbits;
-      }
-      if (!(it->leaf.flags & 1)) {
-        ++n_leaves;
-        n_atoms += (uint32_t)it->leaf.n_atoms;
-      }
+    sn[i].reserve((size_t)(hi - lo));
+    for (auto it = lo; it != hi; ++it)
+      sn[i].push_back(StreamNode{it->leaf.n, (it->leaf.flags & 1) != 0, it->leaf.n_atoms, it->idx, it->coef});
+    ch[i] = StreamChannel{sn[i].data(), sn[i].size()};
+  }
+  const StreamHeader hd{(int)c->dict->families, (uint32_t)im0.w, (uint32_t)im0.h, p0.n_min, p0.n_max};
+  std::vector<uint8_t> raw;
+  std::string why;
+  if (stream_write(hd, ch.data(), n_jobs, step, raw, &why) != AQMP_OK)
+    AQMP_FAIL(AQMP_E_INVALID, "aqmp_code_pack: " + why);
+  const std::vector<uint8_t>* res = &raw;
+  std::vector<uint8_t> z;
+  if (level >= 0) {
+    if (!out) {
+      *size_out = (int64_t)stream_deflate_bound(raw.size());
+      return AQMP_OK;
     }
-    put<uint32_t>(raw, (uint32_t)(hi - lo));
-    put<uint32_t>(raw, n_leaves);
-    put<uint32_t>(raw, n_atoms);
-    raw.insert(raw.end(), bits.begin(), bits.end());
-    for (auto it = lo; it != hi; ++it)
-      if (!(it->leaf.flags & 1)) {
-        if (cb == 1)
-          put<uint8_t>(raw, (uint8_t)it->leaf.n_atoms);
-        else
-          put<uint16_t>(raw, (uint16_t)it->leaf.n_atoms);
-      }
-    for (auto it = lo; it != hi; ++it)
-      if (!(it->leaf.flags & 1))
-        for (int t = 0; t < it->leaf.n_atoms; ++t) put<uint16_t>(raw, (uint16_t)it->idx[t]);
-    for (auto it = lo; it != hi; ++it)
-      if (!(it->leaf.flags & 1))
-        for (int t = 0; t < it->leaf.n_atoms; ++t) {
-          if (!quant) {
-            put<float>(raw, (float)it->coef[t]);
-          } else {
-            const double q = std::nearbyint(it->coef[t] / d);
-            if (qb == 2)
-              put<int16_t>(raw, (int16_t)q);
-            else
-              put<int32_t>(raw, (int32_t)q);
-          }
-        }
+    if (stream_deflate(raw, level, z) != AQMP_OK) AQMP_FAIL(AQMP_E_NOMEM, "aqmp_code_pack: DEFLATE failed");
+    res = &z;
   }
-  if (level < 0) {
-    *size_out = (int64_t)raw.size();
-    if (!out) return AQMP_OK;
-    if (capacity < (int64_t)raw.size()) AQMP_FAIL(AQMP_E_CAPACITY, "aqmp_code_pack: output buffer too small");
-    std::copy(raw.begin(), raw.end(), out);
-    return AQMP_OK;
-  }
-  uLongf bound = compressBound((uLong)raw.size());
-  if (!out) {
-    *size_out = (int64_t)bound;
-    return AQMP_OK;
-  }
-  std::vector<uint8_t> z(bound);
-  if (compress2(z.data(), &bound, raw.data(), (uLong)raw.size(), level) != Z_OK)
-    AQMP_FAIL(AQMP_E_NOMEM, "aqmp_code_pack: DEFLATE failed");
-  *size_out = (int64_t)bound;
-  if (capacity < (int64_t)bound) AQMP_FAIL(AQMP_E_CAPACITY, "aqmp_code_pack: output buffer too small");
-  std::copy(z.begin(), z.begin() + bound, out);
+  *size_out = (int64_t)res->size();
+  if (!out) return AQMP_OK;
+  if (capacity < (int64_t)res->size()) AQMP_FAIL(AQMP_E_CAPACITY, "aqmp_code_pack: output buffer too small");
+  std::copy(res->begin(), res->end(), out);
   return AQMP_OK;
 }
 
