@@ -483,6 +483,8 @@ def main():
     ap.add_argument("--corr-variant", type=int, default=0, help="BF16 correlation kernel variant (0 = default)")
     ap.add_argument("--schedule", default=None, choices=["batched", "concurrent"],
                     help="force a schedule (default: the autotuner's choice)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file caching the autotuner's choice per workload, device and kernel sources")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner: library default kernels, batched schedule")
     ap.add_argument("--no-sweep", action="store_true",
@@ -542,7 +544,8 @@ def main():
         from paper_2605_09190_amd import autotune
         log("autotune")
         t0 = time.perf_counter()
-        tuned = autotune.tune(A, dic, imgs, w["params"], w["jobs"], schedules=args.schedule is None)
+        tuned = autotune.tune(A, dic, imgs, w["params"], w["jobs"], schedules=args.schedule is None,
+                              cache=args.tune_cache)
         tuned["seconds"] = round(time.perf_counter() - t0, 2)
         levels_v, stepwise, sched = (tuned["options"]["corr_variant_levels"], tuned["options"]["stepwise"],
                                      tuned["options"]["schedule"])
@@ -594,9 +597,10 @@ def main():
     torch.cuda._sleep(1000)
     torch.cuda.synchronize()
     roof = roofline(st_t, tm_t, A.PREC_BF16, head_kernel, workload=args.workload)
-    roof["timing"] = ("HIP events around every launch of the same launch sequence issued on the stream (events "
-                      "cannot be timed inside a graph); in a kernel trace of this command these are the "
-                      "dispatches between the two spin_kernel markers")
+    roof["timing"] = ("HIP start/stop events recorded by each correlation and select dispatch itself "
+                      "(hipExtLaunchKernelGGL) in the same launch sequence issued on the stream (events cannot be "
+                      "timed inside a graph); in a kernel trace of this command these are the dispatches "
+                      "between the two spin_kernel markers")
     code_t.free()
     log(f"bf16 batched (stream, timed): {sec_t * 1e3:.3f} ms/step, corr {roof['achieved']} TFLOP/s")
 
@@ -736,7 +740,8 @@ def main():
                                        corr_tile_levels={str(k): list(v) for k, v in tiles_v.items()},
                                        stepwise=stepwise,
                                        schedule="batched" if sched == A.SCHED_BATCHED else "concurrent"),
-                          measured=tuned["measured"], seconds=tuned["seconds"]) if tuned else None),
+                          measured=tuned["measured"], seconds=tuned["seconds"], cached=tuned["cached"])
+                     if tuned else None),
         "roofline": roof,
         "precision_report": prec_rep,
     }

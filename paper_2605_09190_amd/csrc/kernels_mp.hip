@@ -141,6 +141,45 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
+// Wave sums of eight FP64 values at once; every lane receives all eight.
+// Lanes 32 apart trade halves of their lists (each keeps four partial sums),
+// then lanes 16 apart and 8 apart do the same, so that each lane carries one
+// value summed over the eight lanes that differ from it in bits 3-5; the
+// eight lanes sharing those bits then add theirs (DPP).  Value j ends on the
+// lanes whose bits 5, 4, 3 spell j.  The order of the additions is fixed.
+__device__ inline void wave_sum8_f64(const double (&v)[kCand], double (&out)[kCand]) {
+  static_assert(kCand == 8, "eight values");
+  const int lane = threadIdx.x & 63;
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+  double h4[4], h2[2];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const double send = b5 ? v[j] : v[j + 4], keep = b5 ? v[j + 4] : v[j];
+    h4[j] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const double send = b4 ? h4[j] : h4[j + 2], keep = b4 ? h4[j + 2] : h4[j];
+    h2[j] = keep + __shfl_xor(send, 16, 64);
+  }
+  double d;
+  {
+    const double send = b3 ? h2[0] : h2[1], keep = b3 ? h2[1] : h2[0];
+    // lanes 8 apart inside a row of 16: rotate the row by 8
+    d = keep + __longlong_as_double((long long)dpp_u64<0x128, 0xF>((unsigned long long)__double_as_longlong(send)));
+  }
+#define AQMP_SUMSTEP(C) { d += __longlong_as_double((long long)dpp_u64<C, 0xF>((unsigned long long)__double_as_longlong(d))); }
+  AQMP_SUMSTEP(0xB1) AQMP_SUMSTEP(0x4E) AQMP_SUMSTEP(0x141)
+#undef AQMP_SUMSTEP
+  const unsigned long long u = (unsigned long long)__double_as_longlong(d);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)u, 8 * j);
+    const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), 8 * j);
+    out[j] = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+  }
+}
+
 template <int N>
 __global__ __launch_bounds__(64 * SelCfg<N>::WPN * SelCfg<N>::NPG) void k_select(StepArgs a) {
   constexpr int WPN = SelCfg<N>::WPN, NPG = SelCfg<N>::NPG, W = WPN * NPG;
@@ -169,7 +208,8 @@ __global__ __launch_bounds__(64 * SelCfg<N>::WPN * SelCfg<N>::NPG) void k_select
   for (int base = blockIdx.x * NPG; base < count; base += stride) {
     const int pos = base + slot;
     const bool valid = pos < count;               // uniform over the node's waves
-    int node = 0, t = 0;
+    int node = 0, t = 0, kk = 0, jidx = 0;
+    double eps2 = 0.0;
     int cand[kCand];
     double rv[PH][PW];
     double c[kCand];
@@ -179,16 +219,22 @@ __global__ __launch_bounds__(64 * SelCfg<N>::WPN * SelCfg<N>::NPG) void k_select
       c[ci] = 0.0;
     }
     if (valid) {
-      // The keys depend only on the position: their loads go out first.
+      // The node and its keys (which depend only on the position) are
+      // loaded together: one round trip, the key loads unconditional (a
+      // clamped index) so that nothing waits between them.
+      node = a.act[pos];
       unsigned long long k[KPL];
       const unsigned long long* kp = a.keys + (size_t)pos * nkeys;
 #pragma unroll
       for (int j = 0; j < KPL; ++j) {
         const int idx = lane + j * 64;
-        k[j] = idx < nkeys ? kp[idx] : 0ull;
+        const unsigned long long v = kp[idx < nkeys ? idx : nkeys - 1];
+        k[j] = idx < nkeys ? v : 0ull;
       }
-      node = a.act[pos];
+      // all five loads in flight before anything waits for one of them
+      __builtin_amdgcn_sched_barrier(0);
       t = a.lv.t[node];
+      jidx = a.lv.job[node];
       const float* r = a.r32 + (size_t)node * K;
 #pragma unroll
       for (int dy = 0; dy < PH; ++dy) {
@@ -249,6 +295,18 @@ __global__ __launch_bounds__(64 * SelCfg<N>::WPN * SelCfg<N>::NPG) void k_select
         const int f = at / K, p = at % N;
         sp[i] = at >= 0 ? a.tab[(size_t)f * K + p * N + h * G::ROWS + col] : 0.0;
       }
+      // the stop test's inputs share the table rows' round trip; held in
+      // scalar registers (uniform per node), the end of the step waits for
+      // no load
+      {
+        const double e2v = a.jobs[jidx].eps2[lg];
+        const int kv = a.jobs[jidx].k[lg];
+        const unsigned long long eb = (unsigned long long)__double_as_longlong(e2v);
+        const unsigned elo = __builtin_amdgcn_readfirstlane((int)(unsigned)eb);
+        const unsigned ehi = __builtin_amdgcn_readfirstlane((int)(unsigned)(eb >> 32));
+        eps2 = __longlong_as_double((long long)(((unsigned long long)ehi << 32) | elo));
+        kk = __builtin_amdgcn_readfirstlane(kv);
+      }
 #pragma unroll
       for (int i = 0; i < NQ; ++i) (&sQ[w][0][0])[lane + 64 * i] = sq[i];
 #pragma unroll
@@ -256,7 +314,8 @@ __global__ __launch_bounds__(64 * SelCfg<N>::WPN * SelCfg<N>::NPG) void k_select
       __builtin_amdgcn_wave_barrier();
 
       // 2. FP64 re-score of the candidates: this lane's patch, row sums kept
-      // apart so that the FMA chains are short, then the wave sum.
+      // apart so that the FMA chains are short; the eight wave sums at once.
+      double part8[kCand];
 #pragma unroll
       for (int ci = 0; ci < kCand; ++ci) {
         const int at = cand[ci];
@@ -285,10 +344,16 @@ __global__ __launch_bounds__(64 * SelCfg<N>::WPN * SelCfg<N>::NPG) void k_select
             for (int dy = 0; dy < PH; ++dy) part = fma(sP[w][ci][ry + dy], sr[dy], part);
           }
         }
-        c[ci] = wave_sum_f64(part);
+        part8[ci] = part;
         // one candidate at a time: keeps the scheduler from holding every
         // candidate's table entries in registers at once
         __builtin_amdgcn_sched_barrier(0);
+      }
+      if constexpr (WPN == 1) {
+        wave_sum8_f64(part8, c);
+      } else {
+#pragma unroll
+        for (int ci = 0; ci < kCand; ++ci) c[ci] = wave_sum_f64(part8[ci]);
       }
     }
     // the node's candidate totals (a barrier when a node spans several waves)
@@ -313,43 +378,48 @@ __global__ __launch_bounds__(64 * SelCfg<N>::WPN * SelCfg<N>::NPG) void k_select
     double coef = 0.0;
     double ew = 0.0;
     if (valid) {
-      // 3. arg-max over the re-scored candidates, lowest atom index on ties.
-      int best = -1;
-      double bmag = -1.0;
+      // 3. arg-max over the re-scored candidates, lowest atom index on ties
+      // (the running best carried by value: no indexed array reads).
+      int bat = -1, bsel = 0;
+      double bmag = -1.0, bc = 0.0;
 #pragma unroll
       for (int ci = 0; ci < kCand; ++ci) {
         const int at = cand[ci];
-        if (at < 0) continue;
         const double m = fabs(c[ci]);
-        if (best < 0 || m > bmag || (m == bmag && at < cand[best])) {
-          best = ci;
-          bmag = m;
-        }
+        const bool take = at >= 0 && (bat < 0 || m > bmag || (m == bmag && at < bat));
+        bat = take ? at : bat;
+        bmag = take ? m : bmag;
+        bc = take ? c[ci] : bc;
+        bsel = take ? ci : bsel;
       }
-      zero = (best < 0 || bmag == 0.0);
-      int bsel = 0;
-#pragma unroll
-      for (int ci = 0; ci < kCand; ++ci)
-        if (ci == best) {
-          atom = cand[ci];
-          coef = c[ci];
-          bsel = ci;
-        }
+      zero = (bat < 0 || bmag == 0.0);
+      atom = bat < 0 ? 0 : bat;
+      coef = bc;
 
       // 4. rank-1 update of this wave's rows and their squared norm.
       if (!zero) {
         const int q = (atom % K) / N, p = atom % N;
         const bool dc = (p == 0 && q == 0);
         float* rw = a.r32 + (size_t)node * K;
+        // the chosen atom's rows, read once (the constant atom is exactly
+        // 1/N: inv_n times 1)
+        double ty[PH], tx[PW];
+#pragma unroll
+        for (int dy = 0; dy < PH; ++dy) ty[dy] = sP[w][bsel][ry + dy];
+#pragma unroll
+        for (int dx = 0; dx < PW; ++dx) tx[dx] = sQ[w][bsel][px + dx];
+#pragma unroll
+        for (int dy = 0; dy < PH; ++dy) ty[dy] = dc ? inv_n : ty[dy];
+#pragma unroll
+        for (int dx = 0; dx < PW; ++dx) tx[dx] = dc ? 1.0 : tx[dx];
         double eh[PH];
 #pragma unroll
         for (int dy = 0; dy < PH; ++dy) {
-          const double ty = sP[w][bsel][ry + dy];
           f32v rn;
           eh[dy] = 0.0;
 #pragma unroll
           for (int dx = 0; dx < PW; ++dx) {
-            const double phi = dc ? inv_n : ty * sQ[w][bsel][px + dx];
+            const double phi = ty[dy] * tx[dx];
             rn[dx] = (float)fma(-coef, phi, rv[dy][dx]);
             eh[dy] = fma((double)rn[dx], (double)rn[dx], eh[dy]);
           }
@@ -386,13 +456,12 @@ __global__ __launch_bounds__(64 * SelCfg<N>::WPN * SelCfg<N>::NPG) void k_select
     if (valid) {
       // 5. record and stop test (a zero correlation stops without a record).
       // Every input of the test is uniform over the node's waves.
-      const JobDev& jb = a.jobs[a.lv.job[node]];
       uint8_t st = ST_ZERO;
       if (!zero) {
         st = ST_RUN;
-        if (e < jb.eps2[lg])
+        if (e < eps2)
           st = ST_ACC;
-        else if (t + 1 >= jb.k[lg])
+        else if (t + 1 >= kk)
           st = ST_SPARSE;
       }
       if (h == 0) {
