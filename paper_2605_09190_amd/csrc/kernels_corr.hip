@@ -911,6 +911,21 @@ __device__ inline void gen_trip(f32x16 (&acc)[G::MA][G::MB], GenFrag<G>& f, cons
   }
 }
 
+// The FP32 tables (nfam N x N, 1 KB blocks) into sT by direct-to-LDS loads,
+// block c = 4 i + wave, issued at kernel entry: no registers, and their
+// round trip overlaps that of the first tile's active-list loads.
+template <int N>
+__device__ inline void gen_table_dma(const float* tabT32, int nfam, float* sT) {
+  constexpr int MAXB = 2 * N * N * 4 / 1024;   // blocks of both families
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int nb = nfam * N * N * 4 / 1024;
+#pragma unroll
+  for (int i = 0; i < MAXB / 4; ++i) {
+    const int c = 4 * i + w;
+    if (c < nb) lds_dma16(tabT32, nb * 1024, (char*)sT + c * 1024, lane * 16, c * 1024);
+  }
+}
+
 // Every tile of one launch with node tiles of 32 MB nodes.
 template <int N, int MB>
 __device__ void gen_tiles(const uint16_t* __restrict__ X, const int32_t* __restrict__ act, int count,
@@ -948,6 +963,11 @@ __device__ void gen_tiles(const uint16_t* __restrict__ X, const int32_t* __restr
       const int pos = min(b0 + row, count - 1);
       p.b_off[i] = (uint32_t)(((size_t)act[pos] * K + gc * 8) * 2);
     }
+    // The table blocks (loaded before the active-list entries, and loads
+    // complete in order) have landed in every wave; the previous tile's
+    // epilogue is done with sK (= buffer 0).
+    AQMP_WAIT_VM(G::B_INS);
+    __syncthreads();
     // Rows of this lane: atom a0 + 64 wa + 32 ma + rr of family fam, i.e.
     // q = qb + (64 wa + 32 ma + rr) / N, p = (64 wa + 32 ma + rr) % N.
     GenLane<G> ln;
@@ -978,7 +998,6 @@ __device__ void gen_tiles(const uint16_t* __restrict__ X, const int32_t* __restr
         for (int r = 0; r < 16; ++r) acc[ma][mb][r] = 0.f;
     GenFrag<G> f;
 
-    __syncthreads();   // previous tile's epilogue is done with sK (= buffer 0)
     gen_dma<G>(p, rg.template buf<0>(), 0, 0, G::B_INS);
     gen_dma<G>(p, rg.template buf<1>(), 1, 0, G::B_INS);
     gen_dma<G>(p, rg.template buf<2>(), 2, 0, G::B_INS);
@@ -1023,12 +1042,13 @@ __global__ __launch_bounds__(256, 1) void k_corr_bf16_gen(const float* __restric
   __shared__ __attribute__((aligned(1024))) char sR1[kGenBufBytes];
   __shared__ __attribute__((aligned(1024))) char sR2[kGenBufBytes];
   __shared__ __attribute__((aligned(1024))) char sR3[kGenBufBytes];
-  __shared__ float sT[2 * K];   // [f][y][p] = fl32(T_f[p][y])
-  const int tid = threadIdx.x;
-  for (int i = tid; i < nfam * K / 4; i += 256) ((float4*)sT)[i] = ((const float4*)tabT32)[i];
-  __syncthreads();
+  __shared__ __attribute__((aligned(16))) float sT[2 * K];   // [f][y][p] = fl32(T_f[p][y])
+  gen_table_dma<N>(tabT32, nfam, sT);
   const int count = *act_count;
-  if (count <= 0) return;
+  if (count <= 0) {
+    AQMP_WAIT_VM(0);   // no load into LDS outlives the workgroup
+    return;
+  }
   const GenRing rg{sR0, sR1, sR2, sR3};
   // node-tile range: the tuned one when given, else 3..7 (N = 64), 1..7 (N = 32)
   const int mb_lo = tile_range ? (tile_range & 0xF) : (N == 64 ? 3 : 1);
@@ -1054,6 +1074,7 @@ __global__ __launch_bounds__(256, 1) void k_corr_bf16_gen(const float* __restric
       default: gen_tiles<N, 7>(X, act, count, keys, n_atom_tiles, nfam, sT, rg); break;
     }
   }
+  AQMP_WAIT_VM(0);   // a workgroup without a tile still waits for its table loads
 }
 
 // ---------------------------------------------------------------------------
