@@ -33,13 +33,13 @@ TAU_40K = 0.0075              # RMS tolerance at which the 2048x2048x3 workload 
 # profiles/traffic_k_select_2048x2048x3_ycbcr.md); valid only for the kernel
 # source and the workload they were taken on.
 _MP_SRC = dict(workload="c3", src="paper_2605_09190_amd/csrc/kernels_mp.hip",
-               sha256="15c6ff00192a461ad4dd60ad1e0a99d86bfda611ace6221666c81c68447adfc4")
+               sha256="45553f16cb303ee36623d2712813526f01bd307484efed3d672db2849a446a0d")
 TRAFFIC = {
-    "k_corr_bf16_gen<64>": dict(bytes_per_launch=15.69e6, fetch=13.28e6, write=2.41e6, workload="c3",
+    "k_corr_bf16_gen<64>": dict(bytes_per_launch=15.72e6, fetch=13.32e6, write=2.41e6, workload="c3",
                                 src="paper_2605_09190_amd/csrc/kernels_corr.hip",
-                                sha256="b3775b1b9612aaa553e2368099a2a8d2248cdbfc322bcf852338f0733eb8661e"),
-    "k_select<64>": dict(bytes_per_launch=51.61e6, fetch=22.57e6, write=29.04e6, **_MP_SRC),
-    "k_select<32>": dict(bytes_per_launch=21.04e6, fetch=9.22e6, write=11.82e6, **_MP_SRC),
+                                sha256="63a2e056697124a976d5e6c8cf6354f3e76ab995dd8e3366f2cdd3ba6353517e"),
+    "k_select<64>": dict(bytes_per_launch=51.51e6, fetch=22.47e6, write=29.04e6, **_MP_SRC),
+    "k_select<32>": dict(bytes_per_launch=20.98e6, fetch=9.16e6, write=11.82e6, **_MP_SRC),
 }
 
 
