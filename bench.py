@@ -37,7 +37,7 @@ _MP_SRC = dict(workload="c3", src="paper_2605_09190_amd/csrc/kernels_mp.hip",
 TRAFFIC = {
     "k_corr_bf16_gen<64>": dict(bytes_per_launch=15.72e6, fetch=13.32e6, write=2.41e6, workload="c3",
                                 src="paper_2605_09190_amd/csrc/kernels_corr.hip",
-                                sha256="63a2e056697124a976d5e6c8cf6354f3e76ab995dd8e3366f2cdd3ba6353517e"),
+                                sha256="838ba24a85d0bd586b2844b584e35206c74b9daba940cd60689c2a5d2c39024e"),
     "k_select<64>": dict(bytes_per_launch=51.51e6, fetch=22.47e6, write=29.04e6, **_MP_SRC),
     "k_select<32>": dict(bytes_per_launch=20.98e6, fetch=9.16e6, write=11.82e6, **_MP_SRC),
 }

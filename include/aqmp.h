@@ -143,9 +143,13 @@ typedef struct {
                           BF16 form one MP step per launch (correlation
                           and select) instead of the whole-level
                           pursuit; same method, for comparison. */
-  int32_t corr_variant;  /* tuning: 0 = library default; 1..6 force one
-                            family of BF16 correlation kernels (results
-                            are identical, only speed differs) */
+  int32_t corr_variant;  /* tuning: 0 = library default; 2, 3 or 6 force
+                            one family of BF16 correlation kernels (results
+                            are identical, only speed differs): 2 direct-
+                            to-LDS loads, two workgroups per CU (N >= 16);
+                            3 register-staged loads (every N); 6 atoms
+                            generated in registers (N = 32, 64; other N
+                            take 3).  Other values are AQMP_E_INVALID. */
   int32_t solver;      /* AQMP_SOLVER_DENSE: every MP step correlates the
                           residual with all M atoms (Section 2.2, eq. (1)),
                           in the precision above.
@@ -167,7 +171,7 @@ typedef struct {
                           exceed AQMP_OMP_MAX_ATOMS; precision and
                           corr_variant do not apply. */
   uint32_t corr_variant_levels;  /* tuning, per block size: bits 4 lg .. 4 lg + 3
-                                    hold the BF16 correlation variant (0..6) for
+                                    hold the BF16 correlation variant (0, 2, 3, 6) for
                                     N = 2^lg, 2 <= lg <= 6; a zero nibble takes
                                     corr_variant.  An autotuner fills it from
                                     timed encodes of the caller's workload. */

@@ -148,13 +148,17 @@ def _stream_handle(stream) -> int | None:
     return stream.cuda_stream
 
 
+# The BF16 correlation variants of the library (0 = its default per block size).
+CORR_VARIANTS = (0, 2, 3, 6)
+
+
 def pack_variant_levels(per_n) -> int:
     """{N: variant} -> the aqmp_options.corr_variant_levels word (one nibble
     per block size, at bits 4 log2(N))."""
     word = 0
     for n, v in dict(per_n).items():
         lg = int(n).bit_length() - 1
-        if 1 << lg != int(n) or not 2 <= lg <= 6 or not 0 <= int(v) <= 6:
+        if 1 << lg != int(n) or not 2 <= lg <= 6 or int(v) not in CORR_VARIANTS:
             raise ValueError(f"bad per-level variant {n}: {v}")
         word |= int(v) << (4 * lg)
     return word

@@ -38,7 +38,7 @@ import os
 import time
 
 # Kernel families worth timing per block size (the others map onto these).
-CANDIDATES = {64: (6, 5, 1, 2, 3), 32: (6, 5, 1, 2, 3, 4), 16: (2, 5, 1, 3, 4)}
+CANDIDATES = {64: (6, 2), 32: (6, 2), 16: (2, 3)}
 DEFAULT = {64: 6, 32: 6, 16: 2}
 # Node-tile ranges (lo, hi) of the generated-atom kernel worth timing.
 TILE_CANDIDATES = {64: ((3, 7), (4, 7), (5, 7), (2, 7), (3, 5)), 32: ((1, 7), (2, 7), (3, 7), (1, 4), (2, 5))}

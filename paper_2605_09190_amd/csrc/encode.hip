@@ -183,12 +183,12 @@ int validate(const aqmp_dict* d, const aqmp_image* imgs, int n_imgs, const aqmp_
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad schedule");
     if (opt->flags & ~(AQMP_OPT_TIMING | AQMP_OPT_STEPWISE))
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: unknown option flags");
-    if (opt->corr_variant < 0 || opt->corr_variant > 6)
-      AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad corr_variant");
+    if (!corr_variant_valid(opt->corr_variant))
+      AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad corr_variant (0, 2, 3 or 6)");
     if (opt->corr_variant_levels & ~0x7FFFF00u)
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: corr_variant_levels has bits outside the block sizes 4..64");
     for (int lg = 2; lg <= 6; ++lg)
-      if (((opt->corr_variant_levels >> (4 * lg)) & 0xFu) > 6)
+      if (!corr_variant_valid((int)((opt->corr_variant_levels >> (4 * lg)) & 0xFu)))
         AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad corr_variant_levels entry for N = " + std::to_string(1 << lg));
     if (opt->solver != AQMP_SOLVER_DENSE && opt->solver != AQMP_SOLVER_GRAM && opt->solver != AQMP_SOLVER_OMP)
       AQMP_FAIL(AQMP_E_INVALID, "aqmp_encode: bad solver");

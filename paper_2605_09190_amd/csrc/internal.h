@@ -237,6 +237,8 @@ hipError_t launch_export_write(const ExportSeg* segs, int nseg, const uint32_t* 
 // Name of the correlation kernel launch_corr runs (or the fused pursuit for
 // n <= kFusedMaxN); "" when the combination is invalid.
 const char* corr_kernel_name(int n, int precision, int variant);
+// The BF16 correlation variants the library has: 0 (default), 2, 3, 6.
+inline bool corr_variant_valid(int v) { return v == 0 || v == 2 || v == 3 || v == 6; }
 
 // Tile geometry of the correlation kernel per block size (atoms per tile).
 int corr_atom_tile(int n);

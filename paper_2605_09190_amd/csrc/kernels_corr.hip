@@ -335,6 +335,8 @@ struct DmaGeo {
 
 // vmcnt(n) with the other counters left alone (gfx9 encoding).
 #define AQMP_WAIT_VM(n) __builtin_amdgcn_s_waitcnt(((n) & 0xF) | (0x7 << 4) | (0xF << 8) | ((((n) >> 4) & 0x3) << 14))
+// lgkmcnt(0) and vmcnt(n) together (gfx9 encoding, expcnt left alone).
+#define AQMP_WAIT_VM_LGKM0(n) __builtin_amdgcn_s_waitcnt(((n) & 0xF) | (0x7 << 4) | ((((n) >> 4) & 0x3) << 14))
 
 // DMA addressing: buffer loads with an SGPR resource per operand, a 32-bit
 // per-lane byte offset (one VGPR each) and a wave-uniform SGPR offset for the
@@ -505,207 +507,6 @@ __global__ __launch_bounds__(256, MINB) void k_corr_bf16_dma(const uint16_t* __r
     AQMP_DMA_TAIL(3, sA0, sB0, sA2, sB2)
     static_assert(NST - S0 <= 4, "tail covers the remaining stages");
 #undef AQMP_DMA_TAIL
-    __syncthreads();   // all waves done reading the ring before sK reuses sA0
-    epilogue<typename G::C>(acc, sK, a0, a_tile, n_atom_tiles, b0, count, keys);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// BF16, large blocks, software-pipelined form of the direct-to-LDS kernel.
-//
-// Same tile (256 x 128), BK = 64 (every lane request covers a whole 128-byte
-// line of a row slice) and three-stage ring, one workgroup per CU, but the
-// wave never stalls in long runs of memory instructions: the 12 loads of
-// stage s + 2 are spread over the MFMAs of the first three k-steps of stage
-// s (one after every second MFMA), and the wait + barrier that publishes
-// stage s + 1 sits inside the last k-step of stage s, so the first fragments
-// of stage s + 1 are read while the last MFMAs of stage s run.  Fragments are
-// double-buffered in registers across k-steps and across stages.  The MFMA
-// sequence (and so every accumulator bit) is the one of the other forms.
-// ---------------------------------------------------------------------------
-template <class G>
-struct PipeFrag {
-  bf16x8 a[2][G::MA];
-  bf16x8 b[2][G::MB];
-};
-
-// One DMA instruction (compile-time index I of the wave's 12) of stage s.
-template <class G, int K, int I>
-__device__ inline void dma_one(const DmaPtrs<G>& p, char* sa, char* sb, int s) {
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int kofs = s * G::BK * 2;
-  if constexpr (I < G::A_INS) {
-    lds_dma16(p.a_base, p.a_bytes, sa + (w * G::A_INS + I) * 1024, (int)p.a_off[I & 1],
-              (int)p.a_sofs + I * G::RPB * K * 2 + kofs);
-  } else {
-    constexpr int J = I - G::A_INS;
-    lds_dma16(p.b_base, (int)0xFFFFFFFFu, sb + (w * G::B_INS + J) * 1024, (int)p.b_off[J], kofs);
-  }
-}
-
-template <class G, int KK>
-__device__ inline void pipe_read(PipeFrag<G>& f, const char* sa, const char* sb, const int (&off)[G::BK / 16]) {
-  const int w = threadIdx.x >> 6;
-  const int wa = w % G::WA, wb = w / G::WA;
-  const char* pa = sa + wa * G::WTA * G::ROWB;
-  const char* pb = sb + wb * G::WTB * G::ROWB;
-  constexpr int P = KK & 1;
-#pragma unroll
-  for (int ma = 0; ma < G::MA; ++ma) f.a[P][ma] = *(const bf16x8*)(pa + ma * 32 * G::ROWB + off[KK]);
-#pragma unroll
-  for (int mb = 0; mb < G::MB; ++mb) f.b[P][mb] = *(const bf16x8*)(pb + mb * 32 * G::ROWB + off[KK]);
-  __builtin_amdgcn_sched_barrier(0);   // reads go out before the MFMAs that follow
-}
-
-// MFMAs of k-step KK; with DMA, loads KK*4 .. KK*4+3 of stage s_dma go out
-// after MFMAs 1, 3, 5 and 7.
-template <class G, int K, int KK, bool DMA>
-__device__ inline void pipe_mfma(f32x16 (&acc)[G::MA][G::MB], const PipeFrag<G>& f, const DmaPtrs<G>& p, char* da,
-                                 char* db, int s_dma) {
-  constexpr int P = KK & 1;
-  static_assert(G::MA * G::MB == 8 && G::INS == 12, "pipeline pattern: 8 MFMAs and 4 loads per k-step");
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int ma = i / G::MB, mb = i % G::MB;
-    acc[ma][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[P][ma], f.b[P][mb], acc[ma][mb], 0, 0, 0);
-    if constexpr (DMA && KK < 3) {
-      if ((i & 1) == 1) {
-        switch (KK * 4 + i / 2) {
-          case 0: dma_one<G, K, 0>(p, da, db, s_dma); break;
-          case 1: dma_one<G, K, 1>(p, da, db, s_dma); break;
-          case 2: dma_one<G, K, 2>(p, da, db, s_dma); break;
-          case 3: dma_one<G, K, 3>(p, da, db, s_dma); break;
-          case 4: dma_one<G, K, 4>(p, da, db, s_dma); break;
-          case 5: dma_one<G, K, 5>(p, da, db, s_dma); break;
-          case 6: dma_one<G, K, 6>(p, da, db, s_dma); break;
-          case 7: dma_one<G, K, 7>(p, da, db, s_dma); break;
-          case 8: dma_one<G, K, 8>(p, da, db, s_dma); break;
-          case 9: dma_one<G, K, 9>(p, da, db, s_dma); break;
-          case 10: dma_one<G, K, 10>(p, da, db, s_dma); break;
-          default: dma_one<G, K, 11>(p, da, db, s_dma); break;
-        }
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-  }
-}
-
-// lgkmcnt(0) and vmcnt(n) together (gfx9 encoding, expcnt left alone).
-#define AQMP_WAIT_VM_LGKM0(n) __builtin_amdgcn_s_waitcnt(((n) & 0xF) | (0x7 << 4) | ((((n) >> 4) & 0x3) << 14))
-
-// Stage s computed from (ca, cb); DMA: loads of stage s + 2 into (da, db);
-// NEXT: stage s + 1 (in (na, nb)) follows and its first fragments are read
-// here.  Loads complete in order, so after this wave's loads of stage s + 2
-// are out, vmcnt(12) (vmcnt(0) without them) means stage s + 1 has landed.
-template <class G, int K, bool DMA, bool NEXT>
-__device__ inline void pipe_stage(f32x16 (&acc)[G::MA][G::MB], PipeFrag<G>& f, const DmaPtrs<G>& p,
-                                  const char* ca, const char* cb, const char* na, const char* nb, char* da, char* db,
-                                  int s, const int (&off)[G::BK / 16]) {
-  pipe_read<G, 1>(f, ca, cb, off);
-  pipe_mfma<G, K, 0, DMA>(acc, f, p, da, db, s + 2);
-  pipe_read<G, 2>(f, ca, cb, off);
-  pipe_mfma<G, K, 1, DMA>(acc, f, p, da, db, s + 2);
-  pipe_read<G, 3>(f, ca, cb, off);
-  pipe_mfma<G, K, 2, DMA>(acc, f, p, da, db, s + 2);
-  if constexpr (NEXT) {
-    // every wave is done with this stage's fragment reads before any wave
-    // passes, so the loads issued after the barrier may overwrite (ca, cb)
-    if constexpr (DMA) AQMP_WAIT_VM_LGKM0(G::INS);
-    else AQMP_WAIT_VM_LGKM0(0);
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_sched_barrier(0);
-    pipe_read<G, 0>(f, na, nb, off);
-  }
-  pipe_mfma<G, K, 3, DMA>(acc, f, p, da, db, s + 2);
-}
-
-template <int N, int BK>
-__global__ __launch_bounds__(256, 1) void k_corr_bf16_pipe(const uint16_t* __restrict__ D,
-                                                           const uint16_t* __restrict__ X,
-                                                           const int32_t* __restrict__ act,
-                                                           const int32_t* __restrict__ act_count,
-                                                           unsigned long long* __restrict__ keys, int n_atom_tiles) {
-  using G = DmaGeo<BK>;
-  constexpr int K = N * N;
-  constexpr int NST = K / G::BK;
-  static_assert(K % G::BK == 0 && NST >= 2, "stages");
-  __shared__ __attribute__((aligned(1024))) char sA0[G::A_BYTES];
-  __shared__ __attribute__((aligned(1024))) char sA1[G::A_BYTES];
-  __shared__ __attribute__((aligned(1024))) char sA2[G::A_BYTES];
-  __shared__ __attribute__((aligned(1024))) char sB0[G::B_BYTES];
-  __shared__ __attribute__((aligned(1024))) char sB1[G::B_BYTES];
-  __shared__ __attribute__((aligned(1024))) char sB2[G::B_BYTES];
-  static_assert(G::WA * G::BB * kTopR * 4 <= G::A_BYTES, "epilogue scratch fits one A buffer");
-  uint32_t* sK = (uint32_t*)sA0;
-
-  const int count = *act_count;
-  const int ntB = (count + G::BB - 1) / G::BB;
-  const int ntiles = n_atom_tiles * ntB;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int fr = G::swz(lane & 31);
-  int off[G::BK / 16];
-#pragma unroll
-  for (int kk = 0; kk < G::BK / 16; ++kk) off[kk] = (lane & 31) * G::ROWB + (((2 * kk + (lane >> 5)) ^ fr) << 4);
-  const int drow = lane / G::CPR, dslot = lane % G::CPR;
-  TileWalk walk(ntiles);
-  for (int j = walk.slot; j < walk.chunk; j += walk.per) {
-    const int tile = walk.tile(j);
-    if (tile >= ntiles) break;
-    const int a_tile = tile / ntB, b_tile = tile % ntB;
-    const int a0 = a_tile * G::BA, b0 = b_tile * G::BB;
-    DmaPtrs<G> p;
-    const int wu = __builtin_amdgcn_readfirstlane(w);
-    p.a_base = D;
-    p.b_base = X;
-    p.a_bytes = n_atom_tiles * G::BA * K * 2;
-    p.a_sofs = (uint32_t)((a0 + wu * G::A_INS * G::RPB) * K * 2);
-#pragma unroll
-    for (int par = 0; par < 2; ++par) {
-      const int gc = dslot ^ G::swz(par * G::RPB + drow);
-      p.a_off[par] = (uint32_t)((drow * K + gc * 8) * 2);
-    }
-#pragma unroll
-    for (int i = 0; i < G::B_INS; ++i) {
-      const int row = (w * G::B_INS + i) * G::RPB + drow;
-      const int gc = dslot ^ G::swz(row);
-      const int pos = min(b0 + row, count - 1);
-      p.b_off[i] = (uint32_t)(((size_t)act[pos] * K + gc * 8) * 2);
-    }
-    f32x16 acc[G::MA][G::MB];
-#pragma unroll
-    for (int ma = 0; ma < G::MA; ++ma)
-#pragma unroll
-      for (int mb = 0; mb < G::MB; ++mb)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[ma][mb][r] = 0.f;
-    PipeFrag<G> f;
-
-    __syncthreads();   // previous tile's epilogue is done with sK (= sA0)
-    dma_issue<G, K>(p, sA0, sB0, 0);
-    dma_issue<G, K>(p, sA1, sB1, 1);
-    AQMP_WAIT_VM(G::INS);
-    __builtin_amdgcn_s_barrier();
-    pipe_read<G, 0>(f, sA0, sB0, off);
-    // Steady state: stages that load stage s + 2 and hand over to s + 1.
-    constexpr int FULL = NST - 2;
-    constexpr int TRIPS = FULL / 3;
-    for (int t = 0; t < TRIPS; ++t) {
-      const int s = 3 * t;
-      pipe_stage<G, K, true, true>(acc, f, p, sA0, sB0, sA1, sB1, sA2, sB2, s, off);
-      pipe_stage<G, K, true, true>(acc, f, p, sA1, sB1, sA2, sB2, sA0, sB0, s + 1, off);
-      pipe_stage<G, K, true, true>(acc, f, p, sA2, sB2, sA0, sB0, sA1, sB1, s + 2, off);
-    }
-    constexpr int S0 = 3 * TRIPS;
-    static_assert(NST - S0 >= 2 && NST - S0 <= 4, "tail covers the remaining stages");
-#define AQMP_PIPE_TAIL(I, CA, CB, NA, NB, DA, DB)                                                     \
-    if constexpr (S0 + (I) < NST)                                                                     \
-      pipe_stage<G, K, (S0 + (I) + 2 < NST), (S0 + (I) + 1 < NST)>(acc, f, p, CA, CB, NA, NB, DA, DB, \
-                                                                    S0 + (I), off);
-    AQMP_PIPE_TAIL(0, sA0, sB0, sA1, sB1, sA2, sB2)
-    AQMP_PIPE_TAIL(1, sA1, sB1, sA2, sB2, sA0, sB0)
-    AQMP_PIPE_TAIL(2, sA2, sB2, sA0, sB0, sA1, sB1)
-    AQMP_PIPE_TAIL(3, sA0, sB0, sA1, sB1, sA2, sB2)
-#undef AQMP_PIPE_TAIL
     __syncthreads();   // all waves done reading the ring before sK reuses sA0
     epilogue<typename G::C>(acc, sK, a0, a_tile, n_atom_tiles, b0, count, keys);
   }
@@ -1187,8 +988,6 @@ __global__ __launch_bounds__(256, 1) void k_corr_f32(const float* __restrict__ D
 }
 
 using CfgBig = Cfg<256, 128, 64, 2, 2>;     // N >= 16, BF16
-using CfgNarrow = Cfg<256, 32, 64, 4, 1>;   // N = 16, 32, BF16, narrow node tiles
-using CfgNarrow8 = Cfg<128, 32, 64, 4, 1>;  // N = 8, BF16, narrow node tiles
 using CfgMid = Cfg<128, 128, 64, 2, 2>;     // N = 8, BF16
 using CfgSmall = Cfg<32, 256, 16, 1, 4>;    // N = 4, BF16
 using CfgBigF = Cfg<256, 128, 32, 2, 2>;    // N >= 16, FP32
@@ -1207,39 +1006,28 @@ int corr_atom_tile(int n) { return n >= 16 ? 256 : (n == 8 ? 128 : 32); }
 
 int corr_grid(int, int) { return kCorrGrid; }
 
-// Correlation kernel variants (BF16); 0 picks the default.
-//   1: direct-to-LDS, BK 64, three stages, one workgroup per CU (N >= 16);
-//   2: direct-to-LDS, BK 32, three stages, two workgroups per CU (N >= 16);
-//   3: register-staged loads, BK 64, 256 x 128 tiles;
-//   4: as 2 for N = 64; register-staged narrow node tiles (32 nodes) for
-//      N <= 32, so that the few nodes x atoms of the small levels still
-//      spread over every CU.
+// Correlation kernel variants (BF16); 0 picks the default.  All sum the same
+// products in the same order, so the keys are bit-identical.
+//   2: direct-to-LDS loads, BK 32, three stages, two workgroups per CU
+//      (N >= 16; the default of the step-by-step N = 16 level);
+//   3: register-staged loads, BK 64, 256 x 128 tiles (every N; the form
+//      used when a residual buffer exceeds the 32-bit offsets of the
+//      direct-to-LDS loads);
+//   6: atoms generated in registers (N = 32, 64; the default there).
+// Numbers 1, 4 and 5 named forms that never won a timing (one workgroup per
+// CU with BK 64, narrow register-staged tiles, a two-operand software
+// pipeline) and were removed; they are rejected.
 template <int N>
 static void launch_corr_n(int precision, int variant, const void* atoms, const StepArgs& a, int nat, hipStream_t s,
                           hipEvent_t e0, hipEvent_t e1) {
   using CB = typename std::conditional<(N >= 16), CfgBig, typename std::conditional<(N == 8), CfgMid, CfgSmall>::type>::type;
   using CF = typename std::conditional<(N >= 16), CfgBigF, typename std::conditional<(N == 8), CfgMidF, CfgSmallF>::type>::type;
   if (variant == 0) variant = default_variant(N);
-  if constexpr (N <= 32 && N >= 8) {
-    if (precision == AQMP_PREC_BF16 && variant == 4) {
-      using CN = typename std::conditional<(N == 8), CfgNarrow8, CfgNarrow>::type;
-      launch_timed((k_corr_bf16<N, CN>), dim3(2 * kCorrGrid), dim3(256), s, e0, e1, (const uint16_t*)atoms, a.r16,
-                         a.act, a.act_count, a.keys, nat);
-      return;
-    }
-  }
-  if (variant == 4) variant = 2;
   if (precision == AQMP_PREC_BF16) {
     if constexpr (N >= 16) {
-      if (variant == 1)
-        launch_timed((k_corr_bf16_dma<N, 64, 1>), dim3(kCorrGrid), dim3(256), s, e0, e1, (const uint16_t*)atoms,
-                           a.r16, a.act, a.act_count, a.keys, nat);
-      else if (variant == 6 && N >= 32)
+      if (variant == 6 && N >= 32)
         launch_timed((k_corr_bf16_gen<(N >= 32 ? N : 32)>), dim3(kCorrGrid), dim3(256), s, e0, e1, a.tabT32,
                            a.nfam, a.r16, a.act, a.act_count, a.keys, nat, (int)a.corr_tile);
-      else if (variant == 5)
-        launch_timed((k_corr_bf16_pipe<N, 64>), dim3(kCorrGrid), dim3(256), s, e0, e1, (const uint16_t*)atoms, a.r16,
-                           a.act, a.act_count, a.keys, nat);
       else if (variant == 2)
         launch_timed((k_corr_bf16_dma<N, 32, 2>), dim3(2 * kCorrGrid), dim3(256), s, e0, e1, (const uint16_t*)atoms,
                            a.r16, a.act, a.act_count, a.keys, nat);
@@ -1258,7 +1046,7 @@ static void launch_corr_n(int precision, int variant, const void* atoms, const S
 
 const char* corr_kernel_name(int n, int precision, int variant) {
   if (n < AQMP_MIN_N || n > AQMP_MAX_N || (n & (n - 1))) return "";
-  if (variant < 0 || variant > 6) return "";
+  if (!corr_variant_valid(variant)) return "";
   if (precision != AQMP_PREC_FP32 && precision != AQMP_PREC_BF16) return "";
   static const char* const fused[] = {"", "", "k_mp_fused<4>", "k_mp_fused<8>"};
   if (n == 8 && precision == AQMP_PREC_BF16) return "k_pursuit8_bf16<16>";
@@ -1267,14 +1055,9 @@ const char* corr_kernel_name(int n, int precision, int variant) {
   const int li = ilog2(n) - 4;
   if (precision == AQMP_PREC_FP32) return f32[li];
   if (variant == 0) variant = default_variant(n);
-  if (variant == 4) return n <= 32 ? (n == 16 ? "k_corr_bf16<16,narrow>" : "k_corr_bf16<32,narrow>") : "k_corr_bf16_dma<64,32,2>";
-  static const char* const v1[] = {"k_corr_bf16_dma<16,64,1>", "k_corr_bf16_dma<32,64,1>", "k_corr_bf16_dma<64,64,1>"};
   static const char* const v2[] = {"k_corr_bf16_dma<16,32,2>", "k_corr_bf16_dma<32,32,2>", "k_corr_bf16_dma<64,32,2>"};
   static const char* const v3[] = {"k_corr_bf16<16>", "k_corr_bf16<32>", "k_corr_bf16<64>"};
-  static const char* const v5[] = {"k_corr_bf16_pipe<16,64>", "k_corr_bf16_pipe<32,64>", "k_corr_bf16_pipe<64,64>"};
-  if (variant == 1) return v1[li];
   if (variant == 2) return v2[li];
-  if (variant == 5) return v5[li];
   if (variant == 6) return n == 64 ? "k_corr_bf16_gen<64>" : (n == 32 ? "k_corr_bf16_gen<32>" : v3[li]);
   return v3[li];
 }

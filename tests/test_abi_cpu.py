@@ -100,9 +100,12 @@ def test_corr_kernel_names():
     from paper_2605_09190_amd import aqmp as A
     assert A.corr_kernel(64, A.PREC_BF16) == "k_corr_bf16_gen<64>"
     assert A.corr_kernel(32, A.PREC_BF16) == "k_corr_bf16_gen<32>"
-    assert A.corr_kernel(32, A.PREC_BF16, 5) == "k_corr_bf16_pipe<32,64>"
+    assert A.corr_kernel(32, A.PREC_BF16, 2) == "k_corr_bf16_dma<32,32,2>"
+    assert A.corr_kernel(32, A.PREC_BF16, 3) == "k_corr_bf16<32>"
     assert A.corr_kernel(16, A.PREC_BF16) == "k_corr_bf16_dma<16,32,2>"
-    assert A.corr_kernel(64, A.PREC_BF16, 5) == "k_corr_bf16_pipe<64,64>"
+    assert A.corr_kernel(16, A.PREC_BF16, 6) == "k_corr_bf16<16>"       # generated atoms: N >= 32 only
+    for removed in (1, 4, 5):                                             # removed forms are rejected
+        assert A.corr_kernel(64, A.PREC_BF16, removed) == ""
     assert A.corr_kernel(64, A.PREC_FP32) == "k_corr_f32<64>"
     assert A.corr_kernel(8, A.PREC_BF16) == "k_pursuit8_bf16<16>"
     assert A.corr_kernel(8, A.PREC_FP32) == "k_mp_fused<8>"

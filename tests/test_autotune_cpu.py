@@ -26,8 +26,8 @@ def test_pack_variant_levels():
     except ImportError:
         pytest.skip("library not built")
     assert A.pack_variant_levels({}) == 0
-    assert A.pack_variant_levels({64: 5, 32: 1, 16: 4}) == (5 << 24) | (1 << 20) | (4 << 16)
-    for bad in ({48: 1}, {128: 1}, {2: 1}, {64: 7}, {64: -1}):
+    assert A.pack_variant_levels({64: 6, 32: 3, 16: 2}) == (6 << 24) | (3 << 20) | (2 << 16)
+    for bad in ({48: 2}, {128: 2}, {2: 2}, {64: 7}, {64: -1}, {64: 1}, {32: 4}, {16: 5}):
         with pytest.raises(ValueError):
             A.pack_variant_levels(bad)
 
@@ -51,7 +51,7 @@ def test_cache_key_and_round_trip(tmp_path):
     assert k1 != T.cache_key([Img(64, 48, "float32")], prm, [(0, 0)], "other", "abc")
     path = str(tmp_path / "c.json")
     assert T.cache_load(path, k1) is None
-    opt = dict(corr_variant_levels={64: 5}, corr_tile_levels={32: (2, 5)}, stepwise=False, schedule=1)
+    opt = dict(corr_variant_levels={64: 2}, corr_tile_levels={32: (2, 5)}, stepwise=False, schedule=1)
     T.cache_store(path, k1, dict(options=T._options_to_json(opt), measured={}))
     T.cache_store(path, "other", dict(options=T._options_to_json(opt), measured={}))
     got = T.cache_load(path, k1)

@@ -47,7 +47,7 @@ def _bytes(code):
     return e.leaves.tobytes(), e.atom_idx.tobytes(), e.coef.tobytes()
 
 
-@pytest.mark.parametrize("levels", [{64: 5, 32: 1}, {64: 2, 32: 4}, {64: 3, 32: 5, 16: 1}])
+@pytest.mark.parametrize("levels", [{64: 2, 32: 3}, {64: 3, 32: 2}, {64: 2, 32: 6, 16: 3}])
 def test_per_level_variants_are_bit_identical(A, dic, levels):
     w = workload("c1")
     imgs = [_dev(w["channels"][0])]
@@ -63,10 +63,10 @@ def test_per_level_variants_are_bit_identical(A, dic, levels):
 def test_bad_level_word_is_rejected(A, dic, monkeypatch):
     imgs = [_dev(piecewise_image(64, 64, seed=2))]
     p = dict(tol=0.02, max_atoms=8, n_min=8, n_max=32)
-    for word in (7 << 24, 1 << 4, 1 << 28):
+    for word in (7 << 24, 1 << 24, 5 << 20, 4 << 16, 2 << 4, 2 << 28):
         monkeypatch.setattr(A, "pack_variant_levels", lambda _d, word=word: word)
         with pytest.raises(Exception, match="corr_variant_levels"):
-            A.Code(dic, imgs, [p], [(0, 0)], precision=1, schedule=1, corr_variant_levels={64: 1})
+            A.Code(dic, imgs, [p], [(0, 0)], precision=1, schedule=1, corr_variant_levels={64: 2})
 
 
 def test_tuned_options_run_and_match_the_oracle(A, dic):
