@@ -2,7 +2,8 @@
 to 4096x3072) x 32 random-search trials (RMS tolerance, k, N_min, N_max) =
 512 jobs encoded together in one captured graph, checked against the oracle
 on a seeded sample of jobs and top-level blocks (top-level quadtrees are
-independent, so a sampled block is compared exactly).
+independent, so a sampled block is compared exactly): 128 jobs in the BF16
+form, 48 each for the Gram and OMP solvers, the oracle on a process pool.
 
 Forms: the BF16 batched form over all 512 jobs; the plain FP32 form over a
 subset of jobs; the Gram and OMP solvers over all 512 jobs.
@@ -61,15 +62,22 @@ def _sample(w, n_jobs, seed):
 
 
 def _check(w, exp, picks, tol, solver="mp", job_map=None):
+    """Each picked (job, top-level block) node by node against the oracle,
+    which runs on a process pool (one task per block)."""
     rep = PU.Report()
+    tasks = []
     for j, blk in picks:
         ci, pi = w["jobs"][j]
+        tasks.append((w["channels"][ci], dict(w["params"][pi], solver=solver), [blk]))
+    _say("  oracle on", len(tasks), "blocks,", PU.pool_size(), "processes")
+    onodes_all = PU.oracle_jobs_parallel(tasks)
+    for (j, blk), onodes in zip(picks, onodes_all):
+        ci, pi = w["jobs"][j]
         img = w["channels"][ci]
-        p = O.Params.from_dict(dict(w["params"][pi], solver=solver))
-        onodes = O.encode_channel(img, p, blocks=[blk])
         gj = j if job_map is None else job_map[j]
-        PU.compare_job(img, onodes, PU.gpu_nodes_by_key(exp, gj), tol, p.n_max, rep=rep, solver=solver)
-        _say("  job", j, "block", blk, "nodes so far", rep.nodes, "failures", len(rep.failures))
+        PU.compare_job(img, onodes, PU.gpu_nodes_by_key(exp, gj), tol, w["params"][pi]["n_max"], rep=rep,
+                       solver=solver)
+    _say("  compared", len(picks), "blocks,", rep.nodes, "nodes, failures", len(rep.failures))
     return rep
 
 
@@ -89,12 +97,12 @@ def test_sweep_bf16_batched_sampled_parity(A, dic, sweep):
     _say("stats", st["nodes"], st["iters_executed"])
     exp = code.export_nodes()
     code.free()
-    picks = _sample(sweep, 16, seed=41)
-    _say("picks", picks)
+    picks = _sample(sweep, 128, seed=41)
+    _say("picks", picks[:8], "...")
     rep = _check(sweep, exp, picks, TOL["bf16"])
     _say(rep.summary())
     assert rep.ok(), rep.summary()
-    assert rep.nodes >= 16
+    assert rep.nodes >= 128
 
 
 @pytest.mark.timeout(900)
@@ -119,7 +127,7 @@ def test_sweep_solvers_sampled_parity(A, dic, sweep, solver):
     code, imgs = _encode(A, dic, sweep, sweep["jobs"], schedule=A.SCHED_BATCHED, solver=sv)
     exp = code.export_nodes()
     code.free()
-    picks = _sample(sweep, 8, seed=43 if solver == "gram" else 44)
+    picks = _sample(sweep, 48, seed=43 if solver == "gram" else 44)
     rep = _check(sweep, exp, picks, TOL[solver], solver="omp" if solver == "omp" else "mp")
     _say(rep.summary())
     assert rep.ok(), rep.summary()
