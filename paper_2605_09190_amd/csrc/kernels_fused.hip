@@ -129,32 +129,42 @@ __global__ __launch_bounds__(256) void k_mp_fused(const JobDev* __restrict__ job
 
 // ---------------------------------------------------------------------------
 // Whole-level pursuit for N = 16 in the BF16 form.  At N = 16 one MP step of
-// a node is 262 K multiply-adds: a batched launch per step is mostly launch
-// latency and dependent memory chains.  One workgroup takes 32 nodes through
-// their whole pursuit (Section 2.2 steps (a)-(d), eq. (2)) with every array
-// in LDS:
-//   C   correlation of all 512 atoms with the 32 BF16 residuals by MFMA
-//       (32x32x16, FP32 accumulation, pixel order as in the batched kernels);
-//       the A operand is generated in registers from the FP32 1D tables,
-//       bf16(T32_f[p][y] * T32_f[q][x]), the canonical BF16 atom;
-//   E   each wave keeps, per node, the best 8 keys of its 128 atoms
-//       (branch-free sorting networks, as in the batched epilogue);
-//   M   the four wave lists are merged into the node's 8 candidates, ordered
-//       by (|c| key, lower atom), the same ranking as the batched path;
-//   S   one thread per (node, candidate) re-scores in FP64 against the FP32
-//       residual, separably (Section 2.1 outer product);
-//   A   arg-max (lowest atom on ties), rank-1 update in FP64 rounded to FP32,
-//       ||r||^2 in FP64, record (i, c_i), stop test of eq. (2).
-// Up to 32 MP steps run inside the kernel; a node that stops keeps its slot
-// (its correlation is still computed, its state no longer changes).
+// a node is 131 K multiply-adds: a batched launch per step would be mostly
+// launch latency and dependent memory chains.  Here one workgroup of eight
+// waves runs 16 node slots through their whole pursuits (Section 2.2 steps
+// (a)-(d), eq. (2)) with every array in LDS or registers:
+//   C  correlation of all 512 atoms with the 16 BF16 residuals by
+//      v_mfma_f32_16x16x32_bf16 (A = 16 atoms x 32 pixels, B = 32 pixels x
+//      16 slots, FP32 accumulation, pixel order as in the batched kernels).
+//      Wave w holds atoms f = w / 4, q = 4 (w % 4) + ma (ma < 4), all p: the
+//      canonical BF16 atoms bf16(T32_f[p][y] T32_f[q][x]), generated once
+//      per kernel into registers (32 fragments);
+//   E  each lane ranks its 16 correlations of one slot as 32-bit keys (|c|
+//      bits, then 511 - atom), keeps the best 8 with sorting networks and
+//      merges them with the slot's other three lanes of the wave;
+//   M  the slot's eight wave lists are merged into its 8 candidates (the
+//      same ranking as the batched path);
+//   S  FP64 re-score of the candidates against the FP32 residual,
+//      separably (Section 2.1 outer product): a slot is one DPP row of 16
+//      lanes, lane = a 4 x 4 pixel patch, and the eight candidate sums are
+//      reduced over the row by exchanging halves of the list;
+//   A  arg-max (lowest atom on ties), rank-1 update of the lane's patch in
+//      FP64 rounded to FP32, ||r||^2 in FP64, record (i, c_i), stop test.
+// A slot whose node stops takes the next node of the level (the first
+// gridDim.x * 16 nodes are dealt out in order, the rest come from a
+// counter), so stopped nodes cost no MFMA columns while work remains and
+// one wave of workgroups covers the whole level.  Every reduction is a
+// butterfly over XOR partners, so the lanes of a slot hold bit-identical
+// sums and take the same decisions.
 // ---------------------------------------------------------------------------
-constexpr int kP16N = 16, kP16K = 256, kP16G = 32;   // block size, pixels, nodes per workgroup
-constexpr int kP8Nodes = 16;                          // nodes per wave of the N = 8 BF16 pursuit
-constexpr int kP16RS = kP16K + 4;                     // padded FP32 residual row (floats)
-constexpr int kP16AC = 3;                             // A tiles whose fragments stay in registers
+constexpr int kP16N = 16, kP16K = 256;
+constexpr int kP16Slots = 16;                  // node slots per workgroup (the B operand's columns)
+constexpr int kP16Waves = 8;                   // 64 atoms per wave
+constexpr int kP16RowB = 2 * kP16K + 16;       // bytes per slot in the BF16 residual (padded)
+constexpr int kP8Nodes = 16;                   // nodes per wave of the N = 8 BF16 pursuit
 
 typedef __bf16 p16_bf16x8 __attribute__((ext_vector_type(8)));
-typedef float p16_f32x16 __attribute__((ext_vector_type(16)));
+typedef float p16_f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline void p16_cx(uint32_t& a, uint32_t& b) {
   const uint32_t hi = a > b ? a : b;
@@ -185,365 +195,342 @@ __device__ inline void p16_merge8(T (&a)[8], const T (&b)[8]) {
   p16_cxT(a[0], a[1]); p16_cxT(a[2], a[3]); p16_cxT(a[4], a[5]); p16_cxT(a[6], a[7]);
 }
 
-// 16-byte chunk c (8 pixels) of node row nl in the swizzled BF16 residual.
-__device__ inline int p16_chunk(int nl, int c) { return nl * 32 + (c ^ (nl & 15)); }
+// Lane exchanges inside a DPP row of 16 lanes, all XOR partners: row_ror:8
+// (lane ^ 8), row_half_mirror (lane ^ 7 within eight), quad_perm [2,3,0,1]
+// (lane ^ 2) and [1,0,3,2] (lane ^ 1).
+constexpr int kDppX8 = 0x128, kDppX7 = 0x141, kDppX2 = 0x4E, kDppX1 = 0xB1;
+template <int CTRL>
+__device__ inline uint32_t p16_dpp32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ inline double p16_dppf64(double v) {
+  return __longlong_as_double((long long)dpp_u64<CTRL, 0xF>((unsigned long long)__double_as_longlong(v)));
+}
+// Sum over the 16 lanes of a row; a butterfly, so every lane of the row gets
+// the same bits.
+__device__ inline double p16_row_sum(double v) {
+  v += p16_dppf64<kDppX8>(v);
+  v += p16_dppf64<kDppX7>(v);
+  v += p16_dppf64<kDppX2>(v);
+  v += p16_dppf64<kDppX1>(v);
+  return v;
+}
 
-__global__ __launch_bounds__(256, 1) void k_pursuit16_bf16(const JobDev* __restrict__ jobs, LevelDev lv,
-                                                           const int32_t* __restrict__ count_ptr, int32_t lg,
-                                                           int32_t n_atoms, int32_t nfam,
-                                                           const double* __restrict__ tab,
-                                                           const float* __restrict__ tabT32) {
-  constexpr int N = kP16N, K = kP16K, G = kP16G;
-  __shared__ __attribute__((aligned(16))) float sR[G][kP16RS];   // FP32 residual
-  __shared__ __attribute__((aligned(16))) uint4 sB[G * 32];  // BF16 residual, 32 chunks per node
-  __shared__ __attribute__((aligned(16))) double sTab[2][N][N];  // FP64 tables [f][p][y]
-  __shared__ float sT32[2][N][N];                            // FP32 tables [f][y][p]
-  __shared__ uint32_t sKey[4][G][8];
-  __shared__ __attribute__((aligned(16))) int sCand[G][8];
-  __shared__ __attribute__((aligned(16))) double sC[G][8];
-  __shared__ double sE[G], sEps[G];
-  __shared__ int sSt[G], sT[G], sKmax[G];
-  // records of the current 32-step window, flushed to global after it
-  constexpr int RW = 32;
-  __shared__ int sRecIdx[G][RW];
-  __shared__ double sRecCoef[G][RW];
+// Per-slot state, uniform over the slot's 16 lanes.
+struct P16Slot {
+  int node;       // node of the level, -1 when none is left for this slot
+  int t, kmax;
+  double eps2, e;
+  bool run;
+};
 
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int i = tid; i < nfam * K; i += 256) {
-    (&sTab[0][0][0])[i] = tab[i];
-    (&sT32[0][0][0])[i] = tabT32[i];
-  }
-  __syncthreads();
-  const double inv_n = 1.0 / N;
-  const int count = *count_ptr;
-
-  // Correlation geometry: wave w holds atoms [128 w, 128 w + 128); lane row
-  // 32 ma + rr is atom (fam, p = rr & 15, q = 8 (w & 1) + 2 ma + (rr >> 4)).
-  const int rr = lane & 31, hh = lane >> 5;
-  const int fam = min(w >> 1, nfam - 1);
-  const bool fam_ok = (w >> 1) < nfam;
-  float tq[4][8];
+// Loads node `node` into the lane's 4 x 4 patch (FP64 values of the FP32
+// residual), the slot's BF16 row, and makes the first stop test; a node
+// that stops at once gets its final state here.
+__device__ __attribute__((always_inline)) inline void p16_load_node(const JobDev* __restrict__ jobs, const LevelDev& lv, int lg, int node,
+                                     int yq, int xq, int li, char* sBrow, double (&rd)[4][4], P16Slot& s) {
+  const int jidx = lv.job[node];
+  const int bx = lv.x0[node], by = lv.y0[node];
+  const JobDev jl = jobs[jidx];
+  double pv[4][4];
 #pragma unroll
-  for (int ma = 0; ma < 4; ++ma) {
-    const int q = 8 * (w & 1) + 2 * ma + (rr >> 4);
+  for (int i = 0; i < 4; ++i) job_pixels<4>(jl, by + 4 * yq + i, bx + 4 * xq, pv[i]);
+  double ep[4];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) tq[ma][j] = sT32[fam][8 * hh + j][q];
-  }
-  const float* tpcol = &sT32[fam][0][rr & 15];   // T32_f[p][y] at tpcol[y * N]
-  // The A fragments do not change between steps or groups: those of the
-  // first kP16AC tiles are generated once and held in registers, the others
-  // each step.
-  constexpr int AC = kP16AC;
-  p16_bf16x8 afc[N][AC];
+  for (int i = 0; i < 4; ++i) {
+    ep[i] = 0.0;
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    bf16x4 b;
 #pragma unroll
-  for (int kk = 0; kk < N; ++kk) {
-    const float tpk = tpcol[kk * N];
-#pragma unroll
-    for (int ma = 0; ma < AC; ++ma)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) afc[kk][ma][j] = (__bf16)(tpk * tq[ma][j]);
-  }
-  // Keys: the 23 bits of |c| that the batched path ranks on (exponent and 15
-  // mantissa bits), then 511 - atom: the same order as its 64-bit keys.
-  // 511 - atom of accumulator (ma, r) = lb - (32 ma + 8 (r >> 2) + (r & 3)).
-  const uint32_t lb = 511u - (uint32_t)(128 * w + 4 * hh);
-
-  // Update / gather geometry: thread = (node nl, part): 32 pixels, rows 2 part, 2 part + 1.
-  const int nl = tid >> 3, part = tid & 7;
-
-  for (int g0 = blockIdx.x * G; g0 < count; g0 += gridDim.x * G) {
-    // ---- gather (Algorithm 2: y = unravel(b)) and the first stop test ----
-    {
-      const int node = g0 + nl;
-      const bool valid = node < count;
-      const int nd = valid ? node : g0;
-      const JobDev& jb = jobs[lv.job[nd]];
-      const int bx = lv.x0[nd], by = lv.y0[nd];
-      double e = 0.0;
-      const JobDev jl = jb;   // one copy of the job's fields in registers
-#pragma unroll
-      for (int dy = 0; dy < 2; ++dy) {
-        const int y = 2 * part + dy;
-        float f[N];
-        double pv[N];
-        job_pixels<N>(jl, by + y, bx, pv);
-#pragma unroll
-        for (int x = 0; x < N; ++x) {
-          const double v = pv[x];
-          f[x] = (float)v;
-          e += v * v;
-        }
-#pragma unroll
-        for (int x = 0; x < N; ++x) sR[nl][y * N + x] = valid ? f[x] : 0.f;
-#pragma unroll
-        for (int c2 = 0; c2 < 2; ++c2) {
-          p16_bf16x8 b;
-#pragma unroll
-          for (int j = 0; j < 8; ++j) b[j] = (__bf16)(valid ? f[8 * c2 + j] : 0.f);
-          sB[p16_chunk(nl, 2 * y + c2)] = __builtin_bit_cast(uint4, b);
-        }
-      }
-      e += __shfl_xor(e, 1, 64);
-      e += __shfl_xor(e, 2, 64);
-      e += __shfl_xor(e, 4, 64);
-      if (part == 0) {
-        uint8_t st = ST_RUN;
-        if (!valid)
-          st = ST_SPARSE;
-        else if (e < jb.eps2[lg])
-          st = ST_ACC;
-        else if (jb.k[lg] <= 0)
-          st = ST_SPARSE;
-        sE[nl] = e;
-        sEps[nl] = jb.eps2[lg];
-        sKmax[nl] = jb.k[lg];
-        sT[nl] = 0;
-        sSt[nl] = st;
-      }
+    for (int j = 0; j < 4; ++j) {
+      const float f = (float)pv[i][j];
+      rd[i][j] = (double)f;
+      ep[i] = fma(pv[i][j], pv[i][j], ep[i]);
+      b[j] = (__bf16)f;
     }
-    bool any = __syncthreads_or(part == 0 && sSt[nl] == ST_RUN);
-    int step = 0;   // MP steps made in this group (every running node makes one per step)
-
-    while (any) {
-      // ---- C: correlation (MFMA) ----
-      p16_f32x16 acc[4];
-#pragma unroll
-      for (int ma = 0; ma < 4; ++ma)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[ma][r] = 0.f;
-#pragma unroll
-      for (int kk = 0; kk < N; ++kk) {   // k-step kk = pixel row y
-        const p16_bf16x8 bf = __builtin_bit_cast(p16_bf16x8, sB[p16_chunk(rr, 2 * kk + hh)]);
-        const float tpk = tpcol[kk * N];
-#pragma unroll
-        for (int ma = 0; ma < 4; ++ma) {
-          p16_bf16x8 af;
-          if (ma < AC) {
-            af = afc[kk][ma < AC ? ma : 0];
-          } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) af[j] = (__bf16)(tpk * tq[ma][j]);
-          }
-          acc[ma] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bf, acc[ma], 0, 0, 0);
-        }
-      }
-      // ---- E: this wave's best 8 keys per node (node = rr) ----
-      {
-        uint32_t top[8];
-#pragma unroll
-        for (int gi = 0; gi < 8; ++gi) {
-          const int ma = gi >> 1;
-          uint32_t v[8];
-#pragma unroll
-          for (int e8 = 0; e8 < 8; ++e8) {
-            const int r = 8 * (gi & 1) + e8;
-            const uint32_t bits = __float_as_uint(acc[ma][r]);
-            v[e8] = ((bits & 0x7FFFFF00u) << 1) | (lb - (uint32_t)(32 * ma + 8 * (r >> 2) + (r & 3)));
-          }
-          p16_sort8(v);
-          if (gi == 0) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) top[j] = v[j];
-          } else {
-            p16_merge8(top, v);
-          }
-        }
-        uint32_t other[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) other[j] = __shfl_xor(top[j], 32, 64);
-        p16_merge8(top, other);
-        if (lane < 32) {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) sKey[w][rr][j] = fam_ok ? top[j] : 0u;
-        }
-      }
-      __syncthreads();
-      // ---- M: the node's 8 candidates (wave 0: lane half hh merges waves 2 hh, 2 hh + 1) ----
-      if (w == 0) {
-        uint32_t top[8], v[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          top[j] = sKey[2 * hh][rr][j];
-          v[j] = sKey[2 * hh + 1][rr][j];
-        }
-        p16_merge8(top, v);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = __shfl_xor(top[j], 32, 64);
-        p16_merge8(top, v);
-        if (lane < 32) {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const unsigned atom = 511u - (top[j] & 0x1FFu);
-            sCand[rr][j] = (top[j] != 0u && atom < (unsigned)n_atoms) ? (int)atom : -1;
-          }
-        }
-      }
-      __syncthreads();
-      // ---- S: FP64 re-score, thread = (node nl, candidate part) ----
-      {
-        const int atom = sCand[nl][part];
-        double c = 0.0;
-        if (sSt[nl] == ST_RUN && atom >= 0) {
-          const int f = atom / K, q = (atom % K) / N, p = atom % N;
-          const bool dc = (p == 0 && q == 0);
-          double tqx[N], tpy[N];
-          const double2* qrow = (const double2*)&sTab[f][q][0];
-          const double2* prow = (const double2*)&sTab[f][p][0];
-#pragma unroll
-          for (int i = 0; i < N / 2; ++i) {
-            const double2 u = qrow[i], v = prow[i];
-            tqx[2 * i] = dc ? 1.0 : u.x;
-            tqx[2 * i + 1] = dc ? 1.0 : u.y;
-            tpy[2 * i] = v.x;
-            tpy[2 * i + 1] = v.y;
-          }
-          const float4* rrow = (const float4*)&sR[nl][0];
-#pragma unroll 4
-          for (int y = 0; y < N; ++y) {
-            float rv[N];
-#pragma unroll
-            for (int i = 0; i < N / 4; ++i) {
-              const float4 t4 = rrow[y * (N / 4) + i];
-              rv[4 * i] = t4.x; rv[4 * i + 1] = t4.y; rv[4 * i + 2] = t4.z; rv[4 * i + 3] = t4.w;
-            }
-            double sum = 0.0;
-#pragma unroll
-            for (int x = 0; x < N; ++x) sum = fma((double)rv[x], tqx[x], sum);
-            c = dc ? c + sum : fma(tpy[y], sum, c);
-          }
-          if (dc) c *= inv_n;
-        }
-        sC[nl][part] = c;
-      }
-      __syncthreads();
-      // ---- A: arg-max, update, norm, record, stop test ----
-      {
-        const bool run = sSt[nl] == ST_RUN;
-        int cd[8];
-        double cv[8];
-        {
-          const int4* cp = (const int4*)&sCand[nl][0];
-          const double2* vp = (const double2*)&sC[nl][0];
-#pragma unroll
-          for (int i = 0; i < 2; ++i) {
-            const int4 t4 = cp[i];
-            cd[4 * i] = t4.x; cd[4 * i + 1] = t4.y; cd[4 * i + 2] = t4.z; cd[4 * i + 3] = t4.w;
-          }
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const double2 t2 = vp[i];
-            cv[2 * i] = t2.x; cv[2 * i + 1] = t2.y;
-          }
-        }
-        // arg-max |c| over the valid candidates, lowest atom on ties
-        int batom = -1;
-        double bmag = -1.0, bc = 0.0;
-#pragma unroll
-        for (int ci = 0; ci < 8; ++ci) {
-          const double m = fabs(cv[ci]);
-          const bool better = cd[ci] >= 0 && (batom < 0 || m > bmag || (m == bmag && cd[ci] < batom));
-          batom = better ? cd[ci] : batom;
-          bmag = better ? m : bmag;
-          bc = better ? cv[ci] : bc;
-        }
-        const bool zero = (batom < 0 || bmag == 0.0);
-        const int atom = zero ? 0 : batom;
-        const double coef = zero ? 0.0 : bc;
-        double e = 0.0;
-        if (run && !zero) {
-          const int f = atom / K, q = (atom % K) / N, p = atom % N;
-          const bool dc = (p == 0 && q == 0);
-          double tqx[N];
-          const double2* qrow = (const double2*)&sTab[f][q][0];
-#pragma unroll
-          for (int i = 0; i < N / 2; ++i) {
-            const double2 u = qrow[i];
-            tqx[2 * i] = u.x;
-            tqx[2 * i + 1] = u.y;
-          }
-          float rv[2][N];
-          float4* rrow = (float4*)&sR[nl][0];
-#pragma unroll
-          for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-            for (int i = 0; i < N / 4; ++i) {
-              const float4 t4 = rrow[(2 * part + dy) * (N / 4) + i];
-              rv[dy][4 * i] = t4.x; rv[dy][4 * i + 1] = t4.y; rv[dy][4 * i + 2] = t4.z; rv[dy][4 * i + 3] = t4.w;
-            }
-          double eh[2] = {0.0, 0.0};
-#pragma unroll
-          for (int dy = 0; dy < 2; ++dy) {
-            const int y = 2 * part + dy;
-            const double ty = sTab[f][p][y];
-            float rn[N];
-#pragma unroll
-            for (int x = 0; x < N; ++x) {
-              const double phi = dc ? inv_n : ty * tqx[x];
-              rn[x] = (float)fma(-coef, phi, (double)rv[dy][x]);
-              eh[dy] = fma((double)rn[x], (double)rn[x], eh[dy]);
-            }
-#pragma unroll
-            for (int i = 0; i < N / 4; ++i) rrow[y * (N / 4) + i] = make_float4(rn[4 * i], rn[4 * i + 1], rn[4 * i + 2], rn[4 * i + 3]);
-#pragma unroll
-            for (int c2 = 0; c2 < 2; ++c2) {
-              p16_bf16x8 b;
-#pragma unroll
-              for (int j = 0; j < 8; ++j) b[j] = (__bf16)rn[8 * c2 + j];
-              sB[p16_chunk(nl, 2 * y + c2)] = __builtin_bit_cast(uint4, b);
-            }
-          }
-          e = eh[0] + eh[1];
-        }
-        e += __shfl_xor(e, 1, 64);
-        e += __shfl_xor(e, 2, 64);
-        e += __shfl_xor(e, 4, 64);
-        bool still = false;
-        if (part == 0 && run) {
-          const int t = sT[nl];
-          if (zero) {
-            sSt[nl] = ST_ZERO;
-          } else {
-            sRecIdx[nl][t % RW] = atom;
-            sRecCoef[nl][t % RW] = coef;
-            uint8_t st = ST_RUN;
-            if (e < sEps[nl])
-              st = ST_ACC;
-            else if (t + 1 >= sKmax[nl])
-              st = ST_SPARSE;
-            sE[nl] = e;
-            sT[nl] = t + 1;
-            sSt[nl] = st;
-            still = st == ST_RUN;
-          }
-        }
-        any = __syncthreads_or(still);
-        // every RW steps (all running nodes share the step count) and at the
-        // end, the window's records go to global memory
-        ++step;
-        if (step % RW == 0 || !any) {
-          const int base = (step - 1) / RW * RW;
-          for (int i = tid; i < G * RW; i += 256) {
-            const int n2 = i / RW, j = i % RW, ts = base + j;
-            if (g0 + n2 < count && ts < sT[n2]) {
-              const size_t slot = (size_t)(g0 + n2) * lv.kmax + ts;
-              lv.rec_idx[slot] = sRecIdx[n2][j];
-              lv.rec_coef[slot] = sRecCoef[n2][j];
-            }
-          }
-          __syncthreads();
-        }
-      }
-    }
-    // ---- node state for the split test ----
-    if (tid < G && g0 + tid < count) {
-      lv.e[g0 + tid] = sE[tid];
-      lv.t[g0 + tid] = sT[tid];
-      lv.st[g0 + tid] = (uint8_t)sSt[tid];
-    }
-    __syncthreads();
+    *(bf16x4*)(sBrow + ((4 * yq + i) * kP16N + 4 * xq) * 2) = b;
+  }
+  s.node = node;
+  s.e = p16_row_sum((ep[0] + ep[1]) + (ep[2] + ep[3]));
+  s.eps2 = jobs[jidx].eps2[lg];
+  s.kmax = jobs[jidx].k[lg];
+  s.t = 0;
+  uint8_t st = ST_RUN;
+  if (s.e < s.eps2)
+    st = ST_ACC;
+  else if (s.kmax <= 0)
+    st = ST_SPARSE;
+  s.run = st == ST_RUN;
+  if (!s.run && li == 0) {
+    lv.e[node] = s.e;
+    lv.t[node] = 0;
+    lv.st[node] = st;
   }
 }
 
+// Fills the wave's stopped slots from the level's nodes until each runs or
+// none are left: node blockIdx.x * 16 + slot first, then nodes from the
+// counter.  The loop and the lane exchange are uniform over the wave.
+__device__ __attribute__((always_inline)) inline void p16_refill(
+    const JobDev* __restrict__ jobs, const LevelDev& lv, int lg, int count, int32_t* next, int queue0, int slot,
+    int yq, int xq, int li, char* sBrow, double (&rd)[4][4], P16Slot& s, bool& first, bool& dry) {
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    const bool need = !s.run && !dry;
+    if (__ballot(need) == 0ull) break;
+    int idx = 0;
+    if (need && li == 0) idx = first ? (int)blockIdx.x * kP16Slots + slot : queue0 + atomicAdd(next, 1);
+    idx = __shfl(idx, lane & ~15, 64);
+    if (need) {
+      if (idx < count) {
+        p16_load_node(jobs, lv, lg, idx, yq, xq, li, sBrow, rd, s);
+      } else {
+        dry = true;
+        s.node = -1;
+      }
+    }
+    first = false;
+  }
+}
+
+__global__ __launch_bounds__(kP16Waves * 64, 1) void k_pursuit16_bf16(
+    const JobDev* __restrict__ jobs, LevelDev lv, const int32_t* __restrict__ count_ptr,
+    int32_t* __restrict__ next, int32_t lg, int32_t n_atoms, int32_t nfam, const double* __restrict__ tab,
+    const float* __restrict__ tabT32) {
+  constexpr int N = kP16N, K = kP16K, NS = kP16Slots, NT = kP16Waves * 64;
+  __shared__ __attribute__((aligned(16))) char sB[NS * kP16RowB];       // BF16 residual per slot
+  __shared__ __attribute__((aligned(16))) uint32_t sKey[kP16Waves][NS][8];
+  __shared__ __attribute__((aligned(16))) double sTab[2][N][N];         // FP64 T_f[k][n]
+  __shared__ float sT32[2][N][N];                                       // FP32 [f][n][k]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int i = tid; i < nfam * K; i += NT) {
+    (&sTab[0][0][0])[i] = tab[i];
+    (&sT32[0][0][0])[i] = tabT32[i];
+  }
+  for (int i = tid; i < NS * kP16RowB / 16; i += NT) ((uint4*)sB)[i] = make_uint4(0u, 0u, 0u, 0u);
+  __syncthreads();
+  const int count = *count_ptr;
+  const double inv_n = 1.0 / N;
+
+  // ---- correlation geometry: wave w, family w / 4, q = 4 (w % 4) + ma ----
+  const int c16 = lane & 15, quad = lane >> 4;
+  const bool fam_ok = (w >> 2) < nfam;
+  const int fam = fam_ok ? (w >> 2) : 0;
+  const int qb = 4 * (w & 3);
+  // A fragment (tile ma, k-step ks): row p = c16, pixels 32 ks + 8 quad + j,
+  // i.e. y = 2 ks + quad / 2, x = 8 (quad % 2) + j.
+  p16_bf16x8 afr[4][8];
+#pragma unroll
+  for (int ks = 0; ks < 8; ++ks) {
+    const int y = 2 * ks + (quad >> 1), x0 = 8 * (quad & 1);
+    const float tp = sT32[fam][y][c16];
+#pragma unroll
+    for (int ma = 0; ma < 4; ++ma)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) afr[ma][ks][j] = (__bf16)(tp * sT32[fam][x0 + j][qb + ma]);
+  }
+  // 511 - atom of accumulator (ma, r): atom = 256 f + 16 (qb + ma) + 4 quad + r
+  const uint32_t lb = 511u - (uint32_t)(256 * (w >> 2) + 16 * qb + 4 * quad);
+
+  // ---- slot geometry: waves 0-3 own the slots, four per wave (a DPP row each) ----
+  const bool owner = w < NS / 4;
+  const int slot = 4 * w + quad;
+  const int li = c16, yq = li >> 2, xq = li & 3;
+  char* sBrow = sB + (owner ? slot : 0) * kP16RowB;
+  P16Slot s{-1, 0, 0, 0.0, 0.0, false};
+  double rd[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) rd[i][j] = 0.0;
+  const int queue0 = gridDim.x * NS;   // nodes below this are dealt out in order
+  bool first = true, dry = false;
+
+  if (owner) p16_refill(jobs, lv, lg, count, next, queue0, slot, yq, xq, li, sBrow, rd, s, first, dry);
+  first = false;
+  bool any = __syncthreads_or(s.run);
+
+  while (any) {
+    // ---- C: correlation of the wave's 64 atoms with the 16 slots ----
+    p16_f32x4 acc[4];
+#pragma unroll
+    for (int ma = 0; ma < 4; ++ma) acc[ma] = p16_f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const p16_bf16x8 bf = *(const p16_bf16x8*)(sB + c16 * kP16RowB + 64 * ks + 16 * quad);
+#pragma unroll
+      for (int ma = 0; ma < 4; ++ma) acc[ma] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[ma][ks], bf, acc[ma], 0, 0, 0);
+    }
+    // ---- E: the wave's best 8 keys of slot c16 ----
+    {
+      uint32_t top[8], v[8];
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+#pragma unroll
+        for (int e8 = 0; e8 < 8; ++e8) {
+          const int ma = 2 * g + (e8 >> 2), r = e8 & 3;
+          const uint32_t bits = __float_as_uint(acc[ma][r]);
+          v[e8] = ((bits & 0x7FFFFF00u) << 1) | (lb - (uint32_t)(16 * ma + r));
+        }
+        p16_sort8(v);
+        if (g == 0) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) top[j] = v[j];
+        } else {
+          p16_merge8(top, v);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = __shfl_xor(top[j], 16, 64);
+      p16_merge8(top, v);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = __shfl_xor(top[j], 32, 64);
+      p16_merge8(top, v);
+      if (quad == 0) {
+        uint4* kp = (uint4*)&sKey[w][c16][0];
+        kp[0] = fam_ok ? make_uint4(top[0], top[1], top[2], top[3]) : make_uint4(0u, 0u, 0u, 0u);
+        kp[1] = fam_ok ? make_uint4(top[4], top[5], top[6], top[7]) : make_uint4(0u, 0u, 0u, 0u);
+      }
+    }
+    __syncthreads();
+    if (owner) {
+      if (s.run) {
+        // ---- M: the slot's 8 candidates from the eight wave lists ----
+        uint32_t top[8], v[8];
+        {
+          const uint4* kp = (const uint4*)&sKey[li & 7][slot][0];
+          const uint4 k0 = kp[0], k1 = kp[1];
+          top[0] = k0.x; top[1] = k0.y; top[2] = k0.z; top[3] = k0.w;
+          top[4] = k1.x; top[5] = k1.y; top[6] = k1.z; top[7] = k1.w;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = p16_dpp32<kDppX7>(top[j]);
+        p16_merge8(top, v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = p16_dpp32<kDppX1>(top[j]);
+        p16_merge8(top, v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = p16_dpp32<kDppX2>(top[j]);
+        p16_merge8(top, v);
+        int cand[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const unsigned at = 511u - (top[j] & 0x1FFu);
+          cand[j] = (top[j] != 0u && at < (unsigned)n_atoms) ? (int)at : -1;
+        }
+        // ---- S: FP64 re-score, the lane's patch, then the row sums ----
+        double part[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int at = cand[j] < 0 ? 0 : cand[j];
+          const int f = at >> 8, q = (at >> 4) & 15, p = at & 15;
+          const bool dc = (at & 255) == 0;
+          const double2 q0 = *(const double2*)&sTab[f][q][4 * xq];
+          const double2 q1 = *(const double2*)&sTab[f][q][4 * xq + 2];
+          const double2 p0 = *(const double2*)&sTab[f][p][4 * yq];
+          const double2 p1 = *(const double2*)&sTab[f][p][4 * yq + 2];
+          const double tq[4] = {dc ? 1.0 : q0.x, dc ? 1.0 : q0.y, dc ? 1.0 : q1.x, dc ? 1.0 : q1.y};
+          const double tp[4] = {dc ? 1.0 : p0.x, dc ? 1.0 : p0.y, dc ? 1.0 : p1.x, dc ? 1.0 : p1.y};
+          double sy[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            sy[i] = rd[i][0] * tq[0];
+#pragma unroll
+            for (int x = 1; x < 4; ++x) sy[i] = fma(rd[i][x], tq[x], sy[i]);
+          }
+          const double pt = fma(tp[0], sy[0], tp[1] * sy[1]) + fma(tp[2], sy[2], tp[3] * sy[3]);
+          part[j] = cand[j] < 0 ? 0.0 : (dc ? pt * inv_n : pt);
+        }
+        // halves of the list go to the partner 8, 7 (within eight), 2 lanes
+        // away, then one plain sum: lane bits 3, 2, 1 name the candidate
+        const bool b3 = li & 8, b2 = li & 4, b1 = li & 2;
+        double h4[4], h2[2];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) h4[j] = (b3 ? part[j + 4] : part[j]) + p16_dppf64<kDppX8>(b3 ? part[j] : part[j + 4]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) h2[j] = (b2 ? h4[j + 2] : h4[j]) + p16_dppf64<kDppX7>(b2 ? h4[j] : h4[j + 2]);
+        double c = (b1 ? h2[1] : h2[0]) + p16_dppf64<kDppX2>(b1 ? h2[0] : h2[1]);
+        c += p16_dppf64<kDppX1>(c);
+        const int jj = (b3 ? 4 : 0) + (b2 ? 2 : 0) + (b1 ? 1 : 0);
+        int at = -1;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) at = jj == j ? cand[j] : at;
+        // ---- A: arg-max over the row (lowest atom on ties) ----
+        double mag = at >= 0 ? fabs(c) : -1.0;
+#define AQMP_P16_ARGMAX(CTRL)                                                            \
+  {                                                                                      \
+    const double om = p16_dppf64<CTRL>(mag), oc = p16_dppf64<CTRL>(c);                   \
+    const int oa = (int)p16_dpp32<CTRL>((uint32_t)at);                                   \
+    const bool take = om > mag || (om == mag && oa < at);                                \
+    mag = take ? om : mag;                                                               \
+    c = take ? oc : c;                                                                   \
+    at = take ? oa : at;                                                                 \
+  }
+        AQMP_P16_ARGMAX(kDppX8) AQMP_P16_ARGMAX(kDppX7) AQMP_P16_ARGMAX(kDppX2)
+#undef AQMP_P16_ARGMAX
+        const bool zero = at < 0 || mag == 0.0;
+        if (zero) {
+          s.run = false;
+          if (li == 0) {
+            lv.e[s.node] = s.e;
+            lv.t[s.node] = s.t;
+            lv.st[s.node] = ST_ZERO;
+          }
+        } else {
+          // rank-1 update of the patch, ||r||^2, record, stop test
+          const int f = at >> 8, q = (at >> 4) & 15, p = at & 15;
+          const bool dc = (at & 255) == 0;
+          const double2 q0 = *(const double2*)&sTab[f][q][4 * xq];
+          const double2 q1 = *(const double2*)&sTab[f][q][4 * xq + 2];
+          const double2 p0 = *(const double2*)&sTab[f][p][4 * yq];
+          const double2 p1 = *(const double2*)&sTab[f][p][4 * yq + 2];
+          const double tq[4] = {q0.x, q0.y, q1.x, q1.y};
+          const double tp[4] = {p0.x, p0.y, p1.x, p1.y};
+          double eh[4];
+          typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            bf16x4 b;
+            eh[i] = 0.0;
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+              const double phi = dc ? inv_n : tp[i] * tq[x];
+              const float rn = (float)fma(-c, phi, rd[i][x]);
+              rd[i][x] = (double)rn;
+              eh[i] = fma(rd[i][x], rd[i][x], eh[i]);
+              b[x] = (__bf16)rn;
+            }
+            *(bf16x4*)(sBrow + ((4 * yq + i) * N + 4 * xq) * 2) = b;
+          }
+          const double en = p16_row_sum((eh[0] + eh[1]) + (eh[2] + eh[3]));
+          if (li == 0) {
+            const size_t rs = (size_t)s.node * lv.kmax + s.t;
+            lv.rec_idx[rs] = at;
+            lv.rec_coef[rs] = c;
+          }
+          s.t += 1;
+          s.e = en;
+          uint8_t st = ST_RUN;
+          if (en < s.eps2)
+            st = ST_ACC;
+          else if (s.t >= s.kmax)
+            st = ST_SPARSE;
+          if (st != ST_RUN) {
+            s.run = false;
+            if (li == 0) {
+              lv.e[s.node] = s.e;
+              lv.t[s.node] = s.t;
+              lv.st[s.node] = st;
+            }
+          }
+        }
+      }
+      p16_refill(jobs, lv, lg, count, next, queue0, slot, yq, xq, li, sBrow, rd, s, first, dry);
+    }
+    any = __syncthreads_or(s.run);
+  }
+}
 // ---------------------------------------------------------------------------
 // Whole-level pursuit for N = 8 in the BF16 form.  One wave takes G <= 16
 // nodes through their whole pursuit (Section 2.2 steps (a)-(d), eq. (2)),
@@ -826,9 +813,22 @@ __global__ __launch_bounds__(256) void k_pursuit8_bf16(const JobDev* __restrict_
 
 }  // namespace
 
-hipError_t launch_pursuit16_bf16(const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t n_atoms, int32_t nfam,
-                                 const double* tab, const float* tabT32, hipStream_t s) {
-  hipLaunchKernelGGL(k_pursuit16_bf16, dim3(512), dim3(256), 0, s, jobs, lv, count, 4, n_atoms, nfam, tab, tabT32);
+hipError_t launch_pursuit16_bf16(const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int64_t cap,
+                                 int32_t n_atoms, int32_t nfam, const double* tab, const float* tabT32, hipStream_t s) {
+  // Slots take nodes until none are left, so the grid is as many workgroups
+  // as are resident at once (at most one per 16 nodes of the level).
+  int dev = 0, n_cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pursuit16_bf16, kP16Waves * 64, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  int64_t wgs = (cap + kP16Slots - 1) / kP16Slots;
+  if (wgs > (int64_t)n_cus * per_cu) wgs = (int64_t)n_cus * per_cu;
+  if (wgs < 1) wgs = 1;
+  hipLaunchKernelGGL(k_pursuit16_bf16, dim3((unsigned)wgs), dim3(kP16Waves * 64), 0, s, jobs, lv, count, next, 4,
+                     n_atoms, nfam, tab, tabT32);
   return hipGetLastError();
 }
 
