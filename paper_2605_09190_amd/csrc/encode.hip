@@ -520,12 +520,13 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
                                           wk.cbuf, s));
         if (se) AQMP_HIP(hipEventRecord(se->c, s));
       } else if (n == 8 && c->opt.precision == AQMP_PREC_BF16)
-        AQMP_LAUNCH(launch_pursuit8_bf16(c->djobs, a.lv, count, pp.cap[l], D.m, d->nfam, D.d_tab, D.d_tabT32, s));
+        AQMP_LAUNCH(launch_pursuit_bf16(8, c->djobs, a.lv, count, &cnt->next[l], pp.cap[l], D.m, d->nfam, D.d_tab,
+                                        D.d_tabT32, s));
       else if (n <= kFusedMaxN)
         AQMP_LAUNCH(launch_mp_fused(n, c->djobs, a.lv, count, l, D.m, D.d_tab, s));
       else
-        AQMP_LAUNCH(launch_pursuit16_bf16(c->djobs, a.lv, count, &cnt->next[l], pp.cap[l], D.m, d->nfam, D.d_tab,
-                                          D.d_tabT32, s));
+        AQMP_LAUNCH(launch_pursuit_bf16(16, c->djobs, a.lv, count, &cnt->next[l], pp.cap[l], D.m, d->nfam, D.d_tab,
+                                        D.d_tabT32, s));
       if (l > pp.lg_lo && pp.cap[l - 1] > 0)
         AQMP_LAUNCH(launch_split_emit(c->djobs, (int32_t)c->jobs.size(), a.lv, count, level_at(c, l - 1, pp.base[l - 1]), pp.ntop[l - 1],
                                       &cnt->count[l - 1], l, pp.cap[l], wk.ss, &cnt->scan_error, s));

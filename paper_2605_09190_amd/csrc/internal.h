@@ -177,11 +177,11 @@ hipError_t launch_select(int n, const StepArgs& a, int64_t cap, hipStream_t s, h
                          hipEvent_t ev1 = nullptr);
 hipError_t launch_mp_fused(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t lg, int32_t n_atoms,
                            const double* tab, hipStream_t s);
-// N = 8 in the BF16 form: whole-level pursuit, a few nodes per wave.
-hipError_t launch_pursuit8_bf16(const JobDev* jobs, LevelDev lv, const int32_t* count, int64_t cap, int32_t n_atoms,
-                                int32_t nfam, const double* tab, const float* tabT32, hipStream_t s);
-hipError_t launch_pursuit16_bf16(const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int64_t cap,
-                                 int32_t n_atoms, int32_t nfam, const double* tab, const float* tabT32, hipStream_t s);
+// Whole-level BF16 pursuit of a level of N = 8 or 16 (next: the level's
+// node counter, zero on entry; cap: the level's node capacity).
+hipError_t launch_pursuit_bf16(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next,
+                               int64_t cap, int32_t n_atoms, int32_t nfam, const double* tab, const float* tabT32,
+                               hipStream_t s);
 // Gram and OMP forms (FP64).  For N >= 16 launch_gram_init writes the
 // correlations of every node of the level to cbuf ([node][nfam * n * n]) and
 // sets its ||y||^2 and first stop test; the pursuit launches then take each

@@ -128,26 +128,28 @@ __global__ __launch_bounds__(256) void k_mp_fused(const JobDev* __restrict__ job
 }
 
 // ---------------------------------------------------------------------------
-// Whole-level pursuit for N = 16 in the BF16 form.  At N = 16 one MP step of
-// a node is 131 K multiply-adds: a batched launch per step would be mostly
-// launch latency and dependent memory chains.  Here one workgroup of eight
-// waves runs 16 node slots through their whole pursuits (Section 2.2 steps
-// (a)-(d), eq. (2)) with every array in LDS or registers:
-//   C  correlation of all 512 atoms with the 16 BF16 residuals by
+// Whole-level pursuit for N = 8 and N = 16 in the BF16 form.  At these sizes
+// one MP step of a node is 8 K (N = 8) or 131 K (N = 16) multiply-adds: a
+// batched launch per step would be mostly launch latency and dependent
+// memory chains.  Here one workgroup runs 16 node slots through their whole
+// pursuits (Section 2.2 steps (a)-(d), eq. (2)) with every array in LDS or
+// registers:
+//   C  correlation of all M = 2 N^2 atoms with the 16 BF16 residuals by
 //      v_mfma_f32_16x16x32_bf16 (A = 16 atoms x 32 pixels, B = 32 pixels x
 //      16 slots, FP32 accumulation, pixel order as in the batched kernels).
-//      Wave w holds atoms f = w / 4, q = 4 (w % 4) + ma (ma < 4), all p: the
-//      canonical BF16 atoms bf16(T32_f[p][y] T32_f[q][x]), generated once
-//      per kernel into registers (32 fragments);
-//   E  each lane ranks its 16 correlations of one slot as 32-bit keys (|c|
-//      bits, then 511 - atom), keeps the best 8 with sorting networks and
-//      merges them with the slot's other three lanes of the wave;
-//   M  the slot's eight wave lists are merged into its 8 candidates (the
-//      same ranking as the batched path);
+//      The atoms are split evenly over the waves; tile ma of wave w holds
+//      the 16 atoms a' = base_w + 16 ma + row of family f_w (q = a' / N,
+//      p = a' % N), the canonical BF16 atoms bf16(T32_f[p][y] T32_f[q][x])
+//      (the constant atom exactly 1/N), generated once per kernel into
+//      registers;
+//   E  each lane ranks its correlations of one slot as 32-bit keys (|c|
+//      bits, then the inverse atom index), keeps the best 8 with sorting
+//      networks and merges them with the slot's other lanes of the wave;
+//   M  the slot's wave lists are merged into its 8 candidates;
 //   S  FP64 re-score of the candidates against the FP32 residual,
-//      separably (Section 2.1 outer product): a slot is one DPP row of 16
-//      lanes, lane = a 4 x 4 pixel patch, and the eight candidate sums are
-//      reduced over the row by exchanging halves of the list;
+//      separably (Section 2.1 outer product): lane = a patch of 4-pixel row
+//      pieces of one slot, and the eight candidate sums are reduced over the
+//      slot's lanes by exchanging halves of the list;
 //   A  arg-max (lowest atom on ties), rank-1 update of the lane's patch in
 //      FP64 rounded to FP32, ||r||^2 in FP64, record (i, c_i), stop test.
 // A slot whose node stops takes the next node of the level (the first
@@ -157,11 +159,28 @@ __global__ __launch_bounds__(256) void k_mp_fused(const JobDev* __restrict__ job
 // butterfly over XOR partners, so the lanes of a slot hold bit-identical
 // sums and take the same decisions.
 // ---------------------------------------------------------------------------
-constexpr int kP16N = 16, kP16K = 256;
-constexpr int kP16Slots = 16;                  // node slots per workgroup (the B operand's columns)
-constexpr int kP16Waves = 8;                   // 64 atoms per wave
-constexpr int kP16RowB = 2 * kP16K + 16;       // bytes per slot in the BF16 residual (padded)
-constexpr int kP8Nodes = 16;                   // nodes per wave of the N = 8 BF16 pursuit
+constexpr int kPSlots = 16;   // node slots per workgroup (the B operand's columns)
+
+template <int N_>
+struct PGeo {
+  static constexpr int N = N_, K = N * N, M = 2 * K;
+  static constexpr int W = N == 16 ? 8 : 4;         // waves per workgroup
+  static constexpr int NT = 64 * W;
+  static constexpr int AW = M / W;                  // atoms per wave
+  static constexpr int MA = AW / 16;                // atom tiles per wave
+  static constexpr int WPF = W / 2;                 // waves per family
+  static constexpr int KS = K / 32;                 // MFMA k-steps
+  static constexpr int LPS = NT / kPSlots;          // lanes per slot
+  static constexpr int SPW = 64 / LPS;              // slots per wave
+  static constexpr int PR = K / LPS / 4;            // rows of 4 pixels per lane
+  static constexpr int XQ = N / 4;                  // 4-pixel pieces per row
+  static constexpr int IB = N == 16 ? 9 : 7;        // bits of the atom index in a key
+  static constexpr int ROWB = 2 * K + 16;           // bytes per slot in the BF16 residual (padded)
+  static_assert(MA * 16 * W == M && KS * 32 == K, "whole tiles");
+  static_assert(LPS == 16 || LPS == 32, "a slot is one or two DPP rows");
+  static_assert(PR * 4 * LPS == K && PR >= 1, "whole patches");
+  static_assert((1 << IB) == M, "key index width");
+};
 
 typedef __bf16 p16_bf16x8 __attribute__((ext_vector_type(8)));
 typedef float p16_f32x4 __attribute__((ext_vector_type(4)));
@@ -179,80 +198,89 @@ __device__ inline void p16_sort8(uint32_t (&v)[8]) {
   p16_cx(v[2], v[4]); p16_cx(v[3], v[5]);
   p16_cx(v[1], v[2]); p16_cx(v[3], v[4]); p16_cx(v[5], v[6]);
 }
-template <class T>
-__device__ inline void p16_cxT(T& a, T& b) {
-  const T hi = a > b ? a : b;
-  b = a > b ? b : a;
-  a = hi;
-}
 // a, b descending -> a = top 8 of both, descending (bitonic merge)
-template <class T>
-__device__ inline void p16_merge8(T (&a)[8], const T (&b)[8]) {
+__device__ inline void p16_merge8(uint32_t (&a)[8], const uint32_t (&b)[8]) {
 #pragma unroll
   for (int i = 0; i < 8; ++i) a[i] = a[i] > b[7 - i] ? a[i] : b[7 - i];
-  p16_cxT(a[0], a[4]); p16_cxT(a[1], a[5]); p16_cxT(a[2], a[6]); p16_cxT(a[3], a[7]);
-  p16_cxT(a[0], a[2]); p16_cxT(a[1], a[3]); p16_cxT(a[4], a[6]); p16_cxT(a[5], a[7]);
-  p16_cxT(a[0], a[1]); p16_cxT(a[2], a[3]); p16_cxT(a[4], a[5]); p16_cxT(a[6], a[7]);
+  p16_cx(a[0], a[4]); p16_cx(a[1], a[5]); p16_cx(a[2], a[6]); p16_cx(a[3], a[7]);
+  p16_cx(a[0], a[2]); p16_cx(a[1], a[3]); p16_cx(a[4], a[6]); p16_cx(a[5], a[7]);
+  p16_cx(a[0], a[1]); p16_cx(a[2], a[3]); p16_cx(a[4], a[5]); p16_cx(a[6], a[7]);
 }
 
-// Lane exchanges inside a DPP row of 16 lanes, all XOR partners: row_ror:8
-// (lane ^ 8), row_half_mirror (lane ^ 7 within eight), quad_perm [2,3,0,1]
-// (lane ^ 2) and [1,0,3,2] (lane ^ 1).
+// Lane exchanges between XOR partners inside the lanes of a slot:
+// ds_swizzle (lane ^ 16), and the DPP row operations row_ror:8 (lane ^ 8),
+// row_half_mirror (lane ^ 7 within eight), quad_perm [2,3,0,1] (lane ^ 2)
+// and [1,0,3,2] (lane ^ 1).
 constexpr int kDppX8 = 0x128, kDppX7 = 0x141, kDppX2 = 0x4E, kDppX1 = 0xB1;
+constexpr int kSwzX16 = 0x1F | (0x10 << 10);   // bitmask mode: and 31, xor 16
 template <int CTRL>
-__device__ inline uint32_t p16_dpp32(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+__device__ inline uint32_t p16_x32(uint32_t v) {
+  if constexpr (CTRL == kSwzX16)
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, kSwzX16);
+  else
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
 }
 template <int CTRL>
-__device__ inline double p16_dppf64(double v) {
-  return __longlong_as_double((long long)dpp_u64<CTRL, 0xF>((unsigned long long)__double_as_longlong(v)));
+__device__ inline double p16_xf64(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const uint32_t lo = p16_x32<CTRL>((uint32_t)u), hi = p16_x32<CTRL>((uint32_t)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
-// Sum over the 16 lanes of a row; a butterfly, so every lane of the row gets
-// the same bits.
-__device__ inline double p16_row_sum(double v) {
-  v += p16_dppf64<kDppX8>(v);
-  v += p16_dppf64<kDppX7>(v);
-  v += p16_dppf64<kDppX2>(v);
-  v += p16_dppf64<kDppX1>(v);
+// Sum over the LPS lanes of a slot; a butterfly, so every lane of the slot
+// gets the same bits.
+template <int LPS>
+__device__ inline double p_slot_sum(double v) {
+  if constexpr (LPS == 32) v += p16_xf64<kSwzX16>(v);
+  v += p16_xf64<kDppX8>(v);
+  v += p16_xf64<kDppX7>(v);
+  v += p16_xf64<kDppX2>(v);
+  v += p16_xf64<kDppX1>(v);
   return v;
 }
 
-// Per-slot state, uniform over the slot's 16 lanes.
-struct P16Slot {
+// Per-slot state, uniform over the slot's lanes.
+struct PSlot {
   int node;       // node of the level, -1 when none is left for this slot
   int t, kmax;
   double eps2, e;
   bool run;
 };
 
-// Loads node `node` into the lane's 4 x 4 patch (FP64 values of the FP32
-// residual), the slot's BF16 row, and makes the first stop test; a node
+// Lane li of a slot holds the pixels y = PR yq + i (i < PR), x = 4 xq + j
+// (j < 4), yq = li / XQ, xq = li % XQ.
+//
+// Loads node `node` into the lane's patch (FP64 values of the FP32
+// residual) and the slot's BF16 row, and makes the first stop test; a node
 // that stops at once gets its final state here.
-__device__ __attribute__((always_inline)) inline void p16_load_node(const JobDev* __restrict__ jobs, const LevelDev& lv, int lg, int node,
-                                     int yq, int xq, int li, char* sBrow, double (&rd)[4][4], P16Slot& s) {
+template <class G>
+__device__ __attribute__((always_inline)) inline void p_load_node(const JobDev* __restrict__ jobs,
+                                                                  const LevelDev& lv, int lg, int node, int yq,
+                                                                  int xq, int li, char* sBrow,
+                                                                  double (&rd)[G::PR][4], PSlot& s) {
   const int jidx = lv.job[node];
   const int bx = lv.x0[node], by = lv.y0[node];
   const JobDev jl = jobs[jidx];
-  double pv[4][4];
+  double pv[G::PR][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) job_pixels<4>(jl, by + 4 * yq + i, bx + 4 * xq, pv[i]);
-  double ep[4];
+  for (int i = 0; i < G::PR; ++i) job_pixels<4>(jl, by + G::PR * yq + i, bx + 4 * xq, pv[i]);
+  double ep = 0.0;
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    ep[i] = 0.0;
-    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  for (int i = 0; i < G::PR; ++i) {
+    double ei = 0.0;
     bf16x4 b;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const float f = (float)pv[i][j];
       rd[i][j] = (double)f;
-      ep[i] = fma(pv[i][j], pv[i][j], ep[i]);
+      ei = fma(pv[i][j], pv[i][j], ei);
       b[j] = (__bf16)f;
     }
-    *(bf16x4*)(sBrow + ((4 * yq + i) * kP16N + 4 * xq) * 2) = b;
+    ep += ei;
+    *(bf16x4*)(sBrow + ((G::PR * yq + i) * G::N + 4 * xq) * 2) = b;
   }
   s.node = node;
-  s.e = p16_row_sum((ep[0] + ep[1]) + (ep[2] + ep[3]));
+  s.e = p_slot_sum<G::LPS>(ep);
   s.eps2 = jobs[jidx].eps2[lg];
   s.kmax = jobs[jidx].k[lg];
   s.t = 0;
@@ -272,19 +300,20 @@ __device__ __attribute__((always_inline)) inline void p16_load_node(const JobDev
 // Fills the wave's stopped slots from the level's nodes until each runs or
 // none are left: node blockIdx.x * 16 + slot first, then nodes from the
 // counter.  The loop and the lane exchange are uniform over the wave.
-__device__ __attribute__((always_inline)) inline void p16_refill(
+template <class G>
+__device__ __attribute__((always_inline)) inline void p_refill(
     const JobDev* __restrict__ jobs, const LevelDev& lv, int lg, int count, int32_t* next, int queue0, int slot,
-    int yq, int xq, int li, char* sBrow, double (&rd)[4][4], P16Slot& s, bool& first, bool& dry) {
+    int yq, int xq, int li, char* sBrow, double (&rd)[G::PR][4], PSlot& s, bool& first, bool& dry) {
   const int lane = threadIdx.x & 63;
   for (;;) {
     const bool need = !s.run && !dry;
     if (__ballot(need) == 0ull) break;
     int idx = 0;
-    if (need && li == 0) idx = first ? (int)blockIdx.x * kP16Slots + slot : queue0 + atomicAdd(next, 1);
-    idx = __shfl(idx, lane & ~15, 64);
+    if (need && li == 0) idx = first ? (int)blockIdx.x * kPSlots + slot : queue0 + atomicAdd(next, 1);
+    idx = __shfl(idx, lane & ~(G::LPS - 1), 64);
     if (need) {
       if (idx < count) {
-        p16_load_node(jobs, lv, lg, idx, yq, xq, li, sBrow, rd, s);
+        p_load_node<G>(jobs, lv, lg, idx, yq, xq, li, sBrow, rd, s);
       } else {
         dry = true;
         s.node = -1;
@@ -294,13 +323,15 @@ __device__ __attribute__((always_inline)) inline void p16_refill(
   }
 }
 
-__global__ __launch_bounds__(kP16Waves * 64, 1) void k_pursuit16_bf16(
+template <int N>
+__global__ __launch_bounds__(PGeo<N>::NT) void k_pursuit_bf16(
     const JobDev* __restrict__ jobs, LevelDev lv, const int32_t* __restrict__ count_ptr,
     int32_t* __restrict__ next, int32_t lg, int32_t n_atoms, int32_t nfam, const double* __restrict__ tab,
     const float* __restrict__ tabT32) {
-  constexpr int N = kP16N, K = kP16K, NS = kP16Slots, NT = kP16Waves * 64;
-  __shared__ __attribute__((aligned(16))) char sB[NS * kP16RowB];       // BF16 residual per slot
-  __shared__ __attribute__((aligned(16))) uint32_t sKey[kP16Waves][NS][8];
+  using G = PGeo<N>;
+  constexpr int K = G::K, NS = kPSlots, NT = G::NT, MA = G::MA, KS = G::KS, LPS = G::LPS;
+  __shared__ __attribute__((aligned(16))) char sB[NS * G::ROWB];        // BF16 residual per slot
+  __shared__ __attribute__((aligned(16))) uint32_t sKey[G::W][NS][8];
   __shared__ __attribute__((aligned(16))) double sTab[2][N][N];         // FP64 T_f[k][n]
   __shared__ float sT32[2][N][N];                                       // FP32 [f][n][k]
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -308,70 +339,71 @@ __global__ __launch_bounds__(kP16Waves * 64, 1) void k_pursuit16_bf16(
     (&sTab[0][0][0])[i] = tab[i];
     (&sT32[0][0][0])[i] = tabT32[i];
   }
-  for (int i = tid; i < NS * kP16RowB / 16; i += NT) ((uint4*)sB)[i] = make_uint4(0u, 0u, 0u, 0u);
+  for (int i = tid; i < NS * G::ROWB / 16; i += NT) ((uint4*)sB)[i] = make_uint4(0u, 0u, 0u, 0u);
   __syncthreads();
   const int count = *count_ptr;
   const double inv_n = 1.0 / N;
 
-  // ---- correlation geometry: wave w, family w / 4, q = 4 (w % 4) + ma ----
+  // ---- correlation geometry ----
   const int c16 = lane & 15, quad = lane >> 4;
-  const bool fam_ok = (w >> 2) < nfam;
-  const int fam = fam_ok ? (w >> 2) : 0;
-  const int qb = 4 * (w & 3);
-  // A fragment (tile ma, k-step ks): row p = c16, pixels 32 ks + 8 quad + j,
-  // i.e. y = 2 ks + quad / 2, x = 8 (quad % 2) + j.
-  p16_bf16x8 afr[4][8];
+  const int fw = w / G::WPF;                  // the wave's family
+  const bool fam_ok = fw < nfam;
+  const int fam = fam_ok ? fw : 0;
+  const int abase = (w % G::WPF) * G::AW;     // first atom of the wave within its family
+  // A fragment (tile ma, k-step ks): row = c16, pixels 32 ks + 8 quad + j
+  p16_bf16x8 afr[MA][KS];
 #pragma unroll
-  for (int ks = 0; ks < 8; ++ks) {
-    const int y = 2 * ks + (quad >> 1), x0 = 8 * (quad & 1);
-    const float tp = sT32[fam][y][c16];
+  for (int ma = 0; ma < MA; ++ma) {
+    const int a = abase + 16 * ma + c16, q = a / N, p = a % N;
+    const bool dc = a == 0;
 #pragma unroll
-    for (int ma = 0; ma < 4; ++ma)
+    for (int ks = 0; ks < KS; ++ks) {
+      const int px0 = 32 * ks + 8 * quad, y = px0 / N, x0 = px0 % N;
+      const float tp = sT32[fam][y][p];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) afr[ma][ks][j] = (__bf16)(tp * sT32[fam][x0 + j][qb + ma]);
+      for (int j = 0; j < 8; ++j) afr[ma][ks][j] = (__bf16)(dc ? (float)inv_n : tp * sT32[fam][x0 + j][q]);
+    }
   }
-  // 511 - atom of accumulator (ma, r): atom = 256 f + 16 (qb + ma) + 4 quad + r
-  const uint32_t lb = 511u - (uint32_t)(256 * (w >> 2) + 16 * qb + 4 * quad);
+  // (M - 1) - atom of accumulator (ma, r): atom = K f + abase + 16 ma + 4 quad + r
+  const uint32_t lb = (uint32_t)(G::M - 1) - (uint32_t)(K * fw + abase + 4 * quad);
 
-  // ---- slot geometry: waves 0-3 own the slots, four per wave (a DPP row each) ----
-  const bool owner = w < NS / 4;
-  const int slot = 4 * w + quad;
-  const int li = c16, yq = li >> 2, xq = li & 3;
-  char* sBrow = sB + (owner ? slot : 0) * kP16RowB;
-  P16Slot s{-1, 0, 0, 0.0, 0.0, false};
-  double rd[4][4];
+  // ---- slot geometry: wave w owns slots SPW w .. SPW w + SPW - 1 ----
+  const int slot = G::SPW * w + lane / LPS;
+  const int li = lane % LPS, yq = li / G::XQ, xq = li % G::XQ;
+  char* sBrow = sB + slot * G::ROWB;
+  PSlot s{-1, 0, 0, 0.0, 0.0, false};
+  double rd[G::PR][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < G::PR; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) rd[i][j] = 0.0;
   const int queue0 = gridDim.x * NS;   // nodes below this are dealt out in order
   bool first = true, dry = false;
-
-  if (owner) p16_refill(jobs, lv, lg, count, next, queue0, slot, yq, xq, li, sBrow, rd, s, first, dry);
-  first = false;
+  p_refill<G>(jobs, lv, lg, count, next, queue0, slot, yq, xq, li, sBrow, rd, s, first, dry);
   bool any = __syncthreads_or(s.run);
 
   while (any) {
-    // ---- C: correlation of the wave's 64 atoms with the 16 slots ----
-    p16_f32x4 acc[4];
+    // ---- C: correlation of the wave's atoms with the 16 slots ----
+    p16_f32x4 acc[MA];
 #pragma unroll
-    for (int ma = 0; ma < 4; ++ma) acc[ma] = p16_f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int ma = 0; ma < MA; ++ma) acc[ma] = p16_f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < 8; ++ks) {
-      const p16_bf16x8 bf = *(const p16_bf16x8*)(sB + c16 * kP16RowB + 64 * ks + 16 * quad);
+    for (int ks = 0; ks < KS; ++ks) {
+      const p16_bf16x8 bf = *(const p16_bf16x8*)(sB + c16 * G::ROWB + 64 * ks + 16 * quad);
 #pragma unroll
-      for (int ma = 0; ma < 4; ++ma) acc[ma] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[ma][ks], bf, acc[ma], 0, 0, 0);
+      for (int ma = 0; ma < MA; ++ma) acc[ma] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[ma][ks], bf, acc[ma], 0, 0, 0);
     }
     // ---- E: the wave's best 8 keys of slot c16 ----
     {
+      constexpr uint32_t kMask = ~((1u << G::IB) - 1u);
       uint32_t top[8], v[8];
 #pragma unroll
-      for (int g = 0; g < 2; ++g) {
+      for (int g = 0; g < MA / 2; ++g) {
 #pragma unroll
         for (int e8 = 0; e8 < 8; ++e8) {
           const int ma = 2 * g + (e8 >> 2), r = e8 & 3;
           const uint32_t bits = __float_as_uint(acc[ma][r]);
-          v[e8] = ((bits & 0x7FFFFF00u) << 1) | (lb - (uint32_t)(16 * ma + r));
+          v[e8] = ((bits << 1) & kMask) | (lb - (uint32_t)(16 * ma + r));
         }
         p16_sort8(v);
         if (g == 0) {
@@ -382,7 +414,7 @@ __global__ __launch_bounds__(kP16Waves * 64, 1) void k_pursuit16_bf16(
         }
       }
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = __shfl_xor(top[j], 16, 64);
+      for (int j = 0; j < 8; ++j) v[j] = p16_x32<kSwzX16>(top[j]);
       p16_merge8(top, v);
 #pragma unroll
       for (int j = 0; j < 8; ++j) v[j] = __shfl_xor(top[j], 32, 64);
@@ -394,454 +426,214 @@ __global__ __launch_bounds__(kP16Waves * 64, 1) void k_pursuit16_bf16(
       }
     }
     __syncthreads();
-    if (owner) {
-      if (s.run) {
-        // ---- M: the slot's 8 candidates from the eight wave lists ----
-        uint32_t top[8], v[8];
-        {
-          const uint4* kp = (const uint4*)&sKey[li & 7][slot][0];
-          const uint4 k0 = kp[0], k1 = kp[1];
-          top[0] = k0.x; top[1] = k0.y; top[2] = k0.z; top[3] = k0.w;
-          top[4] = k1.x; top[5] = k1.y; top[6] = k1.z; top[7] = k1.w;
-        }
+    if (s.run) {
+      // ---- M: the slot's 8 candidates from the W wave lists ----
+      uint32_t top[8], v[8];
+      {
+        const uint4* kp = (const uint4*)&sKey[li & (G::W - 1)][slot][0];
+        const uint4 k0 = kp[0], k1 = kp[1];
+        top[0] = k0.x; top[1] = k0.y; top[2] = k0.z; top[3] = k0.w;
+        top[4] = k1.x; top[5] = k1.y; top[6] = k1.z; top[7] = k1.w;
+      }
+      if constexpr (G::W == 8) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = p16_dpp32<kDppX7>(top[j]);
+        for (int j = 0; j < 8; ++j) v[j] = p16_x32<kDppX7>(top[j]);
         p16_merge8(top, v);
+      }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = p16_dpp32<kDppX1>(top[j]);
-        p16_merge8(top, v);
+      for (int j = 0; j < 8; ++j) v[j] = p16_x32<kDppX1>(top[j]);
+      p16_merge8(top, v);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = p16_dpp32<kDppX2>(top[j]);
-        p16_merge8(top, v);
-        int cand[8];
+      for (int j = 0; j < 8; ++j) v[j] = p16_x32<kDppX2>(top[j]);
+      p16_merge8(top, v);
+      // The lane's top three slot-lane bits (m) name the candidate it ends
+      // up summing; it takes the list in the order j ^ m, so that the
+      // halving exchanges below keep and send fixed positions.
+      const int m = (li / (LPS / 8)) & 7;
+      int cand[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const unsigned at = 511u - (top[j] & 0x1FFu);
-          cand[j] = (top[j] != 0u && at < (unsigned)n_atoms) ? (int)at : -1;
-        }
-        // ---- S: FP64 re-score, the lane's patch, then the row sums ----
-        double part[8];
+      for (int j = 0; j < 8; ++j) {
+        const unsigned at = (unsigned)(G::M - 1) - (top[j] & (unsigned)(G::M - 1));
+        cand[j] = (top[j] != 0u && at < (unsigned)n_atoms) ? (int)at : -1;
+      }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int at = cand[j] < 0 ? 0 : cand[j];
-          const int f = at >> 8, q = (at >> 4) & 15, p = at & 15;
-          const bool dc = (at & 255) == 0;
-          const double2 q0 = *(const double2*)&sTab[f][q][4 * xq];
-          const double2 q1 = *(const double2*)&sTab[f][q][4 * xq + 2];
-          const double2 p0 = *(const double2*)&sTab[f][p][4 * yq];
-          const double2 p1 = *(const double2*)&sTab[f][p][4 * yq + 2];
-          const double tq[4] = {dc ? 1.0 : q0.x, dc ? 1.0 : q0.y, dc ? 1.0 : q1.x, dc ? 1.0 : q1.y};
-          const double tp[4] = {dc ? 1.0 : p0.x, dc ? 1.0 : p0.y, dc ? 1.0 : p1.x, dc ? 1.0 : p1.y};
-          double sy[4];
+      for (int b = 4; b >= 1; b >>= 1)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            sy[i] = rd[i][0] * tq[0];
-#pragma unroll
-            for (int x = 1; x < 4; ++x) sy[i] = fma(rd[i][x], tq[x], sy[i]);
+        for (int j = 0; j < 8; ++j)
+          if (j < (j ^ b)) {
+            const int a0 = cand[j], a1 = cand[j ^ b];
+            cand[j] = (m & b) ? a1 : a0;
+            cand[j ^ b] = (m & b) ? a0 : a1;
           }
-          const double pt = fma(tp[0], sy[0], tp[1] * sy[1]) + fma(tp[2], sy[2], tp[3] * sy[3]);
-          part[j] = cand[j] < 0 ? 0.0 : (dc ? pt * inv_n : pt);
+      // ---- S: FP64 re-score on the lane's patch, then the slot sums ----
+      // The two constant atoms (p = q = 0) are exactly 1/N: their partial
+      // sum is the patch sum over N.
+      double dcpart = 0.0;
+#pragma unroll
+      for (int i = 0; i < G::PR; ++i) dcpart += (rd[i][0] + rd[i][1]) + (rd[i][2] + rd[i][3]);
+      dcpart *= inv_n;
+      double part[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int at = cand[j] < 0 ? 0 : cand[j];
+        const int f = at / K, q = (at % K) / N, p = at % N;
+        const double2 q0 = *(const double2*)&sTab[f][q][4 * xq];
+        const double2 q1 = *(const double2*)&sTab[f][q][4 * xq + 2];
+        double tp[G::PR];
+        if constexpr (G::PR == 2) {
+          const double2 p0 = *(const double2*)&sTab[f][p][2 * yq];
+          tp[0] = p0.x;
+          tp[1] = p0.y;
+        } else {
+          tp[0] = sTab[f][p][yq];
         }
-        // halves of the list go to the partner 8, 7 (within eight), 2 lanes
-        // away, then one plain sum: lane bits 3, 2, 1 name the candidate
-        const bool b3 = li & 8, b2 = li & 4, b1 = li & 2;
-        double h4[4], h2[2];
+        double pt = 0.0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) h4[j] = (b3 ? part[j + 4] : part[j]) + p16_dppf64<kDppX8>(b3 ? part[j] : part[j + 4]);
+        for (int i = 0; i < G::PR; ++i) {
+          const double sy = fma(rd[i][0], q0.x, rd[i][1] * q0.y) + fma(rd[i][2], q1.x, rd[i][3] * q1.y);
+          pt = i == 0 ? tp[0] * sy : fma(tp[i], sy, pt);
+        }
+        part[j] = (at % K) == 0 ? dcpart : pt;   // an empty candidate's value is never chosen
+      }
+      // halves of the list go to the partners that differ in the lane's top
+      // three slot bits, then plain sums over the rest
+      double h4[4], h2[2], c;
+      if constexpr (LPS == 32) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) h2[j] = (b2 ? h4[j + 2] : h4[j]) + p16_dppf64<kDppX7>(b2 ? h4[j] : h4[j + 2]);
-        double c = (b1 ? h2[1] : h2[0]) + p16_dppf64<kDppX2>(b1 ? h2[0] : h2[1]);
-        c += p16_dppf64<kDppX1>(c);
-        const int jj = (b3 ? 4 : 0) + (b2 ? 2 : 0) + (b1 ? 1 : 0);
-        int at = -1;
+        for (int j = 0; j < 4; ++j) h4[j] = part[j] + p16_xf64<kSwzX16>(part[j + 4]);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) at = jj == j ? cand[j] : at;
-        // ---- A: arg-max over the row (lowest atom on ties) ----
-        double mag = at >= 0 ? fabs(c) : -1.0;
-#define AQMP_P16_ARGMAX(CTRL)                                                            \
+        for (int j = 0; j < 2; ++j) h2[j] = h4[j] + p16_xf64<kDppX8>(h4[j + 2]);
+        c = h2[0] + p16_xf64<kDppX7>(h2[1]);
+        c += p16_xf64<kDppX2>(c);
+        c += p16_xf64<kDppX1>(c);
+      } else {
+        // m = lane bits 3, 2, 1: the half-row mirror flips m bits 1 and 0
+        // together, so the partner's list is taken in reverse order there
+#pragma unroll
+        for (int j = 0; j < 4; ++j) h4[j] = part[j] + p16_xf64<kDppX8>(part[j + 4]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) h2[j] = h4[j] + p16_xf64<kDppX7>(h4[3 - j]);
+        c = h2[0] + p16_xf64<kDppX2>(h2[1]);
+        c += p16_xf64<kDppX1>(c);
+      }
+      int at = cand[0];
+      // ---- A: arg-max over the slot (lowest atom on ties) ----
+      double mag = at >= 0 ? fabs(c) : -1.0;
+#define AQMP_P_ARGMAX(CTRL)                                                              \
   {                                                                                      \
-    const double om = p16_dppf64<CTRL>(mag), oc = p16_dppf64<CTRL>(c);                   \
-    const int oa = (int)p16_dpp32<CTRL>((uint32_t)at);                                   \
+    const double om = p16_xf64<CTRL>(mag), oc = p16_xf64<CTRL>(c);                       \
+    const int oa = (int)p16_x32<CTRL>((uint32_t)at);                                     \
     const bool take = om > mag || (om == mag && oa < at);                                \
     mag = take ? om : mag;                                                               \
     c = take ? oc : c;                                                                   \
     at = take ? oa : at;                                                                 \
   }
-        AQMP_P16_ARGMAX(kDppX8) AQMP_P16_ARGMAX(kDppX7) AQMP_P16_ARGMAX(kDppX2)
-#undef AQMP_P16_ARGMAX
-        const bool zero = at < 0 || mag == 0.0;
-        if (zero) {
+      if constexpr (LPS == 32) {
+        AQMP_P_ARGMAX(kSwzX16) AQMP_P_ARGMAX(kDppX8) AQMP_P_ARGMAX(kDppX7)
+      } else {
+        AQMP_P_ARGMAX(kDppX8) AQMP_P_ARGMAX(kDppX7) AQMP_P_ARGMAX(kDppX2)
+      }
+#undef AQMP_P_ARGMAX
+      const bool zero = at < 0 || mag == 0.0;
+      if (zero) {
+        s.run = false;
+        if (li == 0) {
+          lv.e[s.node] = s.e;
+          lv.t[s.node] = s.t;
+          lv.st[s.node] = ST_ZERO;
+        }
+      } else {
+        // rank-1 update of the patch, ||r||^2, record, stop test
+        const int f = at / K, q = (at % K) / N, p = at % N;
+        const bool dc = (at % K) == 0;
+        const double2 q0 = *(const double2*)&sTab[f][q][4 * xq];
+        const double2 q1 = *(const double2*)&sTab[f][q][4 * xq + 2];
+        const double tq[4] = {q0.x, q0.y, q1.x, q1.y};
+        double tp[G::PR];
+        if constexpr (G::PR == 2) {
+          const double2 p0 = *(const double2*)&sTab[f][p][2 * yq];
+          tp[0] = p0.x;
+          tp[1] = p0.y;
+        } else {
+          tp[0] = sTab[f][p][yq];
+        }
+        double eh = 0.0;
+        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int i = 0; i < G::PR; ++i) {
+          bf16x4 b;
+          double ei = 0.0;
+#pragma unroll
+          for (int x = 0; x < 4; ++x) {
+            const double phi = dc ? inv_n : tp[i] * tq[x];
+            const float rn = (float)fma(-c, phi, rd[i][x]);
+            rd[i][x] = (double)rn;
+            ei = fma(rd[i][x], rd[i][x], ei);
+            b[x] = (__bf16)rn;
+          }
+          eh += ei;
+          *(bf16x4*)(sBrow + ((G::PR * yq + i) * N + 4 * xq) * 2) = b;
+        }
+        const double en = p_slot_sum<LPS>(eh);
+        if (li == 0) {
+          const size_t rs = (size_t)s.node * lv.kmax + s.t;
+          lv.rec_idx[rs] = at;
+          lv.rec_coef[rs] = c;
+        }
+        s.t += 1;
+        s.e = en;
+        uint8_t st = ST_RUN;
+        if (en < s.eps2)
+          st = ST_ACC;
+        else if (s.t >= s.kmax)
+          st = ST_SPARSE;
+        if (st != ST_RUN) {
           s.run = false;
           if (li == 0) {
             lv.e[s.node] = s.e;
             lv.t[s.node] = s.t;
-            lv.st[s.node] = ST_ZERO;
-          }
-        } else {
-          // rank-1 update of the patch, ||r||^2, record, stop test
-          const int f = at >> 8, q = (at >> 4) & 15, p = at & 15;
-          const bool dc = (at & 255) == 0;
-          const double2 q0 = *(const double2*)&sTab[f][q][4 * xq];
-          const double2 q1 = *(const double2*)&sTab[f][q][4 * xq + 2];
-          const double2 p0 = *(const double2*)&sTab[f][p][4 * yq];
-          const double2 p1 = *(const double2*)&sTab[f][p][4 * yq + 2];
-          const double tq[4] = {q0.x, q0.y, q1.x, q1.y};
-          const double tp[4] = {p0.x, p0.y, p1.x, p1.y};
-          double eh[4];
-          typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            bf16x4 b;
-            eh[i] = 0.0;
-#pragma unroll
-            for (int x = 0; x < 4; ++x) {
-              const double phi = dc ? inv_n : tp[i] * tq[x];
-              const float rn = (float)fma(-c, phi, rd[i][x]);
-              rd[i][x] = (double)rn;
-              eh[i] = fma(rd[i][x], rd[i][x], eh[i]);
-              b[x] = (__bf16)rn;
-            }
-            *(bf16x4*)(sBrow + ((4 * yq + i) * N + 4 * xq) * 2) = b;
-          }
-          const double en = p16_row_sum((eh[0] + eh[1]) + (eh[2] + eh[3]));
-          if (li == 0) {
-            const size_t rs = (size_t)s.node * lv.kmax + s.t;
-            lv.rec_idx[rs] = at;
-            lv.rec_coef[rs] = c;
-          }
-          s.t += 1;
-          s.e = en;
-          uint8_t st = ST_RUN;
-          if (en < s.eps2)
-            st = ST_ACC;
-          else if (s.t >= s.kmax)
-            st = ST_SPARSE;
-          if (st != ST_RUN) {
-            s.run = false;
-            if (li == 0) {
-              lv.e[s.node] = s.e;
-              lv.t[s.node] = s.t;
-              lv.st[s.node] = st;
-            }
+            lv.st[s.node] = st;
           }
         }
       }
-      p16_refill(jobs, lv, lg, count, next, queue0, slot, yq, xq, li, sBrow, rd, s, first, dry);
     }
+    p_refill<G>(jobs, lv, lg, count, next, queue0, slot, yq, xq, li, sBrow, rd, s, first, dry);
     any = __syncthreads_or(s.run);
   }
 }
-// ---------------------------------------------------------------------------
-// Whole-level pursuit for N = 8 in the BF16 form.  One wave takes G <= 16
-// nodes through their whole pursuit (Section 2.2 steps (a)-(d), eq. (2)),
-// with no workgroup barrier: the waves of a workgroup are independent.
-// Lane l serves node l % 16 and holds rows 2 (l / 16), 2 (l / 16) + 1 of its
-// FP32 residual in registers for the whole pursuit.
-//   C  correlation of all M <= 128 atoms with the G BF16 residuals by
-//      v_mfma_f32_16x16x32_bf16 (A = 16 atoms x 32 pixels, B = 32 pixels x
-//      16 nodes, FP32 accumulation; output row 4 (l / 16) + r, column
-//      l % 16).  The BF16 atoms never change, so the wave builds all 16 A
-//      fragments (8 atom tiles x 2 pixel halves) once, in registers: atom
-//      a = 16 ma + row, family a / 64, q = (a % 64) / 8, p = a % 8, value
-//      bf16(fl32(T_f[p][y]) fl32(T_f[q][x])), constant atom exactly 1/8.  The
-//      B fragments (BF16 residual rows) go through LDS;
-//   E  each lane ranks the 32 correlations it holds of its node (4 per atom
-//      tile) as 32-bit keys (|c| bits, then 127 - atom: a larger key is a
-//      larger |c|, then the lower atom), keeps its best 8 with sorting
-//      networks and merges them with the node's other three lanes;
-//   S  FP64 re-score of the 8 candidates: each lane sums over its own 16
-//      pixels (sum_y T[p][y] sum_x r[y][x] T[q][x], the table rows read from
-//      LDS in one batch), then the node's four lanes add their partials;
-//   A  arg-max (lowest atom on ties), rank-1 update of the lane's pixels in
-//      FP64 rounded to FP32, ||r||^2 in FP64, record (i, c_i) straight to
-//      memory, stop test.
-// ---------------------------------------------------------------------------
-typedef __bf16 p8_bf16x8 __attribute__((ext_vector_type(8)));
-typedef float p8_f32x4 __attribute__((ext_vector_type(4)));
-
-// Sum over the four lanes l % 16 + 16 j of a node (a fixed order: the
-// partner 16 lanes away, then the partner 32 lanes away).
-__device__ inline double quad_sum(double v) {
-  v += __shfl_xor(v, 16, 64);
-  v += __shfl_xor(v, 32, 64);
-  return v;
-}
-
-template <int G>
-__global__ __launch_bounds__(256) void k_pursuit8_bf16(const JobDev* __restrict__ jobs, LevelDev lv,
-                                                       const int32_t* __restrict__ count_ptr, int32_t n_atoms,
-                                                       int32_t nfam, const double* __restrict__ tab,
-                                                       const float* __restrict__ tabT32) {
-  constexpr int N = 8, K = 64;
-  static_assert(G >= 1 && G <= 16, "at most 16 nodes per wave (the B operand's columns)");
-  __shared__ __attribute__((aligned(16))) double sTab[2][N][N];   // [f][p][y] FP64
-  __shared__ float sT32[2][N][N];                                 // [f][y][p] FP32
-  __shared__ __attribute__((aligned(16))) uint4 sB[4][N][16];     // BF16 residual rows [wave][row][node]
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int i = tid; i < nfam * K; i += 256) {
-    (&sTab[0][0][0])[i] = tab[i];
-    (&sT32[0][0][0])[i] = tabT32[i];
-  }
-  __syncthreads();
-  const int count = *count_ptr;
-  const int c = lane & 15, quad = lane >> 4;      // node column, lane group of the node
-  const int y0 = 2 * quad;                        // the lane's rows y0, y0 + 1
-  const double inv_n = 1.0 / N;
-
-  // A fragments: tile ma (16 atoms), pixel half kh (rows 4 kh .. 4 kh + 3).
-  p8_bf16x8 afr[8][2];
-#pragma unroll
-  for (int ma = 0; ma < 8; ++ma) {
-    const int a = 16 * ma + c;
-    const int f = a / K, q = (a % K) / N, p = a % N;
-    const bool ok = a < n_atoms;
-    const int ff = ok ? f : 0;
-#pragma unroll
-    for (int kh = 0; kh < 2; ++kh) {
-      const int y = 4 * kh + quad;
-      const float tpy = sT32[ff][y][p];
-      p8_bf16x8 v;
-#pragma unroll
-      for (int x = 0; x < N; ++x) {
-        const float prod = (p == 0 && q == 0) ? 0.125f : tpy * sT32[ff][x][q];
-        v[x] = (__bf16)(ok ? prod : 0.f);
-      }
-      afr[ma][kh] = v;
-    }
-  }
-  // atom of accumulator element r of tile ma: 16 ma + 4 quad + r
-  const uint32_t kb = 127u - (uint32_t)(4 * quad);
-
-  const int ngroups = (count + G - 1) / G;
-  for (int grp = blockIdx.x * 4 + w; grp < ngroups; grp += gridDim.x * 4) {
-    const int g0 = grp * G;
-    const int node = g0 + c;
-    const bool mine = c < G && node < count;      // a real node behind this lane's column
-    // ---- gather (Algorithm 2: y = unravel(b)), the lane's two rows ----
-    float rr[2][N];
-    double eps2 = 0.0, e = 0.0;
-    int kmax = 0, t = 0;
-    uint8_t st = ST_SPARSE;
-    {
-      const int nd = mine ? node : g0;
-      const JobDev& jb = jobs[lv.job[nd]];
-      const int bx = lv.x0[nd], by = lv.y0[nd];
-      double ep = 0.0;
-      const JobDev jl = jb;   // one copy of the job's fields in registers
-      double pv[2][N];
-#pragma unroll
-      for (int dy = 0; dy < 2; ++dy) job_pixels<N>(jl, by + y0 + dy, bx, pv[dy]);
-#pragma unroll
-      for (int dy = 0; dy < 2; ++dy) {
-        p8_bf16x8 b;
-#pragma unroll
-        for (int x = 0; x < N; ++x) {
-          const double v = mine ? pv[dy][x] : 0.0;
-          rr[dy][x] = (float)v;
-          ep += v * v;
-          b[x] = (__bf16)rr[dy][x];
-        }
-        sB[w][y0 + dy][c] = __builtin_bit_cast(uint4, b);
-      }
-      e = quad_sum(ep);
-      eps2 = jb.eps2[3];
-      kmax = jb.k[3];
-      if (mine) st = e < eps2 ? ST_ACC : (kmax <= 0 ? ST_SPARSE : ST_RUN);
-    }
-    wave_sync();
-    while (__ballot(st == ST_RUN) != 0ull) {
-      // ---- C: correlation of every atom with the G residuals ----
-      p8_f32x4 acc[8];
-#pragma unroll
-      for (int ma = 0; ma < 8; ++ma) acc[ma] = p8_f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kh = 0; kh < 2; ++kh) {
-        const p8_bf16x8 bf = __builtin_bit_cast(p8_bf16x8, sB[w][4 * kh + quad][c]);
-#pragma unroll
-        for (int ma = 0; ma < 8; ++ma)
-          acc[ma] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[ma][kh], bf, acc[ma], 0, 0, 0);
-      }
-      // ---- E: the node's best 8 keys ----
-      uint32_t top[8];
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        uint32_t v[8];
-#pragma unroll
-        for (int e8 = 0; e8 < 8; ++e8) {
-          const int ma = 2 * g + (e8 >> 2), r = e8 & 3;
-          const uint32_t bits = __float_as_uint(acc[ma][r]) & 0x7FFFFF80u;
-          const uint32_t atom_low = kb - (uint32_t)(16 * ma + r);     // 127 - atom
-          v[e8] = (16 * ma + 4 * quad + r < n_atoms) ? (bits | atom_low) : 0u;
-        }
-        p16_sort8(v);
-        if (g == 0) {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) top[j] = v[j];
-        } else {
-          p16_merge8(top, v);
-        }
-      }
-#pragma unroll
-      for (int sh = 16; sh <= 32; sh <<= 1) {
-        uint32_t o[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) o[j] = __shfl_xor(top[j], sh, 64);
-        p16_merge8(top, o);
-      }
-      // ---- S: FP64 re-score of the 8 candidates on the lane's 16 pixels ----
-      double rd[2][N];
-#pragma unroll
-      for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-        for (int x = 0; x < N; ++x) rd[dy][x] = (double)rr[dy][x];
-      int cand[8];
-      double cv[8];
-#pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        // table rows of four candidates, read before any arithmetic
-        double tq[4][N], tp[4][2];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int j = 4 * half + i;
-          const int at = top[j] != 0u ? (int)(127u - (top[j] & 0x7Fu)) : -1;
-          cand[j] = at;
-          const int aa = at < 0 ? 0 : at;
-          const int f = aa / K, q = (aa % K) / N, p = aa % N;
-          const double2* qr = (const double2*)&sTab[f][q][0];
-#pragma unroll
-          for (int x2 = 0; x2 < N / 2; ++x2) {
-            const double2 u = qr[x2];
-            tq[i][2 * x2] = u.x;
-            tq[i][2 * x2 + 1] = u.y;
-          }
-          const double2 pr = *(const double2*)&sTab[f][p][y0];
-          tp[i][0] = pr.x;
-          tp[i][1] = pr.y;
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int j = 4 * half + i;
-          const int aa = cand[j] < 0 ? 0 : cand[j];
-          const bool dc = (aa % K) == 0;            // p = q = 0: the constant atom
-          double part = 0.0;
-#pragma unroll
-          for (int dy = 0; dy < 2; ++dy) {
-            double sx = 0.0;
-#pragma unroll
-            for (int x = 0; x < N; ++x) sx = fma(rd[dy][x], dc ? 1.0 : tq[i][x], sx);
-            part = dc ? part + sx : fma(tp[i][dy], sx, part);
-          }
-          cv[j] = dc ? part * inv_n : part;
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) cv[j] = quad_sum(cv[j]);
-      // ---- A: arg-max (lowest atom on ties), update, norm, record, stop ----
-      int best = -1;
-      double bmag = -1.0;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const double m = fabs(cv[j]);
-        const bool better = cand[j] >= 0 && (best < 0 || m > bmag || (m == bmag && cand[j] < cand[best < 0 ? 0 : best]));
-        if (better) {
-          best = j;
-          bmag = m;
-        }
-      }
-      const bool zero = best < 0 || bmag == 0.0;
-      int atom = 0;
-      double coef = 0.0;
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if (j == best) {
-          atom = cand[j];
-          coef = cv[j];
-        }
-      const bool run = st == ST_RUN;
-      double en = 0.0;
-      if (run && !zero) {
-        const int f = atom / K, q = (atom % K) / N, p = atom % N;
-        const bool dc = (p == 0 && q == 0);
-        double tqx[N];
-        const double2* qr = (const double2*)&sTab[f][q][0];
-#pragma unroll
-        for (int x2 = 0; x2 < N / 2; ++x2) {
-          const double2 u = qr[x2];
-          tqx[2 * x2] = u.x;
-          tqx[2 * x2 + 1] = u.y;
-        }
-        const double2 pr = *(const double2*)&sTab[f][p][y0];
-        const double tpy[2] = {pr.x, pr.y};
-#pragma unroll
-        for (int dy = 0; dy < 2; ++dy) {
-          p8_bf16x8 b;
-#pragma unroll
-          for (int x = 0; x < N; ++x) {
-            const double phi = dc ? inv_n : tpy[dy] * tqx[x];
-            rr[dy][x] = (float)fma(-coef, phi, rd[dy][x]);
-            en = fma((double)rr[dy][x], (double)rr[dy][x], en);
-            b[x] = (__bf16)rr[dy][x];
-          }
-          sB[w][y0 + dy][c] = __builtin_bit_cast(uint4, b);
-        }
-      }
-      en = quad_sum(en);
-      if (run) {
-        if (zero) {
-          st = ST_ZERO;
-        } else {
-          if (quad == 0) {
-            const size_t slot = (size_t)node * lv.kmax + t;
-            lv.rec_idx[slot] = atom;
-            lv.rec_coef[slot] = coef;
-          }
-          e = en;
-          ++t;
-          st = e < eps2 ? ST_ACC : (t >= kmax ? ST_SPARSE : ST_RUN);
-        }
-      }
-      wave_sync();   // the new BF16 rows are in LDS before the next correlation reads them
-    }
-    if (mine && quad == 0) {
-      lv.e[node] = e;
-      lv.t[node] = t;
-      lv.st[node] = st;
-    }
-    wave_sync();   // the next group overwrites this group's rows
-  }
-}
-
 }  // namespace
 
-hipError_t launch_pursuit16_bf16(const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int64_t cap,
-                                 int32_t n_atoms, int32_t nfam, const double* tab, const float* tabT32, hipStream_t s) {
+namespace {
+template <int N>
+hipError_t launch_pursuit_n(const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next, int64_t cap,
+                            int32_t lg, int32_t n_atoms, int32_t nfam, const double* tab, const float* tabT32,
+                            hipStream_t s) {
+  using G = PGeo<N>;
   // Slots take nodes until none are left, so the grid is as many workgroups
   // as are resident at once (at most one per 16 nodes of the level).
   int dev = 0, n_cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pursuit16_bf16, kP16Waves * 64, 0) != hipSuccess ||
-      per_cu < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pursuit_bf16<N>, G::NT, 0) != hipSuccess || per_cu < 1)
     per_cu = 1;
-  int64_t wgs = (cap + kP16Slots - 1) / kP16Slots;
+  int64_t wgs = (cap + kPSlots - 1) / kPSlots;
   if (wgs > (int64_t)n_cus * per_cu) wgs = (int64_t)n_cus * per_cu;
   if (wgs < 1) wgs = 1;
-  hipLaunchKernelGGL(k_pursuit16_bf16, dim3((unsigned)wgs), dim3(kP16Waves * 64), 0, s, jobs, lv, count, next, 4,
-                     n_atoms, nfam, tab, tabT32);
+  hipLaunchKernelGGL(k_pursuit_bf16<N>, dim3((unsigned)wgs), dim3(G::NT), 0, s, jobs, lv, count, next, lg, n_atoms,
+                     nfam, tab, tabT32);
   return hipGetLastError();
 }
+}  // namespace
 
-hipError_t launch_pursuit8_bf16(const JobDev* jobs, LevelDev lv, const int32_t* count, int64_t cap, int32_t n_atoms,
-                                int32_t nfam, const double* tab, const float* tabT32, hipStream_t s) {
-  constexpr int G = kP8Nodes;
-  int64_t groups = (cap + G - 1) / G;
-  int64_t wgs = (groups + 3) / 4;
-  if (wgs > 4096) wgs = 4096;
-  if (wgs < 1) wgs = 1;
-  hipLaunchKernelGGL(k_pursuit8_bf16<G>, dim3((unsigned)wgs), dim3(256), 0, s, jobs, lv, count, n_atoms, nfam, tab,
-                     tabT32);
-  return hipGetLastError();
+hipError_t launch_pursuit_bf16(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t* next,
+                               int64_t cap, int32_t n_atoms, int32_t nfam, const double* tab, const float* tabT32,
+                               hipStream_t s) {
+  switch (n) {
+    case 8: return launch_pursuit_n<8>(jobs, lv, count, next, cap, 3, n_atoms, nfam, tab, tabT32, s);
+    case 16: return launch_pursuit_n<16>(jobs, lv, count, next, cap, 4, n_atoms, nfam, tab, tabT32, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_mp_fused(int n, const JobDev* jobs, LevelDev lv, const int32_t* count, int32_t lg, int32_t n_atoms,

@@ -107,7 +107,7 @@ def test_corr_kernel_names():
     for removed in (1, 4, 5):                                             # removed forms are rejected
         assert A.corr_kernel(64, A.PREC_BF16, removed) == ""
     assert A.corr_kernel(64, A.PREC_FP32) == "k_corr_f32<64>"
-    assert A.corr_kernel(8, A.PREC_BF16) == "k_pursuit8_bf16<16>"
+    assert A.corr_kernel(8, A.PREC_BF16) == "k_pursuit_bf16<8>"
     assert A.corr_kernel(8, A.PREC_FP32) == "k_mp_fused<8>"
     assert A.corr_kernel(4, A.PREC_BF16) == "k_mp_fused<4>"
     assert A.corr_kernel(4, A.PREC_FP32) == "k_mp_fused<4>"
