@@ -154,8 +154,8 @@ __global__ __launch_bounds__(256) void k_mp_fused(const JobDev* __restrict__ job
 //      FP64 rounded to FP32, ||r||^2 in FP64, record (i, c_i), stop test.
 // A slot whose node stops takes the next node of the level (the first
 // gridDim.x * 16 nodes are dealt out in order, the rest come from a
-// counter), so stopped nodes cost no MFMA columns while work remains and
-// one wave of workgroups covers the whole level.  Every reduction is a
+// counter, up to two fetches per step), so stopped nodes cost no MFMA
+// columns while work remains and one wave of workgroups covers the level.  Every reduction is a
 // butterfly over XOR partners, so the lanes of a slot hold bit-identical
 // sums and take the same decisions.
 // ---------------------------------------------------------------------------
@@ -177,7 +177,7 @@ struct PGeo {
   static constexpr int IB = N == 16 ? 9 : 7;        // bits of the atom index in a key
   static constexpr int ROWB = 2 * K + 16;           // bytes per slot in the BF16 residual (padded)
   static_assert(MA * 16 * W == M && KS * 32 == K, "whole tiles");
-  static_assert(LPS == 16 || LPS == 32, "a slot is one or two DPP rows");
+  static_assert(LPS == 8 || LPS == 16 || LPS == 32, "a slot is half a DPP row, one or two rows");
   static_assert(PR * 4 * LPS == K && PR >= 1, "whole patches");
   static_assert((1 << IB) == M, "key index width");
 };
@@ -231,7 +231,7 @@ __device__ inline double p16_xf64(double v) {
 template <int LPS>
 __device__ inline double p_slot_sum(double v) {
   if constexpr (LPS == 32) v += p16_xf64<kSwzX16>(v);
-  v += p16_xf64<kDppX8>(v);
+  if constexpr (LPS >= 16) v += p16_xf64<kDppX8>(v);
   v += p16_xf64<kDppX7>(v);
   v += p16_xf64<kDppX2>(v);
   v += p16_xf64<kDppX1>(v);
@@ -297,29 +297,29 @@ __device__ __attribute__((always_inline)) inline void p_load_node(const JobDev* 
   }
 }
 
-// Fills the wave's stopped slots from the level's nodes until each runs or
-// none are left: node blockIdx.x * 16 + slot first, then nodes from the
-// counter.  The loop and the lane exchange are uniform over the wave.
+// One fetch for each of the wave's stopped slots: the slot leader takes the
+// next node from the counter, the lanes of the slot receive it and load it.
+// Straight-line code, no loop: a cross-lane exchange inside a loop whose exit
+// depends on an atomic result let the compiler's structurised control flow
+// run lanes of one slot out of step.  A slot whose new node stops at once
+// tries again at the next fetch.
 template <class G>
-__device__ __attribute__((always_inline)) inline void p_refill(
-    const JobDev* __restrict__ jobs, const LevelDev& lv, int lg, int count, int32_t* next, int queue0, int slot,
-    int yq, int xq, int li, char* sBrow, double (&rd)[G::PR][4], PSlot& s, bool& first, bool& dry) {
-  const int lane = threadIdx.x & 63;
-  for (;;) {
-    const bool need = !s.run && !dry;
-    if (__ballot(need) == 0ull) break;
-    int idx = 0;
-    if (need && li == 0) idx = first ? (int)blockIdx.x * kPSlots + slot : queue0 + atomicAdd(next, 1);
-    idx = __shfl(idx, lane & ~(G::LPS - 1), 64);
-    if (need) {
-      if (idx < count) {
-        p_load_node<G>(jobs, lv, lg, idx, yq, xq, li, sBrow, rd, s);
-      } else {
-        dry = true;
-        s.node = -1;
-      }
+__device__ __attribute__((always_inline)) inline void p_fetch(
+    const JobDev* __restrict__ jobs, const LevelDev& lv, int lg, int count, int32_t* next, int queue0, int yq,
+    int xq, int li, char* sBrow, double (&rd)[G::PR][4], PSlot& s, bool& dry) {
+  const int lane = threadIdx.x & 63, lead = lane & ~(G::LPS - 1);
+  // the leader's decision, taken by the whole slot
+  const bool need = __shfl((int)(!s.run && !dry), lead, 64) != 0;
+  int idx = 0;
+  if (need && li == 0) idx = queue0 + atomicAdd(next, 1);
+  idx = __shfl(idx, lead, 64);
+  if (need) {
+    if (idx < count) {
+      p_load_node<G>(jobs, lv, lg, idx, yq, xq, li, sBrow, rd, s);
+    } else {
+      dry = true;
+      s.node = -1;
     }
-    first = false;
   }
 }
 
@@ -377,10 +377,19 @@ __global__ __launch_bounds__(PGeo<N>::NT) void k_pursuit_bf16(
   for (int i = 0; i < G::PR; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) rd[i][j] = 0.0;
-  const int queue0 = gridDim.x * NS;   // nodes below this are dealt out in order
-  bool first = true, dry = false;
-  p_refill<G>(jobs, lv, lg, count, next, queue0, slot, yq, xq, li, sBrow, rd, s, first, dry);
-  bool any = __syncthreads_or(s.run);
+  // Node blockIdx.x * 16 + slot first (no exchange needed), then nodes from
+  // the counter, starting after the first gridDim.x * 16.
+  const int queue0 = gridDim.x * NS;
+  bool dry = false;
+  {
+    const int idx0 = (int)blockIdx.x * NS + slot;
+    if (idx0 < count)
+      p_load_node<G>(jobs, lv, lg, idx0, yq, xq, li, sBrow, rd, s);
+    else
+      dry = true;
+  }
+  p_fetch<G>(jobs, lv, lg, count, next, queue0, yq, xq, li, sBrow, rd, s, dry);
+  bool any = __syncthreads_or(s.run || !dry);
 
   while (any) {
     // ---- C: correlation of the wave's atoms with the 16 slots ----
@@ -443,9 +452,11 @@ __global__ __launch_bounds__(PGeo<N>::NT) void k_pursuit_bf16(
 #pragma unroll
       for (int j = 0; j < 8; ++j) v[j] = p16_x32<kDppX1>(top[j]);
       p16_merge8(top, v);
+      if constexpr (G::W >= 4) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = p16_x32<kDppX2>(top[j]);
-      p16_merge8(top, v);
+        for (int j = 0; j < 8; ++j) v[j] = p16_x32<kDppX2>(top[j]);
+        p16_merge8(top, v);
+      }
       // The lane's top three slot-lane bits (m) name the candidate it ends
       // up summing; it takes the list in the order j ^ m, so that the
       // halving exchanges below keep and send fixed positions.
@@ -506,7 +517,7 @@ __global__ __launch_bounds__(PGeo<N>::NT) void k_pursuit_bf16(
         c = h2[0] + p16_xf64<kDppX7>(h2[1]);
         c += p16_xf64<kDppX2>(c);
         c += p16_xf64<kDppX1>(c);
-      } else {
+      } else if constexpr (LPS == 16) {
         // m = lane bits 3, 2, 1: the half-row mirror flips m bits 1 and 0
         // together, so the partner's list is taken in reverse order there
 #pragma unroll
@@ -515,6 +526,13 @@ __global__ __launch_bounds__(PGeo<N>::NT) void k_pursuit_bf16(
         for (int j = 0; j < 2; ++j) h2[j] = h4[j] + p16_xf64<kDppX7>(h4[3 - j]);
         c = h2[0] + p16_xf64<kDppX2>(h2[1]);
         c += p16_xf64<kDppX1>(c);
+      } else {
+        // m = lane bits 2, 1, 0: the half-row mirror flips all three
+#pragma unroll
+        for (int j = 0; j < 4; ++j) h4[j] = part[j] + p16_xf64<kDppX7>(part[7 - j]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) h2[j] = h4[j] + p16_xf64<kDppX2>(h4[j + 2]);
+        c = h2[0] + p16_xf64<kDppX1>(h2[1]);
       }
       int at = cand[0];
       // ---- A: arg-max over the slot (lowest atom on ties) ----
@@ -530,8 +548,10 @@ __global__ __launch_bounds__(PGeo<N>::NT) void k_pursuit_bf16(
   }
       if constexpr (LPS == 32) {
         AQMP_P_ARGMAX(kSwzX16) AQMP_P_ARGMAX(kDppX8) AQMP_P_ARGMAX(kDppX7)
-      } else {
+      } else if constexpr (LPS == 16) {
         AQMP_P_ARGMAX(kDppX8) AQMP_P_ARGMAX(kDppX7) AQMP_P_ARGMAX(kDppX2)
+      } else {
+        AQMP_P_ARGMAX(kDppX7) AQMP_P_ARGMAX(kDppX2) AQMP_P_ARGMAX(kDppX1)
       }
 #undef AQMP_P_ARGMAX
       const bool zero = at < 0 || mag == 0.0;
@@ -597,8 +617,9 @@ __global__ __launch_bounds__(PGeo<N>::NT) void k_pursuit_bf16(
         }
       }
     }
-    p_refill<G>(jobs, lv, lg, count, next, queue0, slot, yq, xq, li, sBrow, rd, s, first, dry);
-    any = __syncthreads_or(s.run);
+    p_fetch<G>(jobs, lv, lg, count, next, queue0, yq, xq, li, sBrow, rd, s, dry);
+    p_fetch<G>(jobs, lv, lg, count, next, queue0, yq, xq, li, sBrow, rd, s, dry);
+    any = __syncthreads_or(s.run || !dry);
   }
 }
 }  // namespace
