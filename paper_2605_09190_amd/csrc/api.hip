@@ -190,7 +190,10 @@ int aqmp_worklist_split(const aqmp_params* prm, int n_prm, int n, const int32_t*
 const char* aqmp_last_error(void) { return last_error(); }
 
 const char* aqmp_corr_kernel(int n, int precision, int corr_variant) {
-  return aqmp::corr_kernel_name(n, precision, corr_variant);
+  // the N = 8 level of the BF16 form is the whole-level MFMA pursuit
+  const char* name = aqmp::corr_kernel_name(n, precision, corr_variant);
+  if (n == 8 && precision == AQMP_PREC_BF16 && name[0] != '\0') return "k_pursuit_bf16<8>";
+  return name;
 }
 
 }  // extern "C"

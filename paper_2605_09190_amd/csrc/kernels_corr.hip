@@ -1049,7 +1049,7 @@ const char* corr_kernel_name(int n, int precision, int variant) {
   if (!corr_variant_valid(variant)) return "";
   if (precision != AQMP_PREC_FP32 && precision != AQMP_PREC_BF16) return "";
   static const char* const fused[] = {"", "", "k_mp_fused<4>", "k_mp_fused<8>"};
-  if (n == 8 && precision == AQMP_PREC_BF16) return "k_pursuit_bf16<8>";
+  if (n == 8 && precision == AQMP_PREC_BF16) return "k_pursuit8_bf16<16>";
   if (n <= kFusedMaxN) return fused[ilog2(n)];
   static const char* const f32[] = {"k_corr_f32<16>", "k_corr_f32<32>", "k_corr_f32<64>"};
   const int li = ilog2(n) - 4;
