@@ -457,103 +457,64 @@ __global__ __launch_bounds__(PGeo<N>::NT) void k_pursuit_bf16(
         for (int j = 0; j < 8; ++j) v[j] = p16_x32<kDppX2>(top[j]);
         p16_merge8(top, v);
       }
-      // The lane's top three slot-lane bits (m) name the candidate it ends
-      // up summing; it takes the list in the order j ^ m, so that the
-      // halving exchanges below keep and send fixed positions.
-      const int m = (li / (LPS / 8)) & 7;
       int cand[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const unsigned at = (unsigned)(G::M - 1) - (top[j] & (unsigned)(G::M - 1));
         cand[j] = (top[j] != 0u && at < (unsigned)n_atoms) ? (int)at : -1;
       }
-#pragma unroll
-      for (int b = 4; b >= 1; b >>= 1)
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-          if (j < (j ^ b)) {
-            const int a0 = cand[j], a1 = cand[j ^ b];
-            cand[j] = (m & b) ? a1 : a0;
-            cand[j ^ b] = (m & b) ? a0 : a1;
-          }
-      // ---- S: FP64 re-score on the lane's patch, then the slot sums ----
-      // The two constant atoms (p = q = 0) are exactly 1/N: their partial
-      // sum is the patch sum over N.
-      double dcpart = 0.0;
+      // ---- S + A: FP64 re-score on the lane's patch and the slot sums,
+      // candidate by candidate in key order, with the arg-max (lowest atom on
+      // ties).  The BF16 correlation behind a key is within
+      // (2^-8 + K 2^-24) ||r|| of the FP64 value (BF16 atoms and residual,
+      // each within 2^-9 relative, products exact in FP32, FP32 sums);
+      // delta = 2^-7 ||r|| covers that twice.  A candidate whose key bound
+      // plus delta is below the best re-scored |c| can neither be the
+      // arg-max nor tie it, and no later candidate (smaller keys) can either,
+      // so the choice is the one the re-score of all eight makes.
+      const double delta = 0.0078125 * sqrt(s.e);
+      double dcpart = 0.0;   // the constant atoms are exactly 1/N
 #pragma unroll
       for (int i = 0; i < G::PR; ++i) dcpart += (rd[i][0] + rd[i][1]) + (rd[i][2] + rd[i][3]);
       dcpart *= inv_n;
-      double part[8];
+      constexpr uint32_t kFMask = 0x7FFFFFFFu & ~((1u << (G::IB - 1)) - 1u);
+      constexpr uint32_t kFUlp = 1u << (G::IB - 1);
+      double mag = -1.0, c = 0.0;
+      int at = -1;
+      bool live = true;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const int at = cand[j] < 0 ? 0 : cand[j];
-        const int f = at / K, q = (at % K) / N, p = at % N;
-        const double2 q0 = *(const double2*)&sTab[f][q][4 * xq];
-        const double2 q1 = *(const double2*)&sTab[f][q][4 * xq + 2];
-        double tp[G::PR];
-        if constexpr (G::PR == 2) {
-          const double2 p0 = *(const double2*)&sTab[f][p][2 * yq];
-          tp[0] = p0.x;
-          tp[1] = p0.y;
-        } else {
-          tp[0] = sTab[f][p][yq];
+        const int aj = cand[j];
+        const double ub = (double)__uint_as_float(((top[j] >> 1) & kFMask) + kFUlp) + delta;
+        live = live && aj >= 0 && ub >= mag;
+        if (__ballot(live) != 0ull) {   // uniform: some slot of the wave needs candidate j
+          const int a0 = aj < 0 ? 0 : aj;
+          const int f = a0 / K, q = (a0 % K) / N, p = a0 % N;
+          const double2 q0 = *(const double2*)&sTab[f][q][4 * xq];
+          const double2 q1 = *(const double2*)&sTab[f][q][4 * xq + 2];
+          double tp[G::PR];
+          if constexpr (G::PR == 2) {
+            const double2 p0 = *(const double2*)&sTab[f][p][2 * yq];
+            tp[0] = p0.x;
+            tp[1] = p0.y;
+          } else {
+            tp[0] = sTab[f][p][yq];
+          }
+          double pt = 0.0;
+#pragma unroll
+          for (int i = 0; i < G::PR; ++i) {
+            const double sy = fma(rd[i][0], q0.x, rd[i][1] * q0.y) + fma(rd[i][2], q1.x, rd[i][3] * q1.y);
+            pt = i == 0 ? tp[0] * sy : fma(tp[i], sy, pt);
+          }
+          const double cj = p_slot_sum<LPS>((a0 % K) == 0 ? dcpart : pt);
+          const double mj = fabs(cj);
+          if (live && (mj > mag || (mj == mag && aj < at))) {
+            mag = mj;
+            c = cj;
+            at = aj;
+          }
         }
-        double pt = 0.0;
-#pragma unroll
-        for (int i = 0; i < G::PR; ++i) {
-          const double sy = fma(rd[i][0], q0.x, rd[i][1] * q0.y) + fma(rd[i][2], q1.x, rd[i][3] * q1.y);
-          pt = i == 0 ? tp[0] * sy : fma(tp[i], sy, pt);
-        }
-        part[j] = (at % K) == 0 ? dcpart : pt;   // an empty candidate's value is never chosen
       }
-      // halves of the list go to the partners that differ in the lane's top
-      // three slot bits, then plain sums over the rest
-      double h4[4], h2[2], c;
-      if constexpr (LPS == 32) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) h4[j] = part[j] + p16_xf64<kSwzX16>(part[j + 4]);
-#pragma unroll
-        for (int j = 0; j < 2; ++j) h2[j] = h4[j] + p16_xf64<kDppX8>(h4[j + 2]);
-        c = h2[0] + p16_xf64<kDppX7>(h2[1]);
-        c += p16_xf64<kDppX2>(c);
-        c += p16_xf64<kDppX1>(c);
-      } else if constexpr (LPS == 16) {
-        // m = lane bits 3, 2, 1: the half-row mirror flips m bits 1 and 0
-        // together, so the partner's list is taken in reverse order there
-#pragma unroll
-        for (int j = 0; j < 4; ++j) h4[j] = part[j] + p16_xf64<kDppX8>(part[j + 4]);
-#pragma unroll
-        for (int j = 0; j < 2; ++j) h2[j] = h4[j] + p16_xf64<kDppX7>(h4[3 - j]);
-        c = h2[0] + p16_xf64<kDppX2>(h2[1]);
-        c += p16_xf64<kDppX1>(c);
-      } else {
-        // m = lane bits 2, 1, 0: the half-row mirror flips all three
-#pragma unroll
-        for (int j = 0; j < 4; ++j) h4[j] = part[j] + p16_xf64<kDppX7>(part[7 - j]);
-#pragma unroll
-        for (int j = 0; j < 2; ++j) h2[j] = h4[j] + p16_xf64<kDppX2>(h4[j + 2]);
-        c = h2[0] + p16_xf64<kDppX1>(h2[1]);
-      }
-      int at = cand[0];
-      // ---- A: arg-max over the slot (lowest atom on ties) ----
-      double mag = at >= 0 ? fabs(c) : -1.0;
-#define AQMP_P_ARGMAX(CTRL)                                                              \
-  {                                                                                      \
-    const double om = p16_xf64<CTRL>(mag), oc = p16_xf64<CTRL>(c);                       \
-    const int oa = (int)p16_x32<CTRL>((uint32_t)at);                                     \
-    const bool take = om > mag || (om == mag && oa < at);                                \
-    mag = take ? om : mag;                                                               \
-    c = take ? oc : c;                                                                   \
-    at = take ? oa : at;                                                                 \
-  }
-      if constexpr (LPS == 32) {
-        AQMP_P_ARGMAX(kSwzX16) AQMP_P_ARGMAX(kDppX8) AQMP_P_ARGMAX(kDppX7)
-      } else if constexpr (LPS == 16) {
-        AQMP_P_ARGMAX(kDppX8) AQMP_P_ARGMAX(kDppX7) AQMP_P_ARGMAX(kDppX2)
-      } else {
-        AQMP_P_ARGMAX(kDppX7) AQMP_P_ARGMAX(kDppX2) AQMP_P_ARGMAX(kDppX1)
-      }
-#undef AQMP_P_ARGMAX
       const bool zero = at < 0 || mag == 0.0;
       if (zero) {
         s.run = false;
