@@ -148,16 +148,17 @@ __global__ __launch_bounds__(256) void k_mp_fused(const JobDev* __restrict__ job
 //   M  the slot's wave lists are merged into its 8 candidates;
 //   S  FP64 re-score of the candidates against the FP32 residual,
 //      separably (Section 2.1 outer product): lane = a patch of 4-pixel row
-//      pieces of one slot, and the eight candidate sums are reduced over the
-//      slot's lanes by exchanging halves of the list;
+//      pieces of one slot, two candidates at a time in key order, each sum
+//      reduced over the slot's lanes, stopping once the candidates' bounds
+//      fall below the best re-scored value;
 //   A  arg-max (lowest atom on ties), rank-1 update of the lane's patch in
 //      FP64 rounded to FP32, ||r||^2 in FP64, record (i, c_i), stop test.
 // A slot whose node stops takes the next node of the level (the first
 // gridDim.x * 16 nodes are dealt out in order, the rest come from a
 // counter, up to two fetches per step), so stopped nodes cost no MFMA
-// columns while work remains and one wave of workgroups covers the level.  Every reduction is a
-// butterfly over XOR partners, so the lanes of a slot hold bit-identical
-// sums and take the same decisions.
+// columns while work remains and one wave of workgroups covers the level.
+// Every reduction is a butterfly over XOR partners, so the lanes of a slot
+// hold bit-identical sums and take the same decisions.
 // ---------------------------------------------------------------------------
 constexpr int kPSlots = 16;   // node slots per workgroup (the B operand's columns)
 
@@ -238,6 +239,36 @@ __device__ inline double p_slot_sum(double v) {
   return v;
 }
 
+// Two slot sums at once (the same operations on each as p_slot_sum).
+template <int LPS>
+__device__ inline void p_slot_sum2(double& a, double& b) {
+  if constexpr (LPS == 32) {
+    const double ta = p16_xf64<kSwzX16>(a), tb = p16_xf64<kSwzX16>(b);
+    a += ta;
+    b += tb;
+  }
+  if constexpr (LPS >= 16) {
+    const double ta = p16_xf64<kDppX8>(a), tb = p16_xf64<kDppX8>(b);
+    a += ta;
+    b += tb;
+  }
+  {
+    const double ta = p16_xf64<kDppX7>(a), tb = p16_xf64<kDppX7>(b);
+    a += ta;
+    b += tb;
+  }
+  {
+    const double ta = p16_xf64<kDppX2>(a), tb = p16_xf64<kDppX2>(b);
+    a += ta;
+    b += tb;
+  }
+  {
+    const double ta = p16_xf64<kDppX1>(a), tb = p16_xf64<kDppX1>(b);
+    a += ta;
+    b += tb;
+  }
+}
+
 // Per-slot state, uniform over the slot's lanes.
 struct PSlot {
   int node;       // node of the level, -1 when none is left for this slot
@@ -302,16 +333,21 @@ __device__ __attribute__((always_inline)) inline void p_load_node(const JobDev* 
 // Straight-line code, no loop: a cross-lane exchange inside a loop whose exit
 // depends on an atomic result let the compiler's structurised control flow
 // run lanes of one slot out of step.  A slot whose new node stops at once
-// tries again at the next fetch.
+// tries again at the next fetch.  The counter only grows, so once one slot
+// of the workgroup has found it past the level's end (flag *wg_dry in LDS),
+// the others stop asking it.
 template <class G>
 __device__ __attribute__((always_inline)) inline void p_fetch(
     const JobDev* __restrict__ jobs, const LevelDev& lv, int lg, int count, int32_t* next, int queue0, int yq,
-    int xq, int li, char* sBrow, double (&rd)[G::PR][4], PSlot& s, bool& dry) {
+    int xq, int li, char* sBrow, double (&rd)[G::PR][4], PSlot& s, bool& dry, int* wg_dry) {
   const int lane = threadIdx.x & 63, lead = lane & ~(G::LPS - 1);
   // the leader's decision, taken by the whole slot
   const bool need = __shfl((int)(!s.run && !dry), lead, 64) != 0;
-  int idx = 0;
-  if (need && li == 0) idx = queue0 + atomicAdd(next, 1);
+  int idx = count;
+  if (need && li == 0 && __hip_atomic_load(wg_dry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) {
+    idx = queue0 + atomicAdd(next, 1);
+    if (idx >= count) __hip_atomic_store(wg_dry, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
   idx = __shfl(idx, lead, 64);
   if (need) {
     if (idx < count) {
@@ -321,6 +357,21 @@ __device__ __attribute__((always_inline)) inline void p_fetch(
       s.node = -1;
     }
   }
+}
+
+// Whether v holds for some lane of the workgroup: one flag word per wave in
+// LDS, one barrier.  Successive calls alternate between the two flag rows
+// (par), so a row is written again only after a later barrier that every
+// wave reaches after reading it.
+template <int W>
+__device__ __attribute__((always_inline)) inline bool p_wg_any(bool v, uint32_t (&flags)[2][W], int par) {
+  const bool wv = __ballot(v) != 0ull;
+  if ((threadIdx.x & 63) == 0) flags[par][threadIdx.x >> 6] = wv ? 1u : 0u;
+  __syncthreads();
+  uint32_t r = 0u;
+#pragma unroll
+  for (int i = 0; i < W; ++i) r |= flags[par][i];
+  return r != 0u;
 }
 
 template <int N>
@@ -334,7 +385,10 @@ __global__ __launch_bounds__(PGeo<N>::NT) void k_pursuit_bf16(
   __shared__ __attribute__((aligned(16))) uint32_t sKey[G::W][NS][8];
   __shared__ __attribute__((aligned(16))) double sTab[2][N][N];         // FP64 T_f[k][n]
   __shared__ float sT32[2][N][N];                                       // FP32 [f][n][k]
+  __shared__ __attribute__((aligned(16))) uint32_t sAny[2][G::W];       // p_wg_any flags
+  __shared__ int sDry;                                                  // the counter is past the end
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid == 0) sDry = 0;
   for (int i = tid; i < nfam * K; i += NT) {
     (&sTab[0][0][0])[i] = tab[i];
     (&sT32[0][0][0])[i] = tabT32[i];
@@ -388,8 +442,9 @@ __global__ __launch_bounds__(PGeo<N>::NT) void k_pursuit_bf16(
     else
       dry = true;
   }
-  p_fetch<G>(jobs, lv, lg, count, next, queue0, yq, xq, li, sBrow, rd, s, dry);
-  bool any = __syncthreads_or(s.run || !dry);
+  p_fetch<G>(jobs, lv, lg, count, next, queue0, yq, xq, li, sBrow, rd, s, dry, &sDry);
+  int par = 0;
+  bool any = p_wg_any<G::W>(s.run || !dry, sAny, par);
 
   while (any) {
     // ---- C: correlation of the wave's atoms with the 16 slots ----
@@ -464,8 +519,7 @@ __global__ __launch_bounds__(PGeo<N>::NT) void k_pursuit_bf16(
         cand[j] = (top[j] != 0u && at < (unsigned)n_atoms) ? (int)at : -1;
       }
       // ---- S + A: FP64 re-score on the lane's patch and the slot sums,
-      // candidate by candidate in key order, with the arg-max (lowest atom on
-      // ties).  The BF16 correlation behind a key is within
+      // in key order, with the arg-max (lowest atom on ties).  The BF16 correlation behind a key is within
       // (2^-8 + K 2^-24) ||r|| of the FP64 value (BF16 atoms and residual,
       // each within 2^-9 relative, products exact in FP32, FP32 sums);
       // delta = 2^-7 ||r|| covers that twice.  A candidate whose key bound
@@ -482,36 +536,50 @@ __global__ __launch_bounds__(PGeo<N>::NT) void k_pursuit_bf16(
       double mag = -1.0, c = 0.0;
       int at = -1;
       bool live = true;
+      // The lane's part of candidate a's FP64 correlation.
+      auto part = [&](int a) -> double {
+        if ((a % K) == 0) return dcpart;
+        const int f = a / K, q = (a % K) / N, p = a % N;
+        const double2 q0 = *(const double2*)&sTab[f][q][4 * xq];
+        const double2 q1 = *(const double2*)&sTab[f][q][4 * xq + 2];
+        double tp[G::PR];
+        if constexpr (G::PR == 2) {
+          const double2 p0 = *(const double2*)&sTab[f][p][2 * yq];
+          tp[0] = p0.x;
+          tp[1] = p0.y;
+        } else {
+          tp[0] = sTab[f][p][yq];
+        }
+        double pt = 0.0;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int aj = cand[j];
+        for (int i = 0; i < G::PR; ++i) {
+          const double sy = fma(rd[i][0], q0.x, rd[i][1] * q0.y) + fma(rd[i][2], q1.x, rd[i][3] * q1.y);
+          pt = i == 0 ? tp[0] * sy : fma(tp[i], sy, pt);
+        }
+        return pt;
+      };
+      // Candidates two at a time (two slot sums in flight together); the
+      // bound test is made on the first of each pair.  Re-scoring the second
+      // even when its bound has fallen below mag changes nothing: its |c| is
+      // then below mag, so it is not taken, and every later bound is smaller.
+#pragma unroll
+      for (int j = 0; j < 8; j += 2) {
+        const int a0 = cand[j], a1 = cand[j + 1];
         const double ub = (double)__uint_as_float(((top[j] >> 1) & kFMask) + kFUlp) + delta;
-        live = live && aj >= 0 && ub >= mag;
-        if (__ballot(live) != 0ull) {   // uniform: some slot of the wave needs candidate j
-          const int a0 = aj < 0 ? 0 : aj;
-          const int f = a0 / K, q = (a0 % K) / N, p = a0 % N;
-          const double2 q0 = *(const double2*)&sTab[f][q][4 * xq];
-          const double2 q1 = *(const double2*)&sTab[f][q][4 * xq + 2];
-          double tp[G::PR];
-          if constexpr (G::PR == 2) {
-            const double2 p0 = *(const double2*)&sTab[f][p][2 * yq];
-            tp[0] = p0.x;
-            tp[1] = p0.y;
-          } else {
-            tp[0] = sTab[f][p][yq];
+        live = live && a0 >= 0 && ub >= mag;
+        if (__ballot(live) != 0ull) {   // uniform: some slot of the wave needs this pair
+          double c0 = part(a0 < 0 ? 0 : a0), c1 = part(a1 < 0 ? 0 : a1);
+          p_slot_sum2<LPS>(c0, c1);
+          const double m0 = fabs(c0), m1 = fabs(c1);
+          if (live && (m0 > mag || (m0 == mag && a0 < at))) {
+            mag = m0;
+            c = c0;
+            at = a0;
           }
-          double pt = 0.0;
-#pragma unroll
-          for (int i = 0; i < G::PR; ++i) {
-            const double sy = fma(rd[i][0], q0.x, rd[i][1] * q0.y) + fma(rd[i][2], q1.x, rd[i][3] * q1.y);
-            pt = i == 0 ? tp[0] * sy : fma(tp[i], sy, pt);
-          }
-          const double cj = p_slot_sum<LPS>((a0 % K) == 0 ? dcpart : pt);
-          const double mj = fabs(cj);
-          if (live && (mj > mag || (mj == mag && aj < at))) {
-            mag = mj;
-            c = cj;
-            at = aj;
+          if (live && a1 >= 0 && (m1 > mag || (m1 == mag && a1 < at))) {
+            mag = m1;
+            c = c1;
+            at = a1;
           }
         }
       }
@@ -578,9 +646,10 @@ __global__ __launch_bounds__(PGeo<N>::NT) void k_pursuit_bf16(
         }
       }
     }
-    p_fetch<G>(jobs, lv, lg, count, next, queue0, yq, xq, li, sBrow, rd, s, dry);
-    p_fetch<G>(jobs, lv, lg, count, next, queue0, yq, xq, li, sBrow, rd, s, dry);
-    any = __syncthreads_or(s.run || !dry);
+    p_fetch<G>(jobs, lv, lg, count, next, queue0, yq, xq, li, sBrow, rd, s, dry, &sDry);
+    p_fetch<G>(jobs, lv, lg, count, next, queue0, yq, xq, li, sBrow, rd, s, dry, &sDry);
+    par ^= 1;
+    any = p_wg_any<G::W>(s.run || !dry, sAny, par);
   }
 }
 }  // namespace
