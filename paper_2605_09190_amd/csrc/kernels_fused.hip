@@ -451,12 +451,16 @@ __global__ __launch_bounds__(PGeo<N>::NT) void k_pursuit_bf16(
     p16_f32x4 acc[MA];
 #pragma unroll
     for (int ma = 0; ma < MA; ++ma) acc[ma] = p16_f32x4{0.f, 0.f, 0.f, 0.f};
+    // Tiles in pairs, pair by pair, so the keys of one pair (E) can be
+    // ranked while the next pair's MFMAs run.
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const p16_bf16x8 bf = *(const p16_bf16x8*)(sB + c16 * G::ROWB + 64 * ks + 16 * quad);
+    for (int g = 0; g < MA / 2; ++g)
 #pragma unroll
-      for (int ma = 0; ma < MA; ++ma) acc[ma] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[ma][ks], bf, acc[ma], 0, 0, 0);
-    }
+      for (int ks = 0; ks < KS; ++ks) {
+        const p16_bf16x8 bf = *(const p16_bf16x8*)(sB + c16 * G::ROWB + 64 * ks + 16 * quad);
+        acc[2 * g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[2 * g][ks], bf, acc[2 * g], 0, 0, 0);
+        acc[2 * g + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[2 * g + 1][ks], bf, acc[2 * g + 1], 0, 0, 0);
+      }
     // ---- E: the wave's best 8 keys of slot c16 ----
     {
       constexpr uint32_t kMask = ~((1u << G::IB) - 1u);
