@@ -208,18 +208,40 @@ __device__ inline void p16_merge8(uint32_t (&a)[8], const uint32_t (&b)[8]) {
   p16_cx(a[0], a[1]); p16_cx(a[2], a[3]); p16_cx(a[4], a[5]); p16_cx(a[6], a[7]);
 }
 
-// Lane exchanges between XOR partners inside the lanes of a slot:
-// ds_swizzle (lane ^ 16), and the DPP row operations row_ror:8 (lane ^ 8),
-// row_half_mirror (lane ^ 7 within eight), quad_perm [2,3,0,1] (lane ^ 2)
-// and [1,0,3,2] (lane ^ 1).
+// Lane exchanges between XOR partners inside the lanes of a slot: the DPP
+// row operations row_ror:8 (lane ^ 8), row_half_mirror (lane ^ 7 within
+// eight), quad_perm [2,3,0,1] (lane ^ 2) and [1,0,3,2] (lane ^ 1).
 constexpr int kDppX8 = 0x128, kDppX7 = 0x141, kDppX2 = 0x4E, kDppX1 = 0xB1;
-constexpr int kSwzX16 = 0x1F | (0x10 << 10);   // bitmask mode: and 31, xor 16
 template <int CTRL>
 __device__ inline uint32_t p16_x32(uint32_t v) {
-  if constexpr (CTRL == kSwzX16)
-    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, kSwzX16);
-  else
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+// Lanes l and l ^ X (X = 16: v_permlane16_swap, rows of 16 lanes; X = 32:
+// v_permlane32_swap, halves of the wave), both VALU, no LDS round trip.  A
+// register swapped against a copy of itself leaves the value of the lower
+// lane of each pair in p and that of the upper lane in q, in both lanes of
+// the pair.
+template <int X>
+__device__ inline void p_pair(uint32_t v, uint32_t& p, uint32_t& q) {
+  if constexpr (X == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    p = r[0];
+    q = r[1];
+  } else {
+    static_assert(X == 32, "pairs at distance 16 or 32");
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    p = r[0];
+    q = r[1];
+  }
+}
+// v(l) + v(l ^ 16), the same bits in both lanes
+__device__ inline double p_pair_sum16(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  uint32_t p0, q0, p1, q1;
+  p_pair<16>((uint32_t)u, p0, q0);
+  p_pair<16>((uint32_t)(u >> 32), p1, q1);
+  return __longlong_as_double((long long)(((unsigned long long)p1 << 32) | p0)) +
+         __longlong_as_double((long long)(((unsigned long long)q1 << 32) | q0));
 }
 template <int CTRL>
 __device__ inline double p16_xf64(double v) {
@@ -231,7 +253,7 @@ __device__ inline double p16_xf64(double v) {
 // gets the same bits.
 template <int LPS>
 __device__ inline double p_slot_sum(double v) {
-  if constexpr (LPS == 32) v += p16_xf64<kSwzX16>(v);
+  if constexpr (LPS == 32) v = p_pair_sum16(v);
   if constexpr (LPS >= 16) v += p16_xf64<kDppX8>(v);
   v += p16_xf64<kDppX7>(v);
   v += p16_xf64<kDppX2>(v);
@@ -243,9 +265,8 @@ __device__ inline double p_slot_sum(double v) {
 template <int LPS>
 __device__ inline void p_slot_sum2(double& a, double& b) {
   if constexpr (LPS == 32) {
-    const double ta = p16_xf64<kSwzX16>(a), tb = p16_xf64<kSwzX16>(b);
-    a += ta;
-    b += tb;
+    a = p_pair_sum16(a);
+    b = p_pair_sum16(b);
   }
   if constexpr (LPS >= 16) {
     const double ta = p16_xf64<kDppX8>(a), tb = p16_xf64<kDppX8>(b);
@@ -267,6 +288,22 @@ __device__ inline void p_slot_sum2(double& a, double& b) {
     a += ta;
     b += tb;
   }
+}
+
+// BF16 copies of four FP32 values, each rounded to nearest even from the
+// FP32 value.  The empty asm hides where the FP32 values came from; without
+// it the compiler folds an FP64 -> FP32 -> BF16 pair of roundings into one
+// FP64 -> BF16 rounding (round to odd, then to BF16: eight more
+// instructions per value).
+typedef __bf16 p_bf16x4 __attribute__((ext_vector_type(4)));
+__device__ inline p_bf16x4 p_to_bf16x4(float a, float b, float c, float d) {
+  __asm__("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d));
+  p_bf16x4 r;
+  r[0] = (__bf16)a;
+  r[1] = (__bf16)b;
+  r[2] = (__bf16)c;
+  r[3] = (__bf16)d;
+  return r;
 }
 
 // Per-slot state, uniform over the slot's lanes.
@@ -295,20 +332,18 @@ __device__ __attribute__((always_inline)) inline void p_load_node(const JobDev* 
 #pragma unroll
   for (int i = 0; i < G::PR; ++i) job_pixels<4>(jl, by + G::PR * yq + i, bx + 4 * xq, pv[i]);
   double ep = 0.0;
-  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 #pragma unroll
   for (int i = 0; i < G::PR; ++i) {
     double ei = 0.0;
-    bf16x4 b;
+    float f[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const float f = (float)pv[i][j];
-      rd[i][j] = (double)f;
+      f[j] = (float)pv[i][j];
+      rd[i][j] = (double)f[j];
       ei = fma(pv[i][j], pv[i][j], ei);
-      b[j] = (__bf16)f;
     }
     ep += ei;
-    *(bf16x4*)(sBrow + ((G::PR * yq + i) * G::N + 4 * xq) * 2) = b;
+    *(p_bf16x4*)(sBrow + ((G::PR * yq + i) * G::N + 4 * xq) * 2) = p_to_bf16x4(f[0], f[1], f[2], f[3]);
   }
   s.node = node;
   s.e = p_slot_sum<G::LPS>(ep);
@@ -340,6 +375,8 @@ template <class G>
 __device__ __attribute__((always_inline)) inline void p_fetch(
     const JobDev* __restrict__ jobs, const LevelDev& lv, int lg, int count, int32_t* next, int queue0, int yq,
     int xq, int li, char* sBrow, double (&rd)[G::PR][4], PSlot& s, bool& dry, int* wg_dry) {
+  // most steps no slot of the wave is looking for a node (uniform branch)
+  if (__ballot(!s.run && !dry) == 0ull) return;
   const int lane = threadIdx.x & 63, lead = lane & ~(G::LPS - 1);
   // the leader's decision, taken by the whole slot
   const bool need = __shfl((int)(!s.run && !dry), lead, 64) != 0;
@@ -481,11 +518,13 @@ __global__ __launch_bounds__(PGeo<N>::NT) void k_pursuit_bf16(
           p16_merge8(top, v);
         }
       }
+      // the lists of lanes l ^ 16 and l ^ 32 (the same slot column)
+      uint32_t u[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = p16_x32<kSwzX16>(top[j]);
-      p16_merge8(top, v);
+      for (int j = 0; j < 8; ++j) p_pair<16>(top[j], u[j], v[j]);
+      p16_merge8(u, v);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = __shfl_xor(top[j], 32, 64);
+      for (int j = 0; j < 8; ++j) p_pair<32>(u[j], top[j], v[j]);
       p16_merge8(top, v);
       if (quad == 0) {
         uint4* kp = (uint4*)&sKey[w][c16][0];
@@ -611,21 +650,19 @@ __global__ __launch_bounds__(PGeo<N>::NT) void k_pursuit_bf16(
           tp[0] = sTab[f][p][yq];
         }
         double eh = 0.0;
-        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 #pragma unroll
         for (int i = 0; i < G::PR; ++i) {
-          bf16x4 b;
+          float rn[4];
           double ei = 0.0;
 #pragma unroll
           for (int x = 0; x < 4; ++x) {
             const double phi = dc ? inv_n : tp[i] * tq[x];
-            const float rn = (float)fma(-c, phi, rd[i][x]);
-            rd[i][x] = (double)rn;
+            rn[x] = (float)fma(-c, phi, rd[i][x]);
+            rd[i][x] = (double)rn[x];
             ei = fma(rd[i][x], rd[i][x], ei);
-            b[x] = (__bf16)rn;
           }
           eh += ei;
-          *(bf16x4*)(sBrow + ((G::PR * yq + i) * N + 4 * xq) * 2) = b;
+          *(p_bf16x4*)(sBrow + ((G::PR * yq + i) * N + 4 * xq) * 2) = p_to_bf16x4(rn[0], rn[1], rn[2], rn[3]);
         }
         const double en = p_slot_sum<LPS>(eh);
         if (li == 0) {
