@@ -177,6 +177,10 @@ struct PGeo {
   static constexpr int XQ = N / 4;                  // 4-pixel pieces per row
   static constexpr int IB = N == 16 ? 9 : 7;        // bits of the atom index in a key
   static constexpr int ROWB = 2 * K + 16;           // bytes per slot in the BF16 residual (padded)
+  // The update takes the chosen atom's table entries kept from its
+  // re-score (at N = 16 the registers are not there: 255 VGPRs and a slower
+  // schedule; it reads them from LDS again)
+  static constexpr bool KEEP_ROWS = N == 8;
   static_assert(MA * 16 * W == M && KS * 32 == K, "whole tiles");
   static_assert(LPS == 8 || LPS == 16 || LPS == 32, "a slot is half a DPP row, one or two rows");
   static_assert(PR * 4 * LPS == K && PR >= 1, "whole patches");
@@ -579,28 +583,41 @@ __global__ __launch_bounds__(PGeo<N>::NT) void k_pursuit_bf16(
       double mag = -1.0, c = 0.0;
       int at = -1;
       bool live = true;
-      // The lane's part of candidate a's FP64 correlation.
-      auto part = [&](int a) -> double {
-        if ((a % K) == 0) return dcpart;
+      // The FP64 table entries of atom a on the lane's patch: T_f[q][x] for
+      // its four columns, T_f[p][y] for its PR rows.
+      struct Rows {
+        double q[4], t[G::PR];
+      };
+      auto rows = [&](int a) -> Rows {
         const int f = a / K, q = (a % K) / N, p = a % N;
         const double2 q0 = *(const double2*)&sTab[f][q][4 * xq];
         const double2 q1 = *(const double2*)&sTab[f][q][4 * xq + 2];
-        double tp[G::PR];
+        Rows r;
+        r.q[0] = q0.x;
+        r.q[1] = q0.y;
+        r.q[2] = q1.x;
+        r.q[3] = q1.y;
         if constexpr (G::PR == 2) {
           const double2 p0 = *(const double2*)&sTab[f][p][2 * yq];
-          tp[0] = p0.x;
-          tp[1] = p0.y;
+          r.t[0] = p0.x;
+          r.t[1] = p0.y;
         } else {
-          tp[0] = sTab[f][p][yq];
+          r.t[0] = sTab[f][p][yq];
         }
+        return r;
+      };
+      // The lane's part of candidate a's FP64 correlation.
+      auto part = [&](int a, const Rows& r) -> double {
+        if ((a % K) == 0) return dcpart;
         double pt = 0.0;
 #pragma unroll
         for (int i = 0; i < G::PR; ++i) {
-          const double sy = fma(rd[i][0], q0.x, rd[i][1] * q0.y) + fma(rd[i][2], q1.x, rd[i][3] * q1.y);
-          pt = i == 0 ? tp[0] * sy : fma(tp[i], sy, pt);
+          const double sy = fma(rd[i][0], r.q[0], rd[i][1] * r.q[1]) + fma(rd[i][2], r.q[2], rd[i][3] * r.q[3]);
+          pt = i == 0 ? r.t[0] * sy : fma(r.t[i], sy, pt);
         }
         return pt;
       };
+      Rows br{};   // the rows of the best candidate so far (KEEP_ROWS)
       // Candidates two at a time (two slot sums in flight together); the
       // bound test is made on the first of each pair.  Re-scoring the second
       // even when its bound has fallen below mag changes nothing: its |c| is
@@ -611,18 +628,22 @@ __global__ __launch_bounds__(PGeo<N>::NT) void k_pursuit_bf16(
         const double ub = (double)__uint_as_float(((top[j] >> 1) & kFMask) + kFUlp) + delta;
         live = live && a0 >= 0 && ub >= mag;
         if (__ballot(live) != 0ull) {   // uniform: some slot of the wave needs this pair
-          double c0 = part(a0 < 0 ? 0 : a0), c1 = part(a1 < 0 ? 0 : a1);
+          const int b0 = a0 < 0 ? 0 : a0, b1 = a1 < 0 ? 0 : a1;
+          const Rows r0 = rows(b0), r1 = rows(b1);
+          double c0 = part(b0, r0), c1 = part(b1, r1);
           p_slot_sum2<LPS>(c0, c1);
           const double m0 = fabs(c0), m1 = fabs(c1);
           if (live && (m0 > mag || (m0 == mag && a0 < at))) {
             mag = m0;
             c = c0;
             at = a0;
+            if constexpr (G::KEEP_ROWS) br = r0;
           }
           if (live && a1 >= 0 && (m1 > mag || (m1 == mag && a1 < at))) {
             mag = m1;
             c = c1;
             at = a1;
+            if constexpr (G::KEEP_ROWS) br = r1;
           }
         }
       }
@@ -636,19 +657,10 @@ __global__ __launch_bounds__(PGeo<N>::NT) void k_pursuit_bf16(
         }
       } else {
         // rank-1 update of the patch, ||r||^2, record, stop test
-        const int f = at / K, q = (at % K) / N, p = at % N;
         const bool dc = (at % K) == 0;
-        const double2 q0 = *(const double2*)&sTab[f][q][4 * xq];
-        const double2 q1 = *(const double2*)&sTab[f][q][4 * xq + 2];
-        const double tq[4] = {q0.x, q0.y, q1.x, q1.y};
-        double tp[G::PR];
-        if constexpr (G::PR == 2) {
-          const double2 p0 = *(const double2*)&sTab[f][p][2 * yq];
-          tp[0] = p0.x;
-          tp[1] = p0.y;
-        } else {
-          tp[0] = sTab[f][p][yq];
-        }
+        if constexpr (!G::KEEP_ROWS) br = rows(at);
+        const double* tq = br.q;
+        const double* tp = br.t;
         double eh = 0.0;
 #pragma unroll
         for (int i = 0; i < G::PR; ++i) {
