@@ -566,14 +566,18 @@ __global__ __launch_bounds__(PGeo<N>::NT) void k_pursuit_bf16(
         cand[j] = (top[j] != 0u && at < (unsigned)n_atoms) ? (int)at : -1;
       }
       // ---- S + A: FP64 re-score on the lane's patch and the slot sums,
-      // in key order, with the arg-max (lowest atom on ties).  The BF16 correlation behind a key is within
-      // (2^-8 + K 2^-24) ||r|| of the FP64 value (BF16 atoms and residual,
-      // each within 2^-9 relative, products exact in FP32, FP32 sums);
-      // delta = 2^-7 ||r|| covers that twice.  A candidate whose key bound
+      // in key order, with the arg-max (lowest atom on ties).  The BF16
+      // correlation behind a key is within (2^-8 + K 2^-24) ||r|| of the
+      // FP64 value (BF16 atoms and residual, each within 2^-9 relative,
+      // products exact in FP32, FP32 sums); delta = 2^-7 ||r|| is nearly
+      // twice that bound.  A candidate whose key bound
       // plus delta is below the best re-scored |c| can neither be the
       // arg-max nor tie it, and no later candidate (smaller keys) can either,
-      // so the choice is the one the re-score of all eight makes.
-      const double delta = 0.0078125 * sqrt(s.e);
+      // so the choice is the one the re-score of all eight makes.  ||r|| is
+      // taken in FP32 (one instruction instead of the FP64 square root's
+      // refinement), clamped from below and raised by 2^-16, so that delta
+      // is never below 2^-7 ||r||.
+      const double delta = 0.0078125 * (double)(__builtin_sqrtf(fmaxf((float)s.e, 1e-30f)) * 1.0000153f);
       double dcpart = 0.0;   // the constant atoms are exactly 1/N
 #pragma unroll
       for (int i = 0; i < G::PR; ++i) dcpart += (rd[i][0] + rd[i][1]) + (rd[i][2] + rd[i][3]);
