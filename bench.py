@@ -515,8 +515,19 @@ def main():
     from paper_2605_09190_amd import aqmp as A
     from workloads import workload
 
+    # wall-clock seconds of each phase of this run (host and device), so that
+    # the GPU's share of the run can be read off the JSON line
+    phases = {}
+    t_phase = [time.perf_counter()]
+
+    def mark(name):
+        now = time.perf_counter()
+        phases[name] = round(phases.get(name, 0.0) + now - t_phase[0], 3)
+        t_phase[0] = now
+
     log("generating workload", args.workload)
     w = workload(args.workload)
+    mark("workload_generation")
     cpu = None
     cpu_omp = None
     cpu_samples = None
@@ -528,6 +539,7 @@ def main():
             log("cpu baseline (oracle OMP)")
             w_omp = dict(w, params=[dict(p, solver="omp") for p in w["params"]])
             cpu_omp, _ = cpu_baseline(w_omp, budget_s=12.0)
+        mark("cpu_baseline_oracle")
     imgs = to_device(w["channels"])
     npx = sum(int(w["channels"][ci].size) for ci, _ in w["jobs"])
     nmin = min(p["n_min"] for p in w["params"])
@@ -551,6 +563,7 @@ def main():
                                      tuned["options"]["schedule"])
         tiles_v = tuned["options"]["corr_tile_levels"]
         log(f"autotune: {tuned['options']} in {tuned['seconds']} s")
+    mark("device_setup_and_autotune")
     if args.schedule is not None:
         sched = A.SCHED_BATCHED if args.schedule == "batched" else A.SCHED_CONCURRENT
     head_kw = dict(corr_variant=args.corr_variant, corr_variant_levels=levels_v, stepwise=stepwise,
@@ -580,6 +593,7 @@ def main():
             f"{prec_rep['stop_ties']} dPSNR {prec_rep['max_abs_delta_psnr_db']}")
     code.free()   # every form below allocates its own buffers
     log(f"bf16 batched (graph): {sec * 1e3:.3f} ms/step")
+    mark("headline_graph_timing_quality_precision")
 
     # Kernel durations: the same batched launch sequence with HIP events
     # around every MP-step launch (events cannot be timed inside a graph, so
@@ -603,6 +617,7 @@ def main():
                       "between the two spin_kernel markers")
     code_t.free()
     log(f"bf16 batched (stream, timed): {sec_t * 1e3:.3f} ms/step, corr {roof['achieved']} TFLOP/s")
+    mark("headline_event_timed_encodes")
 
     fp32 = None
     if not args.no_fp32:
@@ -620,6 +635,7 @@ def main():
                     leaves=int(sum(st3["leaves"])))
         code3.free()
         log(f"fp32 plain: {sec3 * 1e3:.3f} ms/step")
+        mark("fp32_plain_form")
 
     gram = None
     if not args.no_gram:
@@ -642,6 +658,7 @@ def main():
                     form="labelled variant: exact Gram-update MP in FP64 (not the dense per-step correlation)")
         codeg.free()
         log(f"gram fp64 batched (graph): {secg * 1e3:.3f} ms/step")
+        mark("gram_variant")
 
     omp = None
     if not args.no_omp:
@@ -665,6 +682,7 @@ def main():
                         "the authors' solver; not the MP headline")
         codeo.free()
         log(f"omp fp64 batched (graph): {seco * 1e3:.3f} ms/step")
+        mark("omp_variant")
 
     rd_c1 = None
     if args.workload == "c3":
@@ -673,15 +691,18 @@ def main():
         code1 = A.Code(dic, imgs1, w1["params"], w1["jobs"], precision=A.PREC_BF16, schedule=A.SCHED_BATCHED)
         rd_c1 = dict(workload=w1["name"], points=rate_distortion(A, code1, imgs1, w1))
         code1.free()
+        mark("rate_distortion_512")
     sweep_res = None
     if not args.no_sweep and args.workload == "c3":
         # the paper's search space encoded together: 16 images x 32 trials
         sweep_res = form_compare(A, workload("c4"), steps=3, warmup=1, fp32_steps=1, label="sweep")
         sweep_res["unit_note"] = "Mpixel/s here counts pixel x trial (every trial encodes its image once)"
+        mark("sweep_forms")
     leaves40k = None
     if not args.no_40k and args.workload == "c3":
         leaves40k = form_compare(A, workload("c3", tau=TAU_40K), steps=max(3, args.steps // 2), warmup=1,
                                  fp32_steps=1, label="40k leaves")
+        mark("leaves_40k_forms")
 
     hpo_res = None
     if args.hpo_rounds > 0:
@@ -700,6 +721,7 @@ def main():
                        trials_per_s=round(len(r["history"]) / dt, 2), hypervolume=round(r["hypervolume"], 4),
                        pareto_ssim_cr=front,
                        form="TPE, every trial of a round one job of one BF16 batched graph; SSIM 7x7 and DEFLATE CR")
+        mark("hpo")
 
     value = npx / sec / 1e6
     res = {
@@ -744,6 +766,8 @@ def main():
                      if tuned else None),
         "roofline": roof,
         "precision_report": prec_rep,
+        "phase_seconds": dict(phases, timed_region=round(sec * args.steps, 4),
+                              note="wall clock of each phase of this run; timed_region = steps x ms_per_step"),
     }
     if fp32:
         res["speedup_vs_fp32_plain"] = round(value / fp32["value"], 2)
