@@ -33,13 +33,13 @@ TAU_40K = 0.0075              # RMS tolerance at which the 2048x2048x3 workload 
 # profiles/traffic_k_select_2048x2048x3_ycbcr.md); valid only for the kernel
 # source and the workload they were taken on.
 _MP_SRC = dict(workload="c3", src="paper_2605_09190_amd/csrc/kernels_mp.hip",
-               sha256="2042358c9aea21d25b66b17e1617d93bc3282b2f8e1d54c74d1709067c9e1f16")
+               sha256="0b8b3de286018215fd4e9a6bad4f59838a9a23ab82152b8aa91b7ae6ba2db741")
 TRAFFIC = {
     "k_corr_bf16_gen<64>": dict(bytes_per_launch=15.72e6, fetch=13.32e6, write=2.41e6, workload="c3",
                                 src="paper_2605_09190_amd/csrc/kernels_corr.hip",
                                 sha256="838ba24a85d0bd586b2844b584e35206c74b9daba940cd60689c2a5d2c39024e"),
-    "k_select<64>": dict(bytes_per_launch=51.96e6, fetch=22.47e6, write=29.48e6, **_MP_SRC),
-    "k_select<32>": dict(bytes_per_launch=21.38e6, fetch=9.16e6, write=12.22e6, **_MP_SRC),
+    "k_select<64>": dict(bytes_per_launch=51.99e6, fetch=22.51e6, write=29.48e6, **_MP_SRC),
+    "k_select<32>": dict(bytes_per_launch=21.58e6, fetch=9.29e6, write=12.30e6, **_MP_SRC),
 }
 
 

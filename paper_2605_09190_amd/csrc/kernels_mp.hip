@@ -141,45 +141,6 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-// Wave sums of eight FP64 values at once; every lane receives all eight.
-// Lanes 32 apart trade halves of their lists (each keeps four partial sums),
-// then lanes 16 apart and 8 apart do the same, so that each lane carries one
-// value summed over the eight lanes that differ from it in bits 3-5; the
-// eight lanes sharing those bits then add theirs (DPP).  Value j ends on the
-// lanes whose bits 5, 4, 3 spell j.  The order of the additions is fixed.
-__device__ inline void wave_sum8_f64(const double (&v)[kCand], double (&out)[kCand]) {
-  static_assert(kCand == 8, "eight values");
-  const int lane = threadIdx.x & 63;
-  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
-  double h4[4], h2[2];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const double send = b5 ? v[j] : v[j + 4], keep = b5 ? v[j + 4] : v[j];
-    h4[j] = keep + __shfl_xor(send, 32, 64);
-  }
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const double send = b4 ? h4[j] : h4[j + 2], keep = b4 ? h4[j + 2] : h4[j];
-    h2[j] = keep + __shfl_xor(send, 16, 64);
-  }
-  double d;
-  {
-    const double send = b3 ? h2[0] : h2[1], keep = b3 ? h2[1] : h2[0];
-    // lanes 8 apart inside a row of 16: rotate the row by 8
-    d = keep + __longlong_as_double((long long)dpp_u64<0x128, 0xF>((unsigned long long)__double_as_longlong(send)));
-  }
-#define AQMP_SUMSTEP(C) { d += __longlong_as_double((long long)dpp_u64<C, 0xF>((unsigned long long)__double_as_longlong(d))); }
-  AQMP_SUMSTEP(0xB1) AQMP_SUMSTEP(0x4E) AQMP_SUMSTEP(0x141)
-#undef AQMP_SUMSTEP
-  const unsigned long long u = (unsigned long long)__double_as_longlong(d);
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)u, 8 * j);
-    const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), 8 * j);
-    out[j] = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-  }
-}
-
 template <int N>
 __global__ __launch_bounds__(64 * SelCfg<N>::WPN * SelCfg<N>::NPG, 2) void k_select(StepArgs a) {
   constexpr int WPN = SelCfg<N>::WPN, NPG = SelCfg<N>::NPG, W = WPN * NPG;
@@ -209,8 +170,12 @@ __global__ __launch_bounds__(64 * SelCfg<N>::WPN * SelCfg<N>::NPG, 2) void k_sel
     const int pos = base + slot;
     const bool valid = pos < count;               // uniform over the node's waves
     int node = 0, t = 0, kk = 0, jidx = 0;
-    double eps2 = 0.0;
+    double eps2 = 0.0, eold = 0.0;
     int cand[kCand];
+    uint32_t khi[kCand];   // |c| bits of each candidate's key (15 mantissa bits)
+    // the re-score's choice (one wave per node)
+    int r_bat = -1, r_bsel = 0;
+    double r_bmag = -1.0, r_bc = 0.0;
     double rv[PH][PW];
     double c[kCand];
 #pragma unroll
@@ -235,6 +200,7 @@ __global__ __launch_bounds__(64 * SelCfg<N>::WPN * SelCfg<N>::NPG, 2) void k_sel
       __builtin_amdgcn_sched_barrier(0);
       t = a.lv.t[node];
       jidx = a.lv.job[node];
+      eold = a.lv.e[node];
       const float* r = a.r32 + (size_t)node * K;
 #pragma unroll
       for (int dy = 0; dy < PH; ++dy) {
@@ -268,6 +234,7 @@ __global__ __launch_bounds__(64 * SelCfg<N>::WPN * SelCfg<N>::NPG, 2) void k_sel
         }
         const unsigned at = 0xFFFFFFFFu - mlo;
         cand[rr] = (nonempty && at < (unsigned)a.n_atoms) ? (int)at : -1;
+        khi[rr] = mhi;
       }
 
       // Stage the candidates' table rows this wave needs: for every
@@ -314,10 +281,8 @@ __global__ __launch_bounds__(64 * SelCfg<N>::WPN * SelCfg<N>::NPG, 2) void k_sel
       __builtin_amdgcn_wave_barrier();
 
       // 2. FP64 re-score of the candidates: this lane's patch, row sums kept
-      // apart so that the FMA chains are short; the eight wave sums at once.
-      double part8[kCand];
-#pragma unroll
-      for (int ci = 0; ci < kCand; ++ci) {
+      // apart so that the FMA chains are short.
+      auto part_of = [&](int ci) -> double {
         const int at = cand[ci];
         double part = 0.0;
         if (at >= 0) {
@@ -344,16 +309,51 @@ __global__ __launch_bounds__(64 * SelCfg<N>::WPN * SelCfg<N>::NPG, 2) void k_sel
             for (int dy = 0; dy < PH; ++dy) part = fma(sP[w][ci][ry + dy], sr[dy], part);
           }
         }
-        part8[ci] = part;
-        // one candidate at a time: keeps the scheduler from holding every
-        // candidate's table entries in registers at once
-        __builtin_amdgcn_sched_barrier(0);
-      }
+        return part;
+      };
       if constexpr (WPN == 1) {
-        wave_sum8_f64(part8, c);
+        // Candidates in key order, two at a time, with the arg-max (lowest
+        // atom on ties).  The BF16 correlation behind a key is within
+        // (2^-8 + K 2^-24) ||r|| of the FP64 value (BF16 atoms and residual,
+        // each within 2^-9 relative, products exact in FP32, FP32 sums), and
+        // the key's |c| bits are truncated to 15 mantissa bits, so its bits
+        // plus one unit in the last kept place, plus delta = 2^-7 ||r||,
+        // bound the FP64 |c| from above.  A pair whose first candidate's
+        // bound is below the best re-scored |c| is skipped with every later
+        // one: none of them can be the arg-max or tie it, so the choice is
+        // the one the re-score of all eight makes.  ||r|| is taken in FP32,
+        // clamped from below and raised by 2^-16 (never below the FP64 one).
+        const double delta = 0.0078125 * (double)(__builtin_sqrtf(fmaxf((float)eold, 1e-30f)) * 1.0000153f);
+        bool live = true;
+#pragma unroll
+        for (int j = 0; j < kCand; j += 2) {
+          const double ub = (double)__uint_as_float(khi[j] + 0x100u) + delta;
+          live = live && cand[j] >= 0 && ub >= r_bmag;
+          if (live) {   // the same in every lane of the wave
+            const double c0 = wave_sum_f64(part_of(j)), c1 = wave_sum_f64(part_of(j + 1));
+            const double m0 = fabs(c0), m1 = fabs(c1);
+            if (m0 > r_bmag || (m0 == r_bmag && cand[j] < r_bat)) {
+              r_bmag = m0;
+              r_bc = c0;
+              r_bat = cand[j];
+              r_bsel = j;
+            }
+            if (cand[j + 1] >= 0 && (m1 > r_bmag || (m1 == r_bmag && cand[j + 1] < r_bat))) {
+              r_bmag = m1;
+              r_bc = c1;
+              r_bat = cand[j + 1];
+              r_bsel = j + 1;
+            }
+          }
+        }
       } else {
 #pragma unroll
-        for (int ci = 0; ci < kCand; ++ci) c[ci] = wave_sum_f64(part8[ci]);
+        for (int ci = 0; ci < kCand; ++ci) {
+          c[ci] = wave_sum_f64(part_of(ci));
+          // one candidate at a time: keeps the scheduler from holding every
+          // candidate's table entries in registers at once
+          __builtin_amdgcn_sched_barrier(0);
+        }
       }
     }
     // the node's candidate totals (a barrier when a node spans several waves)
@@ -379,18 +379,21 @@ __global__ __launch_bounds__(64 * SelCfg<N>::WPN * SelCfg<N>::NPG, 2) void k_sel
     double ew = 0.0;
     if (valid) {
       // 3. arg-max over the re-scored candidates, lowest atom index on ties
-      // (the running best carried by value: no indexed array reads).
-      int bat = -1, bsel = 0;
-      double bmag = -1.0, bc = 0.0;
+      // (the running best carried by value: no indexed array reads); one
+      // wave per node made it with the re-score.
+      int bat = r_bat, bsel = r_bsel;
+      double bmag = r_bmag, bc = r_bc;
+      if constexpr (WPN > 1) {
 #pragma unroll
-      for (int ci = 0; ci < kCand; ++ci) {
-        const int at = cand[ci];
-        const double m = fabs(c[ci]);
-        const bool take = at >= 0 && (bat < 0 || m > bmag || (m == bmag && at < bat));
-        bat = take ? at : bat;
-        bmag = take ? m : bmag;
-        bc = take ? c[ci] : bc;
-        bsel = take ? ci : bsel;
+        for (int ci = 0; ci < kCand; ++ci) {
+          const int at = cand[ci];
+          const double m = fabs(c[ci]);
+          const bool take = at >= 0 && (bat < 0 || m > bmag || (m == bmag && at < bat));
+          bat = take ? at : bat;
+          bmag = take ? m : bmag;
+          bc = take ? c[ci] : bc;
+          bsel = take ? ci : bsel;
+        }
       }
       zero = (bat < 0 || bmag == 0.0);
       atom = bat < 0 ? 0 : bat;
