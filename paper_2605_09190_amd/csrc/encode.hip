@@ -60,6 +60,7 @@ struct aqmp_code {
   std::vector<aqmp_params> prm;
   std::vector<aqmp_job> jobs;
   std::vector<aqmp::JobDev> hjobs;
+  std::vector<aqmp::JobDev> hjobs_dev;   // what djobs holds (empty: not uploaded yet)
   aqmp::JobDev* djobs = nullptr;
   std::vector<aqmp::PassPlan> passes;
   aqmp::Counters* dcnt = nullptr;      // one per pass
@@ -566,7 +567,13 @@ int enqueue_pass(aqmp_code* c, size_t pi, hipStream_t s) {
 int run(aqmp_code* c, hipStream_t s) {
   c->lev_pos = c->sev_pos = 0;
   c->nodes_ok = false;
-  AQMP_HIP(hipMemcpyAsync(c->djobs, c->hjobs.data(), sizeof(JobDev) * c->hjobs.size(), hipMemcpyHostToDevice, s));
+  // The job table goes to the device only when it differs from what is
+  // there (a re-encode of the same images changes nothing in it).
+  if (c->hjobs_dev.size() != c->hjobs.size() ||
+      std::memcmp(c->hjobs_dev.data(), c->hjobs.data(), sizeof(JobDev) * c->hjobs.size()) != 0) {
+    AQMP_HIP(hipMemcpyAsync(c->djobs, c->hjobs.data(), sizeof(JobDev) * c->hjobs.size(), hipMemcpyHostToDevice, s));
+    c->hjobs_dev = c->hjobs;
+  }
   // HIP events recorded inside a graph cannot be timed, so a timed encode
   // issues the same launch sequence directly on the stream.
   if (c->opt.schedule != AQMP_SCHED_PLAIN && !(c->opt.flags & AQMP_OPT_TIMING)) {

@@ -263,6 +263,31 @@ def test_reencode_deterministic(A, dic):
         assert e1.coef.tobytes() == e2.coef.tobytes()
 
 
+def test_reencode_other_images(A, dic):
+    """Re-encoding with other images of the same shape (new device buffers,
+    so the job table on the device changes) gives exactly what a fresh code
+    of those images gives, and going back to the first images gives the
+    first result again."""
+    w = workload("c1")
+    img_a = w["channels"][0]
+    img_b = piecewise_image(img_a.shape[0], img_a.shape[1], seed=77)
+    da, db = [_dev(img_a)], [_dev(img_b)]
+    _say("reencode with other images")
+    code = A.Code(dic, da, w["params"], [(0, 0)], precision=1, schedule=1)
+    ea = code.export_nodes()
+    ref_a = (ea.leaves.tobytes(), ea.atom_idx.tobytes(), ea.coef.tobytes())
+    fresh = A.Code(dic, db, w["params"], [(0, 0)], precision=1, schedule=1)
+    eb = fresh.export_nodes()
+    ref_b = (eb.leaves.tobytes(), eb.atom_idx.tobytes(), eb.coef.tobytes())
+    fresh.free()
+    assert ref_a != ref_b
+    for imgs, ref in ((db, ref_b), (db, ref_b), (da, ref_a)):
+        code.reencode(imgs)
+        e = code.export_nodes()
+        assert (e.leaves.tobytes(), e.atom_idx.tobytes(), e.coef.tobytes()) == ref
+    code.free()
+
+
 def test_reencode_deterministic_full_size(A, dic):
     """The 2048 x 2048 three-channel encode: the active lists are rebuilt by
     atomic appends in a different order on every replay, and the exported
